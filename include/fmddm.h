@@ -1,0 +1,191 @@
+/*
+ * fmddm.h -- C ABI of the MI355X (gfx950) fast-multipole displacement
+ * discontinuity library.
+ *
+ * The operation behind every entry point is the influence operator of the
+ * constant-element displacement discontinuity method (DDM): for N straight
+ * elements with unknown shear and normal displacement discontinuities
+ * (D_s, D_n), it returns the shear and normal tractions that those
+ * discontinuities induce at every element midpoint (Section 2, eqs. 2.3-2.5,
+ * the A_xx, A_xy, A_yx, A_yy blocks of a single time step).  The product is
+ * evaluated by the black-box fast multipole method with Chebyshev
+ * interpolation (Section 3: quad-tree, upward pass, M2L over the interaction
+ * list, downward pass, direct neighbour interactions), and the system of one
+ * time step is solved with GMRES whose matrix-vector products are FMM
+ * products (Section 4).
+ *
+ * Conventions (the paper states none of them):
+ *   - plane strain, isotropic, Young's modulus E, Poisson ratio nu;
+ *   - SI units (m, Pa);
+ *   - stresses and tractions are tension-positive;
+ *   - element j runs from (x1[j], y1[j]) to (x2[j], y2[j]); its tangent s
+ *     points from the first to the second endpoint and its normal is s
+ *     rotated by +90 degrees; a displacement discontinuity is
+ *     D = u(+) - u(-), the + face being the side the normal points into,
+ *     so D_n > 0 is opening and D_s > 0 is the + face sliding along s;
+ *   - all vectors are element-major, in the caller's element order:
+ *     D[2j] = D_s, D[2j+1] = D_n; out[2i] = shear traction,
+ *     out[2i+1] = normal traction at the midpoint of element i.
+ *
+ * Memory and ownership: vectors passed to fmddm_apply / fmddm_rhs /
+ * fmddm_solve / fmddm_sif are DEVICE pointers on the context's device; they
+ * are read or written on the context's stream and stay owned by the caller.
+ * Geometry passed to fmddm_build_tree may be host or device memory (flag);
+ * it is copied.  A tree owns all its device memory until fmddm_tree_free.
+ * A context is not thread-safe; use one context per stream.  Calls are
+ * asynchronous with respect to the host unless stated otherwise.
+ *
+ * Errors: every call returns an fmddm_status; nothing is thrown across the
+ * ABI.  On failure fmddm_last_error(ctx) describes the cause.  No entry point
+ * falls back to the CPU.
+ */
+#ifndef FMDDM_H
+#define FMDDM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fmddm_ctx fmddm_ctx;
+typedef struct fmddm_tree fmddm_tree;
+
+typedef enum {
+    FMDDM_OK = 0,
+    FMDDM_ENOTCONV = 1,       /* GMRES stopped at maxit; best iterate kept */
+    FMDDM_EINVAL = -1,        /* bad argument */
+    FMDDM_ENOMEM = -2,        /* device allocation failed */
+    FMDDM_EDEVICE = -3,       /* HIP runtime error */
+    FMDDM_EGEOM = -4,         /* zero-length / non-finite element, point outside root box */
+    FMDDM_EUNSUPPORTED = -5   /* parameter combination not built */
+} fmddm_status;
+
+typedef enum {
+    FMDDM_APPLY_FMM = 0,      /* black-box FMM product (Section 3) */
+    FMDDM_APPLY_DIRECT = 1,   /* exact product, influence evaluated on the fly */
+    FMDDM_APPLY_DENSE = 2     /* exact product with the stored dense matrix */
+} fmddm_apply_mode;
+
+typedef enum {
+    FMDDM_M2L_DENSE = 0,      /* per-offset (3p^2 x 3p^2) operators, as in eq. 3.8 */
+    FMDDM_M2L_SVD = 1         /* the same operators compressed by a truncated SVD */
+} fmddm_m2l_mode;
+
+typedef struct {
+    double E, nu;             /* material (Pa, -) */
+    int leaf;                 /* split a cell holding more than `leaf` points (Section 3.1) */
+    int p;                    /* Chebyshev nodes per dimension, 1..32 */
+    int max_level;            /* cap on tree depth, 0..30 */
+    double kappa;             /* a cell splits only if its children stay at least
+                                 kappa x the largest element half-length it holds wide */
+    int m2l;                  /* fmddm_m2l_mode */
+    double m2l_tol;           /* relative singular-value cut for FMDDM_M2L_SVD */
+    int use_root_box;         /* 1: level-0 square given below; 0: bounding square */
+    double root_x0, root_y0, root_L;
+    int restart, maxit;       /* GMRES(restart), at most maxit matrix-vector products */
+    double tol;               /* GMRES relative residual target */
+} fmddm_params;
+
+typedef struct {
+    int64_t n;                /* elements */
+    int64_t ncell, nleaf;     /* tree cells, leaves */
+    int32_t nlevel;           /* deepest level + 1 */
+    int64_t nU, nV, nW, nX;   /* list lengths (sum over cells) */
+    int64_t near_pairs;       /* directly evaluated point pairs per product */
+    int64_t m2l_rank;         /* M2L rank (3p^2 when uncompressed) */
+    double root_x0, root_y0, root_L;
+    int64_t device_bytes;     /* device memory held by the tree */
+} fmddm_tree_info;
+
+typedef struct {
+    int32_t iters;            /* matrix-vector products inside GMRES */
+    int32_t restarts;
+    double relres;            /* ||b - A x|| / ||b|| of the returned iterate (true residual) */
+    int32_t converged;
+} fmddm_solve_info;
+
+/* Fill *p with defaults: E=20e9, nu=0.25, leaf=32, p=20, max_level=24,
+ * kappa=8, m2l=DENSE, m2l_tol=1e-12, no root box, restart=50,
+ * maxit=10000, tol=1e-10. */
+void fmddm_default_params(fmddm_params *p);
+
+/* Create a context on the current HIP device bound to `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  Validates the parameters
+ * (EINVAL) and builds the Chebyshev tables.  *out is NULL on failure. */
+fmddm_status fmddm_create(const fmddm_params *p, void *hip_stream, fmddm_ctx **out);
+void fmddm_destroy(fmddm_ctx *ctx);
+/* Message of the last failing call on ctx (static storage owned by ctx). */
+const char *fmddm_last_error(const fmddm_ctx *ctx);
+
+/* Build the quad-tree and lists over the element midpoints (Section 3.1).
+ * x1,y1,x2,y2 hold n element endpoints; on_device != 0 means they are
+ * device pointers.  The level-0 square is the bounding square of the
+ * midpoints (or the context's root box), coordinates are quantised to a
+ * 2^31 grid and Morton-ordered, and a cell splits into its non-empty
+ * children (left-to-right, then bottom-to-top) while it holds more than
+ * `leaf` points.  U/V/W/X lists follow.  Synchronises the stream.
+ * EGEOM for zero-length or non-finite elements or points outside the
+ * root box. */
+fmddm_status fmddm_build_tree(fmddm_ctx *ctx, int64_t n, const double *x1,
+                              const double *y1, const double *x2, const double *y2,
+                              int on_device, fmddm_tree **out);
+void fmddm_tree_free(fmddm_tree *t);
+fmddm_status fmddm_tree_get_info(fmddm_ctx *ctx, const fmddm_tree *t, fmddm_tree_info *info);
+
+/* Copy the tree to host arrays (any pointer may be NULL to skip it).
+ * perm[n]: sorted position -> element index; key[n]: Morton keys in sorted
+ * order; per cell (ncell entries, cells ordered by level then Morton key):
+ * level, ix, iy, parent (-1 for the root), child[4*ncell] (-1 = absent,
+ * order BL, BR, TL, TR), pbeg/pend (sorted point range), isleaf;
+ * root[3] = x0, y0, L.  Synchronises the stream. */
+fmddm_status fmddm_tree_export(fmddm_ctx *ctx, const fmddm_tree *t, int64_t *perm,
+                               uint64_t *key, int32_t *level, uint32_t *ix,
+                               uint32_t *iy, int32_t *parent, int32_t *child,
+                               int64_t *pbeg, int64_t *pend, int32_t *isleaf,
+                               double *root);
+
+/* Copy one list as CSR over cells: which = 0 U, 1 V, 2 W, 3 X; off has
+ * ncell+1 entries, idx has off[ncell] entries, sorted by cell index.
+ * U(B): leaves adjacent to leaf B (B included); V(B): children of the
+ * neighbours of B's parent that are not adjacent to B (the interaction
+ * list); W(B): cells finer than leaf B, not adjacent to B, whose parent is
+ * adjacent to B; X(A): leaves B with A in W(B).  Synchronises. */
+fmddm_status fmddm_tree_export_list(fmddm_ctx *ctx, const fmddm_tree *t, int which,
+                                    int64_t *off, int32_t *idx);
+
+/* out = A D for the single-step elastic influence operator (device
+ * pointers, 2n doubles each; out may not alias D).  mode selects the FMM
+ * (Section 3), the exact on-the-fly product or the stored dense matrix
+ * (assembled on first use: 32 n^2 bytes; ENOMEM if it does not fit). */
+fmddm_status fmddm_apply(fmddm_ctx *ctx, fmddm_tree *t, int mode, const double *D,
+                         double *out);
+
+/* Right-hand side of one elastic step (Section 4): tractions the
+ * discontinuities must induce so that the element faces carry the fluid
+ * pressure pf[i] (device, n doubles, compression-positive) under the far
+ * field SH (along x) and Sh (along y), compression-positive:
+ * rhs = -pf n - sigma_inf n, resolved on (s, n).  rhs: device, 2n doubles. */
+fmddm_status fmddm_rhs(fmddm_ctx *ctx, fmddm_tree *t, const double *pf, double SH,
+                       double Sh, double *rhs);
+
+/* Solve A D = rhs by restarted GMRES(restart) (Section 4) with products by
+ * `mode`.  D holds the initial guess on entry and the solution on exit
+ * (device, 2n).  Orthogonalisation (classical Gram-Schmidt, applied twice),
+ * Givens rotations and the residual checks run on the device in FP64; the
+ * final residual is recomputed from b - A x.  FMDDM_ENOTCONV when maxit is
+ * reached (the best iterate is returned).  Synchronises the stream. */
+fmddm_status fmddm_solve(fmddm_ctx *ctx, fmddm_tree *t, int mode, const double *rhs,
+                         double *D, fmddm_solve_info *info);
+
+/* Stress intensity factors of eq. 2.6 from the DDs of tip element `elem`
+ * (D: device, 2n), reading "a" as that element's half-length:
+ * K = 0.806 E / (4 (1 - nu^2)) sqrt(pi / (2 a)) D.  Synchronises. */
+fmddm_status fmddm_sif(fmddm_ctx *ctx, fmddm_tree *t, const double *D, int64_t elem,
+                       double *KI, double *KII);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FMDDM_H */

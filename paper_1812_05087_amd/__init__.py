@@ -1,0 +1,275 @@
+"""Python binding of the fmddm C ABI (include/fmddm.h).
+
+Argument marshalling only: every step of the FMM/DDM path runs in the HIP
+library ``libfmddm.so`` built from ``csrc/``.  PyTorch provides device memory
+and the stream.  There is no CPU fallback: importing works without a GPU,
+but any call needs the built library and a device, and fails loudly
+otherwise.
+
+Functions carry the C names (``fmddm_create``, ``fmddm_build_tree``,
+``fmddm_apply``, ``fmddm_rhs``, ``fmddm_solve``, ``fmddm_sif``, ...).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfmddm.so")
+
+FMDDM_OK, FMDDM_ENOTCONV = 0, 1
+FMDDM_EINVAL, FMDDM_ENOMEM, FMDDM_EDEVICE, FMDDM_EGEOM, FMDDM_EUNSUPPORTED = -1, -2, -3, -4, -5
+FMDDM_APPLY_FMM, FMDDM_APPLY_DIRECT, FMDDM_APPLY_DENSE = 0, 1, 2
+FMDDM_M2L_DENSE, FMDDM_M2L_SVD = 0, 1
+LIST_U, LIST_V, LIST_W, LIST_X = 0, 1, 2, 3
+
+EXPORTED = [
+    "fmddm_default_params", "fmddm_create", "fmddm_destroy", "fmddm_last_error",
+    "fmddm_build_tree", "fmddm_tree_free", "fmddm_tree_get_info", "fmddm_tree_export",
+    "fmddm_tree_export_list", "fmddm_apply", "fmddm_rhs", "fmddm_solve", "fmddm_sif",
+]
+
+
+class FmddmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"fmddm status {status}: {msg}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("E", C.c_double), ("nu", C.c_double),
+        ("leaf", C.c_int), ("p", C.c_int), ("max_level", C.c_int),
+        ("kappa", C.c_double), ("m2l", C.c_int), ("m2l_tol", C.c_double),
+        ("use_root_box", C.c_int), ("root_x0", C.c_double), ("root_y0", C.c_double),
+        ("root_L", C.c_double), ("restart", C.c_int), ("maxit", C.c_int), ("tol", C.c_double),
+    ]
+
+
+class TreeInfo(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64), ("ncell", C.c_int64), ("nleaf", C.c_int64), ("nlevel", C.c_int32),
+        ("nU", C.c_int64), ("nV", C.c_int64), ("nW", C.c_int64), ("nX", C.c_int64),
+        ("near_pairs", C.c_int64), ("m2l_rank", C.c_int64),
+        ("root_x0", C.c_double), ("root_y0", C.c_double), ("root_L", C.c_double),
+        ("device_bytes", C.c_int64),
+    ]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("relres", C.c_double),
+                ("converged", C.c_int32)]
+
+
+_lib = None
+_vp = C.c_void_p
+_d = C.POINTER(C.c_double)
+
+
+def lib():
+    """Load libfmddm.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run paper_1812_05087_amd/build.py "
+                               "(or __graft_entry__.build()) first; there is no fallback")
+        L = C.CDLL(LIB_PATH)
+        L.fmddm_default_params.argtypes = [C.POINTER(Params)]
+        L.fmddm_default_params.restype = None
+        L.fmddm_create.argtypes = [C.POINTER(Params), _vp, C.POINTER(_vp)]
+        L.fmddm_destroy.argtypes = [_vp]
+        L.fmddm_destroy.restype = None
+        L.fmddm_last_error.argtypes = [_vp]
+        L.fmddm_last_error.restype = C.c_char_p
+        L.fmddm_build_tree.argtypes = [_vp, C.c_int64, _vp, _vp, _vp, _vp, C.c_int, C.POINTER(_vp)]
+        L.fmddm_tree_free.argtypes = [_vp]
+        L.fmddm_tree_free.restype = None
+        L.fmddm_tree_get_info.argtypes = [_vp, _vp, C.POINTER(TreeInfo)]
+        L.fmddm_tree_export.argtypes = [_vp, _vp] + [_vp] * 11
+        L.fmddm_tree_export_list.argtypes = [_vp, _vp, C.c_int, _vp, _vp]
+        L.fmddm_apply.argtypes = [_vp, _vp, C.c_int, _vp, _vp]
+        L.fmddm_rhs.argtypes = [_vp, _vp, _vp, C.c_double, C.c_double, _vp]
+        L.fmddm_solve.argtypes = [_vp, _vp, C.c_int, _vp, _vp, C.POINTER(SolveInfo)]
+        L.fmddm_sif.argtypes = [_vp, _vp, _vp, C.c_int64, _d, _d]
+        for name in EXPORTED:
+            f = getattr(L, name)
+            if name not in ("fmddm_default_params", "fmddm_destroy", "fmddm_tree_free",
+                            "fmddm_last_error"):
+                f.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(st, ctx=None):
+    if st < 0:
+        msg = lib().fmddm_last_error(ctx).decode() if ctx else ""
+        raise FmddmError(st, msg)
+    return st
+
+
+def _ptr(t):
+    """Device pointer of a contiguous CUDA/HIP float64 tensor."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a device (cuda) tensor")
+    if t.dtype != torch.float64 or not t.is_contiguous():
+        raise TypeError("expected a contiguous float64 tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+# ----------------------------------------------------------- C-ABI wrappers
+def fmddm_default_params(**kw) -> Params:
+    p = Params()
+    lib().fmddm_default_params(C.byref(p))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise AttributeError(k)
+        setattr(p, k, v)
+    return p
+
+
+def fmddm_create(params: Params, stream=None):
+    """stream: a torch.cuda.Stream, a raw hipStream_t int, or None (the
+    current torch stream)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    raw = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+    out = C.c_void_p()
+    _check(lib().fmddm_create(C.byref(params), C.c_void_p(raw), C.byref(out)))
+    return out
+
+
+def fmddm_destroy(ctx):
+    lib().fmddm_destroy(ctx)
+
+
+def fmddm_last_error(ctx) -> str:
+    return lib().fmddm_last_error(ctx).decode()
+
+
+def fmddm_build_tree(ctx, x1, y1, x2, y2):
+    """Endpoints as numpy arrays (host) or float64 device tensors."""
+    out = C.c_void_p()
+    if isinstance(x1, np.ndarray):
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (x1, y1, x2, y2)]
+        ptrs = [C.c_void_p(a.ctypes.data) for a in arrs]
+        n, dev = arrs[0].shape[0], 0
+    else:
+        ptrs = [_ptr(a) for a in (x1, y1, x2, y2)]
+        n, dev = x1.shape[0], 1
+    _check(lib().fmddm_build_tree(ctx, n, *ptrs, dev, C.byref(out)), ctx)
+    return out
+
+
+def fmddm_tree_free(tree):
+    lib().fmddm_tree_free(tree)
+
+
+def fmddm_tree_get_info(ctx, tree) -> dict:
+    info = TreeInfo()
+    _check(lib().fmddm_tree_get_info(ctx, tree, C.byref(info)), ctx)
+    return {k: getattr(info, k) for k, _ in TreeInfo._fields_}
+
+
+def fmddm_tree_export(ctx, tree) -> dict:
+    info = fmddm_tree_get_info(ctx, tree)
+    n, nc = info["n"], info["ncell"]
+    out = {
+        "perm": np.zeros(n, np.int64), "key": np.zeros(n, np.uint64),
+        "level": np.zeros(nc, np.int32), "ix": np.zeros(nc, np.uint32), "iy": np.zeros(nc, np.uint32),
+        "parent": np.zeros(nc, np.int32), "child": np.zeros((nc, 4), np.int32),
+        "pbeg": np.zeros(nc, np.int64), "pend": np.zeros(nc, np.int64),
+        "isleaf": np.zeros(nc, np.int32), "root": np.zeros(3),
+    }
+    order = ["perm", "key", "level", "ix", "iy", "parent", "child", "pbeg", "pend", "isleaf", "root"]
+    _check(lib().fmddm_tree_export(ctx, tree, *[C.c_void_p(out[k].ctypes.data) for k in order]), ctx)
+    return out
+
+
+def fmddm_tree_export_list(ctx, tree, which):
+    info = fmddm_tree_get_info(ctx, tree)
+    nc = info["ncell"]
+    off = np.zeros(nc + 1, np.int64)
+    _check(lib().fmddm_tree_export_list(ctx, tree, which, C.c_void_p(off.ctypes.data), None), ctx)
+    idx = np.zeros(max(int(off[-1]), 1), np.int32)
+    _check(lib().fmddm_tree_export_list(ctx, tree, which, C.c_void_p(off.ctypes.data),
+                                        C.c_void_p(idx.ctypes.data)), ctx)
+    return off, idx[:int(off[-1])]
+
+
+def fmddm_apply(ctx, tree, mode, D, out):
+    return _check(lib().fmddm_apply(ctx, tree, mode, _ptr(D), _ptr(out)), ctx)
+
+
+def fmddm_rhs(ctx, tree, pf, SH, Sh, rhs):
+    return _check(lib().fmddm_rhs(ctx, tree, _ptr(pf), float(SH), float(Sh), _ptr(rhs)), ctx)
+
+
+def fmddm_solve(ctx, tree, mode, rhs, D):
+    info = SolveInfo()
+    st = _check(lib().fmddm_solve(ctx, tree, mode, _ptr(rhs), _ptr(D), C.byref(info)), ctx)
+    return st, {"iters": info.iters, "restarts": info.restarts, "relres": info.relres,
+                "converged": bool(info.converged)}
+
+
+def fmddm_sif(ctx, tree, D, elem):
+    KI, KII = C.c_double(), C.c_double()
+    _check(lib().fmddm_sif(ctx, tree, _ptr(D), int(elem), C.byref(KI), C.byref(KII)), ctx)
+    return KI.value, KII.value
+
+
+# --------------------------------------------------------------- convenience
+class Problem:
+    """A context plus a tree over one geometry, with device buffers."""
+
+    def __init__(self, x1, y1, x2, y2, device="cuda:0", **params):
+        import torch
+        self.device = torch.device(device)
+        torch.cuda.set_device(self.device)
+        self.params = fmddm_default_params(**params)
+        self.ctx = fmddm_create(self.params)
+        self.tree = fmddm_build_tree(self.ctx, np.asarray(x1), np.asarray(y1),
+                                     np.asarray(x2), np.asarray(y2))
+        self.info = fmddm_tree_get_info(self.ctx, self.tree)
+        self.n = self.info["n"]
+
+    def vec(self, data=None):
+        import torch
+        if data is None:
+            return torch.zeros(2 * self.n, dtype=torch.float64, device=self.device)
+        return torch.as_tensor(np.ascontiguousarray(data, dtype=np.float64)).to(self.device)
+
+    def apply(self, D, mode=FMDDM_APPLY_FMM, out=None):
+        out = self.vec() if out is None else out
+        fmddm_apply(self.ctx, self.tree, mode, D, out)
+        return out
+
+    def rhs(self, pf, SH, Sh):
+        import torch
+        pf = torch.as_tensor(np.ascontiguousarray(pf, dtype=np.float64)).to(self.device)
+        out = self.vec()
+        fmddm_rhs(self.ctx, self.tree, pf, SH, Sh, out)
+        return out
+
+    def solve(self, rhs, mode=FMDDM_APPLY_FMM, x0=None):
+        x = self.vec() if x0 is None else x0.clone()
+        st, info = fmddm_solve(self.ctx, self.tree, mode, rhs, x)
+        info["status"] = st
+        return x, info
+
+    def close(self):
+        if getattr(self, "tree", None):
+            fmddm_tree_free(self.tree)
+            self.tree = None
+        if getattr(self, "ctx", None):
+            fmddm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

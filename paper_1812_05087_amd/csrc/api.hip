@@ -1,0 +1,255 @@
+// C ABI entry points (declared and documented in include/fmddm.h).  Each
+// call validates its arguments, runs on the context's stream, and turns
+// any internal error into a status code plus a message.
+#include "internal.h"
+
+#include <cmath>
+#include <cstring>
+#include <new>
+
+namespace fmddm {
+void sif_eval(fmddm_ctx *ctx, fmddm_tree *t, const double *D, int64_t e, double *KI, double *KII);
+}
+
+using fmddm::Error;
+
+namespace {
+
+template <class F>
+fmddm_status guarded(fmddm_ctx *ctx, F &&f)
+{
+    try {
+        FM_HIP(hipSetDevice(ctx->device));
+        fmddm_status st = f();
+        if (ctx) ctx->err.clear();
+        return st;
+    } catch (const Error &e) {
+        if (ctx) ctx->err = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        if (ctx) ctx->err = "host allocation failed";
+        return FMDDM_ENOMEM;
+    } catch (...) {
+        if (ctx) ctx->err = "unexpected error";
+        return FMDDM_EDEVICE;
+    }
+}
+
+const char *check_params(const fmddm_params *p)
+{
+    if (!(p->E > 0.0) || !std::isfinite(p->E)) return "E must be positive";
+    if (!(p->nu > -1.0 && p->nu < 0.5)) return "nu must lie in (-1, 0.5)";
+    if (p->leaf < 1) return "leaf must be >= 1";
+    if (p->p < 1 || p->p > fmddm::MAXP) return "p must lie in [1, 32]";
+    if (p->max_level < 0 || p->max_level > 30) return "max_level must lie in [0, 30]";
+    if (!(p->kappa >= 0.0)) return "kappa must be >= 0";
+    if (p->m2l != FMDDM_M2L_DENSE && p->m2l != FMDDM_M2L_SVD) return "unknown m2l mode";
+    if (p->use_root_box && !(p->root_L > 0.0)) return "root box side must be positive";
+    if (p->restart < 1 || p->restart > 1000) return "restart must lie in [1, 1000]";
+    if (p->maxit < 0) return "maxit must be >= 0";
+    if (!(p->tol >= 0.0)) return "tol must be >= 0";
+    return nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+void fmddm_default_params(fmddm_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->E = 20e9;
+    p->nu = 0.25;
+    p->leaf = 32;
+    p->p = 20;
+    p->max_level = 24;
+    p->kappa = 8.0;
+    p->m2l = FMDDM_M2L_DENSE;
+    p->m2l_tol = 1e-12;
+    p->restart = 50;
+    p->maxit = 10000;
+    p->tol = 1e-10;
+}
+
+fmddm_status fmddm_create(const fmddm_params *p, void *hip_stream, fmddm_ctx **out)
+{
+    if (!out) return FMDDM_EINVAL;
+    *out = nullptr;
+    if (!p) return FMDDM_EINVAL;
+    if (check_params(p)) return FMDDM_EINVAL;
+    if (p->m2l == FMDDM_M2L_SVD) return FMDDM_EUNSUPPORTED;
+    fmddm_ctx *ctx = new (std::nothrow) fmddm_ctx();
+    if (!ctx) return FMDDM_ENOMEM;
+    ctx->prm = *p;
+    ctx->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&ctx->device) != hipSuccess) {
+        delete ctx;
+        return FMDDM_EDEVICE;
+    }
+    double G = p->E / (2.0 * (1.0 + p->nu));
+    ctx->gc = G / (2.0 * M_PI * (1.0 - p->nu));
+    fmddm_status st = guarded(ctx, [&] {
+        fmddm::setup_cheb(ctx);
+        return FMDDM_OK;
+    });
+    if (st != FMDDM_OK) {
+        delete ctx;
+        return st;
+    }
+    *out = ctx;
+    return FMDDM_OK;
+}
+
+void fmddm_destroy(fmddm_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    delete ctx;
+}
+
+const char *fmddm_last_error(const fmddm_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+fmddm_status fmddm_build_tree(fmddm_ctx *ctx, int64_t n, const double *x1, const double *y1,
+                              const double *x2, const double *y2, int on_device, fmddm_tree **out)
+{
+    if (!ctx || !out) return FMDDM_EINVAL;
+    *out = nullptr;
+    if (n <= 0 || !x1 || !y1 || !x2 || !y2) {
+        ctx->err = "empty geometry or null pointer";
+        return FMDDM_EINVAL;
+    }
+    fmddm_tree *t = new (std::nothrow) fmddm_tree();
+    if (!t) return FMDDM_ENOMEM;
+    fmddm_status st = guarded(ctx, [&] {
+        fmddm::build_tree(ctx, t, n, x1, y1, x2, y2, on_device);
+        return FMDDM_OK;
+    });
+    if (st != FMDDM_OK) {
+        delete t;
+        return st;
+    }
+    *out = t;
+    return FMDDM_OK;
+}
+
+void fmddm_tree_free(fmddm_tree *t) { delete t; }
+
+fmddm_status fmddm_tree_get_info(fmddm_ctx *ctx, const fmddm_tree *t, fmddm_tree_info *info)
+{
+    if (!ctx || !t || !info) return FMDDM_EINVAL;
+    std::memset(info, 0, sizeof(*info));
+    info->n = t->n;
+    info->ncell = t->ncell;
+    info->nleaf = t->nleaf;
+    info->nlevel = t->nlevel;
+    info->nU = t->h_loff[0].empty() ? 0 : t->h_loff[0].back();
+    info->nV = t->h_loff[1].empty() ? 0 : t->h_loff[1].back();
+    info->nW = t->h_loff[2].empty() ? 0 : t->h_loff[2].back();
+    info->nX = t->h_loff[3].empty() ? 0 : t->h_loff[3].back();
+    info->near_pairs = t->near_pairs;
+    info->m2l_rank = 3 * ctx->prm.p * ctx->prm.p;
+    info->root_x0 = t->x0;
+    info->root_y0 = t->y0;
+    info->root_L = t->L;
+    int64_t b = 0;
+    auto add = [&](size_t x) { b += (int64_t)x; };
+    add(t->ocx.bytes() * 5); add(t->scx.bytes() * 5); add(t->perm.bytes()); add(t->key.bytes());
+    add(t->clevel.bytes() * 8); add(t->cmk.bytes()); add(t->ccx.bytes() * 3);
+    for (int w = 0; w < 4; ++w) { add(t->loff[w].bytes()); add(t->lidx[w].bytes()); }
+    add(t->noff.bytes()); add(t->nsrc.bytes()); add(t->Wexp.bytes()); add(t->Fexp.bytes());
+    add(t->Zm2l.bytes()); add(t->q.bytes()); add(t->Dsort.bytes()); add(t->Adense.bytes());
+    add(t->gm_V.bytes()); add(t->gm_w.bytes()); add(t->gm_r.bytes());
+    info->device_bytes = b;
+    return FMDDM_OK;
+}
+
+fmddm_status fmddm_tree_export(fmddm_ctx *ctx, const fmddm_tree *t, int64_t *perm, uint64_t *key,
+                               int32_t *level, uint32_t *ix, uint32_t *iy, int32_t *parent,
+                               int32_t *child, int64_t *pbeg, int64_t *pend, int32_t *isleaf,
+                               double *root)
+{
+    if (!ctx || !t) return FMDDM_EINVAL;
+    return guarded(ctx, [&] {
+        hipStream_t s = ctx->stream;
+        int n = (int)t->n, nc = t->ncell;
+        std::vector<int> tmp;
+        auto widen = [&](const int *dsrc, int cnt, int64_t *dst) {
+            tmp.resize(cnt);
+            FM_HIP(hipMemcpyAsync(tmp.data(), dsrc, cnt * 4, hipMemcpyDeviceToHost, s));
+            FM_HIP(hipStreamSynchronize(s));
+            for (int i = 0; i < cnt; ++i) dst[i] = tmp[i];
+        };
+        if (perm) widen(t->perm.p, n, perm);
+        if (pbeg) widen(t->cpbeg.p, nc, pbeg);
+        if (pend) widen(t->cpend.p, nc, pend);
+        if (key) FM_HIP(hipMemcpyAsync(key, t->key.p, n * 8, hipMemcpyDeviceToHost, s));
+        if (level) FM_HIP(hipMemcpyAsync(level, t->clevel.p, nc * 4, hipMemcpyDeviceToHost, s));
+        if (ix) FM_HIP(hipMemcpyAsync(ix, t->cix.p, nc * 4, hipMemcpyDeviceToHost, s));
+        if (iy) FM_HIP(hipMemcpyAsync(iy, t->ciy.p, nc * 4, hipMemcpyDeviceToHost, s));
+        if (parent) FM_HIP(hipMemcpyAsync(parent, t->cparent.p, nc * 4, hipMemcpyDeviceToHost, s));
+        if (child) FM_HIP(hipMemcpyAsync(child, t->cchild.p, (size_t)nc * 16, hipMemcpyDeviceToHost, s));
+        if (isleaf) FM_HIP(hipMemcpyAsync(isleaf, t->cleaf.p, nc * 4, hipMemcpyDeviceToHost, s));
+        FM_HIP(hipStreamSynchronize(s));
+        if (root) { root[0] = t->x0; root[1] = t->y0; root[2] = t->L; }
+        return FMDDM_OK;
+    });
+}
+
+fmddm_status fmddm_tree_export_list(fmddm_ctx *ctx, const fmddm_tree *t, int which, int64_t *off,
+                                    int32_t *idx)
+{
+    if (!ctx || !t || which < 0 || which > 3) return FMDDM_EINVAL;
+    return guarded(ctx, [&] {
+        const std::vector<int> &o = t->h_loff[which];
+        if (off)
+            for (size_t i = 0; i < o.size(); ++i) off[i] = o[i];
+        if (idx && o.back() > 0) {
+            FM_HIP(hipMemcpyAsync(idx, t->lidx[which].p, (size_t)o.back() * 4, hipMemcpyDeviceToHost,
+                                  ctx->stream));
+            FM_HIP(hipStreamSynchronize(ctx->stream));
+        }
+        return FMDDM_OK;
+    });
+}
+
+fmddm_status fmddm_apply(fmddm_ctx *ctx, fmddm_tree *t, int mode, const double *D, double *out)
+{
+    if (!ctx || !t || !D || !out || D == out) return FMDDM_EINVAL;
+    if (mode < FMDDM_APPLY_FMM || mode > FMDDM_APPLY_DENSE) return FMDDM_EINVAL;
+    return guarded(ctx, [&] {
+        fmddm::apply_mode(ctx, t, mode, D, out);
+        return FMDDM_OK;
+    });
+}
+
+fmddm_status fmddm_rhs(fmddm_ctx *ctx, fmddm_tree *t, const double *pf, double SH, double Sh, double *rhs)
+{
+    if (!ctx || !t || !pf || !rhs) return FMDDM_EINVAL;
+    return guarded(ctx, [&] {
+        fmddm::rhs_build(ctx, t, pf, SH, Sh, rhs);
+        return FMDDM_OK;
+    });
+}
+
+fmddm_status fmddm_solve(fmddm_ctx *ctx, fmddm_tree *t, int mode, const double *rhs, double *D,
+                         fmddm_solve_info *info)
+{
+    if (!ctx || !t || !rhs || !D || rhs == D) return FMDDM_EINVAL;
+    if (mode < FMDDM_APPLY_FMM || mode > FMDDM_APPLY_DENSE) return FMDDM_EINVAL;
+    fmddm_solve_info local;
+    if (!info) info = &local;
+    return guarded(ctx, [&] { return fmddm::gmres_solve(ctx, t, mode, rhs, D, info); });
+}
+
+fmddm_status fmddm_sif(fmddm_ctx *ctx, fmddm_tree *t, const double *D, int64_t elem, double *KI,
+                       double *KII)
+{
+    if (!ctx || !t || !D || !KI || !KII || elem < 0 || elem >= t->n) return FMDDM_EINVAL;
+    return guarded(ctx, [&] {
+        fmddm::sif_eval(ctx, t, D, elem, KI, KII);
+        return FMDDM_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// Constant displacement-discontinuity element (plane strain), device side.
+//
+// Stress at a receiver from a straight element of half-length a carrying a
+// uniform shear (Ds, along the element) and normal (Dn) displacement
+// discontinuity, opening-positive, tension-positive stress.  This is the
+// influence coefficient A_ij of eqs. 2.3-2.5 for the elastic (drained or
+// undrained) part; the paper cites rather than states it, and the classical
+// closed form of the constant element is used: with the element on the
+// local x-axis over [-a, a], r1^2 = (x-a)^2 + y^2, r2^2 = (x+a)^2 + y^2 and
+// f the element integral of -C ln r, C = 1/(4 pi (1 - nu)),
+//   sxx = -2G [Ds (2 f_xy + y f_xyy) + Dn (f_yy + y f_yyy)]
+//   syy = -2G [Ds (-y f_xyy)        + Dn (f_yy - y f_yyy)]
+//   sxy = -2G [Ds (f_yy + y f_yyy)  + Dn (-y f_xyy)]
+// (the minus signs convert the classical D = u(-) - u(+) convention to the
+// opening-positive one).  Only rational functions of the local coordinates
+// appear.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace fmddm {
+
+// Adds the global-frame stress (sxx, syy, sxy) at (X, Y) from the element
+// (cx, cy, cb = cos beta, sb = sin beta, a) with DDs (Ds, Dn).
+// gc = 2 G C = G / (2 pi (1 - nu)).
+__device__ __forceinline__ void elem_stress_add(double X, double Y, double cx, double cy,
+                                                double cb, double sb, double a, double Ds,
+                                                double Dn, double gc, double &sxx, double &syy,
+                                                double &sxy)
+{
+    double dx = X - cx, dy = Y - cy;
+    double x = dx * cb + dy * sb;
+    double y = dy * cb - dx * sb;
+    double xm = x - a, xp = x + a, y2 = y * y;
+    double i1 = 1.0 / (xm * xm + y2);
+    double i2 = 1.0 / (xp * xp + y2);
+    double fxy = y * (i1 - i2);
+    double fyy = xp * i2 - xm * i1;
+    double j1 = i1 * i1, j2 = i2 * i2;
+    double fxyy = (xm * xm - y2) * j1 - (xp * xp - y2) * j2;
+    double fyyy = 2.0 * y * (xm * j1 - xp * j2);
+    double yfxyy = y * fxyy, yfyyy = y * fyyy;
+    double lxx = -gc * (Ds * (2.0 * fxy + yfxyy) + Dn * (fyy + yfyyy));
+    double lyy = -gc * (Dn * (fyy - yfyyy) - Ds * yfxyy);
+    double lxy = -gc * (Ds * (fyy + yfyyy) - Dn * yfxyy);
+    // rotate back: sigma = R l R^T, R = [[cb, -sb], [sb, cb]]
+    double c2 = cb * cb, s2 = sb * sb, cs = cb * sb;
+    sxx += c2 * lxx - 2.0 * cs * lxy + s2 * lyy;
+    syy += s2 * lxx + 2.0 * cs * lxy + c2 * lyy;
+    sxy += cs * (lxx - lyy) + (c2 - s2) * lxy;
+}
+
+// Shear and normal traction on a receiver with tangent (cb, sb).
+__device__ __forceinline__ void traction(double cb, double sb, double sxx, double syy, double sxy,
+                                         double &ts, double &tn)
+{
+    double tx = sxy * cb - sxx * sb;
+    double ty = syy * cb - sxy * sb;
+    ts = cb * tx + sb * ty;
+    tn = cb * ty - sb * tx;
+}
+
+// Source charge per unit length: q = (b_x n_x, b_y n_y, b_x n_y + b_y n_x),
+// b = Ds s + Dn n, n = (-sb, cb).  The far field of an element is the
+// integral along it of the point kernel applied to q.
+__device__ __forceinline__ void charge(double cb, double sb, double Ds, double Dn, double &q0,
+                                       double &q1, double &q2)
+{
+    double bx = Ds * cb - Dn * sb, by = Ds * sb + Dn * cb;
+    q0 = -bx * sb;
+    q1 = by * cb;
+    q2 = bx * cb - by * sb;
+}
+
+// Point kernel K (3 x 3, row = stress component, column = charge
+// component) at offset (x, y), per unit element length: the element
+// formulas with the element integral of -C ln r replaced by -C ln r.
+// Homogeneous of degree -2.
+__device__ __forceinline__ void point_kernel(double x, double y, double gc, double K[9])
+{
+    double x2 = x * x, y2 = y * y, r2 = x2 + y2;
+    double k = -gc / (r2 * r2 * r2);
+    double A = -x2 * x2 + 6.0 * x2 * y2 - y2 * y2;
+    double B = 3.0 * y2 * y2 - 6.0 * x2 * y2 - x2 * x2;
+    double Cc = 3.0 * x2 * x2 - 6.0 * x2 * y2 - y2 * y2;
+    double P = 6.0 * x2 * x * y - 2.0 * x * y2 * y;
+    double Q = 6.0 * x * y2 * y - 2.0 * x2 * x * y;
+    K[0] = k * Cc; K[1] = k * A; K[2] = k * P;
+    K[3] = k * A;  K[4] = k * B; K[5] = k * Q;
+    K[6] = k * P;  K[7] = k * Q; K[8] = k * A;
+}
+
+}  // namespace fmddm

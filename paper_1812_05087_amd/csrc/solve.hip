@@ -1,0 +1,284 @@
+// Right-hand side, restarted GMRES and stress intensity factors on the
+// device (Section 4; eq. 2.6).
+//
+// GMRES(m) with x0 taken from the caller, classical Gram-Schmidt applied
+// twice (two passes of V^T w and w -= V h), Givens rotations on the
+// Hessenberg column, all in FP64 on the device.  The host only reads the
+// running residual estimate after each Arnoldi step to decide when to stop.
+// At every restart the residual is recomputed from b - A x.
+#include "elem.h"
+#include "internal.h"
+
+#include <cmath>
+
+namespace fmddm {
+namespace {
+
+__global__ void k_rhs(int n, const double *__restrict__ cb, const double *__restrict__ sb,
+                      const double *__restrict__ pf, double SH, double Sh, double *__restrict__ rhs)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double ts, tn;
+    traction(cb[i], sb[i], -SH, -Sh, 0.0, ts, tn);
+    rhs[2 * i] = -ts;
+    rhs[2 * i + 1] = -pf[i] - tn;
+}
+
+constexpr int RT = 256;
+
+// Block-level fixed-order sum.
+__device__ double block_sum(double v, double *red)
+{
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = RT / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// out[i] = V_i . w for i < k (one block per i).
+__global__ __launch_bounds__(RT) void k_dots(int m, int k, const double *__restrict__ V, int ldv,
+                                             const double *__restrict__ w, double *__restrict__ out)
+{
+    __shared__ double red[RT];
+    int i = blockIdx.x;
+    if (i >= k) return;
+    const double *v = V + (size_t)i * ldv;
+    double s = 0.0;
+    for (int t = threadIdx.x; t < m; t += RT) s += v[t] * w[t];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) out[i] = s;
+}
+
+// w += sign * sum_{i<k} h[i] V_i
+__global__ void k_vupdate(int m, int k, const double *__restrict__ V, int ldv,
+                          const double *__restrict__ h, double sign, double *__restrict__ w)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m) return;
+    double s = 0.0;
+    for (int i = 0; i < k; ++i) s += h[i] * V[(size_t)i * ldv + t];
+    w[t] += sign * s;
+}
+
+// Single-block norm: out = ||w||.
+__global__ __launch_bounds__(RT) void k_norm(int m, const double *__restrict__ w, double *__restrict__ out)
+{
+    __shared__ double red[RT];
+    double s = 0.0;
+    for (int t = threadIdx.x; t < m; t += RT) s += w[t] * w[t];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) *out = sqrt(s);
+}
+
+// v = src / *nrm (v = 0 when the norm vanishes)
+__global__ void k_scale(int m, const double *__restrict__ src, const double *__restrict__ nrm,
+                        double *__restrict__ v)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m) return;
+    double d = *nrm;
+    v[t] = d != 0.0 ? src[t] / d : 0.0;
+}
+
+__global__ void k_residual(int m, const double *__restrict__ b, const double *__restrict__ Ax,
+                           double *__restrict__ r)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < m) r[t] = b[t] - Ax[t];
+}
+
+// Scalar workspace layout (doubles): g[m+1] | cs[m] | sn[m] | H[(m+1) x m]
+// column-major | h1[m+1] | h2[m+1] | y[m] | nrm | est
+struct SW {
+    int m;
+    __host__ __device__ int g() const { return 0; }
+    __host__ __device__ int cs() const { return m + 1; }
+    __host__ __device__ int sn() const { return 2 * m + 1; }
+    __host__ __device__ int H() const { return 3 * m + 1; }
+    __host__ __device__ int h1() const { return 3 * m + 1 + (m + 1) * m; }
+    __host__ __device__ int h2() const { return h1() + m + 1; }
+    __host__ __device__ int y() const { return h2() + m + 1; }
+    __host__ __device__ int nrm() const { return y() + m; }
+    __host__ __device__ int est() const { return nrm() + 1; }
+    __host__ __device__ int size() const { return est() + 1; }
+};
+
+// g = (beta, 0, ...), est = beta
+__global__ void k_cycle_start(SW s, double *__restrict__ sc)
+{
+    double beta = sc[s.nrm()];
+    for (int i = 0; i <= s.m; ++i) sc[s.g() + i] = 0.0;
+    sc[s.g()] = beta;
+    sc[s.est()] = beta;
+}
+
+// Column j of the Hessenberg matrix from the two Gram-Schmidt passes and the
+// new norm; previous rotations applied, new rotation formed, residual
+// estimate |g_{j+1}| updated.
+__global__ void k_givens(SW s, int j, double *__restrict__ sc)
+{
+    double *H = sc + s.H() + (size_t)j * (s.m + 1);
+    double *cs = sc + s.cs(), *sn = sc + s.sn(), *g = sc + s.g();
+    for (int i = 0; i <= j; ++i) H[i] = sc[s.h1() + i] + sc[s.h2() + i];
+    H[j + 1] = sc[s.nrm()];
+    for (int i = 0; i < j; ++i) {
+        double h0 = H[i], hh = H[i + 1];
+        H[i] = cs[i] * h0 + sn[i] * hh;
+        H[i + 1] = -sn[i] * h0 + cs[i] * hh;
+    }
+    double h0 = H[j], hh = H[j + 1];
+    double den = sqrt(h0 * h0 + hh * hh);
+    cs[j] = den == 0.0 ? 1.0 : h0 / den;
+    sn[j] = den == 0.0 ? 0.0 : hh / den;
+    H[j] = den;
+    H[j + 1] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    sc[s.est()] = fabs(g[j + 1]);
+}
+
+// y = R^{-1} g over the first k columns.
+__global__ void k_backsolve(SW s, int k, double *__restrict__ sc)
+{
+    const double *H = sc + s.H();
+    double *y = sc + s.y();
+    for (int i = k - 1; i >= 0; --i) {
+        double v = sc[s.g() + i];
+        for (int c = i + 1; c < k; ++c) v -= H[(size_t)c * (s.m + 1) + i] * y[c];
+        y[i] = v / H[(size_t)i * (s.m + 1) + i];
+    }
+}
+
+__global__ void k_sif(const double *__restrict__ D, const double *__restrict__ a, int64_t e, double E,
+                      double nu, double *__restrict__ out)
+{
+    double f = 0.806 * E / (4.0 * (1.0 - nu * nu)) * sqrt(M_PI / (2.0 * a[e]));
+    out[0] = f * D[2 * e + 1];
+    out[1] = f * D[2 * e];
+}
+
+}  // namespace
+
+void rhs_build(fmddm_ctx *ctx, fmddm_tree *t, const double *pf, double SH, double Sh, double *rhs)
+{
+    int n = (int)t->n;
+    hipLaunchKernelGGL(k_rhs, dim3(cdiv(n, 256)), dim3(256), 0, ctx->stream, n, t->ocb.p, t->osb.p, pf,
+                       SH, Sh, rhs);
+    FM_CHECK_LAUNCH();
+}
+
+void apply_mode(fmddm_ctx *ctx, fmddm_tree *t, int mode, const double *D, double *out)
+{
+    switch (mode) {
+    case FMDDM_APPLY_FMM: fmm_apply(ctx, t, D, out); break;
+    case FMDDM_APPLY_DIRECT: direct_apply(ctx, t, D, out); break;
+    case FMDDM_APPLY_DENSE: dense_apply(ctx, t, D, out); break;
+    default: throw Error{FMDDM_EINVAL, "unknown apply mode"};
+    }
+}
+
+void sif_eval(fmddm_ctx *ctx, fmddm_tree *t, const double *D, int64_t e, double *KI, double *KII)
+{
+    DBuf<double> o;
+    o.alloc(2);
+    hipLaunchKernelGGL(k_sif, dim3(1), dim3(1), 0, ctx->stream, D, t->oa.p, e, ctx->prm.E, ctx->prm.nu, o.p);
+    FM_CHECK_LAUNCH();
+    double h[2];
+    FM_HIP(hipMemcpyAsync(h, o.p, 16, hipMemcpyDeviceToHost, ctx->stream));
+    FM_HIP(hipStreamSynchronize(ctx->stream));
+    *KI = h[0];
+    *KII = h[1];
+}
+
+fmddm_status gmres_solve(fmddm_ctx *ctx, fmddm_tree *t, int mode, const double *b, double *x,
+                         fmddm_solve_info *info)
+{
+    hipStream_t st = ctx->stream;
+    const int m = ctx->prm.restart;
+    const int n2 = (int)(2 * t->n);
+    const int ldv = (n2 + 63) / 64 * 64;
+    SW s{m};
+    if (t->gm_restart != m || !t->gm_V.p) {
+        t->gm_V.alloc((size_t)(m + 1) * ldv);
+        t->gm_w.alloc(ldv);
+        t->gm_r.alloc(ldv);
+        t->gm_sc.alloc(s.size());
+        t->gm_restart = m;
+    }
+    double *V = t->gm_V.p, *w = t->gm_w.p, *r = t->gm_r.p, *sc = t->gm_sc.p;
+    int gb = cdiv(n2, 256);
+    // ||b||
+    hipLaunchKernelGGL(k_norm, dim3(1), dim3(RT), 0, st, n2, b, sc + s.nrm());
+    FM_CHECK_LAUNCH();
+    double bnorm = 0.0;
+    FM_HIP(hipMemcpyAsync(&bnorm, sc + s.nrm(), 8, hipMemcpyDeviceToHost, st));
+    FM_HIP(hipStreamSynchronize(st));
+    info->iters = 0;
+    info->restarts = 0;
+    info->converged = 0;
+    info->relres = 0.0;
+    if (bnorm == 0.0) {
+        FM_HIP(hipMemsetAsync(x, 0, n2 * 8, st));
+        FM_HIP(hipStreamSynchronize(st));
+        info->converged = 1;
+        return FMDDM_OK;
+    }
+    const double tol = ctx->prm.tol;
+    int it = 0;
+    for (;;) {
+        // true residual
+        apply_mode(ctx, t, mode, x, w);
+        hipLaunchKernelGGL(k_residual, dim3(gb), dim3(256), 0, st, n2, b, w, r);
+        FM_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_norm, dim3(1), dim3(RT), 0, st, n2, r, sc + s.nrm());
+        FM_CHECK_LAUNCH();
+        double beta = 0.0;
+        FM_HIP(hipMemcpyAsync(&beta, sc + s.nrm(), 8, hipMemcpyDeviceToHost, st));
+        FM_HIP(hipStreamSynchronize(st));
+        info->relres = beta / bnorm;
+        if (!std::isfinite(beta)) throw Error{FMDDM_EDEVICE, "non-finite residual"};
+        if (beta <= tol * bnorm) {
+            info->converged = 1;
+            break;
+        }
+        if (it >= ctx->prm.maxit) break;
+        ++info->restarts;
+        hipLaunchKernelGGL(k_scale, dim3(gb), dim3(256), 0, st, n2, r, sc + s.nrm(), V);
+        hipLaunchKernelGGL(k_cycle_start, dim3(1), dim3(1), 0, st, s, sc);
+        FM_CHECK_LAUNCH();
+        int k = 0;
+        for (int j = 0; j < m && it < ctx->prm.maxit; ++j) {
+            double *vj = V + (size_t)j * ldv, *vn = V + (size_t)(j + 1) * ldv;
+            apply_mode(ctx, t, mode, vj, w);
+            ++it;
+            // two classical Gram-Schmidt passes
+            hipLaunchKernelGGL(k_dots, dim3(j + 1), dim3(RT), 0, st, n2, j + 1, V, ldv, w, sc + s.h1());
+            hipLaunchKernelGGL(k_vupdate, dim3(gb), dim3(256), 0, st, n2, j + 1, V, ldv, sc + s.h1(), -1.0, w);
+            hipLaunchKernelGGL(k_dots, dim3(j + 1), dim3(RT), 0, st, n2, j + 1, V, ldv, w, sc + s.h2());
+            hipLaunchKernelGGL(k_vupdate, dim3(gb), dim3(256), 0, st, n2, j + 1, V, ldv, sc + s.h2(), -1.0, w);
+            hipLaunchKernelGGL(k_norm, dim3(1), dim3(RT), 0, st, n2, w, sc + s.nrm());
+            hipLaunchKernelGGL(k_scale, dim3(gb), dim3(256), 0, st, n2, w, sc + s.nrm(), vn);
+            hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, st, s, j, sc);
+            FM_CHECK_LAUNCH();
+            k = j + 1;
+            double est[2];
+            FM_HIP(hipMemcpyAsync(est, sc + s.nrm(), 16, hipMemcpyDeviceToHost, st));
+            FM_HIP(hipStreamSynchronize(st));
+            if (est[1] <= tol * bnorm || est[0] == 0.0) break;
+        }
+        hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(1), 0, st, s, k, sc);
+        hipLaunchKernelGGL(k_vupdate, dim3(gb), dim3(256), 0, st, n2, k, V, ldv, sc + s.y(), 1.0, x);
+        FM_CHECK_LAUNCH();
+    }
+    info->iters = it;
+    FM_HIP(hipStreamSynchronize(st));
+    return info->converged ? FMDDM_OK : FMDDM_ENOTCONV;
+}
+
+}  // namespace fmddm
