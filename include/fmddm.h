@@ -184,6 +184,27 @@ fmddm_status fmddm_solve(fmddm_ctx *ctx, fmddm_tree *t, int mode, const double *
 fmddm_status fmddm_sif(fmddm_ctx *ctx, fmddm_tree *t, const double *D, int64_t elem,
                        double *KI, double *KII);
 
+/* Phases of one FMM product, for fmddm_profile. */
+typedef enum {
+    FMDDM_PH_PREP = 0,        /* D to tree order, source charges */
+    FMDDM_PH_P2M = 1,         /* leaf weights (eq. 3.6) */
+    FMDDM_PH_M2M = 2,         /* upward pass (eq. 3.7), all levels */
+    FMDDM_PH_M2L = 3,         /* interaction-list contraction (eq. 3.8) */
+    FMDDM_PH_DOWN = 4,        /* downward pass (eq. 3.10), all levels */
+    FMDDM_PH_NEAR = 5,        /* L2P + direct neighbour interactions (eq. 3.11) */
+    FMDDM_PH_COUNT = 6
+} fmddm_phase;
+
+/* Record HIP events on the context's stream around the phases whose bit
+ * (1 << fmddm_phase) is set in `mask`, for every following FMM product
+ * (0 disables).  Adds two event records per timed phase and product. */
+fmddm_status fmddm_profile(fmddm_ctx *ctx, unsigned mask);
+
+/* Elapsed milliseconds summed per phase (ms[FMDDM_PH_COUNT]) and the number
+ * of timed launches (count[FMDDM_PH_COUNT], may be NULL) since the previous
+ * read; resets the sums.  Synchronises the stream. */
+fmddm_status fmddm_profile_read(fmddm_ctx *ctx, double *ms, int64_t *count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -63,6 +63,8 @@ def lib():
         L.ora_direct_matvec.argtypes = [C.c_int64] + [_d] * 5 + [C.c_double] * 2 + [_d, _d]
         L.ora_direct_matvec_rows.argtypes = ([C.c_int64] + [_d] * 5 + [C.c_double] * 2
                                              + [_d, _d, C.c_int64, C.c_int64])
+        L.ora_direct_matvec_idx.argtypes = ([C.c_int64] + [_d] * 5 + [C.c_double] * 2
+                                            + [_d, C.c_int64, _i64, _d])
         L.ora_lu_solve.argtypes = [C.c_int64, _d, _d, _d]
         L.ora_gmres_dense.argtypes = [C.c_int64, _d, _d, _d, C.c_int, C.c_double, C.c_int,
                                       C.POINTER(C.c_int), _d]
@@ -203,6 +205,15 @@ def direct_matvec(g: Geometry, D, rows=None):
     return out
 
 
+def direct_matvec_rows(g: Geometry, D, idx):
+    """Rows of the exact product for receivers idx: array [len(idx), 2]."""
+    D = _f64(D)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    out = np.zeros(2 * len(idx))
+    lib().ora_direct_matvec_idx(g.n, *g.args(), g.G, g.nu, _p(D), len(idx), _p(idx, _i64), _p(out))
+    return out.reshape(-1, 2)
+
+
 def lu_solve(A, b):
     A = _f64(A)
     b = _f64(b)
@@ -308,3 +319,8 @@ class Tree:
         if rc != 0:
             raise RuntimeError("oracle FMM failed")
         return out
+
+
+def num_threads() -> int:
+    """Host threads the oracle's parallel loops use."""
+    return int(lib().ora_num_threads())

@@ -295,6 +295,31 @@ void ora_direct_matvec(int64_t n, const double *cx, const double *cy,
     ora_direct_matvec_rows(n, cx, cy, cb, sb, a, G, nu, D, out, 0, n);
 }
 
+/* Selected rows of the on-the-fly product: out[2k], out[2k+1] for
+ * receiver idx[k], k < nidx (for sampled checks at full size). */
+void ora_direct_matvec_idx(int64_t n, const double *cx, const double *cy,
+                           const double *cb, const double *sb, const double *a,
+                           double G, double nu, const double *D, int64_t nidx,
+                           const int64_t *idx, double *out)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t k = 0; k < nidx; ++k) {
+        int64_t i = idx[k];
+        double s = 0.0, t = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            double sg[3];
+            ora_elem_stress(cx[i], cy[i], cx[j], cy[j], cb[j], sb[j], a[j], G, nu,
+                            D[2 * j], D[2 * j + 1], sg);
+            double ts, tn;
+            ora_traction(cb[i], sb[i], sg, &ts, &tn);
+            s += ts;
+            t += tn;
+        }
+        out[2 * k] = s;
+        out[2 * k + 1] = t;
+    }
+}
+
 /* Dense matrix of the polynomial test kernel: element integrals by
  * 8-point Gauss-Legendre (exact for the degree-3 kernel). */
 void ora_dense_matrix_poly(int64_t n, const double *cx, const double *cy,
@@ -961,3 +986,11 @@ int ora_fmm_apply(const ora_tree *t, const double *cx, const double *cy,
     free(W); free(F); free(xb); free(gt); free(gw); free(Sx); free(Sy);
     return 0;
 }
+
+/* Threads the OpenMP loops above use (reporting only). */
+#ifdef _OPENMP
+#include <omp.h>
+int ora_num_threads(void) { return omp_get_max_threads(); }
+#else
+int ora_num_threads(void) { return 1; }
+#endif

@@ -29,7 +29,9 @@ EXPORTED = [
     "fmddm_default_params", "fmddm_create", "fmddm_destroy", "fmddm_last_error",
     "fmddm_build_tree", "fmddm_tree_free", "fmddm_tree_get_info", "fmddm_tree_export",
     "fmddm_tree_export_list", "fmddm_apply", "fmddm_rhs", "fmddm_solve", "fmddm_sif",
+    "fmddm_profile", "fmddm_profile_read",
 ]
+PHASES = ["prep", "p2m", "m2m", "m2l", "down", "near"]
 
 
 class FmddmError(RuntimeError):
@@ -93,6 +95,8 @@ def lib():
         L.fmddm_rhs.argtypes = [_vp, _vp, _vp, C.c_double, C.c_double, _vp]
         L.fmddm_solve.argtypes = [_vp, _vp, C.c_int, _vp, _vp, C.POINTER(SolveInfo)]
         L.fmddm_sif.argtypes = [_vp, _vp, _vp, C.c_int64, _d, _d]
+        L.fmddm_profile.argtypes = [_vp, C.c_uint]
+        L.fmddm_profile_read.argtypes = [_vp, _d, C.POINTER(C.c_int64)]
         for name in EXPORTED:
             f = getattr(L, name)
             if name not in ("fmddm_default_params", "fmddm_destroy", "fmddm_tree_free",
@@ -219,6 +223,18 @@ def fmddm_sif(ctx, tree, D, elem):
     KI, KII = C.c_double(), C.c_double()
     _check(lib().fmddm_sif(ctx, tree, _ptr(D), int(elem), C.byref(KI), C.byref(KII)), ctx)
     return KI.value, KII.value
+
+
+def fmddm_profile(ctx, mask):
+    return _check(lib().fmddm_profile(ctx, int(mask)), ctx)
+
+
+def fmddm_profile_read(ctx):
+    """{phase: (total_ms, launches)} since the previous read."""
+    ms = (C.c_double * len(PHASES))()
+    cnt = (C.c_int64 * len(PHASES))()
+    _check(lib().fmddm_profile_read(ctx, ms, cnt), ctx)
+    return {PHASES[i]: (ms[i], cnt[i]) for i in range(len(PHASES))}
 
 
 # --------------------------------------------------------------- convenience

@@ -252,4 +252,20 @@ fmddm_status fmddm_sif(fmddm_ctx *ctx, fmddm_tree *t, const double *D, int64_t e
     });
 }
 
+fmddm_status fmddm_profile(fmddm_ctx *ctx, unsigned mask)
+{
+    if (!ctx || mask >= (1u << FMDDM_PH_COUNT)) return FMDDM_EINVAL;
+    ctx->prof.mask = mask;
+    return FMDDM_OK;
+}
+
+fmddm_status fmddm_profile_read(fmddm_ctx *ctx, double *ms, int64_t *count)
+{
+    if (!ctx || !ms) return FMDDM_EINVAL;
+    return guarded(ctx, [&] {
+        ctx->prof.read(ctx->stream, ms, count);
+        return FMDDM_OK;
+    });
+}
+
 }  // extern "C"

@@ -534,6 +534,62 @@ double host_cheb_S(int p, int l, double u)
 
 }  // namespace
 
+Profiler::~Profiler()
+{
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+    for (auto &v : rec)
+        for (auto &pr : v) {
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
+        }
+}
+
+hipEvent_t Profiler::take()
+{
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    FM_HIP(hipEventCreate(&e));
+    return e;
+}
+
+void Profiler::begin(int ph, hipStream_t s, hipEvent_t &e0)
+{
+    e0 = nullptr;
+    if (!(mask >> ph & 1u)) return;
+    e0 = take();
+    FM_HIP(hipEventRecord(e0, s));
+}
+
+void Profiler::end(int ph, hipStream_t s, hipEvent_t e0)
+{
+    if (!e0) return;
+    hipEvent_t e1 = take();
+    FM_HIP(hipEventRecord(e1, s));
+    rec[ph].emplace_back(e0, e1);
+}
+
+void Profiler::read(hipStream_t s, double *ms, int64_t *count)
+{
+    FM_HIP(hipStreamSynchronize(s));
+    for (int ph = 0; ph < FMDDM_PH_COUNT; ++ph) {
+        double tot = 0.0;
+        for (auto &pr : rec[ph]) {
+            float t = 0.0f;
+            FM_HIP(hipEventElapsedTime(&t, pr.first, pr.second));
+            tot += t;
+            pool.push_back(pr.first);
+            pool.push_back(pr.second);
+        }
+        if (ms) ms[ph] = tot;
+        if (count) count[ph] = (int64_t)rec[ph].size();
+        rec[ph].clear();
+    }
+}
+
 void setup_cheb(fmddm_ctx *ctx)
 {
     int p = ctx->prm.p;
@@ -678,39 +734,53 @@ void fmm_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out)
     hipStream_t s = ctx->stream;
     int p = ctx->prm.p, Mp = ctx->m2l.Mp, n = (int)t->n;
     const Cheb &C = ctx->cheb;
+    Profiler &P = ctx->prof;
+    hipEvent_t e0;
+    P.begin(FMDDM_PH_PREP, s, e0);
     hipLaunchKernelGGL(k_prep, dim3(cdiv(n, 256)), dim3(256), 0, s, n, t->perm.p, D, t->scb.p,
                        t->ssb.p, t->Dsort.p, t->q.p);
     FM_CHECK_LAUNCH();
+    P.end(FMDDM_PH_PREP, s, e0);
     bool far = t->nV > 0;
     if (far) {
+        P.begin(FMDDM_PH_P2M, s, e0);
         hipLaunchKernelGGL(k_p2m, dim3(t->nleaf), dim3(P2M_T), 0, s, t->nleaf, t->dleaves.p, t->cpbeg.p,
                            t->cpend.p, t->ccx.p, t->ccy.p, t->chw.p, t->scx.p, t->scy.p, t->scb.p,
                            t->ssb.p, t->sa.p, t->q.p, C.tnode.p, C.gl_t.p, C.gl_w.p, p, Mp, t->Wexp.p);
         FM_CHECK_LAUNCH();
+        P.end(FMDDM_PH_P2M, s, e0);
+        P.begin(FMDDM_PH_M2M, s, e0);
         for (int l = t->nlevel - 2; l >= 0; --l) {
             int c0 = t->level_start[l], nc = t->level_start[l + 1] - c0;
             hipLaunchKernelGGL(k_m2m, dim3(nc), dim3(TT), 0, s, c0, nc, t->cleaf.p, t->cchild.p,
                                C.m2m.p, p, Mp, t->Wexp.p);
             FM_CHECK_LAUNCH();
         }
+        P.end(FMDDM_PH_M2M, s, e0);
+        P.begin(FMDDM_PH_M2L, s, e0);
         if (t->ntile) {
             hipLaunchKernelGGL(k_m2l_gemm, dim3(t->ntile, Mp / GM), dim3(256), 0, s, ctx->m2l.ops.p, Mp,
                                t->Wexp.p, t->tile_op.p, t->tile_beg.p, t->tile_end.p, t->pair_k.p,
                                t->pair_src.p, t->pair_scale.p, t->Zm2l.p);
             FM_CHECK_LAUNCH();
         }
+        P.end(FMDDM_PH_M2L, s, e0);
+        P.begin(FMDDM_PH_DOWN, s, e0);
         for (int l = 1; l < t->nlevel; ++l) {
             int c0 = t->level_start[l], nc = t->level_start[l + 1] - c0;
-            hipLaunchKernelGGL(k_down, dim3(nc), dim3(TT), 0, s, c0, nc, t->cparent.p, t->cix.p, t->ciy.p, t->loff[1].p, t->Zm2l.p, C.m2m.p,
-                               p, Mp, l >= 2 ? 1 : 0, t->Fexp.p);
+            hipLaunchKernelGGL(k_down, dim3(nc), dim3(TT), 0, s, c0, nc, t->cparent.p, t->cix.p, t->ciy.p,
+                               t->loff[1].p, t->Zm2l.p, C.m2m.p, p, Mp, l >= 2 ? 1 : 0, t->Fexp.p);
             FM_CHECK_LAUNCH();
         }
+        P.end(FMDDM_PH_DOWN, s, e0);
     }
+    P.begin(FMDDM_PH_NEAR, s, e0);
     hipLaunchKernelGGL(k_l2p_p2p, dim3(t->nleaf), dim3(PT), 0, s, t->nleaf, t->dleaves.p, t->cpbeg.p,
                        t->cpend.p, t->noff.p, t->nsrc.p, t->ccx.p, t->ccy.p, t->chw.p, t->scx.p, t->scy.p,
                        t->scb.p, t->ssb.p, t->sa.p, t->Dsort.p, t->perm.p, t->Fexp.p, C.tnode.p, p, Mp,
                        ctx->gc, far ? 1 : 0, out);
     FM_CHECK_LAUNCH();
+    P.end(FMDDM_PH_NEAR, s, e0);
 }
 
 }  // namespace fmddm

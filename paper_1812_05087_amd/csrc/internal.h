@@ -76,8 +76,23 @@ struct M2LOps {
 
 }  // namespace fmddm
 
+namespace fmddm {
+// Per-phase HIP-event timing of FMM products.
+struct Profiler {
+    unsigned mask = 0;
+    std::vector<hipEvent_t> pool;                      // free events
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> rec[FMDDM_PH_COUNT];
+    hipEvent_t take();
+    void begin(int ph, hipStream_t s, hipEvent_t &e0);
+    void end(int ph, hipStream_t s, hipEvent_t e0);
+    void read(hipStream_t s, double *ms, int64_t *count);
+    ~Profiler();
+};
+}  // namespace fmddm
+
 struct fmddm_ctx {
     fmddm_params prm;
+    fmddm::Profiler prof;
     hipStream_t stream = nullptr;
     int device = 0;
     std::string err;

@@ -1,0 +1,252 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Bars (written in each test):
+  - tree and U/V/W/X lists: bit-exact (integer work);
+  - exact products (direct, dense): <= 1e-12 relative, element by element
+    against the largest entry, at small sizes in full and at the C2 size
+    (20000 elements) on sampled rows;
+  - FMM against the oracle's FMM (same algorithm, different summation
+    order): <= 1e-12 relative;
+  - FMM (p = 20) against the exact product: <= 1e-6 relative (the bound the
+    method is held to), at full C2 size;
+  - solves: Sneddon opening and K_I within 1% (C1), solution within 1e-8 of
+    the oracle's Gaussian elimination.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1812_05087_amd as F  # noqa: E402
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def elementwise(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def compare_tree(prob, T):
+    ex = F.fmddm_tree_export(prob.ctx, prob.tree)
+    assert np.array_equal(ex["perm"], T.perm)
+    assert np.array_equal(ex["key"], T.key)
+    for k in ["level", "ix", "iy", "parent", "child", "pbeg", "pend", "isleaf"]:
+        assert ex[k].shape == getattr(T, k).shape, k
+        assert np.array_equal(ex[k], getattr(T, k)), k
+    assert np.array_equal(ex["root"], T.root)
+    for w, name in enumerate("UVWX"):
+        off, idx = F.fmddm_tree_export_list(prob.ctx, prob.tree, w)
+        o2, i2 = T.lists[name]
+        assert np.array_equal(off, o2), name
+        assert np.array_equal(idx, i2), name
+
+
+def geometry_cases():
+    out = {}
+    wl = W.random_fractures(7, 20, 30)
+    out["random600_leaf16"] = (wl, dict(leaf=16))
+    wl = W.random_fractures(9, 30, 25)
+    out["random750_leaf8"] = (wl, dict(leaf=8))
+    out["random750_leaf1_cap6"] = (wl, dict(leaf=1, max_level=6))
+    out["griffith256"] = (W.griffith(256), dict(leaf=32))
+    out["well5x40"] = (W.well_cluster(5, 40, 400.0, 30.0), dict(leaf=16))
+    wl = W.random_fractures(3, 13, 7)
+    out["ragged91_leaf5"] = (wl, dict(leaf=5))
+    return out
+
+
+CASES = geometry_cases()
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_tree_and_lists_bit_exact(name):
+    wl, kw = CASES[name]
+    g = O.Geometry.of(wl)
+    prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=wl.E, nu=wl.nu, p=4, **kw)
+    T = O.Tree(g, leaf=kw["leaf"], cap=kw.get("max_level", O.MAX_LEVEL))
+    compare_tree(prob, T)
+    prob.close()
+
+
+def test_tree_user_root_box_and_ties():
+    """User level-0 square; duplicated midpoints (crossing elements) keep
+    the element-index tie-break."""
+    x1 = np.array([0.0, 0.5, 1.0, 1.0, 2.0, 0.25])
+    y1 = np.array([0.0, 0.5, 0.0, 1.0, 2.0, 0.0])
+    x2 = np.array([1.0, 0.5, 2.0, 0.0, 3.0, 0.75])
+    y2 = np.array([1.0, -0.5, 0.0, 0.0, 1.0, 1.0])
+    g = O.Geometry(x1, y1, x2, y2)
+    box = (-1.0, -2.0, 8.0)
+    prob = F.Problem(x1, y1, x2, y2, leaf=1, use_root_box=1, root_x0=box[0], root_y0=box[1],
+                     root_L=box[2], p=4, kappa=0.0, max_level=10)
+    T = O.Tree(g, leaf=1, box=box, kappa=0.0, cap=10)
+    compare_tree(prob, T)
+    prob.close()
+
+
+def test_geometry_errors():
+    x1 = np.array([0.0, 1.0])
+    y1 = np.array([0.0, 0.0])
+    x2 = np.array([0.0, 2.0])  # first element has zero length
+    y2 = np.array([0.0, 0.0])
+    ctx = F.fmddm_create(F.fmddm_default_params())
+    with pytest.raises(F.FmddmError) as e:
+        F.fmddm_build_tree(ctx, x1, y1, x2, y2)
+    assert e.value.status == F.FMDDM_EGEOM
+    F.fmddm_destroy(ctx)
+    ctx = F.fmddm_create(F.fmddm_default_params(use_root_box=1, root_x0=0.0, root_y0=0.0, root_L=1.0))
+    with pytest.raises(F.FmddmError) as e:
+        F.fmddm_build_tree(ctx, np.array([5.0]), np.array([5.0]), np.array([6.0]), np.array([5.0]))
+    assert e.value.status == F.FMDDM_EGEOM
+    F.fmddm_destroy(ctx)
+
+
+def test_apply_rejects_aliasing():
+    wl = W.griffith(16)
+    prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, p=4)
+    v = prob.vec()
+    with pytest.raises(F.FmddmError):
+        F.fmddm_apply(prob.ctx, prob.tree, F.FMDDM_APPLY_FMM, v, v)
+    prob.close()
+
+
+@pytest.mark.parametrize("name", ["random600_leaf16", "random750_leaf8", "griffith256", "ragged91_leaf5"])
+def test_exact_products_match_oracle(name):
+    wl, kw = CASES[name]
+    g = O.Geometry.of(wl)
+    prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=wl.E, nu=wl.nu, p=4, **kw)
+    D = W.random_vector(11, g.n)
+    yo = O.dense_matrix(g) @ D
+    for mode in (F.FMDDM_APPLY_DIRECT, F.FMDDM_APPLY_DENSE):
+        y = prob.apply(prob.vec(D), mode).cpu().numpy()
+        assert elementwise(y, yo) < 1e-12, mode
+        assert rel(y, yo) < 1e-12, mode
+    prob.close()
+
+
+@pytest.mark.parametrize("name,p", [("random600_leaf16", 2), ("random600_leaf16", 6),
+                                    ("random750_leaf8", 4), ("random750_leaf8", 8),
+                                    ("ragged91_leaf5", 5), ("well5x40", 6)])
+def test_fmm_matches_oracle_fmm(name, p):
+    wl, kw = CASES[name]
+    g = O.Geometry.of(wl)
+    prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=wl.E, nu=wl.nu, p=p, **kw)
+    T = O.Tree(g, leaf=kw["leaf"], cap=kw.get("max_level", O.MAX_LEVEL))
+    D = W.random_vector(12, g.n)
+    y = prob.apply(prob.vec(D), F.FMDDM_APPLY_FMM).cpu().numpy()
+    yo = T.fmm(D, p)
+    assert rel(y, yo) < 1e-12
+    assert elementwise(y, yo) < 1e-11
+    prob.close()
+
+
+def test_fmm_degenerate_trees():
+    """One element, two elements, a single-leaf tree: no interaction list,
+    everything direct."""
+    for n in (1, 2, 7):
+        wl = W.griffith(n)
+        g = O.Geometry.of(wl)
+        prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=wl.E, nu=wl.nu, p=3, leaf=8)
+        D = W.random_vector(n, g.n)
+        y = prob.apply(prob.vec(D), F.FMDDM_APPLY_FMM).cpu().numpy()
+        yo = O.dense_matrix(g) @ D
+        assert elementwise(y, yo) < 1e-12
+        prob.close()
+
+
+def test_fmm_is_deterministic():
+    wl, kw = CASES["random750_leaf8"]
+    prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=wl.E, nu=wl.nu, p=6, **kw)
+    D = prob.vec(W.random_vector(4, wl.n))
+    a = prob.apply(D).cpu().numpy()
+    b = prob.apply(D).cpu().numpy()
+    assert np.array_equal(a, b)
+    prob.close()
+
+
+@pytest.fixture(scope="module")
+def c2():
+    wl = W.c2()
+    g = O.Geometry.of(wl)
+    prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=wl.E, nu=wl.nu, leaf=32, p=20)
+    yield wl, g, prob
+    prob.close()
+
+
+def test_c2_tree_bit_exact(c2):
+    wl, g, prob = c2
+    compare_tree(prob, O.Tree(g, leaf=32))
+
+
+def test_c2_products_full_size(c2):
+    """N = 20000, p = 20: direct product against oracle rows (sampled, at
+    1e-12), FMM against the direct product (1e-6) and dense (1e-6)."""
+    wl, g, prob = c2
+    D = W.random_vector(5, g.n)
+    Dd = prob.vec(D)
+    yd = prob.apply(Dd, F.FMDDM_APPLY_DIRECT).cpu().numpy().reshape(-1, 2)
+    rng = np.random.default_rng(0)
+    idx = np.unique(np.concatenate([rng.choice(g.n, 300, replace=False), [0, g.n - 1]]))
+    yo = O.direct_matvec_rows(g, D, idx)
+    assert elementwise(yd[idx], yo) < 1e-12
+    yf = prob.apply(Dd, F.FMDDM_APPLY_FMM).cpu().numpy().reshape(-1, 2)
+    assert rel(yf, yd) < 1e-6
+    assert elementwise(yf[idx], yo) < 1e-6
+
+
+def test_solve_griffith_c1():
+    """C1: GMRES(50), tol 1e-10, on each product; Sneddon within 1%, K_I by
+    eq. 2.6 within 1% of p sqrt(pi a); matches the oracle's LU."""
+    wl = W.c1()
+    g = O.Geometry.of(wl)
+    prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=wl.E, nu=wl.nu, tol=1e-10, restart=50)
+    b = prob.rhs(wl.pressure, 0.0, 0.0)
+    bo = O.rhs(g, wl.pressure, 0.0, 0.0)
+    assert elementwise(b.cpu().numpy(), bo) < 1e-15
+    xo = O.lu_solve(O.dense_matrix(g), bo)
+    w = 4 * (1 - g.nu ** 2) * wl.meta["p"] / g.E * np.sqrt(np.maximum(1 - g.cx ** 2, 0))
+    for mode in (F.FMDDM_APPLY_DENSE, F.FMDDM_APPLY_DIRECT, F.FMDDM_APPLY_FMM):
+        x, info = prob.solve(b, mode)
+        assert info["converged"] and info["relres"] <= 1e-10
+        xn = x.cpu().numpy()
+        assert rel(xn, xo) < 1e-8
+        assert rel(xn[1::2], w) < 0.01
+        KI, KII = F.fmddm_sif(prob.ctx, prob.tree, x, g.n - 1)
+        assert abs(KI / (wl.meta["p"] * np.sqrt(np.pi)) - 1) < 0.01
+        assert abs(KII) < 1e-6 * KI
+    prob.close()
+
+
+def test_solve_random_matches_oracle():
+    wl = W.random_fractures(21, 12, 25)
+    g = O.Geometry.of(wl)
+    prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=wl.E, nu=wl.nu, leaf=16, p=12, tol=1e-12)
+    b = prob.rhs(wl.pressure, wl.SH, wl.Sh)
+    bo = O.rhs(g, wl.pressure, wl.SH, wl.Sh)
+    assert elementwise(b.cpu().numpy(), bo) < 1e-15
+    xo = O.lu_solve(O.dense_matrix(g), bo)
+    x, info = prob.solve(b, F.FMDDM_APPLY_FMM)
+    assert info["converged"]
+    assert rel(x.cpu().numpy(), xo) < 1e-6
+    x2, info2 = prob.solve(b, F.FMDDM_APPLY_DIRECT)
+    assert rel(x2.cpu().numpy(), xo) < 1e-9
+    prob.close()
+
+
+def test_solve_maxit_reports_not_converged():
+    wl = W.random_fractures(21, 12, 25)
+    prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=wl.E, nu=wl.nu, leaf=16, p=6, tol=1e-14, maxit=3)
+    b = prob.rhs(wl.pressure, wl.SH, wl.Sh)
+    x, info = prob.solve(b, F.FMDDM_APPLY_FMM)
+    assert info["status"] == F.FMDDM_ENOTCONV and not info["converged"]
+    assert info["iters"] == 3
+    prob.close()
