@@ -35,12 +35,34 @@ PEAK = {  # MI355X published peaks
 FLOP_PER_PAIR = 78
 
 
-def phase_work(info, p):
-    """Algorithmic work of one launch set of each FMM phase."""
+def phase_work(info, p, tree, rank, svd):
+    """Algorithmic work of one launch set of each FMM phase:
+    (bound, amount, unit, peak).  Flops count +,-,* as 1 and a fused
+    multiply-add as 2; bytes are the compulsory HBM traffic."""
+    n = info["n"]
     M = 3 * p * p
+    lev, leaf = tree["level"], tree["isleaf"]
+    parents = int(((lev >= 2) & (leaf == 0)).sum())
+    nfar, nV = info["nfar"], info["nV"]
+    if svd:
+        m2l = 2.0 * rank * M * nfar * 2 + 2.0 * rank * rank * nV
+    else:
+        m2l = 2.0 * M * M * nV
     return {
-        # eq. 3.8: one (3p^2 x 3p^2) operator times a 3p^2 vector per V pair
-        "m2l": ("mfma", 2.0 * M * M * info["nV"], "TFLOP/s", PEAK["fp64_mfma_TFLOPs"]),
+        # D in, D and charges out in tree order (+ permutation, orientation)
+        "prep": ("hbm", 76.0 * n, "GB/s", PEAK["hbm_GBps"]),
+        # per-element anterpolation weights streamed once, charges, leaf weights
+        "p2m": ("hbm", 8.0 * p * p * n + 24.0 * n + 8.0 * M * info["nleaf"], "GB/s", PEAK["hbm_GBps"]),
+        # two separable p x p transfers per child and component
+        "m2m": ("alu", 48.0 * p ** 3 * parents, "TFLOP/s", PEAK["fp64_vector_TFLOPs"]),
+        # eq. 3.8: per V pair one operator product (compressed: r x r, plus the
+        # projections in and out of the r-dimensional space per cell)
+        "m2l": ("mfma", m2l, "TFLOP/s", PEAK["fp64_mfma_TFLOPs"]),
+        # eqs. 3.10-3.11: every (midpoint, ancestor) pair evaluates that
+        # ancestor's field there: two barycentric interpolants (about 6p
+        # each) and the 3-component p x p contraction (6p^2 + 6p)
+        "down": ("alu", (6.0 * p * p + 18.0 * p) * info["l2p_pairs"], "TFLOP/s",
+                 PEAK["fp64_vector_TFLOPs"]),
         "near": ("alu", float(FLOP_PER_PAIR) * info["near_pairs"], "TFLOP/s", PEAK["fp64_vector_TFLOPs"]),
     }
 
@@ -66,20 +88,22 @@ def traffic_for(phase):
     return d.get("phases", {}).get(phase, {}).get("bytes_per_launch")
 
 
-def cpu_baseline(wl, D, rows):
-    """The oracle's exact on-the-fly product, all host cores, on the first
-    `rows` receivers of the workload; scaled to full products per second."""
-    import numpy as np
+def cpu_baseline(wl, D, seconds):
+    """The oracle's exact on-the-fly product of the whole workload on all
+    host cores, repeated for about `seconds` of wall time."""
     import oracle as O
     g = O.Geometry.of(wl)
-    O.direct_matvec_rows(g, D, np.arange(16))  # load/warm
-    t0 = time.perf_counter()
-    O.direct_matvec_rows(g, D, np.arange(rows))
-    dt = time.perf_counter() - t0
-    full = dt * g.n / rows
-    return {"value": 1.0 / full, "unit": "matvecs/s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"exact on-the-fly product (oracle), receivers 0..{rows - 1} of {g.n} "
-                      f"({dt:.2f} s wall), scaled to one full product"}
+    O.direct_matvec_rows(g, D, [0])  # load the library
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        O.direct_matvec(g, D)
+        reps += 1
+        dt = time.perf_counter() - t0
+        if dt >= seconds:
+            break
+    return {"value": reps / dt, "unit": "matvecs/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"oracle exact on-the-fly product of the full workload (N={g.n}), "
+                      f"{reps} products in {dt:.1f} s wall"}
 
 
 def main():
@@ -90,7 +114,9 @@ def main():
     ap.add_argument("--p", type=int, default=20)
     ap.add_argument("--leaf", type=int, default=32)
     ap.add_argument("--exact-steps", type=int, default=20)
-    ap.add_argument("--cpu-rows", type=int, default=4000)
+    ap.add_argument("--m2l", choices=["svd", "dense"], default="svd")
+    ap.add_argument("--m2l-tol", type=float, default=1e-12)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
     args = ap.parse_args()
@@ -109,7 +135,9 @@ def main():
     wl = W.c2()
     n = wl.n
     t0 = time.perf_counter()
-    prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=wl.E, nu=wl.nu, leaf=args.leaf, p=args.p)
+    svd = args.m2l == "svd"
+    prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=wl.E, nu=wl.nu, leaf=args.leaf, p=args.p,
+                     m2l=F.FMDDM_M2L_SVD if svd else F.FMDDM_M2L_DENSE, m2l_tol=args.m2l_tol)
     torch.cuda.synchronize()
     tree_ms = (time.perf_counter() - t0) * 1e3
     info = prob.info
@@ -160,13 +188,20 @@ def main():
             y_ref = o.cpu().numpy()
     err = float(np.linalg.norm(y_fmm - y_ref) / np.linalg.norm(y_ref))
 
-    work = phase_work(info, args.p)
-    roof = None
-    if dom in work:
-        bound, amount, unit, peak = work[dom]
-        achieved = amount / (dom_ms * 1e-3) / 1e12
-        roof = {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak, "unit": unit,
-                "frac": achieved / peak, "traffic": traffic_for(dom), "avg_launch_ms": dom_ms}
+    info = F.fmddm_tree_get_info(prob.ctx, prob.tree)
+    tree = F.fmddm_tree_export(prob.ctx, prob.tree)
+    work = phase_work(info, args.p, tree, info["m2l_rank"], svd)
+    scale = {"GB/s": 1e9, "TFLOP/s": 1e12}
+    phases = {}
+    for ph, (bound, amount, unit, peak) in work.items():
+        ms = phase_ms.get(ph, 0.0)
+        ach = amount / (ms * 1e-3) / scale[unit] if ms > 0 else None
+        phases[ph] = {"ms": ms, "bound": bound, "work": amount, "achieved": ach, "unit": unit,
+                      "frac": ach / peak if ach else None}
+    bound, amount, unit, peak = work[dom]
+    achieved = amount / (dom_ms * 1e-3) / scale[unit]
+    roof = {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": achieved / peak, "traffic": traffic_for(dom), "avg_launch_ms": dom_ms}
 
     line = {
         "metric": "FMM-DDM matvecs/s at N=20k vs dense; served solves/s + p99 latency",
@@ -183,7 +218,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "C2: 200 random pressurized fractures x 100 elements, N=20000, "
                                "seed 2, FP64 FMM leaf 32 p=20",
-                   "N": n, "leaf": args.leaf, "p": args.p},
+                   "N": n, "leaf": args.leaf, "p": args.p, "m2l": args.m2l,
+                   "m2l_tol": args.m2l_tol if svd else None, "m2l_rank": info["m2l_rank"]},
         "vs_dense": {
             "dense_matvecs_per_s": exact.get("dense"),
             "direct_matvecs_per_s": exact.get("direct"),
@@ -191,14 +227,15 @@ def main():
             "fmm_over_direct": value / exact["direct"],
             "fmm_rel_err_vs_exact": err,
         },
-        "phase_ms": phase_ms,
+        "phases": phases,
         "tree_build_ms": tree_ms,
         "first_product_setup_ms": setup_ms,
-        "tree": {k: info[k] for k in ("ncell", "nleaf", "nlevel", "nV", "near_pairs")},
+        "tree": {k: info[k] for k in ("ncell", "nleaf", "nlevel", "nV", "nfar", "near_pairs",
+                                      "l2p_pairs")},
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(wl, Dh, args.cpu_rows)
+        line["cpu_baseline"] = cpu_baseline(wl, Dh, args.cpu_seconds)
     prob.close()
     print(json.dumps(line), flush=True)
 

@@ -93,7 +93,9 @@ typedef struct {
     int32_t nlevel;           /* deepest level + 1 */
     int64_t nU, nV, nW, nX;   /* list lengths (sum over cells) */
     int64_t near_pairs;       /* directly evaluated point pairs per product */
-    int64_t m2l_rank;         /* M2L rank (3p^2 when uncompressed) */
+    int64_t l2p_pairs;        /* (midpoint, ancestor cell) interpolations per product */
+    int64_t nfar;             /* cells at level >= 2 (those with interaction lists) */
+    int64_t m2l_rank;         /* M2L rank (3p^2 when uncompressed; 0 before the first product) */
     double root_x0, root_y0, root_L;
     int64_t device_bytes;     /* device memory held by the tree */
 } fmddm_tree_info;
@@ -190,8 +192,8 @@ typedef enum {
     FMDDM_PH_P2M = 1,         /* leaf weights (eq. 3.6) */
     FMDDM_PH_M2M = 2,         /* upward pass (eq. 3.7), all levels */
     FMDDM_PH_M2L = 3,         /* interaction-list contraction (eq. 3.8) */
-    FMDDM_PH_DOWN = 4,        /* downward pass (eq. 3.10), all levels */
-    FMDDM_PH_NEAR = 5,        /* L2P + direct neighbour interactions (eq. 3.11) */
+    FMDDM_PH_DOWN = 4,        /* downward pass and L2P (eqs. 3.10-3.11, far part) */
+    FMDDM_PH_NEAR = 5,        /* direct neighbour interactions (eq. 3.11, near part) */
     FMDDM_PH_COUNT = 6
 } fmddm_phase;
 

@@ -18,12 +18,13 @@ FLAGS = [
     "-Wno-unused-command-line-argument",
     "-I", os.path.join(ROOT, "include"),
 ]
+LIBS = ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
 
 
 def build(verbose: bool = False) -> str:
     """Always recompiles; the library is written atomically."""
     out = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, *[os.path.join(CSRC, s) for s in SOURCES], "-o", out]
+    cmd = [HIPCC, *FLAGS, *[os.path.join(CSRC, s) for s in SOURCES], "-o", out, *LIBS]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

@@ -44,6 +44,7 @@ const char *check_params(const fmddm_params *p)
     if (p->max_level < 0 || p->max_level > 30) return "max_level must lie in [0, 30]";
     if (!(p->kappa >= 0.0)) return "kappa must be >= 0";
     if (p->m2l != FMDDM_M2L_DENSE && p->m2l != FMDDM_M2L_SVD) return "unknown m2l mode";
+    if (p->m2l == FMDDM_M2L_SVD && !(p->m2l_tol > 0.0 && p->m2l_tol < 1.0)) return "m2l_tol must lie in (0, 1)";
     if (p->use_root_box && !(p->root_L > 0.0)) return "root box side must be positive";
     if (p->restart < 1 || p->restart > 1000) return "restart must lie in [1, 1000]";
     if (p->maxit < 0) return "maxit must be >= 0";
@@ -78,7 +79,6 @@ fmddm_status fmddm_create(const fmddm_params *p, void *hip_stream, fmddm_ctx **o
     *out = nullptr;
     if (!p) return FMDDM_EINVAL;
     if (check_params(p)) return FMDDM_EINVAL;
-    if (p->m2l == FMDDM_M2L_SVD) return FMDDM_EUNSUPPORTED;
     fmddm_ctx *ctx = new (std::nothrow) fmddm_ctx();
     if (!ctx) return FMDDM_ENOMEM;
     ctx->prm = *p;
@@ -90,6 +90,9 @@ fmddm_status fmddm_create(const fmddm_params *p, void *hip_stream, fmddm_ctx **o
     double G = p->E / (2.0 * (1.0 + p->nu));
     ctx->gc = G / (2.0 * M_PI * (1.0 - p->nu));
     fmddm_status st = guarded(ctx, [&] {
+        FM_HIP(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+        FM_HIP(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+        FM_HIP(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
         fmddm::setup_cheb(ctx);
         return FMDDM_OK;
     });
@@ -148,7 +151,9 @@ fmddm_status fmddm_tree_get_info(fmddm_ctx *ctx, const fmddm_tree *t, fmddm_tree
     info->nW = t->h_loff[2].empty() ? 0 : t->h_loff[2].back();
     info->nX = t->h_loff[3].empty() ? 0 : t->h_loff[3].back();
     info->near_pairs = t->near_pairs;
-    info->m2l_rank = 3 * ctx->prm.p * ctx->prm.p;
+    info->l2p_pairs = t->l2p_pairs;
+    for (int c = 0; c < t->ncell; ++c) info->nfar += t->h_level[c] >= 2;
+    info->m2l_rank = ctx->m2l.ready ? ctx->m2l.r : 0;
     info->root_x0 = t->x0;
     info->root_y0 = t->y0;
     info->root_L = t->L;
@@ -157,7 +162,8 @@ fmddm_status fmddm_tree_get_info(fmddm_ctx *ctx, const fmddm_tree *t, fmddm_tree
     add(t->ocx.bytes() * 5); add(t->scx.bytes() * 5); add(t->perm.bytes()); add(t->key.bytes());
     add(t->clevel.bytes() * 8); add(t->cmk.bytes()); add(t->ccx.bytes() * 3);
     for (int w = 0; w < 4; ++w) { add(t->loff[w].bytes()); add(t->lidx[w].bytes()); }
-    add(t->noff.bytes()); add(t->nsrc.bytes()); add(t->Wexp.bytes()); add(t->Fexp.bytes());
+    add(t->noff.bytes()); add(t->nsrc.bytes()); add(t->Wexp.bytes()); add(t->Gexp.bytes());
+    add(t->What.bytes()); add(t->Ghat.bytes()); add(t->p2m_mat.bytes());
     add(t->Zm2l.bytes()); add(t->q.bytes()); add(t->Dsort.bytes()); add(t->Adense.bytes());
     add(t->gm_V.bytes()); add(t->gm_w.bytes()); add(t->gm_r.bytes());
     info->device_bytes = b;

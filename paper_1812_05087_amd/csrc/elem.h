@@ -20,6 +20,18 @@
 
 namespace fmddm {
 
+// 1/x to full double precision: the hardware reciprocal estimate refined by
+// two Newton steps (each doubles the correct bits).  Cheaper than the
+// correctly rounded division sequence; within an ulp or two of it.
+__device__ __forceinline__ double recip(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+
 // Adds the global-frame stress (sxx, syy, sxy) at (X, Y) from the element
 // (cx, cy, cb = cos beta, sb = sin beta, a) with DDs (Ds, Dn).
 // gc = 2 G C = G / (2 pi (1 - nu)).
@@ -32,8 +44,8 @@ __device__ __forceinline__ void elem_stress_add(double X, double Y, double cx, d
     double x = dx * cb + dy * sb;
     double y = dy * cb - dx * sb;
     double xm = x - a, xp = x + a, y2 = y * y;
-    double i1 = 1.0 / (xm * xm + y2);
-    double i2 = 1.0 / (xp * xp + y2);
+    double i1 = recip(xm * xm + y2);
+    double i2 = recip(xp * xp + y2);
     double fxy = y * (i1 - i2);
     double fyy = xp * i2 - xm * i1;
     double j1 = i1 * i1, j2 = i2 * i2;

@@ -4,29 +4,40 @@
 // index c * p^2 + l * p + m for component c and Chebyshev node (l, m) of the
 // cell's square.  Multipole weights W carry the three charge components
 // (b_x n_x, b_y n_y, b_x n_y + b_y n_x) integrated against the interpolants;
-// local fields F carry (sxx, syy, sxy).
+// M2L fields G carry (sxx, syy, sxy).
 //
 // Passes of one product:
 //   prep      D (caller order) -> D and charges in tree order
-//   p2m       leaf weights, eq. 3.6; each element integrated along its
-//             length with p-point Gauss-Legendre (exact: the interpolant on
-//             a straight segment is a polynomial of degree 2(p-1))
+//   p2m       leaf weights, eq. 3.6.  Each element's anterpolation weights
+//             (its p-point Gauss-Legendre integral of the interpolants, exact
+//             for a straight segment) depend on geometry only, so they are
+//             built once per tree; a product streams them (HBM bound)
 //   m2m       eq. 3.7, one level at a time, separable p x p transfers
-//   m2l       eq. 3.8 as a batched dense contraction on FP64 MFMA: V-list
-//             pairs grouped by relative offset, each group multiplied by the
-//             (unit-size) offset operator and scaled by h^-2 (the kernel is
-//             homogeneous of degree -2); one product per pair is stored
-//   down      eq. 3.10: sum of the pair products of the cell (fixed order,
-//             no atomics) plus the parent's field interpolated (L2L)
-//   l2p_p2p   eq. 3.11: local field at each midpoint plus direct element
-//             interactions over U, W and the X lists of the leaf's
-//             ancestors; projected to (shear, normal) traction and
-//             scattered to caller order
+//   m2l       eq. 3.8 as batched dense contractions on FP64 MFMA.  V-list
+//             pairs are grouped by relative offset; each group is multiplied
+//             by the unit-size operator of its offset and scaled by h^-2 (the
+//             kernel is homogeneous of degree -2).  Optionally the operators
+//             are compressed by a truncated SVD of all of them stacked
+//             (the reduction of Fong & Darve's black-box FMM): weights are
+//             projected on r singular vectors, multiplied by r x r operators,
+//             and expanded back.  One product per pair is stored and the
+//             pairs of a cell are summed in list order (no atomics).
+//   l2p       eqs. 3.10-3.11 (far part) in one launch: the M2L fields of a
+//             leaf and of all its ancestors evaluated at its midpoints (the
+//             downward chain of interpolations composes to exactly this)
+//   p2p       eq. 3.11, second term: exact element interactions over U, W
+//             and the X lists of the leaf and its ancestors, in work items
+//             of at most NEAR_CHUNK sources
+//   final     far + near partials summed per point in a fixed order,
+//             projected to (shear, normal) traction, caller order.
 #include "elem.h"
 #include "internal.h"
 
-#include <cmath>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
 #include <algorithm>
+#include <cmath>
 
 namespace fmddm {
 namespace {
@@ -62,7 +73,8 @@ __global__ void k_prep(int n, const int *__restrict__ perm, const double *__rest
     q[3 * i + 2] = q2;
 }
 
-// S_p(xbar_l, u) for all l into out[l]; tnode[l*p + k] = T_k(xbar_l).
+// S_p(xbar_l, u) by the Chebyshev sum 1/p + 2/p sum_k T_k(xbar_l) T_k(u);
+// tn_l[k] = T_k(xbar_l).  Valid (and stable) also outside [-1, 1].
 __device__ __forceinline__ double cheb_S(int p, const double *tn_l, double u)
 {
     double s = 0.0, t0 = 1.0, t1 = u;
@@ -75,37 +87,49 @@ __device__ __forceinline__ double cheb_S(int p, const double *tn_l, double u)
     return (1.0 + 2.0 * s) / p;
 }
 
-// ------------------------------------------------------------------ P2M
-constexpr int P2M_T = 256;
+// All p interpolants at u in [-1, 1] by the barycentric formula for
+// first-kind Chebyshev nodes (weights (-1)^l sin((2l+1) pi / 2p)).
+template <int P>
+__device__ __forceinline__ void bary(const double *xb, const double *bw, double u, double (&S)[P])
+{
+    double den = 0.0;
+    int hit = -1;
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        double d = u - xb[k];
+        if (d == 0.0) hit = k;
+        double t = bw[k] * recip(d);
+        S[k] = t;
+        den += t;
+    }
+    double id = recip(den);
+#pragma unroll
+    for (int k = 0; k < P; ++k) S[k] = hit < 0 ? S[k] * id : (k == hit ? 1.0 : 0.0);
+}
 
-__global__ __launch_bounds__(P2M_T) void k_p2m(int nleaf, const int *__restrict__ leaves,
-                                               const int *__restrict__ pbeg, const int *__restrict__ pend,
-                                               const double *__restrict__ ccx, const double *__restrict__ ccy,
-                                               const double *__restrict__ chw, const double *__restrict__ cx,
-                                               const double *__restrict__ cy, const double *__restrict__ cb,
-                                               const double *__restrict__ sb, const double *__restrict__ a,
-                                               const double *__restrict__ q, const double *__restrict__ tnode,
-                                               const double *__restrict__ glt, const double *__restrict__ glw,
-                                               int p, int Mp, double *__restrict__ W)
+// ---------------------------------------------------- P2M (per tree)
+// Anterpolation weights of every element: M_j[l][m] = integral over the
+// element of S(xbar_l, x) S(xbar_m, y), by p-point Gauss-Legendre.
+__global__ __launch_bounds__(256) void k_p2m_mats(int nleaf, const int *__restrict__ leaves,
+                                                  const int *__restrict__ pbeg, const int *__restrict__ pend,
+                                                  const double *__restrict__ ccx, const double *__restrict__ ccy,
+                                                  const double *__restrict__ chw, const double *__restrict__ cx,
+                                                  const double *__restrict__ cy, const double *__restrict__ cb,
+                                                  const double *__restrict__ sb, const double *__restrict__ a,
+                                                  const double *__restrict__ tnode, const double *__restrict__ glt,
+                                                  const double *__restrict__ glw, int p, double *__restrict__ Pm)
 {
     __shared__ double tn[MAXP * MAXP];
     __shared__ double Sx[MAXP * MAXP], Sy[MAXP * MAXP];  // [g][l]
     __shared__ double wg[MAXP];
-    int c = leaves[xcd_remap(blockIdx.x, nleaf)];
-    int tid = threadIdx.x;
-    int p2 = p * p;
-    for (int e = tid; e < p2; e += P2M_T) tn[e] = tnode[e];
+    int c = leaves[blockIdx.x];
+    int tid = threadIdx.x, p2 = p * p;
+    for (int e = tid; e < p2; e += 256) tn[e] = tnode[e];
     double x0 = ccx[c], y0 = ccy[c], ih = 1.0 / chw[c];
-    // thread owns node entries e = tid + k * P2M_T (< p^2), 3 components each
-    constexpr int EPT = (MAXP * MAXP + P2M_T - 1) / P2M_T;
-    double acc[3][EPT];
-#pragma unroll
-    for (int k = 0; k < EPT; ++k) acc[0][k] = acc[1][k] = acc[2][k] = 0.0;
     __syncthreads();
     for (int j = pbeg[c]; j < pend[c]; ++j) {
         double ex = cx[j], ey = cy[j], ec = cb[j], es = sb[j], ea = a[j];
-        // interpolant values at the p Gauss points of element j
-        for (int t = tid; t < 2 * p2; t += P2M_T) {
+        for (int t = tid; t < 2 * p2; t += 256) {
             int coord = t / p2, r = t - coord * p2;
             int g = r / p, l = r - g * p;
             double xi = ea * glt[g];
@@ -116,216 +140,237 @@ __global__ __launch_bounds__(P2M_T) void k_p2m(int nleaf, const int *__restrict_
         }
         if (tid < p) wg[tid] = ea * glw[tid];
         __syncthreads();
-        double q0 = q[3 * j], q1 = q[3 * j + 1], q2 = q[3 * j + 2];
-#pragma unroll
-        for (int k = 0; k < EPT; ++k) {
-            int e = tid + k * P2M_T;
-            if (e < p2) {
-                int l = e / p, m = e - l * p;
-                double s = 0.0;
-                for (int g = 0; g < p; ++g) s += wg[g] * Sx[g * MAXP + l] * Sy[g * MAXP + m];
-                acc[0][k] += q0 * s;
-                acc[1][k] += q1 * s;
-                acc[2][k] += q2 * s;
-            }
+        for (int e = tid; e < p2; e += 256) {
+            int l = e / p, m = e - l * p;
+            double s = 0.0;
+            for (int g = 0; g < p; ++g) s += wg[g] * Sx[g * MAXP + l] * Sy[g * MAXP + m];
+            Pm[(size_t)j * p2 + e] = s;
         }
         __syncthreads();
     }
+}
+
+// ---------------------------------------------------- P2M (per product)
+__global__ __launch_bounds__(256) void k_p2m(int nleaf, const int *__restrict__ leaves,
+                                             const int *__restrict__ pbeg, const int *__restrict__ pend,
+                                             const double *__restrict__ Pm, const double *__restrict__ q,
+                                             int p2, int Mp, double *__restrict__ W)
+{
+    int c = leaves[xcd_remap(blockIdx.x, nleaf)];
+    int b = pbeg[c], e = pend[c];
     double *Wc = W + (size_t)c * Mp;
-#pragma unroll
-    for (int k = 0; k < EPT; ++k) {
-        int e = tid + k * P2M_T;
-        if (e < p2) {
-            Wc[e] = acc[0][k];
-            Wc[p2 + e] = acc[1][k];
-            Wc[2 * p2 + e] = acc[2][k];
+    for (int t = threadIdx.x; t < p2; t += 256) {
+        double w0 = 0.0, w1 = 0.0, w2 = 0.0;
+#pragma unroll 4
+        for (int j = b; j < e; ++j) {
+            double m = Pm[(size_t)j * p2 + t];
+            w0 += q[3 * j] * m;
+            w1 += q[3 * j + 1] * m;
+            w2 += q[3 * j + 2] * m;
         }
+        Wc[t] = w0;
+        Wc[p2 + t] = w1;
+        Wc[2 * p2 + t] = w2;
     }
 }
 
-// ------------------------------------------------------------------ M2M / L2L
-// T[side][l][l'] = S_p(xbar_l, side_sign/2 + xbar_l'/2), side 0 = lower/left.
-constexpr int TT = 256;
+// ------------------------------------------------------------ M2M
+// T[side][l][l'] = S_p(xbar_l, side_sign/2 + xbar_l'/2) (side 0 = lower or
+// left child): parent interpolant l at child node l'.  The pass applies
+// these p x p matrices along x and then along y.  Each lane owns one
+// column (x pass) or one row (y pass) of one (child, component) matrix and
+// keeps it in registers; the lanes of a wave share the child's side, so the
+// operator is staged in LDS and read there as wave-uniform broadcasts.
+constexpr int XT = 256;  // 4 waves: two per side
 
-__global__ __launch_bounds__(TT) void k_m2m(int c0, int nc, const int *__restrict__ leaf,
+// side of the operator used by this wave (uniform) and the lane's slot
+// among the 2 x 64 lanes of that side
+__device__ __forceinline__ int wave_side() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 7)); }
+
+// Upward pass for the parents of one level (eq. 3.7):
+//   W_P[c] = sum_d Tx_d W_d[c] Ty_d^T   (d over the existing children)
+template <int P>
+__global__ __launch_bounds__(XT) void k_m2m(int c0, int nc, const int *__restrict__ leaf,
                                             const int *__restrict__ child, const double *__restrict__ Tm,
-                                            int p, int Mp, double *__restrict__ W)
+                                            int Mp, double *__restrict__ W)
 {
-    __shared__ double T[2 * MAXP * MAXP];
-    __shared__ double in[3 * MAXP * MAXP], tmp[3 * MAXP * MAXP];
+    constexpr int P2 = P * P, N3 = 3 * P2;
+    constexpr int UO = P <= 20 ? P : 4;  // outer unroll: bounds the live operator values
+    __shared__ double buf[4 * N3];
+    __shared__ double Ts[2 * P2];
+    __shared__ int kid[4];
     int c = c0 + xcd_remap(blockIdx.x, nc);
     if (leaf[c]) return;
-    int tid = threadIdx.x, p2 = p * p, n3 = 3 * p2;
-    for (int e = tid; e < 2 * p2; e += TT) T[e] = Tm[e];
-    constexpr int EPT = (3 * MAXP * MAXP + TT - 1) / TT;
-    double acc[EPT];
+    int tid = threadIdx.x, side = wave_side(), q0 = tid & 127;
+    if (tid < 4) kid[tid] = child[4 * c + tid];
+    for (int e = tid; e < 2 * P2; e += XT) Ts[e] = Tm[e];
+    __syncthreads();
+    for (int e = tid; e < 4 * N3; e += XT) {
+        int d = e / N3, r = e - d * N3;
+        int k = kid[d];
+        buf[e] = k >= 0 ? W[(size_t)k * Mp + r] : 0.0;
+    }
+    __syncthreads();
+    // x pass, child d = side + 2 dy: column m2 of in_d[c] <- Tx_d . column
+    const double *Tx = Ts + side * P2;
+    for (int q = q0; q < 6 * P; q += 128) {
+        int dy = q / (3 * P), r = q - dy * 3 * P, comp = r / P, m2 = r - comp * P;
+        double *col = buf + (side + 2 * dy) * N3 + comp * P2 + m2;
+        double v[P];
 #pragma unroll
-    for (int k = 0; k < EPT; ++k) acc[k] = 0.0;
-    for (int d = 0; d < 4; ++d) {
-        int k = child[4 * c + d];
-        if (k < 0) continue;
-        const double *Tx = T + (d & 1) * p2, *Ty = T + (d >> 1) * p2;
-        __syncthreads();
-        for (int e = tid; e < n3; e += TT) in[e] = W[(size_t)k * Mp + e];
-        __syncthreads();
-        // tmp[c][l][m'] = sum_l' Tx[l][l'] in[c][l'][m']
-        for (int e = tid; e < n3; e += TT) {
-            int cc = e / p2, r = e - cc * p2, l = r / p, m2 = r - l * p;
-            double s = 0.0;
-            for (int l2 = 0; l2 < p; ++l2) s += Tx[l * p + l2] * in[cc * p2 + l2 * p + m2];
-            tmp[e] = s;
-        }
-        __syncthreads();
+        for (int l2 = 0; l2 < P; ++l2) v[l2] = col[l2 * P];
+#pragma unroll UO
+        for (int l = 0; l < P; ++l) {
+            double a = 0.0;
 #pragma unroll
-        for (int kk = 0; kk < EPT; ++kk) {
-            int e = tid + kk * TT;
-            if (e < n3) {
-                int cc = e / p2, r = e - cc * p2, l = r / p, m = r - l * p;
-                double s = 0.0;
-                for (int m2 = 0; m2 < p; ++m2) s += Ty[m * p + m2] * tmp[cc * p2 + l * p + m2];
-                acc[kk] += s;
-            }
+            for (int l2 = 0; l2 < P; ++l2) a += Tx[l * P + l2] * v[l2];
+            col[l * P] = a;
         }
     }
+    __syncthreads();
+    // y pass, child d = 2 side + dx: row l of tmp_d[c] <- row . Ty_d^T
+    const double *Ty = Ts + side * P2;
+    for (int q = q0; q < 6 * P; q += 128) {
+        int dx = q / (3 * P), r = q - dx * 3 * P, comp = r / P, l = r - comp * P;
+        double *row = buf + (2 * side + dx) * N3 + comp * P2 + l * P;
+        double v[P];
 #pragma unroll
-    for (int kk = 0; kk < EPT; ++kk) {
-        int e = tid + kk * TT;
-        if (e < n3) W[(size_t)c * Mp + e] = acc[kk];
+        for (int m2 = 0; m2 < P; ++m2) v[m2] = row[m2];
+#pragma unroll UO
+        for (int m = 0; m < P; ++m) {
+            double a = 0.0;
+#pragma unroll
+            for (int m2 = 0; m2 < P; ++m2) a += Ty[m * P + m2] * v[m2];
+            row[m] = a;
+        }
     }
+    __syncthreads();
+    for (int e = tid; e < N3; e += XT)
+        W[(size_t)c * Mp + e] = ((buf[e] + buf[N3 + e]) + buf[2 * N3 + e]) + buf[3 * N3 + e];
 }
 
-// Downward pass for the cells of one level: F = (sum of its M2L pair
-// products) + L2L(parent field).
-__global__ __launch_bounds__(TT) void k_down(int c0, int nc, const int *__restrict__ parent,
-                                             const uint32_t *__restrict__ cix, const uint32_t *__restrict__ ciy,
-                                             const int *__restrict__ voff, const double *__restrict__ Z,
-                                             const double *__restrict__ Tm, int p, int Mp, int do_l2l,
-                                             double *__restrict__ F)
+// ------------------------------------------------- gathered MFMA GEMM
+// For every pair k of a tile (all pairs of a tile share operator o):
+//   Z[dst[k]] = scale[k] * Op_o . X[src[k]]
+// Op_o = ops + o * op_stride, row-major (Mrows x Kd, leading dim lda);
+// X rows have leading dim ldx, Z rows ldz.  Mrows = gridDim.y * BM, Kd a
+// multiple of 16; gridDim.z > 1 splits K, slice z of the result going to
+// Z + z * zsplit.  Block: 4 waves in 2 x 2, each (BM/2) x (BN/2) built from
+// 16x16x4 FP64 MFMA blocks.  Operand layout of v_mfma_f64_16x16x4f64: lane L
+// holds A[L%16][L/16] and B[L/16][L%16]; accumulator register r of lane L
+// holds D[4r + L/16][L%16].
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void k_ggemm(const double *__restrict__ ops, size_t op_stride, int lda,
+                                               int Kd, const double *__restrict__ X, int ldx,
+                                               const int *__restrict__ tile_op, const int *__restrict__ tile_beg,
+                                               const int *__restrict__ tile_end, const int *__restrict__ pair_src,
+                                               const int *__restrict__ pair_dst,
+                                               const double *__restrict__ pair_scale, double *__restrict__ Z,
+                                               int ldz, size_t zsplit)
 {
-    __shared__ double T[2 * MAXP * MAXP];
-    __shared__ double in[3 * MAXP * MAXP], tmp[3 * MAXP * MAXP];
-    int c = c0 + xcd_remap(blockIdx.x, nc);
-    int tid = threadIdx.x, p2 = p * p, n3 = 3 * p2;
-    constexpr int EPT = (3 * MAXP * MAXP + TT - 1) / TT;
-    double acc[EPT];
-#pragma unroll
-    for (int k = 0; k < EPT; ++k) acc[k] = 0.0;
-    // M2L pair products of this cell, summed in list order
-    int kb = voff[c], ke = voff[c + 1];
-    for (int k = kb; k < ke; ++k) {
-        const double *z = Z + (size_t)k * Mp;
-#pragma unroll
-        for (int kk = 0; kk < EPT; ++kk) {
-            int e = tid + kk * TT;
-            if (e < n3) acc[kk] += z[e];
-        }
-    }
-    if (do_l2l) {
-        int P = parent[c];
-        int sx = (int)(cix[c] & 1u), sy = (int)(ciy[c] & 1u);
-        for (int e = tid; e < 2 * p2; e += TT) T[e] = Tm[e];
-        for (int e = tid; e < n3; e += TT) in[e] = F[(size_t)P * Mp + e];
-        __syncthreads();
-        const double *Tx = T + sx * p2, *Ty = T + sy * p2;
-        // tmp[c][l][m'] = sum_l' Tx[l'][l] in[c][l'][m']
-        for (int e = tid; e < n3; e += TT) {
-            int cc = e / p2, r = e - cc * p2, l = r / p, m2 = r - l * p;
-            double s = 0.0;
-            for (int l2 = 0; l2 < p; ++l2) s += Tx[l2 * p + l] * in[cc * p2 + l2 * p + m2];
-            tmp[e] = s;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < EPT; ++kk) {
-            int e = tid + kk * TT;
-            if (e < n3) {
-                int cc = e / p2, r = e - cc * p2, l = r / p, m = r - l * p;
-                double s = 0.0;
-                for (int m2 = 0; m2 < p; ++m2) s += Ty[m2 * p + m] * tmp[cc * p2 + l * p + m2];
-                acc[kk] += s;
-            }
-        }
-    }
-#pragma unroll
-    for (int kk = 0; kk < EPT; ++kk) {
-        int e = tid + kk * TT;
-        if (e < n3) F[(size_t)c * Mp + e] = acc[kk];
-    }
-}
-
-// ------------------------------------------------------------------ M2L
-// Z[pair] = scale[pair] * Op[o] . X[src[pair]] for the pairs of one tile
-// (all of the same offset o).  64 x 64 output tile per 256-thread block,
-// 4 waves of 32 x 32 built from 2 x 2 MFMA 16x16x4 (FP64) blocks.  Operand
-// layout of v_mfma_f64_16x16x4f64: lane L holds A[L%16][L/16] and
-// B[L/16][L%16]; accumulator register r of lane L holds D[4r + L/16][L%16].
-constexpr int GM = 64, GN = 64, GK = 16;
-
-__global__ __launch_bounds__(256) void k_m2l_gemm(const double *__restrict__ ops, int Mp,
-                                                  const double *__restrict__ X,
-                                                  const int *__restrict__ tile_op,
-                                                  const int *__restrict__ tile_beg,
-                                                  const int *__restrict__ tile_end,
-                                                  const int *__restrict__ pair_k,
-                                                  const int *__restrict__ pair_src,
-                                                  const double *__restrict__ pair_scale,
-                                                  double *__restrict__ Z)
-{
-    __shared__ double As[GM][GK + 1];
-    __shared__ double Bs[GK][GN + 1];
-    __shared__ int src[GN];
+    constexpr int GK = 16, WM = BM / 32, WN = BN / 32;
+    constexpr int RA = (BM * GK + 255) / 256, RB = (BN * GK + 255) / 256;
+    __shared__ double As[BM][GK + 1];
+    __shared__ double Bs[GK][BN + 1];
+    __shared__ int src[BN];
     int tile = blockIdx.x, mt = blockIdx.y;
     int o = tile_op[tile], pb = tile_beg[tile], np = tile_end[tile] - pb;
     int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     int wm = wave >> 1, wn = wave & 1;
-    if (tid < GN) src[tid] = tid < np ? pair_src[pb + tid] : -1;
-    const double *A = ops + (size_t)o * Mp * Mp + (size_t)mt * GM * Mp;
-    d4 acc[2][2];
+    // split-K: this block sums k in [kb, ke); partial results go to slice z
+    int ksteps = Kd / GK, per = (ksteps + gridDim.z - 1) / gridDim.z;
+    int kb = min(Kd, (int)blockIdx.z * per * GK), ke = min(Kd, kb + per * GK);
+    Z += (size_t)blockIdx.z * zsplit;
+    if (tid < BN) src[tid] = tid < np ? pair_src[pb + tid] : -1;
+    const double *A = ops + (size_t)o * op_stride + (size_t)mt * BM * lda;
+    d4 acc[WM][WN];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < WM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < WN; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
     __syncthreads();
-    for (int k0 = 0; k0 < Mp; k0 += GK) {
+    // the next k-step's operands are fetched into registers while the
+    // current one is multiplied
+    double ra[RA], rb[RB];
+    auto fetch = [&](int k0) {
 #pragma unroll
-        for (int r = 0; r < (GM * GK) / 256; ++r) {
+        for (int r = 0; r < RA; ++r) {
             int e = tid + r * 256;
-            int row = e / GK, col = e % GK;
-            As[row][col] = A[(size_t)row * Mp + k0 + col];
+            if (e < BM * GK) ra[r] = A[(size_t)(e / GK) * lda + k0 + e % GK];
         }
 #pragma unroll
-        for (int r = 0; r < (GN * GK) / 256; ++r) {
+        for (int r = 0; r < RB; ++r) {
             int e = tid + r * 256;
-            int j = e / GK, col = e % GK;
-            int s = src[j];
-            Bs[col][j] = s >= 0 ? X[(size_t)s * Mp + k0 + col] : 0.0;
+            if (e < BN * GK) {
+                int s = src[e / GK];
+                rb[r] = s >= 0 ? X[(size_t)s * ldx + k0 + e % GK] : 0.0;
+            }
+        }
+    };
+    if (kb < ke) fetch(kb);
+    for (int k0 = kb; k0 < ke; k0 += GK) {
+#pragma unroll
+        for (int r = 0; r < RA; ++r) {
+            int e = tid + r * 256;
+            if (e < BM * GK) As[e / GK][e % GK] = ra[r];
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            int e = tid + r * 256;
+            if (e < BN * GK) Bs[e % GK][e / GK] = rb[r];
         }
         __syncthreads();
+        if (k0 + GK < ke) fetch(k0 + GK);
 #pragma unroll
         for (int kk = 0; kk < GK; kk += 4) {
-            double av[2], bv[2];
+            double av[WM], bv[WN];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) av[i] = As[wm * 32 + i * 16 + (lane & 15)][kk + (lane >> 4)];
+            for (int i = 0; i < WM; ++i) av[i] = As[wm * (BM / 2) + i * 16 + (lane & 15)][kk + (lane >> 4)];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) bv[j] = Bs[kk + (lane >> 4)][wn * 32 + j * 16 + (lane & 15)];
+            for (int j = 0; j < WN; ++j) bv[j] = Bs[kk + (lane >> 4)][wn * (BN / 2) + j * 16 + (lane & 15)];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < WM; ++i)
 #pragma unroll
-                for (int j = 0; j < 2; ++j)
+                for (int j = 0; j < WN; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        int col = wn * 32 + j * 16 + (lane & 15);
+    for (int j = 0; j < WN; ++j) {
+        int col = wn * (BN / 2) + j * 16 + (lane & 15);
         if (col >= np) continue;
-        double sc = pair_scale[pb + col];
-        double *z = Z + (size_t)pair_k[pb + col] * Mp + mt * GM;
+        double sc = pair_scale ? pair_scale[pb + col] : 1.0;
+        double *z = Z + (size_t)pair_dst[pb + col] * ldz + mt * BM;
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < WM; ++i)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) z[wm * 32 + i * 16 + 4 * r + (lane >> 4)] = sc * acc[i][j][r];
+            for (int r = 0; r < 4; ++r) z[wm * (BM / 2) + i * 16 + 4 * r + (lane >> 4)] = sc * acc[i][j][r];
+    }
+}
+
+// out[i] = sum over the split-K slices of part[z * stride + i], in order.
+__global__ void k_reduce_split(int64_t count, int nsplit, size_t stride, const double *__restrict__ part,
+                               double *__restrict__ out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    double s = 0.0;
+    for (int z = 0; z < nsplit; ++z) s += part[(size_t)z * stride + i];
+    out[i] = s;
+}
+
+// out[c] = sum of the pair products of cell c, in V-list order.
+__global__ __launch_bounds__(256) void k_sum_pairs(int nfar, const int *__restrict__ far_cells,
+                                                   const int *__restrict__ voff, const double *__restrict__ Z,
+                                                   int ldz, int width, double *__restrict__ out, int ldo)
+{
+    int c = far_cells[xcd_remap(blockIdx.x, nfar)];
+    int kb = voff[c], ke = voff[c + 1];
+    for (int e = threadIdx.x; e < width; e += 256) {
+        double s = 0.0;
+        for (int k = kb; k < ke; ++k) s += Z[(size_t)k * ldz + e];
+        out[(size_t)c * ldo + e] = s;
     }
 }
 
@@ -351,147 +396,272 @@ __global__ void k_m2l_ops(int nop, const int *__restrict__ odx, const int *__res
         for (int b = 0; b < 3; ++b) op[(size_t)(a * p2 + tn) * Mp + b * p2 + sn] = K[a * 3 + b];
 }
 
-// ------------------------------------------------------------ L2P + P2P
-constexpr int PT = 256, TPT = 4, TGT = PT / TPT, STILE = 256, MAXNEAR = 512;
-
-__global__ __launch_bounds__(PT) void k_l2p_p2p(
-    int nleaf, const int *__restrict__ leaves, const int *__restrict__ pbeg, const int *__restrict__ pend,
-    const int *__restrict__ noff, const int *__restrict__ nsrc, const double *__restrict__ ccx,
-    const double *__restrict__ ccy, const double *__restrict__ chw, const double *__restrict__ cx,
-    const double *__restrict__ cy, const double *__restrict__ cb, const double *__restrict__ sb,
-    const double *__restrict__ a, const double *__restrict__ Ds, const int *__restrict__ perm,
-    const double *__restrict__ F, const double *__restrict__ tnode, int p, int Mp, double gc,
-    int use_far, double *__restrict__ out)
+// All operators side by side, column-major M x (nop M):
+// fat[(o M + k) M + i] = K_o[i][k].
+__global__ void k_pack_fat(int nop, int M, int Mp, const double *__restrict__ ops, double *__restrict__ fat)
 {
-    __shared__ double tn[MAXP * MAXP];
-    __shared__ double s_cx[STILE], s_cy[STILE], s_cb[STILE], s_sb[STILE], s_a[STILE], s_ds[STILE],
-        s_dn[STILE];
-    __shared__ int s_pre[MAXNEAR + 1], s_beg[MAXNEAR];
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t tot = (int64_t)nop * M * M;
+    if (t >= tot) return;
+    int i = (int)(t % M);
+    int64_t col = t / M;
+    int o = (int)(col / M), k = (int)(col % M);
+    fat[t] = ops[(size_t)o * Mp * Mp + (size_t)i * Mp + k];
+}
+
+// From the column-major left singular vectors U (M x M, leading dim M):
+// Vt (rp x Mp, row i = vector i) and Ur (Mp x rp, column i = vector i);
+// zero outside the first r vectors and the first M entries.
+__global__ void k_bases(int M, int Mp, int r, int rp, const double *__restrict__ U, double *__restrict__ Vt,
+                        double *__restrict__ Ur)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)rp * Mp) return;
+    int i = (int)(t / Mp), k = (int)(t % Mp);
+    double v = (i < r && k < M) ? U[(size_t)i * M + k] : 0.0;
+    Vt[(size_t)i * Mp + k] = v;
+    Ur[(size_t)k * rp + i] = v;
+}
+
+// ops[o][j][i] = scale * Ct[o rp + i][j]
+__global__ void k_transpose_ops(int nop, int rp, double scale, const double *__restrict__ Ct,
+                                double *__restrict__ ops)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)nop * rp * rp) return;
+    int o = (int)(t / ((int64_t)rp * rp));
+    int r = (int)(t % ((int64_t)rp * rp));
+    int j = r / rp, i = r % rp;
+    ops[t] = scale * Ct[((size_t)o * rp + i) * rp + j];
+}
+
+// ------------------------------------------------------------ L2P
+// Far-field stress at every midpoint, eqs. 3.10-3.11 in one step: the
+// chain of parent-to-child interpolations of the downward pass followed by
+// the interpolation at the point is the evaluation of each ancestor's M2L
+// field (a polynomial on that ancestor's square) at the point, so the
+// fields of the leaf and of all its ancestors at level >= 2 are summed
+// there directly.  One block per leaf: an ancestor's field sits in LDS
+// (double-buffered: the next one is fetched while the current one is
+// contracted), the barycentric interpolants of up to 32 points are formed,
+// and tasks (point, component, quarter of the x rows) contract
+// sum_l Sx[l] sum_m G[c][l][m] Sy[m]; quarters combine in a fixed order.
+constexpr int LT = 256, LTM = 32;
+
+template <int P>
+__global__ __launch_bounds__(LT) void k_l2p(int nleaf, const int *__restrict__ leaves,
+                                            const int *__restrict__ pbeg, const int *__restrict__ pend,
+                                            const int *__restrict__ aoff, const int *__restrict__ aidx,
+                                            const double *__restrict__ ccx, const double *__restrict__ ccy,
+                                            const double *__restrict__ chw, const double *__restrict__ cx,
+                                            const double *__restrict__ cy, const double *__restrict__ G, int Mp,
+                                            const double *__restrict__ xbar, const double *__restrict__ bw,
+                                            double *__restrict__ far_s)
+{
+    constexpr int P2 = P * P, N3 = 3 * P2, NPF = (N3 + LT - 1) / LT;
+    constexpr int LQ = (P + 3) / 4;  // x rows per quarter
+    __shared__ double Gb[2][N3];
+    __shared__ double Sx[LTM][P + 1], Sy[LTM][P + 1];
+    __shared__ double s_xb[P], s_bw[P];
     int li = xcd_remap(blockIdx.x, nleaf);
     int c = leaves[li];
-    int tid = threadIdx.x, sub = tid & (TPT - 1), tl = tid / TPT;
-    int p2 = p * p;
-    for (int e = tid; e < p2; e += PT) tn[e] = tnode[e];
-    // flattened near-source ranges
-    int nb = noff[li], ne = noff[li + 1], nn = ne - nb;
-    if (tid == 0) {
-        int s = 0;
-        for (int k = 0; k < nn && k < MAXNEAR; ++k) {
-            int sc = nsrc[nb + k];
-            s_pre[k] = s;
-            s_beg[k] = pbeg[sc];
-            s += pend[sc] - pbeg[sc];
-        }
-        s_pre[nn < MAXNEAR ? nn : MAXNEAR] = s;
-    }
-    __syncthreads();
-    int nchunks = (nn + MAXNEAR - 1) / MAXNEAR;
-    double x0 = ccx[c], y0 = ccy[c], ih = 1.0 / chw[c];
+    int tid = threadIdx.x;
     int tb = pbeg[c], te = pend[c];
-    for (int t0 = tb; t0 < te; t0 += TGT) {
-        int i = t0 + tl;
-        bool act = i < te;
-        double X = act ? cx[i] : 0.0, Y = act ? cy[i] : 0.0;
-        double sxx = 0.0, syy = 0.0, sxy = 0.0;
-        if (act && use_far) {
-            // local expansion at the midpoint: this sub-lane takes rows l = sub (mod 4)
-            double u = (X - x0) * ih, v = (Y - y0) * ih;
-            double Sy[MAXP];
-            for (int m = 0; m < p; ++m) Sy[m] = cheb_S(p, tn + m * p, v);
-            const double *Fc = F + (size_t)c * Mp;
-            for (int l = sub; l < p; l += TPT) {
-                double sx = cheb_S(p, tn + l * p, u);
-                double r0 = 0.0, r1 = 0.0, r2 = 0.0;
-                for (int m = 0; m < p; ++m) {
-                    r0 += Fc[l * p + m] * Sy[m];
-                    r1 += Fc[p2 + l * p + m] * Sy[m];
-                    r2 += Fc[2 * p2 + l * p + m] * Sy[m];
-                }
-                sxx += sx * r0;
-                syy += sx * r1;
-                sxy += sx * r2;
-            }
+    int a0 = aoff[li], na = aoff[li + 1] - a0;
+    if (tid < P) {
+        s_xb[tid] = xbar[tid];
+        s_bw[tid] = bw[tid];
+    }
+    for (int t0 = tb; t0 < te; t0 += LTM) {
+        int ntp = min(LTM, te - t0);
+        double acc[2] = {0.0, 0.0};
+        double pf[NPF];
+        // first ancestor's field
+        __syncthreads();
+        if (na > 0) {
+            const double *G0 = G + (size_t)aidx[a0] * Mp;
+            for (int e = tid; e < N3; e += LT) Gb[0][e] = G0[e];
         }
-        // direct interactions, sources staged through LDS
-        for (int ch = 0; ch < nchunks; ++ch) {
-            int total;
-            if (ch > 0) {
-                __syncthreads();
-                if (tid == 0) {
-                    int s = 0, kb = ch * MAXNEAR;
-                    int kn = min(nn - kb, MAXNEAR);
-                    for (int k = 0; k < kn; ++k) {
-                        int sc = nsrc[nb + kb + k];
-                        s_pre[k] = s;
-                        s_beg[k] = pbeg[sc];
-                        s += pend[sc] - pbeg[sc];
-                    }
-                    s_pre[kn] = s;
+        for (int k = 0; k < na; ++k) {
+            int A = aidx[a0 + k];
+            // fetch the next ancestor's field into registers
+            if (k + 1 < na) {
+                const double *Gn = G + (size_t)aidx[a0 + k + 1] * Mp;
+#pragma unroll
+                for (int r = 0; r < NPF; ++r) {
+                    int e = tid + r * LT;
+                    if (e < N3) pf[r] = Gn[e];
                 }
-                __syncthreads();
             }
-            int kn = min(nn - ch * MAXNEAR, MAXNEAR);
-            total = s_pre[kn];
-            for (int base = 0; base < total; base += STILE) {
-                __syncthreads();
-                int vpos = base + tid;
-                if (tid < STILE && vpos < total) {
-                    int lo = 0, hi = kn - 1;  // last k with s_pre[k] <= vpos
-                    while (lo < hi) {
-                        int mid = (lo + hi + 1) >> 1;
-                        if (s_pre[mid] <= vpos) lo = mid;
-                        else hi = mid - 1;
-                    }
-                    int j = s_beg[lo] + (vpos - s_pre[lo]);
-                    s_cx[tid] = cx[j]; s_cy[tid] = cy[j]; s_cb[tid] = cb[j]; s_sb[tid] = sb[j];
-                    s_a[tid] = a[j]; s_ds[tid] = Ds[2 * j]; s_dn[tid] = Ds[2 * j + 1];
-                }
-                __syncthreads();
-                int cnt = min(STILE, total - base);
-                if (act)
-                    for (int k = sub; k < cnt; k += TPT)
-                        elem_stress_add(X, Y, s_cx[k], s_cy[k], s_cb[k], s_sb[k], s_a[k], s_ds[k], s_dn[k],
-                                        gc, sxx, syy, sxy);
-            }
-            if (ch + 1 < nchunks) __syncthreads();
-        }
-        // reduce the 4 sub-lanes (adjacent lanes), fixed order
-        sxx += __shfl_xor(sxx, 1); syy += __shfl_xor(syy, 1); sxy += __shfl_xor(sxy, 1);
-        sxx += __shfl_xor(sxx, 2); syy += __shfl_xor(syy, 2); sxy += __shfl_xor(sxy, 2);
-        if (act && sub == 0) {
-            double ts, tnn;
-            traction(cb[i], sb[i], sxx, syy, sxy, ts, tnn);
-            int o = perm[i];
-            out[2 * o] = ts;
-            out[2 * o + 1] = tnn;
-        }
-        if (nchunks > 1 && t0 + TGT < te) {
-            // restore chunk 0 for the next target group
-            __syncthreads();
-            if (tid == 0) {
-                int s = 0;
-                for (int k = 0; k < nn && k < MAXNEAR; ++k) {
-                    int sc = nsrc[nb + k];
-                    s_pre[k] = s;
-                    s_beg[k] = pbeg[sc];
-                    s += pend[sc] - pbeg[sc];
-                }
-                s_pre[MAXNEAR] = s;
+            if (tid < 2 * ntp) {
+                int t = tid >> 1, coord = tid & 1;
+                double ih = 1.0 / chw[A];
+                double u = coord ? (cy[t0 + t] - ccy[A]) * ih : (cx[t0 + t] - ccx[A]) * ih;
+                double S[P];
+                bary<P>(s_xb, s_bw, u, S);
+                double *dst = coord ? Sy[t] : Sx[t];
+#pragma unroll
+                for (int m = 0; m < P; ++m) dst[m] = S[m];
             }
             __syncthreads();
+            const double *Gc = Gb[k & 1];
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                int task = tid + r * LT;  // (point, component, quarter), quarter fastest
+                int t = task / 12, rem = task - 12 * t, comp = rem >> 2, quarter = rem & 3;
+                if (t < ntp) {
+                    double sum = 0.0;
+#pragma unroll
+                    for (int j = 0; j < LQ; ++j) {
+                        int l = quarter * LQ + j;
+                        if (l < P) {
+                            double rr = 0.0;
+#pragma unroll
+                            for (int m = 0; m < P; ++m) rr += Gc[comp * P2 + l * P + m] * Sy[t][m];
+                            sum += Sx[t][l] * rr;
+                        }
+                    }
+                    acc[r] += sum;
+                }
+            }
+            if (k + 1 < na) {
+#pragma unroll
+                for (int r = 0; r < NPF; ++r) {
+                    int e = tid + r * LT;
+                    if (e < N3) Gb[(k + 1) & 1][e] = pf[r];
+                }
+            }
+            __syncthreads();
+        }
+        // combine the quarters (4 adjacent lanes) in a fixed order
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            acc[r] += __shfl_xor(acc[r], 1);
+            acc[r] += __shfl_xor(acc[r], 2);
+            int task = tid + r * LT;
+            int t = task / 12, rem = task - 12 * t, comp = rem >> 2, quarter = rem & 3;
+            if (t < ntp && quarter == 0) far_s[3 * (size_t)(t0 + t) + comp] = acc[r];
         }
     }
 }
 
+// ------------------------------------------------------------ P2P
+// Exact element interactions.  A work item is one leaf and a chunk of at
+// most NEAR_CHUNK of its near sources (the sources of its U and W lists and
+// of the X lists of the leaf and its ancestors, flattened per leaf), so a
+// leaf with a large near list is spread over several blocks.  Sources are
+// staged in LDS; `tpt` adjacent lanes per point combine in a fixed order;
+// the item's partial stresses go to part_s.
+constexpr int NT = 128, MAXE = 256;
+
+__global__ __launch_bounds__(NT) void k_p2p(
+    int nitem, const int *__restrict__ it_leaf, const int *__restrict__ it_s0, const int *__restrict__ it_s1,
+    const int *__restrict__ it_poff, const int *__restrict__ leaves, const int *__restrict__ pbeg,
+    const int *__restrict__ pend, const int *__restrict__ noff, const int *__restrict__ nbeg,
+    const int *__restrict__ npre, const double *__restrict__ cx, const double *__restrict__ cy,
+    const double *__restrict__ cb, const double *__restrict__ sb, const double *__restrict__ a,
+    const double *__restrict__ Ds, double gc, double *__restrict__ part)
+{
+    __shared__ double s_cx[NEAR_CHUNK], s_cy[NEAR_CHUNK], s_cb[NEAR_CHUNK], s_sb[NEAR_CHUNK],
+        s_a[NEAR_CHUNK], s_ds[NEAR_CHUNK], s_dn[NEAR_CHUNK];
+    __shared__ int s_pre[MAXE], s_beg[MAXE];
+    int k = xcd_remap(blockIdx.x, nitem);
+    int li = it_leaf[k], s0 = it_s0[k], s1 = it_s1[k];
+    int c = leaves[li];
+    int tid = threadIdx.x;
+    int tb = pbeg[c], te = pend[c], nt = te - tb;
+    int nb = noff[li], nn = noff[li + 1] - nb;
+    bool lds = nn <= MAXE;
+    if (lds)
+        for (int e = tid; e < nn; e += NT) {
+            s_pre[e] = npre[nb + e];
+            s_beg[e] = nbeg[nb + e];
+        }
+    __syncthreads();
+    for (int v = s0 + tid; v < s1; v += NT) {
+        int lo = 0, hi = nn - 1;  // last entry with prefix <= v
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            int pm = lds ? s_pre[mid] : npre[nb + mid];
+            if (pm <= v) lo = mid;
+            else hi = mid - 1;
+        }
+        int j = (lds ? s_beg[lo] : nbeg[nb + lo]) + (v - (lds ? s_pre[lo] : npre[nb + lo]));
+        int q = v - s0;
+        s_cx[q] = cx[j]; s_cy[q] = cy[j]; s_cb[q] = cb[j]; s_sb[q] = sb[j];
+        s_a[q] = a[j]; s_ds[q] = Ds[2 * j]; s_dn[q] = Ds[2 * j + 1];
+    }
+    __syncthreads();
+    int cnt = s1 - s0;
+    int tpt = 1;
+    while (tpt < 16 && tpt * 2 * nt <= NT) tpt *= 2;
+    int tpg = NT / tpt, sub = tid & (tpt - 1);
+    double *pk = part + 3 * (size_t)it_poff[k];
+    for (int t0 = tb; t0 < te; t0 += tpg) {
+        int i = t0 + tid / tpt;
+        bool act = i < te;
+        double X = act ? cx[i] : 0.0, Y = act ? cy[i] : 0.0;
+        double sxx = 0.0, syy = 0.0, sxy = 0.0;
+        if (act)
+            for (int q = sub; q < cnt; q += tpt)
+                elem_stress_add(X, Y, s_cx[q], s_cy[q], s_cb[q], s_sb[q], s_a[q], s_ds[q], s_dn[q], gc, sxx,
+                                syy, sxy);
+        for (int w = 1; w < tpt; w <<= 1) {
+            sxx += __shfl_xor(sxx, w);
+            syy += __shfl_xor(syy, w);
+            sxy += __shfl_xor(sxy, w);
+        }
+        if (act && sub == 0) {
+            double *o = pk + 3 * (size_t)(i - tb);
+            o[0] = sxx;
+            o[1] = syy;
+            o[2] = sxy;
+        }
+    }
+}
+
+// Total stress at each point = far field + the near-field partials of its
+// leaf's work items (in item order); projected to (shear, normal) traction
+// and written in caller order.
+__global__ void k_final(int n, const int *__restrict__ tleaf, const int *__restrict__ leaves,
+                        const int *__restrict__ pbeg, const int *__restrict__ lk_off,
+                        const int *__restrict__ it_poff, const double *__restrict__ part,
+                        const double *__restrict__ far_s, const double *__restrict__ cb,
+                        const double *__restrict__ sb, const int *__restrict__ perm, double *__restrict__ out)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int li = tleaf[i];
+    int t = i - pbeg[leaves[li]];
+    double sxx = 0.0, syy = 0.0, sxy = 0.0;
+    if (far_s) {
+        sxx = far_s[3 * (size_t)i];
+        syy = far_s[3 * (size_t)i + 1];
+        sxy = far_s[3 * (size_t)i + 2];
+    }
+    for (int k = lk_off[li]; k < lk_off[li + 1]; ++k) {
+        const double *o = part + 3 * ((size_t)it_poff[k] + t);
+        sxx += o[0];
+        syy += o[1];
+        sxy += o[2];
+    }
+    double ts, tn;
+    traction(cb[i], sb[i], sxx, syy, sxy, ts, tn);
+    int j = perm[i];
+    out[2 * j] = ts;
+    out[2 * j + 1] = tn;
+}
+
+// ------------------------------------------------------- host helpers
 // Gauss-Legendre nodes/weights on [-1, 1] (Newton on the Legendre
-// recurrence), host side.
+// recurrence).
 void gauss_legendre(int n, std::vector<double> &t, std::vector<double> &w)
 {
     t.assign(n, 0.0);
     w.assign(n, 0.0);
     for (int i = 0; i < n; ++i) {
         double x = std::cos(M_PI * (i + 0.75) / (n + 0.5));
-        double pn = 0, dpn = 1;
+        double dpn = 1;
         for (int it = 0; it < 200; ++it) {
             double pm = 1.0, pc = x;
             for (int k = 2; k <= n; ++k) {
@@ -500,9 +670,8 @@ void gauss_legendre(int n, std::vector<double> &t, std::vector<double> &w)
                 pc = pk;
             }
             if (n == 1) { pc = x; pm = 1.0; }
-            pn = pc;
             dpn = n * (x * pc - pm) / (x * x - 1.0);
-            double dx = pn / dpn;
+            double dx = pc / dpn;
             x -= dx;
             if (std::fabs(dx) < 1e-17) break;
         }
@@ -532,8 +701,87 @@ double host_cheb_S(int p, int l, double u)
     return (1.0 + 2.0 * s) / p;
 }
 
+int offset_slot(int dx, int dy) { return (dx + 3) + 7 * (dy + 3); }
+
+// Offsets (dx, dy) in [-3, 3]^2 outside [-1, 1]^2: the 40 relative
+// positions of a V-list cell.
+void v_offsets(std::vector<int> &dx, std::vector<int> &dy, std::vector<int> &slot2op)
+{
+    slot2op.assign(49, -1);
+    for (int y = -3; y <= 3; ++y)
+        for (int x = -3; x <= 3; ++x) {
+            if (std::abs(x) <= 1 && std::abs(y) <= 1) continue;
+            slot2op[offset_slot(x, y)] = (int)dx.size();
+            dx.push_back(x);
+            dy.push_back(y);
+        }
+}
+
+constexpr int TILE_N = 32;  // pairs per GEMM tile (the BN of the launches)
+constexpr int KSPLIT = 4;   // split-K factor of the projection onto the singular vectors
+
+void upload(hipStream_t s, DBuf<int> &d, const std::vector<int> &h)
+{
+    d.alloc(h.size());
+    if (!h.empty()) FM_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * 4, hipMemcpyHostToDevice, s));
+}
+
+void upload(hipStream_t s, DBuf<double> &d, const std::vector<double> &h)
+{
+    d.alloc(h.size());
+    if (!h.empty()) FM_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * 8, hipMemcpyHostToDevice, s));
+}
+
+template <int BM, int BN>
+void launch_ggemm(hipStream_t s, int ntile, int Mrows, const double *ops, size_t op_stride, int lda, int Kd,
+                  const double *X, int ldx, const int *top, const int *tbeg, const int *tend,
+                  const int *psrc, const int *pdst, const double *pscale, double *Z, int ldz,
+                  int nsplit = 1, size_t zsplit = 0)
+{
+    if (ntile == 0) return;
+    if (Mrows % BM || Kd % 16) throw Error{FMDDM_EDEVICE, "GEMM shape not tiled"};
+    hipLaunchKernelGGL((k_ggemm<BM, BN>), dim3(ntile, Mrows / BM, nsplit), dim3(256), 0, s, ops, op_stride, lda,
+                       Kd, X, ldx, top, tbeg, tend, psrc, pdst, pscale, Z, ldz, zsplit);
+    FM_CHECK_LAUNCH();
+}
+
+template <int P>
+void launch_m2m(hipStream_t s, int c0, int nc, const int *leaf, const int *child, const double *T, int Mp,
+                double *W)
+{
+    hipLaunchKernelGGL((k_m2m<P>), dim3(nc), dim3(XT), 0, s, c0, nc, leaf, child, T, Mp, W);
+    FM_CHECK_LAUNCH();
+}
+
+
+template <int P>
+void launch_l2p(hipStream_t s, fmddm_ctx *ctx, fmddm_tree *t, int Mp)
+{
+    hipLaunchKernelGGL((k_l2p<P>), dim3(t->nleaf), dim3(LT), 0, s, t->nleaf, t->dleaves.p, t->cpbeg.p,
+                       t->cpend.p, t->aoff.p, t->aidx.p, t->ccx.p, t->ccy.p, t->chw.p, t->scx.p, t->scy.p, t->Gexp.p,
+                       Mp, ctx->cheb.xbar.p, ctx->cheb.bw.p, t->far_s.p);
+    FM_CHECK_LAUNCH();
+}
+
+#define FM_DISPATCH_P(p, CALL)                                                          \
+    switch (p) {                                                                        \
+    case 1: CALL(1); break;   case 2: CALL(2); break;   case 3: CALL(3); break;        \
+    case 4: CALL(4); break;   case 5: CALL(5); break;   case 6: CALL(6); break;        \
+    case 7: CALL(7); break;   case 8: CALL(8); break;   case 9: CALL(9); break;        \
+    case 10: CALL(10); break; case 11: CALL(11); break; case 12: CALL(12); break;      \
+    case 13: CALL(13); break; case 14: CALL(14); break; case 15: CALL(15); break;      \
+    case 16: CALL(16); break; case 17: CALL(17); break; case 18: CALL(18); break;      \
+    case 19: CALL(19); break; case 20: CALL(20); break; case 21: CALL(21); break;      \
+    case 22: CALL(22); break; case 23: CALL(23); break; case 24: CALL(24); break;      \
+    case 25: CALL(25); break; case 26: CALL(26); break; case 27: CALL(27); break;      \
+    case 28: CALL(28); break; case 29: CALL(29); break; case 30: CALL(30); break;      \
+    case 31: CALL(31); break; case 32: CALL(32); break;                                \
+    default: throw Error{FMDDM_EINVAL, "p out of range"};                               \
+    }
+
 }  // namespace
 
+// ------------------------------------------------------------ profiler
 Profiler::~Profiler()
 {
     for (hipEvent_t e : pool) (void)hipEventDestroy(e);
@@ -590,16 +838,19 @@ void Profiler::read(hipStream_t s, double *ms, int64_t *count)
     }
 }
 
+// ------------------------------------------------------------- set-up
 void setup_cheb(fmddm_ctx *ctx)
 {
     int p = ctx->prm.p;
     Cheb &C = ctx->cheb;
     C.p = p;
     C.h_xbar.resize(p);
+    C.h_bw.resize(p);
     C.h_tnode.resize(p * p);
     for (int l = 0; l < p; ++l) {
         double th = (2.0 * l + 1.0) * M_PI / (2.0 * p);
         C.h_xbar[l] = std::cos(th);
+        C.h_bw[l] = (l & 1 ? -1.0 : 1.0) * std::sin(th);
         for (int k = 0; k < p; ++k) C.h_tnode[l * p + k] = std::cos(k * th);
     }
     gauss_legendre(p, C.h_glt, C.h_glw);
@@ -610,29 +861,13 @@ void setup_cheb(fmddm_ctx *ctx)
                 C.h_m2m[side * p * p + l * p + l2] =
                     host_cheb_S(p, l, (side ? 0.5 : -0.5) + 0.5 * C.h_xbar[l2]);
     hipStream_t s = ctx->stream;
-    C.xbar.alloc(p); C.tnode.alloc(p * p); C.gl_t.alloc(p); C.gl_w.alloc(p); C.m2m.alloc(2 * p * p);
-    FM_HIP(hipMemcpyAsync(C.xbar.p, C.h_xbar.data(), p * 8, hipMemcpyHostToDevice, s));
-    FM_HIP(hipMemcpyAsync(C.tnode.p, C.h_tnode.data(), p * p * 8, hipMemcpyHostToDevice, s));
-    FM_HIP(hipMemcpyAsync(C.gl_t.p, C.h_glt.data(), p * 8, hipMemcpyHostToDevice, s));
-    FM_HIP(hipMemcpyAsync(C.gl_w.p, C.h_glw.data(), p * 8, hipMemcpyHostToDevice, s));
-    FM_HIP(hipMemcpyAsync(C.m2m.p, C.h_m2m.data(), 2 * p * p * 8, hipMemcpyHostToDevice, s));
+    upload(s, C.xbar, C.h_xbar);
+    upload(s, C.bw, C.h_bw);
+    upload(s, C.tnode, C.h_tnode);
+    upload(s, C.gl_t, C.h_glt);
+    upload(s, C.gl_w, C.h_glw);
+    upload(s, C.m2m, C.h_m2m);
     FM_HIP(hipStreamSynchronize(s));
-}
-
-static int offset_slot(int dx, int dy) { return (dx + 3) + 7 * (dy + 3); }
-
-// Offsets (dx, dy) in [-3, 3]^2 outside [-1, 1]^2: the 40 relative
-// positions of a V-list cell.
-static void v_offsets(std::vector<int> &dx, std::vector<int> &dy, std::vector<int> &slot2op)
-{
-    slot2op.assign(49, -1);
-    for (int y = -3; y <= 3; ++y)
-        for (int x = -3; x <= 3; ++x) {
-            if (std::abs(x) <= 1 && std::abs(y) <= 1) continue;
-            slot2op[offset_slot(x, y)] = (int)dx.size();
-            dx.push_back(x);
-            dy.push_back(y);
-        }
 }
 
 static void build_m2l_ops(fmddm_ctx *ctx)
@@ -640,23 +875,109 @@ static void build_m2l_ops(fmddm_ctx *ctx)
     M2LOps &M = ctx->m2l;
     if (M.ready) return;
     int p = ctx->prm.p, p2 = p * p;
+    M.mode = ctx->prm.m2l;
     M.M = 3 * p2;
     M.Mp = (M.M + 63) / 64 * 64;
-    M.rank = M.Mp;
     std::vector<int> dx, dy, slot;
     v_offsets(dx, dy, slot);
     int nop = (int)dx.size();
     hipStream_t s = ctx->stream;
     DBuf<int> ddx, ddy;
-    ddx.alloc(nop);
-    ddy.alloc(nop);
-    FM_HIP(hipMemcpyAsync(ddx.p, dx.data(), nop * 4, hipMemcpyHostToDevice, s));
-    FM_HIP(hipMemcpyAsync(ddy.p, dy.data(), nop * 4, hipMemcpyHostToDevice, s));
-    M.ops.alloc((size_t)nop * M.Mp * M.Mp);
-    M.ops.zero(s);
+    upload(s, ddx, dx);
+    upload(s, ddy, dy);
     int64_t tot = (int64_t)nop * p2 * p2;
+    if (M.mode == FMDDM_M2L_DENSE) {
+        M.r = M.M;
+        M.rp = M.Mp;
+        M.ops.alloc((size_t)nop * M.Mp * M.Mp);
+        M.ops.zero(s);
+        hipLaunchKernelGGL(k_m2l_ops, dim3(cdiv(tot, 256)), dim3(256), 0, s, nop, ddx.p, ddy.p,
+                           ctx->cheb.xbar.p, p, M.Mp, ctx->gc, M.ops.p);
+        FM_CHECK_LAUNCH();
+        FM_HIP(hipStreamSynchronize(s));
+        M.ready = 1;
+        return;
+    }
+    // Compressed operators.  The point kernel is symmetric and even, so the
+    // transpose of an offset's operator is the operator of the opposite
+    // offset: the column space of all operators side by side is also their
+    // row space, and one SVD gives both bases.
+    DBuf<double> raw;
+    raw.alloc((size_t)nop * M.Mp * M.Mp);
+    raw.zero(s);
     hipLaunchKernelGGL(k_m2l_ops, dim3(cdiv(tot, 256)), dim3(256), 0, s, nop, ddx.p, ddy.p,
-                       ctx->cheb.xbar.p, p, M.Mp, ctx->gc, M.ops.p);
+                       ctx->cheb.xbar.p, p, M.Mp, 1.0, raw.p);
+    FM_CHECK_LAUNCH();
+    int m = M.M, ncol = nop * M.M;
+    DBuf<double> fat, S, U, E;
+    DBuf<int> info;
+    fat.alloc((size_t)m * ncol);
+    S.alloc(m);
+    U.alloc((size_t)m * m);
+    E.alloc(m);
+    info.alloc(1);
+    int64_t ftot = (int64_t)m * ncol;
+    hipLaunchKernelGGL(k_pack_fat, dim3(cdiv(ftot, 256)), dim3(256), 0, s, nop, m, M.Mp, raw.p, fat.p);
+    FM_CHECK_LAUNCH();
+    rocblas_handle h;
+    if (rocblas_create_handle(&h) != rocblas_status_success) throw Error{FMDDM_EDEVICE, "rocblas handle"};
+    rocblas_set_stream(h, s);
+    rocblas_status st = rocsolver_dgesvd(h, rocblas_svect_singular, rocblas_svect_none, m, ncol, fat.p, m, S.p,
+                                         U.p, m, nullptr, 1, E.p, rocblas_outofplace, info.p);
+    FM_HIP(hipStreamSynchronize(s));
+    rocblas_destroy_handle(h);
+    if (st != rocblas_status_success) throw Error{FMDDM_EDEVICE, "rocsolver_dgesvd failed"};
+    int hinfo = 0;
+    std::vector<double> hs(m);
+    FM_HIP(hipMemcpy(&hinfo, info.p, 4, hipMemcpyDeviceToHost));
+    FM_HIP(hipMemcpy(hs.data(), S.p, m * 8, hipMemcpyDeviceToHost));
+    if (hinfo != 0) throw Error{FMDDM_EDEVICE, "SVD did not converge"};
+    int r = 0;
+    M.sv.resize(m);
+    for (int i = 0; i < m; ++i) {
+        M.sv[i] = hs[0] > 0 ? hs[i] / hs[0] : 0.0;
+        if (M.sv[i] > ctx->prm.m2l_tol) r = i + 1;
+    }
+    r = std::max(r, 1);
+    M.r = r;
+    M.rp = (r + 63) / 64 * 64;
+    int rp = M.rp, Mp = M.Mp;
+    M.Vt.alloc((size_t)rp * Mp);
+    M.Ur.alloc((size_t)Mp * rp);
+    hipLaunchKernelGGL(k_bases, dim3(cdiv((int64_t)rp * Mp, 256)), dim3(256), 0, s, m, Mp, r, rp, U.p, M.Vt.p,
+                       M.Ur.p);
+    FM_CHECK_LAUNCH();
+    // C_o = V^T K_o V: first T1[o rp + i] = K_o V[:, i], then
+    // Ct[o rp + i] = V^T T1[o rp + i] (= column i of C_o)
+    std::vector<int> top, tb, te, src, dst, zero;
+    for (int o = 0; o < nop; ++o)
+        for (int i0 = 0; i0 < rp; i0 += TILE_N) {
+            top.push_back(o);
+            zero.push_back(0);
+            tb.push_back((int)src.size());
+            for (int i = i0; i < std::min(rp, i0 + TILE_N); ++i) {
+                src.push_back(i);
+                dst.push_back(o * rp + i);
+            }
+            te.push_back((int)src.size());
+        }
+    DBuf<int> dtop, dtb, dte, dsrc, ddst, dzero;
+    upload(s, dtop, top);
+    upload(s, dtb, tb);
+    upload(s, dte, te);
+    upload(s, dsrc, src);
+    upload(s, ddst, dst);
+    upload(s, dzero, zero);
+    DBuf<double> T1, Ct;
+    T1.alloc((size_t)nop * rp * Mp);
+    Ct.alloc((size_t)nop * rp * rp);
+    launch_ggemm<64, 32>(s, (int)top.size(), Mp, raw.p, (size_t)Mp * Mp, Mp, Mp, M.Vt.p, Mp, dtop.p, dtb.p,
+                         dte.p, dsrc.p, ddst.p, nullptr, T1.p, Mp);
+    launch_ggemm<64, 32>(s, (int)top.size(), rp, M.Vt.p, 0, Mp, Mp, T1.p, Mp, dzero.p, dtb.p, dte.p, ddst.p,
+                         ddst.p, nullptr, Ct.p, rp);
+    M.ops.alloc((size_t)nop * rp * rp);
+    hipLaunchKernelGGL(k_transpose_ops, dim3(cdiv((int64_t)nop * rp * rp, 256)), dim3(256), 0, s, nop, rp,
+                       ctx->gc, Ct.p, M.ops.p);
     FM_CHECK_LAUNCH();
     FM_HIP(hipStreamSynchronize(s));
     M.ready = 1;
@@ -667,11 +988,12 @@ void setup_fmm(fmddm_ctx *ctx, fmddm_tree *t)
     if (t->Wexp.p) return;
     build_m2l_ops(ctx);
     hipStream_t s = ctx->stream;
-    int Mp = ctx->m2l.Mp, ncell = t->ncell;
-    // M2L schedule: V pairs grouped by offset, tiles of GN pairs
+    const M2LOps &M = ctx->m2l;
+    int Mp = M.Mp, rp = M.rp, ncell = t->ncell, p = ctx->prm.p;
+    // M2L schedule: V pairs grouped by offset, tiles of TILE_N pairs
     std::vector<int> hv(t->nV), hix(ncell), hiy(ncell);
     std::vector<double> hhw(ncell);
-    FM_HIP(hipMemcpyAsync(hv.data(), t->lidx[1].p, t->nV * 4, hipMemcpyDeviceToHost, s));
+    if (t->nV) FM_HIP(hipMemcpyAsync(hv.data(), t->lidx[1].p, t->nV * 4, hipMemcpyDeviceToHost, s));
     FM_HIP(hipMemcpyAsync(hix.data(), t->cix.p, ncell * 4, hipMemcpyDeviceToHost, s));
     FM_HIP(hipMemcpyAsync(hiy.data(), t->ciy.p, ncell * 4, hipMemcpyDeviceToHost, s));
     FM_HIP(hipMemcpyAsync(hhw.data(), t->chw.p, ncell * 8, hipMemcpyDeviceToHost, s));
@@ -681,50 +1003,77 @@ void setup_fmm(fmddm_ctx *ctx, fmddm_tree *t)
     int nop = (int)dx.size();
     std::vector<std::vector<int>> byop(nop);
     const std::vector<int> &vo = t->h_loff[1];
+    std::vector<int> owner(t->nV);
     for (int c = 0; c < ncell; ++c)
         for (int k = vo[c]; k < vo[c + 1]; ++k) {
             int src = hv[k];
+            owner[k] = c;
             int ox = (int)hix[src] - (int)hix[c], oy = (int)hiy[src] - (int)hiy[c];
             if (std::abs(ox) > 3 || std::abs(oy) > 3 || slot[offset_slot(ox, oy)] < 0)
                 throw Error{FMDDM_EDEVICE, "V-list entry outside the offset stencil"};
             byop[slot[offset_slot(ox, oy)]].push_back(k);
         }
-    std::vector<int> top, tbeg, tend, pk, psrc;
+    std::vector<int> top, tbeg, tend, psrc, pdst;
     std::vector<double> pscale;
     for (int o = 0; o < nop; ++o) {
         const std::vector<int> &ks = byop[o];
-        for (size_t b = 0; b < ks.size(); b += GN) {
+        for (size_t b = 0; b < ks.size(); b += TILE_N) {
             top.push_back(o);
-            tbeg.push_back((int)pk.size());
-            size_t e = std::min(ks.size(), b + GN);
-            for (size_t i = b; i < e; ++i) {
+            tbeg.push_back((int)psrc.size());
+            for (size_t i = b; i < std::min(ks.size(), b + TILE_N); ++i) {
                 int k = ks[i];
-                int c = (int)(std::upper_bound(vo.begin(), vo.end(), k) - vo.begin()) - 1;
-                pk.push_back(k);
+                double h = hhw[owner[k]];
                 psrc.push_back(hv[k]);
-                pscale.push_back(1.0 / (hhw[c] * hhw[c]));
+                pdst.push_back(k);
+                pscale.push_back(1.0 / (h * h));
             }
-            tend.push_back((int)pk.size());
+            tend.push_back((int)psrc.size());
         }
     }
     t->ntile = (int)top.size();
-    t->tile_op.alloc(t->ntile); t->tile_beg.alloc(t->ntile); t->tile_end.alloc(t->ntile);
-    t->pair_k.alloc(pk.size()); t->pair_src.alloc(pk.size()); t->pair_scale.alloc(pk.size());
-    if (t->ntile) {
-        FM_HIP(hipMemcpyAsync(t->tile_op.p, top.data(), top.size() * 4, hipMemcpyHostToDevice, s));
-        FM_HIP(hipMemcpyAsync(t->tile_beg.p, tbeg.data(), tbeg.size() * 4, hipMemcpyHostToDevice, s));
-        FM_HIP(hipMemcpyAsync(t->tile_end.p, tend.data(), tend.size() * 4, hipMemcpyHostToDevice, s));
-        FM_HIP(hipMemcpyAsync(t->pair_k.p, pk.data(), pk.size() * 4, hipMemcpyHostToDevice, s));
-        FM_HIP(hipMemcpyAsync(t->pair_src.p, psrc.data(), psrc.size() * 4, hipMemcpyHostToDevice, s));
-        FM_HIP(hipMemcpyAsync(t->pair_scale.p, pscale.data(), pscale.size() * 8, hipMemcpyHostToDevice, s));
+    upload(s, t->tile_op, top);
+    upload(s, t->tile_beg, tbeg);
+    upload(s, t->tile_end, tend);
+    upload(s, t->pair_src, psrc);
+    upload(s, t->pair_dst, pdst);
+    upload(s, t->pair_scale, pscale);
+    // cells at level >= 2
+    std::vector<int> far, fop, fb, fe;
+    for (int c = 0; c < ncell; ++c)
+        if (t->h_level[c] >= 2) far.push_back(c);
+    for (size_t b = 0; b < far.size(); b += TILE_N) {
+        fop.push_back(0);
+        fb.push_back((int)b);
+        fe.push_back((int)std::min(far.size(), b + TILE_N));
     }
+    t->nfar = (int)far.size();
+    t->nftile = (int)fop.size();
+    upload(s, t->far_cells, far);
+    upload(s, t->ftile_op, fop);
+    upload(s, t->ftile_beg, fb);
+    upload(s, t->ftile_end, fe);
+    // per-element anterpolation weights
+    t->p2m_mat.alloc((size_t)t->n * p * p);
+    hipLaunchKernelGGL(k_p2m_mats, dim3(t->nleaf), dim3(256), 0, s, t->nleaf, t->dleaves.p, t->cpbeg.p,
+                       t->cpend.p, t->ccx.p, t->ccy.p, t->chw.p, t->scx.p, t->scy.p, t->scb.p, t->ssb.p,
+                       t->sa.p, ctx->cheb.tnode.p, ctx->cheb.gl_t.p, ctx->cheb.gl_w.p, p, t->p2m_mat.p);
+    FM_CHECK_LAUNCH();
     t->Wexp.alloc((size_t)ncell * Mp);
-    t->Fexp.alloc((size_t)ncell * Mp);
-    t->Zm2l.alloc((size_t)std::max<int64_t>(t->nV, 1) * Mp);
+    t->Gexp.alloc((size_t)ncell * Mp);
+    t->Zm2l.alloc((size_t)std::max<int64_t>(t->nV, 1) * rp);
     t->Wexp.zero(s);
-    t->Fexp.zero(s);
+    t->Gexp.zero(s);
+    if (M.mode == FMDDM_M2L_SVD) {
+        t->What.alloc((size_t)ncell * rp);
+        t->Ghat.alloc((size_t)ncell * rp);
+        t->What.zero(s);
+        t->Ghat.zero(s);
+    }
     t->q.alloc(3 * (size_t)t->n);
-    t->Dsort.alloc(2 * (size_t)t->n);  // D in tree order
+    t->Dsort.alloc(2 * (size_t)t->n);
+    t->far_s.alloc(3 * (size_t)t->n);
+    t->part_s.alloc(3 * (size_t)t->npartial);
+    if (M.mode == FMDDM_M2L_SVD) t->ksplit.alloc((size_t)KSPLIT * ncell * rp);
     FM_HIP(hipStreamSynchronize(s));
 }
 
@@ -732,55 +1081,89 @@ void fmm_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out)
 {
     setup_fmm(ctx, t);
     hipStream_t s = ctx->stream;
-    int p = ctx->prm.p, Mp = ctx->m2l.Mp, n = (int)t->n;
+    const M2LOps &M = ctx->m2l;
+    int p = ctx->prm.p, Mp = M.Mp, rp = M.rp, n = (int)t->n;
     const Cheb &C = ctx->cheb;
     Profiler &P = ctx->prof;
     hipEvent_t e0;
     P.begin(FMDDM_PH_PREP, s, e0);
-    hipLaunchKernelGGL(k_prep, dim3(cdiv(n, 256)), dim3(256), 0, s, n, t->perm.p, D, t->scb.p,
-                       t->ssb.p, t->Dsort.p, t->q.p);
+    hipLaunchKernelGGL(k_prep, dim3(cdiv(n, 256)), dim3(256), 0, s, n, t->perm.p, D, t->scb.p, t->ssb.p,
+                       t->Dsort.p, t->q.p);
     FM_CHECK_LAUNCH();
     P.end(FMDDM_PH_PREP, s, e0);
+    // the near field depends only on the prepared sources: it runs on the
+    // side stream while the far-field passes run here
+    hipStream_t s2 = ctx->side;
+    FM_HIP(hipEventRecord(ctx->ev_fork, s));
+    FM_HIP(hipStreamWaitEvent(s2, ctx->ev_fork, 0));
+    hipEvent_t e1;
+    P.begin(FMDDM_PH_NEAR, s2, e1);
+    hipLaunchKernelGGL(k_p2p, dim3(t->nitem), dim3(NT), 0, s2, t->nitem, t->it_leaf.p, t->it_s0.p, t->it_s1.p,
+                       t->it_poff.p, t->dleaves.p, t->cpbeg.p, t->cpend.p, t->noff.p, t->nbeg.p, t->npre.p,
+                       t->scx.p, t->scy.p, t->scb.p, t->ssb.p, t->sa.p, t->Dsort.p, ctx->gc, t->part_s.p);
+    FM_CHECK_LAUNCH();
+    P.end(FMDDM_PH_NEAR, s2, e1);
+    FM_HIP(hipEventRecord(ctx->ev_join, s2));
     bool far = t->nV > 0;
     if (far) {
         P.begin(FMDDM_PH_P2M, s, e0);
-        hipLaunchKernelGGL(k_p2m, dim3(t->nleaf), dim3(P2M_T), 0, s, t->nleaf, t->dleaves.p, t->cpbeg.p,
-                           t->cpend.p, t->ccx.p, t->ccy.p, t->chw.p, t->scx.p, t->scy.p, t->scb.p,
-                           t->ssb.p, t->sa.p, t->q.p, C.tnode.p, C.gl_t.p, C.gl_w.p, p, Mp, t->Wexp.p);
+        hipLaunchKernelGGL(k_p2m, dim3(t->nleaf), dim3(256), 0, s, t->nleaf, t->dleaves.p, t->cpbeg.p,
+                           t->cpend.p, t->p2m_mat.p, t->q.p, p * p, Mp, t->Wexp.p);
         FM_CHECK_LAUNCH();
         P.end(FMDDM_PH_P2M, s, e0);
         P.begin(FMDDM_PH_M2M, s, e0);
-        for (int l = t->nlevel - 2; l >= 0; --l) {
+        // levels 0 and 1 have no interaction lists: their weights are unused
+        for (int l = t->nlevel - 2; l >= 2; --l) {
             int c0 = t->level_start[l], nc = t->level_start[l + 1] - c0;
-            hipLaunchKernelGGL(k_m2m, dim3(nc), dim3(TT), 0, s, c0, nc, t->cleaf.p, t->cchild.p,
-                               C.m2m.p, p, Mp, t->Wexp.p);
-            FM_CHECK_LAUNCH();
+#define FM_M2M(PP) launch_m2m<PP>(s, c0, nc, t->cleaf.p, t->cchild.p, C.m2m.p, Mp, t->Wexp.p)
+            FM_DISPATCH_P(p, FM_M2M)
+#undef FM_M2M
         }
         P.end(FMDDM_PH_M2M, s, e0);
         P.begin(FMDDM_PH_M2L, s, e0);
-        if (t->ntile) {
-            hipLaunchKernelGGL(k_m2l_gemm, dim3(t->ntile, Mp / GM), dim3(256), 0, s, ctx->m2l.ops.p, Mp,
-                               t->Wexp.p, t->tile_op.p, t->tile_beg.p, t->tile_end.p, t->pair_k.p,
-                               t->pair_src.p, t->pair_scale.p, t->Zm2l.p);
+        if (M.mode == FMDDM_M2L_SVD) {
+            // projection onto the singular vectors: K = 3p^2 is long and the
+            // output small, so K is split over KSPLIT blocks and summed after
+            launch_ggemm<32, 32>(s, t->nftile, rp, M.Vt.p, 0, Mp, Mp, t->Wexp.p, Mp, t->ftile_op.p,
+                                 t->ftile_beg.p, t->ftile_end.p, t->far_cells.p, t->far_cells.p, nullptr,
+                                 t->ksplit.p, rp, KSPLIT, (size_t)t->ncell * rp);
+            {
+                int64_t c0 = t->level_start[2], cnt = (int64_t)(t->ncell - c0) * rp;
+                hipLaunchKernelGGL(k_reduce_split, dim3(cdiv(cnt, 256)), dim3(256), 0, s, cnt, KSPLIT,
+                                   (size_t)t->ncell * rp, t->ksplit.p + c0 * rp, t->What.p + c0 * rp);
+                FM_CHECK_LAUNCH();
+            }
+            launch_ggemm<64, 32>(s, t->ntile, rp, M.ops.p, (size_t)rp * rp, rp, rp, t->What.p, rp, t->tile_op.p,
+                                 t->tile_beg.p, t->tile_end.p, t->pair_src.p, t->pair_dst.p, t->pair_scale.p,
+                                 t->Zm2l.p, rp);
+            hipLaunchKernelGGL(k_sum_pairs, dim3(t->nfar), dim3(256), 0, s, t->nfar, t->far_cells.p,
+                               t->loff[1].p, t->Zm2l.p, rp, rp, t->Ghat.p, rp);
+            FM_CHECK_LAUNCH();
+            launch_ggemm<64, 32>(s, t->nftile, Mp, M.Ur.p, 0, rp, rp, t->Ghat.p, rp, t->ftile_op.p,
+                                 t->ftile_beg.p, t->ftile_end.p, t->far_cells.p, t->far_cells.p, nullptr,
+                                 t->Gexp.p, Mp);
+        } else {
+            launch_ggemm<64, 32>(s, t->ntile, Mp, M.ops.p, (size_t)Mp * Mp, Mp, Mp, t->Wexp.p, Mp, t->tile_op.p,
+                                 t->tile_beg.p, t->tile_end.p, t->pair_src.p, t->pair_dst.p, t->pair_scale.p,
+                                 t->Zm2l.p, Mp);
+            hipLaunchKernelGGL(k_sum_pairs, dim3(t->nfar), dim3(256), 0, s, t->nfar, t->far_cells.p,
+                               t->loff[1].p, t->Zm2l.p, Mp, Mp, t->Gexp.p, Mp);
             FM_CHECK_LAUNCH();
         }
         P.end(FMDDM_PH_M2L, s, e0);
-        P.begin(FMDDM_PH_DOWN, s, e0);
-        for (int l = 1; l < t->nlevel; ++l) {
-            int c0 = t->level_start[l], nc = t->level_start[l + 1] - c0;
-            hipLaunchKernelGGL(k_down, dim3(nc), dim3(TT), 0, s, c0, nc, t->cparent.p, t->cix.p, t->ciy.p,
-                               t->loff[1].p, t->Zm2l.p, C.m2m.p, p, Mp, l >= 2 ? 1 : 0, t->Fexp.p);
-            FM_CHECK_LAUNCH();
-        }
-        P.end(FMDDM_PH_DOWN, s, e0);
     }
-    P.begin(FMDDM_PH_NEAR, s, e0);
-    hipLaunchKernelGGL(k_l2p_p2p, dim3(t->nleaf), dim3(PT), 0, s, t->nleaf, t->dleaves.p, t->cpbeg.p,
-                       t->cpend.p, t->noff.p, t->nsrc.p, t->ccx.p, t->ccy.p, t->chw.p, t->scx.p, t->scy.p,
-                       t->scb.p, t->ssb.p, t->sa.p, t->Dsort.p, t->perm.p, t->Fexp.p, C.tnode.p, p, Mp,
-                       ctx->gc, far ? 1 : 0, out);
+    P.begin(FMDDM_PH_DOWN, s, e0);
+    if (far) {
+#define FM_L2P(PP) launch_l2p<PP>(s, ctx, t, Mp)
+        FM_DISPATCH_P(p, FM_L2P)
+#undef FM_L2P
+    }
+    P.end(FMDDM_PH_DOWN, s, e0);
+    FM_HIP(hipStreamWaitEvent(s, ctx->ev_join, 0));
+    hipLaunchKernelGGL(k_final, dim3(cdiv(n, 256)), dim3(256), 0, s, n, t->tleaf.p, t->dleaves.p, t->cpbeg.p,
+                       t->lk_off.p, t->it_poff.p, t->part_s.p, far ? t->far_s.p : (const double *)nullptr,
+                       t->scb.p, t->ssb.p, t->perm.p, out);
     FM_CHECK_LAUNCH();
-    P.end(FMDDM_PH_NEAR, s, e0);
 }
 
 }  // namespace fmddm

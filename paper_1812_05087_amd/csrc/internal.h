@@ -54,6 +54,7 @@ struct DBuf {
 };
 
 constexpr int MAXP = 32;
+constexpr int NEAR_CHUNK = 256;  // sources per near-field work item
 
 // ------------------------------------------------------------- context
 struct Cheb {
@@ -62,16 +63,21 @@ struct Cheb {
     DBuf<double> xbar;      // p nodes
     DBuf<double> gl_t, gl_w;  // p-point Gauss-Legendre
     DBuf<double> m2m;       // [side][l_parent][l_child] = S_p(xbar_l, +-1/2 + xbar_l'/2), 2 x p x p
-    std::vector<double> h_xbar, h_tnode, h_m2m, h_glt, h_glw;
+    DBuf<double> bw;        // barycentric weights of the nodes
+    std::vector<double> h_xbar, h_tnode, h_m2m, h_glt, h_glw, h_bw;
 };
 
 struct M2LOps {
     int ready = 0;
+    int mode = 0;           // fmddm_m2l_mode
     int M = 0;              // 3 p^2
-    int Mp = 0;             // padded row stride (multiple of 64)
-    int rank = 0;           // operator dimension used by the GEMM (Mp or compressed)
-    DBuf<double> ops;       // 49 offset slots x rank x rank (unused slots unfilled)
-    DBuf<double> Ut, Vt;    // SVD bases (compressed mode): rank x Mp each
+    int Mp = 0;             // expansion stride (3 p^2 padded to a multiple of 64)
+    int r = 0;              // retained rank (M when uncompressed)
+    int rp = 0;             // operator dimension used by the GEMMs (Mp or r padded to 64)
+    DBuf<double> ops;       // 40 offset operators, rp x rp each, row-major
+    DBuf<double> Ur;        // compressed mode: Mp x rp, columns = left singular vectors
+    DBuf<double> Vt;        // compressed mode: rp x Mp, rows = the same vectors
+    std::vector<double> sv; // normalised singular values (compressed mode)
 };
 
 }  // namespace fmddm
@@ -94,6 +100,16 @@ struct fmddm_ctx {
     fmddm_params prm;
     fmddm::Profiler prof;
     hipStream_t stream = nullptr;
+    // second stream (default priority) for work independent of the far
+    // field, forked from and joined back into `stream` with events
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    ~fmddm_ctx()
+    {
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
+        if (side) (void)hipStreamDestroy(side);
+    }
     int device = 0;
     std::string err;
     fmddm::Cheb cheb;
@@ -124,18 +140,37 @@ struct fmddm_tree {
     std::vector<int> h_loff[4];
     // near field: per leaf, source cells whose points act directly
     fmddm::DBuf<int> noff, nsrc;
+    fmddm::DBuf<int> nbeg, npre, ntot;  // per near entry: first source, prefix in its leaf; per leaf: total
+    fmddm::DBuf<int> aoff, aidx;        // per leaf: its ancestors (itself first) at level >= 2
+    // near-field work items: a leaf's sources split into chunks of at most
+    // NEAR_CHUNK, each item producing partial stresses for the leaf's points
+    int nitem = 0;
+    int64_t npartial = 0;
+    fmddm::DBuf<int> it_leaf, it_s0, it_s1, it_poff, lk_off, tleaf;
     std::vector<int> leaves;          // host list of leaf cells (tree order)
     fmddm::DBuf<int> dleaves;
-    int64_t near_pairs = 0;
+    int64_t near_pairs = 0, l2p_pairs = 0;
     // M2L schedule: pairs are V-list entries grouped by offset into tiles
     int ntile = 0;
-    fmddm::DBuf<int> tile_op, tile_beg, tile_end, pair_k, pair_src;
+    fmddm::DBuf<int> tile_op, tile_beg, tile_end, pair_src, pair_dst;
     fmddm::DBuf<double> pair_scale;
     int64_t nV = 0;
+    // cells at level >= 2 (the only ones with interaction lists), as
+    // identity "pairs" for the compress / decompress products
+    int nfar = 0, nftile = 0;
+    fmddm::DBuf<int> far_cells, ftile_op, ftile_beg, ftile_end;
     // expansions
-    fmddm::DBuf<double> Wexp, Fexp, Zm2l, Wc, Gc;
+    fmddm::DBuf<double> p2m_mat;      // per element (tree order): p^2 weights of its anterpolation
+    fmddm::DBuf<double> Wexp;         // multipole weights, ncell x Mp
+    fmddm::DBuf<double> What;         // compressed weights, ncell x rp
+    fmddm::DBuf<double> Zm2l;         // one M2L product per V pair, nV x rp
+    fmddm::DBuf<double> Ghat;         // summed compressed M2L fields, ncell x rp
+    fmddm::DBuf<double> Gexp;         // M2L field of each cell at its nodes, ncell x Mp
     fmddm::DBuf<double> q;            // charges, tree order, 3 per element
     fmddm::DBuf<double> Dsort;        // D in tree order
+    fmddm::DBuf<double> far_s;        // far-field stress per point, tree order, 3 each
+    fmddm::DBuf<double> part_s;       // near-field partial stresses per work item
+    fmddm::DBuf<double> ksplit;       // split-K partial products
     // dense operator (built on demand)
     fmddm::DBuf<double> Adense;
     // solver workspace

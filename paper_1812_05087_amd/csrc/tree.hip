@@ -678,21 +678,72 @@ void build_tree(fmddm_ctx *ctx, fmddm_tree *t, int64_t n64, const double *x1, co
                        t->cparent.p, ploff.p, plidx.p, 1, (int *)nullptr, (const int *)t->noff.p,
                        t->nsrc.p);
     FM_CHECK_LAUNCH();
-    // count of directly evaluated pairs (reporting only)
+    // flattened near-source ranges and ancestor lists per leaf (schedule
+    // for the near-field kernel), and the count of direct pairs
     {
-        std::vector<int> hn(hnoff[t->nleaf]), hb(ncell), he(ncell);
-        FM_HIP(hipMemcpyAsync(hn.data(), t->nsrc.p, hn.size() * 4, hipMemcpyDeviceToHost, s));
+        std::vector<int> hn(hnoff[t->nleaf]), hb(ncell), he(ncell), hp(ncell);
+        if (!hn.empty())
+            FM_HIP(hipMemcpyAsync(hn.data(), t->nsrc.p, hn.size() * 4, hipMemcpyDeviceToHost, s));
         FM_HIP(hipMemcpyAsync(hb.data(), t->cpbeg.p, ncell * 4, hipMemcpyDeviceToHost, s));
         FM_HIP(hipMemcpyAsync(he.data(), t->cpend.p, ncell * 4, hipMemcpyDeviceToHost, s));
+        FM_HIP(hipMemcpyAsync(hp.data(), t->cparent.p, ncell * 4, hipMemcpyDeviceToHost, s));
         FM_HIP(hipStreamSynchronize(s));
+        std::vector<int> nbeg(hn.size()), npre(hn.size()), ntot(t->nleaf), aoff(t->nleaf + 1, 0), aidx;
         int64_t pairs = 0;
         for (int i = 0; i < t->nleaf; ++i) {
             int c = t->leaves[i];
-            int64_t srcs = 0;
-            for (int k = hnoff[i]; k < hnoff[i + 1]; ++k) srcs += he[hn[k]] - hb[hn[k]];
-            pairs += srcs * (he[c] - hb[c]);
+            int acc = 0;
+            for (int k = hnoff[i]; k < hnoff[i + 1]; ++k) {
+                nbeg[k] = hb[hn[k]];
+                npre[k] = acc;
+                acc += he[hn[k]] - hb[hn[k]];
+            }
+            ntot[i] = acc;
+            pairs += (int64_t)acc * (he[c] - hb[c]);
+            for (int A = c; A >= 0; A = hp[A])
+                if (t->h_level[A] >= 2) aidx.push_back(A);
+            aoff[i + 1] = (int)aidx.size();
+            t->l2p_pairs += (int64_t)(aoff[i + 1] - aoff[i]) * (he[c] - hb[c]);
         }
         t->near_pairs = pairs;
+        auto up = [&](DBuf<int> &d, const std::vector<int> &h) {
+            d.alloc(h.size());
+            if (!h.empty()) FM_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * 4, hipMemcpyHostToDevice, s));
+        };
+        up(t->nbeg, nbeg);
+        up(t->npre, npre);
+        up(t->ntot, ntot);
+        up(t->aoff, aoff);
+        up(t->aidx, aidx);
+        // near-field work items and the leaf of every point
+        std::vector<int> it_leaf, it_s0, it_s1, it_poff, lk_off(t->nleaf + 1, 0), tleaf(n, -1);
+        int64_t poff = 0;
+        for (int i = 0; i < t->nleaf; ++i) {
+            int c = t->leaves[i];
+            int nt = he[c] - hb[c];
+            for (int k = hb[c]; k < he[c]; ++k) tleaf[k] = i;
+            int s0 = 0;
+            do {
+                int s1 = std::min(ntot[i], s0 + NEAR_CHUNK);
+                it_leaf.push_back(i);
+                it_s0.push_back(s0);
+                it_s1.push_back(s1);
+                it_poff.push_back((int)poff);
+                poff += nt;
+                s0 = s1;
+            } while (s0 < ntot[i]);
+            lk_off[i + 1] = (int)it_leaf.size();
+        }
+        if (poff > (int64_t)1 << 30) throw Error{FMDDM_EINVAL, "near-field partials too large"};
+        t->nitem = (int)it_leaf.size();
+        t->npartial = poff;
+        up(t->it_leaf, it_leaf);
+        up(t->it_s0, it_s0);
+        up(t->it_s1, it_s1);
+        up(t->it_poff, it_poff);
+        up(t->lk_off, lk_off);
+        up(t->tleaf, tleaf);
+        FM_HIP(hipStreamSynchronize(s));
     }
 }
 

@@ -250,3 +250,52 @@ def test_solve_maxit_reports_not_converged():
     assert info["status"] == F.FMDDM_ENOTCONV and not info["converged"]
     assert info["iters"] == 3
     prob.close()
+
+
+# ------------------------------------------------ SVD-compressed M2L
+@pytest.mark.parametrize("name,p", [("random600_leaf16", 6), ("random750_leaf8", 8), ("well5x40", 10)])
+def test_fmm_svd_close_to_oracle_fmm(name, p):
+    """Compressed M2L (singular values below 1e-12 of the largest dropped):
+    within 1e-9 of the oracle's uncompressed FMM."""
+    wl, kw = CASES[name]
+    g = O.Geometry.of(wl)
+    prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=wl.E, nu=wl.nu, p=p, m2l=F.FMDDM_M2L_SVD,
+                     m2l_tol=1e-12, **kw)
+    T = O.Tree(g, leaf=kw["leaf"], cap=kw.get("max_level", O.MAX_LEVEL))
+    D = W.random_vector(13, g.n)
+    y = prob.apply(prob.vec(D), F.FMDDM_APPLY_FMM).cpu().numpy()
+    yo = T.fmm(D, p)
+    assert rel(y, yo) < 1e-9
+    info = F.fmddm_tree_get_info(prob.ctx, prob.tree)
+    assert 0 < info["m2l_rank"] < 3 * p * p
+    prob.close()
+
+
+def test_c2_fmm_svd_full_size(c2):
+    """C2 with the compressed M2L: FMM vs the exact product <= 1e-6 (and
+    sampled oracle rows)."""
+    wl, g, prob0 = c2
+    prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=wl.E, nu=wl.nu, leaf=32, p=20,
+                     m2l=F.FMDDM_M2L_SVD, m2l_tol=1e-12)
+    D = W.random_vector(5, g.n)
+    Dd = prob.vec(D)
+    yf = prob.apply(Dd, F.FMDDM_APPLY_FMM).cpu().numpy().reshape(-1, 2)
+    yd = prob0.apply(Dd, F.FMDDM_APPLY_DIRECT).cpu().numpy().reshape(-1, 2)
+    assert rel(yf, yd) < 1e-6
+    rng = np.random.default_rng(1)
+    idx = rng.choice(g.n, 200, replace=False)
+    yo = O.direct_matvec_rows(g, D, idx)
+    assert elementwise(yf[idx], yo) < 1e-6
+    prob.close()
+
+
+def test_solve_svd_griffith():
+    wl = W.c1()
+    g = O.Geometry.of(wl)
+    prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=wl.E, nu=wl.nu, tol=1e-10, m2l=F.FMDDM_M2L_SVD)
+    b = prob.rhs(wl.pressure, 0.0, 0.0)
+    xo = O.lu_solve(O.dense_matrix(g), O.rhs(g, wl.pressure, 0.0, 0.0))
+    x, info = prob.solve(b, F.FMDDM_APPLY_FMM)
+    assert info["converged"]
+    assert rel(x.cpu().numpy(), xo) < 1e-8
+    prob.close()
