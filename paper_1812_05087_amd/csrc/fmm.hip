@@ -198,17 +198,33 @@ __global__ __launch_bounds__(XT) void k_m2m(int c0, int nc, const int *__restric
     constexpr int UO = P <= 20 ? P : 4;  // outer unroll: bounds the live operator values
     __shared__ double buf[4 * N3];
     __shared__ double Ts[2 * P2];
-    __shared__ int kid[4];
     int c = c0 + xcd_remap(blockIdx.x, nc);
     if (leaf[c]) return;
     int tid = threadIdx.x, side = wave_side(), q0 = tid & 127;
-    if (tid < 4) kid[tid] = child[4 * c + tid];
+    // all child weights are requested before any is stored, so one block
+    // pays the memory latency once; a missing child reads the first
+    // existing one and stores zeros
+    int k4[4], kany = -1;
+#pragma unroll
+    for (int d = 3; d >= 0; --d) {
+        k4[d] = child[4 * c + d];
+        if (k4[d] >= 0) kany = k4[d];
+    }
+    constexpr int NL = (4 * N3 + XT - 1) / XT;
+    double v[NL];
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+        int e = tid + j * XT;
+        int d = min(e / N3, 3), r = min(e - d * N3, N3 - 1);
+        int k = k4[d] >= 0 ? k4[d] : kany;
+        v[j] = W[(size_t)k * Mp + r];
+    }
     for (int e = tid; e < 2 * P2; e += XT) Ts[e] = Tm[e];
-    __syncthreads();
-    for (int e = tid; e < 4 * N3; e += XT) {
-        int d = e / N3, r = e - d * N3;
-        int k = kid[d];
-        buf[e] = k >= 0 ? W[(size_t)k * Mp + r] : 0.0;
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+        int e = tid + j * XT;
+        int d = min(e / N3, 3);
+        if (e < 4 * N3) buf[e] = k4[d] >= 0 ? v[j] : 0.0;
     }
     __syncthreads();
     // x pass, child d = side + 2 dy: column m2 of in_d[c] <- Tx_d . column
