@@ -36,35 +36,57 @@ FLOP_PER_PAIR = 78
 
 
 def phase_work(info, p, tree, rank, svd):
-    """Algorithmic work of one launch set of each FMM phase:
+    """Algorithmic work of each kernel of one FMM product:
     (bound, amount, unit, peak).  Flops count +,-,* as 1 and a fused
     multiply-add as 2; bytes are the compulsory HBM traffic."""
     n = info["n"]
     M = 3 * p * p
     lev, leaf = tree["level"], tree["isleaf"]
-    parents = int(((lev >= 2) & (leaf == 0)).sum())
-    nfar, nV = info["nfar"], info["nV"]
-    if svd:
-        m2l = 2.0 * rank * M * nfar * 2 + 2.0 * rank * rank * nV
-    else:
-        m2l = 2.0 * M * M * nV
-    return {
-        # D in, D and charges out in tree order (+ permutation, orientation)
-        "prep": ("hbm", 76.0 * n, "GB/s", PEAK["hbm_GBps"]),
-        # per-element anterpolation weights streamed once, charges, leaf weights
-        "p2m": ("hbm", 8.0 * p * p * n + 24.0 * n + 8.0 * M * info["nleaf"], "GB/s", PEAK["hbm_GBps"]),
-        # two separable p x p transfers per child and component
-        "m2m": ("alu", 48.0 * p ** 3 * parents, "TFLOP/s", PEAK["fp64_vector_TFLOPs"]),
-        # eq. 3.8: per V pair one operator product (compressed: r x r, plus the
-        # projections in and out of the r-dimensional space per cell)
-        "m2l": ("mfma", m2l, "TFLOP/s", PEAK["fp64_mfma_TFLOPs"]),
-        # eqs. 3.10-3.11: every (midpoint, ancestor) pair evaluates that
+    internal = int(((lev >= 2) & (leaf == 0)).sum())
+    nleaf, nfar, nV = info["nleaf"], info["nfar"], info["nV"]
+    hbm, mfma, alu = PEAK["hbm_GBps"], PEAK["fp64_mfma_TFLOPs"], PEAK["fp64_vector_TFLOPs"]
+    slots = 4 if p <= 24 else 2
+    work = {
+        # D in, sorted D and charges out, permutation, orientation
+        "prep": ("hbm", 76.0 * n, "GB/s", hbm),
+        # eq. 3.6: the per-element anterpolation matrices streamed once, the
+        # charges, the leaf weights written
+        "p2m": ("hbm", 8.0 * p * p * n + 24.0 * n + 8.0 * M * nleaf, "GB/s", hbm),
+        # eq. 3.7 per (ancestor, leaf) pair: the two p x p composite
+        # transfers applied to 3 components (12 p^3), plus forming them
+        # (2p barycentric interpolants of about 6p flops)
+        "m2m": ("alu", (12.0 * p ** 3 + 12.0 * p * p) * info["m2m_pairs"], "TFLOP/s", alu),
+        # item partials read once, the weights of internal cells written once
+        "m2m_sum": ("hbm", 8.0 * M * (-(-info["m2m_pairs"] // slots) + internal), "GB/s", hbm),
+        # eqs. 3.9-3.11: every (midpoint, ancestor) pair evaluates that
         # ancestor's field there: two barycentric interpolants (about 6p
         # each) and the 3-component p x p contraction (6p^2 + 6p)
-        "down": ("alu", (6.0 * p * p + 18.0 * p) * info["l2p_pairs"], "TFLOP/s",
-                 PEAK["fp64_vector_TFLOPs"]),
-        "near": ("alu", float(FLOP_PER_PAIR) * info["near_pairs"], "TFLOP/s", PEAK["fp64_vector_TFLOPs"]),
+        "l2p": ("alu", (6.0 * p * p + 18.0 * p) * info["l2p_pairs"], "TFLOP/s", alu),
+        "p2p": ("alu", float(FLOP_PER_PAIR) * info["near_pairs"], "TFLOP/s", alu),
+        # far and near stress in, geometry and permutation, tractions out
+        "final": ("hbm", 80.0 * n, "GB/s", hbm),
     }
+    if svd:
+        # projections in and out of the rank-r space, one per far cell, and
+        # the r x r operator product per interaction pair (eq. 3.8)
+        work["compress"] = ("mfma", 2.0 * rank * M * nfar, "TFLOP/s", mfma)
+        work["compress_sum"] = ("hbm", 8.0 * rank * nfar * 5, "GB/s", hbm)
+        work["m2l"] = ("mfma", 2.0 * rank * rank * nV, "TFLOP/s", mfma)
+        work["m2l_sum"] = ("hbm", 8.0 * rank * (nV + nfar), "GB/s", hbm)
+        work["decompress"] = ("mfma", 2.0 * rank * M * nfar, "TFLOP/s", mfma)
+    else:
+        work["m2l"] = ("mfma", 2.0 * M * M * nV, "TFLOP/s", mfma)
+        work["m2l_sum"] = ("hbm", 8.0 * M * (nV + nfar), "GB/s", hbm)
+    return work
+
+
+def kernel_name(phase, p):
+    """The library kernel behind each profiled launch."""
+    return {"prep": "k_prep", "p2m": "k_p2m", "m2m": f"k_m2m<{p}>", "m2m_sum": "k_m2m_sum",
+            "compress": "k_ggemm<32, 32> (projection)", "compress_sum": "k_reduce_split",
+            "m2l": "k_ggemm<64, 32> (pair products)", "m2l_sum": "k_sum_pairs",
+            "decompress": "k_ggemm<64, 32> (back-projection)", "l2p": f"k_l2p<{p}>", "p2p": "k_p2p",
+            "final": "k_final"}[phase]
 
 
 def kernel_source_hash():
@@ -195,12 +217,14 @@ def main():
     phases = {}
     for ph, (bound, amount, unit, peak) in work.items():
         ms = phase_ms.get(ph, 0.0)
+        if ms <= 0:
+            continue
         ach = amount / (ms * 1e-3) / scale[unit] if ms > 0 else None
         phases[ph] = {"ms": ms, "bound": bound, "work": amount, "achieved": ach, "unit": unit,
                       "frac": ach / peak if ach else None}
     bound, amount, unit, peak = work[dom]
     achieved = amount / (dom_ms * 1e-3) / scale[unit]
-    roof = {"bound": bound, "kernel": dom, "achieved": achieved, "peak": peak, "unit": unit,
+    roof = {"bound": bound, "kernel": kernel_name(dom, args.p), "achieved": achieved, "peak": peak, "unit": unit,
             "frac": achieved / peak, "traffic": traffic_for(dom), "avg_launch_ms": dom_ms}
 
     line = {
@@ -231,7 +255,7 @@ def main():
         "tree_build_ms": tree_ms,
         "first_product_setup_ms": setup_ms,
         "tree": {k: info[k] for k in ("ncell", "nleaf", "nlevel", "nV", "nfar", "near_pairs",
-                                      "l2p_pairs")},
+                                      "l2p_pairs", "m2m_pairs")},
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

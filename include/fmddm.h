@@ -94,6 +94,7 @@ typedef struct {
     int64_t nU, nV, nW, nX;   /* list lengths (sum over cells) */
     int64_t near_pairs;       /* directly evaluated point pairs per product */
     int64_t l2p_pairs;        /* (midpoint, ancestor cell) interpolations per product */
+    int64_t m2m_pairs;        /* (ancestor cell, leaf) composite transfers per product */
     int64_t nfar;             /* cells at level >= 2 (those with interaction lists) */
     int64_t m2l_rank;         /* M2L rank (3p^2 when uncompressed; 0 before the first product) */
     double root_x0, root_y0, root_L;
@@ -187,19 +188,25 @@ fmddm_status fmddm_sif(fmddm_ctx *ctx, fmddm_tree *t, const double *D, int64_t e
                        double *KI, double *KII);
 
 /* Phases of one FMM product, for fmddm_profile. */
-typedef enum {
+typedef enum {                /* one entry per kernel of an FMM product */
     FMDDM_PH_PREP = 0,        /* D to tree order, source charges */
     FMDDM_PH_P2M = 1,         /* leaf weights (eq. 3.6) */
-    FMDDM_PH_M2M = 2,         /* upward pass (eq. 3.7), all levels */
-    FMDDM_PH_M2L = 3,         /* interaction-list contraction (eq. 3.8) */
-    FMDDM_PH_DOWN = 4,        /* downward pass and L2P (eqs. 3.10-3.11, far part) */
-    FMDDM_PH_NEAR = 5,        /* direct neighbour interactions (eq. 3.11, near part) */
-    FMDDM_PH_COUNT = 6
+    FMDDM_PH_M2M = 2,         /* upward pass (eq. 3.7): partial weights per work item */
+    FMDDM_PH_M2M_SUM = 3,     /* upward pass: partials summed per cell */
+    FMDDM_PH_COMPRESS = 4,    /* weights projected on the M2L singular vectors (SVD mode) */
+    FMDDM_PH_COMPRESS_SUM = 5,/* split-K partials of the projection summed (SVD mode) */
+    FMDDM_PH_M2L = 6,         /* one operator product per interaction pair (eq. 3.8) */
+    FMDDM_PH_M2L_SUM = 7,     /* pair results summed per target cell (eq. 3.8) */
+    FMDDM_PH_DECOMPRESS = 8,  /* M2L fields back on the Chebyshev nodes (SVD mode) */
+    FMDDM_PH_L2P = 9,         /* downward pass and L2P (eqs. 3.9-3.11, far part) */
+    FMDDM_PH_P2P = 10,        /* direct neighbour interactions (eq. 3.11, near part) */
+    FMDDM_PH_FINAL = 11,      /* far + near stress to tractions, caller order */
+    FMDDM_PH_COUNT = 12
 } fmddm_phase;
 
-/* Record HIP events on the context's stream around the phases whose bit
- * (1 << fmddm_phase) is set in `mask`, for every following FMM product
- * (0 disables).  Adds two event records per timed phase and product. */
+/* Record HIP events around the kernels whose bit (1 << fmddm_phase) is set
+ * in `mask`, on the stream each runs on, for every following FMM product
+ * (0 disables).  Adds two event records per timed kernel and product. */
 fmddm_status fmddm_profile(fmddm_ctx *ctx, unsigned mask);
 
 /* Elapsed milliseconds summed per phase (ms[FMDDM_PH_COUNT]) and the number

@@ -31,7 +31,8 @@ EXPORTED = [
     "fmddm_tree_export_list", "fmddm_apply", "fmddm_rhs", "fmddm_solve", "fmddm_sif",
     "fmddm_profile", "fmddm_profile_read",
 ]
-PHASES = ["prep", "p2m", "m2m", "m2l", "down", "near"]
+PHASES = ["prep", "p2m", "m2m", "m2m_sum", "compress", "compress_sum", "m2l", "m2l_sum", "decompress",
+          "l2p", "p2p", "final"]
 
 
 class FmddmError(RuntimeError):
@@ -54,7 +55,8 @@ class TreeInfo(C.Structure):
     _fields_ = [
         ("n", C.c_int64), ("ncell", C.c_int64), ("nleaf", C.c_int64), ("nlevel", C.c_int32),
         ("nU", C.c_int64), ("nV", C.c_int64), ("nW", C.c_int64), ("nX", C.c_int64),
-        ("near_pairs", C.c_int64), ("l2p_pairs", C.c_int64), ("nfar", C.c_int64),
+        ("near_pairs", C.c_int64), ("l2p_pairs", C.c_int64), ("m2m_pairs", C.c_int64),
+        ("nfar", C.c_int64),
         ("m2l_rank", C.c_int64),
         ("root_x0", C.c_double), ("root_y0", C.c_double), ("root_L", C.c_double),
         ("device_bytes", C.c_int64),

@@ -152,8 +152,9 @@ fmddm_status fmddm_tree_get_info(fmddm_ctx *ctx, const fmddm_tree *t, fmddm_tree
     info->nX = t->h_loff[3].empty() ? 0 : t->h_loff[3].back();
     info->near_pairs = t->near_pairs;
     info->l2p_pairs = t->l2p_pairs;
+    info->m2m_pairs = t->m2m_pairs;
     for (int c = 0; c < t->ncell; ++c) info->nfar += t->h_level[c] >= 2;
-    info->m2l_rank = ctx->m2l.ready ? ctx->m2l.r : 0;
+    info->m2l_rank = ctx->m2l->ready ? ctx->m2l->r : 0;
     info->root_x0 = t->x0;
     info->root_y0 = t->y0;
     info->root_L = t->L;

@@ -151,6 +151,7 @@ __global__ __launch_bounds__(256) void k_p2m_mats(int nleaf, const int *__restri
 }
 
 // ---------------------------------------------------- P2M (per product)
+// eq. 3.6: leaf weights from the stored per-element anterpolation matrices.
 __global__ __launch_bounds__(256) void k_p2m(int nleaf, const int *__restrict__ leaves,
                                              const int *__restrict__ pbeg, const int *__restrict__ pend,
                                              const double *__restrict__ Pm, const double *__restrict__ q,
@@ -175,94 +176,136 @@ __global__ __launch_bounds__(256) void k_p2m(int nleaf, const int *__restrict__ 
 }
 
 // ------------------------------------------------------------ M2M
-// T[side][l][l'] = S_p(xbar_l, side_sign/2 + xbar_l'/2) (side 0 = lower or
-// left child): parent interpolant l at child node l'.  The pass applies
-// these p x p matrices along x and then along y.  Each lane owns one
-// column (x pass) or one row (y pass) of one (child, component) matrix and
-// keeps it in registers; the lanes of a wave share the child's side, so the
-// operator is staged in LDS and read there as wave-uniform broadcasts.
-constexpr int XT = 256;  // 4 waves: two per side
+// eq. 3.7 applied level after level gives an ancestor A the weights
+//   W_A = sum over leaves L below A of  Tx_{A<-L} W_L Ty_{A<-L}^T,
+// where the composite transfer is the product of the 1D child-to-parent
+// interpolation matrices along the path.  Each of them maps a polynomial of
+// degree < p exactly, so the composite is A's interpolant evaluated at L's
+// nodes: Tx_{A<-L}[l][l'] = S_p(xbar_l, (x_L + h_L xbar_l' - x_A) / h_A).
+// Evaluating it directly removes the level-by-level chain of dependent
+// launches.  Work items are (ancestor, up to 4 of its leaves); each writes
+// its partial sum, and the partials of an ancestor are added in a fixed
+// order afterwards.
+constexpr int XT = 256;
 
-// side of the operator used by this wave (uniform) and the lane's slot
-// among the 2 x 64 lanes of that side
-__device__ __forceinline__ int wave_side() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 7)); }
+// leaves per work item: 4, or 2 where 4 would not fit in LDS
+__host__ __device__ constexpr int m2m_slots(int p) { return p <= 24 ? 4 : 2; }
 
-// Upward pass for the parents of one level (eq. 3.7):
-//   W_P[c] = sum_d Tx_d W_d[c] Ty_d^T   (d over the existing children)
 template <int P>
-__global__ __launch_bounds__(XT) void k_m2m(int c0, int nc, const int *__restrict__ leaf,
-                                            const int *__restrict__ child, const double *__restrict__ Tm,
-                                            int Mp, double *__restrict__ W)
+__global__ __launch_bounds__(XT) void k_m2m(int nitem, const int *__restrict__ it_anc,
+                                            const int *__restrict__ it_leaf, const double *__restrict__ ccx,
+                                            const double *__restrict__ ccy, const double *__restrict__ chw,
+                                            const double *__restrict__ xbar, const double *__restrict__ bw, int Mp,
+                                            const double *__restrict__ W, double *__restrict__ part)
 {
-    constexpr int P2 = P * P, N3 = 3 * P2;
+    constexpr int P2 = P * P, N3 = 3 * P2, NS = m2m_slots(P);
     constexpr int UO = P <= 20 ? P : 4;  // outer unroll: bounds the live operator values
-    __shared__ double buf[4 * N3];
-    __shared__ double Ts[2 * P2];
-    int c = c0 + xcd_remap(blockIdx.x, nc);
-    if (leaf[c]) return;
-    int tid = threadIdx.x, side = wave_side(), q0 = tid & 127;
-    // all child weights are requested before any is stored, so one block
-    // pays the memory latency once; a missing child reads the first
-    // existing one and stores zeros
-    int k4[4], kany = -1;
+    __shared__ double buf[NS * N3];
+    __shared__ double Tx[NS][P2], Ty[NS][P2];  // [leaf slot][l * P + l']
+    __shared__ double s_xb[P], s_bw[P];
+    int item = xcd_remap(blockIdx.x, nitem);
+    int tid = threadIdx.x;
+    int A = it_anc[item];
+    // every leaf weight is requested before any is stored; an empty slot
+    // reads the first leaf and stores zeros
+    int k4[NS];
 #pragma unroll
-    for (int d = 3; d >= 0; --d) {
-        k4[d] = child[4 * c + d];
-        if (k4[d] >= 0) kany = k4[d];
-    }
-    constexpr int NL = (4 * N3 + XT - 1) / XT;
+    for (int d = 0; d < NS; ++d) k4[d] = it_leaf[4 * item + d];
+    constexpr int NL = (NS * N3 + XT - 1) / XT;
     double v[NL];
 #pragma unroll
     for (int j = 0; j < NL; ++j) {
         int e = tid + j * XT;
-        int d = min(e / N3, 3), r = min(e - d * N3, N3 - 1);
-        int k = k4[d] >= 0 ? k4[d] : kany;
+        int d = min(e / N3, NS - 1), r = min(e - d * N3, N3 - 1);
+        int k = k4[d] >= 0 ? k4[d] : k4[0];
         v[j] = W[(size_t)k * Mp + r];
     }
-    for (int e = tid; e < 2 * P2; e += XT) Ts[e] = Tm[e];
+    if (tid < P) {
+        s_xb[tid] = xbar[tid];
+        s_bw[tid] = bw[tid];
+    }
 #pragma unroll
     for (int j = 0; j < NL; ++j) {
         int e = tid + j * XT;
-        int d = min(e / N3, 3);
-        if (e < 4 * N3) buf[e] = k4[d] >= 0 ? v[j] : 0.0;
+        int d = min(e / N3, NS - 1);
+        if (e < NS * N3) buf[e] = k4[d] >= 0 ? v[j] : 0.0;
     }
     __syncthreads();
-    // x pass, child d = side + 2 dy: column m2 of in_d[c] <- Tx_d . column
-    const double *Tx = Ts + side * P2;
-    for (int q = q0; q < 6 * P; q += 128) {
-        int dy = q / (3 * P), r = q - dy * 3 * P, comp = r / P, m2 = r - comp * P;
-        double *col = buf + (side + 2 * dy) * N3 + comp * P2 + m2;
-        double v[P];
+    // composite transfers: task (slot, coordinate, child node l')
+    double xa = ccx[A], ya = ccy[A], iha = 1.0 / chw[A];
+    for (int q = tid; q < 2 * NS * P; q += XT) {
+        int d = q / (2 * P), r = q - d * 2 * P, coord = r / P, l2 = r - coord * P;
+        int L = k4[d] >= 0 ? k4[d] : k4[0];
+        double u = coord ? (ccy[L] + chw[L] * s_xb[l2] - ya) * iha : (ccx[L] + chw[L] * s_xb[l2] - xa) * iha;
+        double S[P];
+        bary<P>(s_xb, s_bw, u, S);
+        double *T = coord ? Ty[d] : Tx[d];
 #pragma unroll
-        for (int l2 = 0; l2 < P; ++l2) v[l2] = col[l2 * P];
+        for (int l = 0; l < P; ++l) T[l * P + l2] = S[l];
+    }
+    __syncthreads();
+    // x pass: task (slot d, component, column m2): column <- Tx_d . column
+    for (int q = tid; q < 3 * NS * P; q += XT) {
+        int d = q / (3 * P), r = q - d * 3 * P, comp = r / P, m2 = r - comp * P;
+        double *col = buf + d * N3 + comp * P2 + m2;
+        const double *T = Tx[d];
+        double u[P];
+#pragma unroll
+        for (int l2 = 0; l2 < P; ++l2) u[l2] = col[l2 * P];
 #pragma unroll UO
         for (int l = 0; l < P; ++l) {
-            double a = 0.0;
+            double acc = 0.0;
 #pragma unroll
-            for (int l2 = 0; l2 < P; ++l2) a += Tx[l * P + l2] * v[l2];
-            col[l * P] = a;
+            for (int l2 = 0; l2 < P; ++l2) acc += T[l * P + l2] * u[l2];
+            col[l * P] = acc;
         }
     }
     __syncthreads();
-    // y pass, child d = 2 side + dx: row l of tmp_d[c] <- row . Ty_d^T
-    const double *Ty = Ts + side * P2;
-    for (int q = q0; q < 6 * P; q += 128) {
-        int dx = q / (3 * P), r = q - dx * 3 * P, comp = r / P, l = r - comp * P;
-        double *row = buf + (2 * side + dx) * N3 + comp * P2 + l * P;
-        double v[P];
+    // y pass: task (slot d, component, row l): row <- row . Ty_d^T
+    for (int q = tid; q < 3 * NS * P; q += XT) {
+        int d = q / (3 * P), r = q - d * 3 * P, comp = r / P, l = r - comp * P;
+        double *row = buf + d * N3 + comp * P2 + l * P;
+        const double *T = Ty[d];
+        double u[P];
 #pragma unroll
-        for (int m2 = 0; m2 < P; ++m2) v[m2] = row[m2];
+        for (int m2 = 0; m2 < P; ++m2) u[m2] = row[m2];
 #pragma unroll UO
         for (int m = 0; m < P; ++m) {
-            double a = 0.0;
+            double acc = 0.0;
 #pragma unroll
-            for (int m2 = 0; m2 < P; ++m2) a += Ty[m * P + m2] * v[m2];
-            row[m] = a;
+            for (int m2 = 0; m2 < P; ++m2) acc += T[m * P + m2] * u[m2];
+            row[m] = acc;
         }
     }
     __syncthreads();
-    for (int e = tid; e < N3; e += XT)
-        W[(size_t)c * Mp + e] = ((buf[e] + buf[N3 + e]) + buf[2 * N3 + e]) + buf[3 * N3 + e];
+    for (int e = tid; e < N3; e += XT) {
+        double acc = buf[e];
+#pragma unroll
+        for (int d = 1; d < NS; ++d) acc += buf[d * N3 + e];
+        part[(size_t)item * Mp + e] = acc;
+    }
+}
+
+// W_A = sum of A's item partials, in item order.
+__global__ __launch_bounds__(256) void k_m2m_sum(int nanc, const int *__restrict__ anc,
+                                                 const int *__restrict__ ioff, const double *__restrict__ part,
+                                                 int n3, int Mp, double *__restrict__ W)
+{
+    constexpr int U = 8;  // loads in flight per thread; the sum stays in item order
+    int i = xcd_remap(blockIdx.x, nanc);
+    int A = anc[i], kb = ioff[i], ke = ioff[i + 1];
+    for (int e = threadIdx.x; e < n3; e += 256) {
+        double s = 0.0;
+        for (int k0 = kb; k0 < ke; k0 += U) {
+            double v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = part[(size_t)min(k0 + u, ke - 1) * Mp + e];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (k0 + u < ke) s += v[u];
+        }
+        W[(size_t)A * Mp + e] = s;
+    }
 }
 
 // ------------------------------------------------- gathered MFMA GEMM
@@ -381,11 +424,19 @@ __global__ __launch_bounds__(256) void k_sum_pairs(int nfar, const int *__restri
                                                    const int *__restrict__ voff, const double *__restrict__ Z,
                                                    int ldz, int width, double *__restrict__ out, int ldo)
 {
+    constexpr int U = 8;  // loads in flight per thread; the sum stays in list order
     int c = far_cells[xcd_remap(blockIdx.x, nfar)];
     int kb = voff[c], ke = voff[c + 1];
     for (int e = threadIdx.x; e < width; e += 256) {
         double s = 0.0;
-        for (int k = kb; k < ke; ++k) s += Z[(size_t)k * ldz + e];
+        for (int k0 = kb; k0 < ke; k0 += U) {
+            double v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = Z[(size_t)min(k0 + u, ke - 1) * ldz + e];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (k0 + u < ke) s += v[u];
+        }
         out[(size_t)c * ldo + e] = s;
     }
 }
@@ -704,18 +755,6 @@ void gauss_legendre(int n, std::vector<double> &t, std::vector<double> &w)
     }
 }
 
-double host_cheb_S(int p, int l, double u)
-{
-    double th = (2.0 * l + 1.0) * M_PI / (2.0 * p);
-    double s = 0.0, t0 = 1.0, t1 = u;
-    for (int k = 1; k < p; ++k) {
-        s += std::cos(k * th) * t1;
-        double t2 = 2.0 * u * t1 - t0;
-        t0 = t1;
-        t1 = t2;
-    }
-    return (1.0 + 2.0 * s) / p;
-}
 
 int offset_slot(int dx, int dy) { return (dx + 3) + 7 * (dy + 3); }
 
@@ -762,20 +801,20 @@ void launch_ggemm(hipStream_t s, int ntile, int Mrows, const double *ops, size_t
 }
 
 template <int P>
-void launch_m2m(hipStream_t s, int c0, int nc, const int *leaf, const int *child, const double *T, int Mp,
-                double *W)
+void launch_m2m(hipStream_t s, fmddm_ctx *ctx, fmddm_tree *t, int Mp)
 {
-    hipLaunchKernelGGL((k_m2m<P>), dim3(nc), dim3(XT), 0, s, c0, nc, leaf, child, T, Mp, W);
+    hipLaunchKernelGGL((k_m2m<P>), dim3(t->nuitem), dim3(XT), 0, s, t->nuitem, t->uit_anc.p, t->uit_leaf.p,
+                       t->ccx.p, t->ccy.p, t->chw.p, ctx->cheb->xbar.p, ctx->cheb->bw.p, Mp, t->Wexp.p,
+                       t->upart.p);
     FM_CHECK_LAUNCH();
 }
-
 
 template <int P>
 void launch_l2p(hipStream_t s, fmddm_ctx *ctx, fmddm_tree *t, int Mp)
 {
     hipLaunchKernelGGL((k_l2p<P>), dim3(t->nleaf), dim3(LT), 0, s, t->nleaf, t->dleaves.p, t->cpbeg.p,
                        t->cpend.p, t->aoff.p, t->aidx.p, t->ccx.p, t->ccy.p, t->chw.p, t->scx.p, t->scy.p, t->Gexp.p,
-                       Mp, ctx->cheb.xbar.p, ctx->cheb.bw.p, t->far_s.p);
+                       Mp, ctx->cheb->xbar.p, ctx->cheb->bw.p, t->far_s.p);
     FM_CHECK_LAUNCH();
 }
 
@@ -858,7 +897,7 @@ void Profiler::read(hipStream_t s, double *ms, int64_t *count)
 void setup_cheb(fmddm_ctx *ctx)
 {
     int p = ctx->prm.p;
-    Cheb &C = ctx->cheb;
+    Cheb &C = *ctx->cheb;
     C.p = p;
     C.h_xbar.resize(p);
     C.h_bw.resize(p);
@@ -870,25 +909,18 @@ void setup_cheb(fmddm_ctx *ctx)
         for (int k = 0; k < p; ++k) C.h_tnode[l * p + k] = std::cos(k * th);
     }
     gauss_legendre(p, C.h_glt, C.h_glw);
-    C.h_m2m.resize(2 * p * p);
-    for (int side = 0; side < 2; ++side)
-        for (int l = 0; l < p; ++l)
-            for (int l2 = 0; l2 < p; ++l2)
-                C.h_m2m[side * p * p + l * p + l2] =
-                    host_cheb_S(p, l, (side ? 0.5 : -0.5) + 0.5 * C.h_xbar[l2]);
     hipStream_t s = ctx->stream;
     upload(s, C.xbar, C.h_xbar);
     upload(s, C.bw, C.h_bw);
     upload(s, C.tnode, C.h_tnode);
     upload(s, C.gl_t, C.h_glt);
     upload(s, C.gl_w, C.h_glw);
-    upload(s, C.m2m, C.h_m2m);
     FM_HIP(hipStreamSynchronize(s));
 }
 
 static void build_m2l_ops(fmddm_ctx *ctx)
 {
-    M2LOps &M = ctx->m2l;
+    M2LOps &M = *ctx->m2l;
     if (M.ready) return;
     int p = ctx->prm.p, p2 = p * p;
     M.mode = ctx->prm.m2l;
@@ -908,7 +940,7 @@ static void build_m2l_ops(fmddm_ctx *ctx)
         M.ops.alloc((size_t)nop * M.Mp * M.Mp);
         M.ops.zero(s);
         hipLaunchKernelGGL(k_m2l_ops, dim3(cdiv(tot, 256)), dim3(256), 0, s, nop, ddx.p, ddy.p,
-                           ctx->cheb.xbar.p, p, M.Mp, ctx->gc, M.ops.p);
+                           ctx->cheb->xbar.p, p, M.Mp, ctx->gc, M.ops.p);
         FM_CHECK_LAUNCH();
         FM_HIP(hipStreamSynchronize(s));
         M.ready = 1;
@@ -922,7 +954,7 @@ static void build_m2l_ops(fmddm_ctx *ctx)
     raw.alloc((size_t)nop * M.Mp * M.Mp);
     raw.zero(s);
     hipLaunchKernelGGL(k_m2l_ops, dim3(cdiv(tot, 256)), dim3(256), 0, s, nop, ddx.p, ddy.p,
-                       ctx->cheb.xbar.p, p, M.Mp, 1.0, raw.p);
+                       ctx->cheb->xbar.p, p, M.Mp, 1.0, raw.p);
     FM_CHECK_LAUNCH();
     int m = M.M, ncol = nop * M.M;
     DBuf<double> fat, S, U, E;
@@ -1004,7 +1036,7 @@ void setup_fmm(fmddm_ctx *ctx, fmddm_tree *t)
     if (t->Wexp.p) return;
     build_m2l_ops(ctx);
     hipStream_t s = ctx->stream;
-    const M2LOps &M = ctx->m2l;
+    const M2LOps &M = *ctx->m2l;
     int Mp = M.Mp, rp = M.rp, ncell = t->ncell, p = ctx->prm.p;
     // M2L schedule: V pairs grouped by offset, tiles of TILE_N pairs
     std::vector<int> hv(t->nV), hix(ncell), hiy(ncell);
@@ -1072,13 +1104,42 @@ void setup_fmm(fmddm_ctx *ctx, fmddm_tree *t)
     t->p2m_mat.alloc((size_t)t->n * p * p);
     hipLaunchKernelGGL(k_p2m_mats, dim3(t->nleaf), dim3(256), 0, s, t->nleaf, t->dleaves.p, t->cpbeg.p,
                        t->cpend.p, t->ccx.p, t->ccy.p, t->chw.p, t->scx.p, t->scy.p, t->scb.p, t->ssb.p,
-                       t->sa.p, ctx->cheb.tnode.p, ctx->cheb.gl_t.p, ctx->cheb.gl_w.p, p, t->p2m_mat.p);
+                       t->sa.p, ctx->cheb->tnode.p, ctx->cheb->gl_t.p, ctx->cheb->gl_w.p, p, t->p2m_mat.p);
     FM_CHECK_LAUNCH();
     t->Wexp.alloc((size_t)ncell * Mp);
     t->Gexp.alloc((size_t)ncell * Mp);
     t->Zm2l.alloc((size_t)std::max<int64_t>(t->nV, 1) * rp);
     t->Wexp.zero(s);
     t->Gexp.zero(s);
+    // upward-pass work items: every non-leaf cell of level >= 2 with its
+    // leaf descendants, in tree order, m2m_slots(p) per item
+    {
+        std::vector<int> hpar(ncell);
+        FM_HIP(hipMemcpyAsync(hpar.data(), t->cparent.p, ncell * 4, hipMemcpyDeviceToHost, s));
+        FM_HIP(hipStreamSynchronize(s));
+        std::vector<std::vector<int>> desc(ncell);
+        for (int L : t->leaves)
+            for (int A = hpar[L]; A >= 0 && t->h_level[A] >= 2; A = hpar[A]) desc[A].push_back(L);
+        std::vector<int> anc, ioff(1, 0), ianc, ileaf;
+        for (int A = 0; A < ncell; ++A) {
+            if (desc[A].empty()) continue;
+            anc.push_back(A);
+            size_t ns = m2m_slots(p);
+            for (size_t b = 0; b < desc[A].size(); b += ns) {
+                ianc.push_back(A);
+                for (size_t d = 0; d < 4; ++d)
+                    ileaf.push_back(d < ns && b + d < desc[A].size() ? desc[A][b + d] : -1);
+            }
+            ioff.push_back((int)ianc.size());
+        }
+        t->nuanc = (int)anc.size();
+        t->nuitem = (int)ianc.size();
+        upload(s, t->uanc, anc);
+        upload(s, t->uioff, ioff);
+        upload(s, t->uit_anc, ianc);
+        upload(s, t->uit_leaf, ileaf);
+        t->upart.alloc((size_t)std::max(t->nuitem, 1) * Mp);
+    }
     if (M.mode == FMDDM_M2L_SVD) {
         t->What.alloc((size_t)ncell * rp);
         t->Ghat.alloc((size_t)ncell * rp);
@@ -1097,9 +1158,9 @@ void fmm_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out)
 {
     setup_fmm(ctx, t);
     hipStream_t s = ctx->stream;
-    const M2LOps &M = ctx->m2l;
+    const M2LOps &M = *ctx->m2l;
     int p = ctx->prm.p, Mp = M.Mp, rp = M.rp, n = (int)t->n;
-    const Cheb &C = ctx->cheb;
+    const Cheb &C = *ctx->cheb;
     Profiler &P = ctx->prof;
     hipEvent_t e0;
     P.begin(FMDDM_PH_PREP, s, e0);
@@ -1113,12 +1174,12 @@ void fmm_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out)
     FM_HIP(hipEventRecord(ctx->ev_fork, s));
     FM_HIP(hipStreamWaitEvent(s2, ctx->ev_fork, 0));
     hipEvent_t e1;
-    P.begin(FMDDM_PH_NEAR, s2, e1);
+    P.begin(FMDDM_PH_P2P, s2, e1);
     hipLaunchKernelGGL(k_p2p, dim3(t->nitem), dim3(NT), 0, s2, t->nitem, t->it_leaf.p, t->it_s0.p, t->it_s1.p,
                        t->it_poff.p, t->dleaves.p, t->cpbeg.p, t->cpend.p, t->noff.p, t->nbeg.p, t->npre.p,
                        t->scx.p, t->scy.p, t->scb.p, t->ssb.p, t->sa.p, t->Dsort.p, ctx->gc, t->part_s.p);
     FM_CHECK_LAUNCH();
-    P.end(FMDDM_PH_NEAR, s2, e1);
+    P.end(FMDDM_PH_P2P, s2, e1);
     FM_HIP(hipEventRecord(ctx->ev_join, s2));
     bool far = t->nV > 0;
     if (far) {
@@ -1127,59 +1188,74 @@ void fmm_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out)
                            t->cpend.p, t->p2m_mat.p, t->q.p, p * p, Mp, t->Wexp.p);
         FM_CHECK_LAUNCH();
         P.end(FMDDM_PH_P2M, s, e0);
-        P.begin(FMDDM_PH_M2M, s, e0);
-        // levels 0 and 1 have no interaction lists: their weights are unused
-        for (int l = t->nlevel - 2; l >= 2; --l) {
-            int c0 = t->level_start[l], nc = t->level_start[l + 1] - c0;
-#define FM_M2M(PP) launch_m2m<PP>(s, c0, nc, t->cleaf.p, t->cchild.p, C.m2m.p, Mp, t->Wexp.p)
+        if (t->nuitem > 0) {
+            P.begin(FMDDM_PH_M2M, s, e0);
+#define FM_M2M(PP) launch_m2m<PP>(s, ctx, t, Mp)
             FM_DISPATCH_P(p, FM_M2M)
 #undef FM_M2M
+            P.end(FMDDM_PH_M2M, s, e0);
+            P.begin(FMDDM_PH_M2M_SUM, s, e0);
+            hipLaunchKernelGGL(k_m2m_sum, dim3(t->nuanc), dim3(256), 0, s, t->nuanc, t->uanc.p, t->uioff.p,
+                               t->upart.p, 3 * p * p, Mp, t->Wexp.p);
+            FM_CHECK_LAUNCH();
+            P.end(FMDDM_PH_M2M_SUM, s, e0);
         }
-        P.end(FMDDM_PH_M2M, s, e0);
-        P.begin(FMDDM_PH_M2L, s, e0);
         if (M.mode == FMDDM_M2L_SVD) {
             // projection onto the singular vectors: K = 3p^2 is long and the
             // output small, so K is split over KSPLIT blocks and summed after
+            P.begin(FMDDM_PH_COMPRESS, s, e0);
             launch_ggemm<32, 32>(s, t->nftile, rp, M.Vt.p, 0, Mp, Mp, t->Wexp.p, Mp, t->ftile_op.p,
                                  t->ftile_beg.p, t->ftile_end.p, t->far_cells.p, t->far_cells.p, nullptr,
                                  t->ksplit.p, rp, KSPLIT, (size_t)t->ncell * rp);
+            P.end(FMDDM_PH_COMPRESS, s, e0);
+            P.begin(FMDDM_PH_COMPRESS_SUM, s, e0);
             {
                 int64_t c0 = t->level_start[2], cnt = (int64_t)(t->ncell - c0) * rp;
                 hipLaunchKernelGGL(k_reduce_split, dim3(cdiv(cnt, 256)), dim3(256), 0, s, cnt, KSPLIT,
                                    (size_t)t->ncell * rp, t->ksplit.p + c0 * rp, t->What.p + c0 * rp);
                 FM_CHECK_LAUNCH();
             }
+            P.end(FMDDM_PH_COMPRESS_SUM, s, e0);
+            P.begin(FMDDM_PH_M2L, s, e0);
             launch_ggemm<64, 32>(s, t->ntile, rp, M.ops.p, (size_t)rp * rp, rp, rp, t->What.p, rp, t->tile_op.p,
                                  t->tile_beg.p, t->tile_end.p, t->pair_src.p, t->pair_dst.p, t->pair_scale.p,
                                  t->Zm2l.p, rp);
+            P.end(FMDDM_PH_M2L, s, e0);
+            P.begin(FMDDM_PH_M2L_SUM, s, e0);
             hipLaunchKernelGGL(k_sum_pairs, dim3(t->nfar), dim3(256), 0, s, t->nfar, t->far_cells.p,
                                t->loff[1].p, t->Zm2l.p, rp, rp, t->Ghat.p, rp);
             FM_CHECK_LAUNCH();
+            P.end(FMDDM_PH_M2L_SUM, s, e0);
+            P.begin(FMDDM_PH_DECOMPRESS, s, e0);
             launch_ggemm<64, 32>(s, t->nftile, Mp, M.Ur.p, 0, rp, rp, t->Ghat.p, rp, t->ftile_op.p,
                                  t->ftile_beg.p, t->ftile_end.p, t->far_cells.p, t->far_cells.p, nullptr,
                                  t->Gexp.p, Mp);
+            P.end(FMDDM_PH_DECOMPRESS, s, e0);
         } else {
+            P.begin(FMDDM_PH_M2L, s, e0);
             launch_ggemm<64, 32>(s, t->ntile, Mp, M.ops.p, (size_t)Mp * Mp, Mp, Mp, t->Wexp.p, Mp, t->tile_op.p,
                                  t->tile_beg.p, t->tile_end.p, t->pair_src.p, t->pair_dst.p, t->pair_scale.p,
                                  t->Zm2l.p, Mp);
+            P.end(FMDDM_PH_M2L, s, e0);
+            P.begin(FMDDM_PH_M2L_SUM, s, e0);
             hipLaunchKernelGGL(k_sum_pairs, dim3(t->nfar), dim3(256), 0, s, t->nfar, t->far_cells.p,
                                t->loff[1].p, t->Zm2l.p, Mp, Mp, t->Gexp.p, Mp);
             FM_CHECK_LAUNCH();
+            P.end(FMDDM_PH_M2L_SUM, s, e0);
         }
-        P.end(FMDDM_PH_M2L, s, e0);
-    }
-    P.begin(FMDDM_PH_DOWN, s, e0);
-    if (far) {
+        P.begin(FMDDM_PH_L2P, s, e0);
 #define FM_L2P(PP) launch_l2p<PP>(s, ctx, t, Mp)
         FM_DISPATCH_P(p, FM_L2P)
 #undef FM_L2P
+        P.end(FMDDM_PH_L2P, s, e0);
     }
-    P.end(FMDDM_PH_DOWN, s, e0);
     FM_HIP(hipStreamWaitEvent(s, ctx->ev_join, 0));
+    P.begin(FMDDM_PH_FINAL, s, e0);
     hipLaunchKernelGGL(k_final, dim3(cdiv(n, 256)), dim3(256), 0, s, n, t->tleaf.p, t->dleaves.p, t->cpbeg.p,
                        t->lk_off.p, t->it_poff.p, t->part_s.p, far ? t->far_s.p : (const double *)nullptr,
                        t->scb.p, t->ssb.p, t->perm.p, out);
     FM_CHECK_LAUNCH();
+    P.end(FMDDM_PH_FINAL, s, e0);
 }
 
 }  // namespace fmddm

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -62,9 +63,8 @@ struct Cheb {
     DBuf<double> tnode;     // [l][k] = T_k(xbar_l), p x p
     DBuf<double> xbar;      // p nodes
     DBuf<double> gl_t, gl_w;  // p-point Gauss-Legendre
-    DBuf<double> m2m;       // [side][l_parent][l_child] = S_p(xbar_l, +-1/2 + xbar_l'/2), 2 x p x p
     DBuf<double> bw;        // barycentric weights of the nodes
-    std::vector<double> h_xbar, h_tnode, h_m2m, h_glt, h_glw, h_bw;
+    std::vector<double> h_xbar, h_tnode, h_glt, h_glw, h_bw;
 };
 
 struct M2LOps {
@@ -112,8 +112,10 @@ struct fmddm_ctx {
     }
     int device = 0;
     std::string err;
-    fmddm::Cheb cheb;
-    fmddm::M2LOps m2l;
+    // Chebyshev tables and M2L operators depend only on p, the material and
+    // the M2L mode: contexts created by a server share one set
+    std::shared_ptr<fmddm::Cheb> cheb;
+    std::shared_ptr<fmddm::M2LOps> m2l;
     double gc = 0.0;        // G / (2 pi (1 - nu))
 };
 
@@ -149,7 +151,7 @@ struct fmddm_tree {
     fmddm::DBuf<int> it_leaf, it_s0, it_s1, it_poff, lk_off, tleaf;
     std::vector<int> leaves;          // host list of leaf cells (tree order)
     fmddm::DBuf<int> dleaves;
-    int64_t near_pairs = 0, l2p_pairs = 0;
+    int64_t near_pairs = 0, l2p_pairs = 0, m2m_pairs = 0;
     // M2L schedule: pairs are V-list entries grouped by offset into tiles
     int ntile = 0;
     fmddm::DBuf<int> tile_op, tile_beg, tile_end, pair_src, pair_dst;
@@ -162,6 +164,10 @@ struct fmddm_tree {
     // expansions
     fmddm::DBuf<double> p2m_mat;      // per element (tree order): p^2 weights of its anterpolation
     fmddm::DBuf<double> Wexp;         // multipole weights, ncell x Mp
+    int nuanc = 0, nuitem = 0;         // upward pass: ancestors, (ancestor, 4 leaves) items
+    fmddm::DBuf<int> uanc, uioff;      // ancestors and their item ranges
+    fmddm::DBuf<int> uit_anc, uit_leaf;  // per item: ancestor, 4 leaf slots (-1 = empty)
+    fmddm::DBuf<double> upart;         // per item partial weights, nuitem x Mp
     fmddm::DBuf<double> What;         // compressed weights, ncell x rp
     fmddm::DBuf<double> Zm2l;         // one M2L product per V pair, nV x rp
     fmddm::DBuf<double> Ghat;         // summed compressed M2L fields, ncell x rp
@@ -173,10 +179,18 @@ struct fmddm_tree {
     fmddm::DBuf<double> ksplit;       // split-K partial products
     // dense operator (built on demand)
     fmddm::DBuf<double> Adense;
-    // solver workspace
+    // solver workspace; gm_host is pinned host memory the device writes the
+    // residual norm and estimate to, gm_ev marks when they have arrived
     fmddm::DBuf<double> gm_V, gm_w, gm_r, gm_sc;
     int gm_restart = 0;
+    double *gm_host = nullptr;
+    hipEvent_t gm_ev = nullptr;
     int64_t bytes = 0;
+    ~fmddm_tree()
+    {
+        if (gm_ev) (void)hipEventDestroy(gm_ev);
+        if (gm_host) (void)hipHostFree(gm_host);
+    }
 };
 
 namespace fmddm {
@@ -192,9 +206,35 @@ void fmm_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out);
 void direct_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out);
 void dense_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out);
 // solve.hip
-void rhs_build(fmddm_ctx *ctx, fmddm_tree *t, const double *pf, double SH, double Sh, double *rhs);
+void rhs_build(fmddm_ctx *ctx, fmddm_tree *t, const double *pf, double SH, double Sh, double *rhs,
+               double pscale = 1.0);
 fmddm_status gmres_solve(fmddm_ctx *ctx, fmddm_tree *t, int mode, const double *b, double *x,
                          fmddm_solve_info *info);
+
+// One restarted-GMRES solve advanced in asynchronous steps: every call of
+// advance() enqueues the next piece of work (a residual, an Arnoldi step)
+// on the context's stream once the scalars it depends on have reached the
+// host.  start() needs b and x resident; x is the initial guess and holds
+// the iterate.  The work and its order are the same whether the caller
+// waits (block = true) or polls.
+struct GmresRun {
+    fmddm_ctx *ctx = nullptr;
+    fmddm_tree *t = nullptr;
+    int mode = 0;
+    const double *b = nullptr;
+    double *x = nullptr;
+    double tol = 0.0;
+    int maxit = 0;
+    enum State { IDLE, BNORM, RESID, ITER, DONE } state = IDLE;
+    int j = 0, it = 0, restarts = 0;
+    double bnorm = 0.0, relres = 0.0;
+    bool converged = false;
+    void start(fmddm_ctx *c, fmddm_tree *tr, int md, const double *rhs, double *x0, double tl, int mx);
+    bool advance(bool block);  // true once finished
+  private:
+    void enqueue_residual();
+    void enqueue_step();
+};
 void apply_mode(fmddm_ctx *ctx, fmddm_tree *t, int mode, const double *D, double *out);
 
 inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }

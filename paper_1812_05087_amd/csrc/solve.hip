@@ -15,14 +15,21 @@ namespace fmddm {
 namespace {
 
 __global__ void k_rhs(int n, const double *__restrict__ cb, const double *__restrict__ sb,
-                      const double *__restrict__ pf, double SH, double Sh, double *__restrict__ rhs)
+                      const double *__restrict__ pf, double pscale, double SH, double Sh,
+                      double *__restrict__ rhs)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double ts, tn;
     traction(cb[i], sb[i], -SH, -Sh, 0.0, ts, tn);
     rhs[2 * i] = -ts;
-    rhs[2 * i + 1] = -pf[i] - tn;
+    rhs[2 * i + 1] = -pscale * pf[i] - tn;
+}
+
+__global__ void k_fill(int n, double v, double *__restrict__ x)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = v;
 }
 
 constexpr int RT = 256;
@@ -165,11 +172,12 @@ __global__ void k_sif(const double *__restrict__ D, const double *__restrict__ a
 
 }  // namespace
 
-void rhs_build(fmddm_ctx *ctx, fmddm_tree *t, const double *pf, double SH, double Sh, double *rhs)
+void rhs_build(fmddm_ctx *ctx, fmddm_tree *t, const double *pf, double SH, double Sh, double *rhs,
+               double pscale)
 {
     int n = (int)t->n;
     hipLaunchKernelGGL(k_rhs, dim3(cdiv(n, 256)), dim3(256), 0, ctx->stream, n, t->ocb.p, t->osb.p, pf,
-                       SH, Sh, rhs);
+                       pscale, SH, Sh, rhs);
     FM_CHECK_LAUNCH();
 }
 
@@ -196,13 +204,9 @@ void sif_eval(fmddm_ctx *ctx, fmddm_tree *t, const double *D, int64_t e, double 
     *KII = h[1];
 }
 
-fmddm_status gmres_solve(fmddm_ctx *ctx, fmddm_tree *t, int mode, const double *b, double *x,
-                         fmddm_solve_info *info)
+static void gmres_workspace(fmddm_tree *t, int m)
 {
-    hipStream_t st = ctx->stream;
-    const int m = ctx->prm.restart;
-    const int n2 = (int)(2 * t->n);
-    const int ldv = (n2 + 63) / 64 * 64;
+    const int n2 = (int)(2 * t->n), ldv = (n2 + 63) / 64 * 64;
     SW s{m};
     if (t->gm_restart != m || !t->gm_V.p) {
         t->gm_V.alloc((size_t)(m + 1) * ldv);
@@ -211,74 +215,152 @@ fmddm_status gmres_solve(fmddm_ctx *ctx, fmddm_tree *t, int mode, const double *
         t->gm_sc.alloc(s.size());
         t->gm_restart = m;
     }
-    double *V = t->gm_V.p, *w = t->gm_w.p, *r = t->gm_r.p, *sc = t->gm_sc.p;
-    int gb = cdiv(n2, 256);
-    // ||b||
-    hipLaunchKernelGGL(k_norm, dim3(1), dim3(RT), 0, st, n2, b, sc + s.nrm());
+    if (!t->gm_host) FM_HIP(hipHostMalloc((void **)&t->gm_host, 2 * sizeof(double), hipHostMallocDefault));
+    if (!t->gm_ev) FM_HIP(hipEventCreateWithFlags(&t->gm_ev, hipEventDisableTiming));
+}
+
+void GmresRun::start(fmddm_ctx *c, fmddm_tree *tr, int md, const double *rhs, double *x0, double tl, int mx)
+{
+    ctx = c;
+    t = tr;
+    mode = md;
+    b = rhs;
+    x = x0;
+    tol = tl;
+    maxit = mx;
+    j = it = restarts = 0;
+    bnorm = relres = 0.0;
+    converged = false;
+    gmres_workspace(t, ctx->prm.restart);
+    SW s{ctx->prm.restart};
+    hipStream_t st = ctx->stream;
+    const int n2 = (int)(2 * t->n);
+    hipLaunchKernelGGL(k_norm, dim3(1), dim3(RT), 0, st, n2, b, t->gm_sc.p + s.nrm());
     FM_CHECK_LAUNCH();
-    double bnorm = 0.0;
-    FM_HIP(hipMemcpyAsync(&bnorm, sc + s.nrm(), 8, hipMemcpyDeviceToHost, st));
-    FM_HIP(hipStreamSynchronize(st));
-    info->iters = 0;
-    info->restarts = 0;
-    info->converged = 0;
-    info->relres = 0.0;
-    if (bnorm == 0.0) {
-        FM_HIP(hipMemsetAsync(x, 0, n2 * 8, st));
-        FM_HIP(hipStreamSynchronize(st));
-        info->converged = 1;
-        return FMDDM_OK;
+    FM_HIP(hipMemcpyAsync(t->gm_host, t->gm_sc.p + s.nrm(), 8, hipMemcpyDeviceToHost, st));
+    FM_HIP(hipEventRecord(t->gm_ev, st));
+    state = BNORM;
+}
+
+// r = b - A x and its norm
+void GmresRun::enqueue_residual()
+{
+    SW s{ctx->prm.restart};
+    hipStream_t st = ctx->stream;
+    const int n2 = (int)(2 * t->n);
+    apply_mode(ctx, t, mode, x, t->gm_w.p);
+    hipLaunchKernelGGL(k_residual, dim3(cdiv(n2, 256)), dim3(256), 0, st, n2, b, t->gm_w.p, t->gm_r.p);
+    hipLaunchKernelGGL(k_norm, dim3(1), dim3(RT), 0, st, n2, t->gm_r.p, t->gm_sc.p + s.nrm());
+    FM_CHECK_LAUNCH();
+    FM_HIP(hipMemcpyAsync(t->gm_host, t->gm_sc.p + s.nrm(), 8, hipMemcpyDeviceToHost, st));
+    FM_HIP(hipEventRecord(t->gm_ev, st));
+}
+
+// Arnoldi step j: w = A v_j, two classical Gram-Schmidt passes, the new
+// basis vector, the Hessenberg column and its Givens rotation
+void GmresRun::enqueue_step()
+{
+    const int m = ctx->prm.restart;
+    SW s{m};
+    hipStream_t st = ctx->stream;
+    const int n2 = (int)(2 * t->n), ldv = (n2 + 63) / 64 * 64, gb = cdiv(n2, 256);
+    double *V = t->gm_V.p, *w = t->gm_w.p, *sc = t->gm_sc.p;
+    double *vj = V + (size_t)j * ldv, *vn = V + (size_t)(j + 1) * ldv;
+    apply_mode(ctx, t, mode, vj, w);
+    ++it;
+    hipLaunchKernelGGL(k_dots, dim3(j + 1), dim3(RT), 0, st, n2, j + 1, V, ldv, w, sc + s.h1());
+    hipLaunchKernelGGL(k_vupdate, dim3(gb), dim3(256), 0, st, n2, j + 1, V, ldv, sc + s.h1(), -1.0, w);
+    hipLaunchKernelGGL(k_dots, dim3(j + 1), dim3(RT), 0, st, n2, j + 1, V, ldv, w, sc + s.h2());
+    hipLaunchKernelGGL(k_vupdate, dim3(gb), dim3(256), 0, st, n2, j + 1, V, ldv, sc + s.h2(), -1.0, w);
+    hipLaunchKernelGGL(k_norm, dim3(1), dim3(RT), 0, st, n2, w, sc + s.nrm());
+    hipLaunchKernelGGL(k_scale, dim3(gb), dim3(256), 0, st, n2, w, sc + s.nrm(), vn);
+    hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, st, s, j, sc);
+    FM_CHECK_LAUNCH();
+    FM_HIP(hipMemcpyAsync(t->gm_host, sc + s.nrm(), 16, hipMemcpyDeviceToHost, st));
+    FM_HIP(hipEventRecord(t->gm_ev, st));
+}
+
+bool GmresRun::advance(bool block)
+{
+    if (state == DONE || state == IDLE) return true;
+    if (block) {
+        FM_HIP(hipEventSynchronize(t->gm_ev));
+    } else {
+        hipError_t q = hipEventQuery(t->gm_ev);
+        if (q == hipErrorNotReady) return false;
+        FM_HIP(q);
     }
-    const double tol = ctx->prm.tol;
-    int it = 0;
-    for (;;) {
-        // true residual
-        apply_mode(ctx, t, mode, x, w);
-        hipLaunchKernelGGL(k_residual, dim3(gb), dim3(256), 0, st, n2, b, w, r);
-        FM_CHECK_LAUNCH();
-        hipLaunchKernelGGL(k_norm, dim3(1), dim3(RT), 0, st, n2, r, sc + s.nrm());
-        FM_CHECK_LAUNCH();
-        double beta = 0.0;
-        FM_HIP(hipMemcpyAsync(&beta, sc + s.nrm(), 8, hipMemcpyDeviceToHost, st));
-        FM_HIP(hipStreamSynchronize(st));
-        info->relres = beta / bnorm;
-        if (!std::isfinite(beta)) throw Error{FMDDM_EDEVICE, "non-finite residual"};
-        if (beta <= tol * bnorm) {
-            info->converged = 1;
-            break;
+    const int m = ctx->prm.restart;
+    SW s{m};
+    hipStream_t st = ctx->stream;
+    const int n2 = (int)(2 * t->n), ldv = (n2 + 63) / 64 * 64, gb = cdiv(n2, 256);
+    double *V = t->gm_V.p, *sc = t->gm_sc.p;
+    const double *h = t->gm_host;
+    switch (state) {
+    case BNORM:
+        bnorm = h[0];
+        if (!std::isfinite(bnorm)) throw Error{FMDDM_EINVAL, "non-finite right-hand side"};
+        if (bnorm == 0.0) {
+            hipLaunchKernelGGL(k_fill, dim3(cdiv(n2, 256)), dim3(256), 0, st, n2, 0.0, x);
+            FM_CHECK_LAUNCH();
+            FM_HIP(hipStreamSynchronize(st));
+            converged = true;
+            state = DONE;
+            return true;
         }
-        if (it >= ctx->prm.maxit) break;
-        ++info->restarts;
-        hipLaunchKernelGGL(k_scale, dim3(gb), dim3(256), 0, st, n2, r, sc + s.nrm(), V);
+        enqueue_residual();
+        state = RESID;
+        return false;
+    case RESID: {
+        double beta = h[0];
+        relres = beta / bnorm;
+        if (!std::isfinite(beta)) throw Error{FMDDM_EDEVICE, "non-finite residual"};
+        if (beta <= tol * bnorm || it >= maxit) {
+            converged = beta <= tol * bnorm;
+            state = DONE;
+            return true;
+        }
+        ++restarts;
+        hipLaunchKernelGGL(k_scale, dim3(gb), dim3(256), 0, st, n2, t->gm_r.p, sc + s.nrm(), V);
         hipLaunchKernelGGL(k_cycle_start, dim3(1), dim3(1), 0, st, s, sc);
         FM_CHECK_LAUNCH();
-        int k = 0;
-        for (int j = 0; j < m && it < ctx->prm.maxit; ++j) {
-            double *vj = V + (size_t)j * ldv, *vn = V + (size_t)(j + 1) * ldv;
-            apply_mode(ctx, t, mode, vj, w);
-            ++it;
-            // two classical Gram-Schmidt passes
-            hipLaunchKernelGGL(k_dots, dim3(j + 1), dim3(RT), 0, st, n2, j + 1, V, ldv, w, sc + s.h1());
-            hipLaunchKernelGGL(k_vupdate, dim3(gb), dim3(256), 0, st, n2, j + 1, V, ldv, sc + s.h1(), -1.0, w);
-            hipLaunchKernelGGL(k_dots, dim3(j + 1), dim3(RT), 0, st, n2, j + 1, V, ldv, w, sc + s.h2());
-            hipLaunchKernelGGL(k_vupdate, dim3(gb), dim3(256), 0, st, n2, j + 1, V, ldv, sc + s.h2(), -1.0, w);
-            hipLaunchKernelGGL(k_norm, dim3(1), dim3(RT), 0, st, n2, w, sc + s.nrm());
-            hipLaunchKernelGGL(k_scale, dim3(gb), dim3(256), 0, st, n2, w, sc + s.nrm(), vn);
-            hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, st, s, j, sc);
-            FM_CHECK_LAUNCH();
-            k = j + 1;
-            double est[2];
-            FM_HIP(hipMemcpyAsync(est, sc + s.nrm(), 16, hipMemcpyDeviceToHost, st));
-            FM_HIP(hipStreamSynchronize(st));
-            if (est[1] <= tol * bnorm || est[0] == 0.0) break;
-        }
-        hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(1), 0, st, s, k, sc);
-        hipLaunchKernelGGL(k_vupdate, dim3(gb), dim3(256), 0, st, n2, k, V, ldv, sc + s.y(), 1.0, x);
-        FM_CHECK_LAUNCH();
+        j = 0;
+        enqueue_step();
+        state = ITER;
+        return false;
     }
-    info->iters = it;
-    FM_HIP(hipStreamSynchronize(st));
-    return info->converged ? FMDDM_OK : FMDDM_ENOTCONV;
+    case ITER: {
+        double nrm = h[0], est = h[1];
+        int k = j + 1;
+        if (est <= tol * bnorm || nrm == 0.0 || k == m || it >= maxit) {
+            hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(1), 0, st, s, k, sc);
+            hipLaunchKernelGGL(k_vupdate, dim3(gb), dim3(256), 0, st, n2, k, V, ldv, sc + s.y(), 1.0, x);
+            FM_CHECK_LAUNCH();
+            enqueue_residual();
+            state = RESID;
+        } else {
+            ++j;
+            enqueue_step();
+        }
+        return false;
+    }
+    default: return true;
+    }
+}
+
+fmddm_status gmres_solve(fmddm_ctx *ctx, fmddm_tree *t, int mode, const double *b, double *x,
+                         fmddm_solve_info *info)
+{
+    GmresRun g;
+    g.start(ctx, t, mode, b, x, ctx->prm.tol, ctx->prm.maxit);
+    while (!g.advance(true)) {
+    }
+    info->iters = g.it;
+    info->restarts = g.restarts;
+    info->relres = g.relres;
+    info->converged = g.converged;
+    FM_HIP(hipStreamSynchronize(ctx->stream));
+    return g.converged ? FMDDM_OK : FMDDM_ENOTCONV;
 }
 
 }  // namespace fmddm

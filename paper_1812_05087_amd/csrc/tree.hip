@@ -704,6 +704,7 @@ void build_tree(fmddm_ctx *ctx, fmddm_tree *t, int64_t n64, const double *x1, co
                 if (t->h_level[A] >= 2) aidx.push_back(A);
             aoff[i + 1] = (int)aidx.size();
             t->l2p_pairs += (int64_t)(aoff[i + 1] - aoff[i]) * (he[c] - hb[c]);
+            t->m2m_pairs += aoff[i + 1] - aoff[i] - (t->h_level[c] >= 2 ? 1 : 0);
         }
         t->near_pairs = pairs;
         auto up = [&](DBuf<int> &d, const std::vector<int> &h) {
