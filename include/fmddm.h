@@ -214,6 +214,101 @@ fmddm_status fmddm_profile(fmddm_ctx *ctx, unsigned mask);
  * read; resets the sums.  Synchronises the stream. */
 fmddm_status fmddm_profile_read(fmddm_ctx *ctx, double *ms, int64_t *count);
 
+/* Device memory of the library on the current device.  Every device buffer
+ * comes from a cache: a block released by a freed tree or context is kept
+ * and handed out again instead of being returned to the runtime (hipFree
+ * would wait for all work on the device).  in_use counts the bytes held by
+ * live objects, cached the bytes kept for reuse; fmddm_trim_cache returns
+ * the cached blocks to the runtime and reports how many bytes it freed.  An
+ * allocation that fails empties the cache and is retried once. */
+int64_t fmddm_memory_in_use(void);
+int64_t fmddm_memory_cached(void);
+int64_t fmddm_trim_cache(void);
+
+/* ------------------------------------------------------------------------
+ * Serving: many fracture solves of different sizes on one device.
+ *
+ * Each request is the problem of Section 4 for its own geometry: build the
+ * tree, form the right-hand side, solve with GMRES whose products are FMM
+ * products.  `steps` load steps ramp the fluid pressure linearly from
+ * pf/steps to pf (far-field stress constant), each solved to `tol` starting
+ * from the previous step's DDs (an elastic, quasi-static sequence of single
+ * time steps; the time-dependent poroelastic history term is not part of a
+ * request).
+ *
+ * Continuous batching: fmddm_server_step advances every admitted request by
+ * one unit of work (one GMRES residual or Arnoldi step, enqueued on that
+ * request's own streams, so the work of different requests overlaps on the
+ * device) and admits at most one queued request when a slot is free and the
+ * device-memory estimate of the queued request fits the budget next to the
+ * admitted ones (first come, first served).  Requests never share device
+ * buffers and every kernel is deterministic, so a result does not depend on
+ * which other requests ran beside it.
+ *
+ * Threading: a server is driven from one host thread.  All host memory
+ * passed in is copied; nothing is kept after the call returns.
+ * ------------------------------------------------------------------------ */
+typedef struct fmddm_server fmddm_server;
+
+typedef struct {
+    int64_t n;                /* elements */
+    const double *x1, *y1, *x2, *y2;  /* host: element endpoints (n each) */
+    const double *pf;         /* host: fluid pressure per element at the last step (Pa) */
+    double SH, Sh;            /* far-field compressive stresses along x and y (Pa) */
+    int32_t steps;            /* load steps, >= 1 */
+    double tol;               /* GMRES relative residual per step, in (0, 1) */
+} fmddm_request;
+
+typedef enum {
+    FMDDM_REQ_QUEUED = 0,
+    FMDDM_REQ_RUNNING = 1,
+    FMDDM_REQ_DONE = 2,
+    FMDDM_REQ_FAILED = 3      /* `status` says why (e.g. FMDDM_ENOTCONV, FMDDM_ENOMEM) */
+} fmddm_req_state;
+
+typedef struct {
+    int32_t state;            /* fmddm_req_state */
+    int32_t status;           /* fmddm_status of a finished request */
+    int32_t steps_done;
+    int32_t iters;            /* GMRES products over all steps */
+    double relres;            /* true relative residual of the last step */
+    double t_submit, t_admit, t_done;  /* seconds on the server's clock */
+    int64_t device_bytes;     /* device memory charged against the budget (the estimate) */
+} fmddm_result;
+
+/* Creates a server for problems with parameters `p` (material, tree and FMM
+ * settings, GMRES restart and maxit; p->tol is ignored, each request has
+ * its own).  At most `max_slots` requests are admitted at once (1..64);
+ * `hbm_budget` bytes (0: 90 % of the device memory free at creation) bound
+ * the sum of the admitted requests' estimated footprints.  The M2L operators
+ * are built once here and shared by all requests. */
+fmddm_status fmddm_server_create(const fmddm_params *p, int max_slots, int64_t hbm_budget,
+                                 fmddm_server **out);
+void fmddm_server_destroy(fmddm_server *s);
+const char *fmddm_server_last_error(const fmddm_server *s);
+
+/* Device-memory estimate (bytes) the server charges a request of n
+ * elements against the budget. */
+int64_t fmddm_server_footprint(const fmddm_server *s, int64_t n);
+
+/* Queues a request; *ticket identifies it.  Validates the request (EINVAL)
+ * and copies its arrays. */
+fmddm_status fmddm_server_submit(fmddm_server *s, const fmddm_request *r, int64_t *ticket);
+
+/* One engine step (see above).  *active (may be NULL) receives the number
+ * of admitted, unfinished requests and *queued the number waiting.  Does
+ * not block on device work except while admitting a request (tree build
+ * and its one-time set-up). */
+fmddm_status fmddm_server_step(fmddm_server *s, int *active, int *queued);
+
+/* State of a request.  Once it is DONE, D (host, 2n doubles, may be NULL)
+ * receives its DDs in the convention of fmddm_apply; the server keeps them
+ * until fmddm_server_release. */
+fmddm_status fmddm_server_poll(fmddm_server *s, int64_t ticket, fmddm_result *res, double *D);
+
+/* Forgets a finished request. */
+fmddm_status fmddm_server_release(fmddm_server *s, int64_t ticket);
+
 #ifdef __cplusplus
 }
 #endif

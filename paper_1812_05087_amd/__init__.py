@@ -30,7 +30,11 @@ EXPORTED = [
     "fmddm_build_tree", "fmddm_tree_free", "fmddm_tree_get_info", "fmddm_tree_export",
     "fmddm_tree_export_list", "fmddm_apply", "fmddm_rhs", "fmddm_solve", "fmddm_sif",
     "fmddm_profile", "fmddm_profile_read",
+    "fmddm_server_create", "fmddm_server_destroy", "fmddm_server_last_error", "fmddm_server_footprint",
+    "fmddm_server_submit", "fmddm_server_step", "fmddm_server_poll", "fmddm_server_release",
+    "fmddm_memory_in_use", "fmddm_memory_cached", "fmddm_trim_cache",
 ]
+FMDDM_REQ_QUEUED, FMDDM_REQ_RUNNING, FMDDM_REQ_DONE, FMDDM_REQ_FAILED = 0, 1, 2, 3
 PHASES = ["prep", "p2m", "m2m", "m2m_sum", "compress", "compress_sum", "m2l", "m2l_sum", "decompress",
           "l2p", "p2p", "final"]
 
@@ -61,6 +65,18 @@ class TreeInfo(C.Structure):
         ("root_x0", C.c_double), ("root_y0", C.c_double), ("root_L", C.c_double),
         ("device_bytes", C.c_int64),
     ]
+
+
+class Request(C.Structure):
+    _fields_ = [("n", C.c_int64), ("x1", C.c_void_p), ("y1", C.c_void_p), ("x2", C.c_void_p),
+                ("y2", C.c_void_p), ("pf", C.c_void_p), ("SH", C.c_double), ("Sh", C.c_double),
+                ("steps", C.c_int32), ("tol", C.c_double)]
+
+
+class Result(C.Structure):
+    _fields_ = [("state", C.c_int32), ("status", C.c_int32), ("steps_done", C.c_int32),
+                ("iters", C.c_int32), ("relres", C.c_double), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_done", C.c_double), ("device_bytes", C.c_int64)]
 
 
 class SolveInfo(C.Structure):
@@ -100,11 +116,28 @@ def lib():
         L.fmddm_sif.argtypes = [_vp, _vp, _vp, C.c_int64, _d, _d]
         L.fmddm_profile.argtypes = [_vp, C.c_uint]
         L.fmddm_profile_read.argtypes = [_vp, _d, C.POINTER(C.c_int64)]
+        L.fmddm_server_create.argtypes = [C.POINTER(Params), C.c_int, C.c_int64, C.POINTER(_vp)]
+        L.fmddm_server_destroy.argtypes = [_vp]
+        L.fmddm_server_destroy.restype = None
+        L.fmddm_server_last_error.argtypes = [_vp]
+        L.fmddm_server_last_error.restype = C.c_char_p
+        L.fmddm_server_footprint.argtypes = [_vp, C.c_int64]
+        L.fmddm_server_footprint.restype = C.c_int64
+        L.fmddm_server_submit.argtypes = [_vp, C.POINTER(Request), C.POINTER(C.c_int64)]
+        L.fmddm_server_step.argtypes = [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.fmddm_server_poll.argtypes = [_vp, C.c_int64, C.POINTER(Result), _vp]
+        L.fmddm_server_release.argtypes = [_vp, C.c_int64]
+        for name in ("fmddm_memory_in_use", "fmddm_memory_cached", "fmddm_trim_cache"):
+            getattr(L, name).argtypes = []
         for name in EXPORTED:
             f = getattr(L, name)
             if name not in ("fmddm_default_params", "fmddm_destroy", "fmddm_tree_free",
-                            "fmddm_last_error"):
+                            "fmddm_last_error", "fmddm_server_destroy", "fmddm_server_last_error",
+                            "fmddm_server_footprint", "fmddm_memory_in_use", "fmddm_memory_cached",
+                            "fmddm_trim_cache"):
                 f.restype = C.c_int
+        for name in ("fmddm_memory_in_use", "fmddm_memory_cached", "fmddm_trim_cache"):
+            getattr(L, name).restype = C.c_int64
         _lib = L
     return _lib
 
@@ -292,3 +325,69 @@ class Problem:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------ serving
+def _scheck(st, srv):
+    if st < 0:
+        raise FmddmError(st, lib().fmddm_server_last_error(srv).decode())
+    return st
+
+
+def fmddm_server_create(params: Params, max_slots: int, hbm_budget: int = 0):
+    out = _vp()
+    st = lib().fmddm_server_create(C.byref(params), int(max_slots), int(hbm_budget), C.byref(out))
+    if st < 0:
+        raise FmddmError(st, "server creation failed")
+    return out
+
+
+def fmddm_server_destroy(srv):
+    lib().fmddm_server_destroy(srv)
+
+
+def fmddm_server_footprint(srv, n: int) -> int:
+    return int(lib().fmddm_server_footprint(srv, int(n)))
+
+
+def fmddm_server_submit(srv, x1, y1, x2, y2, pf, SH, Sh, steps, tol) -> int:
+    arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (x1, y1, x2, y2, pf)]
+    n = arrs[0].size
+    if any(a.size != n for a in arrs):
+        raise ValueError("geometry and pressure arrays must have the same length")
+    r = Request(n, *[a.ctypes.data for a in arrs], float(SH), float(Sh), int(steps), float(tol))
+    t = C.c_int64()
+    _scheck(lib().fmddm_server_submit(srv, C.byref(r), C.byref(t)), srv)
+    return t.value
+
+
+def fmddm_server_step(srv):
+    a, q = C.c_int(), C.c_int()
+    _scheck(lib().fmddm_server_step(srv, C.byref(a), C.byref(q)), srv)
+    return a.value, q.value
+
+
+def fmddm_server_poll(srv, ticket: int, n: int = 0):
+    """(result dict, D or None); D (host, 2n) once the request is done."""
+    r = Result()
+    D = np.empty(2 * n) if n else None
+    _scheck(lib().fmddm_server_poll(srv, int(ticket), C.byref(r),
+                                    C.c_void_p(D.ctypes.data) if D is not None else None), srv)
+    res = {k: getattr(r, k) for k, _ in Result._fields_}
+    return res, (D if res["state"] == FMDDM_REQ_DONE else None)
+
+
+def fmddm_server_release(srv, ticket: int):
+    _scheck(lib().fmddm_server_release(srv, int(ticket)), srv)
+
+
+def fmddm_memory_in_use() -> int:
+    return int(lib().fmddm_memory_in_use())
+
+
+def fmddm_memory_cached() -> int:
+    return int(lib().fmddm_memory_cached())
+
+
+def fmddm_trim_cache() -> int:
+    return int(lib().fmddm_trim_cache())

@@ -9,11 +9,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfmddm.so")
-SOURCES = ["api.hip", "tree.hip", "fmm.hip", "direct.hip", "solve.hip"]
+SOURCES = ["api.hip", "alloc.hip", "tree.hip", "fmm.hip", "direct.hip", "solve.hip", "serve.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-    # no packed FP32 instructions (see DESIGN notes on the toolchain)
+    # packed FP32 instructions are kept out of the generated code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
     "-I", os.path.join(ROOT, "include"),

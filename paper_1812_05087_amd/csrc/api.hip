@@ -90,9 +90,9 @@ fmddm_status fmddm_create(const fmddm_params *p, void *hip_stream, fmddm_ctx **o
     double G = p->E / (2.0 * (1.0 + p->nu));
     ctx->gc = G / (2.0 * M_PI * (1.0 - p->nu));
     fmddm_status st = guarded(ctx, [&] {
-        FM_HIP(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
-        FM_HIP(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
-        FM_HIP(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+        fmddm::init_streams(ctx);
+        ctx->cheb = std::make_shared<fmddm::Cheb>();
+        ctx->m2l = std::make_shared<fmddm::M2LOps>();
         fmddm::setup_cheb(ctx);
         return FMDDM_OK;
     });
@@ -136,7 +136,14 @@ fmddm_status fmddm_build_tree(fmddm_ctx *ctx, int64_t n, const double *x1, const
     return FMDDM_OK;
 }
 
-void fmddm_tree_free(fmddm_tree *t) { delete t; }
+void fmddm_tree_free(fmddm_tree *t)
+{
+    if (!t) return;
+    // the tree's blocks go back to the allocator cache: no work that uses
+    // them may still be running
+    (void)hipDeviceSynchronize();
+    delete t;
+}
 
 fmddm_status fmddm_tree_get_info(fmddm_ctx *ctx, const fmddm_tree *t, fmddm_tree_info *info)
 {

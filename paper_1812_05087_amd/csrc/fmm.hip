@@ -894,6 +894,14 @@ void Profiler::read(hipStream_t s, double *ms, int64_t *count)
 }
 
 // ------------------------------------------------------------- set-up
+// The side stream and the fork/join events of a context (default priority).
+void init_streams(fmddm_ctx *ctx)
+{
+    FM_HIP(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+    FM_HIP(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+    FM_HIP(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
+}
+
 void setup_cheb(fmddm_ctx *ctx)
 {
     int p = ctx->prm.p;
@@ -918,7 +926,7 @@ void setup_cheb(fmddm_ctx *ctx)
     FM_HIP(hipStreamSynchronize(s));
 }
 
-static void build_m2l_ops(fmddm_ctx *ctx)
+void build_m2l_ops(fmddm_ctx *ctx)
 {
     M2LOps &M = *ctx->m2l;
     if (M.ready) return;

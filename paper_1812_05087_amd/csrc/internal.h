@@ -30,24 +30,33 @@ struct Error {
 #define FM_CHECK_LAUNCH() FM_HIP(hipGetLastError())
 
 // ------------------------------------------------------- device buffers
-// Owning device allocation (hipMalloc), freed in the destructor.
+// alloc.hip: caching device allocator; sizes are rounded up and *rounded
+// receives the block size that dev_release takes back
+void *dev_alloc(size_t bytes, size_t *rounded);
+void dev_release(void *p, size_t rounded);
+size_t dev_cache_trim();
+size_t dev_bytes(bool cached);
+
+// Owning device allocation from the cache, returned to it in the destructor.
 template <class T>
 struct DBuf {
     T *p = nullptr;
     size_t n = 0;
+    size_t cap = 0;  // bytes of the cached block
     DBuf() = default;
     DBuf(const DBuf &) = delete;
     DBuf &operator=(const DBuf &) = delete;
     ~DBuf() { reset(); }
     void reset() {
-        if (p) (void)hipFree(p);
+        if (p) dev_release(p, cap);
         p = nullptr;
         n = 0;
+        cap = 0;
     }
     void alloc(size_t count) {
         reset();
         if (count == 0) count = 1;
-        FM_HIP(hipMalloc((void **)&p, count * sizeof(T)));
+        p = (T *)dev_alloc(count * sizeof(T), &cap);
         n = count;
     }
     void zero(hipStream_t s) { FM_HIP(hipMemsetAsync(p, 0, n * sizeof(T), s)); }
@@ -199,7 +208,9 @@ namespace fmddm {
 void build_tree(fmddm_ctx *ctx, fmddm_tree *t, int64_t n, const double *x1, const double *y1,
                 const double *x2, const double *y2, int on_device);
 // fmm.hip
+void init_streams(fmddm_ctx *ctx);
 void setup_cheb(fmddm_ctx *ctx);
+void build_m2l_ops(fmddm_ctx *ctx);
 void setup_fmm(fmddm_ctx *ctx, fmddm_tree *t);
 void fmm_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out);
 // direct.hip

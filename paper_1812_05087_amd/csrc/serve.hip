@@ -1,0 +1,393 @@
+// Serving engine: many fracture solves of different sizes on one device,
+// batched continuously.
+//
+// A request is the problem of Section 4 for its own geometry (tree, right-
+// hand side, GMRES with FMM products), repeated over `steps` load steps of
+// a linearly ramped fluid pressure, each warm-started from the previous
+// DDs.  The engine keeps up to max_slots requests admitted.  Each slot owns
+// a context with its own pair of streams (default priority) and shares the
+// M2L operators and Chebyshev tables built once for the server.  One engine
+// step polls every slot's last enqueued work without blocking and enqueues
+// its next unit (a GMRES residual or Arnoldi step), so the kernels of
+// different requests run side by side on the device; then it admits at
+// most one queued request if a slot is free and its footprint estimate
+// fits the memory budget (first come, first served).  A request's buffers
+// are its own and every kernel is deterministic, so its result does not
+// depend on what runs beside it.
+#include "internal.h"
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <unordered_map>
+
+using fmddm::DBuf;
+using fmddm::Error;
+
+namespace {
+
+struct Req {
+    fmddm_request r{};
+    std::vector<double> geo;  // x1 | y1 | x2 | y2 | pf, n each
+    std::vector<double> D;    // result, caller order
+    fmddm_result res{};
+};
+
+struct Slot {
+    fmddm_ctx *ctx = nullptr;
+    hipStream_t stream = nullptr;
+    int64_t req = 0;          // 0: free
+    int phase = 0;            // 1 solving, 2 copying the result out
+    int step = 0;
+    fmddm_tree *t = nullptr;
+    DBuf<double> pf, b, x;
+    fmddm::GmresRun g;
+    double *hostD = nullptr;  // pinned
+    size_t host_cap = 0;
+    hipEvent_t ev = nullptr;
+    int64_t charged = 0;
+};
+
+double seconds_since(std::chrono::steady_clock::time_point t0)
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+struct fmddm_server {
+    fmddm_params prm{};
+    int max_slots = 0;
+    int64_t budget = 0, used = 0;
+    int device = 0;
+    std::string err;
+    fmddm_ctx *base = nullptr;  // owns the shared operator sets
+    hipStream_t base_stream = nullptr;
+    std::unordered_map<int64_t, Req> reqs;
+    std::deque<int64_t> queue;
+    int64_t next = 1;
+    std::deque<Slot> slots;  // never relocated: slots hold device buffers
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    ~fmddm_server();
+};
+
+fmddm_server::~fmddm_server()
+{
+    (void)hipSetDevice(device);
+    (void)hipDeviceSynchronize();
+    for (Slot &s : slots) {
+        delete s.t;
+        s.pf.reset();
+        s.b.reset();
+        s.x.reset();
+        if (s.hostD) (void)hipHostFree(s.hostD);
+        if (s.ev) (void)hipEventDestroy(s.ev);
+        delete s.ctx;
+        if (s.stream) (void)hipStreamDestroy(s.stream);
+    }
+    delete base;
+    if (base_stream) (void)hipStreamDestroy(base_stream);
+}
+
+namespace {
+
+// Footprint estimate of a request of n elements: per element the geometry
+// copies, keys and permutation, near-field partials, the P2M matrices and
+// the vectors of GMRES(m); per cell (at most 4n/leaf cells) the weight and
+// field vectors, their compressed forms, split-K partials, the M2L pair
+// results (up to 27 interaction pairs per cell) and the upward-pass
+// partials.  Sizes are rounded up by the allocator, hence the final 25 %.
+int64_t footprint(const fmddm_params &p, int rank_pad, int64_t n)
+{
+    const int64_t M = 3LL * p.p * p.p, Mp = (M + 63) / 64 * 64;
+    const int64_t rp = p.m2l == FMDDM_M2L_SVD ? rank_pad : Mp;
+    const int64_t cells = 4 * n / std::max(1, p.leaf) + 64;
+    int64_t per_elem = 8LL * p.p * p.p + 8 * 2 * (p.restart + 4) + 8 * 48;
+    int64_t per_cell = 8 * (3 * Mp + 2 * rp + 4 * rp + 27 * rp) + 4 * 64;
+    int64_t b = n * per_elem + cells * per_cell + (4 << 20);
+    return b + b / 4;
+}
+
+void check_request(const fmddm_request *r)
+{
+    if (!r || r->n <= 0 || !r->x1 || !r->y1 || !r->x2 || !r->y2 || !r->pf)
+        throw Error{FMDDM_EINVAL, "request: empty geometry or null pointer"};
+    if (r->steps < 1) throw Error{FMDDM_EINVAL, "request: steps must be >= 1"};
+    if (!(r->tol > 0.0 && r->tol < 1.0)) throw Error{FMDDM_EINVAL, "request: tol must be in (0, 1)"};
+    if (!std::isfinite(r->SH) || !std::isfinite(r->Sh)) throw Error{FMDDM_EINVAL, "request: non-finite stress"};
+}
+
+fmddm_ctx *slot_context(fmddm_server *s, hipStream_t st)
+{
+    fmddm_ctx *c = new fmddm_ctx();
+    c->prm = s->prm;
+    c->stream = st;
+    c->device = s->device;
+    c->gc = s->base->gc;
+    c->cheb = s->base->cheb;
+    c->m2l = s->base->m2l;
+    fmddm::init_streams(c);
+    return c;
+}
+
+void retire(fmddm_server *s, Slot &sl)
+{
+    delete sl.t;  // its work has completed: the slot's event was observed
+    sl.t = nullptr;
+    s->used -= sl.charged;
+    sl.charged = 0;
+    sl.req = 0;
+    sl.phase = 0;
+}
+
+void fail(fmddm_server *s, Slot &sl, fmddm_status st)
+{
+    Req &q = s->reqs[sl.req];
+    q.res.state = FMDDM_REQ_FAILED;
+    q.res.status = st;
+    q.res.t_done = seconds_since(s->t0);
+    (void)hipStreamSynchronize(sl.stream);
+    retire(s, sl);
+}
+
+void admit(fmddm_server *s, Slot &sl, int64_t id)
+{
+    Req &q = s->reqs[id];
+    const int64_t n = q.r.n;
+    sl.req = id;
+    sl.step = 0;
+    sl.charged = q.res.device_bytes = footprint(s->prm, s->base->m2l->rp, n);
+    s->used += sl.charged;
+    q.res.state = FMDDM_REQ_RUNNING;
+    q.res.t_admit = seconds_since(s->t0);
+    const double *g = q.geo.data();
+    sl.t = new fmddm_tree();
+    fmddm::build_tree(sl.ctx, sl.t, n, g, g + n, g + 2 * n, g + 3 * n, 0);
+    fmddm::setup_fmm(sl.ctx, sl.t);
+    if (sl.pf.n < (size_t)n) sl.pf.alloc(n);
+    if (sl.b.n < (size_t)(2 * n)) sl.b.alloc(2 * n);
+    if (sl.x.n < (size_t)(2 * n)) sl.x.alloc(2 * n);
+    FM_HIP(hipMemcpyAsync(sl.pf.p, g + 4 * n, n * 8, hipMemcpyHostToDevice, sl.stream));
+    FM_HIP(hipMemsetAsync(sl.x.p, 0, 2 * n * 8, sl.stream));
+    fmddm::rhs_build(sl.ctx, sl.t, sl.pf.p, q.r.SH, q.r.Sh, sl.b.p, 1.0 / q.r.steps);
+    sl.g.start(sl.ctx, sl.t, FMDDM_APPLY_FMM, sl.b.p, sl.x.p, q.r.tol, s->prm.maxit);
+    sl.phase = 1;
+}
+
+// Moves one slot forward if its last enqueued work has finished.
+void advance(fmddm_server *s, Slot &sl)
+{
+    Req &q = s->reqs[sl.req];
+    const int64_t n = q.r.n;
+    if (sl.phase == 1) {
+        if (!sl.g.advance(false)) return;
+        q.res.iters += sl.g.it;
+        q.res.relres = sl.g.relres;
+        if (!sl.g.converged) {
+            fail(s, sl, FMDDM_ENOTCONV);
+            return;
+        }
+        q.res.steps_done = ++sl.step;
+        if (sl.step < q.r.steps) {
+            double scale = (double)(sl.step + 1) / q.r.steps;
+            fmddm::rhs_build(sl.ctx, sl.t, sl.pf.p, q.r.SH, q.r.Sh, sl.b.p, scale);
+            sl.g.start(sl.ctx, sl.t, FMDDM_APPLY_FMM, sl.b.p, sl.x.p, q.r.tol, s->prm.maxit);
+            return;
+        }
+        size_t need = (size_t)(2 * n) * 8;
+        if (sl.host_cap < need) {
+            if (sl.hostD) FM_HIP(hipHostFree(sl.hostD));
+            sl.hostD = nullptr;
+            FM_HIP(hipHostMalloc((void **)&sl.hostD, need, hipHostMallocDefault));
+            sl.host_cap = need;
+        }
+        FM_HIP(hipMemcpyAsync(sl.hostD, sl.x.p, need, hipMemcpyDeviceToHost, sl.stream));
+        FM_HIP(hipEventRecord(sl.ev, sl.stream));
+        sl.phase = 2;
+        return;
+    }
+    if (sl.phase == 2) {
+        hipError_t e = hipEventQuery(sl.ev);
+        if (e == hipErrorNotReady) return;
+        FM_HIP(e);
+        q.D.assign(sl.hostD, sl.hostD + 2 * n);
+        q.res.state = FMDDM_REQ_DONE;
+        q.res.status = FMDDM_OK;
+        q.res.t_done = seconds_since(s->t0);
+        retire(s, sl);
+    }
+}
+
+template <class F>
+fmddm_status sguard(fmddm_server *s, F &&f)
+{
+    try {
+        (void)hipSetDevice(s->device);
+        return f();
+    } catch (const Error &e) {
+        s->err = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        s->err = "host allocation failed";
+        return FMDDM_ENOMEM;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+fmddm_status fmddm_server_create(const fmddm_params *p, int max_slots, int64_t hbm_budget, fmddm_server **out)
+{
+    if (!out) return FMDDM_EINVAL;
+    *out = nullptr;
+    if (!p || max_slots < 1 || max_slots > 64 || hbm_budget < 0) return FMDDM_EINVAL;
+    fmddm_server *s = new (std::nothrow) fmddm_server();
+    if (!s) return FMDDM_ENOMEM;
+    s->prm = *p;
+    s->max_slots = max_slots;
+    if (hipGetDevice(&s->device) != hipSuccess) {
+        delete s;
+        return FMDDM_EDEVICE;
+    }
+    fmddm_status st = sguard(s, [&] {
+        FM_HIP(hipStreamCreateWithFlags(&s->base_stream, hipStreamNonBlocking));
+        fmddm_ctx *b = nullptr;
+        fmddm_status cs = fmddm_create(p, s->base_stream, &b);
+        if (cs != FMDDM_OK) throw Error{cs, "server: invalid parameters"};
+        s->base = b;
+        fmddm::build_m2l_ops(b);
+        if (hbm_budget == 0) {
+            size_t fr = 0, tot = 0;
+            FM_HIP(hipMemGetInfo(&fr, &tot));
+            hbm_budget = (int64_t)(0.9 * (double)fr);
+        }
+        s->budget = hbm_budget;
+        s->slots.resize(max_slots);
+        for (Slot &sl : s->slots) {
+            FM_HIP(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
+            FM_HIP(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
+            sl.ctx = slot_context(s, sl.stream);
+        }
+        return FMDDM_OK;
+    });
+    if (st != FMDDM_OK) {
+        delete s;
+        return st;
+    }
+    *out = s;
+    return FMDDM_OK;
+}
+
+void fmddm_server_destroy(fmddm_server *s) { delete s; }
+
+const char *fmddm_server_last_error(const fmddm_server *s) { return s ? s->err.c_str() : "null server"; }
+
+int64_t fmddm_server_footprint(const fmddm_server *s, int64_t n)
+{
+    if (!s || n <= 0) return 0;
+    return footprint(s->prm, s->base->m2l->rp, n);
+}
+
+fmddm_status fmddm_server_submit(fmddm_server *s, const fmddm_request *r, int64_t *ticket)
+{
+    if (!s || !ticket) return FMDDM_EINVAL;
+    return sguard(s, [&] {
+        check_request(r);
+        int64_t id = s->next++;
+        Req &q = s->reqs[id];
+        q.r = *r;
+        const int64_t n = r->n;
+        q.geo.resize(5 * n);
+        std::memcpy(q.geo.data(), r->x1, n * 8);
+        std::memcpy(q.geo.data() + n, r->y1, n * 8);
+        std::memcpy(q.geo.data() + 2 * n, r->x2, n * 8);
+        std::memcpy(q.geo.data() + 3 * n, r->y2, n * 8);
+        std::memcpy(q.geo.data() + 4 * n, r->pf, n * 8);
+        q.r.x1 = q.r.y1 = q.r.x2 = q.r.y2 = q.r.pf = nullptr;
+        q.res.state = FMDDM_REQ_QUEUED;
+        q.res.t_submit = seconds_since(s->t0);
+        s->queue.push_back(id);
+        *ticket = id;
+        return FMDDM_OK;
+    });
+}
+
+fmddm_status fmddm_server_step(fmddm_server *s, int *active, int *queued)
+{
+    if (!s) return FMDDM_EINVAL;
+    return sguard(s, [&] {
+        for (Slot &sl : s->slots) {
+            if (!sl.req) continue;
+            try {
+                advance(s, sl);
+            } catch (const Error &e) {
+                s->err = e.msg;
+                fail(s, sl, e.code);
+            }
+        }
+        // admission: first come, first served
+        while (!s->queue.empty()) {
+            Slot *free_slot = nullptr;
+            int busy = 0;
+            for (Slot &sl : s->slots) {
+                if (sl.req) ++busy;
+                else if (!free_slot) free_slot = &sl;
+            }
+            if (!free_slot) break;
+            int64_t id = s->queue.front();
+            Req &q = s->reqs[id];
+            int64_t est = footprint(s->prm, s->base->m2l->rp, q.r.n);
+            if (est > s->budget) {
+                s->queue.pop_front();
+                q.res.state = FMDDM_REQ_FAILED;
+                q.res.status = FMDDM_ENOMEM;
+                q.res.t_done = seconds_since(s->t0);
+                continue;
+            }
+            if (s->used + est > s->budget && busy > 0) break;
+            s->queue.pop_front();
+            try {
+                admit(s, *free_slot, id);
+            } catch (const Error &e) {
+                s->err = e.msg;
+                fail(s, *free_slot, e.code);
+            }
+            break;  // at most one admission per step
+        }
+        int a = 0;
+        for (Slot &sl : s->slots) a += sl.req != 0;
+        if (active) *active = a;
+        if (queued) *queued = (int)s->queue.size();
+        return FMDDM_OK;
+    });
+}
+
+fmddm_status fmddm_server_poll(fmddm_server *s, int64_t ticket, fmddm_result *res, double *D)
+{
+    if (!s || !res) return FMDDM_EINVAL;
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) {
+        s->err = "unknown ticket";
+        return FMDDM_EINVAL;
+    }
+    *res = it->second.res;
+    if (D && it->second.res.state == FMDDM_REQ_DONE)
+        std::memcpy(D, it->second.D.data(), it->second.D.size() * 8);
+    return FMDDM_OK;
+}
+
+fmddm_status fmddm_server_release(fmddm_server *s, int64_t ticket)
+{
+    if (!s) return FMDDM_EINVAL;
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end() || it->second.res.state < FMDDM_REQ_DONE) {
+        s->err = "release: unknown or unfinished ticket";
+        return FMDDM_EINVAL;
+    }
+    s->reqs.erase(it);
+    return FMDDM_OK;
+}
+
+}  // extern "C"

@@ -35,15 +35,17 @@ def test_struct_layouts_match_header():
     compiler gives them (computed from the header by gcc)."""
     import subprocess
     import tempfile
-    src = '#include "fmddm.h"\n#include <stdio.h>\nint main(){printf("%zu %zu %zu\\n",' \
-          'sizeof(fmddm_params),sizeof(fmddm_tree_info),sizeof(fmddm_solve_info));return 0;}\n'
+    src = '#include "fmddm.h"\n#include <stdio.h>\nint main(){printf("%zu %zu %zu %zu %zu\\n",' \
+          'sizeof(fmddm_params),sizeof(fmddm_tree_info),sizeof(fmddm_solve_info),' \
+          'sizeof(fmddm_request),sizeof(fmddm_result));return 0;}\n'
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "s.c")
         open(c, "w").write(src)
         exe = os.path.join(d, "s")
         subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
         sizes = list(map(int, subprocess.check_output([exe]).split()))
-    assert sizes == [C.sizeof(F.Params), C.sizeof(F.TreeInfo), C.sizeof(F.SolveInfo)]
+    assert sizes == [C.sizeof(F.Params), C.sizeof(F.TreeInfo), C.sizeof(F.SolveInfo),
+                     C.sizeof(F.Request), C.sizeof(F.Result)]
 
 
 def test_default_params_and_validation_without_device():
@@ -66,6 +68,19 @@ def test_default_params_and_validation_without_device():
     assert lib.fmddm_build_tree(None, 1, None, None, None, None, 0, C.byref(out)) == F.FMDDM_EINVAL
     lib.fmddm_destroy(None)
     lib.fmddm_tree_free(None)
+    # server entry points: invalid arguments are rejected before any device work
+    p = F.fmddm_default_params()
+    for slots, budget in [(0, 0), (65, 0), (4, -1)]:
+        assert lib.fmddm_server_create(C.byref(p), slots, budget, C.byref(out)) == F.FMDDM_EINVAL
+        assert not out.value
+    t = C.c_int64()
+    a = C.c_int()
+    assert lib.fmddm_server_submit(None, None, C.byref(t)) == F.FMDDM_EINVAL
+    assert lib.fmddm_server_step(None, C.byref(a), C.byref(a)) == F.FMDDM_EINVAL
+    assert lib.fmddm_server_poll(None, 1, None, None) == F.FMDDM_EINVAL
+    assert lib.fmddm_server_release(None, 1) == F.FMDDM_EINVAL
+    assert lib.fmddm_server_footprint(None, 100) == 0
+    lib.fmddm_server_destroy(None)
 
 
 def test_binding_refuses_host_tensors():

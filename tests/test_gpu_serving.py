@@ -1,0 +1,162 @@
+"""Serving engine on the GPU (through the C ABI): continuous batching of
+fracture solves of different sizes.
+
+Bars:
+  - a request's DDs are the same alone and in a mix of concurrently running
+    requests: bitwise (per-request buffers, deterministic kernels);
+  - a served solution satisfies the oracle's exact system (direct product,
+    same right-hand side) to the requested tolerance plus the FMM error;
+  - admission never lets the admitted requests' estimated footprints exceed
+    the budget; a request larger than the budget fails with ENOMEM;
+  - the footprint estimate covers the device memory a request allocates;
+  - a request that cannot converge within maxit fails with ENOTCONV.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1812_05087_amd as F  # noqa: E402
+
+P_SERVE = dict(p=10, leaf=32, m2l=1, m2l_tol=1e-10, restart=50, maxit=5000)
+
+
+def submit(srv, req, tol=1e-6):
+    wl = req.workload()
+    return F.fmddm_server_submit(srv, wl.x1, wl.y1, wl.x2, wl.y2, wl.pressure, wl.SH, wl.Sh,
+                                 req.steps, tol), wl
+
+
+def drain(srv, tickets, limit_s=120.0, watch=None):
+    """Step the engine until every ticket is finished; returns {ticket: result}."""
+    t0 = time.time()
+    while True:
+        F.fmddm_server_step(srv)
+        if watch is not None:
+            watch()
+        res = {t: F.fmddm_server_poll(srv, t)[0] for t in tickets}
+        if all(r["state"] >= F.FMDDM_REQ_DONE for r in res.values()):
+            return res
+        assert time.time() - t0 < limit_s, "serving loop did not finish"
+
+
+def test_alone_equals_mix_bitwise():
+    reqs = W.serving_stream(seed=7, count=10, nmin=500, nmax=6000, steps_max=3)
+    prm = F.fmddm_default_params(**P_SERVE)
+    srv = F.fmddm_server_create(prm, 5)
+    try:
+        mix = {}
+        tickets = []
+        for r in reqs:
+            t, wl = submit(srv, r)
+            tickets.append(t)
+            mix[t] = wl.n
+        res = drain(srv, tickets)
+        assert all(v["state"] == F.FMDDM_REQ_DONE for v in res.values()), res
+        D_mix = {t: F.fmddm_server_poll(srv, t, mix[t])[1] for t in tickets}
+        # the same requests again, one at a time on the same server
+        for k, r in enumerate(reqs[::3]):
+            t, wl = submit(srv, r)
+            res1 = drain(srv, [t])[t]
+            assert res1["state"] == F.FMDDM_REQ_DONE
+            D1 = F.fmddm_server_poll(srv, t, wl.n)[1]
+            D0 = D_mix[tickets[3 * k]]
+            assert np.array_equal(D1, D0), float(np.max(np.abs(D1 - D0)))
+            assert res1["iters"] == res[tickets[3 * k]]["iters"]
+    finally:
+        F.fmddm_server_destroy(srv)
+
+
+def test_served_solution_satisfies_exact_system():
+    req = W.serving_stream(seed=11, count=1, nmin=600, nmax=600, steps_max=1)[0]
+    req.steps = 3
+    prm = F.fmddm_default_params(**P_SERVE)
+    srv = F.fmddm_server_create(prm, 2)
+    try:
+        tol = 1e-9
+        t, wl = submit(srv, req, tol=tol)
+        r = drain(srv, [t])[t]
+        assert r["state"] == F.FMDDM_REQ_DONE and r["steps_done"] == 3
+        D = F.fmddm_server_poll(srv, t, wl.n)[1]
+    finally:
+        F.fmddm_server_destroy(srv)
+    g = O.Geometry.of(wl)
+    b = O.rhs(g, wl.pressure, wl.SH, wl.Sh)
+    res = O.direct_matvec(g, D) - b
+    # requested tolerance plus the FMM error at p = 10 (well below 1e-6)
+    assert np.linalg.norm(res) / np.linalg.norm(b) < 1e-6
+    D_lu = O.lu_solve(O.dense_matrix(g), b)
+    assert np.linalg.norm(D - D_lu) / np.linalg.norm(D_lu) < 1e-4
+
+
+def test_admission_respects_budget():
+    reqs = W.serving_stream(seed=13, count=4, nmin=3000, nmax=4000, steps_max=2)
+    prm = F.fmddm_default_params(**P_SERVE)
+    probe = F.fmddm_server_create(prm, 1)
+    big = max(F.fmddm_server_footprint(probe, r.n) for r in reqs)
+    F.fmddm_server_destroy(probe)
+    budget = int(1.2 * big)  # room for one request at a time
+    srv = F.fmddm_server_create(prm, 4, budget)
+    try:
+        tickets = [submit(srv, r)[0] for r in reqs]
+        # a request that can never fit
+        huge = W.serving_stream(seed=17, count=1, nmin=40000, nmax=40000)[0]
+        assert F.fmddm_server_footprint(srv, huge.n) > budget
+        t_huge = submit(srv, huge)[0]
+        peak = [0]
+
+        def watch():
+            run = [F.fmddm_server_poll(srv, t)[0] for t in tickets]
+            charged = sum(r["device_bytes"] for r in run if r["state"] == F.FMDDM_REQ_RUNNING)
+            assert charged <= budget
+            peak[0] = max(peak[0], sum(r["state"] == F.FMDDM_REQ_RUNNING for r in run))
+
+        res = drain(srv, tickets + [t_huge], watch=watch)
+        assert all(res[t]["state"] == F.FMDDM_REQ_DONE for t in tickets)
+        assert res[t_huge]["state"] == F.FMDDM_REQ_FAILED and res[t_huge]["status"] == F.FMDDM_ENOMEM
+        assert peak[0] == 1
+    finally:
+        F.fmddm_server_destroy(srv)
+
+
+def test_footprint_estimate_covers_allocation():
+    prm = F.fmddm_default_params(**P_SERVE)
+    for seed, n in [(19, 1000), (23, 8000), (29, 30000)]:
+        srv = F.fmddm_server_create(prm, 1)
+        try:
+            req = W.serving_stream(seed=seed, count=1, nmin=n, nmax=n, steps_max=1)[0]
+            before = F.fmddm_memory_in_use()
+            t, wl = submit(srv, req)
+            F.fmddm_server_step(srv)  # admits: tree, operators' schedule, GMRES workspace
+            used = F.fmddm_memory_in_use() - before
+            est = F.fmddm_server_footprint(srv, wl.n)
+            assert 0 < used <= est, (wl.n, used, est)
+            drain(srv, [t])
+        finally:
+            F.fmddm_server_destroy(srv)
+
+
+def test_not_converged_request_fails_cleanly():
+    prm = F.fmddm_default_params(**dict(P_SERVE, maxit=3))
+    srv = F.fmddm_server_create(prm, 2)
+    try:
+        req = W.serving_stream(seed=31, count=1, nmin=800, nmax=800, steps_max=1)[0]
+        t, _ = submit(srv, req, tol=1e-12)
+        r = drain(srv, [t])[t]
+        assert r["state"] == F.FMDDM_REQ_FAILED and r["status"] == F.FMDDM_ENOTCONV
+        assert r["iters"] == 3
+        # the slot is usable again
+        t2, _ = submit(srv, req, tol=0.9)
+        assert drain(srv, [t2])[t2]["state"] >= F.FMDDM_REQ_DONE
+        assert F.fmddm_server_step(srv) == (0, 0)
+    finally:
+        F.fmddm_server_destroy(srv)

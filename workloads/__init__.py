@@ -189,3 +189,45 @@ def c2() -> Workload:
 def c4() -> Workload:
     """2000 random fractures x 100 elements (N=200000), seed 4."""
     return random_fractures(4, 2000, 100)
+
+
+@dataclass
+class ServingRequest:
+    """One request of a serving stream: a random-fracture problem (as in
+    random_fractures) with n_frac fractures of `elems` elements in a box
+    scaled to keep the fracture density of the 200-fracture, 100 m case,
+    `steps` load steps, and an arrival time in units of the mean
+    inter-arrival gap (multiply by 1/rate)."""
+
+    index: int
+    seed: int
+    n_frac: int
+    elems: int
+    box: float
+    steps: int
+    arrival_units: float
+
+    @property
+    def n(self) -> int:
+        return self.n_frac * self.elems
+
+    def workload(self) -> Workload:
+        return random_fractures(self.seed, self.n_frac, self.elems, box=self.box)
+
+
+def serving_stream(seed: int = 5, count: int = 1024, nmin: int = 1000, nmax: int = 50000,
+                   steps_max: int = 10, elems: int = 100) -> list:
+    """Poisson-arrival request stream: N log-uniform in [nmin, nmax] rounded
+    to whole fractures of `elems` elements, steps uniform in 1..steps_max,
+    exponential inter-arrival gaps of unit mean.  Geometry is generated on
+    demand (ServingRequest.workload) from a per-request seed."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out, t = [], 0.0
+    for i in range(count):
+        n = float(np.exp(rng.uniform(np.log(nmin), np.log(nmax))))
+        n_frac = max(1, int(round(n / elems)))
+        steps = int(rng.integers(1, steps_max + 1))
+        t += float(rng.exponential(1.0))
+        box = 100.0 * float(np.sqrt(n_frac / 200.0))
+        out.append(ServingRequest(i, seed * 100003 + i, n_frac, elems, box, steps, t))
+    return out
