@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -110,6 +112,78 @@ def traffic_for(phase):
     return d.get("phases", {}).get(phase, {}).get("bytes_per_launch")
 
 
+SERVE_PARAMS = dict(p=10, leaf=32, m2l=1, m2l_tol=1e-10, restart=50, maxit=20000)
+
+
+def serve_run(F, wls, reqs, slots, arrivals):
+    """Serve the requests with `slots` admission slots; request i is
+    submitted at arrivals[i] seconds.  Returns (makespan s, latencies s)."""
+    prm = F.fmddm_default_params(**SERVE_PARAMS)
+    srv = F.fmddm_server_create(prm, slots)
+    try:
+        warm = F.fmddm_server_submit(srv, wls[0].x1, wls[0].y1, wls[0].x2, wls[0].y2, wls[0].pressure,
+                                     wls[0].SH, wls[0].Sh, 1, 1e-6)
+        while F.fmddm_server_poll(srv, warm)[0]["state"] < F.FMDDM_REQ_DONE:
+            F.fmddm_server_step(srv)
+        order = sorted(range(len(reqs)), key=lambda i: arrivals[i])
+        tickets, pend, done = {}, 0, {}
+        t0 = time.perf_counter()
+        while len(done) < len(reqs):
+            now = time.perf_counter() - t0
+            while pend < len(order) and arrivals[order[pend]] <= now:
+                i = order[pend]
+                w = wls[i]
+                tickets[i] = F.fmddm_server_submit(srv, w.x1, w.y1, w.x2, w.y2, w.pressure, w.SH, w.Sh,
+                                                   reqs[i].steps, 1e-6)
+                pend += 1
+            F.fmddm_server_step(srv)
+            for i, t in tickets.items():
+                if i not in done:
+                    r = F.fmddm_server_poll(srv, t)[0]
+                    if r["state"] >= F.FMDDM_REQ_DONE:
+                        if r["state"] != F.FMDDM_REQ_DONE:
+                            raise RuntimeError(f"request {i} failed: status {r['status']}")
+                        done[i] = r
+        t_first = min(r["t_submit"] for r in done.values())
+        span = max(r["t_done"] for r in done.values()) - t_first
+        lat = np.array([r["t_done"] - r["t_submit"] for r in done.values()])
+        iters = int(sum(r["iters"] for r in done.values()))
+        return span, lat, iters
+    finally:
+        F.fmddm_server_destroy(srv)
+
+
+def serving_leg(F, W, count, slots, load):
+    """Serving of the seed-5 request stream (N log-uniform in [1e3, 5e4],
+    1-10 load steps, tol 1e-6): the one-at-a-time service rate, the batched
+    saturation rate, and a Poisson stream at `load` x the one-at-a-time rate
+    served batched and one at a time."""
+    reqs = W.serving_stream(5, count)
+    wls = [r.workload() for r in reqs]
+    zero = [0.0] * count
+    span1, _, iters = serve_run(F, wls, reqs, 1, zero)
+    rate1 = count / span1
+    spanb, _, _ = serve_run(F, wls, reqs, slots, zero)
+    lam = load * rate1
+    arr = [r.arrival_units / lam for r in reqs]
+    spans, lat, _ = serve_run(F, wls, reqs, slots, arr)
+    span_o, lat_o, _ = serve_run(F, wls, reqs, 1, arr)
+    pct = lambda a, q: float(np.percentile(a, q))
+    return {
+        "requests": count, "slots": slots, "elements_total": int(sum(w.n for w in wls)),
+        "gmres_products_total": iters,
+        "params": {"p": SERVE_PARAMS["p"], "leaf": SERVE_PARAMS["leaf"], "m2l": "svd 1e-10", "tol": 1e-6,
+                   "restart": SERVE_PARAMS["restart"]},
+        "one_at_a_time_solves_per_s": rate1,
+        "batched_saturated_solves_per_s": count / spanb,
+        "poisson_rate_per_s": lam,
+        "served": {"solves_per_s": count / spans, "p50_s": pct(lat, 50), "p99_s": pct(lat, 99)},
+        "one_at_a_time_same_stream": {"solves_per_s": count / span_o, "p50_s": pct(lat_o, 50),
+                                      "p99_s": pct(lat_o, 99)},
+        "note": "elastic quasi-static load steps (pressure ramp); the first requests of the seed-5 stream",
+    }
+
+
 def cpu_baseline(wl, D, seconds):
     """The oracle's exact on-the-fly product of the whole workload on all
     host cores, repeated for about `seconds` of wall time."""
@@ -141,13 +215,15 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--serve-load", type=float, default=0.75)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs one instance per GPU and has no "
               "multi-GPU path; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_1812_05087_amd as F
@@ -258,9 +334,11 @@ def main():
                                       "l2p_pairs", "m2m_pairs")},
         "roofline": roof,
     }
+    prob.close()
+    if args.serve_requests > 0:
+        line["serving"] = serving_leg(F, W, args.serve_requests, args.serve_slots, args.serve_load)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, Dh, args.cpu_seconds)
-    prob.close()
     print(json.dumps(line), flush=True)
 
 
