@@ -88,6 +88,14 @@ def lib():
         L.ora_fmm_apply.argtypes = ([C.c_void_p] + [_d] * 5 + [C.c_double] * 2 +
                                     [C.c_int, C.c_int, _d, _d])
         L.ora_fmm_apply.restype = C.c_int
+        L.ora_poro_consts.argtypes = [C.c_double] * 6 + [_d]
+        L.ora_E1.argtypes = [C.c_double]
+        L.ora_E1.restype = C.c_double
+        L.ora_poro_point_transient.argtypes = [_d] + [C.c_double] * 3 + [_d, C.c_double, _d]
+        L.ora_poro_point.argtypes = [_d] + [C.c_double] * 3 + [_d, C.c_double, _d]
+        L.ora_poro_elem_transient.argtypes = ([_d] + [C.c_double] * 12 + [C.c_int, C.c_int, _d])
+        L.ora_poro_matrix.argtypes = ([C.c_int64] + [_d] * 5 + [_d, C.c_double, C.c_int,
+                                                               C.c_int, C.c_int, _d])
         _lib = L
     return _lib
 
@@ -324,3 +332,76 @@ class Tree:
 def num_threads() -> int:
     """Host threads the oracle's parallel loops use."""
     return int(lib().ora_num_threads())
+
+
+# --------------------------------------------------------------------------
+# poroelastic influence (Section 2, eqs. 2.1-2.5)
+# --------------------------------------------------------------------------
+class Poro:
+    """Material constants of the fully coupled (Biot) medium: drained E, nu,
+    undrained nu_u, Biot alpha, permeability and fluid viscosity."""
+
+    def __init__(self, E=20e9, nu=0.2, nuu=0.35, alpha=0.8, perm=1e-18, visc=1e-3):
+        self.P = np.zeros(10)
+        lib().ora_poro_consts(E, nu, nuu, alpha, perm, visc, _p(self.P))
+        self.E, self.nu, self.nuu, self.alpha = E, nu, nuu, alpha
+        (self.G, _, _, _, self.kappa, self.M, self.S, self.c, self.eta, self.B) = self.P
+
+
+def E1(z):
+    return lib().ora_E1(float(z))
+
+
+def poro_point(po: Poro, x, y, t, q, qf=0.0, transient=False):
+    """(sxx, syy, sxy, p) of a point DD with charges q and a fluid source qf,
+    both held from t = 0; transient=True drops the drained elastic part."""
+    out = np.zeros(4)
+    qq = _f64(q)
+    f = lib().ora_poro_point_transient if transient else lib().ora_poro_point
+    f(_p(po.P), float(x), float(y), float(t), _p(qq), float(qf), _p(out))
+    return out
+
+
+def poro_elem_transient(po: Poro, X, Y, cx, cy, cb, sb, a, Ds, Dn, Dq, t1, t0=0.0, nq=12, np_min=4):
+    out = np.zeros(4)
+    lib().ora_poro_elem_transient(_p(po.P), X, Y, cx, cy, cb, sb, a, Ds, Dn, Dq, t1, t0, nq, np_min,
+                                  _p(out))
+    return out
+
+
+def poro_matrix(g: Geometry, po: Poro, dt, m, nq=12, np_min=4):
+    """Time-marching coefficient matrix (3n x 3n): m = 0 gives F(dt), m >= 1
+    gives F((m+1)dt) - F(m dt); rows (shear, normal, pressure) per receiver,
+    columns (Ds, Dn, Dq) per element."""
+    A = np.zeros((3 * g.n, 3 * g.n))
+    lib().ora_poro_matrix(g.n, _p(g.cx), _p(g.cy), _p(g.cb), _p(g.sb), _p(g.a), _p(po.P),
+                          float(dt), int(m), int(nq), int(np_min), _p(A))
+    return A
+
+
+def poro_rhs(g: Geometry, pf, p0, SH, Sh):
+    """Right-hand side of one time step without history (Section 4): the
+    induced tractions cancel the fluid pressure and the far field, the
+    induced pore pressure at the faces equals pf - p0."""
+    b2 = rhs(g, pf, SH, Sh)
+    b = np.zeros(3 * g.n)
+    b[0::3] = b2[0::2]
+    b[1::3] = b2[1::2]
+    b[2::3] = np.asarray(pf, dtype=np.float64) - p0
+    return b
+
+
+def poro_march(g: Geometry, po: Poro, dt, steps, pf, p0, SH, Sh, nq=12, np_min=4):
+    """Time marching of eqs. 2.3-2.5 with dense matrices and Gaussian
+    elimination: D^h solves K_0 D^h = b - sum_{k<h} K_{h-k} D^k.  Returns the
+    list of D^h (3n each) and the history contributions."""
+    K = [poro_matrix(g, po, dt, m, nq, np_min) for m in range(steps)]
+    b = poro_rhs(g, pf, p0, SH, Sh)
+    Ds, hist = [], []
+    for h in range(1, steps + 1):
+        hs = np.zeros(3 * g.n)
+        for k in range(1, h):
+            hs += K[h - k] @ Ds[k - 1]
+        hist.append(hs)
+        Ds.append(lu_solve(K[0], b - hs))
+    return Ds, hist, K

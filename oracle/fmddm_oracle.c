@@ -987,6 +987,298 @@ int ora_fmm_apply(const ora_tree *t, const double *cx, const double *cy,
     return 0;
 }
 
+
+/* ------------------------------------------------------------------------ */
+/* Poroelastic influence (fully coupled Biot theory, plane strain),          */
+/* Section 2, eqs. 2.1-2.5.                                                  */
+/* ------------------------------------------------------------------------ */
+/* The paper writes the boundary integral equations with fundamental
+ * solutions of instantaneous impulses and cites, without stating, their
+ * continuous-impulse forms and the constant-element coefficients.  They are
+ * derived here for an infinite plane, sources switched on at t = 0 and then
+ * held (Heaviside in time).
+ *
+ * Field equations: total stress sigma = 2G eps + lambda tr(eps) I - alpha p I,
+ * equilibrium div sigma = 0, fluid content zeta = alpha tr(eps_m) + p / M
+ * with eps_m the strain of the porous matrix, and dzeta/dt = kappa lap p + g
+ * (kappa = permeability / viscosity, g the fluid source).
+ *
+ * Solution: u = u_d + grad phi, where u_d is the drained elastic field of the
+ * source and lap phi = eta p, eta = alpha (1 - 2 nu) / (2 G (1 - nu)).  Then
+ * grad phi carries the stress 2G (grad grad phi - I lap phi), which is
+ * divergence-free, and the pressure obeys S dp/dt - kappa lap p =
+ * g - alpha d(tr eps_md)/dt with S = 1/M + alpha eta, so p diffuses with
+ * c = kappa / S.
+ *
+ * Displacement discontinuity (point eigenstrain with charges q = (b_x n_x,
+ * b_y n_y, b_x n_y + b_y n_x)): the matrix volumetric strain of the drained
+ * field is a regular cos 2t / sin 2t part with coefficients a = 2G (q0 - q1),
+ * b = 2G q2, times -(1 - 2 nu) / (4 pi G (1 - nu)) / r^2, plus a point term
+ * V delta(x), V = -(q0 + q1)(1 - 2 nu) / (2 (1 - nu)) (the drained dilatation
+ * at the source minus the eigenstrain itself, which is fracture volume, not
+ * matrix strain).  Held from t = 0 it sets p(0+) = -(alpha/S) tr(eps_md),
+ * which then diffuses: smoothing r^-2 {cos, sin} 2t by the heat kernel
+ * multiplies it by P(2,z) = 1 - e^-z (1 + z), z = r^2 / (4 c t), and the
+ * point term becomes the heat kernel e^-z / (4 pi c t).  phi follows from
+ * lap phi = eta p in closed form.
+ *
+ * Fluid source of unit volume rate: p = E1(z) / (4 pi kappa), phi radial
+ * with phi'/r = (eta t / (2 pi S)) (z E1(z) + 1 - e^-z) / r^2.
+ *
+ * Limits (the pins of the tests): t -> 0+ gives the undrained elastic field
+ * (nu_u) with p = -B (1 + nu_u)(sxx + syy) / 3; t -> infinity the drained one
+ * (nu) with p -> 0 for the displacement discontinuity.
+ *
+ * Everything below returns the transient part only, i.e. the response minus
+ * the drained elastic field of the displacement discontinuity (which the
+ * elastic element formulas above give in closed form).  Constants array
+ * P: [0] G [1] nu [2] nu_u [3] alpha [4] kappa [5] M [6] S [7] c [8] eta [9] B. */
+
+void ora_poro_consts(double E, double nu, double nuu, double alpha, double perm,
+                     double visc, double P[10])
+{
+    double G = E / (2.0 * (1.0 + nu));
+    double M = 2.0 * G * (nuu - nu) / (alpha * alpha * (1.0 - 2.0 * nuu) * (1.0 - 2.0 * nu));
+    double eta = alpha * (1.0 - 2.0 * nu) / (2.0 * G * (1.0 - nu));
+    double S = 1.0 / M + alpha * eta;
+    double kap = perm / visc;
+    P[0] = G; P[1] = nu; P[2] = nuu; P[3] = alpha; P[4] = kap; P[5] = M;
+    P[6] = S; P[7] = kap / S; P[8] = eta;
+    P[9] = 3.0 * (nuu - nu) / (alpha * (1.0 - 2.0 * nu) * (1.0 + nuu));
+}
+
+/* Exponential integral E1(z), z > 0: the power series of Abramowitz &
+ * Stegun 5.1.11 for z <= 1.5, the continued fraction 5.1.22 (even part,
+ * modified Lentz evaluation) above. */
+double ora_E1(double z)
+{
+    if (z <= 1.5) {
+        double s = 0.0, term = 1.0;
+        for (int k = 1; k < 60; ++k) {
+            term *= -z / k;               /* (-z)^k / k! */
+            s += term / k;
+            if (fabs(term / k) < 1e-18 * fabs(s)) break;
+        }
+        return -0.57721566490153286061 - log(z) - s;
+    }
+    /* E1 = e^-z / (z + 1 - 1/(z + 3 - 4/(z + 5 - 9/(...)))) */
+    const double tiny = 1e-300;
+    double f = z + 1.0, C = f, D = 0.0;
+    for (int k = 1; k < 500; ++k) {
+        double an = -(double)k * k, bn = z + 2.0 * k + 1.0;
+        D = bn + an * D;
+        if (fabs(D) < tiny) D = tiny;
+        C = bn + an / C;
+        if (fabs(C) < tiny) C = tiny;
+        D = 1.0 / D;
+        double del = C * D;
+        f *= del;
+        if (fabs(del - 1.0) < 1e-16) break;
+    }
+    return exp(-z) / f;
+}
+
+/* h(z) = 1 - (1 - e^-z)/z and its first two derivatives (series for small z). */
+static void poro_h(double z, double *h, double *h1, double *h2)
+{
+    if (z < 0.5) {
+        /* h = sum_{k>=1} (-1)^(k+1) z^k / (k+1)! */
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, fact = 1.0; /* fact = (k+1)! */
+        for (int k = 1; k < 30; ++k) {
+            fact *= (k + 1);
+            double sg = (k & 1) ? 1.0 : -1.0;
+            s0 += sg * pow(z, k) / fact;
+            s1 += sg * k * pow(z, k - 1) / fact;
+            if (k >= 2) s2 += sg * k * (k - 1) * pow(z, k - 2) / fact;
+        }
+        *h = s0; *h1 = s1; *h2 = s2;
+        return;
+    }
+    double em = exp(-z), om = -expm1(-z); /* 1 - e^-z */
+    *h = 1.0 - om / z;
+    *h1 = om / (z * z) - em / z;
+    *h2 = -2.0 * om / (z * z * z) + 2.0 * em / (z * z) + em / z;
+}
+
+/* P(2, z) = 1 - e^-z (1 + z). */
+static double poro_P2(double z)
+{
+    if (z < 0.1) {
+        double s = 0.0, fact = 1.0;
+        for (int k = 2; k < 20; ++k) {
+            fact = 1.0;
+            for (int j = 2; j <= k; ++j) fact *= j;
+            s += ((k & 1) ? -1.0 : 1.0) * (k - 1) * pow(z, k) / fact;
+        }
+        return s;
+    }
+    return 1.0 - exp(-z) * (1.0 + z);
+}
+
+/* Second derivatives (xx, yy, xy) of a radial function with derivatives
+ * f1 = phi'(r)/r and f2 = phi''(r). */
+static void radial_d2(double x, double y, double f1, double f2, double d[3])
+{
+    double r2 = x * x + y * y;
+    d[0] = f2 * x * x / r2 + f1 * y * y / r2;
+    d[1] = f2 * y * y / r2 + f1 * x * x / r2;
+    d[2] = (f2 - f1) * x * y / r2;
+}
+
+/* Transient response (sxx, syy, sxy, p) at offset (x, y), time t > 0, of a
+ * point displacement discontinuity with charges q (held from t = 0) and of a
+ * point fluid source of volume rate qf (held from t = 0). */
+void ora_poro_point_transient(const double *P, double x, double y, double t,
+                              const double q[3], double qf, double out[4])
+{
+    const double G = P[0], nu = P[1], alpha = P[3], kap = P[4], S = P[6], c = P[7],
+                 eta = P[8];
+    double r2 = x * x + y * y, r = sqrt(r2);
+    double z = r2 / (4.0 * c * t);
+    double ez = exp(-z), om = -expm1(-z);
+    double kd = (1.0 - 2.0 * nu) / (4.0 * M_PI * G * (1.0 - nu));
+    double a = 2.0 * G * (q[0] - q[1]), b = 2.0 * G * q[2];
+    double V = -(q[0] + q[1]) * (1.0 - 2.0 * nu) / (2.0 * (1.0 - nu));
+    double cos2 = (x * x - y * y) / r2, sin2 = 2.0 * x * y / r2;
+    /* pressure */
+    double p = (alpha * kd / S) * (a * cos2 + b * sin2) * poro_P2(z) / r2
+               - (alpha / S) * V * ez / (4.0 * M_PI * c * t);
+    /* regular part: phi = Cphi (a F(r)(x^2 - y^2) + b F(r) 2xy),
+     * F = -h(z) / (4 r^2) */
+    double h, h1, h2;
+    poro_h(z, &h, &h1, &h2);
+    double F = -h / (4.0 * r2);
+    double F1 = (h - z * h1) / (2.0 * r2 * r);
+    double F2 = (-2.0 * z * z * h2 - 3.0 * h + 3.0 * z * h1) / (2.0 * r2 * r2);
+    double Fd[3];
+    radial_d2(x, y, F1 / r, F2, Fd);
+    double Fx = F1 * x / r, Fy = F1 * y / r;
+    /* g = x^2 - y^2 */
+    double cxx = Fd[0] * (x * x - y * y) + 2.0 * Fx * 2.0 * x + F * 2.0;
+    double cyy = Fd[1] * (x * x - y * y) + 2.0 * Fy * (-2.0 * y) - F * 2.0;
+    double cxy = Fd[2] * (x * x - y * y) + Fx * (-2.0 * y) + Fy * (2.0 * x);
+    /* g = 2xy */
+    double sxx = Fd[0] * 2.0 * x * y + 2.0 * Fx * 2.0 * y;
+    double syy = Fd[1] * 2.0 * x * y + 2.0 * Fy * 2.0 * x;
+    double sxy = Fd[2] * 2.0 * x * y + Fx * 2.0 * x + Fy * 2.0 * y + F * 2.0;
+    double Cphi = alpha * kd * eta / S;
+    double pxx = Cphi * (a * cxx + b * sxx);
+    double pyy = Cphi * (a * cyy + b * syy);
+    double pxy = Cphi * (a * cxy + b * sxy);
+    /* point term: radial phi, phi'/r = Kd (1 - e^-z) / r^2 */
+    double Kd = -alpha * eta * V / (2.0 * M_PI * S);
+    double d[3];
+    radial_d2(x, y, Kd * om / r2, Kd * (2.0 * z * ez - om) / r2, d);
+    pxx += d[0]; pyy += d[1]; pxy += d[2];
+    /* fluid source */
+    if (qf != 0.0) {
+        double e1 = ora_E1(z);
+        p += qf * e1 / (4.0 * M_PI * kap);
+        double Kf = qf * eta * t / (2.0 * M_PI * S);
+        double A = z * e1 + om;
+        radial_d2(x, y, Kf * A / r2, Kf * (2.0 * z * e1 - A) / r2, d);
+        pxx += d[0]; pyy += d[1]; pxy += d[2];
+    }
+    out[0] = -2.0 * G * pyy;
+    out[1] = -2.0 * G * pxx;
+    out[2] = 2.0 * G * pxy;
+    out[3] = p;
+}
+
+/* Full response of a point DD (drained elastic point kernel + transient). */
+void ora_poro_point(const double *P, double x, double y, double t,
+                    const double q[3], double qf, double out[4])
+{
+    double K[9];
+    ora_point_kernel(x, y, P[0], P[1], K);
+    ora_poro_point_transient(P, x, y, t, q, qf, out);
+    for (int r = 0; r < 3; ++r) out[r] += K[3 * r] * q[0] + K[3 * r + 1] * q[1] + K[3 * r + 2] * q[2];
+}
+
+/* Element integral of the transient response difference T(t1) - T(t0)
+ * (t0 = 0: T(t1) alone) of element j (midpoint, cos/sin of its direction,
+ * half-length a) carrying per-unit-length DDs (Ds, Dn) and fluid source Dq,
+ * at the global point (X, Y).  The element is split at the foot of the
+ * perpendicular from the receiver; on each side s = s0 +- L u^3 with
+ * composite Gauss-Legendre in u (the substitution smooths the logarithmic
+ * singularity of the fluid source and clusters nodes near the receiver);
+ * panels are sized by the diffusion length sqrt(4 c t0).  nq = points per
+ * panel, np_min = minimum panels (refinement studies double either). */
+void ora_poro_elem_transient(const double *P, double X, double Y, double cx,
+                             double cy, double cb, double sb, double a,
+                             double Ds, double Dn, double Dq, double t1,
+                             double t0, int nq, int np_min, double out[4])
+{
+    double q[3];
+    ora_charge(cb, sb, Ds, Dn, q);
+    double dx = X - cx, dy = Y - cy;
+    double xl = dx * cb + dy * sb;
+    double s0 = xl < -a ? -a : (xl > a ? a : xl);
+    double tmin = t0 > 0.0 ? t0 : t1;
+    double ell = sqrt(4.0 * P[7] * tmin);
+    double gt[64], gw[64];
+    ora_gauss_legendre(nq, gt, gw);
+    for (int k = 0; k < 4; ++k) out[k] = 0.0;
+    for (int side = 0; side < 2; ++side) {
+        double L = side ? a - s0 : s0 + a;
+        if (L <= 0.0) continue;
+        int np = np_min + (int)ceil(2.0 * L / ell);
+        if (np > 400) np = 400;
+        for (int pn = 0; pn < np; ++pn) {
+            double u0 = (double)pn / np, u1 = (double)(pn + 1) / np;
+            for (int g = 0; g < nq; ++g) {
+                double u = 0.5 * (u0 + u1) + 0.5 * (u1 - u0) * gt[g];
+                double w = 0.5 * (u1 - u0) * gw[g] * 3.0 * L * u * u;
+                double s = side ? s0 + L * u * u * u : s0 - L * u * u * u;
+                double sx = cx + s * cb, sy = cy + s * sb;
+                double r1[4], r0[4] = {0, 0, 0, 0};
+                ora_poro_point_transient(P, X - sx, Y - sy, t1, q, Dq, r1);
+                if (t0 > 0.0) ora_poro_point_transient(P, X - sx, Y - sy, t0, q, Dq, r0);
+                for (int k = 0; k < 4; ++k) out[k] += w * (r1[k] - r0[k]);
+            }
+        }
+    }
+}
+
+/* Time-marching operator of the constant spatial / constant temporal
+ * elements (eqs. 2.3-2.5): the response at every midpoint (shear and normal
+ * traction, pore pressure) to unit (Ds, Dn, Dq) on every element held over
+ * one interval, evaluated m intervals after the interval ends:
+ *   m = 0:  F(dt)                       (left-hand side; includes the
+ *                                        drained elastic part)
+ *   m >= 1: F((m+1) dt) - F(m dt)       (history coefficients)
+ * Returned as the dense 3n x 3n matrix, row 3i + r (r: shear, normal,
+ * pressure), column 3j + c (c: Ds, Dn, Dq). */
+void ora_poro_matrix(int64_t n, const double *cx, const double *cy,
+                     const double *cb, const double *sb, const double *a,
+                     const double *P, double dt, int m, int nq, int np_min,
+                     double *A)
+{
+    double t1 = (m + 1) * dt, t0 = m * dt;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t j = 0; j < n; ++j) {
+            for (int col = 0; col < 3; ++col) {
+                double Ds = col == 0, Dn = col == 1, Dq = col == 2;
+                double o[4];
+                ora_poro_elem_transient(P, cx[i], cy[i], cx[j], cy[j], cb[j], sb[j],
+                                        a[j], Ds, Dn, Dq, t1, t0, nq, np_min, o);
+                if (m == 0 && col < 2) {
+                    double sg[3];
+                    ora_elem_stress(cx[i], cy[i], cx[j], cy[j], cb[j], sb[j], a[j],
+                                    P[0], P[1], Ds, Dn, sg);
+                    o[0] += sg[0]; o[1] += sg[1]; o[2] += sg[2];
+                }
+                double ts, tn;
+                ora_traction(cb[i], sb[i], o, &ts, &tn);
+                A[(3 * i + 0) * 3 * n + 3 * j + col] = ts;
+                A[(3 * i + 1) * 3 * n + 3 * j + col] = tn;
+                A[(3 * i + 2) * 3 * n + 3 * j + col] = o[3];
+            }
+        }
+    }
+}
+
 /* Threads the OpenMP loops above use (reporting only). */
 #ifdef _OPENMP
 #include <omp.h>
