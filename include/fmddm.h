@@ -214,6 +214,59 @@ fmddm_status fmddm_profile(fmddm_ctx *ctx, unsigned mask);
  * read; resets the sums.  Synchronises the stream. */
 fmddm_status fmddm_profile_read(fmddm_ctx *ctx, double *ms, int64_t *count);
 
+/* ------------------------------------------------------------------------
+ * Poroelastic time marching (Section 2, eqs. 2.1-2.5).
+ *
+ * Unknowns per element j: D[3j] = D_s, D[3j+1] = D_n (m, as above),
+ * D[3j+2] = D_q, the fluid volume leaving the fracture per unit time and
+ * unit element length (m^2/s).  Responses per element i: out[3i] shear
+ * traction, out[3i+1] normal traction, out[3i+2] pore pressure change at
+ * the midpoint (Pa).  The medium is fully coupled Biot poroelastic: the
+ * context's E and nu are the drained constants, fmddm_poro_params adds the
+ * undrained Poisson ratio, the Biot coefficient and the mobility
+ * (permeability / viscosity).  Time is discretised in equal intervals dt
+ * with constant DDs in each interval, collocated at interval ends: the
+ * system of step h is
+ *     K_0 D^h = b_h - sum_{k=1}^{h-1} K_{h-k} D^k,
+ * K_0 = F(dt), K_m = F((m+1) dt) - F(m dt), F(t) the response at time t to
+ * unit sources switched on at 0 and held.  All products here evaluate the
+ * element integrals exactly (no multipole approximation); their cost is
+ * proportional to n^2 times the number of time levels.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    double nu_u;              /* undrained Poisson ratio, nu < nu_u < 0.5 */
+    double alpha;             /* Biot coefficient, (0, 1] */
+    double perm, visc;        /* permeability (m^2) and fluid viscosity (Pa s) */
+    double dt;                /* time step (s) */
+    double p0;                /* initial pore pressure (Pa), for fmddm_poro_rhs */
+} fmddm_poro_params;
+
+/* Attaches the poroelastic medium to the context (validated: EINVAL). */
+fmddm_status fmddm_poro_set(fmddm_ctx *ctx, const fmddm_poro_params *pp);
+
+/* out = K_lag D (device, 3n each; out must not alias D): lag 0 is the
+ * left-hand side F(dt) including the drained elastic part, lag >= 1 the
+ * history coefficient F((lag+1) dt) - F(lag dt). */
+fmddm_status fmddm_poro_apply(fmddm_ctx *ctx, fmddm_tree *t, int lag, const double *D, double *out);
+
+/* rhs -= sum_{k=1}^{h-1} K_{h-k} D^k for step h >= 1 (h = 1: nothing).
+ * Dhist (device) holds D^1, ..., D^{h-1}, 3n each, consecutively; rhs
+ * (device, 3n) must not alias it.  The sum is evaluated once per time
+ * level j dt (j = 1..h) on differences of the stored DDs. */
+fmddm_status fmddm_add_history(fmddm_ctx *ctx, fmddm_tree *t, int h, const double *Dhist, double *rhs);
+
+/* Right-hand side of one step without history (Section 4): the induced
+ * tractions cancel the fluid pressure pf (device, n) and the far field (SH,
+ * Sh compressive, along x and y); the induced pore pressure at the faces is
+ * pf - p0.  rhs: device, 3n. */
+fmddm_status fmddm_poro_rhs(fmddm_ctx *ctx, fmddm_tree *t, const double *pf, double SH, double Sh,
+                            double *rhs);
+
+/* Solves K_0 D = rhs by restarted GMRES (the context's restart, maxit,
+ * tol); D (device, 3n) is the initial guess and receives the solution. */
+fmddm_status fmddm_poro_solve(fmddm_ctx *ctx, fmddm_tree *t, const double *rhs, double *D,
+                              fmddm_solve_info *info);
+
 /* Device memory of the library on the current device.  Every device buffer
  * comes from a cache: a block released by a freed tree or context is kept
  * and handed out again instead of being returned to the runtime (hipFree

@@ -33,6 +33,7 @@ EXPORTED = [
     "fmddm_server_create", "fmddm_server_destroy", "fmddm_server_last_error", "fmddm_server_footprint",
     "fmddm_server_submit", "fmddm_server_step", "fmddm_server_poll", "fmddm_server_release",
     "fmddm_memory_in_use", "fmddm_memory_cached", "fmddm_trim_cache",
+    "fmddm_poro_set", "fmddm_poro_apply", "fmddm_add_history", "fmddm_poro_rhs", "fmddm_poro_solve",
 ]
 FMDDM_REQ_QUEUED, FMDDM_REQ_RUNNING, FMDDM_REQ_DONE, FMDDM_REQ_FAILED = 0, 1, 2, 3
 PHASES = ["prep", "p2m", "m2m", "m2m_sum", "compress", "compress_sum", "m2l", "m2l_sum", "decompress",
@@ -77,6 +78,11 @@ class Result(C.Structure):
     _fields_ = [("state", C.c_int32), ("status", C.c_int32), ("steps_done", C.c_int32),
                 ("iters", C.c_int32), ("relres", C.c_double), ("t_submit", C.c_double),
                 ("t_admit", C.c_double), ("t_done", C.c_double), ("device_bytes", C.c_int64)]
+
+
+class PoroParams(C.Structure):
+    _fields_ = [("nu_u", C.c_double), ("alpha", C.c_double), ("perm", C.c_double), ("visc", C.c_double),
+                ("dt", C.c_double), ("p0", C.c_double)]
 
 
 class SolveInfo(C.Structure):
@@ -129,6 +135,11 @@ def lib():
         L.fmddm_server_release.argtypes = [_vp, C.c_int64]
         for name in ("fmddm_memory_in_use", "fmddm_memory_cached", "fmddm_trim_cache"):
             getattr(L, name).argtypes = []
+        L.fmddm_poro_set.argtypes = [_vp, C.POINTER(PoroParams)]
+        L.fmddm_poro_apply.argtypes = [_vp, _vp, C.c_int, _vp, _vp]
+        L.fmddm_add_history.argtypes = [_vp, _vp, C.c_int, _vp, _vp]
+        L.fmddm_poro_rhs.argtypes = [_vp, _vp, _vp, C.c_double, C.c_double, _vp]
+        L.fmddm_poro_solve.argtypes = [_vp, _vp, _vp, _vp, C.POINTER(SolveInfo)]
         for name in EXPORTED:
             f = getattr(L, name)
             if name not in ("fmddm_default_params", "fmddm_destroy", "fmddm_tree_free",
@@ -391,3 +402,30 @@ def fmddm_memory_cached() -> int:
 
 def fmddm_trim_cache() -> int:
     return int(lib().fmddm_trim_cache())
+
+
+# ------------------------------------------------------------ poroelastic
+def fmddm_poro_set(ctx, nu_u, alpha, perm, visc, dt, p0=0.0):
+    pp = PoroParams(float(nu_u), float(alpha), float(perm), float(visc), float(dt), float(p0))
+    _check(lib().fmddm_poro_set(ctx, C.byref(pp)), ctx)
+
+
+def fmddm_poro_apply(ctx, tree, lag, D, out):
+    _check(lib().fmddm_poro_apply(ctx, tree, int(lag), _ptr(D), _ptr(out)), ctx)
+
+
+def fmddm_add_history(ctx, tree, h, Dhist, rhs):
+    """rhs -= sum_{k=1}^{h-1} K_{h-k} D^k; Dhist: device tensor holding
+    D^1..D^{h-1} consecutively (or None when h == 1)."""
+    dh = _ptr(Dhist) if Dhist is not None else None
+    _check(lib().fmddm_add_history(ctx, tree, int(h), dh, _ptr(rhs)), ctx)
+
+
+def fmddm_poro_rhs(ctx, tree, pf, SH, Sh, rhs):
+    _check(lib().fmddm_poro_rhs(ctx, tree, _ptr(pf), float(SH), float(Sh), _ptr(rhs)), ctx)
+
+
+def fmddm_poro_solve(ctx, tree, rhs, D):
+    info = SolveInfo()
+    st = _check(lib().fmddm_poro_solve(ctx, tree, _ptr(rhs), _ptr(D), C.byref(info)), ctx)
+    return st, {k: getattr(info, k) for k, _ in SolveInfo._fields_}

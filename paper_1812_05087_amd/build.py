@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfmddm.so")
-SOURCES = ["api.hip", "alloc.hip", "tree.hip", "fmm.hip", "direct.hip", "solve.hip", "serve.hip"]
+SOURCES = ["api.hip", "alloc.hip", "tree.hip", "fmm.hip", "direct.hip", "solve.hip", "serve.hip", "poro.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

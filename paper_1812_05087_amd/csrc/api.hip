@@ -256,6 +256,61 @@ fmddm_status fmddm_solve(fmddm_ctx *ctx, fmddm_tree *t, int mode, const double *
     return guarded(ctx, [&] { return fmddm::gmres_solve(ctx, t, mode, rhs, D, info); });
 }
 
+fmddm_status fmddm_poro_set(fmddm_ctx *ctx, const fmddm_poro_params *pp)
+{
+    if (!ctx || !pp) return FMDDM_EINVAL;
+    const double nu = ctx->prm.nu;
+    if (!(pp->nu_u > nu && pp->nu_u < 0.5) || !(pp->alpha > 0.0 && pp->alpha <= 1.0) || !(pp->perm > 0.0) ||
+        !(pp->visc > 0.0) || !(pp->dt > 0.0) || !std::isfinite(pp->p0)) {
+        ctx->err = "poroelastic parameters: need nu < nu_u < 0.5, 0 < alpha <= 1, perm, visc, dt > 0";
+        return FMDDM_EINVAL;
+    }
+    ctx->poro = *pp;
+    ctx->poro_set = 1;
+    return FMDDM_OK;
+}
+
+fmddm_status fmddm_poro_apply(fmddm_ctx *ctx, fmddm_tree *t, int lag, const double *D, double *out)
+{
+    if (!ctx || !t || !D || !out || D == out || lag < 0) return FMDDM_EINVAL;
+    return guarded(ctx, [&] {
+        fmddm::poro_apply(ctx, t, lag, D, out);
+        return FMDDM_OK;
+    });
+}
+
+fmddm_status fmddm_add_history(fmddm_ctx *ctx, fmddm_tree *t, int h, const double *Dhist, double *rhs)
+{
+    if (!ctx || !t || !rhs || h < 1 || (h > 1 && !Dhist)) return FMDDM_EINVAL;
+    if (h > 1 && rhs + 3 * t->n > Dhist && Dhist + 3 * t->n * (h - 1) > rhs) return FMDDM_EINVAL;
+    return guarded(ctx, [&] {
+        fmddm::poro_history(ctx, t, h, Dhist, rhs);
+        return FMDDM_OK;
+    });
+}
+
+fmddm_status fmddm_poro_rhs(fmddm_ctx *ctx, fmddm_tree *t, const double *pf, double SH, double Sh, double *rhs)
+{
+    if (!ctx || !t || !pf || !rhs) return FMDDM_EINVAL;
+    if (!ctx->poro_set) {
+        ctx->err = "poroelastic parameters not set (fmddm_poro_set)";
+        return FMDDM_EINVAL;
+    }
+    return guarded(ctx, [&] {
+        fmddm::poro_rhs(ctx, t, pf, SH, Sh, rhs);
+        return FMDDM_OK;
+    });
+}
+
+fmddm_status fmddm_poro_solve(fmddm_ctx *ctx, fmddm_tree *t, const double *rhs, double *D,
+                              fmddm_solve_info *info)
+{
+    if (!ctx || !t || !rhs || !D || rhs == D) return FMDDM_EINVAL;
+    fmddm_solve_info local;
+    if (!info) info = &local;
+    return guarded(ctx, [&] { return fmddm::gmres_solve(ctx, t, fmddm::APPLY_PORO, rhs, D, info); });
+}
+
 fmddm_status fmddm_sif(fmddm_ctx *ctx, fmddm_tree *t, const double *D, int64_t elem, double *KI,
                        double *KII)
 {

@@ -720,40 +720,6 @@ __global__ void k_final(int n, const int *__restrict__ tleaf, const int *__restr
 }
 
 // ------------------------------------------------------- host helpers
-// Gauss-Legendre nodes/weights on [-1, 1] (Newton on the Legendre
-// recurrence).
-void gauss_legendre(int n, std::vector<double> &t, std::vector<double> &w)
-{
-    t.assign(n, 0.0);
-    w.assign(n, 0.0);
-    for (int i = 0; i < n; ++i) {
-        double x = std::cos(M_PI * (i + 0.75) / (n + 0.5));
-        double dpn = 1;
-        for (int it = 0; it < 200; ++it) {
-            double pm = 1.0, pc = x;
-            for (int k = 2; k <= n; ++k) {
-                double pk = ((2.0 * k - 1.0) * x * pc - (k - 1.0) * pm) / k;
-                pm = pc;
-                pc = pk;
-            }
-            if (n == 1) { pc = x; pm = 1.0; }
-            dpn = n * (x * pc - pm) / (x * x - 1.0);
-            double dx = pc / dpn;
-            x -= dx;
-            if (std::fabs(dx) < 1e-17) break;
-        }
-        double pm = 1.0, pc = x;
-        for (int k = 2; k <= n; ++k) {
-            double pk = ((2.0 * k - 1.0) * x * pc - (k - 1.0) * pm) / k;
-            pm = pc;
-            pc = pk;
-        }
-        if (n == 1) { pc = x; pm = 1.0; }
-        dpn = n * (x * pc - pm) / (x * x - 1.0);
-        t[i] = x;
-        w[i] = 2.0 / ((1.0 - x * x) * dpn * dpn);
-    }
-}
 
 
 int offset_slot(int dx, int dy) { return (dx + 3) + 7 * (dy + 3); }
@@ -835,6 +801,41 @@ void launch_l2p(hipStream_t s, fmddm_ctx *ctx, fmddm_tree *t, int Mp)
     }
 
 }  // namespace
+
+// Gauss-Legendre nodes/weights on [-1, 1] (Newton on the Legendre
+// recurrence).
+void gauss_legendre(int n, std::vector<double> &t, std::vector<double> &w)
+{
+    t.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        double x = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        double dpn = 1;
+        for (int it = 0; it < 200; ++it) {
+            double pm = 1.0, pc = x;
+            for (int k = 2; k <= n; ++k) {
+                double pk = ((2.0 * k - 1.0) * x * pc - (k - 1.0) * pm) / k;
+                pm = pc;
+                pc = pk;
+            }
+            if (n == 1) { pc = x; pm = 1.0; }
+            dpn = n * (x * pc - pm) / (x * x - 1.0);
+            double dx = pc / dpn;
+            x -= dx;
+            if (std::fabs(dx) < 1e-17) break;
+        }
+        double pm = 1.0, pc = x;
+        for (int k = 2; k <= n; ++k) {
+            double pk = ((2.0 * k - 1.0) * x * pc - (k - 1.0) * pm) / k;
+            pm = pc;
+            pc = pk;
+        }
+        if (n == 1) { pc = x; pm = 1.0; }
+        dpn = n * (x * pc - pm) / (x * x - 1.0);
+        t[i] = x;
+        w[i] = 2.0 / ((1.0 - x * x) * dpn * dpn);
+    }
+}
 
 // ------------------------------------------------------------ profiler
 Profiler::~Profiler()

@@ -125,6 +125,8 @@ struct fmddm_ctx {
     // the M2L mode: contexts created by a server share one set
     std::shared_ptr<fmddm::Cheb> cheb;
     std::shared_ptr<fmddm::M2LOps> m2l;
+    fmddm_poro_params poro{};  // poroelastic medium and time step (fmddm_poro_set)
+    int poro_set = 0;
     double gc = 0.0;        // G / (2 pi (1 - nu))
 };
 
@@ -192,6 +194,9 @@ struct fmddm_tree {
     // residual norm and estimate to, gm_ev marks when they have arrived
     fmddm::DBuf<double> gm_V, gm_w, gm_r, gm_sc;
     int gm_restart = 0;
+    int64_t gm_len = 0;
+    // poroelastic workspace: chunk partials, term times, term vectors
+    fmddm::DBuf<double> poro_part, poro_times, poro_E;
     double *gm_host = nullptr;
     hipEvent_t gm_ev = nullptr;
     int64_t bytes = 0;
@@ -208,6 +213,7 @@ namespace fmddm {
 void build_tree(fmddm_ctx *ctx, fmddm_tree *t, int64_t n, const double *x1, const double *y1,
                 const double *x2, const double *y2, int on_device);
 // fmm.hip
+void gauss_legendre(int n, std::vector<double> &t, std::vector<double> &w);
 void init_streams(fmddm_ctx *ctx);
 void setup_cheb(fmddm_ctx *ctx);
 void build_m2l_ops(fmddm_ctx *ctx);
@@ -247,6 +253,13 @@ struct GmresRun {
     void enqueue_step();
 };
 void apply_mode(fmddm_ctx *ctx, fmddm_tree *t, int mode, const double *D, double *out);
+// apply mode of the poroelastic left-hand side F(dt) (3 unknowns per element)
+constexpr int APPLY_PORO = 100;
+inline int64_t vec_len(const fmddm_tree *t, int mode) { return (mode == APPLY_PORO ? 3 : 2) * t->n; }
+// poro.hip
+void poro_apply(fmddm_ctx *ctx, fmddm_tree *t, int lag, const double *D, double *out);
+void poro_history(fmddm_ctx *ctx, fmddm_tree *t, int h, const double *Dh, double *rhs);
+void poro_rhs(fmddm_ctx *ctx, fmddm_tree *t, const double *pf, double SH, double Sh, double *rhs);
 
 inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 

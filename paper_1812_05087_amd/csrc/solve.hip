@@ -187,6 +187,7 @@ void apply_mode(fmddm_ctx *ctx, fmddm_tree *t, int mode, const double *D, double
     case FMDDM_APPLY_FMM: fmm_apply(ctx, t, D, out); break;
     case FMDDM_APPLY_DIRECT: direct_apply(ctx, t, D, out); break;
     case FMDDM_APPLY_DENSE: dense_apply(ctx, t, D, out); break;
+    case APPLY_PORO: poro_apply(ctx, t, 0, D, out); break;
     default: throw Error{FMDDM_EINVAL, "unknown apply mode"};
     }
 }
@@ -204,16 +205,17 @@ void sif_eval(fmddm_ctx *ctx, fmddm_tree *t, const double *D, int64_t e, double 
     *KII = h[1];
 }
 
-static void gmres_workspace(fmddm_tree *t, int m)
+static void gmres_workspace(fmddm_tree *t, int m, int n2)
 {
-    const int n2 = (int)(2 * t->n), ldv = (n2 + 63) / 64 * 64;
+    const int ldv = (n2 + 63) / 64 * 64;
     SW s{m};
-    if (t->gm_restart != m || !t->gm_V.p) {
+    if (t->gm_restart != m || t->gm_len != n2 || !t->gm_V.p) {
         t->gm_V.alloc((size_t)(m + 1) * ldv);
         t->gm_w.alloc(ldv);
         t->gm_r.alloc(ldv);
         t->gm_sc.alloc(s.size());
         t->gm_restart = m;
+        t->gm_len = n2;
     }
     if (!t->gm_host) FM_HIP(hipHostMalloc((void **)&t->gm_host, 2 * sizeof(double), hipHostMallocDefault));
     if (!t->gm_ev) FM_HIP(hipEventCreateWithFlags(&t->gm_ev, hipEventDisableTiming));
@@ -231,10 +233,10 @@ void GmresRun::start(fmddm_ctx *c, fmddm_tree *tr, int md, const double *rhs, do
     j = it = restarts = 0;
     bnorm = relres = 0.0;
     converged = false;
-    gmres_workspace(t, ctx->prm.restart);
+    gmres_workspace(t, ctx->prm.restart, (int)vec_len(t, mode));
     SW s{ctx->prm.restart};
     hipStream_t st = ctx->stream;
-    const int n2 = (int)(2 * t->n);
+    const int n2 = (int)vec_len(t, mode);
     hipLaunchKernelGGL(k_norm, dim3(1), dim3(RT), 0, st, n2, b, t->gm_sc.p + s.nrm());
     FM_CHECK_LAUNCH();
     FM_HIP(hipMemcpyAsync(t->gm_host, t->gm_sc.p + s.nrm(), 8, hipMemcpyDeviceToHost, st));
@@ -247,7 +249,7 @@ void GmresRun::enqueue_residual()
 {
     SW s{ctx->prm.restart};
     hipStream_t st = ctx->stream;
-    const int n2 = (int)(2 * t->n);
+    const int n2 = (int)vec_len(t, mode);
     apply_mode(ctx, t, mode, x, t->gm_w.p);
     hipLaunchKernelGGL(k_residual, dim3(cdiv(n2, 256)), dim3(256), 0, st, n2, b, t->gm_w.p, t->gm_r.p);
     hipLaunchKernelGGL(k_norm, dim3(1), dim3(RT), 0, st, n2, t->gm_r.p, t->gm_sc.p + s.nrm());
@@ -263,7 +265,7 @@ void GmresRun::enqueue_step()
     const int m = ctx->prm.restart;
     SW s{m};
     hipStream_t st = ctx->stream;
-    const int n2 = (int)(2 * t->n), ldv = (n2 + 63) / 64 * 64, gb = cdiv(n2, 256);
+    const int n2 = (int)vec_len(t, mode), ldv = (n2 + 63) / 64 * 64, gb = cdiv(n2, 256);
     double *V = t->gm_V.p, *w = t->gm_w.p, *sc = t->gm_sc.p;
     double *vj = V + (size_t)j * ldv, *vn = V + (size_t)(j + 1) * ldv;
     apply_mode(ctx, t, mode, vj, w);
@@ -293,7 +295,7 @@ bool GmresRun::advance(bool block)
     const int m = ctx->prm.restart;
     SW s{m};
     hipStream_t st = ctx->stream;
-    const int n2 = (int)(2 * t->n), ldv = (n2 + 63) / 64 * 64, gb = cdiv(n2, 256);
+    const int n2 = (int)vec_len(t, mode), ldv = (n2 + 63) / 64 * 64, gb = cdiv(n2, 256);
     double *V = t->gm_V.p, *sc = t->gm_sc.p;
     const double *h = t->gm_host;
     switch (state) {

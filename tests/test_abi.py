@@ -35,9 +35,9 @@ def test_struct_layouts_match_header():
     compiler gives them (computed from the header by gcc)."""
     import subprocess
     import tempfile
-    src = '#include "fmddm.h"\n#include <stdio.h>\nint main(){printf("%zu %zu %zu %zu %zu\\n",' \
+    src = '#include "fmddm.h"\n#include <stdio.h>\nint main(){printf("%zu %zu %zu %zu %zu %zu\\n",' \
           'sizeof(fmddm_params),sizeof(fmddm_tree_info),sizeof(fmddm_solve_info),' \
-          'sizeof(fmddm_request),sizeof(fmddm_result));return 0;}\n'
+          'sizeof(fmddm_request),sizeof(fmddm_result),sizeof(fmddm_poro_params));return 0;}\n'
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "s.c")
         open(c, "w").write(src)
@@ -45,7 +45,7 @@ def test_struct_layouts_match_header():
         subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
         sizes = list(map(int, subprocess.check_output([exe]).split()))
     assert sizes == [C.sizeof(F.Params), C.sizeof(F.TreeInfo), C.sizeof(F.SolveInfo),
-                     C.sizeof(F.Request), C.sizeof(F.Result)]
+                     C.sizeof(F.Request), C.sizeof(F.Result), C.sizeof(F.PoroParams)]
 
 
 def test_default_params_and_validation_without_device():
@@ -81,6 +81,11 @@ def test_default_params_and_validation_without_device():
     assert lib.fmddm_server_release(None, 1) == F.FMDDM_EINVAL
     assert lib.fmddm_server_footprint(None, 100) == 0
     lib.fmddm_server_destroy(None)
+    assert lib.fmddm_poro_set(None, None) == F.FMDDM_EINVAL
+    assert lib.fmddm_poro_apply(None, None, 0, None, None) == F.FMDDM_EINVAL
+    assert lib.fmddm_add_history(None, None, 2, None, None) == F.FMDDM_EINVAL
+    assert lib.fmddm_poro_rhs(None, None, None, 0.0, 0.0, None) == F.FMDDM_EINVAL
+    assert lib.fmddm_poro_solve(None, None, None, None, None) == F.FMDDM_EINVAL
 
 
 def test_binding_refuses_host_tensors():

@@ -1,0 +1,136 @@
+"""GPU parity of the poroelastic path (Section 2, eqs. 2.1-2.5) against the
+oracle, through the C ABI.
+
+Both sides evaluate the same element integrals by their own quadrature,
+each converged to about 1e-12 relative (pinned for the oracle in
+test_oracle_poro), so products agree to 1e-10 of the largest entry of each
+response kind (tractions, pressure).  Time marching over several steps with
+GMRES at tolerance 1e-12 agrees with the oracle's Gaussian elimination to
+1e-8 relative.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1812_05087_amd as F  # noqa: E402
+
+MED = dict(E=20e9, nu=0.2, nuu=0.35, alpha=0.8, perm=1e-18, visc=1e-3)
+DT = 60.0
+P0 = 48.26e6
+
+
+def make(wl, **kw):
+    prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=MED["E"], nu=MED["nu"], **kw)
+    F.fmddm_poro_set(prob.ctx, MED["nuu"], MED["alpha"], MED["perm"], MED["visc"], DT, P0)
+    return prob
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float64)).cuda()
+
+
+def cmp(gpu, ref):
+    """max error per response kind, relative to that kind's largest entry"""
+    out = []
+    for k in range(3):
+        r = ref[k::3]
+        out.append(float(np.abs(gpu[k::3] - r).max() / max(np.abs(r).max(), 1e-300)))
+    return max(out)
+
+
+def geometries():
+    wl1 = W.well_cluster(n_frac=3, elems=20, half_length=2.0, spacing=1.0)
+    wl2 = W.random_fractures(41, n_frac=6, elems=9, box=6.0, lmin=0.5, lmax=2.0)
+    return [wl1, wl2]
+
+
+def test_poro_apply_matches_oracle():
+    po = O.Poro(**MED)
+    for wl in geometries():
+        prob = make(wl)
+        g = O.Geometry.of(wl)
+        rng = np.random.default_rng(7)
+        D = rng.standard_normal(3 * g.n) * np.tile([1e-3, 1e-3, 1e-9], g.n)
+        Dd = dev(D)
+        for lag in (0, 1, 4):
+            out = torch.zeros(3 * g.n, dtype=torch.float64, device="cuda")
+            F.fmddm_poro_apply(prob.ctx, prob.tree, lag, Dd, out)
+            ref = O.poro_matrix(g, po, DT, lag) @ D
+            e = cmp(out.cpu().numpy(), ref)
+            assert e <= 1e-10, (wl.name, lag, e)
+        prob.close()
+
+
+def test_history_matches_oracle():
+    po = O.Poro(**MED)
+    wl = geometries()[1]
+    g = O.Geometry.of(wl)
+    prob = make(wl)
+    rng = np.random.default_rng(11)
+    h = 6
+    Dh = [rng.standard_normal(3 * g.n) * np.tile([1e-3, 1e-3, 1e-9], g.n) for _ in range(h - 1)]
+    b = rng.standard_normal(3 * g.n) * 1e6
+    rhs = dev(b)
+    F.fmddm_add_history(prob.ctx, prob.tree, h, dev(np.concatenate(Dh)), rhs)
+    ref = b.copy()
+    for k in range(1, h):
+        ref -= O.poro_matrix(g, po, DT, h - k) @ Dh[k - 1]
+    got = rhs.cpu().numpy()
+    e = cmp(got - b, ref - b)
+    assert e <= 1e-10, e
+    # h = 1 leaves the right-hand side unchanged
+    r1 = dev(b)
+    F.fmddm_add_history(prob.ctx, prob.tree, 1, None, r1)
+    assert np.array_equal(r1.cpu().numpy(), b)
+    prob.close()
+
+
+def test_time_marching_matches_oracle():
+    po = O.Poro(**MED)
+    wl = W.well_cluster(n_frac=3, elems=12, half_length=2.0, spacing=1.0)
+    g = O.Geometry.of(wl)
+    steps = 5
+    ref, _, _ = O.poro_march(g, po, DT, steps, wl.pressure, P0, wl.SH, wl.Sh)
+    prob = make(wl, tol=1e-12, restart=60)
+    n3 = 3 * g.n
+    b0 = torch.zeros(n3, dtype=torch.float64, device="cuda")
+    F.fmddm_poro_rhs(prob.ctx, prob.tree, dev(wl.pressure), wl.SH, wl.Sh, b0)
+    assert cmp(b0.cpu().numpy(), O.poro_rhs(g, wl.pressure, P0, wl.SH, wl.Sh)) <= 1e-14
+    hist = torch.zeros(steps * n3, dtype=torch.float64, device="cuda")
+    D = torch.zeros(n3, dtype=torch.float64, device="cuda")
+    for h in range(1, steps + 1):
+        rhs = b0.clone()
+        F.fmddm_add_history(prob.ctx, prob.tree, h, hist[: (h - 1) * n3] if h > 1 else None, rhs)
+        st, info = F.fmddm_poro_solve(prob.ctx, prob.tree, rhs, D)
+        assert st == F.FMDDM_OK and info["converged"], info
+        hist[(h - 1) * n3: h * n3] = D
+        e = float(np.linalg.norm(D.cpu().numpy() - ref[h - 1]) / np.linalg.norm(ref[h - 1]))
+        assert e <= 1e-8, (h, e)
+    # the symmetric stack: no shear DD on the middle fracture
+    Dm = D.cpu().numpy().reshape(-1, 3)
+    assert np.abs(Dm[12:24, 0]).max() <= 1e-8 * np.abs(Dm[:, 1]).max()
+    prob.close()
+
+
+def test_poro_errors():
+    wl = geometries()[0]
+    prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=MED["E"], nu=MED["nu"])
+    n3 = 3 * prob.n
+    D = torch.zeros(n3, dtype=torch.float64, device="cuda")
+    out = torch.zeros(n3, dtype=torch.float64, device="cuda")
+    with pytest.raises(F.FmddmError):
+        F.fmddm_poro_apply(prob.ctx, prob.tree, 0, D, out)   # medium not set
+    with pytest.raises(F.FmddmError):
+        F.fmddm_poro_set(prob.ctx, 0.1, 0.8, 1e-18, 1e-3, 60.0)   # nu_u < nu
+    F.fmddm_poro_set(prob.ctx, 0.35, 0.8, 1e-18, 1e-3, 60.0)
+    with pytest.raises(F.FmddmError):
+        F.fmddm_poro_apply(prob.ctx, prob.tree, 0, D, D)     # aliasing
+    prob.close()
