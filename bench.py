@@ -184,6 +184,44 @@ def serving_leg(F, W, count, slots, load):
     }
 
 
+def history_leg(F, W, elems, steps):
+    """Poroelastic time marching on the horizontal-well cluster (5 fractures,
+    0.2 m elements, 10 m apart, Table 2 loads; Biot constants of the well
+    example, 60 s steps): one exact left-hand-side product and the history
+    sum of the last step, timed on the device."""
+    import torch
+    wl = W.well_cluster(n_frac=5, elems=elems, half_length=0.1 * elems, spacing=10.0)
+    prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=20e9, nu=0.2)
+    try:
+        F.fmddm_poro_set(prob.ctx, 0.35, 0.8, 1e-18, 1e-3, 60.0, 48.26e6)
+        n3 = 3 * prob.n
+        rng = np.random.default_rng(3)
+        scale = np.tile([1e-4, 1e-4, 1e-10], prob.n)
+        hist = torch.as_tensor(np.concatenate([rng.standard_normal(n3) * scale for _ in range(steps - 1)])).cuda()
+        D = hist[:n3].clone()
+        out = torch.zeros(n3, dtype=torch.float64, device="cuda")
+        F.fmddm_poro_apply(prob.ctx, prob.tree, 0, D, out)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F.fmddm_poro_apply(prob.ctx, prob.tree, 0, D, out)
+        torch.cuda.synchronize()
+        t_lhs = time.perf_counter() - t0
+        rhs = torch.zeros(n3, dtype=torch.float64, device="cuda")
+        t0 = time.perf_counter()
+        F.fmddm_add_history(prob.ctx, prob.tree, steps, hist, rhs)
+        torch.cuda.synchronize()
+        t_hist = time.perf_counter() - t0
+        n = prob.n
+        return {"workload": f"well cluster 5 x {elems} elements (N={n}), dt 60 s, history of step {steps}",
+                "n": n, "lhs_product_ms": t_lhs * 1e3, "history_ms": t_hist * 1e3,
+                "lags": steps - 1, "time_levels_evaluated": steps,
+                "lag_applications_per_s": (steps - 1) / t_hist,
+                "element_pair_terms_per_s": n * n * steps / t_hist,
+                "method": "exact element integrals on the fly (no multipole approximation)"}
+    finally:
+        prob.close()
+
+
 def cpu_baseline(wl, D, seconds):
     """The oracle's exact on-the-fly product of the whole workload on all
     host cores, repeated for about `seconds` of wall time."""
@@ -218,6 +256,10 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=48)
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-load", type=float, default=0.75)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only copy 256 MiB device-to-device 5 times (reference for HBM byte counters)")
+    ap.add_argument("--history-elems", type=int, default=400)
+    ap.add_argument("--history-steps", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs one instance per GPU and has no "
@@ -230,6 +272,15 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        nbytes = 256 << 20
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "launches": 5}), flush=True)
+        return
     wl = W.c2()
     n = wl.n
     t0 = time.perf_counter()
@@ -337,6 +388,8 @@ def main():
     prob.close()
     if args.serve_requests > 0:
         line["serving"] = serving_leg(F, W, args.serve_requests, args.serve_slots, args.serve_load)
+    if args.history_elems > 0:
+        line["history"] = history_leg(F, W, args.history_elems, args.history_steps)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, Dh, args.cpu_seconds)
     print(json.dumps(line), flush=True)

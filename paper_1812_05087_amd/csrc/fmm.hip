@@ -503,16 +503,19 @@ __global__ void k_transpose_ops(int nop, int rp, double scale, const double *__r
 }
 
 // ------------------------------------------------------------ L2P
-// Far-field stress at every midpoint, eqs. 3.10-3.11 in one step: the
+// Far-field stress at every midpoint, eqs. 3.9-3.11 in one step: the
 // chain of parent-to-child interpolations of the downward pass followed by
 // the interpolation at the point is the evaluation of each ancestor's M2L
 // field (a polynomial on that ancestor's square) at the point, so the
 // fields of the leaf and of all its ancestors at level >= 2 are summed
-// there directly.  One block per leaf: an ancestor's field sits in LDS
-// (double-buffered: the next one is fetched while the current one is
-// contracted), the barycentric interpolants of up to 32 points are formed,
-// and tasks (point, component, quarter of the x rows) contract
-// sum_l Sx[l] sum_m G[c][l][m] Sy[m]; quarters combine in a fixed order.
+// there directly.  One block per leaf and chunk of up to 32 points; an
+// ancestor's field G sits in LDS (double-buffered: the next one is fetched
+// while the current one is used).  For each ancestor the barycentric
+// interpolants Sx, Sy of the points are formed, the product
+// R[(c,l)][t] = sum_m G[c][l][m] Sy[t][m] runs on FP64 MFMA (rows (c,l)
+// in 16-row tiles, one per wave, points in two 16-column tiles, m in
+// k-steps of 4), and sigma_c(t) += sum_l Sx[t][l] R[(c,l)][t] is summed
+// in l order.
 constexpr int LT = 256, LTM = 32;
 
 template <int P>
@@ -526,70 +529,97 @@ __global__ __launch_bounds__(LT) void k_l2p(int nleaf, const int *__restrict__ l
                                             double *__restrict__ far_s)
 {
     constexpr int P2 = P * P, N3 = 3 * P2, NPF = (N3 + LT - 1) / LT;
-    constexpr int LQ = (P + 3) / 4;  // x rows per quarter
+    constexpr int RT = (3 * P + 15) / 16;  // 16-row tiles over (c, l)
+    constexpr int KS = (P + 3) / 4;        // k-steps over m
     __shared__ double Gb[2][N3];
     __shared__ double Sx[LTM][P + 1], Sy[LTM][P + 1];
+    __shared__ double Rb[16 * RT][LTM + 1];
     __shared__ double s_xb[P], s_bw[P];
+    constexpr int MAXA = 32;  // ancestors kept in LDS (tree depth is at most 31)
+    __shared__ int s_anc[MAXA];
+    __shared__ double s_acx[MAXA], s_acy[MAXA], s_aih[MAXA];
     int li = xcd_remap(blockIdx.x, nleaf);
     int c = leaves[li];
-    int tid = threadIdx.x;
+    int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     int tb = pbeg[c], te = pend[c];
-    int a0 = aoff[li], na = aoff[li + 1] - a0;
+    int a0 = aoff[li], na = min(aoff[li + 1] - a0, MAXA);
     if (tid < P) {
         s_xb[tid] = xbar[tid];
         s_bw[tid] = bw[tid];
     }
+    // the ancestors and their squares, read once
+    if (tid < na) {
+        int A = aidx[a0 + tid];
+        s_anc[tid] = A;
+        s_acx[tid] = ccx[A];
+        s_acy[tid] = ccy[A];
+        s_aih[tid] = 1.0 / chw[A];
+    }
+    __syncthreads();
     for (int t0 = tb; t0 < te; t0 += LTM) {
         int ntp = min(LTM, te - t0);
-        double acc[2] = {0.0, 0.0};
+        double acc = 0.0;  // task tid < 3 * LTM: point tid % 32, component tid / 32
         double pf[NPF];
-        // first ancestor's field
         __syncthreads();
         if (na > 0) {
-            const double *G0 = G + (size_t)aidx[a0] * Mp;
+            const double *G0 = G + (size_t)s_anc[0] * Mp;
             for (int e = tid; e < N3; e += LT) Gb[0][e] = G0[e];
         }
         for (int k = 0; k < na; ++k) {
-            int A = aidx[a0 + k];
-            // fetch the next ancestor's field into registers
             if (k + 1 < na) {
-                const double *Gn = G + (size_t)aidx[a0 + k + 1] * Mp;
+                const double *Gn = G + (size_t)s_anc[k + 1] * Mp;
 #pragma unroll
                 for (int r = 0; r < NPF; ++r) {
                     int e = tid + r * LT;
                     if (e < N3) pf[r] = Gn[e];
                 }
             }
-            if (tid < 2 * ntp) {
+            if (tid < 2 * LTM) {
                 int t = tid >> 1, coord = tid & 1;
-                double ih = 1.0 / chw[A];
-                double u = coord ? (cy[t0 + t] - ccy[A]) * ih : (cx[t0 + t] - ccx[A]) * ih;
-                double S[P];
-                bary<P>(s_xb, s_bw, u, S);
                 double *dst = coord ? Sy[t] : Sx[t];
+                if (t < ntp) {
+                    double ih = s_aih[k];
+                    double u = coord ? (cy[t0 + t] - s_acy[k]) * ih : (cx[t0 + t] - s_acx[k]) * ih;
+                    double S[P];
+                    bary<P>(s_xb, s_bw, u, S);
 #pragma unroll
-                for (int m = 0; m < P; ++m) dst[m] = S[m];
+                    for (int m = 0; m < P; ++m) dst[m] = S[m];
+                } else {
+#pragma unroll
+                    for (int m = 0; m < P; ++m) dst[m] = 0.0;
+                }
             }
             __syncthreads();
             const double *Gc = Gb[k & 1];
+            for (int mt = wave; mt < RT; mt += 4) {
+                d4 r0 = {0.0, 0.0, 0.0, 0.0}, r1 = {0.0, 0.0, 0.0, 0.0};
+                int row = 16 * mt + (lane & 15);
 #pragma unroll
-            for (int r = 0; r < 2; ++r) {
-                int task = tid + r * LT;  // (point, component, quarter), quarter fastest
-                int t = task / 12, rem = task - 12 * t, comp = rem >> 2, quarter = rem & 3;
-                if (t < ntp) {
-                    double sum = 0.0;
-#pragma unroll
-                    for (int j = 0; j < LQ; ++j) {
-                        int l = quarter * LQ + j;
-                        if (l < P) {
-                            double rr = 0.0;
-#pragma unroll
-                            for (int m = 0; m < P; ++m) rr += Gc[comp * P2 + l * P + m] * Sy[t][m];
-                            sum += Sx[t][l] * rr;
-                        }
-                    }
-                    acc[r] += sum;
+                for (int s = 0; s < KS; ++s) {
+                    int m = 4 * s + (lane >> 4);
+                    double av = (row < 3 * P && m < P) ? Gc[row * P + m] : 0.0;
+                    double b0 = m < P ? Sy[lane & 15][m] : 0.0;
+                    double b1 = m < P ? Sy[16 + (lane & 15)][m] : 0.0;
+                    r0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, r0, 0, 0, 0);
+                    r1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, r1, 0, 0, 0);
                 }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    int rw = 16 * mt + 4 * r + (lane >> 4);
+                    if (rw < 3 * P) {
+                        int l = rw % P, t = lane & 15;
+                        Rb[rw][t] = r0[r] * Sx[t][l];
+                        Rb[rw][t + 16] = r1[r] * Sx[t + 16][l];
+                    }
+                }
+            }
+            __syncthreads();
+            if (tid < 3 * LTM) {
+                int t = tid & 31, comp = tid >> 5;
+                double sum = 0.0;
+#pragma unroll
+                for (int l = 0; l < P; ++l) sum += Rb[comp * P + l][t];
+                acc += sum;
             }
             if (k + 1 < na) {
 #pragma unroll
@@ -600,14 +630,9 @@ __global__ __launch_bounds__(LT) void k_l2p(int nleaf, const int *__restrict__ l
             }
             __syncthreads();
         }
-        // combine the quarters (4 adjacent lanes) in a fixed order
-#pragma unroll
-        for (int r = 0; r < 2; ++r) {
-            acc[r] += __shfl_xor(acc[r], 1);
-            acc[r] += __shfl_xor(acc[r], 2);
-            int task = tid + r * LT;
-            int t = task / 12, rem = task - 12 * t, comp = rem >> 2, quarter = rem & 3;
-            if (t < ntp && quarter == 0) far_s[3 * (size_t)(t0 + t) + comp] = acc[r];
+        if (tid < 3 * LTM) {
+            int t = tid & 31, comp = tid >> 5;
+            if (t < ntp) far_s[3 * (size_t)(t0 + t) + comp] = acc;
         }
     }
 }
