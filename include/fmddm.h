@@ -229,9 +229,11 @@ fmddm_status fmddm_profile_read(fmddm_ctx *ctx, double *ms, int64_t *count);
  * system of step h is
  *     K_0 D^h = b_h - sum_{k=1}^{h-1} K_{h-k} D^k,
  * K_0 = F(dt), K_m = F((m+1) dt) - F(m dt), F(t) the response at time t to
- * unit sources switched on at 0 and held.  All products here evaluate the
- * element integrals exactly (no multipole approximation); their cost is
- * proportional to n^2 times the number of time levels.
+ * unit sources switched on at 0 and held.  With mode FMDDM_APPLY_DIRECT the
+ * products evaluate every element integral exactly (cost n^2 per time
+ * level); with FMDDM_APPLY_FMM the far field goes through the black-box
+ * FMM of Section 3 with the time-dependent kernel (operators per tree
+ * level and time level, built on first use and kept with the tree).
  * ------------------------------------------------------------------------ */
 typedef struct {
     double nu_u;              /* undrained Poisson ratio, nu < nu_u < 0.5 */
@@ -239,6 +241,10 @@ typedef struct {
     double perm, visc;        /* permeability (m^2) and fluid viscosity (Pa s) */
     double dt;                /* time step (s) */
     double p0;                /* initial pore pressure (Pa), for fmddm_poro_rhs */
+    int32_t mode;             /* FMDDM_APPLY_DIRECT: exact element integrals for every pair;
+                                 FMDDM_APPLY_FMM: the same for neighbouring elements and
+                                 Chebyshev multipoles (the context's p, 2..16) for well-separated
+                                 cells, the time levels contracted in one M2L product */
 } fmddm_poro_params;
 
 /* Attaches the poroelastic medium to the context (validated: EINVAL). */

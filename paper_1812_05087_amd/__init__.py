@@ -82,7 +82,7 @@ class Result(C.Structure):
 
 class PoroParams(C.Structure):
     _fields_ = [("nu_u", C.c_double), ("alpha", C.c_double), ("perm", C.c_double), ("visc", C.c_double),
-                ("dt", C.c_double), ("p0", C.c_double)]
+                ("dt", C.c_double), ("p0", C.c_double), ("mode", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -405,8 +405,9 @@ def fmddm_trim_cache() -> int:
 
 
 # ------------------------------------------------------------ poroelastic
-def fmddm_poro_set(ctx, nu_u, alpha, perm, visc, dt, p0=0.0):
-    pp = PoroParams(float(nu_u), float(alpha), float(perm), float(visc), float(dt), float(p0))
+def fmddm_poro_set(ctx, nu_u, alpha, perm, visc, dt, p0=0.0, mode=1):
+    """mode: FMDDM_APPLY_DIRECT (1, exact) or FMDDM_APPLY_FMM (0)."""
+    pp = PoroParams(float(nu_u), float(alpha), float(perm), float(visc), float(dt), float(p0), int(mode))
     _check(lib().fmddm_poro_set(ctx, C.byref(pp)), ctx)
 
 

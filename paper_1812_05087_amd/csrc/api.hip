@@ -261,9 +261,15 @@ fmddm_status fmddm_poro_set(fmddm_ctx *ctx, const fmddm_poro_params *pp)
     if (!ctx || !pp) return FMDDM_EINVAL;
     const double nu = ctx->prm.nu;
     if (!(pp->nu_u > nu && pp->nu_u < 0.5) || !(pp->alpha > 0.0 && pp->alpha <= 1.0) || !(pp->perm > 0.0) ||
-        !(pp->visc > 0.0) || !(pp->dt > 0.0) || !std::isfinite(pp->p0)) {
-        ctx->err = "poroelastic parameters: need nu < nu_u < 0.5, 0 < alpha <= 1, perm, visc, dt > 0";
+        !(pp->visc > 0.0) || !(pp->dt > 0.0) || !std::isfinite(pp->p0) ||
+        (pp->mode != FMDDM_APPLY_DIRECT && pp->mode != FMDDM_APPLY_FMM)) {
+        ctx->err = "poroelastic parameters: need nu < nu_u < 0.5, 0 < alpha <= 1, perm, visc, dt > 0, "
+                   "mode DIRECT or FMM";
         return FMDDM_EINVAL;
+    }
+    if (pp->mode == FMDDM_APPLY_FMM && (ctx->prm.p < 2 || ctx->prm.p > 16)) {
+        ctx->err = "poroelastic FMM needs 2 <= p <= 16";
+        return FMDDM_EUNSUPPORTED;
     }
     ctx->poro = *pp;
     ctx->poro_set = 1;

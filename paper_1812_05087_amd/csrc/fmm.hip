@@ -191,14 +191,19 @@ constexpr int XT = 256;
 // leaves per work item: 4, or 2 where 4 would not fit in LDS
 __host__ __device__ constexpr int m2m_slots(int p) { return p <= 24 ? 4 : 2; }
 
-template <int P>
+// NC components per cell (3 stress charges; 4 with a fluid source).  Cell
+// k's weights for term blockIdx.y are at W + k ldw + blockIdx.y tstride,
+// item partials at part + item ldw + blockIdx.y tstride.
+template <int P, int NC>
 __global__ __launch_bounds__(XT) void k_m2m(int nitem, const int *__restrict__ it_anc,
                                             const int *__restrict__ it_leaf, const double *__restrict__ ccx,
                                             const double *__restrict__ ccy, const double *__restrict__ chw,
                                             const double *__restrict__ xbar, const double *__restrict__ bw, int Mp,
-                                            const double *__restrict__ W, double *__restrict__ part)
+                                            int tstride, const double *__restrict__ W, double *__restrict__ part)
 {
-    constexpr int P2 = P * P, N3 = 3 * P2, NS = m2m_slots(P);
+    constexpr int P2 = P * P, N3 = NC * P2, NS = m2m_slots(P);
+    W += (size_t)blockIdx.y * tstride;
+    part += (size_t)blockIdx.y * tstride;
     constexpr int UO = P <= 20 ? P : 4;  // outer unroll: bounds the live operator values
     __shared__ double buf[NS * N3];
     __shared__ double Tx[NS][P2], Ty[NS][P2];  // [leaf slot][l * P + l']
@@ -245,8 +250,8 @@ __global__ __launch_bounds__(XT) void k_m2m(int nitem, const int *__restrict__ i
     }
     __syncthreads();
     // x pass: task (slot d, component, column m2): column <- Tx_d . column
-    for (int q = tid; q < 3 * NS * P; q += XT) {
-        int d = q / (3 * P), r = q - d * 3 * P, comp = r / P, m2 = r - comp * P;
+    for (int q = tid; q < NC * NS * P; q += XT) {
+        int d = q / (NC * P), r = q - d * NC * P, comp = r / P, m2 = r - comp * P;
         double *col = buf + d * N3 + comp * P2 + m2;
         const double *T = Tx[d];
         double u[P];
@@ -262,8 +267,8 @@ __global__ __launch_bounds__(XT) void k_m2m(int nitem, const int *__restrict__ i
     }
     __syncthreads();
     // y pass: task (slot d, component, row l): row <- row . Ty_d^T
-    for (int q = tid; q < 3 * NS * P; q += XT) {
-        int d = q / (3 * P), r = q - d * 3 * P, comp = r / P, l = r - comp * P;
+    for (int q = tid; q < NC * NS * P; q += XT) {
+        int d = q / (NC * P), r = q - d * NC * P, comp = r / P, l = r - comp * P;
         double *row = buf + d * N3 + comp * P2 + l * P;
         const double *T = Ty[d];
         double u[P];
@@ -289,8 +294,10 @@ __global__ __launch_bounds__(XT) void k_m2m(int nitem, const int *__restrict__ i
 // W_A = sum of A's item partials, in item order.
 __global__ __launch_bounds__(256) void k_m2m_sum(int nanc, const int *__restrict__ anc,
                                                  const int *__restrict__ ioff, const double *__restrict__ part,
-                                                 int n3, int Mp, double *__restrict__ W)
+                                                 int n3, int Mp, int tstride, double *__restrict__ W)
 {
+    part += (size_t)blockIdx.y * tstride;
+    W += (size_t)blockIdx.y * tstride;
     constexpr int U = 8;  // loads in flight per thread; the sum stays in item order
     int i = xcd_remap(blockIdx.x, nanc);
     int A = anc[i], kb = ioff[i], ke = ioff[i + 1];
@@ -518,7 +525,9 @@ __global__ void k_transpose_ops(int nop, int rp, double scale, const double *__r
 // in l order.
 constexpr int LT = 256, LTM = 32;
 
-template <int P>
+// NC field components per cell (rows of G, stride Mp); far_s gets NC
+// values per point.
+template <int P, int NC>
 __global__ __launch_bounds__(LT) void k_l2p(int nleaf, const int *__restrict__ leaves,
                                             const int *__restrict__ pbeg, const int *__restrict__ pend,
                                             const int *__restrict__ aoff, const int *__restrict__ aidx,
@@ -528,8 +537,8 @@ __global__ __launch_bounds__(LT) void k_l2p(int nleaf, const int *__restrict__ l
                                             const double *__restrict__ xbar, const double *__restrict__ bw,
                                             double *__restrict__ far_s)
 {
-    constexpr int P2 = P * P, N3 = 3 * P2, NPF = (N3 + LT - 1) / LT;
-    constexpr int RT = (3 * P + 15) / 16;  // 16-row tiles over (c, l)
+    constexpr int P2 = P * P, N3 = NC * P2, NPF = (N3 + LT - 1) / LT;
+    constexpr int RT = (NC * P + 15) / 16;  // 16-row tiles over (c, l)
     constexpr int KS = (P + 3) / 4;        // k-steps over m
     __shared__ double Gb[2][N3];
     __shared__ double Sx[LTM][P + 1], Sy[LTM][P + 1];
@@ -558,7 +567,7 @@ __global__ __launch_bounds__(LT) void k_l2p(int nleaf, const int *__restrict__ l
     __syncthreads();
     for (int t0 = tb; t0 < te; t0 += LTM) {
         int ntp = min(LTM, te - t0);
-        double acc = 0.0;  // task tid < 3 * LTM: point tid % 32, component tid / 32
+        double acc = 0.0;  // task tid < NC * LTM: point tid % 32, component tid / 32
         double pf[NPF];
         __syncthreads();
         if (na > 0) {
@@ -597,7 +606,7 @@ __global__ __launch_bounds__(LT) void k_l2p(int nleaf, const int *__restrict__ l
 #pragma unroll
                 for (int s = 0; s < KS; ++s) {
                     int m = 4 * s + (lane >> 4);
-                    double av = (row < 3 * P && m < P) ? Gc[row * P + m] : 0.0;
+                    double av = (row < NC * P && m < P) ? Gc[row * P + m] : 0.0;
                     double b0 = m < P ? Sy[lane & 15][m] : 0.0;
                     double b1 = m < P ? Sy[16 + (lane & 15)][m] : 0.0;
                     r0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, r0, 0, 0, 0);
@@ -606,7 +615,7 @@ __global__ __launch_bounds__(LT) void k_l2p(int nleaf, const int *__restrict__ l
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     int rw = 16 * mt + 4 * r + (lane >> 4);
-                    if (rw < 3 * P) {
+                    if (rw < NC * P) {
                         int l = rw % P, t = lane & 15;
                         Rb[rw][t] = r0[r] * Sx[t][l];
                         Rb[rw][t + 16] = r1[r] * Sx[t + 16][l];
@@ -614,7 +623,7 @@ __global__ __launch_bounds__(LT) void k_l2p(int nleaf, const int *__restrict__ l
                 }
             }
             __syncthreads();
-            if (tid < 3 * LTM) {
+            if (tid < NC * LTM) {
                 int t = tid & 31, comp = tid >> 5;
                 double sum = 0.0;
 #pragma unroll
@@ -630,9 +639,9 @@ __global__ __launch_bounds__(LT) void k_l2p(int nleaf, const int *__restrict__ l
             }
             __syncthreads();
         }
-        if (tid < 3 * LTM) {
+        if (tid < NC * LTM) {
             int t = tid & 31, comp = tid >> 5;
-            if (t < ntp) far_s[3 * (size_t)(t0 + t) + comp] = acc;
+            if (t < ntp) far_s[NC * (size_t)(t0 + t) + comp] = acc;
         }
     }
 }
@@ -747,21 +756,6 @@ __global__ void k_final(int n, const int *__restrict__ tleaf, const int *__restr
 // ------------------------------------------------------- host helpers
 
 
-int offset_slot(int dx, int dy) { return (dx + 3) + 7 * (dy + 3); }
-
-// Offsets (dx, dy) in [-3, 3]^2 outside [-1, 1]^2: the 40 relative
-// positions of a V-list cell.
-void v_offsets(std::vector<int> &dx, std::vector<int> &dy, std::vector<int> &slot2op)
-{
-    slot2op.assign(49, -1);
-    for (int y = -3; y <= 3; ++y)
-        for (int x = -3; x <= 3; ++x) {
-            if (std::abs(x) <= 1 && std::abs(y) <= 1) continue;
-            slot2op[offset_slot(x, y)] = (int)dx.size();
-            dx.push_back(x);
-            dy.push_back(y);
-        }
-}
 
 constexpr int TILE_N = 32;  // pairs per GEMM tile (the BN of the launches)
 constexpr int KSPLIT = 4;   // split-K factor of the projection onto the singular vectors
@@ -791,21 +785,22 @@ void launch_ggemm(hipStream_t s, int ntile, int Mrows, const double *ops, size_t
     FM_CHECK_LAUNCH();
 }
 
-template <int P>
-void launch_m2m(hipStream_t s, fmddm_ctx *ctx, fmddm_tree *t, int Mp)
+template <int P, int NC = 3>
+void launch_m2m(hipStream_t s, fmddm_ctx *ctx, fmddm_tree *t, int ldw, int nterm, int tstride, const double *W,
+                double *part)
 {
-    hipLaunchKernelGGL((k_m2m<P>), dim3(t->nuitem), dim3(XT), 0, s, t->nuitem, t->uit_anc.p, t->uit_leaf.p,
-                       t->ccx.p, t->ccy.p, t->chw.p, ctx->cheb->xbar.p, ctx->cheb->bw.p, Mp, t->Wexp.p,
-                       t->upart.p);
+    hipLaunchKernelGGL((k_m2m<P, NC>), dim3(t->nuitem, nterm), dim3(XT), 0, s, t->nuitem, t->uit_anc.p,
+                       t->uit_leaf.p, t->ccx.p, t->ccy.p, t->chw.p, ctx->cheb->xbar.p, ctx->cheb->bw.p, ldw, tstride,
+                       W, part);
     FM_CHECK_LAUNCH();
 }
 
-template <int P>
-void launch_l2p(hipStream_t s, fmddm_ctx *ctx, fmddm_tree *t, int Mp)
+template <int P, int NC = 3>
+void launch_l2p(hipStream_t s, fmddm_ctx *ctx, fmddm_tree *t, const double *G, int ldg, double *far)
 {
-    hipLaunchKernelGGL((k_l2p<P>), dim3(t->nleaf), dim3(LT), 0, s, t->nleaf, t->dleaves.p, t->cpbeg.p,
-                       t->cpend.p, t->aoff.p, t->aidx.p, t->ccx.p, t->ccy.p, t->chw.p, t->scx.p, t->scy.p, t->Gexp.p,
-                       Mp, ctx->cheb->xbar.p, ctx->cheb->bw.p, t->far_s.p);
+    hipLaunchKernelGGL((k_l2p<P, NC>), dim3(t->nleaf), dim3(LT), 0, s, t->nleaf, t->dleaves.p, t->cpbeg.p,
+                       t->cpend.p, t->aoff.p, t->aidx.p, t->ccx.p, t->ccy.p, t->chw.p, t->scx.p, t->scy.p, G, ldg,
+                       ctx->cheb->xbar.p, ctx->cheb->bw.p, far);
     FM_CHECK_LAUNCH();
 }
 
@@ -825,7 +820,34 @@ void launch_l2p(hipStream_t s, fmddm_ctx *ctx, fmddm_tree *t, int Mp)
     default: throw Error{FMDDM_EINVAL, "p out of range"};                               \
     }
 
+// p of the four-component (poroelastic) passes
+#define FM_DISPATCH_P16(p, CALL)                                                        \
+    switch (p) {                                                                        \
+    case 2: CALL(2); break;   case 3: CALL(3); break;   case 4: CALL(4); break;        \
+    case 5: CALL(5); break;   case 6: CALL(6); break;   case 7: CALL(7); break;        \
+    case 8: CALL(8); break;   case 9: CALL(9); break;   case 10: CALL(10); break;      \
+    case 11: CALL(11); break; case 12: CALL(12); break; case 13: CALL(13); break;      \
+    case 14: CALL(14); break; case 15: CALL(15); break; case 16: CALL(16); break;      \
+    default: throw Error{FMDDM_EUNSUPPORTED, "four-component FMM needs 2 <= p <= 16"};  \
+    }
+
 }  // namespace
+
+int offset_slot(int dx, int dy) { return (dx + 3) + 7 * (dy + 3); }
+
+// Offsets (dx, dy) in [-3, 3]^2 outside [-1, 1]^2: the 40 relative
+// positions of a V-list cell.
+void v_offsets(std::vector<int> &dx, std::vector<int> &dy, std::vector<int> &slot2op)
+{
+    slot2op.assign(49, -1);
+    for (int y = -3; y <= 3; ++y)
+        for (int x = -3; x <= 3; ++x) {
+            if (std::abs(x) <= 1 && std::abs(y) <= 1) continue;
+            slot2op[offset_slot(x, y)] = (int)dx.size();
+            dx.push_back(x);
+            dy.push_back(y);
+        }
+}
 
 // Gauss-Legendre nodes/weights on [-1, 1] (Newton on the Legendre
 // recurrence).
@@ -920,6 +942,47 @@ void Profiler::read(hipStream_t s, double *ms, int64_t *count)
 }
 
 // ------------------------------------------------------------- set-up
+// ------------------------------------------------ generic passes
+// The passes of the product above for fields with four components per node
+// (three eigenstrain charges and a fluid source), several terms at once:
+// weights of cell k and term j at W + k ldw + j tstride.
+void fmm_m2m4(fmddm_ctx *ctx, fmddm_tree *t, int nterm, int ldw, int tstride, double *W, double *part)
+{
+    if (t->nuitem == 0) return;
+    hipStream_t s = ctx->stream;
+    int p = ctx->prm.p;
+#define FM_M2M4(PP) launch_m2m<PP, 4>(s, ctx, t, ldw, nterm, tstride, W, part)
+    FM_DISPATCH_P16(p, FM_M2M4)
+#undef FM_M2M4
+    hipLaunchKernelGGL(k_m2m_sum, dim3(t->nuanc, nterm), dim3(256), 0, s, t->nuanc, t->uanc.p, t->uioff.p, part,
+                       4 * p * p, ldw, tstride, W);
+    FM_CHECK_LAUNCH();
+}
+
+void fmm_l2p4(fmddm_ctx *ctx, fmddm_tree *t, const double *G, int ldg, double *far)
+{
+    hipStream_t s = ctx->stream;
+#define FM_L2P4(PP) launch_l2p<PP, 4>(s, ctx, t, G, ldg, far)
+    FM_DISPATCH_P16(ctx->prm.p, FM_L2P4)
+#undef FM_L2P4
+}
+
+void fmm_pair_gemm(hipStream_t s, int ntile, int Mrows, const double *ops, size_t op_stride, int lda, int Kd,
+                   const double *X, int ldx, const int *tile_op, const int *tile_beg, const int *tile_end,
+                   const int *psrc, const int *pdst, double *Z, int ldz)
+{
+    launch_ggemm<64, 32>(s, ntile, Mrows, ops, op_stride, lda, Kd, X, ldx, tile_op, tile_beg, tile_end, psrc, pdst,
+                         nullptr, Z, ldz);
+}
+
+void fmm_sum_pairs(hipStream_t s, fmddm_tree *t, const double *Z, int ldz, int width, double *out, int ldo)
+{
+    if (t->nfar == 0) return;
+    hipLaunchKernelGGL(k_sum_pairs, dim3(t->nfar), dim3(256), 0, s, t->nfar, t->far_cells.p, t->loff[1].p, Z, ldz,
+                       width, out, ldo);
+    FM_CHECK_LAUNCH();
+}
+
 // The side stream and the fork/join events of a context (default priority).
 void init_streams(fmddm_ctx *ctx)
 {
@@ -1224,13 +1287,13 @@ void fmm_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out)
         P.end(FMDDM_PH_P2M, s, e0);
         if (t->nuitem > 0) {
             P.begin(FMDDM_PH_M2M, s, e0);
-#define FM_M2M(PP) launch_m2m<PP>(s, ctx, t, Mp)
+#define FM_M2M(PP) launch_m2m<PP>(s, ctx, t, Mp, 1, 0, t->Wexp.p, t->upart.p)
             FM_DISPATCH_P(p, FM_M2M)
 #undef FM_M2M
             P.end(FMDDM_PH_M2M, s, e0);
             P.begin(FMDDM_PH_M2M_SUM, s, e0);
             hipLaunchKernelGGL(k_m2m_sum, dim3(t->nuanc), dim3(256), 0, s, t->nuanc, t->uanc.p, t->uioff.p,
-                               t->upart.p, 3 * p * p, Mp, t->Wexp.p);
+                               t->upart.p, 3 * p * p, Mp, 0, t->Wexp.p);
             FM_CHECK_LAUNCH();
             P.end(FMDDM_PH_M2M_SUM, s, e0);
         }
@@ -1278,7 +1341,7 @@ void fmm_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out)
             P.end(FMDDM_PH_M2L_SUM, s, e0);
         }
         P.begin(FMDDM_PH_L2P, s, e0);
-#define FM_L2P(PP) launch_l2p<PP>(s, ctx, t, Mp)
+#define FM_L2P(PP) launch_l2p<PP>(s, ctx, t, t->Gexp.p, Mp, t->far_s.p)
         FM_DISPATCH_P(p, FM_L2P)
 #undef FM_L2P
         P.end(FMDDM_PH_L2P, s, e0);

@@ -197,6 +197,14 @@ struct fmddm_tree {
     int64_t gm_len = 0;
     // poroelastic workspace: chunk partials, term times, term vectors
     fmddm::DBuf<double> poro_part, poro_times, poro_E;
+    // poroelastic FMM: V pairs grouped by (level, offset) "combos", tiles of
+    // pairs sharing a combo, operators for time levels dt .. H dt
+    int pf_ready = 0, pf_ncombo = 0, pf_ntile = 0, pf_H = 0, pf_p = 0, pf_Mq = 0;
+    double pf_dt = 0.0;
+    std::vector<int> pf_h_combo_lvl, pf_h_combo_ox, pf_h_combo_oy;
+    fmddm::DBuf<int> pf_tile_op, pf_tile_beg, pf_tile_end, pf_psrc, pf_pdst, pf_combo_lvl, pf_combo_ox,
+        pf_combo_oy;
+    fmddm::DBuf<double> pf_ops, pf_W, pf_part, pf_Z, pf_G, pf_far, pf_Q, pf_D3, pf_near, pf_D2, pf_o2;
     double *gm_host = nullptr;
     hipEvent_t gm_ev = nullptr;
     int64_t bytes = 0;
@@ -217,6 +225,14 @@ void gauss_legendre(int n, std::vector<double> &t, std::vector<double> &w);
 void init_streams(fmddm_ctx *ctx);
 void setup_cheb(fmddm_ctx *ctx);
 void build_m2l_ops(fmddm_ctx *ctx);
+void v_offsets(std::vector<int> &dx, std::vector<int> &dy, std::vector<int> &slot2op);
+int offset_slot(int x, int y);
+void fmm_m2m4(fmddm_ctx *ctx, fmddm_tree *t, int nterm, int ldw, int tstride, double *W, double *part);
+void fmm_l2p4(fmddm_ctx *ctx, fmddm_tree *t, const double *G, int ldg, double *far);
+void fmm_pair_gemm(hipStream_t s, int ntile, int Mrows, const double *ops, size_t op_stride, int lda, int Kd,
+                   const double *X, int ldx, const int *tile_op, const int *tile_beg, const int *tile_end,
+                   const int *psrc, const int *pdst, double *Z, int ldz);
+void fmm_sum_pairs(hipStream_t s, fmddm_tree *t, const double *Z, int ldz, int width, double *out, int ldo);
 void setup_fmm(fmddm_ctx *ctx, fmddm_tree *t);
 void fmm_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out);
 // direct.hip

@@ -294,6 +294,186 @@ __global__ void k_poro_rhs(int n, const double *__restrict__ cb, const double *_
     rhs[3 * i + 2] = pf[i] - p0;
 }
 
+// ------------------------------------------------ multipole form (FMM)
+// Far field of well-separated cells by the black-box FMM of Section 3 with
+// the transient kernel: four charges per node (q0, q1, q2, q_f) and four
+// responses (sxx, syy, sxy, p).  The kernel is not homogeneous, so the M2L
+// operators are formed per (tree level, offset) and per time level; the
+// operators of all time levels of a (level, offset) are stored side by
+// side, so one product contracts over the time levels and the interaction
+// list together (the weights of a cell for all time levels are contiguous).
+
+// operator entry block: target node tn, source node sn, time level j of
+// combo c; rows (component_out, tn), columns (j, component_in, sn)
+__global__ void k_pops(int ncombo, const int *__restrict__ clvl, const int *__restrict__ cox,
+                       const int *__restrict__ coy, double rootL, const double *__restrict__ xbar, int p, int H,
+                       double dt, int Mq, PoroK K, double *__restrict__ ops)
+{
+    int p2 = p * p;
+    int64_t per = (int64_t)p2 * p2 * H;
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= per * ncombo) return;
+    int c = (int)(g / per);
+    int64_t r = g - (int64_t)c * per;
+    int j = (int)(r / ((int64_t)p2 * p2));
+    int rr = (int)(r - (int64_t)j * p2 * p2);
+    int tn = rr / p2, sn = rr - tn * p2;
+    double hw = rootL / (double)(2LL << clvl[c]);  // half-width of a cell of that level
+    double X = hw * xbar[tn / p], Y = hw * xbar[tn % p];
+    double sx = hw * (2.0 * cox[c] + xbar[sn / p]), sy = hw * (2.0 * coy[c] + xbar[sn % p]);
+    double t = (j + 1) * dt;
+    const size_t ld = (size_t)H * Mq;
+    double *op = ops + (size_t)c * Mq * ld;
+    for (int ci = 0; ci < 4; ++ci) {
+        double q[3] = {ci == 0 ? 1.0 : 0.0, ci == 1 ? 1.0 : 0.0, ci == 2 ? 1.0 : 0.0};
+        double o[4];
+        transient(K, X - sx, Y - sy, t, q, ci == 3 ? 1.0 : 0.0, o);
+        for (int co = 0; co < 4; ++co) op[(size_t)(co * p2 + tn) * ld + (size_t)j * Mq + ci * p2 + sn] = o[co];
+    }
+}
+
+// charges per element (tree order) and term: Q[(j n + i) 4 + c], and the
+// DDs in tree order D3[(j n + i) 3 + c]
+__global__ void k_pprep(int n, int H, const int *__restrict__ perm, const double *__restrict__ E,
+                        const double *__restrict__ cb, const double *__restrict__ sb, double *__restrict__ Q,
+                        double *__restrict__ D3)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int j = blockIdx.y;
+    if (i >= n) return;
+    const double *e = E + (size_t)j * 3 * n + 3 * (size_t)perm[i];
+    double q0, q1, q2;
+    charge(cb[i], sb[i], e[0], e[1], q0, q1, q2);
+    double *qq = Q + ((size_t)j * n + i) * 4;
+    qq[0] = q0;
+    qq[1] = q1;
+    qq[2] = q2;
+    qq[3] = e[2];
+    double *d = D3 + ((size_t)j * n + i) * 3;
+    d[0] = e[0];
+    d[1] = e[1];
+    d[2] = e[2];
+}
+
+// leaf weights per term (eq. 3.6): W[(leaf H + j) Mq + c p^2 + t]
+__global__ __launch_bounds__(256) void k_pp2m(int nleaf, const int *__restrict__ leaves,
+                                              const int *__restrict__ pbeg, const int *__restrict__ pend,
+                                              const double *__restrict__ Pm, const double *__restrict__ Q, int n,
+                                              int p2, int H, int Mq, double *__restrict__ W)
+{
+    int c = leaves[blockIdx.x];
+    int j = blockIdx.y;
+    int b = pbeg[c], e = pend[c];
+    const double *Qj = Q + (size_t)j * n * 4;
+    double *Wc = W + ((size_t)c * H + j) * Mq;
+    for (int t = threadIdx.x; t < p2; t += 256) {
+        double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
+        for (int i = b; i < e; ++i) {
+            double m = Pm[(size_t)i * p2 + t];
+            w0 += Qj[4 * i] * m;
+            w1 += Qj[4 * i + 1] * m;
+            w2 += Qj[4 * i + 2] * m;
+            w3 += Qj[4 * i + 3] * m;
+        }
+        Wc[t] = w0;
+        Wc[p2 + t] = w1;
+        Wc[2 * p2 + t] = w2;
+        Wc[3 * p2 + t] = w3;
+    }
+}
+
+// Near field per work item (a leaf and a chunk of its near sources, as in
+// the elastic product): exact transient element integrals for every term;
+// partial (sxx, syy, sxy, p) per target point of the item.
+constexpr int PN = 64;
+__global__ __launch_bounds__(PN) void k_pp2p(int nitem, const int *__restrict__ it_leaf,
+                                             const int *__restrict__ it_s0, const int *__restrict__ it_s1,
+                                             const int *__restrict__ it_poff, const int *__restrict__ leaves,
+                                             const int *__restrict__ pbeg, const int *__restrict__ pend,
+                                             const int *__restrict__ noff, const int *__restrict__ nbeg,
+                                             const int *__restrict__ npre, const double *__restrict__ cx,
+                                             const double *__restrict__ cy, const double *__restrict__ cb,
+                                             const double *__restrict__ sb, const double *__restrict__ a, int n,
+                                             int H, double dt, const double *__restrict__ D3, PoroK K,
+                                             double *__restrict__ part)
+{
+    int k = blockIdx.x;
+    int li = it_leaf[k], s0 = it_s0[k], s1 = it_s1[k];
+    int c = leaves[li];
+    int tb = pbeg[c], te = pend[c];
+    int nb = noff[li], nn = noff[li + 1] - nb;
+    double *pk = part + 4 * (size_t)it_poff[k];
+    for (int i = tb + threadIdx.x; i < te; i += PN) {
+        double X = cx[i], Y = cy[i];
+        double o[4] = {0.0, 0.0, 0.0, 0.0};
+        int lo = 0;
+        for (int v = s0; v < s1; ++v) {
+            while (lo + 1 < nn && npre[nb + lo + 1] <= v) ++lo;  // v ascends
+            int jsrc = nbeg[nb + lo] + (v - npre[nb + lo]);
+            double ecx = cx[jsrc], ecy = cy[jsrc], ecb = cb[jsrc], esb = sb[jsrc], ea = a[jsrc];
+            for (int j = 0; j < H; ++j) {
+                const double *d = D3 + ((size_t)j * n + jsrc) * 3;
+                if (d[0] == 0.0 && d[1] == 0.0 && d[2] == 0.0) continue;
+                double q[3];
+                charge(ecb, esb, d[0], d[1], q[0], q[1], q[2]);
+                elem_transient(K, X, Y, ecx, ecy, ecb, esb, ea, q, d[2], (j + 1) * dt, 1.0, o);
+            }
+        }
+        double *pp = pk + 4 * (size_t)(i - tb);
+        pp[0] = o[0];
+        pp[1] = o[1];
+        pp[2] = o[2];
+        pp[3] = o[3];
+    }
+}
+
+// far + near (in item order) -> (shear, normal traction, pressure), caller
+// order; mode 0: =, 1: -=; o2 (if given): drained elastic tractions added
+__global__ void k_pfinal(int n, const int *__restrict__ tleaf, const int *__restrict__ leaves,
+                         const int *__restrict__ pbeg, const int *__restrict__ lk_off,
+                         const int *__restrict__ it_poff, const double *__restrict__ part,
+                         const double *__restrict__ far, const double *__restrict__ cb,
+                         const double *__restrict__ sb, const int *__restrict__ perm,
+                         const double *__restrict__ o2, int mode, double *__restrict__ out)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int li = tleaf[i];
+    int t = i - pbeg[leaves[li]];
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    if (far)
+        for (int c = 0; c < 4; ++c) s[c] = far[4 * (size_t)i + c];
+    for (int k = lk_off[li]; k < lk_off[li + 1]; ++k) {
+        const double *o = part + 4 * ((size_t)it_poff[k] + t);
+        for (int c = 0; c < 4; ++c) s[c] += o[c];
+    }
+    double ts, tn;
+    traction(cb[i], sb[i], s[0], s[1], s[2], ts, tn);
+    int j = perm[i];
+    if (o2) {
+        ts += o2[2 * j];
+        tn += o2[2 * j + 1];
+    }
+    double *y = out + 3 * (size_t)j;
+    if (mode) {
+        y[0] -= ts;
+        y[1] -= tn;
+        y[2] -= s[3];
+    } else {
+        y[0] = ts;
+        y[1] = tn;
+        y[2] = s[3];
+    }
+}
+
+__global__ void k_take2(int n, const double *__restrict__ E, double *__restrict__ D2)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    D2[2 * i] = E[3 * i];
+    D2[2 * i + 1] = E[3 * i + 1];
+}
+
 bool g_gl_ready[64] = {false};
 
 void upload_rules(int device)
@@ -341,19 +521,173 @@ void poro_sum(fmddm_ctx *ctx, fmddm_tree *t, int nterm, const std::vector<double
     FM_CHECK_LAUNCH();
 }
 
+// Schedule and operators of the multipole form for H time levels.
+void poro_fmm_setup(fmddm_ctx *ctx, fmddm_tree *t, int H)
+{
+    setup_fmm(ctx, t);
+    hipStream_t s = ctx->stream;
+    const int p = ctx->prm.p, p2 = p * p, Mq = (4 * p2 + 63) / 64 * 64;
+    const fmddm_poro_params &pp = ctx->poro;
+    bool same = t->pf_ready && t->pf_p == p && t->pf_dt == pp.dt;
+    if (!same) {
+        const int ncell = t->ncell;
+        std::vector<int> hv(t->nV), hix(ncell), hiy(ncell);
+        if (t->nV) FM_HIP(hipMemcpyAsync(hv.data(), t->lidx[1].p, t->nV * 4, hipMemcpyDeviceToHost, s));
+        FM_HIP(hipMemcpyAsync(hix.data(), t->cix.p, ncell * 4, hipMemcpyDeviceToHost, s));
+        FM_HIP(hipMemcpyAsync(hiy.data(), t->ciy.p, ncell * 4, hipMemcpyDeviceToHost, s));
+        FM_HIP(hipStreamSynchronize(s));
+        const std::vector<int> &vo = t->h_loff[1];
+        std::vector<int> key2combo(64 * 49, -1), clvl, cox, coy;
+        std::vector<std::vector<int>> bycombo;
+        for (int c = 0; c < ncell; ++c)
+            for (int k = vo[c]; k < vo[c + 1]; ++k) {
+                int src = hv[k];
+                int ox = (int)hix[src] - (int)hix[c], oy = (int)hiy[src] - (int)hiy[c];
+                int key = t->h_level[c] * 49 + offset_slot(ox, oy);
+                if (key2combo[key] < 0) {
+                    key2combo[key] = (int)clvl.size();
+                    clvl.push_back(t->h_level[c]);
+                    cox.push_back(ox);
+                    coy.push_back(oy);
+                    bycombo.emplace_back();
+                }
+                bycombo[key2combo[key]].push_back(k);
+            }
+        std::vector<int> top, tbeg, tend, psrc, pdst;
+        for (size_t cmb = 0; cmb < bycombo.size(); ++cmb)
+            for (size_t b = 0; b < bycombo[cmb].size(); b += 32) {
+                top.push_back((int)cmb);
+                tbeg.push_back((int)psrc.size());
+                for (size_t i = b; i < std::min(bycombo[cmb].size(), b + 32); ++i) {
+                    int k = bycombo[cmb][i];
+                    psrc.push_back(hv[k]);
+                    pdst.push_back(k);
+                }
+                tend.push_back((int)psrc.size());
+            }
+        auto up = [&](DBuf<int> &d, const std::vector<int> &h) {
+            d.alloc(std::max<size_t>(h.size(), 1));
+            if (!h.empty()) FM_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * 4, hipMemcpyHostToDevice, s));
+        };
+        up(t->pf_tile_op, top);
+        up(t->pf_tile_beg, tbeg);
+        up(t->pf_tile_end, tend);
+        up(t->pf_psrc, psrc);
+        up(t->pf_pdst, pdst);
+        up(t->pf_combo_lvl, clvl);
+        up(t->pf_combo_ox, cox);
+        up(t->pf_combo_oy, coy);
+        t->pf_ncombo = (int)clvl.size();
+        t->pf_ntile = (int)top.size();
+        t->pf_p = p;
+        t->pf_Mq = Mq;
+        t->pf_dt = pp.dt;
+        t->pf_H = 0;
+        t->pf_G.alloc((size_t)ncell * Mq);
+        t->pf_G.zero(s);
+        t->pf_Z.alloc((size_t)std::max<int64_t>(t->nV, 1) * Mq);
+        t->pf_far.alloc(4 * (size_t)t->n);
+        t->pf_near.alloc(4 * (size_t)std::max<int64_t>(t->npartial, 1));
+        t->pf_D2.alloc(2 * (size_t)t->n);
+        t->pf_o2.alloc(2 * (size_t)t->n);
+        t->pf_ready = 1;
+        FM_HIP(hipStreamSynchronize(s));
+    }
+    if (t->pf_H < H) {
+        int Hn = std::max(H, 2 * t->pf_H);
+        if (t->pf_ncombo > 0) {
+            size_t tot = (size_t)t->pf_ncombo * Mq * Hn * Mq;
+            t->pf_ops.alloc(tot);
+            t->pf_ops.zero(s);
+            int64_t work = (int64_t)p2 * p2 * Hn * t->pf_ncombo;
+            hipLaunchKernelGGL(k_pops, dim3(cdiv(work, 256)), dim3(256), 0, s, t->pf_ncombo, t->pf_combo_lvl.p,
+                               t->pf_combo_ox.p, t->pf_combo_oy.p, t->L, ctx->cheb->xbar.p, p, Hn, pp.dt, Mq,
+                               poro_constants(ctx), t->pf_ops.p);
+            FM_CHECK_LAUNCH();
+        }
+        t->pf_W.alloc((size_t)t->ncell * Hn * Mq);
+        t->pf_W.zero(s);
+        t->pf_part.alloc((size_t)std::max(t->nuitem, 1) * Hn * Mq);
+        t->pf_Q.alloc((size_t)Hn * t->n * 4);
+        t->pf_D3.alloc((size_t)Hn * t->n * 3);
+        t->pf_H = Hn;
+        FM_HIP(hipStreamSynchronize(s));
+    }
+}
+
+// out (mode 0: =, 1: -=) the sum over time levels j = 1..H of F_transient(j dt)
+// applied to E[j-1] (3n each, caller order), plus, if drained, the drained
+// elastic part of E[0]; multipole form.
+void poro_fmm_sum(fmddm_ctx *ctx, fmddm_tree *t, int H, const double *E, bool drained, int mode, double *out)
+{
+    upload_rules(ctx->device);
+    poro_fmm_setup(ctx, t, H);
+    hipStream_t s = ctx->stream;
+    const int n = (int)t->n, p = ctx->prm.p, p2 = p * p, Mq = t->pf_Mq;
+    PoroK K = poro_constants(ctx);
+    hipLaunchKernelGGL(k_pprep, dim3(cdiv(n, 256), H), dim3(256), 0, s, n, H, t->perm.p, E, t->scb.p, t->ssb.p,
+                       t->pf_Q.p, t->pf_D3.p);
+    FM_CHECK_LAUNCH();
+    bool far = t->nV > 0 && t->pf_ntile > 0;
+    if (far) {
+        hipLaunchKernelGGL(k_pp2m, dim3(t->nleaf, H), dim3(256), 0, s, t->nleaf, t->dleaves.p, t->cpbeg.p,
+                           t->cpend.p, t->p2m_mat.p, t->pf_Q.p, n, p2, H, Mq, t->pf_W.p);
+        FM_CHECK_LAUNCH();
+        fmm_m2m4(ctx, t, H, H * Mq, Mq, t->pf_W.p, t->pf_part.p);
+        fmm_pair_gemm(s, t->pf_ntile, Mq, t->pf_ops.p, (size_t)Mq * t->pf_H * Mq, t->pf_H * Mq, H * Mq, t->pf_W.p,
+                      H * Mq, t->pf_tile_op.p, t->pf_tile_beg.p, t->pf_tile_end.p, t->pf_psrc.p, t->pf_pdst.p,
+                      t->pf_Z.p, Mq);
+        fmm_sum_pairs(s, t, t->pf_Z.p, Mq, Mq, t->pf_G.p, Mq);
+        fmm_l2p4(ctx, t, t->pf_G.p, Mq, t->pf_far.p);
+    }
+    hipLaunchKernelGGL(k_pp2p, dim3(t->nitem), dim3(PN), 0, s, t->nitem, t->it_leaf.p, t->it_s0.p, t->it_s1.p,
+                       t->it_poff.p, t->dleaves.p, t->cpbeg.p, t->cpend.p, t->noff.p, t->nbeg.p, t->npre.p,
+                       t->scx.p, t->scy.p, t->scb.p, t->ssb.p, t->sa.p, n, H, ctx->poro.dt, t->pf_D3.p, K,
+                       t->pf_near.p);
+    FM_CHECK_LAUNCH();
+    const double *o2 = nullptr;
+    if (drained) {
+        hipLaunchKernelGGL(k_take2, dim3(cdiv(n, 256)), dim3(256), 0, s, n, E, t->pf_D2.p);
+        FM_CHECK_LAUNCH();
+        fmm_apply(ctx, t, t->pf_D2.p, t->pf_o2.p);
+        o2 = t->pf_o2.p;
+    }
+    hipLaunchKernelGGL(k_pfinal, dim3(cdiv(n, 256)), dim3(256), 0, s, n, t->tleaf.p, t->dleaves.p, t->cpbeg.p,
+                       t->lk_off.p, t->it_poff.p, t->pf_near.p, far ? t->pf_far.p : (const double *)nullptr,
+                       t->scb.p, t->ssb.p, t->perm.p, o2, mode, out);
+    FM_CHECK_LAUNCH();
+}
+
 }  // namespace
 
 void poro_apply(fmddm_ctx *ctx, fmddm_tree *t, int lag, const double *D, double *out)
 {
+    if (!ctx->poro_set) throw Error{FMDDM_EINVAL, "poroelastic parameters not set (fmddm_poro_set)"};
     const double dt = ctx->poro.dt;
     const int n = (int)t->n, m3 = 3 * n;
+    const bool fmm = ctx->poro.mode == FMDDM_APPLY_FMM;
+    hipStream_t s = ctx->stream;
     if (lag == 0) {
-        poro_sum(ctx, t, 1, {dt}, D, 0, 0, out);
+        if (fmm) poro_fmm_sum(ctx, t, 1, D, true, 0, out);
+        else poro_sum(ctx, t, 1, {dt}, D, 0, 0, out);
+        return;
+    }
+    if (fmm) {
+        // time levels 1..lag+1 with E[lag-1] = -D, E[lag] = D, the rest zero
+        const int H = lag + 1;
+        if (t->poro_E.n < (size_t)H * m3) t->poro_E.alloc((size_t)H * m3);
+        hipLaunchKernelGGL(k_scale_copy, dim3(cdiv((int64_t)H * m3, 256)), dim3(256), 0, s, H * m3, 0.0,
+                           t->poro_E.p, t->poro_E.p);
+        hipLaunchKernelGGL(k_scale_copy, dim3(cdiv(m3, 256)), dim3(256), 0, s, m3, -1.0, D,
+                           t->poro_E.p + (size_t)(lag - 1) * m3);
+        hipLaunchKernelGGL(k_scale_copy, dim3(cdiv(m3, 256)), dim3(256), 0, s, m3, 1.0, D,
+                           t->poro_E.p + (size_t)lag * m3);
+        FM_CHECK_LAUNCH();
+        poro_fmm_sum(ctx, t, H, t->poro_E.p, false, 0, out);
         return;
     }
     // terms (t1, D) and (t0, -D): the drained parts cancel
     if (t->poro_E.n < (size_t)2 * m3) t->poro_E.alloc((size_t)2 * m3);
-    hipStream_t s = ctx->stream;
     hipLaunchKernelGGL(k_scale_copy, dim3(cdiv(m3, 256)), dim3(256), 0, s, m3, 1.0, D, t->poro_E.p);
     hipLaunchKernelGGL(k_scale_copy, dim3(cdiv(m3, 256)), dim3(256), 0, s, m3, -1.0, D, t->poro_E.p + m3);
     FM_CHECK_LAUNCH();
@@ -363,12 +697,17 @@ void poro_apply(fmddm_ctx *ctx, fmddm_tree *t, int lag, const double *D, double 
 void poro_history(fmddm_ctx *ctx, fmddm_tree *t, int h, const double *Dh, double *rhs)
 {
     if (h < 2) return;
+    if (!ctx->poro_set) throw Error{FMDDM_EINVAL, "poroelastic parameters not set (fmddm_poro_set)"};
     const double dt = ctx->poro.dt;
     const int n = (int)t->n, m3 = 3 * n;
     if (t->poro_E.n < (size_t)h * m3) t->poro_E.alloc((size_t)h * m3);
     hipStream_t s = ctx->stream;
     hipLaunchKernelGGL(k_hist_terms, dim3(cdiv(m3, 256), h), dim3(256), 0, s, m3, h, Dh, t->poro_E.p);
     FM_CHECK_LAUNCH();
+    if (ctx->poro.mode == FMDDM_APPLY_FMM) {
+        poro_fmm_sum(ctx, t, h, t->poro_E.p, false, 1, rhs);
+        return;
+    }
     std::vector<double> times(h);
     for (int j = 1; j <= h; ++j) times[j - 1] = j * dt;
     poro_sum(ctx, t, h, times, t->poro_E.p, -1, 1, rhs);

@@ -134,3 +134,38 @@ def test_poro_errors():
     with pytest.raises(F.FmddmError):
         F.fmddm_poro_apply(prob.ctx, prob.tree, 0, D, D)     # aliasing
     prob.close()
+
+
+def test_poro_fmm_matches_exact():
+    """The multipole form (Chebyshev p = 12, the transient kernel's M2L per
+    level and time level) against the exact products on a well cluster whose
+    cells (metres) are far wider than the diffusion lengths (< 0.2 m): the
+    far field is then a smooth function on well-separated cells and p = 12
+    interpolates it to ~1e-8; the bar is 1e-6 of the largest entry of each
+    response kind."""
+    wl = W.well_cluster(n_frac=5, elems=200, half_length=20.0, spacing=10.0)
+    n3 = 3 * wl.n
+    rng = np.random.default_rng(5)
+    scale = np.tile([1e-4, 1e-4, 1e-10], wl.n)
+    D = dev(rng.standard_normal(n3) * scale)
+    hist = dev(np.concatenate([rng.standard_normal(n3) * scale for _ in range(5)]))
+    res = {}
+    for mode in (F.FMDDM_APPLY_DIRECT, F.FMDDM_APPLY_FMM):
+        prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=MED["E"], nu=MED["nu"], p=12, leaf=32)
+        F.fmddm_poro_set(prob.ctx, MED["nuu"], MED["alpha"], MED["perm"], MED["visc"], DT, P0, mode=mode)
+        outs = []
+        for lag in (0, 2):
+            o = torch.zeros(n3, dtype=torch.float64, device="cuda")
+            F.fmddm_poro_apply(prob.ctx, prob.tree, lag, D, o)
+            outs.append(o.cpu().numpy())
+        r = torch.zeros(n3, dtype=torch.float64, device="cuda")
+        F.fmddm_add_history(prob.ctx, prob.tree, 6, hist, r)
+        outs.append(r.cpu().numpy())
+        res[mode] = outs
+        info = F.fmddm_tree_get_info(prob.ctx, prob.tree)
+        prob.close()
+    assert info["nV"] > 0
+    for k, (a, b) in enumerate(zip(res[F.FMDDM_APPLY_FMM], res[F.FMDDM_APPLY_DIRECT])):
+        e = cmp(a, b)
+        print("poro fmm vs exact", k, e)
+        assert e <= 1e-6, (k, e)
