@@ -184,42 +184,58 @@ def serving_leg(F, W, count, slots, load):
     }
 
 
-def history_leg(F, W, elems, steps):
-    """Poroelastic time marching on the horizontal-well cluster (5 fractures,
-    0.2 m elements, 10 m apart, Table 2 loads; Biot constants of the well
-    example, 60 s steps): one exact left-hand-side product and the history
-    sum of the last step, timed on the device."""
+def history_run(F, W, elems, steps, mode, p):
+    """One left-hand-side product and the history sum of step `steps` on the
+    horizontal-well cluster (5 fractures of `elems` 0.2 m elements, 10 m
+    apart; Biot constants of the well example, 60 s steps), timed on the
+    device after one untimed pass that builds the operators."""
     import torch
     wl = W.well_cluster(n_frac=5, elems=elems, half_length=0.1 * elems, spacing=10.0)
-    prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=20e9, nu=0.2)
+    prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=20e9, nu=0.2, p=p, leaf=32)
     try:
-        F.fmddm_poro_set(prob.ctx, 0.35, 0.8, 1e-18, 1e-3, 60.0, 48.26e6)
+        F.fmddm_poro_set(prob.ctx, 0.35, 0.8, 1e-18, 1e-3, 60.0, 48.26e6, mode=mode)
         n3 = 3 * prob.n
         rng = np.random.default_rng(3)
         scale = np.tile([1e-4, 1e-4, 1e-10], prob.n)
-        hist = torch.as_tensor(np.concatenate([rng.standard_normal(n3) * scale for _ in range(steps - 1)])).cuda()
+        hist = torch.as_tensor(np.concatenate([rng.standard_normal(n3) * scale
+                                               for _ in range(steps - 1)])).cuda()
         D = hist[:n3].clone()
         out = torch.zeros(n3, dtype=torch.float64, device="cuda")
-        F.fmddm_poro_apply(prob.ctx, prob.tree, 0, D, out)  # warm-up
+        rhs = torch.zeros(n3, dtype=torch.float64, device="cuda")
+        F.fmddm_poro_apply(prob.ctx, prob.tree, 0, D, out)        # builds operators
+        F.fmddm_add_history(prob.ctx, prob.tree, steps, hist, rhs)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         F.fmddm_poro_apply(prob.ctx, prob.tree, 0, D, out)
         torch.cuda.synchronize()
         t_lhs = time.perf_counter() - t0
-        rhs = torch.zeros(n3, dtype=torch.float64, device="cuda")
         t0 = time.perf_counter()
         F.fmddm_add_history(prob.ctx, prob.tree, steps, hist, rhs)
         torch.cuda.synchronize()
         t_hist = time.perf_counter() - t0
-        n = prob.n
-        return {"workload": f"well cluster 5 x {elems} elements (N={n}), dt 60 s, history of step {steps}",
-                "n": n, "lhs_product_ms": t_lhs * 1e3, "history_ms": t_hist * 1e3,
-                "lags": steps - 1, "time_levels_evaluated": steps,
-                "lag_applications_per_s": (steps - 1) / t_hist,
-                "element_pair_terms_per_s": n * n * steps / t_hist,
-                "method": "exact element integrals on the fly (no multipole approximation)"}
+        return prob.n, t_lhs, t_hist, out.cpu().numpy(), rhs.cpu().numpy()
     finally:
         prob.close()
+
+
+def history_leg(F, W, elems, steps, p=10):
+    """Poroelastic time marching (the left-hand-side product and the history
+    sum over earlier steps): multipole form at the full well-cluster size,
+    and multipole against exact evaluation at a tenth of it."""
+    small = max(elems // 10, 40)
+    out = {"dt_s": 60.0, "history_of_step": steps, "time_levels": steps, "p": p}
+    n, tl, th, _, _ = history_run(F, W, elems, steps, F.FMDDM_APPLY_FMM, p)
+    out["fmm_full"] = {"workload": f"well cluster 5 x {elems} elements (N={n})", "lhs_product_ms": tl * 1e3,
+                       "history_ms": th * 1e3, "lag_applications_per_s": (steps - 1) / th}
+    n2, tl2, th2, o_f, r_f = history_run(F, W, small, steps, F.FMDDM_APPLY_FMM, p)
+    _, tl3, th3, o_e, r_e = history_run(F, W, small, steps, F.FMDDM_APPLY_DIRECT, p)
+    rel = lambda a, b: float(max(np.abs(a[k::3] - b[k::3]).max() / max(np.abs(b[k::3]).max(), 1e-300)
+                                 for k in range(3)))
+    out["small"] = {"workload": f"well cluster 5 x {small} elements (N={n2})",
+                    "fmm": {"lhs_product_ms": tl2 * 1e3, "history_ms": th2 * 1e3},
+                    "exact": {"lhs_product_ms": tl3 * 1e3, "history_ms": th3 * 1e3},
+                    "fmm_err_vs_exact": {"lhs": rel(o_f, o_e), "history": rel(r_f, r_e)}}
+    return out
 
 
 def cpu_baseline(wl, D, seconds):
@@ -258,7 +274,7 @@ def main():
     ap.add_argument("--serve-load", type=float, default=0.75)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy 256 MiB device-to-device 5 times (reference for HBM byte counters)")
-    ap.add_argument("--history-elems", type=int, default=400)
+    ap.add_argument("--history-elems", type=int, default=4000)
     ap.add_argument("--history-steps", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:

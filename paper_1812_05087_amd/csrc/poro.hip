@@ -52,7 +52,8 @@ struct PoroK {
 // Ein(z) = sum (-1)^(k+1) z^k / (k k!) nested as z (1 - z/4 (1 - 2z/9
 // (1 - 3z/16 (...)))) to depth 30; above: the continued fraction
 // e^-z / (z + 1 - 1/(z + 3 - 4/(z + 5 - ...))) evaluated backwards from
-// depth 64.
+// depth 2 + 90/z (its truncation error falls like exp(-4 sqrt(depth z)),
+// below 1e-16 there); zero where e^-z underflows.
 __device__ double e1(double z)
 {
     if (z <= 2.0) {
@@ -60,8 +61,10 @@ __device__ double e1(double z)
         for (int k = 30; k >= 1; --k) v = 1.0 - z * k / ((k + 1.0) * (k + 1.0)) * v;
         return -0.57721566490153286061 - log(z) + z * v;
     }
+    if (z > 745.0) return 0.0;
+    int depth = min(64, 2 + (int)(90.0 / z));
     double f = 0.0;
-    for (int k = 64; k >= 1; --k) f = (double)k * k / (z + 2.0 * k + 1.0 - f);
+    for (int k = depth; k >= 1; --k) f = (double)k * k / (z + 2.0 * k + 1.0 - f);
     return exp(-z) / (z + 1.0 - f);
 }
 
@@ -385,7 +388,7 @@ __global__ __launch_bounds__(256) void k_pp2m(int nleaf, const int *__restrict__
 // Near field per work item (a leaf and a chunk of its near sources, as in
 // the elastic product): exact transient element integrals for every term;
 // partial (sxx, syy, sxy, p) per target point of the item.
-constexpr int PN = 64;
+constexpr int PN = 128;
 __global__ __launch_bounds__(PN) void k_pp2p(int nitem, const int *__restrict__ it_leaf,
                                              const int *__restrict__ it_s0, const int *__restrict__ it_s1,
                                              const int *__restrict__ it_poff, const int *__restrict__ leaves,
@@ -400,30 +403,43 @@ __global__ __launch_bounds__(PN) void k_pp2p(int nitem, const int *__restrict__ 
     int k = blockIdx.x;
     int li = it_leaf[k], s0 = it_s0[k], s1 = it_s1[k];
     int c = leaves[li];
-    int tb = pbeg[c], te = pend[c];
+    int tb = pbeg[c], te = pend[c], nt = te - tb;
     int nb = noff[li], nn = noff[li + 1] - nb;
+    // tpt adjacent lanes per target point take every tpt-th source and
+    // combine by a fixed butterfly
+    int tpt = 1;
+    while (tpt < 16 && tpt * 2 * nt <= PN) tpt *= 2;
+    int tpg = PN / tpt, sub = threadIdx.x & (tpt - 1);
     double *pk = part + 4 * (size_t)it_poff[k];
-    for (int i = tb + threadIdx.x; i < te; i += PN) {
-        double X = cx[i], Y = cy[i];
+    for (int t0 = tb; t0 < te; t0 += tpg) {
+        int i = t0 + (int)threadIdx.x / tpt;
+        bool act = i < te;
+        double X = act ? cx[i] : 0.0, Y = act ? cy[i] : 0.0;
         double o[4] = {0.0, 0.0, 0.0, 0.0};
-        int lo = 0;
-        for (int v = s0; v < s1; ++v) {
-            while (lo + 1 < nn && npre[nb + lo + 1] <= v) ++lo;  // v ascends
-            int jsrc = nbeg[nb + lo] + (v - npre[nb + lo]);
-            double ecx = cx[jsrc], ecy = cy[jsrc], ecb = cb[jsrc], esb = sb[jsrc], ea = a[jsrc];
-            for (int j = 0; j < H; ++j) {
-                const double *d = D3 + ((size_t)j * n + jsrc) * 3;
-                if (d[0] == 0.0 && d[1] == 0.0 && d[2] == 0.0) continue;
-                double q[3];
-                charge(ecb, esb, d[0], d[1], q[0], q[1], q[2]);
-                elem_transient(K, X, Y, ecx, ecy, ecb, esb, ea, q, d[2], (j + 1) * dt, 1.0, o);
+        if (act) {
+            int lo = 0;
+            for (int v = s0 + sub; v < s1; v += tpt) {
+                while (lo + 1 < nn && npre[nb + lo + 1] <= v) ++lo;  // v ascends
+                int jsrc = nbeg[nb + lo] + (v - npre[nb + lo]);
+                double ecx = cx[jsrc], ecy = cy[jsrc], ecb = cb[jsrc], esb = sb[jsrc], ea = a[jsrc];
+                for (int j = 0; j < H; ++j) {
+                    const double *d = D3 + ((size_t)j * n + jsrc) * 3;
+                    if (d[0] == 0.0 && d[1] == 0.0 && d[2] == 0.0) continue;
+                    double q[3];
+                    charge(ecb, esb, d[0], d[1], q[0], q[1], q[2]);
+                    elem_transient(K, X, Y, ecx, ecy, ecb, esb, ea, q, d[2], (j + 1) * dt, 1.0, o);
+                }
             }
         }
-        double *pp = pk + 4 * (size_t)(i - tb);
-        pp[0] = o[0];
-        pp[1] = o[1];
-        pp[2] = o[2];
-        pp[3] = o[3];
+        for (int w = 1; w < tpt; w <<= 1)
+            for (int cc = 0; cc < 4; ++cc) o[cc] += __shfl_xor(o[cc], w);
+        if (act && sub == 0) {
+            double *pp = pk + 4 * (size_t)(i - tb);
+            pp[0] = o[0];
+            pp[1] = o[1];
+            pp[2] = o[2];
+            pp[3] = o[3];
+        }
     }
 }
 
