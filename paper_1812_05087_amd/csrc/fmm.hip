@@ -325,7 +325,7 @@ __global__ __launch_bounds__(256) void k_m2m_sum(int nanc, const int *__restrict
 // 16x16x4 FP64 MFMA blocks.  Operand layout of v_mfma_f64_16x16x4f64: lane L
 // holds A[L%16][L/16] and B[L/16][L%16]; accumulator register r of lane L
 // holds D[4r + L/16][L%16].
-template <int BM, int BN>
+template <int BM, int BN, int GK>
 __global__ __launch_bounds__(256) void k_ggemm(const double *__restrict__ ops, size_t op_stride, int lda,
                                                int Kd, const double *__restrict__ X, int ldx,
                                                const int *__restrict__ tile_op, const int *__restrict__ tile_beg,
@@ -334,7 +334,7 @@ __global__ __launch_bounds__(256) void k_ggemm(const double *__restrict__ ops, s
                                                const double *__restrict__ pair_scale, double *__restrict__ Z,
                                                int ldz, size_t zsplit)
 {
-    constexpr int GK = 16, WM = BM / 32, WN = BN / 32;
+    constexpr int WM = BM / 32, WN = BN / 32;
     constexpr int RA = (BM * GK + 255) / 256, RB = (BN * GK + 255) / 256;
     __shared__ double As[BM][GK + 1];
     __shared__ double Bs[GK][BN + 1];
@@ -780,8 +780,14 @@ void launch_ggemm(hipStream_t s, int ntile, int Mrows, const double *ops, size_t
 {
     if (ntile == 0) return;
     if (Mrows % BM || Kd % 16) throw Error{FMDDM_EDEVICE, "GEMM shape not tiled"};
-    hipLaunchKernelGGL((k_ggemm<BM, BN>), dim3(ntile, Mrows / BM, nsplit), dim3(256), 0, s, ops, op_stride, lda,
-                       Kd, X, ldx, top, tbeg, tend, psrc, pdst, pscale, Z, ldz, zsplit);
+    // long K: 64-deep k-steps keep 16 MFMA per wave busy per fetched tile;
+    // short K: 16-deep steps, smaller tiles in LDS and more blocks per CU
+    if (Kd % 64 == 0 && Kd >= 512)
+        hipLaunchKernelGGL((k_ggemm<BM, BN, 64>), dim3(ntile, Mrows / BM, nsplit), dim3(256), 0, s, ops, op_stride,
+                           lda, Kd, X, ldx, top, tbeg, tend, psrc, pdst, pscale, Z, ldz, zsplit);
+    else
+        hipLaunchKernelGGL((k_ggemm<BM, BN, 16>), dim3(ntile, Mrows / BM, nsplit), dim3(256), 0, s, ops, op_stride,
+                           lda, Kd, X, ldx, top, tbeg, tend, psrc, pdst, pscale, Z, ldz, zsplit);
     FM_CHECK_LAUNCH();
 }
 
