@@ -510,138 +510,95 @@ __global__ void k_transpose_ops(int nop, int rp, double scale, const double *__r
 }
 
 // ------------------------------------------------------------ L2P
-// Far-field stress at every midpoint, eqs. 3.9-3.11 in one step: the
-// chain of parent-to-child interpolations of the downward pass followed by
-// the interpolation at the point is the evaluation of each ancestor's M2L
-// field (a polynomial on that ancestor's square) at the point, so the
-// fields of the leaf and of all its ancestors at level >= 2 are summed
-// there directly.  One block per leaf and chunk of up to 32 points; an
-// ancestor's field G sits in LDS (double-buffered: the next one is fetched
-// while the current one is used).  For each ancestor the barycentric
-// interpolants Sx, Sy of the points are formed, the product
-// R[(c,l)][t] = sum_m G[c][l][m] Sy[t][m] runs on FP64 MFMA (rows (c,l)
-// in 16-row tiles, one per wave, points in two 16-column tiles, m in
-// k-steps of 4), and sigma_c(t) += sum_l Sx[t][l] R[(c,l)][t] is summed
-// in l order.
+// Far-field stress at every midpoint, eqs. 3.9-3.11: the chain of
+// parent-to-child interpolations of the downward pass followed by the
+// interpolation at the point is the evaluation of each ancestor's M2L
+// field (a polynomial on that ancestor's square) at the point, so every
+// far cell's field is evaluated directly at the points below it.  Work
+// items are (far cell, chunk of up to 32 of its points); an item loads the
+// cell's field once, forms the barycentric interpolants Sx, Sy of its
+// points, computes R[(c,l)][t] = sum_m G[c][l][m] Sy[t][m] on FP64 MFMA
+// (rows (c,l) in 16-row tiles, one per wave; points in two 16-column
+// tiles; m in k-steps of 4) and sigma_c(t) = sum_l Sx[t][l] R[(c,l)][t],
+// and writes it to the slot of the cell's level:
+// far[((level - 2) n + point) NC + c].  The final pass sums a point's levels
+// in order.
 constexpr int LT = 256, LTM = 32;
 
-// NC field components per cell (rows of G, stride Mp); far_s gets NC
-// values per point.
+// NC field components per cell (rows of G, stride ldg).
 template <int P, int NC>
-__global__ __launch_bounds__(LT) void k_l2p(int nleaf, const int *__restrict__ leaves,
-                                            const int *__restrict__ pbeg, const int *__restrict__ pend,
-                                            const int *__restrict__ aoff, const int *__restrict__ aidx,
-                                            const double *__restrict__ ccx, const double *__restrict__ ccy,
-                                            const double *__restrict__ chw, const double *__restrict__ cx,
-                                            const double *__restrict__ cy, const double *__restrict__ G, int Mp,
-                                            const double *__restrict__ xbar, const double *__restrict__ bw,
-                                            double *__restrict__ far_s)
+__global__ __launch_bounds__(LT) void k_l2p(int nitem, const int *__restrict__ it_cell,
+                                            const int *__restrict__ it_p0, const int *__restrict__ pend,
+                                            const int *__restrict__ level, const double *__restrict__ ccx,
+                                            const double *__restrict__ ccy, const double *__restrict__ chw,
+                                            const double *__restrict__ cx, const double *__restrict__ cy,
+                                            const double *__restrict__ G, int ldg, const double *__restrict__ xbar,
+                                            const double *__restrict__ bw, int n, double *__restrict__ far)
 {
-    constexpr int P2 = P * P, N3 = NC * P2, NPF = (N3 + LT - 1) / LT;
+    constexpr int P2 = P * P, N3 = NC * P2;
     constexpr int RT = (NC * P + 15) / 16;  // 16-row tiles over (c, l)
-    constexpr int KS = (P + 3) / 4;        // k-steps over m
-    __shared__ double Gb[2][N3];
+    constexpr int KS = (P + 3) / 4;         // k-steps over m
+    __shared__ double Gb[N3];
     __shared__ double Sx[LTM][P + 1], Sy[LTM][P + 1];
     __shared__ double Rb[16 * RT][LTM + 1];
     __shared__ double s_xb[P], s_bw[P];
-    constexpr int MAXA = 32;  // ancestors kept in LDS (tree depth is at most 31)
-    __shared__ int s_anc[MAXA];
-    __shared__ double s_acx[MAXA], s_acy[MAXA], s_aih[MAXA];
-    int li = xcd_remap(blockIdx.x, nleaf);
-    int c = leaves[li];
+    int item = xcd_remap(blockIdx.x, nitem);
+    int A = it_cell[item], t0 = it_p0[item];
+    int ntp = min(LTM, pend[A] - t0);
     int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    int tb = pbeg[c], te = pend[c];
-    int a0 = aoff[li], na = min(aoff[li + 1] - a0, MAXA);
+    const double *GA = G + (size_t)A * ldg;
+    for (int e = tid; e < N3; e += LT) Gb[e] = GA[e];
     if (tid < P) {
         s_xb[tid] = xbar[tid];
         s_bw[tid] = bw[tid];
     }
-    // the ancestors and their squares, read once
-    if (tid < na) {
-        int A = aidx[a0 + tid];
-        s_anc[tid] = A;
-        s_acx[tid] = ccx[A];
-        s_acy[tid] = ccy[A];
-        s_aih[tid] = 1.0 / chw[A];
+    __syncthreads();
+    if (tid < 2 * LTM) {
+        int t = tid >> 1, coord = tid & 1;
+        double *dst = coord ? Sy[t] : Sx[t];
+        if (t < ntp) {
+            double ih = 1.0 / chw[A];
+            double u = coord ? (cy[t0 + t] - ccy[A]) * ih : (cx[t0 + t] - ccx[A]) * ih;
+            double S[P];
+            bary<P>(s_xb, s_bw, u, S);
+#pragma unroll
+            for (int m = 0; m < P; ++m) dst[m] = S[m];
+        } else {
+#pragma unroll
+            for (int m = 0; m < P; ++m) dst[m] = 0.0;
+        }
     }
     __syncthreads();
-    for (int t0 = tb; t0 < te; t0 += LTM) {
-        int ntp = min(LTM, te - t0);
-        double acc = 0.0;  // task tid < NC * LTM: point tid % 32, component tid / 32
-        double pf[NPF];
-        __syncthreads();
-        if (na > 0) {
-            const double *G0 = G + (size_t)s_anc[0] * Mp;
-            for (int e = tid; e < N3; e += LT) Gb[0][e] = G0[e];
+    for (int mt = wave; mt < RT; mt += 4) {
+        d4 r0 = {0.0, 0.0, 0.0, 0.0}, r1 = {0.0, 0.0, 0.0, 0.0};
+        int row = 16 * mt + (lane & 15);
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            int m = 4 * s + (lane >> 4);
+            double av = (row < NC * P && m < P) ? Gb[row * P + m] : 0.0;
+            double b0 = m < P ? Sy[lane & 15][m] : 0.0;
+            double b1 = m < P ? Sy[16 + (lane & 15)][m] : 0.0;
+            r0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, r0, 0, 0, 0);
+            r1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, r1, 0, 0, 0);
         }
-        for (int k = 0; k < na; ++k) {
-            if (k + 1 < na) {
-                const double *Gn = G + (size_t)s_anc[k + 1] * Mp;
 #pragma unroll
-                for (int r = 0; r < NPF; ++r) {
-                    int e = tid + r * LT;
-                    if (e < N3) pf[r] = Gn[e];
-                }
+        for (int r = 0; r < 4; ++r) {
+            int rw = 16 * mt + 4 * r + (lane >> 4);
+            if (rw < NC * P) {
+                int l = rw % P, t = lane & 15;
+                Rb[rw][t] = r0[r] * Sx[t][l];
+                Rb[rw][t + 16] = r1[r] * Sx[t + 16][l];
             }
-            if (tid < 2 * LTM) {
-                int t = tid >> 1, coord = tid & 1;
-                double *dst = coord ? Sy[t] : Sx[t];
-                if (t < ntp) {
-                    double ih = s_aih[k];
-                    double u = coord ? (cy[t0 + t] - s_acy[k]) * ih : (cx[t0 + t] - s_acx[k]) * ih;
-                    double S[P];
-                    bary<P>(s_xb, s_bw, u, S);
-#pragma unroll
-                    for (int m = 0; m < P; ++m) dst[m] = S[m];
-                } else {
-#pragma unroll
-                    for (int m = 0; m < P; ++m) dst[m] = 0.0;
-                }
-            }
-            __syncthreads();
-            const double *Gc = Gb[k & 1];
-            for (int mt = wave; mt < RT; mt += 4) {
-                d4 r0 = {0.0, 0.0, 0.0, 0.0}, r1 = {0.0, 0.0, 0.0, 0.0};
-                int row = 16 * mt + (lane & 15);
-#pragma unroll
-                for (int s = 0; s < KS; ++s) {
-                    int m = 4 * s + (lane >> 4);
-                    double av = (row < NC * P && m < P) ? Gc[row * P + m] : 0.0;
-                    double b0 = m < P ? Sy[lane & 15][m] : 0.0;
-                    double b1 = m < P ? Sy[16 + (lane & 15)][m] : 0.0;
-                    r0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, r0, 0, 0, 0);
-                    r1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, r1, 0, 0, 0);
-                }
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    int rw = 16 * mt + 4 * r + (lane >> 4);
-                    if (rw < NC * P) {
-                        int l = rw % P, t = lane & 15;
-                        Rb[rw][t] = r0[r] * Sx[t][l];
-                        Rb[rw][t + 16] = r1[r] * Sx[t + 16][l];
-                    }
-                }
-            }
-            __syncthreads();
-            if (tid < NC * LTM) {
-                int t = tid & 31, comp = tid >> 5;
-                double sum = 0.0;
-#pragma unroll
-                for (int l = 0; l < P; ++l) sum += Rb[comp * P + l][t];
-                acc += sum;
-            }
-            if (k + 1 < na) {
-#pragma unroll
-                for (int r = 0; r < NPF; ++r) {
-                    int e = tid + r * LT;
-                    if (e < N3) Gb[(k + 1) & 1][e] = pf[r];
-                }
-            }
-            __syncthreads();
         }
-        if (tid < NC * LTM) {
-            int t = tid & 31, comp = tid >> 5;
-            if (t < ntp) far_s[NC * (size_t)(t0 + t) + comp] = acc;
+    }
+    __syncthreads();
+    if (tid < NC * LTM) {
+        int t = tid & 31, comp = tid >> 5;
+        if (t < ntp) {
+            double sum = 0.0;
+#pragma unroll
+            for (int l = 0; l < P; ++l) sum += Rb[comp * P + l][t];
+            far[(((size_t)(level[A] - 2)) * n + t0 + t) * NC + comp] = sum;
         }
     }
 }
@@ -725,21 +682,25 @@ __global__ __launch_bounds__(NT) void k_p2p(
 // leaf's work items (in item order); projected to (shear, normal) traction
 // and written in caller order.
 __global__ void k_final(int n, const int *__restrict__ tleaf, const int *__restrict__ leaves,
-                        const int *__restrict__ pbeg, const int *__restrict__ lk_off,
-                        const int *__restrict__ it_poff, const double *__restrict__ part,
-                        const double *__restrict__ far_s, const double *__restrict__ cb,
-                        const double *__restrict__ sb, const int *__restrict__ perm, double *__restrict__ out)
+                        const int *__restrict__ pbeg, const int *__restrict__ level,
+                        const int *__restrict__ lk_off, const int *__restrict__ it_poff,
+                        const double *__restrict__ part, const double *__restrict__ far,
+                        const double *__restrict__ cb, const double *__restrict__ sb, const int *__restrict__ perm,
+                        double *__restrict__ out)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int li = tleaf[i];
-    int t = i - pbeg[leaves[li]];
+    int c = leaves[li];
+    int t = i - pbeg[c];
     double sxx = 0.0, syy = 0.0, sxy = 0.0;
-    if (far_s) {
-        sxx = far_s[3 * (size_t)i];
-        syy = far_s[3 * (size_t)i + 1];
-        sxy = far_s[3 * (size_t)i + 2];
-    }
+    if (far)  // the fields of the point's cells at levels 2 .. its leaf's, in level order
+        for (int l = 2; l <= level[c]; ++l) {
+            const double *f = far + ((size_t)(l - 2) * n + i) * 3;
+            sxx += f[0];
+            syy += f[1];
+            sxy += f[2];
+        }
     for (int k = lk_off[li]; k < lk_off[li + 1]; ++k) {
         const double *o = part + 3 * ((size_t)it_poff[k] + t);
         sxx += o[0];
@@ -804,9 +765,10 @@ void launch_m2m(hipStream_t s, fmddm_ctx *ctx, fmddm_tree *t, int ldw, int nterm
 template <int P, int NC = 3>
 void launch_l2p(hipStream_t s, fmddm_ctx *ctx, fmddm_tree *t, const double *G, int ldg, double *far)
 {
-    hipLaunchKernelGGL((k_l2p<P, NC>), dim3(t->nleaf), dim3(LT), 0, s, t->nleaf, t->dleaves.p, t->cpbeg.p,
-                       t->cpend.p, t->aoff.p, t->aidx.p, t->ccx.p, t->ccy.p, t->chw.p, t->scx.p, t->scy.p, G, ldg,
-                       ctx->cheb->xbar.p, ctx->cheb->bw.p, far);
+    if (t->nlpitem == 0) return;
+    hipLaunchKernelGGL((k_l2p<P, NC>), dim3(t->nlpitem), dim3(LT), 0, s, t->nlpitem, t->lp_cell.p, t->lp_p0.p,
+                       t->cpend.p, t->clevel.p, t->ccx.p, t->ccy.p, t->chw.p, t->scx.p, t->scy.p, G, ldg,
+                       ctx->cheb->xbar.p, ctx->cheb->bw.p, (int)t->n, far);
     FM_CHECK_LAUNCH();
 }
 
@@ -1251,7 +1213,27 @@ void setup_fmm(fmddm_ctx *ctx, fmddm_tree *t)
     }
     t->q.alloc(3 * (size_t)t->n);
     t->Dsort.alloc(2 * (size_t)t->n);
-    t->far_s.alloc(3 * (size_t)t->n);
+    // downward-pass items: every far cell's points in chunks of 32
+    {
+        std::vector<int> hb(ncell), he(ncell), lc, lp;
+        FM_HIP(hipMemcpyAsync(hb.data(), t->cpbeg.p, ncell * 4, hipMemcpyDeviceToHost, s));
+        FM_HIP(hipMemcpyAsync(he.data(), t->cpend.p, ncell * 4, hipMemcpyDeviceToHost, s));
+        FM_HIP(hipStreamSynchronize(s));
+        int maxlev = 0;
+        for (int c = 0; c < ncell; ++c) {
+            if (t->h_level[c] < 2) continue;
+            maxlev = std::max(maxlev, t->h_level[c]);
+            for (int q = hb[c]; q < he[c]; q += LTM) {
+                lc.push_back(c);
+                lp.push_back(q);
+            }
+        }
+        t->nlpitem = (int)lc.size();
+        t->nfarlev = maxlev >= 2 ? maxlev - 1 : 0;
+        upload(s, t->lp_cell, lc);
+        upload(s, t->lp_p0, lp);
+    }
+    t->far_s.alloc(3 * (size_t)std::max(t->nfarlev, 1) * t->n);
     t->part_s.alloc(3 * (size_t)t->npartial);
     if (M.mode == FMDDM_M2L_SVD) t->ksplit.alloc((size_t)KSPLIT * ncell * rp);
     FM_HIP(hipStreamSynchronize(s));
@@ -1355,7 +1337,8 @@ void fmm_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out)
     FM_HIP(hipStreamWaitEvent(s, ctx->ev_join, 0));
     P.begin(FMDDM_PH_FINAL, s, e0);
     hipLaunchKernelGGL(k_final, dim3(cdiv(n, 256)), dim3(256), 0, s, n, t->tleaf.p, t->dleaves.p, t->cpbeg.p,
-                       t->lk_off.p, t->it_poff.p, t->part_s.p, far ? t->far_s.p : (const double *)nullptr,
+                       t->clevel.p, t->lk_off.p, t->it_poff.p, t->part_s.p,
+                       far ? t->far_s.p : (const double *)nullptr,
                        t->scb.p, t->ssb.p, t->perm.p, out);
     FM_CHECK_LAUNCH();
     P.end(FMDDM_PH_FINAL, s, e0);

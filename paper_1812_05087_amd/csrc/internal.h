@@ -185,7 +185,9 @@ struct fmddm_tree {
     fmddm::DBuf<double> Gexp;         // M2L field of each cell at its nodes, ncell x Mp
     fmddm::DBuf<double> q;            // charges, tree order, 3 per element
     fmddm::DBuf<double> Dsort;        // D in tree order
-    fmddm::DBuf<double> far_s;        // far-field stress per point, tree order, 3 each
+    fmddm::DBuf<double> far_s;        // far-field stress per (level >= 2, point), tree order, 3 each
+    int nlpitem = 0, nfarlev = 0;     // downward-pass items (far cell, 32 points); levels 2.. in far_s
+    fmddm::DBuf<int> lp_cell, lp_p0;
     fmddm::DBuf<double> part_s;       // near-field partial stresses per work item
     fmddm::DBuf<double> ksplit;       // split-K partial products
     // dense operator (built on demand)

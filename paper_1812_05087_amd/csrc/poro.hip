@@ -446,19 +446,22 @@ __global__ __launch_bounds__(PN) void k_pp2p(int nitem, const int *__restrict__ 
 // far + near (in item order) -> (shear, normal traction, pressure), caller
 // order; mode 0: =, 1: -=; o2 (if given): drained elastic tractions added
 __global__ void k_pfinal(int n, const int *__restrict__ tleaf, const int *__restrict__ leaves,
-                         const int *__restrict__ pbeg, const int *__restrict__ lk_off,
-                         const int *__restrict__ it_poff, const double *__restrict__ part,
-                         const double *__restrict__ far, const double *__restrict__ cb,
-                         const double *__restrict__ sb, const int *__restrict__ perm,
-                         const double *__restrict__ o2, int mode, double *__restrict__ out)
+                         const int *__restrict__ pbeg, const int *__restrict__ level,
+                         const int *__restrict__ lk_off, const int *__restrict__ it_poff,
+                         const double *__restrict__ part, const double *__restrict__ far,
+                         const double *__restrict__ cb, const double *__restrict__ sb,
+                         const int *__restrict__ perm, const double *__restrict__ o2, int mode,
+                         double *__restrict__ out)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int li = tleaf[i];
-    int t = i - pbeg[leaves[li]];
+    int cl = leaves[li];
+    int t = i - pbeg[cl];
     double s[4] = {0.0, 0.0, 0.0, 0.0};
-    if (far)
-        for (int c = 0; c < 4; ++c) s[c] = far[4 * (size_t)i + c];
+    if (far)  // the point's cells at levels 2 .. its leaf's, in level order
+        for (int l = 2; l <= level[cl]; ++l)
+            for (int c = 0; c < 4; ++c) s[c] += far[((size_t)(l - 2) * n + i) * 4 + c];
     for (int k = lk_off[li]; k < lk_off[li + 1]; ++k) {
         const double *o = part + 4 * ((size_t)it_poff[k] + t);
         for (int c = 0; c < 4; ++c) s[c] += o[c];
@@ -602,7 +605,7 @@ void poro_fmm_setup(fmddm_ctx *ctx, fmddm_tree *t, int H)
         t->pf_G.alloc((size_t)ncell * Mq);
         t->pf_G.zero(s);
         t->pf_Z.alloc((size_t)std::max<int64_t>(t->nV, 1) * Mq);
-        t->pf_far.alloc(4 * (size_t)t->n);
+        t->pf_far.alloc(4 * (size_t)std::max(t->nfarlev, 1) * t->n);
         t->pf_near.alloc(4 * (size_t)std::max<int64_t>(t->npartial, 1));
         t->pf_D2.alloc(2 * (size_t)t->n);
         t->pf_o2.alloc(2 * (size_t)t->n);
@@ -669,7 +672,8 @@ void poro_fmm_sum(fmddm_ctx *ctx, fmddm_tree *t, int H, const double *E, bool dr
         o2 = t->pf_o2.p;
     }
     hipLaunchKernelGGL(k_pfinal, dim3(cdiv(n, 256)), dim3(256), 0, s, n, t->tleaf.p, t->dleaves.p, t->cpbeg.p,
-                       t->lk_off.p, t->it_poff.p, t->pf_near.p, far ? t->pf_far.p : (const double *)nullptr,
+                       t->clevel.p, t->lk_off.p, t->it_poff.p, t->pf_near.p,
+                       far ? t->pf_far.p : (const double *)nullptr,
                        t->scb.p, t->ssb.p, t->perm.p, o2, mode, out);
     FM_CHECK_LAUNCH();
 }
