@@ -72,6 +72,16 @@ typedef enum {
     FMDDM_M2L_SVD = 1         /* the same operators compressed by a truncated SVD */
 } fmddm_m2l_mode;
 
+/* Arithmetic of the FMM product's two heavy passes, the near field (P2P)
+ * and the M2L products.  P2M, M2M, L2P, the sums of the far and near parts
+ * and everything in GMRES stay FP64. */
+typedef enum {
+    FMDDM_PREC_FP64 = 0,      /* everything FP64 */
+    FMDDM_PREC_FP32 = 1,      /* P2P in FP32; M2L on FP32 MFMA, FP32 sums */
+    FMDDM_PREC_BF16 = 2       /* P2P in FP32; M2L on BF16 MFMA (operators and
+                                 weights rounded to bf16), FP32 sums */
+} fmddm_precision;
+
 typedef struct {
     double E, nu;             /* material (Pa, -) */
     int leaf;                 /* split a cell holding more than `leaf` points (Section 3.1) */
@@ -85,6 +95,10 @@ typedef struct {
     double root_x0, root_y0, root_L;
     int restart, maxit;       /* GMRES(restart), at most maxit matrix-vector products */
     double tol;               /* GMRES relative residual target */
+    int precision;            /* fmddm_precision of FMDDM_APPLY_FMM products */
+    double inner_tol;         /* reduced precision: relative residual target of
+                                 each inner GMRES solve of iterative refinement
+                                 (0 = 1e-5 for FP32, 3e-3 for BF16) */
 } fmddm_params;
 
 typedef struct {
@@ -104,13 +118,16 @@ typedef struct {
 typedef struct {
     int32_t iters;            /* matrix-vector products inside GMRES */
     int32_t restarts;
-    double relres;            /* ||b - A x|| / ||b|| of the returned iterate (true residual) */
+    double relres;            /* ||b - A x|| / ||b|| of the returned iterate (true residual;
+                                 with the FP64 product under iterative refinement) */
     int32_t converged;
+    int32_t refinements;      /* iterative refinement: outer steps, i.e. FP64
+                                 residual products (0 for a plain GMRES solve) */
 } fmddm_solve_info;
 
 /* Fill *p with defaults: E=20e9, nu=0.25, leaf=32, p=20, max_level=24,
  * kappa=8, m2l=DENSE, m2l_tol=1e-12, no root box, restart=50,
- * maxit=10000, tol=1e-10. */
+ * maxit=10000, tol=1e-10, precision=FP64, inner_tol=0. */
 void fmddm_default_params(fmddm_params *p);
 
 /* Create a context on the current HIP device bound to `hip_stream`
@@ -160,7 +177,9 @@ fmddm_status fmddm_tree_export_list(fmddm_ctx *ctx, const fmddm_tree *t, int whi
 /* out = A D for the single-step elastic influence operator (device
  * pointers, 2n doubles each; out may not alias D).  mode selects the FMM
  * (Section 3), the exact on-the-fly product or the stored dense matrix
- * (assembled on first use: 32 n^2 bytes; ENOMEM if it does not fit). */
+ * (assembled on first use: 32 n^2 bytes; ENOMEM if it does not fit).
+ * The FMM product runs at the context's precision (fmddm_precision); the
+ * exact products are always FP64. */
 fmddm_status fmddm_apply(fmddm_ctx *ctx, fmddm_tree *t, int mode, const double *D,
                          double *out);
 
@@ -177,7 +196,14 @@ fmddm_status fmddm_rhs(fmddm_ctx *ctx, fmddm_tree *t, const double *pf, double S
  * (device, 2n).  Orthogonalisation (classical Gram-Schmidt, applied twice),
  * Givens rotations and the residual checks run on the device in FP64; the
  * final residual is recomputed from b - A x.  FMDDM_ENOTCONV when maxit is
- * reached (the best iterate is returned).  Synchronises the stream. */
+ * reached (the best iterate is returned).  Synchronises the stream.
+ *
+ * With mode FMM and a reduced precision the solve is iterative refinement:
+ * r = rhs - A D with the FP64 FMM product, an inner GMRES (FP64 basis,
+ * orthogonalisation and rotations) solves A' d = r with the reduced-precision
+ * product A' to inner_tol relative, D += d, until ||r|| <= tol ||rhs||.
+ * maxit bounds the inner products; ENOTCONV also when a refinement step
+ * fails to reduce ||r|| (A' too far from A for the system's conditioning). */
 fmddm_status fmddm_solve(fmddm_ctx *ctx, fmddm_tree *t, int mode, const double *rhs,
                          double *D, fmddm_solve_info *info);
 

@@ -23,6 +23,7 @@ FMDDM_OK, FMDDM_ENOTCONV = 0, 1
 FMDDM_EINVAL, FMDDM_ENOMEM, FMDDM_EDEVICE, FMDDM_EGEOM, FMDDM_EUNSUPPORTED = -1, -2, -3, -4, -5
 FMDDM_APPLY_FMM, FMDDM_APPLY_DIRECT, FMDDM_APPLY_DENSE = 0, 1, 2
 FMDDM_M2L_DENSE, FMDDM_M2L_SVD = 0, 1
+FMDDM_PREC_FP64, FMDDM_PREC_FP32, FMDDM_PREC_BF16 = 0, 1, 2
 LIST_U, LIST_V, LIST_W, LIST_X = 0, 1, 2, 3
 
 EXPORTED = [
@@ -53,6 +54,7 @@ class Params(C.Structure):
         ("kappa", C.c_double), ("m2l", C.c_int), ("m2l_tol", C.c_double),
         ("use_root_box", C.c_int), ("root_x0", C.c_double), ("root_y0", C.c_double),
         ("root_L", C.c_double), ("restart", C.c_int), ("maxit", C.c_int), ("tol", C.c_double),
+        ("precision", C.c_int), ("inner_tol", C.c_double),
     ]
 
 
@@ -87,7 +89,7 @@ class PoroParams(C.Structure):
 
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("relres", C.c_double),
-                ("converged", C.c_int32)]
+                ("converged", C.c_int32), ("refinements", C.c_int32)]
 
 
 _lib = None
@@ -263,7 +265,7 @@ def fmddm_solve(ctx, tree, mode, rhs, D):
     info = SolveInfo()
     st = _check(lib().fmddm_solve(ctx, tree, mode, _ptr(rhs), _ptr(D), C.byref(info)), ctx)
     return st, {"iters": info.iters, "restarts": info.restarts, "relres": info.relres,
-                "converged": bool(info.converged)}
+                "converged": bool(info.converged), "refinements": info.refinements}
 
 
 def fmddm_sif(ctx, tree, D, elem):

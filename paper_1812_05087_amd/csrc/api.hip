@@ -49,6 +49,8 @@ const char *check_params(const fmddm_params *p)
     if (p->restart < 1 || p->restart > 1000) return "restart must lie in [1, 1000]";
     if (p->maxit < 0) return "maxit must be >= 0";
     if (!(p->tol >= 0.0)) return "tol must be >= 0";
+    if (p->precision < FMDDM_PREC_FP64 || p->precision > FMDDM_PREC_BF16) return "unknown precision";
+    if (!(p->inner_tol >= 0.0 && p->inner_tol < 1.0)) return "inner_tol must lie in [0, 1)";
     return nullptr;
 }
 
@@ -266,6 +268,10 @@ fmddm_status fmddm_poro_set(fmddm_ctx *ctx, const fmddm_poro_params *pp)
         ctx->err = "poroelastic parameters: need nu < nu_u < 0.5, 0 < alpha <= 1, perm, visc, dt > 0, "
                    "mode DIRECT or FMM";
         return FMDDM_EINVAL;
+    }
+    if (ctx->prm.precision != FMDDM_PREC_FP64) {
+        ctx->err = "the poroelastic operators are FP64 only";
+        return FMDDM_EUNSUPPORTED;
     }
     if (pp->mode == FMDDM_APPLY_FMM && (ctx->prm.p < 2 || ctx->prm.p > 16)) {
         ctx->err = "poroelastic FMM needs 2 <= p <= 16";

@@ -62,6 +62,34 @@ __device__ __forceinline__ void elem_stress_add(double X, double Y, double cx, d
     sxy += cs * (lxx - lyy) + (c2 - s2) * lxy;
 }
 
+// The same element stress in FP32 arithmetic, for the reduced-precision
+// product.  The receiver-element offset (dx, dy) comes in already formed in
+// FP64 (coordinates of a 100 m domain would lose the element scale if
+// rounded to FP32 first); the local frame, the rational functions and the
+// rotation are FP32, with the hardware reciprocal (1 ulp).
+__device__ __forceinline__ void elem_stress_add32(float dx, float dy, float cb, float sb, float a, float Ds,
+                                                  float Dn, float gc, float &sxx, float &syy, float &sxy)
+{
+    float x = dx * cb + dy * sb;
+    float y = dy * cb - dx * sb;
+    float xm = x - a, xp = x + a, y2 = y * y;
+    float i1 = __builtin_amdgcn_rcpf(xm * xm + y2);
+    float i2 = __builtin_amdgcn_rcpf(xp * xp + y2);
+    float fxy = y * (i1 - i2);
+    float fyy = xp * i2 - xm * i1;
+    float j1 = i1 * i1, j2 = i2 * i2;
+    float fxyy = (xm * xm - y2) * j1 - (xp * xp - y2) * j2;
+    float fyyy = 2.0f * y * (xm * j1 - xp * j2);
+    float yfxyy = y * fxyy, yfyyy = y * fyyy;
+    float lxx = -gc * (Ds * (2.0f * fxy + yfxyy) + Dn * (fyy + yfyyy));
+    float lyy = -gc * (Dn * (fyy - yfyyy) - Ds * yfxyy);
+    float lxy = -gc * (Ds * (fyy + yfyyy) - Dn * yfxyy);
+    float c2 = cb * cb, s2 = sb * sb, cs = cb * sb;
+    sxx += c2 * lxx - 2.0f * cs * lxy + s2 * lyy;
+    syy += s2 * lxx + 2.0f * cs * lxy + c2 * lyy;
+    sxy += cs * (lxx - lyy) + (c2 - s2) * lxy;
+}
+
 // Shear and normal traction on a receiver with tangent (cb, sb).
 __device__ __forceinline__ void traction(double cb, double sb, double sxx, double syy, double sxy,
                                          double &ts, double &tn)

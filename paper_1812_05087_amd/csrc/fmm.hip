@@ -416,36 +416,201 @@ __global__ __launch_bounds__(256) void k_ggemm(const double *__restrict__ ops, s
 }
 
 // out[i] = sum over the split-K slices of part[z * stride + i], in order.
-__global__ void k_reduce_split(int64_t count, int nsplit, size_t stride, const double *__restrict__ part,
-                               double *__restrict__ out)
+template <typename T>
+__global__ void k_reduce_split(int64_t count, int nsplit, size_t stride, const T *__restrict__ part,
+                               T *__restrict__ out)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count) return;
-    double s = 0.0;
+    T s = 0;
     for (int z = 0; z < nsplit; ++z) s += part[(size_t)z * stride + i];
     out[i] = s;
 }
 
-// out[c] = sum of the pair products of cell c, in V-list order.
+// out[c] = sum of the pair products of cell c, in V-list order, accumulated
+// in the precision of the products.
+template <typename TI, typename TO>
 __global__ __launch_bounds__(256) void k_sum_pairs(int nfar, const int *__restrict__ far_cells,
-                                                   const int *__restrict__ voff, const double *__restrict__ Z,
-                                                   int ldz, int width, double *__restrict__ out, int ldo)
+                                                   const int *__restrict__ voff, const TI *__restrict__ Z,
+                                                   int ldz, int width, TO *__restrict__ out, int ldo)
 {
     constexpr int U = 8;  // loads in flight per thread; the sum stays in list order
     int c = far_cells[xcd_remap(blockIdx.x, nfar)];
     int kb = voff[c], ke = voff[c + 1];
     for (int e = threadIdx.x; e < width; e += 256) {
-        double s = 0.0;
+        TI s = 0;
         for (int k0 = kb; k0 < ke; k0 += U) {
-            double v[U];
+            TI v[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) v[u] = Z[(size_t)min(k0 + u, ke - 1) * ldz + e];
 #pragma unroll
             for (int u = 0; u < U; ++u)
                 if (k0 + u < ke) s += v[u];
         }
-        out[(size_t)c * ldo + e] = s;
+        out[(size_t)c * ldo + e] = (TO)s;
     }
+}
+
+// ------------------------------------------- reduced-precision M2L products
+// The grouped product of k_ggemm with operands held in FP32 or BF16 and the
+// sums accumulated in FP32.  Operands are converted to the compute type CT
+// (float, or bf16 as uint16_t bits) as they are staged in LDS, where both
+// sit with k contiguous: As[m][k], Bs[n][k].  In each 16-deep k-step lane L
+// reads the four consecutive k = kk + 4 (L/16) + i of row L%16 of both: one
+// v_mfma_f32_16x16x16bf16_1k, or four v_mfma_f32_16x16x4f32 of which the
+// i-th sums k = kk + 4 (L/16) + i (the order of a sum's index is free as
+// long as A and B agree).  Accumulator register r of lane L holds
+// D[4 (L/16) + r][L%16] for both instructions.
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef short s4 __attribute__((ext_vector_type(4)));
+
+// float -> bf16 bits, round to nearest even (finite inputs)
+__device__ __forceinline__ uint32_t bf16_bits(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+
+__device__ __forceinline__ void ld4(const double *p, float v[4])
+{
+    double2 a = *(const double2 *)p, b = *(const double2 *)(p + 2);
+    v[0] = (float)a.x; v[1] = (float)a.y; v[2] = (float)b.x; v[3] = (float)b.y;
+}
+__device__ __forceinline__ void ld4(const float *p, float v[4])
+{
+    float4 a = *(const float4 *)p;
+    v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
+}
+__device__ __forceinline__ void ld4(const uint16_t *p, float v[4])
+{
+    uint2 a = *(const uint2 *)p;
+    v[0] = __uint_as_float(a.x << 16); v[1] = __uint_as_float(a.x & 0xffff0000u);
+    v[2] = __uint_as_float(a.y << 16); v[3] = __uint_as_float(a.y & 0xffff0000u);
+}
+__device__ __forceinline__ void st4(float *p, const float v[4]) { *(float4 *)p = float4{v[0], v[1], v[2], v[3]}; }
+__device__ __forceinline__ void st4(uint16_t *p, const float v[4])
+{
+    *(uint2 *)p = uint2{bf16_bits(v[0]) | (bf16_bits(v[1]) << 16), bf16_bits(v[2]) | (bf16_bits(v[3]) << 16)};
+}
+
+template <typename CT> struct LdsPad;           // row padding of the LDS tiles, in elements
+template <> struct LdsPad<float> { static constexpr int v = 4; };
+template <> struct LdsPad<uint16_t> { static constexpr int v = 8; };
+
+template <int BM, int BN, int GK, typename CT, typename TA, typename TX, typename TZ>
+__global__ __launch_bounds__(256) void k_lgemm(const TA *__restrict__ ops, size_t op_stride, int lda, int Kd,
+                                               const TX *__restrict__ X, int ldx, const int *__restrict__ tile_op,
+                                               const int *__restrict__ tile_beg, const int *__restrict__ tile_end,
+                                               const int *__restrict__ pair_src, const int *__restrict__ pair_dst,
+                                               const double *__restrict__ pair_scale, TZ *__restrict__ Z, int ldz,
+                                               size_t zsplit)
+{
+    constexpr int WM = BM / 32, WN = BN / 32, KP = GK + LdsPad<CT>::v;
+    constexpr int G4 = GK / 4;                       // 4-element groups per row and k-step
+    constexpr int RA = (BM * G4 + 255) / 256, RB = (BN * G4 + 255) / 256;
+    __shared__ __align__(16) CT As[BM][KP];
+    __shared__ __align__(16) CT Bs[BN][KP];
+    __shared__ int src[BN];
+    int tile = blockIdx.x, mt = blockIdx.y;
+    int o = tile_op[tile], pb = tile_beg[tile], np = tile_end[tile] - pb;
+    int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    int wm = wave >> 1, wn = wave & 1;
+    int ksteps = Kd / GK, per = (ksteps + gridDim.z - 1) / gridDim.z;
+    int kb = min(Kd, (int)blockIdx.z * per * GK), ke = min(Kd, kb + per * GK);
+    Z += (size_t)blockIdx.z * zsplit;
+    if (tid < BN) src[tid] = tid < np ? pair_src[pb + tid] : -1;
+    const TA *A = ops + (size_t)o * op_stride + (size_t)mt * BM * lda;
+    f4 acc[WM][WN];
+#pragma unroll
+    for (int i = 0; i < WM; ++i)
+#pragma unroll
+        for (int j = 0; j < WN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    __syncthreads();
+    float ra[RA][4], rb[RB][4];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int r = 0; r < RA; ++r) {
+            int e = tid + r * 256;
+            if (e < BM * G4) ld4(A + (size_t)(e / G4) * lda + k0 + 4 * (e % G4), ra[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            int e = tid + r * 256;
+            if (e < BN * G4) {
+                int s = src[e / G4];
+                if (s >= 0) ld4(X + (size_t)s * ldx + k0 + 4 * (e % G4), rb[r]);
+                else rb[r][0] = rb[r][1] = rb[r][2] = rb[r][3] = 0.f;
+            }
+        }
+    };
+    if (kb < ke) fetch(kb);
+    for (int k0 = kb; k0 < ke; k0 += GK) {
+#pragma unroll
+        for (int r = 0; r < RA; ++r) {
+            int e = tid + r * 256;
+            if (e < BM * G4) st4(&As[e / G4][4 * (e % G4)], ra[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            int e = tid + r * 256;
+            if (e < BN * G4) st4(&Bs[e / G4][4 * (e % G4)], rb[r]);
+        }
+        __syncthreads();
+        if (k0 + GK < ke) fetch(k0 + GK);
+#pragma unroll
+        for (int kk = 0; kk < GK; kk += 16) {
+            int kq = kk + 4 * (lane >> 4);
+            if constexpr (sizeof(CT) == 4) {
+                f4 av[WM], bv[WN];
+#pragma unroll
+                for (int i = 0; i < WM; ++i) av[i] = *(const f4 *)&As[wm * (BM / 2) + i * 16 + (lane & 15)][kq];
+#pragma unroll
+                for (int j = 0; j < WN; ++j) bv[j] = *(const f4 *)&Bs[wn * (BN / 2) + j * 16 + (lane & 15)][kq];
+#pragma unroll
+                for (int i = 0; i < WM; ++i)
+#pragma unroll
+                    for (int j = 0; j < WN; ++j)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i][c], bv[j][c], acc[i][j], 0, 0, 0);
+            } else {
+                s4 av[WM], bv[WN];
+#pragma unroll
+                for (int i = 0; i < WM; ++i) av[i] = *(const s4 *)&As[wm * (BM / 2) + i * 16 + (lane & 15)][kq];
+#pragma unroll
+                for (int j = 0; j < WN; ++j) bv[j] = *(const s4 *)&Bs[wn * (BN / 2) + j * 16 + (lane & 15)][kq];
+#pragma unroll
+                for (int i = 0; i < WM; ++i)
+#pragma unroll
+                    for (int j = 0; j < WN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[i], bv[j], acc[i][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < WN; ++j) {
+        int col = wn * (BN / 2) + j * 16 + (lane & 15);
+        if (col >= np) continue;
+        float sc = pair_scale ? (float)pair_scale[pb + col] : 1.0f;
+        TZ *z = Z + (size_t)pair_dst[pb + col] * ldz + mt * BM;
+#pragma unroll
+        for (int i = 0; i < WM; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) z[wm * (BM / 2) + i * 16 + 4 * (lane >> 4) + r] = (TZ)(sc * acc[i][j][r]);
+    }
+}
+
+// Operator copies for the reduced-precision products.
+__global__ void k_to_f32(int64_t n, const double *__restrict__ a, float *__restrict__ b)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+__global__ void k_to_bf16(int64_t n, const double *__restrict__ a, uint16_t *__restrict__ b)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (uint16_t)bf16_bits((float)a[i]);
 }
 
 // Unit-size M2L operators: target square centred at the origin, half-width
@@ -609,9 +774,12 @@ __global__ __launch_bounds__(LT) void k_l2p(int nitem, const int *__restrict__ i
 // of the X lists of the leaf and its ancestors, flattened per leaf), so a
 // leaf with a large near list is spread over several blocks.  Sources are
 // staged in LDS; `tpt` adjacent lanes per point combine in a fixed order;
-// the item's partial stresses go to part_s.
+// the item's partial stresses go to part_s.  RT = float is the
+// reduced-precision variant: offsets formed in FP64, the element formulas
+// and the per-point sums in FP32.
 constexpr int NT = 128, MAXE = 256;
 
+template <typename RT>
 __global__ __launch_bounds__(NT) void k_p2p(
     int nitem, const int *__restrict__ it_leaf, const int *__restrict__ it_s0, const int *__restrict__ it_s1,
     const int *__restrict__ it_poff, const int *__restrict__ leaves, const int *__restrict__ pbeg,
@@ -620,8 +788,8 @@ __global__ __launch_bounds__(NT) void k_p2p(
     const double *__restrict__ cb, const double *__restrict__ sb, const double *__restrict__ a,
     const double *__restrict__ Ds, double gc, double *__restrict__ part)
 {
-    __shared__ double s_cx[NEAR_CHUNK], s_cy[NEAR_CHUNK], s_cb[NEAR_CHUNK], s_sb[NEAR_CHUNK],
-        s_a[NEAR_CHUNK], s_ds[NEAR_CHUNK], s_dn[NEAR_CHUNK];
+    __shared__ double s_cx[NEAR_CHUNK], s_cy[NEAR_CHUNK];
+    __shared__ RT s_cb[NEAR_CHUNK], s_sb[NEAR_CHUNK], s_a[NEAR_CHUNK], s_ds[NEAR_CHUNK], s_dn[NEAR_CHUNK];
     __shared__ int s_pre[MAXE], s_beg[MAXE];
     int k = xcd_remap(blockIdx.x, nitem);
     int li = it_leaf[k], s0 = it_s0[k], s1 = it_s1[k];
@@ -646,8 +814,8 @@ __global__ __launch_bounds__(NT) void k_p2p(
         }
         int j = (lds ? s_beg[lo] : nbeg[nb + lo]) + (v - (lds ? s_pre[lo] : npre[nb + lo]));
         int q = v - s0;
-        s_cx[q] = cx[j]; s_cy[q] = cy[j]; s_cb[q] = cb[j]; s_sb[q] = sb[j];
-        s_a[q] = a[j]; s_ds[q] = Ds[2 * j]; s_dn[q] = Ds[2 * j + 1];
+        s_cx[q] = cx[j]; s_cy[q] = cy[j]; s_cb[q] = (RT)cb[j]; s_sb[q] = (RT)sb[j];
+        s_a[q] = (RT)a[j]; s_ds[q] = (RT)Ds[2 * j]; s_dn[q] = (RT)Ds[2 * j + 1];
     }
     __syncthreads();
     int cnt = s1 - s0;
@@ -659,11 +827,19 @@ __global__ __launch_bounds__(NT) void k_p2p(
         int i = t0 + tid / tpt;
         bool act = i < te;
         double X = act ? cx[i] : 0.0, Y = act ? cy[i] : 0.0;
-        double sxx = 0.0, syy = 0.0, sxy = 0.0;
-        if (act)
-            for (int q = sub; q < cnt; q += tpt)
-                elem_stress_add(X, Y, s_cx[q], s_cy[q], s_cb[q], s_sb[q], s_a[q], s_ds[q], s_dn[q], gc, sxx,
-                                syy, sxy);
+        RT sxx = 0, syy = 0, sxy = 0;
+        if (act) {
+            if constexpr (sizeof(RT) == 8) {
+                for (int q = sub; q < cnt; q += tpt)
+                    elem_stress_add(X, Y, s_cx[q], s_cy[q], s_cb[q], s_sb[q], s_a[q], s_ds[q], s_dn[q], gc, sxx,
+                                    syy, sxy);
+            } else {
+                float g = (float)gc;
+                for (int q = sub; q < cnt; q += tpt)
+                    elem_stress_add32((float)(X - s_cx[q]), (float)(Y - s_cy[q]), s_cb[q], s_sb[q], s_a[q],
+                                      s_ds[q], s_dn[q], g, sxx, syy, sxy);
+            }
+        }
         for (int w = 1; w < tpt; w <<= 1) {
             sxx += __shfl_xor(sxx, w);
             syy += __shfl_xor(syy, w);
@@ -750,6 +926,125 @@ void launch_ggemm(hipStream_t s, int ntile, int Mrows, const double *ops, size_t
         hipLaunchKernelGGL((k_ggemm<BM, BN, 16>), dim3(ntile, Mrows / BM, nsplit), dim3(256), 0, s, ops, op_stride,
                            lda, Kd, X, ldx, top, tbeg, tend, psrc, pdst, pscale, Z, ldz, zsplit);
     FM_CHECK_LAUNCH();
+}
+
+template <int BM, int BN, typename CT, typename TA, typename TX, typename TZ>
+void launch_lgemm(hipStream_t s, int ntile, int Mrows, const TA *ops, size_t op_stride, int lda, int Kd,
+                  const TX *X, int ldx, const int *top, const int *tbeg, const int *tend, const int *psrc,
+                  const int *pdst, const double *pscale, TZ *Z, int ldz, int nsplit = 1, size_t zsplit = 0)
+{
+    if (ntile == 0) return;
+    // 4-element vector loads need rows and k-steps on multiples of 4
+    if (Mrows % BM || Kd % 16 || lda % 4 || ldx % 4 || op_stride % 4)
+        throw Error{FMDDM_EDEVICE, "GEMM shape not tiled"};
+    if (Kd % 64 == 0 && Kd >= 512)
+        hipLaunchKernelGGL((k_lgemm<BM, BN, 64, CT, TA, TX, TZ>), dim3(ntile, Mrows / BM, nsplit), dim3(256), 0, s,
+                           ops, op_stride, lda, Kd, X, ldx, top, tbeg, tend, psrc, pdst, pscale, Z, ldz, zsplit);
+    else
+        hipLaunchKernelGGL((k_lgemm<BM, BN, 16, CT, TA, TX, TZ>), dim3(ntile, Mrows / BM, nsplit), dim3(256), 0, s,
+                           ops, op_stride, lda, Kd, X, ldx, top, tbeg, tend, psrc, pdst, pscale, Z, ldz, zsplit);
+    FM_CHECK_LAUNCH();
+}
+
+// The M2L products (projection, translation, expansion) at reduced
+// precision: CT the MFMA operand type, TO the stored operators' type.
+// Weights in: Wexp (FP64); fields out: Gexp (FP64); FP32 in between.
+template <typename CT, typename TO>
+void m2l_lowp(hipStream_t s, fmddm_tree *t, const M2LOps &M, const TO *Vt, const TO *ops, const TO *Ur,
+              Profiler &P)
+{
+    int Mp = M.Mp, rp = M.rp;
+    hipEvent_t e0;
+    if (M.mode == FMDDM_M2L_SVD) {
+        P.begin(FMDDM_PH_COMPRESS, s, e0);
+        launch_lgemm<32, 32, CT>(s, t->nftile, rp, Vt, 0, Mp, Mp, t->Wexp.p, Mp, t->ftile_op.p, t->ftile_beg.p,
+                                 t->ftile_end.p, t->far_cells.p, t->far_cells.p, nullptr, t->ksplit32.p, rp,
+                                 KSPLIT, (size_t)t->ncell * rp);
+        P.end(FMDDM_PH_COMPRESS, s, e0);
+        P.begin(FMDDM_PH_COMPRESS_SUM, s, e0);
+        {
+            int64_t c0 = t->level_start[2], cnt = (int64_t)(t->ncell - c0) * rp;
+            hipLaunchKernelGGL(k_reduce_split<float>, dim3(cdiv(cnt, 256)), dim3(256), 0, s, cnt, KSPLIT,
+                               (size_t)t->ncell * rp, t->ksplit32.p + c0 * rp, t->What32.p + c0 * rp);
+            FM_CHECK_LAUNCH();
+        }
+        P.end(FMDDM_PH_COMPRESS_SUM, s, e0);
+        P.begin(FMDDM_PH_M2L, s, e0);
+        launch_lgemm<64, 32, CT>(s, t->ntile, rp, ops, (size_t)rp * rp, rp, rp, t->What32.p, rp, t->tile_op.p,
+                                 t->tile_beg.p, t->tile_end.p, t->pair_src.p, t->pair_dst.p, t->pair_scale.p,
+                                 t->Zm2l32.p, rp);
+        P.end(FMDDM_PH_M2L, s, e0);
+        P.begin(FMDDM_PH_M2L_SUM, s, e0);
+        hipLaunchKernelGGL((k_sum_pairs<float, float>), dim3(t->nfar), dim3(256), 0, s, t->nfar, t->far_cells.p,
+                           t->loff[1].p, t->Zm2l32.p, rp, rp, t->Ghat32.p, rp);
+        FM_CHECK_LAUNCH();
+        P.end(FMDDM_PH_M2L_SUM, s, e0);
+        P.begin(FMDDM_PH_DECOMPRESS, s, e0);
+        launch_lgemm<64, 32, CT>(s, t->nftile, Mp, Ur, 0, rp, rp, t->Ghat32.p, rp, t->ftile_op.p,
+                                 t->ftile_beg.p, t->ftile_end.p, t->far_cells.p, t->far_cells.p, nullptr,
+                                 t->Gexp.p, Mp);
+        P.end(FMDDM_PH_DECOMPRESS, s, e0);
+    } else {
+        P.begin(FMDDM_PH_M2L, s, e0);
+        launch_lgemm<64, 32, CT>(s, t->ntile, Mp, ops, (size_t)Mp * Mp, Mp, Mp, t->Wexp.p, Mp, t->tile_op.p,
+                                 t->tile_beg.p, t->tile_end.p, t->pair_src.p, t->pair_dst.p, t->pair_scale.p,
+                                 t->Zm2l32.p, Mp);
+        P.end(FMDDM_PH_M2L, s, e0);
+        P.begin(FMDDM_PH_M2L_SUM, s, e0);
+        hipLaunchKernelGGL((k_sum_pairs<float, double>), dim3(t->nfar), dim3(256), 0, s, t->nfar,
+                           t->far_cells.p, t->loff[1].p, t->Zm2l32.p, Mp, Mp, t->Gexp.p, Mp);
+        FM_CHECK_LAUNCH();
+        P.end(FMDDM_PH_M2L_SUM, s, e0);
+    }
+}
+
+// Reduced-precision operator copies (once per operator set) and the tree's
+// FP32 intermediates (once per tree).
+void setup_lowp(fmddm_ctx *ctx, fmddm_tree *t, int prec)
+{
+    M2LOps &M = *ctx->m2l;
+    hipStream_t s = ctx->stream;
+    auto conv32 = [&](const DBuf<double> &a, DBuf<float> &b) {
+        b.alloc(a.n);
+        hipLaunchKernelGGL(k_to_f32, dim3(cdiv(a.n, 256)), dim3(256), 0, s, (int64_t)a.n, a.p, b.p);
+        FM_CHECK_LAUNCH();
+    };
+    auto conv16 = [&](const DBuf<double> &a, DBuf<uint16_t> &b) {
+        b.alloc(a.n);
+        hipLaunchKernelGGL(k_to_bf16, dim3(cdiv(a.n, 256)), dim3(256), 0, s, (int64_t)a.n, a.p, b.p);
+        FM_CHECK_LAUNCH();
+    };
+    bool svd = M.mode == FMDDM_M2L_SVD;
+    if (prec == FMDDM_PREC_FP32 && !M.have32) {
+        conv32(M.ops, M.ops32);
+        if (svd) {
+            conv32(M.Vt, M.Vt32);
+            conv32(M.Ur, M.Ur32);
+        }
+        FM_HIP(hipStreamSynchronize(s));
+        M.have32 = true;
+    }
+    if (prec == FMDDM_PREC_BF16 && !M.have16) {
+        conv16(M.ops, M.ops16);
+        if (svd) {
+            conv16(M.Vt, M.Vt16);
+            conv16(M.Ur, M.Ur16);
+        }
+        FM_HIP(hipStreamSynchronize(s));
+        M.have16 = true;
+    }
+    if (!t->Zm2l32.p) {
+        int w = svd ? M.rp : M.Mp;
+        t->Zm2l32.alloc((size_t)std::max<int64_t>(t->nV, 1) * w);
+        if (svd) {
+            t->What32.alloc((size_t)t->ncell * M.rp);
+            t->Ghat32.alloc((size_t)t->ncell * M.rp);
+            t->ksplit32.alloc((size_t)KSPLIT * t->ncell * M.rp);
+            t->What32.zero(s);
+            t->Ghat32.zero(s);
+        }
+        FM_HIP(hipStreamSynchronize(s));
+    }
 }
 
 template <int P, int NC = 3>
@@ -946,7 +1241,7 @@ void fmm_pair_gemm(hipStream_t s, int ntile, int Mrows, const double *ops, size_
 void fmm_sum_pairs(hipStream_t s, fmddm_tree *t, const double *Z, int ldz, int width, double *out, int ldo)
 {
     if (t->nfar == 0) return;
-    hipLaunchKernelGGL(k_sum_pairs, dim3(t->nfar), dim3(256), 0, s, t->nfar, t->far_cells.p, t->loff[1].p, Z, ldz,
+    hipLaunchKernelGGL((k_sum_pairs<double, double>), dim3(t->nfar), dim3(256), 0, s, t->nfar, t->far_cells.p, t->loff[1].p, Z, ldz,
                        width, out, ldo);
     FM_CHECK_LAUNCH();
 }
@@ -1239,9 +1534,10 @@ void setup_fmm(fmddm_ctx *ctx, fmddm_tree *t)
     FM_HIP(hipStreamSynchronize(s));
 }
 
-void fmm_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out)
+void fmm_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out, int prec)
 {
     setup_fmm(ctx, t);
+    if (prec != FMDDM_PREC_FP64) setup_lowp(ctx, t, prec);
     hipStream_t s = ctx->stream;
     const M2LOps &M = *ctx->m2l;
     int p = ctx->prm.p, Mp = M.Mp, rp = M.rp, n = (int)t->n;
@@ -1260,9 +1556,16 @@ void fmm_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out)
     FM_HIP(hipStreamWaitEvent(s2, ctx->ev_fork, 0));
     hipEvent_t e1;
     P.begin(FMDDM_PH_P2P, s2, e1);
-    hipLaunchKernelGGL(k_p2p, dim3(t->nitem), dim3(NT), 0, s2, t->nitem, t->it_leaf.p, t->it_s0.p, t->it_s1.p,
-                       t->it_poff.p, t->dleaves.p, t->cpbeg.p, t->cpend.p, t->noff.p, t->nbeg.p, t->npre.p,
-                       t->scx.p, t->scy.p, t->scb.p, t->ssb.p, t->sa.p, t->Dsort.p, ctx->gc, t->part_s.p);
+    if (prec == FMDDM_PREC_FP64)
+        hipLaunchKernelGGL(k_p2p<double>, dim3(t->nitem), dim3(NT), 0, s2, t->nitem, t->it_leaf.p, t->it_s0.p,
+                           t->it_s1.p, t->it_poff.p, t->dleaves.p, t->cpbeg.p, t->cpend.p, t->noff.p, t->nbeg.p,
+                           t->npre.p, t->scx.p, t->scy.p, t->scb.p, t->ssb.p, t->sa.p, t->Dsort.p, ctx->gc,
+                           t->part_s.p);
+    else
+        hipLaunchKernelGGL(k_p2p<float>, dim3(t->nitem), dim3(NT), 0, s2, t->nitem, t->it_leaf.p, t->it_s0.p,
+                           t->it_s1.p, t->it_poff.p, t->dleaves.p, t->cpbeg.p, t->cpend.p, t->noff.p, t->nbeg.p,
+                           t->npre.p, t->scx.p, t->scy.p, t->scb.p, t->ssb.p, t->sa.p, t->Dsort.p, ctx->gc,
+                           t->part_s.p);
     FM_CHECK_LAUNCH();
     P.end(FMDDM_PH_P2P, s2, e1);
     FM_HIP(hipEventRecord(ctx->ev_join, s2));
@@ -1285,7 +1588,11 @@ void fmm_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out)
             FM_CHECK_LAUNCH();
             P.end(FMDDM_PH_M2M_SUM, s, e0);
         }
-        if (M.mode == FMDDM_M2L_SVD) {
+        if (prec == FMDDM_PREC_FP32) {
+            m2l_lowp<float>(s, t, M, M.Vt32.p, M.ops32.p, M.Ur32.p, P);
+        } else if (prec == FMDDM_PREC_BF16) {
+            m2l_lowp<uint16_t>(s, t, M, M.Vt16.p, M.ops16.p, M.Ur16.p, P);
+        } else if (M.mode == FMDDM_M2L_SVD) {
             // projection onto the singular vectors: K = 3p^2 is long and the
             // output small, so K is split over KSPLIT blocks and summed after
             P.begin(FMDDM_PH_COMPRESS, s, e0);
@@ -1296,7 +1603,7 @@ void fmm_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out)
             P.begin(FMDDM_PH_COMPRESS_SUM, s, e0);
             {
                 int64_t c0 = t->level_start[2], cnt = (int64_t)(t->ncell - c0) * rp;
-                hipLaunchKernelGGL(k_reduce_split, dim3(cdiv(cnt, 256)), dim3(256), 0, s, cnt, KSPLIT,
+                hipLaunchKernelGGL(k_reduce_split<double>, dim3(cdiv(cnt, 256)), dim3(256), 0, s, cnt, KSPLIT,
                                    (size_t)t->ncell * rp, t->ksplit.p + c0 * rp, t->What.p + c0 * rp);
                 FM_CHECK_LAUNCH();
             }
@@ -1307,7 +1614,7 @@ void fmm_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out)
                                  t->Zm2l.p, rp);
             P.end(FMDDM_PH_M2L, s, e0);
             P.begin(FMDDM_PH_M2L_SUM, s, e0);
-            hipLaunchKernelGGL(k_sum_pairs, dim3(t->nfar), dim3(256), 0, s, t->nfar, t->far_cells.p,
+            hipLaunchKernelGGL((k_sum_pairs<double, double>), dim3(t->nfar), dim3(256), 0, s, t->nfar, t->far_cells.p,
                                t->loff[1].p, t->Zm2l.p, rp, rp, t->Ghat.p, rp);
             FM_CHECK_LAUNCH();
             P.end(FMDDM_PH_M2L_SUM, s, e0);
@@ -1323,7 +1630,7 @@ void fmm_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out)
                                  t->Zm2l.p, Mp);
             P.end(FMDDM_PH_M2L, s, e0);
             P.begin(FMDDM_PH_M2L_SUM, s, e0);
-            hipLaunchKernelGGL(k_sum_pairs, dim3(t->nfar), dim3(256), 0, s, t->nfar, t->far_cells.p,
+            hipLaunchKernelGGL((k_sum_pairs<double, double>), dim3(t->nfar), dim3(256), 0, s, t->nfar, t->far_cells.p,
                                t->loff[1].p, t->Zm2l.p, Mp, Mp, t->Gexp.p, Mp);
             FM_CHECK_LAUNCH();
             P.end(FMDDM_PH_M2L_SUM, s, e0);

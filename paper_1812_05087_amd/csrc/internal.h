@@ -87,6 +87,10 @@ struct M2LOps {
     DBuf<double> Ur;        // compressed mode: Mp x rp, columns = left singular vectors
     DBuf<double> Vt;        // compressed mode: rp x Mp, rows = the same vectors
     std::vector<double> sv; // normalised singular values (compressed mode)
+    // reduced-precision copies of ops / Vt / Ur, made on first use
+    bool have32 = false, have16 = false;
+    DBuf<float> ops32, Vt32, Ur32;
+    DBuf<uint16_t> ops16, Vt16, Ur16;   // bf16 bit patterns
 };
 
 }  // namespace fmddm
@@ -190,6 +194,8 @@ struct fmddm_tree {
     fmddm::DBuf<int> lp_cell, lp_p0;
     fmddm::DBuf<double> part_s;       // near-field partial stresses per work item
     fmddm::DBuf<double> ksplit;       // split-K partial products
+    // reduced-precision M2L intermediates (FP32), allocated on first use
+    fmddm::DBuf<float> What32, Zm2l32, Ghat32, ksplit32;
     // dense operator (built on demand)
     fmddm::DBuf<double> Adense;
     // solver workspace; gm_host is pinned host memory the device writes the
@@ -236,7 +242,8 @@ void fmm_pair_gemm(hipStream_t s, int ntile, int Mrows, const double *ops, size_
                    const int *psrc, const int *pdst, double *Z, int ldz);
 void fmm_sum_pairs(hipStream_t s, fmddm_tree *t, const double *Z, int ldz, int width, double *out, int ldo);
 void setup_fmm(fmddm_ctx *ctx, fmddm_tree *t);
-void fmm_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out);
+// prec: fmddm_precision of the near field and the M2L products
+void fmm_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out, int prec = FMDDM_PREC_FP64);
 // direct.hip
 void direct_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out);
 void dense_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out);
@@ -273,6 +280,9 @@ struct GmresRun {
 void apply_mode(fmddm_ctx *ctx, fmddm_tree *t, int mode, const double *D, double *out);
 // apply mode of the poroelastic left-hand side F(dt) (3 unknowns per element)
 constexpr int APPLY_PORO = 100;
+// the FP64 FMM product whatever the context's precision (residuals of
+// iterative refinement)
+constexpr int APPLY_FMM_FP64 = 101;
 inline int64_t vec_len(const fmddm_tree *t, int mode) { return (mode == APPLY_PORO ? 3 : 2) * t->n; }
 // poro.hip
 void poro_apply(fmddm_ctx *ctx, fmddm_tree *t, int lag, const double *D, double *out);

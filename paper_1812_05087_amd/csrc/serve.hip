@@ -243,6 +243,7 @@ fmddm_status fmddm_server_create(const fmddm_params *p, int max_slots, int64_t h
     if (!out) return FMDDM_EINVAL;
     *out = nullptr;
     if (!p || max_slots < 1 || max_slots > 64 || hbm_budget < 0) return FMDDM_EINVAL;
+    if (p->precision != FMDDM_PREC_FP64) return FMDDM_EUNSUPPORTED;  // served solves are FP64 GMRES
     fmddm_server *s = new (std::nothrow) fmddm_server();
     if (!s) return FMDDM_ENOMEM;
     s->prm = *p;

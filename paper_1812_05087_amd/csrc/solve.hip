@@ -100,6 +100,12 @@ __global__ void k_residual(int m, const double *__restrict__ b, const double *__
     if (t < m) r[t] = b[t] - Ax[t];
 }
 
+__global__ void k_axpy1(int m, const double *__restrict__ d, double *__restrict__ x)
+{
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < m) x[t] += d[t];
+}
+
 // Scalar workspace layout (doubles): g[m+1] | cs[m] | sn[m] | H[(m+1) x m]
 // column-major | h1[m+1] | h2[m+1] | y[m] | nrm | est
 struct SW {
@@ -184,7 +190,8 @@ void rhs_build(fmddm_ctx *ctx, fmddm_tree *t, const double *pf, double SH, doubl
 void apply_mode(fmddm_ctx *ctx, fmddm_tree *t, int mode, const double *D, double *out)
 {
     switch (mode) {
-    case FMDDM_APPLY_FMM: fmm_apply(ctx, t, D, out); break;
+    case FMDDM_APPLY_FMM: fmm_apply(ctx, t, D, out, ctx->prm.precision); break;
+    case APPLY_FMM_FP64: fmm_apply(ctx, t, D, out, FMDDM_PREC_FP64); break;
     case FMDDM_APPLY_DIRECT: direct_apply(ctx, t, D, out); break;
     case FMDDM_APPLY_DENSE: dense_apply(ctx, t, D, out); break;
     case APPLY_PORO: poro_apply(ctx, t, 0, D, out); break;
@@ -350,9 +357,80 @@ bool GmresRun::advance(bool block)
     }
 }
 
+// Mixed-precision solve by iterative refinement: the residual with the FP64
+// FMM product, corrections from GMRES on the reduced-precision product (its
+// basis, orthogonalisation and rotations FP64).  A correction solved to
+// relative residual tau on an operator A' with ||A - A'|| / ||A|| = delta
+// reduces the FP64 residual by about tau + kappa(A) delta per step.
+static fmddm_status ir_solve(fmddm_ctx *ctx, fmddm_tree *t, const double *b, double *x, fmddm_solve_info *info)
+{
+    hipStream_t st = ctx->stream;
+    const int n2 = (int)(2 * t->n), gb = cdiv(n2, 256);
+    double tau = ctx->prm.inner_tol > 0.0 ? ctx->prm.inner_tol
+                                          : (ctx->prm.precision == FMDDM_PREC_FP32 ? 1e-5 : 3e-3);
+    DBuf<double> r, d, ax, nrm;
+    r.alloc(n2);
+    d.alloc(n2);
+    ax.alloc(n2);
+    nrm.alloc(1);
+    auto norm = [&](const double *v) {
+        hipLaunchKernelGGL(k_norm, dim3(1), dim3(RT), 0, st, n2, v, nrm.p);
+        FM_CHECK_LAUNCH();
+        double h;
+        FM_HIP(hipMemcpyAsync(&h, nrm.p, 8, hipMemcpyDeviceToHost, st));
+        FM_HIP(hipStreamSynchronize(st));
+        return h;
+    };
+    *info = fmddm_solve_info{};
+    double bnorm = norm(b);
+    if (!std::isfinite(bnorm)) throw Error{FMDDM_EINVAL, "non-finite right-hand side"};
+    if (bnorm == 0.0) {
+        hipLaunchKernelGGL(k_fill, dim3(gb), dim3(256), 0, st, n2, 0.0, x);
+        FM_CHECK_LAUNCH();
+        FM_HIP(hipStreamSynchronize(st));
+        info->converged = 1;
+        return FMDDM_OK;
+    }
+    double prev = INFINITY;
+    for (;;) {
+        fmm_apply(ctx, t, x, ax.p, FMDDM_PREC_FP64);
+        hipLaunchKernelGGL(k_residual, dim3(gb), dim3(256), 0, st, n2, b, ax.p, r.p);
+        FM_CHECK_LAUNCH();
+        double rn = norm(r.p);
+        ++info->refinements;
+        info->relres = rn / bnorm;
+        if (!std::isfinite(rn)) throw Error{FMDDM_EDEVICE, "non-finite residual"};
+        if (rn <= ctx->prm.tol * bnorm) {
+            info->converged = 1;
+            return FMDDM_OK;
+        }
+        // no progress: the reduced-precision operator is too far from the
+        // FP64 one for this system
+        if (rn >= 0.99 * prev || info->iters >= ctx->prm.maxit) return FMDDM_ENOTCONV;
+        prev = rn;
+        // on the last step the inner solve need not beat the outer target
+        double tin = std::min(0.5, std::max(tau, 0.3 * ctx->prm.tol * bnorm / rn));
+        hipLaunchKernelGGL(k_fill, dim3(gb), dim3(256), 0, st, n2, 0.0, d.p);
+        FM_CHECK_LAUNCH();
+        GmresRun g;
+        g.start(ctx, t, FMDDM_APPLY_FMM, r.p, d.p, tin, ctx->prm.maxit - info->iters);
+        while (!g.advance(true)) {
+        }
+        info->iters += g.it;
+        info->restarts += g.restarts;
+        hipLaunchKernelGGL(k_axpy1, dim3(gb), dim3(256), 0, st, n2, d.p, x);
+        FM_CHECK_LAUNCH();
+    }
+}
+
 fmddm_status gmres_solve(fmddm_ctx *ctx, fmddm_tree *t, int mode, const double *b, double *x,
                          fmddm_solve_info *info)
 {
+    if (mode == FMDDM_APPLY_FMM && ctx->prm.precision != FMDDM_PREC_FP64) {
+        fmddm_status stt = ir_solve(ctx, t, b, x, info);
+        FM_HIP(hipStreamSynchronize(ctx->stream));
+        return stt;
+    }
     GmresRun g;
     g.start(ctx, t, mode, b, x, ctx->prm.tol, ctx->prm.maxit);
     while (!g.advance(true)) {
@@ -361,6 +439,7 @@ fmddm_status gmres_solve(fmddm_ctx *ctx, fmddm_tree *t, int mode, const double *
     info->restarts = g.restarts;
     info->relres = g.relres;
     info->converged = g.converged;
+    info->refinements = 0;
     FM_HIP(hipStreamSynchronize(ctx->stream));
     return g.converged ? FMDDM_OK : FMDDM_ENOTCONV;
 }
