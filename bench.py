@@ -238,6 +238,86 @@ def history_leg(F, W, elems, steps, p=10):
     return out
 
 
+def precision_leg(F, W, steps, tune, leaf, p, solve_tol=1e-8, target_err=1e-6):
+    """Mixed precision at N=200000 (2000 random fractures x 100 elements,
+    seed 4): autotuned leaf and p for the FP64 product, then products and
+    solves at FP64, FP32 and BF16-M2L on that configuration.  Errors of each
+    product against the FP64 FMM product and the exact product (on-the-fly
+    FP64 on the GPU); each solve reaches tol on the FP64 FMM residual, and
+    its exact-operator residual and distance to the FP64 solve are stated."""
+    import torch
+    wl = W.c4()
+    n = wl.n
+    out = {"workload": "2000 random pressurized fractures x 100 elements, N=200000, seed 4", "N": n,
+           "solve_tol": solve_tol}
+    common = dict(E=wl.E, nu=wl.nu, m2l=F.FMDDM_M2L_SVD, m2l_tol=1e-10, restart=50, maxit=20000)
+    if tune:
+        base = F.fmddm_default_params(**common)
+        t0 = time.perf_counter()
+        st, best, log = F.fmddm_autotune(base, wl.x1, wl.y1, wl.x2, wl.y2, leaves=(16, 32, 64, 128),
+                                         ps=tuple(range(8, 25, 2)), target_err=target_err, reps=5)
+        out["autotune"] = {"seconds": time.perf_counter() - t0, "target_err": target_err, "status": st,
+                           "leaf": best.leaf, "p": best.p, "tried": log}
+        leaf, p = best.leaf, best.p
+    out["leaf"], out["p"] = leaf, p
+    D = None
+    res = {}
+    y = {}
+    x = {}
+    b = None
+    ref = None
+    for name, prec in [("fp64", F.FMDDM_PREC_FP64), ("fp32", F.FMDDM_PREC_FP32), ("bf16", F.FMDDM_PREC_BF16)]:
+        prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, leaf=leaf, p=p, precision=prec, tol=solve_tol, **common)
+        if D is None:
+            D = prob.vec(W.random_vector(9, n))
+            b = prob.rhs(wl.pressure, wl.SH, wl.Sh)
+        o = prob.vec()
+        prob.apply(D, F.FMDDM_APPLY_FMM, o)
+        for _ in range(3):
+            prob.apply(D, F.FMDDM_APPLY_FMM, o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            prob.apply(D, F.FMDDM_APPLY_FMM, o)
+        torch.cuda.synchronize()
+        r = {"matvecs_per_s": steps / (time.perf_counter() - t0)}
+        y[name] = o.cpu().numpy()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xs, info = prob.solve(b)
+        torch.cuda.synchronize()
+        r["solve_s"] = time.perf_counter() - t0
+        r["solve"] = info
+        x[name] = xs
+        if name == "fp64":
+            ref = prob            # kept for the exact products below
+        else:
+            prob.close()
+        res[name] = r
+    # exact (on-the-fly FP64) products on the GPU
+    ex = ref.apply(D, F.FMDDM_APPLY_DIRECT)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ref.apply(D, F.FMDDM_APPLY_DIRECT, ex)
+    torch.cuda.synchronize()
+    out["direct_matvecs_per_s"] = 1.0 / (time.perf_counter() - t0)
+    ex = ex.cpu().numpy()
+    rel = lambda a, c: float(np.abs(a - c).max() / np.abs(c).max())
+    bn = float(torch.linalg.norm(b))
+    for name in res:
+        res[name]["product_err_vs_fp64_fmm"] = rel(y[name], y["fp64"])
+        res[name]["product_err_vs_exact"] = rel(y[name], ex)
+        ax = ref.apply(x[name], F.FMDDM_APPLY_DIRECT)
+        res[name]["solution_exact_residual"] = float(torch.linalg.norm(b - ax)) / bn
+        res[name]["solution_diff_vs_fp64_solve"] = float(torch.linalg.norm(x[name] - x["fp64"]) /
+                                                         torch.linalg.norm(x["fp64"]))
+        res[name]["matvecs_over_fp64"] = res[name]["matvecs_per_s"] / res["fp64"]["matvecs_per_s"]
+        res[name]["solve_speedup_over_fp64"] = res["fp64"]["solve_s"] / res[name]["solve_s"]
+    ref.close()
+    out["precisions"] = res
+    return out
+
+
 def cpu_baseline(wl, D, seconds):
     """The oracle's exact on-the-fly product of the whole workload on all
     host cores, repeated for about `seconds` of wall time."""
@@ -276,6 +356,11 @@ def main():
                     help="only copy 256 MiB device-to-device 5 times (reference for HBM byte counters)")
     ap.add_argument("--history-elems", type=int, default=4000)
     ap.add_argument("--history-steps", type=int, default=10)
+    ap.add_argument("--precision-steps", type=int, default=20,
+                    help="products timed per precision at N=200000 (0 skips the mixed-precision leg)")
+    ap.add_argument("--precision-no-tune", action="store_true")
+    ap.add_argument("--precision-leaf", type=int, default=64)
+    ap.add_argument("--precision-p", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs one instance per GPU and has no "
@@ -406,6 +491,9 @@ def main():
         line["serving"] = serving_leg(F, W, args.serve_requests, args.serve_slots, args.serve_load)
     if args.history_elems > 0:
         line["history"] = history_leg(F, W, args.history_elems, args.history_steps)
+    if args.precision_steps > 0:
+        line["mixed_precision"] = precision_leg(F, W, args.precision_steps, not args.precision_no_tune,
+                                                args.precision_leaf, args.precision_p)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, Dh, args.cpu_seconds)
     print(json.dumps(line), flush=True)

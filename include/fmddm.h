@@ -96,9 +96,6 @@ typedef struct {
     int restart, maxit;       /* GMRES(restart), at most maxit matrix-vector products */
     double tol;               /* GMRES relative residual target */
     int precision;            /* fmddm_precision of FMDDM_APPLY_FMM products */
-    double inner_tol;         /* reduced precision: relative residual target of
-                                 each inner GMRES solve of iterative refinement
-                                 (0 = 1e-5 for FP32, 3e-3 for BF16) */
 } fmddm_params;
 
 typedef struct {
@@ -121,13 +118,13 @@ typedef struct {
     double relres;            /* ||b - A x|| / ||b|| of the returned iterate (true residual;
                                  with the FP64 product under iterative refinement) */
     int32_t converged;
-    int32_t refinements;      /* iterative refinement: outer steps, i.e. FP64
-                                 residual products (0 for a plain GMRES solve) */
+    int32_t refinements;      /* reduced precision: FP64 residual products (one
+                                 per restart cycle plus the last); 0 otherwise */
 } fmddm_solve_info;
 
 /* Fill *p with defaults: E=20e9, nu=0.25, leaf=32, p=20, max_level=24,
  * kappa=8, m2l=DENSE, m2l_tol=1e-12, no root box, restart=50,
- * maxit=10000, tol=1e-10, precision=FP64, inner_tol=0. */
+ * maxit=10000, tol=1e-10, precision=FP64. */
 void fmddm_default_params(fmddm_params *p);
 
 /* Create a context on the current HIP device bound to `hip_stream`
@@ -198,12 +195,14 @@ fmddm_status fmddm_rhs(fmddm_ctx *ctx, fmddm_tree *t, const double *pf, double S
  * final residual is recomputed from b - A x.  FMDDM_ENOTCONV when maxit is
  * reached (the best iterate is returned).  Synchronises the stream.
  *
- * With mode FMM and a reduced precision the solve is iterative refinement:
- * r = rhs - A D with the FP64 FMM product, an inner GMRES (FP64 basis,
- * orthogonalisation and rotations) solves A' d = r with the reduced-precision
- * product A' to inner_tol relative, D += d, until ||r|| <= tol ||rhs||.
- * maxit bounds the inner products; ENOTCONV also when a refinement step
- * fails to reduce ||r|| (A' too far from A for the system's conditioning). */
+ * With mode FMM and a reduced precision every restart cycle is a step of
+ * iterative refinement: the residual r = rhs - A D it starts from is
+ * computed with the FP64 FMM product A, the cycle's Arnoldi steps use the
+ * reduced-precision product A' (basis, orthogonalisation, rotations and the
+ * update of D stay FP64), and convergence is ||r|| <= tol ||rhs|| with the
+ * FP64 product.  maxit bounds the reduced-precision products; ENOTCONV also
+ * when a cycle fails to reduce ||r|| (A' too far from A for the system's
+ * conditioning).  info->refinements counts the FP64 residuals. */
 fmddm_status fmddm_solve(fmddm_ctx *ctx, fmddm_tree *t, int mode, const double *rhs,
                          double *D, fmddm_solve_info *info);
 
@@ -212,6 +211,38 @@ fmddm_status fmddm_solve(fmddm_ctx *ctx, fmddm_tree *t, int mode, const double *
  * K = 0.806 E / (4 (1 - nu^2)) sqrt(pi / (2 a)) D.  Synchronises. */
 fmddm_status fmddm_sif(fmddm_ctx *ctx, fmddm_tree *t, const double *D, int64_t elem,
                        double *KI, double *KII);
+
+/* One configuration tried by fmddm_autotune. */
+typedef struct {
+    int32_t leaf, p;
+    double ms;                /* mean time of one FMM product (ms); -1 when not
+                                 timed (error target missed) */
+    double err;               /* ||y - y_exact|| / ||y_exact|| for uniform opening */
+} fmddm_tune_entry;
+
+/* Choose the leaf size and the Chebyshev order for one geometry (host
+ * endpoints, n elements).  The paper sets the order by hand and gives no
+ * rule for the leaf size (Section 5); this measures both: for every leaf
+ * size in leaves[0..nleaves) the orders ps[0..nps) are tried in ascending
+ * order until the FMM product's relative error (2-norm) against the exact
+ * product is at most target_err; that configuration's product is
+ * timed (reps products on the device) and the fastest over the leaf sizes
+ * is kept.  The test vector is a uniform opening (Dn = 1e-3, Ds = 0 on every
+ * element): smooth, like the DDs of loaded fractures, it weighs the far
+ * field as solutions do, where a random vector is dominated by the near
+ * field (which the FMM evaluates exactly).  Every other field of *base
+ * (material, M2L mode, precision,
+ * solver settings) is used as given.  *best = *base with leaf and p set.
+ * log[0..log_cap) receives each configuration tried (log may be NULL when
+ * log_cap = 0), *nlog (may be NULL) their number.  FMDDM_ENOTCONV when no
+ * configuration meets the target (*best is then the most accurate one).
+ * Runs on a stream of its own on the current device and synchronises it;
+ * allocates trees and operators for the duration of the call. */
+fmddm_status fmddm_autotune(const fmddm_params *base, int64_t n, const double *x1,
+                            const double *y1, const double *x2, const double *y2,
+                            const int32_t *leaves, int32_t nleaves, const int32_t *ps,
+                            int32_t nps, double target_err, int32_t reps, fmddm_params *best,
+                            fmddm_tune_entry *log, int32_t log_cap, int32_t *nlog);
 
 /* Phases of one FMM product, for fmddm_profile. */
 typedef enum {                /* one entry per kernel of an FMM product */

@@ -35,6 +35,7 @@ EXPORTED = [
     "fmddm_server_submit", "fmddm_server_step", "fmddm_server_poll", "fmddm_server_release",
     "fmddm_memory_in_use", "fmddm_memory_cached", "fmddm_trim_cache",
     "fmddm_poro_set", "fmddm_poro_apply", "fmddm_add_history", "fmddm_poro_rhs", "fmddm_poro_solve",
+    "fmddm_autotune",
 ]
 FMDDM_REQ_QUEUED, FMDDM_REQ_RUNNING, FMDDM_REQ_DONE, FMDDM_REQ_FAILED = 0, 1, 2, 3
 PHASES = ["prep", "p2m", "m2m", "m2m_sum", "compress", "compress_sum", "m2l", "m2l_sum", "decompress",
@@ -54,7 +55,7 @@ class Params(C.Structure):
         ("kappa", C.c_double), ("m2l", C.c_int), ("m2l_tol", C.c_double),
         ("use_root_box", C.c_int), ("root_x0", C.c_double), ("root_y0", C.c_double),
         ("root_L", C.c_double), ("restart", C.c_int), ("maxit", C.c_int), ("tol", C.c_double),
-        ("precision", C.c_int), ("inner_tol", C.c_double),
+        ("precision", C.c_int),
     ]
 
 
@@ -85,6 +86,10 @@ class Result(C.Structure):
 class PoroParams(C.Structure):
     _fields_ = [("nu_u", C.c_double), ("alpha", C.c_double), ("perm", C.c_double), ("visc", C.c_double),
                 ("dt", C.c_double), ("p0", C.c_double), ("mode", C.c_int32)]
+
+
+class TuneEntry(C.Structure):
+    _fields_ = [("leaf", C.c_int32), ("p", C.c_int32), ("ms", C.c_double), ("err", C.c_double)]
 
 
 class SolveInfo(C.Structure):
@@ -142,6 +147,9 @@ def lib():
         L.fmddm_add_history.argtypes = [_vp, _vp, C.c_int, _vp, _vp]
         L.fmddm_poro_rhs.argtypes = [_vp, _vp, _vp, C.c_double, C.c_double, _vp]
         L.fmddm_poro_solve.argtypes = [_vp, _vp, _vp, _vp, C.POINTER(SolveInfo)]
+        L.fmddm_autotune.argtypes = [C.POINTER(Params), C.c_int64, _vp, _vp, _vp, _vp, _vp, C.c_int32, _vp,
+                                     C.c_int32, C.c_double, C.c_int32, C.POINTER(Params), _vp, C.c_int32,
+                                     C.POINTER(C.c_int32)]
         for name in EXPORTED:
             f = getattr(L, name)
             if name not in ("fmddm_default_params", "fmddm_destroy", "fmddm_tree_free",
@@ -266,6 +274,25 @@ def fmddm_solve(ctx, tree, mode, rhs, D):
     st = _check(lib().fmddm_solve(ctx, tree, mode, _ptr(rhs), _ptr(D), C.byref(info)), ctx)
     return st, {"iters": info.iters, "restarts": info.restarts, "relres": info.relres,
                 "converged": bool(info.converged), "refinements": info.refinements}
+
+
+def fmddm_autotune(params: Params, x1, y1, x2, y2, leaves=(16, 32, 64, 128), ps=tuple(range(8, 25, 2)),
+                   target_err=1e-6, reps=10):
+    """Returns (status, best Params, [TuneEntry as dict, ...])."""
+    x1, y1, x2, y2 = (np.ascontiguousarray(v, dtype=np.float64) for v in (x1, y1, x2, y2))
+    lv = (C.c_int32 * len(leaves))(*leaves)
+    pv = (C.c_int32 * len(ps))(*ps)
+    cap = len(leaves) * len(ps)
+    log = (TuneEntry * cap)()
+    nlog = C.c_int32()
+    best = Params()
+    dp = lambda a: a.ctypes.data_as(C.c_void_p)
+    st = lib().fmddm_autotune(C.byref(params), int(x1.shape[0]), dp(x1), dp(y1), dp(x2), dp(y2), lv,
+                              len(leaves), pv, len(ps), float(target_err), int(reps), C.byref(best), log,
+                              cap, C.byref(nlog))
+    if st < 0:
+        raise FmddmError(st, "autotune failed")
+    return st, best, [{k: getattr(log[i], k) for k, _ in TuneEntry._fields_} for i in range(nlog.value)]
 
 
 def fmddm_sif(ctx, tree, D, elem):

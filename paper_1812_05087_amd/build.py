@@ -9,7 +9,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfmddm.so")
-SOURCES = ["api.hip", "alloc.hip", "tree.hip", "fmm.hip", "direct.hip", "solve.hip", "serve.hip", "poro.hip"]
+SOURCES = ["api.hip", "alloc.hip", "tree.hip", "fmm.hip", "direct.hip", "solve.hip", "serve.hip", "poro.hip",
+           "tune.hip"]
+OBJDIR = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -21,10 +23,26 @@ FLAGS = [
 LIBS = ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
 
 
-def build(verbose: bool = False) -> str:
-    """Always recompiles; the library is written atomically."""
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Always recompiles (one hipcc per source, in parallel, then one link);
+    the library is written atomically."""
+    from concurrent.futures import ThreadPoolExecutor
+    os.makedirs(OBJDIR, exist_ok=True)
+    jobs = jobs or min(len(SOURCES), os.cpu_count() or 1, 16)
+    cflags = [f for f in FLAGS if f != "-shared"]
+
+    def compile_one(src):
+        obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
+        cmd = [HIPCC, *cflags, "-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        return obj
+
+    with ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(compile_one, SOURCES))
     out = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, *[os.path.join(CSRC, s) for s in SOURCES], "-o", out, *LIBS]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", out, *LIBS]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

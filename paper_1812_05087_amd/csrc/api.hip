@@ -50,7 +50,6 @@ const char *check_params(const fmddm_params *p)
     if (p->maxit < 0) return "maxit must be >= 0";
     if (!(p->tol >= 0.0)) return "tol must be >= 0";
     if (p->precision < FMDDM_PREC_FP64 || p->precision > FMDDM_PREC_BF16) return "unknown precision";
-    if (!(p->inner_tol >= 0.0 && p->inner_tol < 1.0)) return "inner_tol must lie in [0, 1)";
     return nullptr;
 }
 

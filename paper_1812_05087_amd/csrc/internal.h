@@ -200,7 +200,7 @@ struct fmddm_tree {
     fmddm::DBuf<double> Adense;
     // solver workspace; gm_host is pinned host memory the device writes the
     // residual norm and estimate to, gm_ev marks when they have arrived
-    fmddm::DBuf<double> gm_V, gm_w, gm_r, gm_sc;
+    fmddm::DBuf<double> gm_V, gm_w, gm_r, gm_sc, gm_part;
     int gm_restart = 0;
     int64_t gm_len = 0;
     // poroelastic workspace: chunk partials, term times, term vectors
@@ -213,12 +213,13 @@ struct fmddm_tree {
     fmddm::DBuf<int> pf_tile_op, pf_tile_beg, pf_tile_end, pf_psrc, pf_pdst, pf_combo_lvl, pf_combo_ox,
         pf_combo_oy;
     fmddm::DBuf<double> pf_ops, pf_W, pf_part, pf_Z, pf_G, pf_far, pf_Q, pf_D3, pf_near, pf_D2, pf_o2;
-    double *gm_host = nullptr;
-    hipEvent_t gm_ev = nullptr;
+    double *gm_host = nullptr;        // 2 slots of 2 doubles
+    hipEvent_t gm_ev[2] = {nullptr, nullptr};
     int64_t bytes = 0;
     ~fmddm_tree()
     {
-        if (gm_ev) (void)hipEventDestroy(gm_ev);
+        for (hipEvent_t e : gm_ev)
+            if (e) (void)hipEventDestroy(e);
         if (gm_host) (void)hipHostFree(gm_host);
     }
 };
@@ -262,20 +263,31 @@ fmddm_status gmres_solve(fmddm_ctx *ctx, fmddm_tree *t, int mode, const double *
 struct GmresRun {
     fmddm_ctx *ctx = nullptr;
     fmddm_tree *t = nullptr;
-    int mode = 0;
+    int mode = 0;                  // product of the Arnoldi steps
+    int rmode = 0;                 // product of the residuals at the restarts
+    double prev_beta = 0.0;        // residual at the previous restart (mixed precision)
     const double *b = nullptr;
     double *x = nullptr;
     double tol = 0.0;
     int maxit = 0;
     enum State { IDLE, BNORM, RESID, ITER, DONE } state = IDLE;
-    int j = 0, it = 0, restarts = 0;
+    int j = 0;                     // oldest Arnoldi step whose scalars are unread
+    int next = 0;                  // next Arnoldi step to enqueue (at most j + 2)
+    int it = 0, restarts = 0, residuals = 0;
     double bnorm = 0.0, relres = 0.0;
     bool converged = false;
-    void start(fmddm_ctx *c, fmddm_tree *tr, int md, const double *rhs, double *x0, double tl, int mx);
+    // rmd < 0: residuals with the Arnoldi product.  A different residual
+    // product makes each restart cycle a step of iterative refinement: the
+    // cycle's Krylov space is built with `md`, the residual it corrects and
+    // the stopping test use `rmd`; a cycle that does not reduce that
+    // residual ends the solve (not converged).
+    void start(fmddm_ctx *c, fmddm_tree *tr, int md, const double *rhs, double *x0, double tl, int mx,
+               int rmd = -1);
     bool advance(bool block);  // true once finished
   private:
     void enqueue_residual();
     void enqueue_step();
+    void post(int slot, int count);
 };
 void apply_mode(fmddm_ctx *ctx, fmddm_tree *t, int mode, const double *D, double *out);
 // apply mode of the poroelastic left-hand side F(dt) (3 unknowns per element)

@@ -48,18 +48,43 @@ __device__ double block_sum(double v, double *red)
     return r;
 }
 
-// out[i] = V_i . w for i < k (one block per i).
-__global__ __launch_bounds__(RT) void k_dots(int m, int k, const double *__restrict__ V, int ldv,
-                                             const double *__restrict__ w, double *__restrict__ out)
+// Dot products V_i . w (i < k) in two fixed-order stages.  Stage 1: block c
+// takes the chunk [c DCH, (c+1) DCH) of the vectors, stages w's chunk in
+// LDS, and each of its four waves forms the chunk's partial dot for
+// i = wave, wave + 4, ... (lanes stride the chunk, then a shuffle tree);
+// part[i * nchunk + c].  Stage 2: one block per i sums the partials in
+// chunk order.  The vectors are read once in total, over m / DCH blocks.
+constexpr int DCH = 1024;
+
+__global__ __launch_bounds__(RT) void k_dots_part(int m, int k, const double *__restrict__ V, int ldv,
+                                                  const double *__restrict__ w, int nchunk,
+                                                  double *__restrict__ part)
+{
+    __shared__ double ws[DCH];
+    int c = blockIdx.x, t0 = c * DCH, len = min(DCH, m - t0);
+    for (int t = threadIdx.x; t < DCH; t += RT) ws[t] = t < len ? w[t0 + t] : 0.0;
+    __syncthreads();
+    int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i = wave; i < k; i += RT / 64) {
+        const double *v = V + (size_t)i * ldv + t0;
+        double s = 0.0;
+#pragma unroll 4
+        for (int t = lane; t < len; t += 64) s += v[t] * ws[t];
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+        if (lane == 0) part[(size_t)i * nchunk + c] = s;
+    }
+}
+
+// out[i] = sum over chunks of part[i * nchunk + c]; sqrt of it if `root`
+__global__ __launch_bounds__(RT) void k_dots_sum(int nchunk, const double *__restrict__ part, int root,
+                                                 double *__restrict__ out)
 {
     __shared__ double red[RT];
     int i = blockIdx.x;
-    if (i >= k) return;
-    const double *v = V + (size_t)i * ldv;
     double s = 0.0;
-    for (int t = threadIdx.x; t < m; t += RT) s += v[t] * w[t];
+    for (int c = threadIdx.x; c < nchunk; c += RT) s += part[(size_t)i * nchunk + c];
     s = block_sum(s, red);
-    if (threadIdx.x == 0) out[i] = s;
+    if (threadIdx.x == 0) out[i] = root ? sqrt(s) : s;
 }
 
 // w += sign * sum_{i<k} h[i] V_i
@@ -73,15 +98,6 @@ __global__ void k_vupdate(int m, int k, const double *__restrict__ V, int ldv,
     w[t] += sign * s;
 }
 
-// Single-block norm: out = ||w||.
-__global__ __launch_bounds__(RT) void k_norm(int m, const double *__restrict__ w, double *__restrict__ out)
-{
-    __shared__ double red[RT];
-    double s = 0.0;
-    for (int t = threadIdx.x; t < m; t += RT) s += w[t] * w[t];
-    s = block_sum(s, red);
-    if (threadIdx.x == 0) *out = sqrt(s);
-}
 
 // v = src / *nrm (v = 0 when the norm vanishes)
 __global__ void k_scale(int m, const double *__restrict__ src, const double *__restrict__ nrm,
@@ -98,12 +114,6 @@ __global__ void k_residual(int m, const double *__restrict__ b, const double *__
 {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < m) r[t] = b[t] - Ax[t];
-}
-
-__global__ void k_axpy1(int m, const double *__restrict__ d, double *__restrict__ x)
-{
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < m) x[t] += d[t];
 }
 
 // Scalar workspace layout (doubles): g[m+1] | cs[m] | sn[m] | H[(m+1) x m]
@@ -176,6 +186,24 @@ __global__ void k_sif(const double *__restrict__ D, const double *__restrict__ a
     out[1] = f * D[2 * e];
 }
 
+// out[0..k) = V_i . w, with the partials in `part` (k * nchunk doubles)
+void dots(hipStream_t st, int m, int k, const double *V, int ldv, const double *w, double *part, double *out)
+{
+    int nchunk = cdiv(m, DCH);
+    hipLaunchKernelGGL(k_dots_part, dim3(nchunk), dim3(RT), 0, st, m, k, V, ldv, w, nchunk, part);
+    hipLaunchKernelGGL(k_dots_sum, dim3(k), dim3(RT), 0, st, nchunk, part, 0, out);
+    FM_CHECK_LAUNCH();
+}
+
+// *out = ||w||
+void norm2(hipStream_t st, int m, const double *w, double *part, double *out)
+{
+    int nchunk = cdiv(m, DCH);
+    hipLaunchKernelGGL(k_dots_part, dim3(nchunk), dim3(RT), 0, st, m, 1, w, 0, w, nchunk, part);
+    hipLaunchKernelGGL(k_dots_sum, dim3(1), dim3(RT), 0, st, nchunk, part, 1, out);
+    FM_CHECK_LAUNCH();
+}
+
 }  // namespace
 
 void rhs_build(fmddm_ctx *ctx, fmddm_tree *t, const double *pf, double SH, double Sh, double *rhs,
@@ -221,33 +249,47 @@ static void gmres_workspace(fmddm_tree *t, int m, int n2)
         t->gm_w.alloc(ldv);
         t->gm_r.alloc(ldv);
         t->gm_sc.alloc(s.size());
+        t->gm_part.alloc((size_t)(m + 1) * cdiv(n2, DCH));
         t->gm_restart = m;
         t->gm_len = n2;
     }
-    if (!t->gm_host) FM_HIP(hipHostMalloc((void **)&t->gm_host, 2 * sizeof(double), hipHostMallocDefault));
-    if (!t->gm_ev) FM_HIP(hipEventCreateWithFlags(&t->gm_ev, hipEventDisableTiming));
+    if (!t->gm_host) FM_HIP(hipHostMalloc((void **)&t->gm_host, 4 * sizeof(double), hipHostMallocDefault));
+    for (int k = 0; k < 2; ++k)
+        if (!t->gm_ev[k]) FM_HIP(hipEventCreateWithFlags(&t->gm_ev[k], hipEventDisableTiming));
 }
 
-void GmresRun::start(fmddm_ctx *c, fmddm_tree *tr, int md, const double *rhs, double *x0, double tl, int mx)
+// Host slots: the norm of b and of residuals arrive in slot 0; Arnoldi step
+// j's (new norm, residual estimate) in slot j % 2, so that step j + 1 can be
+// in flight while step j's scalars are read.
+void GmresRun::post(int slot, int count)
+{
+    SW s{ctx->prm.restart};
+    FM_HIP(hipMemcpyAsync(t->gm_host + 2 * slot, t->gm_sc.p + s.nrm(), 8 * count, hipMemcpyDeviceToHost,
+                          ctx->stream));
+    FM_HIP(hipEventRecord(t->gm_ev[slot], ctx->stream));
+}
+
+void GmresRun::start(fmddm_ctx *c, fmddm_tree *tr, int md, const double *rhs, double *x0, double tl, int mx,
+                     int rmd)
 {
     ctx = c;
     t = tr;
     mode = md;
+    rmode = rmd < 0 ? md : rmd;
+    residuals = 0;
+    prev_beta = INFINITY;
     b = rhs;
     x = x0;
     tol = tl;
     maxit = mx;
-    j = it = restarts = 0;
+    j = next = it = restarts = 0;
     bnorm = relres = 0.0;
     converged = false;
     gmres_workspace(t, ctx->prm.restart, (int)vec_len(t, mode));
     SW s{ctx->prm.restart};
-    hipStream_t st = ctx->stream;
     const int n2 = (int)vec_len(t, mode);
-    hipLaunchKernelGGL(k_norm, dim3(1), dim3(RT), 0, st, n2, b, t->gm_sc.p + s.nrm());
-    FM_CHECK_LAUNCH();
-    FM_HIP(hipMemcpyAsync(t->gm_host, t->gm_sc.p + s.nrm(), 8, hipMemcpyDeviceToHost, st));
-    FM_HIP(hipEventRecord(t->gm_ev, st));
+    norm2(ctx->stream, n2, b, t->gm_part.p, t->gm_sc.p + s.nrm());
+    post(0, 1);
     state = BNORM;
 }
 
@@ -257,45 +299,46 @@ void GmresRun::enqueue_residual()
     SW s{ctx->prm.restart};
     hipStream_t st = ctx->stream;
     const int n2 = (int)vec_len(t, mode);
-    apply_mode(ctx, t, mode, x, t->gm_w.p);
+    apply_mode(ctx, t, rmode, x, t->gm_w.p);
+    ++residuals;
     hipLaunchKernelGGL(k_residual, dim3(cdiv(n2, 256)), dim3(256), 0, st, n2, b, t->gm_w.p, t->gm_r.p);
-    hipLaunchKernelGGL(k_norm, dim3(1), dim3(RT), 0, st, n2, t->gm_r.p, t->gm_sc.p + s.nrm());
-    FM_CHECK_LAUNCH();
-    FM_HIP(hipMemcpyAsync(t->gm_host, t->gm_sc.p + s.nrm(), 8, hipMemcpyDeviceToHost, st));
-    FM_HIP(hipEventRecord(t->gm_ev, st));
+    norm2(st, n2, t->gm_r.p, t->gm_part.p, t->gm_sc.p + s.nrm());
+    post(0, 1);
 }
 
-// Arnoldi step j: w = A v_j, two classical Gram-Schmidt passes, the new
+// Arnoldi step `next`: w = A v_j, two classical Gram-Schmidt passes, the new
 // basis vector, the Hessenberg column and its Givens rotation
 void GmresRun::enqueue_step()
 {
-    const int m = ctx->prm.restart;
+    const int m = ctx->prm.restart, jj = next++;
     SW s{m};
     hipStream_t st = ctx->stream;
     const int n2 = (int)vec_len(t, mode), ldv = (n2 + 63) / 64 * 64, gb = cdiv(n2, 256);
     double *V = t->gm_V.p, *w = t->gm_w.p, *sc = t->gm_sc.p;
-    double *vj = V + (size_t)j * ldv, *vn = V + (size_t)(j + 1) * ldv;
+    double *vj = V + (size_t)jj * ldv, *vn = V + (size_t)(jj + 1) * ldv;
     apply_mode(ctx, t, mode, vj, w);
     ++it;
-    hipLaunchKernelGGL(k_dots, dim3(j + 1), dim3(RT), 0, st, n2, j + 1, V, ldv, w, sc + s.h1());
-    hipLaunchKernelGGL(k_vupdate, dim3(gb), dim3(256), 0, st, n2, j + 1, V, ldv, sc + s.h1(), -1.0, w);
-    hipLaunchKernelGGL(k_dots, dim3(j + 1), dim3(RT), 0, st, n2, j + 1, V, ldv, w, sc + s.h2());
-    hipLaunchKernelGGL(k_vupdate, dim3(gb), dim3(256), 0, st, n2, j + 1, V, ldv, sc + s.h2(), -1.0, w);
-    hipLaunchKernelGGL(k_norm, dim3(1), dim3(RT), 0, st, n2, w, sc + s.nrm());
+    dots(st, n2, jj + 1, V, ldv, w, t->gm_part.p, sc + s.h1());
+    hipLaunchKernelGGL(k_vupdate, dim3(gb), dim3(256), 0, st, n2, jj + 1, V, ldv, sc + s.h1(), -1.0, w);
+    dots(st, n2, jj + 1, V, ldv, w, t->gm_part.p, sc + s.h2());
+    hipLaunchKernelGGL(k_vupdate, dim3(gb), dim3(256), 0, st, n2, jj + 1, V, ldv, sc + s.h2(), -1.0, w);
+    norm2(st, n2, w, t->gm_part.p, sc + s.nrm());
     hipLaunchKernelGGL(k_scale, dim3(gb), dim3(256), 0, st, n2, w, sc + s.nrm(), vn);
-    hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, st, s, j, sc);
+    hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, st, s, jj, sc);
     FM_CHECK_LAUNCH();
-    FM_HIP(hipMemcpyAsync(t->gm_host, sc + s.nrm(), 16, hipMemcpyDeviceToHost, st));
-    FM_HIP(hipEventRecord(t->gm_ev, st));
+    post(jj & 1, 2);
 }
 
 bool GmresRun::advance(bool block)
 {
     if (state == DONE || state == IDLE) return true;
+    // the oldest result not yet read: slot 0 for norms, step j's otherwise
+    int slot = state == ITER ? (j & 1) : 0;
+    hipEvent_t ev = t->gm_ev[slot];
     if (block) {
-        FM_HIP(hipEventSynchronize(t->gm_ev));
+        FM_HIP(hipEventSynchronize(ev));
     } else {
-        hipError_t q = hipEventQuery(t->gm_ev);
+        hipError_t q = hipEventQuery(ev);
         if (q == hipErrorNotReady) return false;
         FM_HIP(q);
     }
@@ -304,7 +347,7 @@ bool GmresRun::advance(bool block)
     hipStream_t st = ctx->stream;
     const int n2 = (int)vec_len(t, mode), ldv = (n2 + 63) / 64 * 64, gb = cdiv(n2, 256);
     double *V = t->gm_V.p, *sc = t->gm_sc.p;
-    const double *h = t->gm_host;
+    const double *h = t->gm_host + 2 * slot;
     switch (state) {
     case BNORM:
         bnorm = h[0];
@@ -324,7 +367,11 @@ bool GmresRun::advance(bool block)
         double beta = h[0];
         relres = beta / bnorm;
         if (!std::isfinite(beta)) throw Error{FMDDM_EDEVICE, "non-finite residual"};
-        if (beta <= tol * bnorm || it >= maxit) {
+        // a refinement cycle that did not reduce the residual: the Arnoldi
+        // product is too far from the residual product for this system
+        bool stalled = rmode != mode && beta >= prev_beta;
+        prev_beta = beta;
+        if (beta <= tol * bnorm || it >= maxit || stalled) {
             converged = beta <= tol * bnorm;
             state = DONE;
             return true;
@@ -333,15 +380,19 @@ bool GmresRun::advance(bool block)
         hipLaunchKernelGGL(k_scale, dim3(gb), dim3(256), 0, st, n2, t->gm_r.p, sc + s.nrm(), V);
         hipLaunchKernelGGL(k_cycle_start, dim3(1), dim3(1), 0, st, s, sc);
         FM_CHECK_LAUNCH();
-        j = 0;
+        j = next = 0;
         enqueue_step();
+        if (next < m && it < maxit) enqueue_step();  // one step ahead
         state = ITER;
         return false;
     }
     case ITER: {
         double nrm = h[0], est = h[1];
         int k = j + 1;
-        if (est <= tol * bnorm || nrm == 0.0 || k == m || it >= maxit) {
+        bool ahead = next > k;  // step j + 1 already enqueued
+        if (est <= tol * bnorm || nrm == 0.0 || k == m || (!ahead && it >= maxit)) {
+            // a step enqueued ahead leaves H's first k columns and g[0..k)
+            // as they were: the update uses the first k only
             hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(1), 0, st, s, k, sc);
             hipLaunchKernelGGL(k_vupdate, dim3(gb), dim3(256), 0, st, n2, k, V, ldv, sc + s.y(), 1.0, x);
             FM_CHECK_LAUNCH();
@@ -349,7 +400,7 @@ bool GmresRun::advance(bool block)
             state = RESID;
         } else {
             ++j;
-            enqueue_step();
+            if (next < m && it < maxit) enqueue_step();
         }
         return false;
     }
@@ -357,89 +408,20 @@ bool GmresRun::advance(bool block)
     }
 }
 
-// Mixed-precision solve by iterative refinement: the residual with the FP64
-// FMM product, corrections from GMRES on the reduced-precision product (its
-// basis, orthogonalisation and rotations FP64).  A correction solved to
-// relative residual tau on an operator A' with ||A - A'|| / ||A|| = delta
-// reduces the FP64 residual by about tau + kappa(A) delta per step.
-static fmddm_status ir_solve(fmddm_ctx *ctx, fmddm_tree *t, const double *b, double *x, fmddm_solve_info *info)
-{
-    hipStream_t st = ctx->stream;
-    const int n2 = (int)(2 * t->n), gb = cdiv(n2, 256);
-    double tau = ctx->prm.inner_tol > 0.0 ? ctx->prm.inner_tol
-                                          : (ctx->prm.precision == FMDDM_PREC_FP32 ? 1e-5 : 3e-3);
-    DBuf<double> r, d, ax, nrm;
-    r.alloc(n2);
-    d.alloc(n2);
-    ax.alloc(n2);
-    nrm.alloc(1);
-    auto norm = [&](const double *v) {
-        hipLaunchKernelGGL(k_norm, dim3(1), dim3(RT), 0, st, n2, v, nrm.p);
-        FM_CHECK_LAUNCH();
-        double h;
-        FM_HIP(hipMemcpyAsync(&h, nrm.p, 8, hipMemcpyDeviceToHost, st));
-        FM_HIP(hipStreamSynchronize(st));
-        return h;
-    };
-    *info = fmddm_solve_info{};
-    double bnorm = norm(b);
-    if (!std::isfinite(bnorm)) throw Error{FMDDM_EINVAL, "non-finite right-hand side"};
-    if (bnorm == 0.0) {
-        hipLaunchKernelGGL(k_fill, dim3(gb), dim3(256), 0, st, n2, 0.0, x);
-        FM_CHECK_LAUNCH();
-        FM_HIP(hipStreamSynchronize(st));
-        info->converged = 1;
-        return FMDDM_OK;
-    }
-    double prev = INFINITY;
-    for (;;) {
-        fmm_apply(ctx, t, x, ax.p, FMDDM_PREC_FP64);
-        hipLaunchKernelGGL(k_residual, dim3(gb), dim3(256), 0, st, n2, b, ax.p, r.p);
-        FM_CHECK_LAUNCH();
-        double rn = norm(r.p);
-        ++info->refinements;
-        info->relres = rn / bnorm;
-        if (!std::isfinite(rn)) throw Error{FMDDM_EDEVICE, "non-finite residual"};
-        if (rn <= ctx->prm.tol * bnorm) {
-            info->converged = 1;
-            return FMDDM_OK;
-        }
-        // no progress: the reduced-precision operator is too far from the
-        // FP64 one for this system
-        if (rn >= 0.99 * prev || info->iters >= ctx->prm.maxit) return FMDDM_ENOTCONV;
-        prev = rn;
-        // on the last step the inner solve need not beat the outer target
-        double tin = std::min(0.5, std::max(tau, 0.3 * ctx->prm.tol * bnorm / rn));
-        hipLaunchKernelGGL(k_fill, dim3(gb), dim3(256), 0, st, n2, 0.0, d.p);
-        FM_CHECK_LAUNCH();
-        GmresRun g;
-        g.start(ctx, t, FMDDM_APPLY_FMM, r.p, d.p, tin, ctx->prm.maxit - info->iters);
-        while (!g.advance(true)) {
-        }
-        info->iters += g.it;
-        info->restarts += g.restarts;
-        hipLaunchKernelGGL(k_axpy1, dim3(gb), dim3(256), 0, st, n2, d.p, x);
-        FM_CHECK_LAUNCH();
-    }
-}
-
 fmddm_status gmres_solve(fmddm_ctx *ctx, fmddm_tree *t, int mode, const double *b, double *x,
                          fmddm_solve_info *info)
 {
-    if (mode == FMDDM_APPLY_FMM && ctx->prm.precision != FMDDM_PREC_FP64) {
-        fmddm_status stt = ir_solve(ctx, t, b, x, info);
-        FM_HIP(hipStreamSynchronize(ctx->stream));
-        return stt;
-    }
+    // reduced-precision FMM: Arnoldi on it, residuals with the FP64 product
+    bool mixed = mode == FMDDM_APPLY_FMM && ctx->prm.precision != FMDDM_PREC_FP64;
     GmresRun g;
-    g.start(ctx, t, mode, b, x, ctx->prm.tol, ctx->prm.maxit);
+    g.start(ctx, t, mode, b, x, ctx->prm.tol, ctx->prm.maxit, mixed ? APPLY_FMM_FP64 : -1);
     while (!g.advance(true)) {
     }
     info->iters = g.it;
     info->restarts = g.restarts;
     info->relres = g.relres;
     info->converged = g.converged;
-    info->refinements = 0;
+    info->refinements = mixed ? g.residuals : 0;
     FM_HIP(hipStreamSynchronize(ctx->stream));
     return g.converged ? FMDDM_OK : FMDDM_ENOTCONV;
 }

@@ -35,9 +35,10 @@ def test_struct_layouts_match_header():
     compiler gives them (computed from the header by gcc)."""
     import subprocess
     import tempfile
-    src = '#include "fmddm.h"\n#include <stdio.h>\nint main(){printf("%zu %zu %zu %zu %zu %zu\\n",' \
+    src = '#include "fmddm.h"\n#include <stdio.h>\nint main(){printf("%zu %zu %zu %zu %zu %zu %zu\\n",' \
           'sizeof(fmddm_params),sizeof(fmddm_tree_info),sizeof(fmddm_solve_info),' \
-          'sizeof(fmddm_request),sizeof(fmddm_result),sizeof(fmddm_poro_params));return 0;}\n'
+          'sizeof(fmddm_request),sizeof(fmddm_result),sizeof(fmddm_poro_params),' \
+          'sizeof(fmddm_tune_entry));return 0;}\n'
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "s.c")
         open(c, "w").write(src)
@@ -45,7 +46,8 @@ def test_struct_layouts_match_header():
         subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
         sizes = list(map(int, subprocess.check_output([exe]).split()))
     assert sizes == [C.sizeof(F.Params), C.sizeof(F.TreeInfo), C.sizeof(F.SolveInfo),
-                     C.sizeof(F.Request), C.sizeof(F.Result), C.sizeof(F.PoroParams)]
+                     C.sizeof(F.Request), C.sizeof(F.Result), C.sizeof(F.PoroParams),
+                     C.sizeof(F.TuneEntry)]
 
 
 def test_default_params_and_validation_without_device():
@@ -57,7 +59,8 @@ def test_default_params_and_validation_without_device():
     lib = F.lib()
     out = C.c_void_p()
     for field, bad in [("p", 0), ("p", 33), ("leaf", 0), ("nu", 0.5), ("E", -1.0),
-                       ("max_level", 31), ("restart", 0), ("tol", -1.0)]:
+                       ("max_level", 31), ("restart", 0), ("tol", -1.0), ("precision", 3),
+                       ("precision", -1)]:
         q = F.fmddm_default_params(**{field: bad})
         assert lib.fmddm_create(C.byref(q), None, C.byref(out)) == F.FMDDM_EINVAL, field
         assert not out.value
@@ -86,6 +89,21 @@ def test_default_params_and_validation_without_device():
     assert lib.fmddm_add_history(None, None, 2, None, None) == F.FMDDM_EINVAL
     assert lib.fmddm_poro_rhs(None, None, None, 0.0, 0.0, None) == F.FMDDM_EINVAL
     assert lib.fmddm_poro_solve(None, None, None, None, None) == F.FMDDM_EINVAL
+    # autotuner: argument checks come first
+    best = F.Params()
+    x = (C.c_double * 4)(0.0, 1.0, 2.0, 3.0)
+    lv = (C.c_int32 * 2)(16, 32)
+    pv = (C.c_int32 * 2)(8, 10)
+    args = [C.byref(p), 2, x, x, x, x, lv, 2, pv, 2, 1e-6, 3, C.byref(best), None, 0, None]
+    for i, bad in [(0, None), (2, None), (6, None), (7, 0), (9, 0), (10, 0.0), (11, 0), (12, None),
+                   (14, 4)]:
+        a2 = list(args)
+        a2[i] = bad
+        assert lib.fmddm_autotune(*a2) == F.FMDDM_EINVAL, i
+    bad_p = (C.c_int32 * 2)(8, 33)
+    a2 = list(args)
+    a2[8] = bad_p
+    assert lib.fmddm_autotune(*a2) == F.FMDDM_EINVAL
 
 
 def test_binding_refuses_host_tensors():
