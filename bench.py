@@ -115,10 +115,10 @@ def traffic_for(phase):
 SERVE_PARAMS = dict(p=10, leaf=32, m2l=1, m2l_tol=1e-10, restart=50, maxit=20000)
 
 
-def serve_run(F, wls, reqs, slots, arrivals):
+def serve_run(F, wls, reqs, slots, arrivals, precond=1):
     """Serve the requests with `slots` admission slots; request i is
     submitted at arrivals[i] seconds.  Returns (makespan s, latencies s)."""
-    prm = F.fmddm_default_params(**SERVE_PARAMS)
+    prm = F.fmddm_default_params(**SERVE_PARAMS, precond=precond)
     srv = F.fmddm_server_create(prm, slots)
     try:
         warm = F.fmddm_server_submit(srv, wls[0].x1, wls[0].y1, wls[0].x2, wls[0].y2, wls[0].pressure,
@@ -136,7 +136,9 @@ def serve_run(F, wls, reqs, slots, arrivals):
                 tickets[i] = F.fmddm_server_submit(srv, w.x1, w.y1, w.x2, w.y2, w.pressure, w.SH, w.Sh,
                                                    reqs[i].steps, 1e-6)
                 pend += 1
-            F.fmddm_server_step(srv)
+            active, queued = F.fmddm_server_step(srv)
+            if active + queued == len(tickets) - len(done):
+                continue  # nothing finished in this step
             for i, t in tickets.items():
                 if i not in done:
                     r = F.fmddm_server_poll(srv, t)[0]
@@ -157,7 +159,9 @@ def serving_leg(F, W, count, slots, load):
     """Serving of the seed-5 request stream (N log-uniform in [1e3, 5e4],
     1-10 load steps, tol 1e-6): the one-at-a-time service rate, the batched
     saturation rate, and a Poisson stream at `load` x the one-at-a-time rate
-    served batched and one at a time."""
+    served batched and one at a time; GMRES with block-Jacobi
+    preconditioning, and the batched saturation rate without it (the
+    paper's plain GMRES) for comparison."""
     reqs = W.serving_stream(5, count)
     wls = [r.workload() for r in reqs]
     zero = [0.0] * count
@@ -168,12 +172,16 @@ def serving_leg(F, W, count, slots, load):
     arr = [r.arrival_units / lam for r in reqs]
     spans, lat, _ = serve_run(F, wls, reqs, slots, arr)
     span_o, lat_o, _ = serve_run(F, wls, reqs, 1, arr)
+    span_np, _, iters_np = serve_run(F, wls, reqs, slots, zero, precond=0)
     pct = lambda a, q: float(np.percentile(a, q))
     return {
         "requests": count, "slots": slots, "elements_total": int(sum(w.n for w in wls)),
         "gmres_products_total": iters,
         "params": {"p": SERVE_PARAMS["p"], "leaf": SERVE_PARAMS["leaf"], "m2l": "svd 1e-10", "tol": 1e-6,
-                   "restart": SERVE_PARAMS["restart"]},
+                   "restart": SERVE_PARAMS["restart"], "precond": "block-Jacobi, 32-element groups",
+                   "graphs": True},
+        "unpreconditioned": {"batched_saturated_solves_per_s": count / span_np,
+                             "gmres_products_total": iters_np},
         "one_at_a_time_solves_per_s": rate1,
         "batched_saturated_solves_per_s": count / spanb,
         "poisson_rate_per_s": lam,
@@ -241,7 +249,8 @@ def history_leg(F, W, elems, steps, p=10):
 def precision_leg(F, W, steps, tune, leaf, p, solve_tol=1e-8, target_err=1e-6):
     """Mixed precision at N=200000 (2000 random fractures x 100 elements,
     seed 4): autotuned leaf and p for the FP64 product, then products and
-    solves at FP64, FP32 and BF16-M2L on that configuration.  Errors of each
+    solves at FP64, FP32 and BF16-M2L on that configuration (block-Jacobi
+    preconditioned GMRES; the FP64 solve also unpreconditioned).  Errors of each
     product against the FP64 FMM product and the exact product (on-the-fly
     FP64 on the GPU); each solve reaches tol on the FP64 FMM residual, and
     its exact-operator residual and distance to the FP64 solve are stated."""
@@ -250,7 +259,7 @@ def precision_leg(F, W, steps, tune, leaf, p, solve_tol=1e-8, target_err=1e-6):
     n = wl.n
     out = {"workload": "2000 random pressurized fractures x 100 elements, N=200000, seed 4", "N": n,
            "solve_tol": solve_tol}
-    common = dict(E=wl.E, nu=wl.nu, m2l=F.FMDDM_M2L_SVD, m2l_tol=1e-10, restart=50, maxit=20000)
+    common = dict(E=wl.E, nu=wl.nu, m2l=F.FMDDM_M2L_SVD, m2l_tol=1e-10, restart=50, maxit=30000)
     if tune:
         base = F.fmddm_default_params(**common)
         t0 = time.perf_counter()
@@ -267,7 +276,8 @@ def precision_leg(F, W, steps, tune, leaf, p, solve_tol=1e-8, target_err=1e-6):
     b = None
     ref = None
     for name, prec in [("fp64", F.FMDDM_PREC_FP64), ("fp32", F.FMDDM_PREC_FP32), ("bf16", F.FMDDM_PREC_BF16)]:
-        prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, leaf=leaf, p=p, precision=prec, tol=solve_tol, **common)
+        prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, leaf=leaf, p=p, precision=prec, tol=solve_tol,
+                         precond=F.FMDDM_PRECOND_BLOCK, **common)
         if D is None:
             D = prob.vec(W.random_vector(9, n))
             b = prob.rhs(wl.pressure, wl.SH, wl.Sh)
@@ -281,6 +291,13 @@ def precision_leg(F, W, steps, tune, leaf, p, solve_tol=1e-8, target_err=1e-6):
             prob.apply(D, F.FMDDM_APPLY_FMM, o)
         torch.cuda.synchronize()
         r = {"matvecs_per_s": steps / (time.perf_counter() - t0)}
+        # per-kernel times (HIP events on each kernel's stream)
+        F.fmddm_profile(prob.ctx, (1 << len(F.PHASES)) - 1)
+        for _ in range(3):
+            prob.apply(D, F.FMDDM_APPLY_FMM, o)
+        ph = F.fmddm_profile_read(prob.ctx)
+        F.fmddm_profile(prob.ctx, 0)
+        r["phase_ms"] = {k: v[0] / 3 for k, v in ph.items() if v[1] > 0}   # per product
         y[name] = o.cpu().numpy()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -291,6 +308,15 @@ def precision_leg(F, W, steps, tune, leaf, p, solve_tol=1e-8, target_err=1e-6):
         x[name] = xs
         if name == "fp64":
             ref = prob            # kept for the exact products below
+            # the paper's unpreconditioned GMRES on the same FP64 product
+            prob0 = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, leaf=leaf, p=p, tol=solve_tol, **common)
+            prob0.apply(D, F.FMDDM_APPLY_FMM, o)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info0 = prob0.solve(b)
+            torch.cuda.synchronize()
+            out["fp64_unpreconditioned_solve"] = {"solve_s": time.perf_counter() - t0, "solve": info0}
+            prob0.close()
         else:
             prob.close()
         res[name] = r
@@ -405,7 +431,9 @@ def main():
     for _ in range(5):
         prob.apply(D, F.FMDDM_APPLY_FMM, out)
     ph = F.fmddm_profile_read(prob.ctx)
-    phase_ms = {k: v[0] / max(v[1], 1) for k, v in ph.items()}
+    # per product (a phase may take more than one launch, on different streams)
+    phase_ms = {k: v[0] / 5 for k, v in ph.items()}
+    phase_launches = {k: v[1] / 5 for k, v in ph.items()}
     dom = max(phase_ms, key=phase_ms.get)
     # timed region: K products, the dominant phase bracketed by HIP events
     F.fmddm_profile(prob.ctx, 1 << F.PHASES.index(dom))
@@ -417,7 +445,7 @@ def main():
     elapsed = time.perf_counter() - t0
     dom_tot, dom_cnt = F.fmddm_profile_read(prob.ctx)[dom]
     F.fmddm_profile(prob.ctx, 0)
-    dom_ms = dom_tot / max(dom_cnt, 1)
+    dom_ms = dom_tot / args.steps          # kernel time per product
     value = args.steps / elapsed
     y_fmm = out.cpu().numpy()
 
@@ -448,12 +476,13 @@ def main():
         if ms <= 0:
             continue
         ach = amount / (ms * 1e-3) / scale[unit] if ms > 0 else None
-        phases[ph] = {"ms": ms, "bound": bound, "work": amount, "achieved": ach, "unit": unit,
-                      "frac": ach / peak if ach else None}
+        phases[ph] = {"ms": ms, "launches": phase_launches.get(ph), "bound": bound, "work": amount,
+                      "achieved": ach, "unit": unit, "frac": ach / peak if ach else None}
     bound, amount, unit, peak = work[dom]
     achieved = amount / (dom_ms * 1e-3) / scale[unit]
     roof = {"bound": bound, "kernel": kernel_name(dom, args.p), "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": traffic_for(dom), "avg_launch_ms": dom_ms}
+            "frac": achieved / peak, "traffic": traffic_for(dom), "ms_per_product": dom_ms,
+            "avg_launch_ms": dom_tot / max(dom_cnt, 1)}
 
     line = {
         "metric": "FMM-DDM matvecs/s at N=20k vs dense; served solves/s + p99 latency",

@@ -82,6 +82,17 @@ typedef enum {
                                  weights rounded to bf16), FP32 sums */
 } fmddm_precision;
 
+/* Preconditioning of the elastic GMRES solves.  The paper's GMRES is
+ * unpreconditioned (NONE); BLOCK is right block-Jacobi preconditioning
+ * with the exact inverse of the influence matrix restricted to groups of
+ * at most 32 neighbouring elements (runs in tree order within one leaf),
+ * built once per tree: 8 (2m)^2 bytes per group of m elements.  It changes
+ * the iteration count, not the solution. */
+typedef enum {
+    FMDDM_PRECOND_NONE = 0,
+    FMDDM_PRECOND_BLOCK = 1
+} fmddm_precond;
+
 typedef struct {
     double E, nu;             /* material (Pa, -) */
     int leaf;                 /* split a cell holding more than `leaf` points (Section 3.1) */
@@ -96,6 +107,10 @@ typedef struct {
     int restart, maxit;       /* GMRES(restart), at most maxit matrix-vector products */
     double tol;               /* GMRES relative residual target */
     int precision;            /* fmddm_precision of FMDDM_APPLY_FMM products */
+    int use_graphs;           /* 1: GMRES replays each Arnoldi step (product,
+                                 orthogonalisation, rotation) as a HIP graph
+                                 captured on its first use; 0: plain launches */
+    int precond;              /* fmddm_precond of elastic GMRES solves */
 } fmddm_params;
 
 typedef struct {
@@ -124,7 +139,7 @@ typedef struct {
 
 /* Fill *p with defaults: E=20e9, nu=0.25, leaf=32, p=20, max_level=24,
  * kappa=8, m2l=DENSE, m2l_tol=1e-12, no root box, restart=50,
- * maxit=10000, tol=1e-10, precision=FP64. */
+ * maxit=10000, tol=1e-10, precision=FP64, use_graphs=1, precond=NONE. */
 void fmddm_default_params(fmddm_params *p);
 
 /* Create a context on the current HIP device bound to `hip_stream`

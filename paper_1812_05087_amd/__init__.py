@@ -24,6 +24,7 @@ FMDDM_EINVAL, FMDDM_ENOMEM, FMDDM_EDEVICE, FMDDM_EGEOM, FMDDM_EUNSUPPORTED = -1,
 FMDDM_APPLY_FMM, FMDDM_APPLY_DIRECT, FMDDM_APPLY_DENSE = 0, 1, 2
 FMDDM_M2L_DENSE, FMDDM_M2L_SVD = 0, 1
 FMDDM_PREC_FP64, FMDDM_PREC_FP32, FMDDM_PREC_BF16 = 0, 1, 2
+FMDDM_PRECOND_NONE, FMDDM_PRECOND_BLOCK = 0, 1
 LIST_U, LIST_V, LIST_W, LIST_X = 0, 1, 2, 3
 
 EXPORTED = [
@@ -55,7 +56,7 @@ class Params(C.Structure):
         ("kappa", C.c_double), ("m2l", C.c_int), ("m2l_tol", C.c_double),
         ("use_root_box", C.c_int), ("root_x0", C.c_double), ("root_y0", C.c_double),
         ("root_L", C.c_double), ("restart", C.c_int), ("maxit", C.c_int), ("tol", C.c_double),
-        ("precision", C.c_int),
+        ("precision", C.c_int), ("use_graphs", C.c_int), ("precond", C.c_int),
     ]
 
 

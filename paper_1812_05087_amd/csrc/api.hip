@@ -50,6 +50,8 @@ const char *check_params(const fmddm_params *p)
     if (p->maxit < 0) return "maxit must be >= 0";
     if (!(p->tol >= 0.0)) return "tol must be >= 0";
     if (p->precision < FMDDM_PREC_FP64 || p->precision > FMDDM_PREC_BF16) return "unknown precision";
+    if (p->use_graphs != 0 && p->use_graphs != 1) return "use_graphs must be 0 or 1";
+    if (p->precond != FMDDM_PRECOND_NONE && p->precond != FMDDM_PRECOND_BLOCK) return "unknown precond";
     return nullptr;
 }
 
@@ -72,6 +74,7 @@ void fmddm_default_params(fmddm_params *p)
     p->restart = 50;
     p->maxit = 10000;
     p->tol = 1e-10;
+    p->use_graphs = 1;
 }
 
 fmddm_status fmddm_create(const fmddm_params *p, void *hip_stream, fmddm_ctx **out)

@@ -1250,6 +1250,7 @@ void fmm_sum_pairs(hipStream_t s, fmddm_tree *t, const double *Z, int ldz, int w
 void init_streams(fmddm_ctx *ctx)
 {
     FM_HIP(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+    FM_HIP(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
     FM_HIP(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
     FM_HIP(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
 }

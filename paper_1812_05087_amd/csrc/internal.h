@@ -117,8 +117,12 @@ struct fmddm_ctx {
     // field, forked from and joined back into `stream` with events
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // idle stream that graphs are captured on (the caller's stream may be
+    // the null stream, which cannot capture); graphs launch on `stream`
+    hipStream_t cap = nullptr;
     ~fmddm_ctx()
     {
+        if (cap) (void)hipStreamDestroy(cap);
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (ev_join) (void)hipEventDestroy(ev_join);
         if (side) (void)hipStreamDestroy(side);
@@ -203,6 +207,13 @@ struct fmddm_tree {
     fmddm::DBuf<double> gm_V, gm_w, gm_r, gm_sc, gm_part;
     int gm_restart = 0;
     int64_t gm_len = 0;
+    // block-Jacobi preconditioner: groups of elements (first tree position,
+    // count), offsets of their inverses (column-major) in pc_inv
+    int pc_nblk = 0;
+    fmddm::DBuf<int> pc_beg, pc_cnt;
+    fmddm::DBuf<int64_t> pc_off;
+    fmddm::DBuf<double> pc_inv;
+    fmddm::DBuf<double> gm_z;          // preconditioned basis vector M^-1 v_j
     // poroelastic workspace: chunk partials, term times, term vectors
     fmddm::DBuf<double> poro_part, poro_times, poro_E;
     // poroelastic FMM: V pairs grouped by (level, offset) "combos", tiles of
@@ -213,11 +224,25 @@ struct fmddm_tree {
     fmddm::DBuf<int> pf_tile_op, pf_tile_beg, pf_tile_end, pf_psrc, pf_pdst, pf_combo_lvl, pf_combo_ox,
         pf_combo_oy;
     fmddm::DBuf<double> pf_ops, pf_W, pf_part, pf_Z, pf_G, pf_far, pf_Q, pf_D3, pf_near, pf_D2, pf_o2;
+    // Arnoldi steps captured as graphs, one per step index, valid for the
+    // context and apply mode they were captured with
+    std::vector<hipGraphExec_t> gm_graph;
+    const fmddm_ctx *gm_graph_ctx = nullptr;
+    int gm_graph_mode = -1;
+    void drop_graphs()
+    {
+        for (hipGraphExec_t &g : gm_graph)
+            if (g) (void)hipGraphExecDestroy(g);
+        gm_graph.clear();
+        gm_graph_ctx = nullptr;
+        gm_graph_mode = -1;
+    }
     double *gm_host = nullptr;        // 2 slots of 2 doubles
     hipEvent_t gm_ev[2] = {nullptr, nullptr};
     int64_t bytes = 0;
     ~fmddm_tree()
     {
+        drop_graphs();
         for (hipEvent_t e : gm_ev)
             if (e) (void)hipEventDestroy(e);
         if (gm_host) (void)hipHostFree(gm_host);
@@ -287,7 +312,10 @@ struct GmresRun {
   private:
     void enqueue_residual();
     void enqueue_step();
+    void step_body(int jj);
     void post(int slot, int count);
+    bool eager_done = false;       // a first step ran uncaptured (lazy set-up done)
+    bool pc = false;               // right preconditioning by the block-Jacobi inverse
 };
 void apply_mode(fmddm_ctx *ctx, fmddm_tree *t, int mode, const double *D, double *out);
 // apply mode of the poroelastic left-hand side F(dt) (3 unknowns per element)
@@ -296,6 +324,9 @@ constexpr int APPLY_PORO = 100;
 // iterative refinement)
 constexpr int APPLY_FMM_FP64 = 101;
 inline int64_t vec_len(const fmddm_tree *t, int mode) { return (mode == APPLY_PORO ? 3 : 2) * t->n; }
+// precond.hip
+void pc_setup(fmddm_ctx *ctx, fmddm_tree *t);
+void pc_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *in, int acc, double *out);
 // poro.hip
 void poro_apply(fmddm_ctx *ctx, fmddm_tree *t, int lag, const double *D, double *out);
 void poro_history(fmddm_ctx *ctx, fmddm_tree *t, int h, const double *Dh, double *rhs);

@@ -97,13 +97,16 @@ namespace {
 // the vectors of GMRES(m); per cell (at most 4n/leaf cells) the weight and
 // field vectors, their compressed forms, split-K partials, the M2L pair
 // results (up to 27 interaction pairs per cell) and the upward-pass
-// partials.  Sizes are rounded up by the allocator, hence the final 25 %.
+// partials; with block-Jacobi preconditioning the group inverses (at most
+// (2 x 32)^2 doubles per 32 elements) and one more vector.  Sizes are
+// rounded up by the allocator, hence the final 25 %.
 int64_t footprint(const fmddm_params &p, int rank_pad, int64_t n)
 {
     const int64_t M = 3LL * p.p * p.p, Mp = (M + 63) / 64 * 64;
     const int64_t rp = p.m2l == FMDDM_M2L_SVD ? rank_pad : Mp;
     const int64_t cells = 4 * n / std::max(1, p.leaf) + 64;
     int64_t per_elem = 8LL * p.p * p.p + 8 * 2 * (p.restart + 4) + 8 * 48;
+    if (p.precond == FMDDM_PRECOND_BLOCK) per_elem += 8 * 128 + 8 * 2 + 16;
     int64_t per_cell = 8 * (3 * Mp + 2 * rp + 4 * rp + 27 * rp) + 4 * 64;
     int64_t b = n * per_elem + cells * per_cell + (4 << 20);
     return b + b / 4;

@@ -250,6 +250,7 @@ static void gmres_workspace(fmddm_tree *t, int m, int n2)
         t->gm_r.alloc(ldv);
         t->gm_sc.alloc(s.size());
         t->gm_part.alloc((size_t)(m + 1) * cdiv(n2, DCH));
+        t->drop_graphs();
         t->gm_restart = m;
         t->gm_len = n2;
     }
@@ -283,9 +284,15 @@ void GmresRun::start(fmddm_ctx *c, fmddm_tree *tr, int md, const double *rhs, do
     tol = tl;
     maxit = mx;
     j = next = it = restarts = 0;
+    eager_done = false;
+    pc = ctx->prm.precond == FMDDM_PRECOND_BLOCK && mode != APPLY_PORO;
     bnorm = relres = 0.0;
     converged = false;
     gmres_workspace(t, ctx->prm.restart, (int)vec_len(t, mode));
+    if (pc) {
+        pc_setup(ctx, t);
+        if (!t->gm_z.p || t->gm_z.n < (size_t)vec_len(t, mode)) t->gm_z.alloc(vec_len(t, mode));
+    }
     SW s{ctx->prm.restart};
     const int n2 = (int)vec_len(t, mode);
     norm2(ctx->stream, n2, b, t->gm_part.p, t->gm_sc.p + s.nrm());
@@ -307,17 +314,71 @@ void GmresRun::enqueue_residual()
 }
 
 // Arnoldi step `next`: w = A v_j, two classical Gram-Schmidt passes, the new
-// basis vector, the Hessenberg column and its Givens rotation
+// basis vector, the Hessenberg column and its Givens rotation, its scalars
+// copied to the host slot.  Every step index has a fixed set of launches
+// over fixed buffers (the basis, the work vector, the scalars; b and x are
+// not touched), so after one uncaptured step has done the product's lazy
+// set-up, step jj is captured once as a graph and replayed in later cycles
+// and later solves on the tree.  Modes whose products may allocate on use
+// (the poroelastic operators) and profiled products stay uncaptured.
 void GmresRun::enqueue_step()
 {
     const int m = ctx->prm.restart, jj = next++;
+    hipStream_t st = ctx->stream;
+    ++it;
+    bool graph = ctx->prm.use_graphs && eager_done && ctx->prof.mask == 0 &&
+                 (mode == FMDDM_APPLY_FMM || mode == FMDDM_APPLY_DIRECT || mode == FMDDM_APPLY_DENSE);
+    if (graph) {
+        if (t->gm_graph_ctx != ctx || t->gm_graph_mode != mode || (int)t->gm_graph.size() != m) {
+            t->drop_graphs();
+            t->gm_graph.assign(m, nullptr);
+            t->gm_graph_ctx = ctx;
+            t->gm_graph_mode = mode;
+        }
+        hipGraphExec_t &ge = t->gm_graph[jj];
+        if (!ge) {
+            // the step's launches follow ctx->stream: point it at the
+            // capture stream for the duration
+            hipGraph_t g = nullptr;
+            hipStream_t cs = ctx->cap;
+            FM_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+            ctx->stream = cs;
+            try {
+                step_body(jj);
+            } catch (...) {
+                ctx->stream = st;
+                (void)hipStreamEndCapture(cs, &g);
+                if (g) (void)hipGraphDestroy(g);
+                throw;
+            }
+            ctx->stream = st;
+            FM_HIP(hipStreamEndCapture(cs, &g));
+            hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            FM_HIP(e);
+        }
+        FM_HIP(hipGraphLaunch(ge, st));
+    } else {
+        step_body(jj);
+        eager_done = true;
+    }
+    FM_HIP(hipEventRecord(t->gm_ev[jj & 1], st));
+}
+
+void GmresRun::step_body(int jj)
+{
+    const int m = ctx->prm.restart;
     SW s{m};
     hipStream_t st = ctx->stream;
     const int n2 = (int)vec_len(t, mode), ldv = (n2 + 63) / 64 * 64, gb = cdiv(n2, 256);
     double *V = t->gm_V.p, *w = t->gm_w.p, *sc = t->gm_sc.p;
     double *vj = V + (size_t)jj * ldv, *vn = V + (size_t)(jj + 1) * ldv;
-    apply_mode(ctx, t, mode, vj, w);
-    ++it;
+    if (pc) {
+        pc_apply(ctx, t, vj, 0, t->gm_z.p);
+        apply_mode(ctx, t, mode, t->gm_z.p, w);
+    } else {
+        apply_mode(ctx, t, mode, vj, w);
+    }
     dots(st, n2, jj + 1, V, ldv, w, t->gm_part.p, sc + s.h1());
     hipLaunchKernelGGL(k_vupdate, dim3(gb), dim3(256), 0, st, n2, jj + 1, V, ldv, sc + s.h1(), -1.0, w);
     dots(st, n2, jj + 1, V, ldv, w, t->gm_part.p, sc + s.h2());
@@ -326,7 +387,7 @@ void GmresRun::enqueue_step()
     hipLaunchKernelGGL(k_scale, dim3(gb), dim3(256), 0, st, n2, w, sc + s.nrm(), vn);
     hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, st, s, jj, sc);
     FM_CHECK_LAUNCH();
-    post(jj & 1, 2);
+    FM_HIP(hipMemcpyAsync(t->gm_host + 2 * (jj & 1), sc + s.nrm(), 16, hipMemcpyDeviceToHost, st));
 }
 
 bool GmresRun::advance(bool block)
@@ -394,7 +455,15 @@ bool GmresRun::advance(bool block)
             // a step enqueued ahead leaves H's first k columns and g[0..k)
             // as they were: the update uses the first k only
             hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(1), 0, st, s, k, sc);
-            hipLaunchKernelGGL(k_vupdate, dim3(gb), dim3(256), 0, st, n2, k, V, ldv, sc + s.y(), 1.0, x);
+            if (pc) {  // x += M^-1 V y
+                double *u = t->gm_w.p;
+                hipLaunchKernelGGL(k_fill, dim3(gb), dim3(256), 0, st, n2, 0.0, u);
+                hipLaunchKernelGGL(k_vupdate, dim3(gb), dim3(256), 0, st, n2, k, V, ldv, sc + s.y(), 1.0, u);
+                FM_CHECK_LAUNCH();
+                pc_apply(ctx, t, u, 1, x);
+            } else {
+                hipLaunchKernelGGL(k_vupdate, dim3(gb), dim3(256), 0, st, n2, k, V, ldv, sc + s.y(), 1.0, x);
+            }
             FM_CHECK_LAUNCH();
             enqueue_residual();
             state = RESID;
