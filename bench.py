@@ -84,11 +84,11 @@ def phase_work(info, p, tree, rank, svd):
 
 def kernel_name(phase, p):
     """The library kernel behind each profiled launch."""
-    return {"prep": "k_prep", "p2m": "k_p2m", "m2m": f"k_m2m<{p}>", "m2m_sum": "k_m2m_sum",
-            "compress": "k_ggemm<32, 32> (projection)", "compress_sum": "k_reduce_split",
-            "m2l": "k_ggemm<64, 32> (pair products)", "m2l_sum": "k_sum_pairs",
-            "decompress": "k_ggemm<64, 32> (back-projection)", "l2p": f"k_l2p<{p}>", "p2p": "k_p2p",
-            "final": "k_final"}[phase]
+    return {"prep": "k_prep", "p2m": "k_p2m", "m2m": f"k_m2m<{p}, 3>", "m2m_sum": "k_m2m_sum",
+            "compress": "k_ggemm<32, 32, *> (projection)", "compress_sum": "k_reduce_split<double>",
+            "m2l": "k_ggemm<64, 32, *> (pair products)", "m2l_sum": "k_sum_pairs<double, double>",
+            "decompress": "k_ggemm<64, 32, *> (back-projection)", "l2p": f"k_l2p<{p}, 3>",
+            "p2p": "k_p2p<double>", "final": "k_final"}[phase]
 
 
 def kernel_source_hash():

@@ -151,27 +151,61 @@ __global__ __launch_bounds__(256) void k_p2m_mats(int nleaf, const int *__restri
 }
 
 // ---------------------------------------------------- P2M (per product)
-// eq. 3.6: leaf weights from the stored per-element anterpolation matrices.
+// eq. 3.6: leaf weights from the stored per-element anterpolation matrices
+// (HBM bound: the matrices are streamed once).  For p^2 < 256 the block's
+// threads split the leaf's elements into G = 256 / p^2 interleaved groups,
+// so that G rows of the matrices are in flight at once; the group partials
+// are added in group order.
 __global__ __launch_bounds__(256) void k_p2m(int nleaf, const int *__restrict__ leaves,
                                              const int *__restrict__ pbeg, const int *__restrict__ pend,
                                              const double *__restrict__ Pm, const double *__restrict__ q,
                                              int p2, int Mp, double *__restrict__ W)
 {
+    __shared__ double red[3][256];
     int c = leaves[xcd_remap(blockIdx.x, nleaf)];
     int b = pbeg[c], e = pend[c];
     double *Wc = W + (size_t)c * Mp;
-    for (int t = threadIdx.x; t < p2; t += 256) {
-        double w0 = 0.0, w1 = 0.0, w2 = 0.0;
+    if (p2 >= 128) {
+        for (int t = threadIdx.x; t < p2; t += 256) {
+            double w0 = 0.0, w1 = 0.0, w2 = 0.0;
 #pragma unroll 4
-        for (int j = b; j < e; ++j) {
+            for (int j = b; j < e; ++j) {
+                double m = Pm[(size_t)j * p2 + t];
+                w0 += q[3 * j] * m;
+                w1 += q[3 * j + 1] * m;
+                w2 += q[3 * j + 2] * m;
+            }
+            Wc[t] = w0;
+            Wc[p2 + t] = w1;
+            Wc[2 * p2 + t] = w2;
+        }
+        return;
+    }
+    int G = 256 / p2, tid = threadIdx.x, g = tid / p2, t = tid - g * p2;
+    double w0 = 0.0, w1 = 0.0, w2 = 0.0;
+    if (g < G) {
+#pragma unroll 4
+        for (int j = b + g; j < e; j += G) {
             double m = Pm[(size_t)j * p2 + t];
             w0 += q[3 * j] * m;
             w1 += q[3 * j + 1] * m;
             w2 += q[3 * j + 2] * m;
         }
-        Wc[t] = w0;
-        Wc[p2 + t] = w1;
-        Wc[2 * p2 + t] = w2;
+    }
+    red[0][tid] = w0;
+    red[1][tid] = w1;
+    red[2][tid] = w2;
+    __syncthreads();
+    if (tid < p2) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int h = 0; h < G; ++h) {
+            s0 += red[0][h * p2 + tid];
+            s1 += red[1][h * p2 + tid];
+            s2 += red[2][h * p2 + tid];
+        }
+        Wc[tid] = s0;
+        Wc[p2 + tid] = s1;
+        Wc[2 * p2 + tid] = s2;
     }
 }
 
