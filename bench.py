@@ -112,7 +112,7 @@ def traffic_for(phase):
     return d.get("phases", {}).get(phase, {}).get("bytes_per_launch")
 
 
-SERVE_PARAMS = dict(p=10, leaf=32, m2l=1, m2l_tol=1e-10, restart=50, maxit=20000)
+SERVE_PARAMS = dict(p=10, leaf=32, m2l=1, m2l_tol=1e-10, restart=50, maxit=20000, use_graphs=0)
 
 
 def serve_run(F, wls, reqs, slots, arrivals, precond=1):
@@ -179,7 +179,7 @@ def serving_leg(F, W, count, slots, load):
         "gmres_products_total": iters,
         "params": {"p": SERVE_PARAMS["p"], "leaf": SERVE_PARAMS["leaf"], "m2l": "svd 1e-10", "tol": 1e-6,
                    "restart": SERVE_PARAMS["restart"], "precond": "block-Jacobi, 32-element groups",
-                   "graphs": True},
+                   "graphs": bool(SERVE_PARAMS["use_graphs"])},
         "unpreconditioned": {"batched_saturated_solves_per_s": count / span_np,
                              "gmres_products_total": iters_np},
         "one_at_a_time_solves_per_s": rate1,

@@ -109,7 +109,9 @@ typedef struct {
     int precision;            /* fmddm_precision of FMDDM_APPLY_FMM products */
     int use_graphs;           /* 1: GMRES replays each Arnoldi step (product,
                                  orthogonalisation, rotation) as a HIP graph
-                                 captured on its first use; 0: plain launches */
+                                 captured on its first use; 0: plain launches
+                                 (default: replays measured no faster, and
+                                 capture costs ~1 ms per step index and tree) */
     int precond;              /* fmddm_precond of elastic GMRES solves */
 } fmddm_params;
 
@@ -139,7 +141,7 @@ typedef struct {
 
 /* Fill *p with defaults: E=20e9, nu=0.25, leaf=32, p=20, max_level=24,
  * kappa=8, m2l=DENSE, m2l_tol=1e-12, no root box, restart=50,
- * maxit=10000, tol=1e-10, precision=FP64, use_graphs=1, precond=NONE. */
+ * maxit=10000, tol=1e-10, precision=FP64, use_graphs=0, precond=NONE. */
 void fmddm_default_params(fmddm_params *p);
 
 /* Create a context on the current HIP device bound to `hip_stream`

@@ -74,7 +74,7 @@ void fmddm_default_params(fmddm_params *p)
     p->restart = 50;
     p->maxit = 10000;
     p->tol = 1e-10;
-    p->use_graphs = 1;
+    p->use_graphs = 0;
 }
 
 fmddm_status fmddm_create(const fmddm_params *p, void *hip_stream, fmddm_ctx **out)

@@ -54,7 +54,7 @@ def test_default_params_and_validation_without_device():
     if not os.path.exists(F.LIB_PATH):
         pytest.skip("library not built")
     p = F.fmddm_default_params()
-    assert (p.leaf, p.p, p.max_level, p.restart) == (32, 20, 24, 50)
+    assert (p.leaf, p.p, p.max_level, p.restart, p.use_graphs, p.precond, p.precision) == (32, 20, 24, 50, 0, 0, 0)
     assert p.E == 20e9 and p.nu == 0.25 and p.kappa == 8.0 and p.tol == 1e-10
     lib = F.lib()
     out = C.c_void_p()
