@@ -82,12 +82,14 @@ typedef enum {
                                  weights rounded to bf16), FP32 sums */
 } fmddm_precision;
 
-/* Preconditioning of the elastic GMRES solves.  The paper's GMRES is
- * unpreconditioned (NONE); BLOCK is right block-Jacobi preconditioning
- * with the exact inverse of the influence matrix restricted to groups of
- * at most 32 neighbouring elements (runs in tree order within one leaf),
- * built once per tree: 8 (2m)^2 bytes per group of m elements.  It changes
- * the iteration count, not the solution. */
+/* Preconditioning of the GMRES solves (fmddm_solve, fmddm_poro_solve).
+ * The paper's GMRES is unpreconditioned (NONE); BLOCK is right block-Jacobi
+ * preconditioning with the exact inverse of the operator restricted to
+ * groups of neighbouring elements (runs in tree order within one leaf):
+ * at most 32 elements for the elastic system (8 (2m)^2 bytes per group of
+ * m), at most 21 for the poroelastic left-hand side F(dt) (8 (3m)^2 bytes;
+ * rebuilt when the medium or dt changes).  Built once per tree.  It
+ * changes the iteration count, not the solution. */
 typedef enum {
     FMDDM_PRECOND_NONE = 0,
     FMDDM_PRECOND_BLOCK = 1

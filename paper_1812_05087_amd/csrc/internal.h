@@ -76,6 +76,18 @@ struct Cheb {
     std::vector<double> h_xbar, h_tnode, h_glt, h_glw, h_bw;
 };
 
+// Block-Jacobi preconditioner: groups of elements (first tree position,
+// count), each with the inverse of its (nc m)^2 block, column-major, at
+// inv + off[group]; nc unknowns per element (2 elastic, 3 poroelastic).
+// key: the parameters the blocks were built for (poroelastic medium, dt).
+struct PcBlocks {
+    int nblk = 0, nc = 0;
+    DBuf<int> beg, cnt;
+    DBuf<int64_t> off;
+    DBuf<double> inv;
+    double key[6] = {0, 0, 0, 0, 0, 0};
+};
+
 struct M2LOps {
     int ready = 0;
     int mode = 0;           // fmddm_m2l_mode
@@ -207,12 +219,8 @@ struct fmddm_tree {
     fmddm::DBuf<double> gm_V, gm_w, gm_r, gm_sc, gm_part;
     int gm_restart = 0;
     int64_t gm_len = 0;
-    // block-Jacobi preconditioner: groups of elements (first tree position,
-    // count), offsets of their inverses (column-major) in pc_inv
-    int pc_nblk = 0;
-    fmddm::DBuf<int> pc_beg, pc_cnt;
-    fmddm::DBuf<int64_t> pc_off;
-    fmddm::DBuf<double> pc_inv;
+    // block-Jacobi preconditioners of the elastic and poroelastic systems
+    fmddm::PcBlocks pc, ppc;
     fmddm::DBuf<double> gm_z;          // preconditioned basis vector M^-1 v_j
     // poroelastic workspace: chunk partials, term times, term vectors
     fmddm::DBuf<double> poro_part, poro_times, poro_E;
@@ -326,11 +334,16 @@ constexpr int APPLY_FMM_FP64 = 101;
 inline int64_t vec_len(const fmddm_tree *t, int mode) { return (mode == APPLY_PORO ? 3 : 2) * t->n; }
 // precond.hip
 void pc_setup(fmddm_ctx *ctx, fmddm_tree *t);
-void pc_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *in, int acc, double *out);
+// groups of at most maxm elements (runs in tree order within one leaf) and
+// the offsets of their (nc m)^2 inverses; allocates B's arrays
+void pc_groups(fmddm_ctx *ctx, fmddm_tree *t, int maxm, int nc, PcBlocks &B);
+// out = M^-1 in (acc = 0) or out += M^-1 in (acc = 1), caller order
+void pc_apply(fmddm_ctx *ctx, fmddm_tree *t, const PcBlocks &B, const double *in, int acc, double *out);
 // poro.hip
 void poro_apply(fmddm_ctx *ctx, fmddm_tree *t, int lag, const double *D, double *out);
 void poro_history(fmddm_ctx *ctx, fmddm_tree *t, int h, const double *Dh, double *rhs);
 void poro_rhs(fmddm_ctx *ctx, fmddm_tree *t, const double *pf, double SH, double Sh, double *rhs);
+void pc_setup_poro(fmddm_ctx *ctx, fmddm_tree *t);
 
 inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 

@@ -37,6 +37,7 @@
 // the diffusion length) takes one 8-point rule over the whole element.  The
 // drained part is the closed-form constant element.
 #include "elem.h"
+#include "gj.h"
 #include "internal.h"
 
 #include <cmath>
@@ -251,6 +252,54 @@ __global__ __launch_bounds__(PT) void k_poro_pairs(int n, const double *__restri
     pp[0] = ts;
     pp[1] = tn;
     pp[2] = o[3];
+}
+
+// Block-Jacobi blocks of the left-hand side F(dt): one workgroup per group
+// of m <= PPB elements (tree order), A[3i + r][3j + c] = response r (shear
+// traction, normal traction, pressure) at element i to a unit unknown c
+// (D_s, D_n, D_q) on element j, by the same element integrals as the
+// product; inverted in LDS, written column-major at inv + off[b].
+constexpr int PPB = GJN / 3;
+
+__global__ __launch_bounds__(256) void k_ppc_build(int nblk, const int *__restrict__ beg,
+                                                   const int *__restrict__ cnt, const int64_t *__restrict__ off,
+                                                   const double *__restrict__ cx, const double *__restrict__ cy,
+                                                   const double *__restrict__ cb, const double *__restrict__ sb,
+                                                   const double *__restrict__ ha, double dt, PoroK K,
+                                                   double *__restrict__ inv, int *__restrict__ bad)
+{
+    __shared__ double A[GJN][GJN + 1];
+    __shared__ double colk[GJN];
+    __shared__ int piv[GJN];
+    __shared__ double e_cx[PPB], e_cy[PPB], e_cb[PPB], e_sb[PPB], e_a[PPB];
+    int b = blockIdx.x, tid = threadIdx.x;
+    int s0 = beg[b], m = cnt[b], nb = 3 * m;
+    if (tid < m) {
+        e_cx[tid] = cx[s0 + tid]; e_cy[tid] = cy[s0 + tid]; e_cb[tid] = cb[s0 + tid];
+        e_sb[tid] = sb[s0 + tid]; e_a[tid] = ha[s0 + tid];
+    }
+    __syncthreads();
+    for (int e = tid; e < 3 * m * m; e += 256) {
+        int c = e / (m * m), ij = e - c * m * m, i = ij / m, j = ij - i * m;
+        double Ds = c == 0 ? 1.0 : 0.0, Dn = c == 1 ? 1.0 : 0.0, Dq = c == 2 ? 1.0 : 0.0;
+        double q[3], o[4] = {0.0, 0.0, 0.0, 0.0};
+        charge(e_cb[j], e_sb[j], Ds, Dn, q[0], q[1], q[2]);
+        elem_transient(K, e_cx[i], e_cy[i], e_cx[j], e_cy[j], e_cb[j], e_sb[j], e_a[j], q, Dq, dt, 1.0, o);
+        elem_stress_add(e_cx[i], e_cy[i], e_cx[j], e_cy[j], e_cb[j], e_sb[j], e_a[j], Ds, Dn, K.gc, o[0], o[1],
+                        o[2]);
+        double ts, tn;
+        traction(e_cb[i], e_sb[i], o[0], o[1], o[2], ts, tn);
+        A[3 * i][3 * j + c] = ts;
+        A[3 * i + 1][3 * j + c] = tn;
+        A[3 * i + 2][3 * j + c] = o[3];
+    }
+    __syncthreads();
+    gj_invert(A, nb, colk, piv, bad);
+    double *o = inv + off[b];
+    for (int e = tid; e < nb * nb; e += 256) {
+        int c = e / nb, r = e % nb;
+        o[e] = A[r][c];
+    }
 }
 
 __global__ void k_scale_copy(int m, double a, const double *__restrict__ x, double *__restrict__ y)
@@ -731,6 +780,36 @@ void poro_history(fmddm_ctx *ctx, fmddm_tree *t, int h, const double *Dh, double
     std::vector<double> times(h);
     for (int j = 1; j <= h; ++j) times[j - 1] = j * dt;
     poro_sum(ctx, t, h, times, t->poro_E.p, -1, 1, rhs);
+}
+
+// Block-Jacobi preconditioner of the poroelastic left-hand side, rebuilt
+// when the medium or the time step changes.
+void pc_setup_poro(fmddm_ctx *ctx, fmddm_tree *t)
+{
+    if (!ctx->poro_set) throw Error{FMDDM_EINVAL, "poroelastic parameters not set (fmddm_poro_set)"};
+    PcBlocks &B = t->ppc;
+    const fmddm_poro_params &q = ctx->poro;
+    const double key[6] = {q.nu_u, q.alpha, q.perm, q.visc, q.dt, ctx->prm.E + 1e-3 * ctx->prm.nu};
+    bool same = B.nblk > 0;
+    for (int k = 0; k < 6; ++k) same = same && B.key[k] == key[k];
+    if (same) return;
+    hipStream_t s = ctx->stream;
+    upload_rules(ctx->device);
+    pc_groups(ctx, t, PPB, 3, B);
+    DBuf<int> bad;
+    bad.alloc(1);
+    bad.zero(s);
+    hipLaunchKernelGGL(k_ppc_build, dim3(B.nblk), dim3(256), 0, s, B.nblk, B.beg.p, B.cnt.p, B.off.p, t->scx.p,
+                       t->scy.p, t->scb.p, t->ssb.p, t->sa.p, q.dt, poro_constants(ctx), B.inv.p, bad.p);
+    FM_CHECK_LAUNCH();
+    int hbad = 0;
+    FM_HIP(hipMemcpyAsync(&hbad, bad.p, 4, hipMemcpyDeviceToHost, s));
+    FM_HIP(hipStreamSynchronize(s));
+    if (hbad) {
+        B.nblk = 0;
+        throw Error{FMDDM_EGEOM, "singular poroelastic preconditioner block"};
+    }
+    for (int k = 0; k < 6; ++k) B.key[k] = key[k];
 }
 
 void poro_rhs(fmddm_ctx *ctx, fmddm_tree *t, const double *pf, double SH, double Sh, double *rhs)

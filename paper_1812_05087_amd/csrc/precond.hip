@@ -11,8 +11,10 @@
 // its elements from their shear/normal DDs, the exact element formulas) is
 // assembled and inverted by one workgroup in LDS (Gauss-Jordan with
 // partial pivoting) once per tree; a product with M^-1 is then one small
-// dense product per group.
+// dense product per group.  The poroelastic system's blocks (3 unknowns per
+// element) are built in poro.hip and applied here.
 #include "elem.h"
+#include "gj.h"
 #include "internal.h"
 
 #include <cmath>
@@ -21,12 +23,11 @@
 namespace fmddm {
 namespace {
 
-constexpr int PCB = 32;          // elements per group
-constexpr int PCN = 2 * PCB;     // block dimension
+constexpr int PCB = GJN / 2;  // elements per elastic group
 
 // One workgroup per group: assemble the block, invert in place, write the
-// inverse column-major at inv + off[b].  bad[0] is set (vector store) when a
-// pivot vanishes.
+// inverse column-major at inv + off[b].  bad[0] is set when a pivot
+// vanishes.
 __global__ __launch_bounds__(256) void k_pc_build(int nblk, const int *__restrict__ beg,
                                                   const int *__restrict__ cnt, const int64_t *__restrict__ off,
                                                   const double *__restrict__ cx, const double *__restrict__ cy,
@@ -34,9 +35,9 @@ __global__ __launch_bounds__(256) void k_pc_build(int nblk, const int *__restric
                                                   const double *__restrict__ a, double gc,
                                                   double *__restrict__ inv, int *__restrict__ bad)
 {
-    __shared__ double A[PCN][PCN + 1];
-    __shared__ double colk[PCN];
-    __shared__ int piv[PCN];
+    __shared__ double A[GJN][GJN + 1];
+    __shared__ double colk[GJN];
+    __shared__ int piv[GJN];
     __shared__ double e_cx[PCB], e_cy[PCB], e_cb[PCB], e_sb[PCB], e_a[PCB];
     int b = blockIdx.x, tid = threadIdx.x;
     int s0 = beg[b], m = cnt[b], nb = 2 * m;
@@ -59,63 +60,7 @@ __global__ __launch_bounds__(256) void k_pc_build(int nblk, const int *__restric
         }
     }
     __syncthreads();
-    // in-place Gauss-Jordan: after step k, column k holds the inverse's
-    // column for the (row-swapped) matrix; swaps are undone on the columns
-    for (int k = 0; k < nb; ++k) {
-        if (tid < 64) {  // pivot: largest |A[i][k]|, i >= k (smallest i on ties)
-            double v = (tid >= k && tid < nb) ? fabs(A[tid][k]) : -1.0;
-            int idx = tid;
-            for (int o = 32; o > 0; o >>= 1) {
-                double v2 = __shfl_xor(v, o);
-                int i2 = __shfl_xor(idx, o);
-                if (v2 > v || (v2 == v && i2 < idx)) {
-                    v = v2;
-                    idx = i2;
-                }
-            }
-            if (tid == 0) {
-                piv[k] = idx;
-                if (!(v > 0.0)) bad[0] = 1;
-            }
-        }
-        __syncthreads();
-        int p = piv[k];
-        if (p != k)
-            for (int j = tid; j < nb; j += 256) {
-                double t = A[k][j];
-                A[k][j] = A[p][j];
-                A[p][j] = t;
-            }
-        __syncthreads();
-        double d = 1.0 / A[k][k];
-        if (tid < nb) colk[tid] = A[tid][k];
-        __syncthreads();
-        // row k scaled, column k replaced, the rest eliminated
-        for (int e = tid; e < nb * nb; e += 256) {
-            int i = e / nb, j = e % nb;
-            if (i == k) {
-                A[k][j] = j == k ? d : A[k][j] * d;
-            } else if (j == k) {
-                A[i][k] = -colk[i] * d;
-            }
-        }
-        __syncthreads();
-        for (int e = tid; e < nb * nb; e += 256) {
-            int i = e / nb, j = e % nb;
-            if (i != k && j != k) A[i][j] -= colk[i] * A[k][j];
-        }
-        __syncthreads();
-    }
-    for (int k = nb - 1; k >= 0; --k) {
-        int p = piv[k];
-        if (p != k)
-            for (int i = tid; i < nb; i += 256) {
-                double t = A[i][k];
-                A[i][k] = A[i][p];
-                A[i][p] = t;
-            }
-        __syncthreads();
-    }
+    gj_invert(A, nb, colk, piv, bad);
     double *o = inv + off[b];
     for (int e = tid; e < nb * nb; e += 256) {
         int c = e / nb, r = e % nb;
@@ -124,17 +69,21 @@ __global__ __launch_bounds__(256) void k_pc_build(int nblk, const int *__restric
 }
 
 // out = M^-1 in (acc = 0) or out += M^-1 in (acc = 1); vectors in caller
-// order, two entries per element.  One 64-lane workgroup per group.
-__global__ __launch_bounds__(64) void k_pc_apply(int nblk, const int *__restrict__ beg,
+// order, nc entries per element.  One 64-lane workgroup per group.
+__global__ __launch_bounds__(64) void k_pc_apply(int nblk, int nc, const int *__restrict__ beg,
                                                  const int *__restrict__ cnt, const int64_t *__restrict__ off,
                                                  const int *__restrict__ perm, const double *__restrict__ inv,
                                                  const double *__restrict__ in, int acc, double *__restrict__ out)
 {
-    __shared__ double xs[PCN];
+    __shared__ double xs[GJN];
     int b = blockIdx.x, tid = threadIdx.x;
-    int s0 = beg[b], nb = 2 * cnt[b];
-    int idx = tid < nb ? 2 * perm[s0 + tid / 2] + (tid & 1) : 0;
-    if (tid < nb) xs[tid] = in[idx];
+    int s0 = beg[b], nb = nc * cnt[b];
+    int idx = 0;
+    if (tid < nb) {
+        int el = tid / nc;
+        idx = nc * perm[s0 + el] + (tid - nc * el);
+        xs[tid] = in[idx];
+    }
     __syncthreads();
     if (tid < nb) {
         const double *col = inv + off[b] + tid;
@@ -146,9 +95,8 @@ __global__ __launch_bounds__(64) void k_pc_apply(int nblk, const int *__restrict
 
 }  // namespace
 
-void pc_setup(fmddm_ctx *ctx, fmddm_tree *t)
+void pc_groups(fmddm_ctx *ctx, fmddm_tree *t, int maxm, int nc, PcBlocks &B)
 {
-    if (t->pc_nblk > 0) return;
     hipStream_t s = ctx->stream;
     int ncell = t->ncell;
     std::vector<int> hb(ncell), he(ncell);
@@ -159,39 +107,52 @@ void pc_setup(fmddm_ctx *ctx, fmddm_tree *t)
     std::vector<int64_t> off;
     int64_t tot = 0;
     for (int c : t->leaves)
-        for (int q = hb[c]; q < he[c]; q += PCB) {
-            int m = std::min(PCB, he[c] - q);
+        for (int q = hb[c]; q < he[c]; q += maxm) {
+            int m = std::min(maxm, he[c] - q);
             beg.push_back(q);
             cnt.push_back(m);
             off.push_back(tot);
-            tot += 4 * (int64_t)m * m;
+            tot += (int64_t)(nc * m) * (nc * m);
         }
     int nblk = (int)beg.size();
-    t->pc_beg.alloc(nblk);
-    t->pc_cnt.alloc(nblk);
-    t->pc_off.alloc(nblk);
-    t->pc_inv.alloc(tot);
-    FM_HIP(hipMemcpyAsync(t->pc_beg.p, beg.data(), nblk * 4, hipMemcpyHostToDevice, s));
-    FM_HIP(hipMemcpyAsync(t->pc_cnt.p, cnt.data(), nblk * 4, hipMemcpyHostToDevice, s));
-    FM_HIP(hipMemcpyAsync(t->pc_off.p, off.data(), nblk * 8, hipMemcpyHostToDevice, s));
+    B.beg.alloc(nblk);
+    B.cnt.alloc(nblk);
+    B.off.alloc(nblk);
+    B.inv.alloc(tot);
+    FM_HIP(hipMemcpyAsync(B.beg.p, beg.data(), nblk * 4, hipMemcpyHostToDevice, s));
+    FM_HIP(hipMemcpyAsync(B.cnt.p, cnt.data(), nblk * 4, hipMemcpyHostToDevice, s));
+    FM_HIP(hipMemcpyAsync(B.off.p, off.data(), nblk * 8, hipMemcpyHostToDevice, s));
+    FM_HIP(hipStreamSynchronize(s));
+    B.nblk = nblk;
+    B.nc = nc;
+}
+
+void pc_setup(fmddm_ctx *ctx, fmddm_tree *t)
+{
+    PcBlocks &B = t->pc;
+    if (B.nblk > 0) return;
+    hipStream_t s = ctx->stream;
+    pc_groups(ctx, t, PCB, 2, B);
     DBuf<int> bad;
     bad.alloc(1);
     bad.zero(s);
-    hipLaunchKernelGGL(k_pc_build, dim3(nblk), dim3(256), 0, s, nblk, t->pc_beg.p, t->pc_cnt.p, t->pc_off.p,
-                       t->scx.p, t->scy.p, t->scb.p, t->ssb.p, t->sa.p, ctx->gc, t->pc_inv.p, bad.p);
+    hipLaunchKernelGGL(k_pc_build, dim3(B.nblk), dim3(256), 0, s, B.nblk, B.beg.p, B.cnt.p, B.off.p, t->scx.p,
+                       t->scy.p, t->scb.p, t->ssb.p, t->sa.p, ctx->gc, B.inv.p, bad.p);
     FM_CHECK_LAUNCH();
     int hbad = 0;
     FM_HIP(hipMemcpyAsync(&hbad, bad.p, 4, hipMemcpyDeviceToHost, s));
     FM_HIP(hipStreamSynchronize(s));
-    if (hbad) throw Error{FMDDM_EGEOM, "singular preconditioner block (coincident elements?)"};
-    t->pc_nblk = nblk;
-    t->bytes += (int64_t)tot * 8 + (int64_t)nblk * 16;
+    if (hbad) {
+        B.nblk = 0;
+        throw Error{FMDDM_EGEOM, "singular preconditioner block (coincident elements?)"};
+    }
+    t->bytes += (int64_t)B.inv.bytes() + (int64_t)B.nblk * 16;
 }
 
-void pc_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *in, int acc, double *out)
+void pc_apply(fmddm_ctx *ctx, fmddm_tree *t, const PcBlocks &B, const double *in, int acc, double *out)
 {
-    hipLaunchKernelGGL(k_pc_apply, dim3(t->pc_nblk), dim3(64), 0, ctx->stream, t->pc_nblk, t->pc_beg.p,
-                       t->pc_cnt.p, t->pc_off.p, t->perm.p, t->pc_inv.p, in, acc, out);
+    hipLaunchKernelGGL(k_pc_apply, dim3(B.nblk), dim3(64), 0, ctx->stream, B.nblk, B.nc, B.beg.p, B.cnt.p,
+                       B.off.p, t->perm.p, B.inv.p, in, acc, out);
     FM_CHECK_LAUNCH();
 }
 

@@ -285,12 +285,13 @@ void GmresRun::start(fmddm_ctx *c, fmddm_tree *tr, int md, const double *rhs, do
     maxit = mx;
     j = next = it = restarts = 0;
     eager_done = false;
-    pc = ctx->prm.precond == FMDDM_PRECOND_BLOCK && mode != APPLY_PORO;
+    pc = ctx->prm.precond == FMDDM_PRECOND_BLOCK;
     bnorm = relres = 0.0;
     converged = false;
     gmres_workspace(t, ctx->prm.restart, (int)vec_len(t, mode));
     if (pc) {
-        pc_setup(ctx, t);
+        if (mode == APPLY_PORO) pc_setup_poro(ctx, t);
+        else pc_setup(ctx, t);
         if (!t->gm_z.p || t->gm_z.n < (size_t)vec_len(t, mode)) t->gm_z.alloc(vec_len(t, mode));
     }
     SW s{ctx->prm.restart};
@@ -374,7 +375,7 @@ void GmresRun::step_body(int jj)
     double *V = t->gm_V.p, *w = t->gm_w.p, *sc = t->gm_sc.p;
     double *vj = V + (size_t)jj * ldv, *vn = V + (size_t)(jj + 1) * ldv;
     if (pc) {
-        pc_apply(ctx, t, vj, 0, t->gm_z.p);
+        pc_apply(ctx, t, mode == APPLY_PORO ? t->ppc : t->pc, vj, 0, t->gm_z.p);
         apply_mode(ctx, t, mode, t->gm_z.p, w);
     } else {
         apply_mode(ctx, t, mode, vj, w);
@@ -460,7 +461,7 @@ bool GmresRun::advance(bool block)
                 hipLaunchKernelGGL(k_fill, dim3(gb), dim3(256), 0, st, n2, 0.0, u);
                 hipLaunchKernelGGL(k_vupdate, dim3(gb), dim3(256), 0, st, n2, k, V, ldv, sc + s.y(), 1.0, u);
                 FM_CHECK_LAUNCH();
-                pc_apply(ctx, t, u, 1, x);
+                pc_apply(ctx, t, mode == APPLY_PORO ? t->ppc : t->pc, u, 1, x);
             } else {
                 hipLaunchKernelGGL(k_vupdate, dim3(gb), dim3(256), 0, st, n2, k, V, ldv, sc + s.y(), 1.0, x);
             }

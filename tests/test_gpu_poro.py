@@ -199,3 +199,37 @@ def test_poro_fmm_time_marching():
         e = cmp(a, b)
         print("poro fmm marching step", h + 1, e)
         assert e <= 1e-6, (h, e)
+
+
+@pytest.mark.parametrize("mode", [F.FMDDM_APPLY_DIRECT, F.FMDDM_APPLY_FMM])
+def test_poro_block_jacobi(mode):
+    """Block-Jacobi preconditioning of the poroelastic left-hand side (groups
+    of at most 21 elements, 3 unknowns each): same solution as plain GMRES
+    (both to 1e-11), in at most half the products."""
+    wl = W.well_cluster(n_frac=3, elems=60, half_length=6.0, spacing=2.0)
+    n3 = 3 * wl.n
+    res = {}
+    for pc in (F.FMDDM_PRECOND_NONE, F.FMDDM_PRECOND_BLOCK):
+        prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=MED["E"], nu=MED["nu"], p=8, leaf=16, tol=1e-11,
+                         restart=50, maxit=20000, precond=pc)
+        F.fmddm_poro_set(prob.ctx, MED["nuu"], MED["alpha"], MED["perm"], MED["visc"], DT, P0, mode=mode)
+        b0 = torch.zeros(n3, dtype=torch.float64, device="cuda")
+        F.fmddm_poro_rhs(prob.ctx, prob.tree, dev(wl.pressure), wl.SH, wl.Sh, b0)
+        hist = torch.zeros(2 * n3, dtype=torch.float64, device="cuda")
+        D = torch.zeros(n3, dtype=torch.float64, device="cuda")
+        its = []
+        for h in (1, 2):
+            rhs = b0.clone()
+            F.fmddm_add_history(prob.ctx, prob.tree, h, hist[:n3] if h > 1 else None, rhs)
+            st, info = F.fmddm_poro_solve(prob.ctx, prob.tree, rhs, D)
+            assert st == F.FMDDM_OK and info["converged"], (pc, h, info)
+            hist[(h - 1) * n3: h * n3] = D
+            its.append(info["iters"])
+        res[pc] = (hist.cpu().numpy(), its)
+        print(f"mode {mode} precond {pc}: iterations {its}")
+        prob.close()
+    for h in range(2):
+        a = res[F.FMDDM_PRECOND_BLOCK][0][h * n3:(h + 1) * n3]
+        b = res[F.FMDDM_PRECOND_NONE][0][h * n3:(h + 1) * n3]
+        assert cmp(a, b) <= 1e-7, (h, cmp(a, b))
+        assert 2 * res[F.FMDDM_PRECOND_BLOCK][1][h] <= res[F.FMDDM_PRECOND_NONE][1][h], res
