@@ -344,6 +344,51 @@ def precision_leg(F, W, steps, tune, leaf, p, solve_tol=1e-8, target_err=1e-6):
     return out
 
 
+def march_leg(F, W, elems, steps, p=10):
+    """A full poroelastic time march (the horizontal-well example's shape,
+    Section 5.2.1): 5 fractures of `elems` 0.2 m elements 10 m apart, `steps`
+    steps of 60 s, every step's history sum and GMRES solve (tol 1e-6,
+    block-Jacobi, restart 100) on the multipole operators."""
+    import torch
+    wl = W.well_cluster(n_frac=5, elems=elems, half_length=0.1 * elems, spacing=10.0)
+    n3 = 3 * wl.n
+    prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=20e9, nu=0.2, p=p, leaf=32, m2l=1, m2l_tol=1e-10, tol=1e-6,
+                     restart=100, maxit=5000, precond=F.FMDDM_PRECOND_BLOCK)
+    F.fmddm_poro_set(prob.ctx, 0.35, 0.8, 1e-18, 1e-3, 60.0, 48.26e6, mode=F.FMDDM_APPLY_FMM)
+    b0 = torch.zeros(n3, dtype=torch.float64, device="cuda")
+    F.fmddm_poro_rhs(prob.ctx, prob.tree, torch.as_tensor(wl.pressure).cuda(), wl.SH, wl.Sh, b0)
+    hist = torch.zeros(steps * n3, dtype=torch.float64, device="cuda")
+    D = torch.zeros(n3, dtype=torch.float64, device="cuda")
+    th = tsv = 0.0
+    its, worst = 0, 0.0
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    for h in range(1, steps + 1):
+        t0 = time.perf_counter()
+        rhs = b0.clone()
+        F.fmddm_add_history(prob.ctx, prob.tree, h, hist[: (h - 1) * n3] if h > 1 else None, rhs)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st, info = F.fmddm_poro_solve(prob.ctx, prob.tree, rhs, D)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if st != F.FMDDM_OK:
+            raise RuntimeError(f"march step {h}: {info}")
+        hist[(h - 1) * n3: h * n3] = D
+        th += t1 - t0
+        tsv += t2 - t1
+        its += info["iters"]
+        worst = max(worst, info["relres"])
+    total = time.perf_counter() - t_all
+    Dm = D.cpu().numpy().reshape(-1, 3)
+    mid = Dm[2 * elems: 3 * elems]
+    prob.close()
+    return {"workload": f"well cluster 5 x {elems} elements (N={wl.n}), {steps} steps of 60 s", "p": p,
+            "total_s": total, "history_s": th, "solve_s": tsv, "gmres_products": its,
+            "max_step_relres": worst,
+            "middle_fracture_max_shear_over_opening": float(np.abs(mid[:, 0]).max() / np.abs(Dm[:, 1]).max())}
+
+
 def cpu_baseline(wl, D, seconds):
     """The oracle's exact on-the-fly product of the whole workload on all
     host cores, repeated for about `seconds` of wall time."""
@@ -382,6 +427,9 @@ def main():
                     help="only copy 256 MiB device-to-device 5 times (reference for HBM byte counters)")
     ap.add_argument("--history-elems", type=int, default=4000)
     ap.add_argument("--history-steps", type=int, default=10)
+    ap.add_argument("--march-elems", type=int, default=400)
+    ap.add_argument("--march-steps", type=int, default=50,
+                    help="poroelastic time steps of the full-march leg (0 skips it)")
     ap.add_argument("--precision-steps", type=int, default=20,
                     help="products timed per precision at N=200000 (0 skips the mixed-precision leg)")
     ap.add_argument("--precision-no-tune", action="store_true")
@@ -520,6 +568,8 @@ def main():
         line["serving"] = serving_leg(F, W, args.serve_requests, args.serve_slots, args.serve_load)
     if args.history_elems > 0:
         line["history"] = history_leg(F, W, args.history_elems, args.history_steps)
+    if args.march_steps > 0:
+        line["march"] = march_leg(F, W, args.march_elems, args.march_steps)
     if args.precision_steps > 0:
         line["mixed_precision"] = precision_leg(F, W, args.precision_steps, not args.precision_no_tune,
                                                 args.precision_leaf, args.precision_p)
