@@ -144,7 +144,7 @@ __global__ void k_cycle_start(SW s, double *__restrict__ sc)
 // Column j of the Hessenberg matrix from the two Gram-Schmidt passes and the
 // new norm; previous rotations applied, new rotation formed, residual
 // estimate |g_{j+1}| updated.
-__global__ void k_givens(SW s, int j, double *__restrict__ sc)
+__device__ void givens_step(SW s, int j, double *__restrict__ sc)
 {
     double *H = sc + s.H() + (size_t)j * (s.m + 1);
     double *cs = sc + s.cs(), *sn = sc + s.sn(), *g = sc + s.g();
@@ -164,6 +164,62 @@ __global__ void k_givens(SW s, int j, double *__restrict__ sc)
     g[j + 1] = -sn[j] * g[j];
     g[j] = cs[j] * g[j];
     sc[s.est()] = fabs(g[j + 1]);
+}
+
+__global__ void k_givens(SW s, int j, double *__restrict__ sc) { givens_step(s, j, sc); }
+
+// Fused Arnoldi pieces for short vectors (few dot-product chunks), where
+// launches, not bytes, set the time.  k_vupdate_sum: every block forms the
+// k dot products from the chunk partials (same fixed order in every block,
+// so all blocks agree bit for bit; block 0 stores them for the rotation),
+// then w += sign * sum_i h_i V_i over its 256 entries; with `npart`, also
+// the block's partial of ||w||^2 after the update.
+constexpr int FCH = 32;  // most chunks summed per dot product in the fused path
+
+__global__ __launch_bounds__(256) void k_vupdate_sum(int m, int k, const double *__restrict__ V, int ldv,
+                                                     const double *__restrict__ part, int nchunk, double sign,
+                                                     double *__restrict__ w, double *__restrict__ hout,
+                                                     double *__restrict__ npart)
+{
+    extern __shared__ double hs[];  // k
+    __shared__ double red[RT];
+    for (int i = threadIdx.x; i < k; i += RT) {
+        double s = 0.0;
+        for (int c = 0; c < nchunk; ++c) s += part[(size_t)i * nchunk + c];
+        hs[i] = s;
+        if (blockIdx.x == 0) hout[i] = s;
+    }
+    __syncthreads();
+    int t = blockIdx.x * RT + threadIdx.x;
+    double wt = 0.0;
+    if (t < m) {
+        double s = 0.0;
+        for (int i = 0; i < k; ++i) s += hs[i] * V[(size_t)i * ldv + t];
+        wt = w[t] + sign * s;
+        w[t] = wt;
+    }
+    if (npart) {
+        double q = block_sum(wt * wt, red);
+        if (threadIdx.x == 0) npart[blockIdx.x] = q;
+    }
+}
+
+// ||w|| from the update blocks' partials (every block sums them the same
+// way), v = w / ||w||, and in block 0 the Hessenberg column and rotation.
+__global__ __launch_bounds__(256) void k_scale_givens(int m, const double *__restrict__ w,
+                                                      const double *__restrict__ npart, int nnp,
+                                                      double *__restrict__ v, SW s, int j,
+                                                      double *__restrict__ sc)
+{
+    __shared__ double red[RT];
+    double q = 0.0;
+    for (int b = threadIdx.x; b < nnp; b += RT) q += npart[b];
+    double nrm = sqrt(block_sum(q, red));
+    for (int t = blockIdx.x * RT + threadIdx.x; t < m; t += gridDim.x * RT) v[t] = nrm != 0.0 ? w[t] / nrm : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        sc[s.nrm()] = nrm;
+        givens_step(s, j, sc);
+    }
 }
 
 // y = R^{-1} g over the first k columns.
@@ -249,7 +305,7 @@ static void gmres_workspace(fmddm_tree *t, int m, int n2)
         t->gm_w.alloc(ldv);
         t->gm_r.alloc(ldv);
         t->gm_sc.alloc(s.size());
-        t->gm_part.alloc((size_t)(m + 1) * cdiv(n2, DCH));
+        t->gm_part.alloc((size_t)(m + 1) * cdiv(n2, DCH) + cdiv(n2, 256));
         t->drop_graphs();
         t->gm_restart = m;
         t->gm_len = n2;
@@ -380,13 +436,28 @@ void GmresRun::step_body(int jj)
     } else {
         apply_mode(ctx, t, mode, vj, w);
     }
-    dots(st, n2, jj + 1, V, ldv, w, t->gm_part.p, sc + s.h1());
-    hipLaunchKernelGGL(k_vupdate, dim3(gb), dim3(256), 0, st, n2, jj + 1, V, ldv, sc + s.h1(), -1.0, w);
-    dots(st, n2, jj + 1, V, ldv, w, t->gm_part.p, sc + s.h2());
-    hipLaunchKernelGGL(k_vupdate, dim3(gb), dim3(256), 0, st, n2, jj + 1, V, ldv, sc + s.h2(), -1.0, w);
-    norm2(st, n2, w, t->gm_part.p, sc + s.nrm());
-    hipLaunchKernelGGL(k_scale, dim3(gb), dim3(256), 0, st, n2, w, sc + s.nrm(), vn);
-    hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, st, s, jj, sc);
+    const int nchunk = cdiv(n2, DCH);
+    if (nchunk <= FCH) {
+        // five launches: two (partial dots, update) passes, then norm,
+        // scaling and rotation
+        const size_t hsm = (size_t)(jj + 1) * 8;
+        double *np = t->gm_part.p + (size_t)(m + 1) * nchunk;  // gb norm partials after the dot partials
+        hipLaunchKernelGGL(k_dots_part, dim3(nchunk), dim3(RT), 0, st, n2, jj + 1, V, ldv, w, nchunk, t->gm_part.p);
+        hipLaunchKernelGGL(k_vupdate_sum, dim3(gb), dim3(RT), hsm, st, n2, jj + 1, V, ldv, t->gm_part.p, nchunk,
+                           -1.0, w, sc + s.h1(), (double *)nullptr);
+        hipLaunchKernelGGL(k_dots_part, dim3(nchunk), dim3(RT), 0, st, n2, jj + 1, V, ldv, w, nchunk, t->gm_part.p);
+        hipLaunchKernelGGL(k_vupdate_sum, dim3(gb), dim3(RT), hsm, st, n2, jj + 1, V, ldv, t->gm_part.p, nchunk,
+                           -1.0, w, sc + s.h2(), np);
+        hipLaunchKernelGGL(k_scale_givens, dim3(std::min(gb, 64)), dim3(RT), 0, st, n2, w, np, gb, vn, s, jj, sc);
+    } else {
+        dots(st, n2, jj + 1, V, ldv, w, t->gm_part.p, sc + s.h1());
+        hipLaunchKernelGGL(k_vupdate, dim3(gb), dim3(256), 0, st, n2, jj + 1, V, ldv, sc + s.h1(), -1.0, w);
+        dots(st, n2, jj + 1, V, ldv, w, t->gm_part.p, sc + s.h2());
+        hipLaunchKernelGGL(k_vupdate, dim3(gb), dim3(256), 0, st, n2, jj + 1, V, ldv, sc + s.h2(), -1.0, w);
+        norm2(st, n2, w, t->gm_part.p, sc + s.nrm());
+        hipLaunchKernelGGL(k_scale, dim3(gb), dim3(256), 0, st, n2, w, sc + s.nrm(), vn);
+        hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, st, s, jj, sc);
+    }
     FM_CHECK_LAUNCH();
     FM_HIP(hipMemcpyAsync(t->gm_host + 2 * (jj & 1), sc + s.nrm(), 16, hipMemcpyDeviceToHost, st));
 }
