@@ -119,10 +119,10 @@ def traffic_for(phase):
 SERVE_PARAMS = dict(p=10, leaf=32, m2l=1, m2l_tol=1e-10, restart=50, maxit=20000, use_graphs=0)
 
 
-def serve_run(F, wls, reqs, slots, arrivals, precond=1):
+def serve_run(F, wls, reqs, slots, arrivals, precond=1, precision=0):
     """Serve the requests with `slots` admission slots; request i is
     submitted at arrivals[i] seconds.  Returns (makespan s, latencies s)."""
-    prm = F.fmddm_default_params(**SERVE_PARAMS, precond=precond)
+    prm = F.fmddm_default_params(**SERVE_PARAMS, precond=precond, precision=precision)
     srv = F.fmddm_server_create(prm, slots)
     try:
         warm = F.fmddm_server_submit(srv, wls[0].x1, wls[0].y1, wls[0].x2, wls[0].y2, wls[0].pressure,
@@ -177,6 +177,7 @@ def serving_leg(F, W, count, slots, load):
     spans, lat, _ = serve_run(F, wls, reqs, slots, arr)
     span_o, lat_o, _ = serve_run(F, wls, reqs, 1, arr)
     span_np, _, iters_np = serve_run(F, wls, reqs, slots, zero, precond=0)
+    span_32, _, iters_32 = serve_run(F, wls, reqs, slots, zero, precision=F.FMDDM_PREC_FP32)
     pct = lambda a, q: float(np.percentile(a, q))
     return {
         "requests": count, "slots": slots, "elements_total": int(sum(w.n for w in wls)),
@@ -186,6 +187,8 @@ def serving_leg(F, W, count, slots, load):
                    "graphs": bool(SERVE_PARAMS["use_graphs"])},
         "unpreconditioned": {"batched_saturated_solves_per_s": count / span_np,
                              "gmres_products_total": iters_np},
+        "fp32_products": {"batched_saturated_solves_per_s": count / span_32, "gmres_products_total": iters_32,
+                          "note": "Arnoldi on FP32-P2P/FP32-M2L products, residuals and stopping test FP64"},
         "one_at_a_time_solves_per_s": rate1,
         "batched_saturated_solves_per_s": count / spanb,
         "poisson_rate_per_s": lam,

@@ -380,6 +380,10 @@ int64_t fmddm_trim_cache(void);
  * buffers and every kernel is deterministic, so a result does not depend on
  * which other requests ran beside it.
  *
+ * The server's parameters apply to every request.  With a reduced
+ * precision, a solve's Arnoldi steps use the reduced-precision FMM product
+ * and its residuals and stopping test the FP64 product (as fmddm_solve).
+ *
  * Threading: a server is driven from one host thread.  All host memory
  * passed in is copied; nothing is kept after the call returns.
  * ------------------------------------------------------------------------ */

@@ -108,6 +108,7 @@ int64_t footprint(const fmddm_params &p, int rank_pad, int64_t n)
     int64_t per_elem = 8LL * p.p * p.p + 8 * 2 * (p.restart + 4) + 8 * 48;
     if (p.precond == FMDDM_PRECOND_BLOCK) per_elem += 8 * 128 + 8 * 2 + 16;
     int64_t per_cell = 8 * (3 * Mp + 2 * rp + 4 * rp + 27 * rp) + 4 * 64;
+    if (p.precision != FMDDM_PREC_FP64) per_cell += 4 * (2 * rp + 4 * rp + 27 * rp);  // FP32 intermediates
     int64_t b = n * per_elem + cells * per_cell + (4 << 20);
     return b + b / 4;
 }
@@ -154,6 +155,13 @@ void fail(fmddm_server *s, Slot &sl, fmddm_status st)
     retire(s, sl);
 }
 
+// Reduced-precision products: Arnoldi on them, residuals and the stopping
+// test with the FP64 product (as fmddm_solve)
+int residual_mode(const fmddm_server *s)
+{
+    return s->prm.precision != FMDDM_PREC_FP64 ? fmddm::APPLY_FMM_FP64 : -1;
+}
+
 void admit(fmddm_server *s, Slot &sl, int64_t id)
 {
     Req &q = s->reqs[id];
@@ -174,7 +182,7 @@ void admit(fmddm_server *s, Slot &sl, int64_t id)
     FM_HIP(hipMemcpyAsync(sl.pf.p, g + 4 * n, n * 8, hipMemcpyHostToDevice, sl.stream));
     FM_HIP(hipMemsetAsync(sl.x.p, 0, 2 * n * 8, sl.stream));
     fmddm::rhs_build(sl.ctx, sl.t, sl.pf.p, q.r.SH, q.r.Sh, sl.b.p, 1.0 / q.r.steps);
-    sl.g.start(sl.ctx, sl.t, FMDDM_APPLY_FMM, sl.b.p, sl.x.p, q.r.tol, s->prm.maxit);
+    sl.g.start(sl.ctx, sl.t, FMDDM_APPLY_FMM, sl.b.p, sl.x.p, q.r.tol, s->prm.maxit, residual_mode(s));
     sl.phase = 1;
 }
 
@@ -195,7 +203,7 @@ void advance(fmddm_server *s, Slot &sl)
         if (sl.step < q.r.steps) {
             double scale = (double)(sl.step + 1) / q.r.steps;
             fmddm::rhs_build(sl.ctx, sl.t, sl.pf.p, q.r.SH, q.r.Sh, sl.b.p, scale);
-            sl.g.start(sl.ctx, sl.t, FMDDM_APPLY_FMM, sl.b.p, sl.x.p, q.r.tol, s->prm.maxit);
+            sl.g.start(sl.ctx, sl.t, FMDDM_APPLY_FMM, sl.b.p, sl.x.p, q.r.tol, s->prm.maxit, residual_mode(s));
             return;
         }
         size_t need = (size_t)(2 * n) * 8;
@@ -246,7 +254,6 @@ fmddm_status fmddm_server_create(const fmddm_params *p, int max_slots, int64_t h
     if (!out) return FMDDM_EINVAL;
     *out = nullptr;
     if (!p || max_slots < 1 || max_slots > 64 || hbm_budget < 0) return FMDDM_EINVAL;
-    if (p->precision != FMDDM_PREC_FP64) return FMDDM_EUNSUPPORTED;  // served solves are FP64 GMRES
     fmddm_server *s = new (std::nothrow) fmddm_server();
     if (!s) return FMDDM_ENOMEM;
     s->prm = *p;

@@ -160,3 +160,30 @@ def test_not_converged_request_fails_cleanly():
         assert F.fmddm_server_step(srv) == (0, 0)
     finally:
         F.fmddm_server_destroy(srv)
+
+
+@pytest.mark.parametrize("prec", [F.FMDDM_PREC_FP32, F.FMDDM_PREC_BF16])
+def test_served_mixed_precision_meets_tolerance(prec):
+    """A server with reduced-precision products: each step's Arnoldi runs on
+    them, residuals on the FP64 product, so the served DDs satisfy the
+    oracle's exact system to the requested tolerance plus the FMM error,
+    and agree with the FP64 server's."""
+    req = W.serving_stream(seed=37, count=1, nmin=1500, nmax=1500, steps_max=1)[0]
+    req.steps = 2
+    out = {}
+    for p in (F.FMDDM_PREC_FP64, prec):
+        prm = F.fmddm_default_params(**P_SERVE, precision=p, precond=F.FMDDM_PRECOND_BLOCK)
+        srv = F.fmddm_server_create(prm, 2)
+        try:
+            t, wl = submit(srv, req, tol=1e-8)
+            r = drain(srv, [t])[t]
+            assert r["state"] == F.FMDDM_REQ_DONE and r["relres"] <= 1e-8, r
+            out[p] = F.fmddm_server_poll(srv, t, wl.n)[1]
+        finally:
+            F.fmddm_server_destroy(srv)
+    g = O.Geometry.of(wl)
+    b = O.rhs(g, wl.pressure, wl.SH, wl.Sh)
+    res = np.linalg.norm(O.direct_matvec(g, out[prec]) - b) / np.linalg.norm(b)
+    d = np.linalg.norm(out[prec] - out[F.FMDDM_PREC_FP64]) / np.linalg.norm(out[F.FMDDM_PREC_FP64])
+    print(f"precision {prec}: exact residual {res:.2e}, vs FP64 server {d:.2e}")
+    assert res <= 1e-6 and d <= 1e-6, (res, d)
