@@ -96,6 +96,8 @@ def lib():
         L.ora_poro_elem_transient.argtypes = ([_d] + [C.c_double] * 12 + [C.c_int, C.c_int, _d])
         L.ora_poro_matrix.argtypes = ([C.c_int64] + [_d] * 5 + [_d, C.c_double, C.c_int,
                                                                C.c_int, C.c_int, _d])
+        L.ora_poro_matrix_rows.argtypes = ([C.c_int64] + [_d] * 5 + [_d, C.c_double, C.c_int, C.c_int, C.c_int,
+                                                                    C.c_int64, _i64, _d])
         _lib = L
     return _lib
 
@@ -377,6 +379,16 @@ def poro_matrix(g: Geometry, po: Poro, dt, m, nq=12, np_min=4):
     lib().ora_poro_matrix(g.n, _p(g.cx), _p(g.cy), _p(g.cb), _p(g.sb), _p(g.a), _p(po.P),
                           float(dt), int(m), int(nq), int(np_min), _p(A))
     return A
+
+
+def poro_matrix_rows(g: Geometry, po: Poro, dt, m, rows, nq=12, np_min=4):
+    """Rows of poro_matrix for the receivers `rows`: array [3 len(rows), 3n]
+    (shear, normal, pressure per receiver)."""
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    R = np.zeros((3 * len(rows), 3 * g.n))
+    lib().ora_poro_matrix_rows(g.n, _p(g.cx), _p(g.cy), _p(g.cb), _p(g.sb), _p(g.a), _p(po.P),
+                               float(dt), int(m), int(nq), int(np_min), len(rows), _p(rows, _i64), _p(R))
+    return R
 
 
 def poro_rhs(g: Geometry, pf, p0, SH, Sh):

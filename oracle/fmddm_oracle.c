@@ -1279,6 +1279,37 @@ void ora_poro_matrix(int64_t n, const double *cx, const double *cy,
     }
 }
 
+/* Rows of the same matrix for the receivers rows[0..nrow): R[(3 k + r) 3n +
+ * 3 j + col] = A[(3 rows[k] + r) 3n + 3 j + col]. */
+void ora_poro_matrix_rows(int64_t n, const double *cx, const double *cy,
+                          const double *cb, const double *sb, const double *a,
+                          const double *P, double dt, int m, int nq, int np_min,
+                          int64_t nrow, const int64_t *rows, double *R)
+{
+    double t1 = (m + 1) * dt, t0 = m * dt;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t kj = 0; kj < nrow * n; ++kj) {
+        int64_t k = kj / n, j = kj % n, i = rows[k];
+        for (int col = 0; col < 3; ++col) {
+            double Ds = col == 0, Dn = col == 1, Dq = col == 2;
+            double o[4];
+            ora_poro_elem_transient(P, cx[i], cy[i], cx[j], cy[j], cb[j], sb[j],
+                                    a[j], Ds, Dn, Dq, t1, t0, nq, np_min, o);
+            if (m == 0 && col < 2) {
+                double sg[3];
+                ora_elem_stress(cx[i], cy[i], cx[j], cy[j], cb[j], sb[j], a[j],
+                                P[0], P[1], Ds, Dn, sg);
+                o[0] += sg[0]; o[1] += sg[1]; o[2] += sg[2];
+            }
+            double ts, tn;
+            ora_traction(cb[i], sb[i], o, &ts, &tn);
+            R[(3 * k + 0) * 3 * n + 3 * j + col] = ts;
+            R[(3 * k + 1) * 3 * n + 3 * j + col] = tn;
+            R[(3 * k + 2) * 3 * n + 3 * j + col] = o[3];
+        }
+    }
+}
+
 /* Threads the OpenMP loops above use (reporting only). */
 #ifdef _OPENMP
 #include <omp.h>

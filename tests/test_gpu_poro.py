@@ -233,3 +233,41 @@ def test_poro_block_jacobi(mode):
         b = res[F.FMDDM_PRECOND_NONE][0][h * n3:(h + 1) * n3]
         assert cmp(a, b) <= 1e-7, (h, cmp(a, b))
         assert 2 * res[F.FMDDM_PRECOND_BLOCK][1][h] <= res[F.FMDDM_PRECOND_NONE][1][h], res
+
+
+def test_poro_full_size_sampled_rows():
+    """N = 20000 (five fractures of 4000 0.2 m elements, 10 m apart), the
+    multipole configuration the bench times (p = 10, leaf 32): the
+    left-hand-side product and a 4-level history sum against the oracle's
+    exact rows for 20 sampled receivers; bar 1e-6 of the largest entry of
+    each response kind, as for the smaller multipole test."""
+    wl = W.well_cluster(n_frac=5, elems=4000, half_length=400.0, spacing=10.0)
+    g = O.Geometry.of(wl)
+    po = O.Poro(**MED)
+    rows = np.random.default_rng(2).choice(g.n, 20, replace=False)
+    idx = np.stack([3 * rows, 3 * rows + 1, 3 * rows + 2], 1).reshape(-1)
+    rng = np.random.default_rng(5)
+    scale = np.tile([1e-4, 1e-4, 1e-10], g.n)
+    D = rng.standard_normal(3 * g.n) * scale
+    h = 4
+    Dh = [rng.standard_normal(3 * g.n) * scale for _ in range(h - 1)]
+    b = rng.standard_normal(3 * g.n) * 1e6
+    prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=MED["E"], nu=MED["nu"], p=10, leaf=32)
+    try:
+        F.fmddm_poro_set(prob.ctx, MED["nuu"], MED["alpha"], MED["perm"], MED["visc"], DT, P0,
+                         mode=F.FMDDM_APPLY_FMM)
+        out = torch.zeros(3 * g.n, dtype=torch.float64, device="cuda")
+        F.fmddm_poro_apply(prob.ctx, prob.tree, 0, dev(D), out)
+        rhs = dev(b)
+        F.fmddm_add_history(prob.ctx, prob.tree, h, dev(np.concatenate(Dh)), rhs)
+        y0 = out.cpu().numpy()[idx]
+        yh = rhs.cpu().numpy()[idx]
+    finally:
+        prob.close()
+    ref0 = O.poro_matrix_rows(g, po, DT, 0, rows) @ D
+    refh = b[idx].copy()
+    for k in range(1, h):
+        refh -= O.poro_matrix_rows(g, po, DT, h - k, rows) @ Dh[k - 1]
+    e0, eh = cmp(y0, ref0), cmp(yh - b[idx], refh - b[idx])
+    print(f"N=20000 poro FMM vs oracle rows: lhs {e0:.2e}, history {eh:.2e}")
+    assert e0 <= 1e-6 and eh <= 1e-6, (e0, eh)

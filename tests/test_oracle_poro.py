@@ -189,3 +189,16 @@ def test_well_cluster_symmetry(po):
     assert np.allclose(top[:, 0], -bot[:, 0], rtol=1e-9, atol=1e-12 * np.abs(D[:, 1]).max())
     # fluid leaks off into the formation while the fracture pressure exceeds p0
     assert (D[:, 2] > 0).all()
+
+
+def test_matrix_rows_are_rows_of_the_matrix(po):
+    """The sampled-row evaluation (used for full-size GPU parity) is the
+    same matrix restricted to the chosen receivers."""
+    wl = W.well_cluster(n_frac=2, elems=7, half_length=1.0, spacing=0.5)
+    g = O.Geometry.of(wl)
+    rows = np.array([0, 5, 13])
+    for m in (0, 2):
+        A = O.poro_matrix(g, po, 60.0, m)
+        R = O.poro_matrix_rows(g, po, 60.0, m, rows)
+        idx = np.stack([3 * rows, 3 * rows + 1, 3 * rows + 2], 1).reshape(-1)
+        assert np.array_equal(R, A[idx])
