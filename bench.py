@@ -273,9 +273,12 @@ def precision_leg(F, W, steps, tune, leaf, p, solve_tol=1e-8, target_err=1e-6):
         st, best, log = F.fmddm_autotune(base, wl.x1, wl.y1, wl.x2, wl.y2, leaves=(16, 32, 64, 128),
                                          ps=tuple(range(8, 25, 2)), target_err=target_err, reps=5)
         out["autotune"] = {"seconds": time.perf_counter() - t0, "target_err": target_err, "status": st,
-                           "leaf": best.leaf, "p": best.p, "tried": log}
-        leaf, p = best.leaf, best.p
-    out["leaf"], out["p"] = leaf, p
+                           "leaf": best.leaf, "p": best.p, "m2l_tiles": best.m2l_tiles, "tried": log}
+        leaf, p, tiles = best.leaf, best.p, best.m2l_tiles
+    else:
+        tiles = 0
+    out["leaf"], out["p"], out["m2l_tiles"] = leaf, p, tiles
+    common["m2l_tiles"] = tiles
     D = None
     res = {}
     y = {}

@@ -115,6 +115,11 @@ typedef struct {
                                  (default: replays measured no faster, and
                                  capture costs ~1 ms per step index and tree) */
     int precond;              /* fmddm_precond of elastic GMRES solves */
+    int m2l_tiles;            /* tile set of the M2L products, 0..3: (split-K of
+                                 the projection, row tile of the pair products,
+                                 row tile of the expansion) = (4, 64, 64),
+                                 (2, 32, 64), (8, 64, 32), (4, 32, 32);
+                                 fmddm_autotune picks one */
 } fmddm_params;
 
 typedef struct {
@@ -143,7 +148,8 @@ typedef struct {
 
 /* Fill *p with defaults: E=20e9, nu=0.25, leaf=32, p=20, max_level=24,
  * kappa=8, m2l=DENSE, m2l_tol=1e-12, no root box, restart=50,
- * maxit=10000, tol=1e-10, precision=FP64, use_graphs=0, precond=NONE. */
+ * maxit=10000, tol=1e-10, precision=FP64, use_graphs=0, precond=NONE,
+ * m2l_tiles=0. */
 void fmddm_default_params(fmddm_params *p);
 
 /* Create a context on the current HIP device bound to `hip_stream`
@@ -237,6 +243,7 @@ typedef struct {
     double ms;                /* mean time of one FMM product (ms); -1 when not
                                  timed (error target missed) */
     double err;               /* ||y - y_exact|| / ||y_exact|| for uniform opening */
+    int32_t m2l_tiles;        /* tile set the product was timed with */
 } fmddm_tune_entry;
 
 /* Choose the leaf size and the Chebyshev order for one geometry (host
@@ -246,7 +253,8 @@ typedef struct {
  * order until the FMM product's relative error (2-norm) against the exact
  * product is at most target_err; that configuration's product is
  * timed (reps products on the device) and the fastest over the leaf sizes
- * is kept.  The test vector is a uniform opening (Dn = 1e-3, Ds = 0 on every
+ * is kept; then every M2L tile set (m2l_tiles) is timed on it and the
+ * fastest kept (log entries for those carry err of the chosen leaf and p).  The test vector is a uniform opening (Dn = 1e-3, Ds = 0 on every
  * element): smooth, like the DDs of loaded fractures, it weighs the far
  * field as solutions do, where a random vector is dominated by the near
  * field (which the FMM evaluates exactly).  Every other field of *base

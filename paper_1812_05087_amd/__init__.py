@@ -56,7 +56,7 @@ class Params(C.Structure):
         ("kappa", C.c_double), ("m2l", C.c_int), ("m2l_tol", C.c_double),
         ("use_root_box", C.c_int), ("root_x0", C.c_double), ("root_y0", C.c_double),
         ("root_L", C.c_double), ("restart", C.c_int), ("maxit", C.c_int), ("tol", C.c_double),
-        ("precision", C.c_int), ("use_graphs", C.c_int), ("precond", C.c_int),
+        ("precision", C.c_int), ("use_graphs", C.c_int), ("precond", C.c_int), ("m2l_tiles", C.c_int),
     ]
 
 
@@ -90,7 +90,8 @@ class PoroParams(C.Structure):
 
 
 class TuneEntry(C.Structure):
-    _fields_ = [("leaf", C.c_int32), ("p", C.c_int32), ("ms", C.c_double), ("err", C.c_double)]
+    _fields_ = [("leaf", C.c_int32), ("p", C.c_int32), ("ms", C.c_double), ("err", C.c_double),
+                ("m2l_tiles", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -283,7 +284,7 @@ def fmddm_autotune(params: Params, x1, y1, x2, y2, leaves=(16, 32, 64, 128), ps=
     x1, y1, x2, y2 = (np.ascontiguousarray(v, dtype=np.float64) for v in (x1, y1, x2, y2))
     lv = (C.c_int32 * len(leaves))(*leaves)
     pv = (C.c_int32 * len(ps))(*ps)
-    cap = len(leaves) * len(ps)
+    cap = len(leaves) * len(ps) + 4
     log = (TuneEntry * cap)()
     nlog = C.c_int32()
     best = Params()

@@ -39,9 +39,12 @@ __global__ __launch_bounds__(DT) void k_direct(int n, const double *__restrict__
         int cnt = min(DTILE, n - base);
         if (act)
             for (int k = sub; k < cnt; k += DTPT)
-                elem_stress_add(X, Y, s_cx[k], s_cy[k], s_cb[k], s_sb[k], s_a[k], s_ds[k], s_dn[k], gc,
-                                sxx, syy, sxy);
+                elem_stress_unit(X, Y, s_cx[k], s_cy[k], s_cb[k], s_sb[k], s_a[k], s_ds[k], s_dn[k], sxx, syy,
+                                 sxy);
     }
+    sxx *= -gc;
+    syy *= -gc;
+    sxy *= -gc;
 #pragma unroll
     for (int w = 1; w < DTPT; w <<= 1) {
         sxx += __shfl_xor(sxx, w);

@@ -62,6 +62,36 @@ __device__ __forceinline__ void elem_stress_add(double X, double Y, double cx, d
     sxy += cs * (lxx - lyy) + (c2 - s2) * lxy;
 }
 
+// elem_stress_add without the factor -gc (the caller scales the sum once),
+// and with one reciprocal for both end-point distances: r = 1/(d1 d2) to
+// full precision (two Newton steps), 1/d1 = d2 r, 1/d2 = d1 r (within two
+// ulp).  For the inner loops of the near field and the exact product.
+__device__ __forceinline__ void elem_stress_unit(double X, double Y, double cx, double cy, double cb, double sb,
+                                                 double a, double Ds, double Dn, double &sxx, double &syy,
+                                                 double &sxy)
+{
+    double dx = X - cx, dy = Y - cy;
+    double x = dx * cb + dy * sb;
+    double y = dy * cb - dx * sb;
+    double xm = x - a, xp = x + a, y2 = y * y;
+    double d1 = xm * xm + y2, d2 = xp * xp + y2;
+    double r = recip(d1 * d2);
+    double i1 = d2 * r, i2 = d1 * r;
+    double fxy = y * (i1 - i2);
+    double fyy = xp * i2 - xm * i1;
+    double j1 = i1 * i1, j2 = i2 * i2;
+    double fxyy = (xm * xm - y2) * j1 - (xp * xp - y2) * j2;
+    double fyyy = 2.0 * y * (xm * j1 - xp * j2);
+    double yfxyy = y * fxyy, yfyyy = y * fyyy;
+    double lxx = Ds * (2.0 * fxy + yfxyy) + Dn * (fyy + yfyyy);
+    double lyy = Dn * (fyy - yfyyy) - Ds * yfxyy;
+    double lxy = Ds * (fyy + yfyyy) - Dn * yfxyy;
+    double c2 = cb * cb, s2 = sb * sb, cs = cb * sb;
+    sxx += c2 * lxx - 2.0 * cs * lxy + s2 * lyy;
+    syy += s2 * lxx + 2.0 * cs * lxy + c2 * lyy;
+    sxy += cs * (lxx - lyy) + (c2 - s2) * lxy;
+}
+
 // The same element stress in FP32 arithmetic, for the reduced-precision
 // product.  The receiver-element offset (dx, dy) comes in already formed in
 // FP64 (coordinates of a 100 m domain would lose the element scale if

@@ -865,8 +865,11 @@ __global__ __launch_bounds__(NT) void k_p2p(
         if (act) {
             if constexpr (sizeof(RT) == 8) {
                 for (int q = sub; q < cnt; q += tpt)
-                    elem_stress_add(X, Y, s_cx[q], s_cy[q], s_cb[q], s_sb[q], s_a[q], s_ds[q], s_dn[q], gc, sxx,
-                                    syy, sxy);
+                    elem_stress_unit(X, Y, s_cx[q], s_cy[q], s_cb[q], s_sb[q], s_a[q], s_ds[q], s_dn[q], sxx, syy,
+                                     sxy);
+                sxx *= -gc;
+                syy *= -gc;
+                sxy *= -gc;
             } else {
                 float g = (float)gc;
                 for (int q = sub; q < cnt; q += tpt)
@@ -929,7 +932,14 @@ __global__ void k_final(int n, const int *__restrict__ tleaf, const int *__restr
 
 
 constexpr int TILE_N = 32;  // pairs per GEMM tile (the BN of the launches)
-constexpr int KSPLIT = 4;   // split-K factor of the projection onto the singular vectors
+// M2L GEMM tile sets (fmddm_params.m2l_tiles): split-K factor of the
+// projection onto the singular vectors, row-tile height of the pair
+// products and of the expansion back onto the nodes
+struct TileSet {
+    int ksplit, bm_pair, bm_back;
+};
+constexpr TileSet TILESETS[4] = {{4, 64, 64}, {2, 32, 64}, {8, 64, 32}, {4, 32, 32}};
+constexpr int KSPLIT_MAX = 8;
 
 void upload(hipStream_t s, DBuf<int> &d, const std::vector<int> &h)
 {
@@ -980,12 +990,27 @@ void launch_lgemm(hipStream_t s, int ntile, int Mrows, const TA *ops, size_t op_
     FM_CHECK_LAUNCH();
 }
 
+// launch_ggemm / launch_lgemm with the row-tile height chosen at run time
+template <class... A>
+void ggemm_bm(int bm, hipStream_t s, A... a)
+{
+    if (bm == 32) launch_ggemm<32, 32>(s, a...);
+    else launch_ggemm<64, 32>(s, a...);
+}
+
+template <typename CT, class... A>
+void lgemm_bm(int bm, hipStream_t s, A... a)
+{
+    if (bm == 32) launch_lgemm<32, 32, CT>(s, a...);
+    else launch_lgemm<64, 32, CT>(s, a...);
+}
+
 // The M2L products (projection, translation, expansion) at reduced
 // precision: CT the MFMA operand type, TO the stored operators' type.
 // Weights in: Wexp (FP64); fields out: Gexp (FP64); FP32 in between.
 template <typename CT, typename TO>
 void m2l_lowp(hipStream_t s, fmddm_tree *t, const M2LOps &M, const TO *Vt, const TO *ops, const TO *Ur,
-              Profiler &P)
+              Profiler &P, const TileSet &ts)
 {
     int Mp = M.Mp, rp = M.rp;
     hipEvent_t e0;
@@ -993,18 +1018,18 @@ void m2l_lowp(hipStream_t s, fmddm_tree *t, const M2LOps &M, const TO *Vt, const
         P.begin(FMDDM_PH_COMPRESS, s, e0);
         launch_lgemm<32, 32, CT>(s, t->nftile, rp, Vt, 0, Mp, Mp, t->Wexp.p, Mp, t->ftile_op.p, t->ftile_beg.p,
                                  t->ftile_end.p, t->far_cells.p, t->far_cells.p, nullptr, t->ksplit32.p, rp,
-                                 KSPLIT, (size_t)t->ncell * rp);
+                                 ts.ksplit, (size_t)t->ncell * rp);
         P.end(FMDDM_PH_COMPRESS, s, e0);
         P.begin(FMDDM_PH_COMPRESS_SUM, s, e0);
         {
             int64_t c0 = t->level_start[2], cnt = (int64_t)(t->ncell - c0) * rp;
-            hipLaunchKernelGGL(k_reduce_split<float>, dim3(cdiv(cnt, 256)), dim3(256), 0, s, cnt, KSPLIT,
+            hipLaunchKernelGGL(k_reduce_split<float>, dim3(cdiv(cnt, 256)), dim3(256), 0, s, cnt, ts.ksplit,
                                (size_t)t->ncell * rp, t->ksplit32.p + c0 * rp, t->What32.p + c0 * rp);
             FM_CHECK_LAUNCH();
         }
         P.end(FMDDM_PH_COMPRESS_SUM, s, e0);
         P.begin(FMDDM_PH_M2L, s, e0);
-        launch_lgemm<64, 32, CT>(s, t->ntile, rp, ops, (size_t)rp * rp, rp, rp, t->What32.p, rp, t->tile_op.p,
+        lgemm_bm<CT>(ts.bm_pair, s, t->ntile, rp, ops, (size_t)rp * rp, rp, rp, t->What32.p, rp, t->tile_op.p,
                                  t->tile_beg.p, t->tile_end.p, t->pair_src.p, t->pair_dst.p, t->pair_scale.p,
                                  t->Zm2l32.p, rp);
         P.end(FMDDM_PH_M2L, s, e0);
@@ -1014,13 +1039,13 @@ void m2l_lowp(hipStream_t s, fmddm_tree *t, const M2LOps &M, const TO *Vt, const
         FM_CHECK_LAUNCH();
         P.end(FMDDM_PH_M2L_SUM, s, e0);
         P.begin(FMDDM_PH_DECOMPRESS, s, e0);
-        launch_lgemm<64, 32, CT>(s, t->nftile, Mp, Ur, 0, rp, rp, t->Ghat32.p, rp, t->ftile_op.p,
+        lgemm_bm<CT>(ts.bm_back, s, t->nftile, Mp, Ur, 0, rp, rp, t->Ghat32.p, rp, t->ftile_op.p,
                                  t->ftile_beg.p, t->ftile_end.p, t->far_cells.p, t->far_cells.p, nullptr,
                                  t->Gexp.p, Mp);
         P.end(FMDDM_PH_DECOMPRESS, s, e0);
     } else {
         P.begin(FMDDM_PH_M2L, s, e0);
-        launch_lgemm<64, 32, CT>(s, t->ntile, Mp, ops, (size_t)Mp * Mp, Mp, Mp, t->Wexp.p, Mp, t->tile_op.p,
+        lgemm_bm<CT>(ts.bm_pair, s, t->ntile, Mp, ops, (size_t)Mp * Mp, Mp, Mp, t->Wexp.p, Mp, t->tile_op.p,
                                  t->tile_beg.p, t->tile_end.p, t->pair_src.p, t->pair_dst.p, t->pair_scale.p,
                                  t->Zm2l32.p, Mp);
         P.end(FMDDM_PH_M2L, s, e0);
@@ -1073,7 +1098,7 @@ void setup_lowp(fmddm_ctx *ctx, fmddm_tree *t, int prec)
         if (svd) {
             t->What32.alloc((size_t)t->ncell * M.rp);
             t->Ghat32.alloc((size_t)t->ncell * M.rp);
-            t->ksplit32.alloc((size_t)KSPLIT * t->ncell * M.rp);
+            t->ksplit32.alloc((size_t)KSPLIT_MAX * t->ncell * M.rp);
             t->What32.zero(s);
             t->Ghat32.zero(s);
         }
@@ -1565,7 +1590,7 @@ void setup_fmm(fmddm_ctx *ctx, fmddm_tree *t)
     }
     t->far_s.alloc(3 * (size_t)std::max(t->nfarlev, 1) * t->n);
     t->part_s.alloc(3 * (size_t)t->npartial);
-    if (M.mode == FMDDM_M2L_SVD) t->ksplit.alloc((size_t)KSPLIT * ncell * rp);
+    if (M.mode == FMDDM_M2L_SVD) t->ksplit.alloc((size_t)KSPLIT_MAX * ncell * rp);
     FM_HIP(hipStreamSynchronize(s));
 }
 
@@ -1578,6 +1603,7 @@ void fmm_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out, int 
     int p = ctx->prm.p, Mp = M.Mp, rp = M.rp, n = (int)t->n;
     const Cheb &C = *ctx->cheb;
     Profiler &P = ctx->prof;
+    const TileSet &ts = TILESETS[ctx->prm.m2l_tiles];
     hipEvent_t e0;
     P.begin(FMDDM_PH_PREP, s, e0);
     hipLaunchKernelGGL(k_prep, dim3(cdiv(n, 256)), dim3(256), 0, s, n, t->perm.p, D, t->scb.p, t->ssb.p,
@@ -1624,27 +1650,27 @@ void fmm_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out, int 
             P.end(FMDDM_PH_M2M_SUM, s, e0);
         }
         if (prec == FMDDM_PREC_FP32) {
-            m2l_lowp<float>(s, t, M, M.Vt32.p, M.ops32.p, M.Ur32.p, P);
+            m2l_lowp<float>(s, t, M, M.Vt32.p, M.ops32.p, M.Ur32.p, P, ts);
         } else if (prec == FMDDM_PREC_BF16) {
-            m2l_lowp<uint16_t>(s, t, M, M.Vt16.p, M.ops16.p, M.Ur16.p, P);
+            m2l_lowp<uint16_t>(s, t, M, M.Vt16.p, M.ops16.p, M.Ur16.p, P, ts);
         } else if (M.mode == FMDDM_M2L_SVD) {
             // projection onto the singular vectors: K = 3p^2 is long and the
-            // output small, so K is split over KSPLIT blocks and summed after
+            // output small, so K is split over ts.ksplit blocks and summed after
             P.begin(FMDDM_PH_COMPRESS, s, e0);
             launch_ggemm<32, 32>(s, t->nftile, rp, M.Vt.p, 0, Mp, Mp, t->Wexp.p, Mp, t->ftile_op.p,
                                  t->ftile_beg.p, t->ftile_end.p, t->far_cells.p, t->far_cells.p, nullptr,
-                                 t->ksplit.p, rp, KSPLIT, (size_t)t->ncell * rp);
+                                 t->ksplit.p, rp, ts.ksplit, (size_t)t->ncell * rp);
             P.end(FMDDM_PH_COMPRESS, s, e0);
             P.begin(FMDDM_PH_COMPRESS_SUM, s, e0);
             {
                 int64_t c0 = t->level_start[2], cnt = (int64_t)(t->ncell - c0) * rp;
-                hipLaunchKernelGGL(k_reduce_split<double>, dim3(cdiv(cnt, 256)), dim3(256), 0, s, cnt, KSPLIT,
+                hipLaunchKernelGGL(k_reduce_split<double>, dim3(cdiv(cnt, 256)), dim3(256), 0, s, cnt, ts.ksplit,
                                    (size_t)t->ncell * rp, t->ksplit.p + c0 * rp, t->What.p + c0 * rp);
                 FM_CHECK_LAUNCH();
             }
             P.end(FMDDM_PH_COMPRESS_SUM, s, e0);
             P.begin(FMDDM_PH_M2L, s, e0);
-            launch_ggemm<64, 32>(s, t->ntile, rp, M.ops.p, (size_t)rp * rp, rp, rp, t->What.p, rp, t->tile_op.p,
+            ggemm_bm(ts.bm_pair, s, t->ntile, rp, M.ops.p, (size_t)rp * rp, rp, rp, t->What.p, rp, t->tile_op.p,
                                  t->tile_beg.p, t->tile_end.p, t->pair_src.p, t->pair_dst.p, t->pair_scale.p,
                                  t->Zm2l.p, rp);
             P.end(FMDDM_PH_M2L, s, e0);
@@ -1654,13 +1680,13 @@ void fmm_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out, int 
             FM_CHECK_LAUNCH();
             P.end(FMDDM_PH_M2L_SUM, s, e0);
             P.begin(FMDDM_PH_DECOMPRESS, s, e0);
-            launch_ggemm<64, 32>(s, t->nftile, Mp, M.Ur.p, 0, rp, rp, t->Ghat.p, rp, t->ftile_op.p,
+            ggemm_bm(ts.bm_back, s, t->nftile, Mp, M.Ur.p, 0, rp, rp, t->Ghat.p, rp, t->ftile_op.p,
                                  t->ftile_beg.p, t->ftile_end.p, t->far_cells.p, t->far_cells.p, nullptr,
                                  t->Gexp.p, Mp);
             P.end(FMDDM_PH_DECOMPRESS, s, e0);
         } else {
             P.begin(FMDDM_PH_M2L, s, e0);
-            launch_ggemm<64, 32>(s, t->ntile, Mp, M.ops.p, (size_t)Mp * Mp, Mp, Mp, t->Wexp.p, Mp, t->tile_op.p,
+            ggemm_bm(ts.bm_pair, s, t->ntile, Mp, M.ops.p, (size_t)Mp * Mp, Mp, Mp, t->Wexp.p, Mp, t->tile_op.p,
                                  t->tile_beg.p, t->tile_end.p, t->pair_src.p, t->pair_dst.p, t->pair_scale.p,
                                  t->Zm2l.p, Mp);
             P.end(FMDDM_PH_M2L, s, e0);

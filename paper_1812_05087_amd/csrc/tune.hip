@@ -152,9 +152,42 @@ extern "C" fmddm_status fmddm_autotune(const fmddm_params *base, int64_t n, cons
                     best_err = err;
                     accp = q;
                 }
-                if (count < log_cap) log[count] = fmddm_tune_entry{q.leaf, q.p, ms, err};
+                if (count < log_cap) log[count] = fmddm_tune_entry{q.leaf, q.p, ms, err, q.m2l_tiles};
                 ++count;
                 if (ok) break;  // a larger p only costs more
+            }
+        }
+        if (met) {
+            // M2L tile sets on the chosen configuration (the error does not
+            // depend on them beyond rounding)
+            double best_err_m = 0.0;
+            for (int i = 0; i < count && i < log_cap; ++i)
+                if (log[i].leaf == bestp.leaf && log[i].p == bestp.p && log[i].ms >= 0) best_err_m = log[i].err;
+            Ctx c;
+            fmddm_params q = bestp;
+            check(fmddm_create(&q, st.s, &c.c), nullptr, "autotune: parameters");
+            c.c->cheb = opsets[q.p]->c->cheb;
+            c.c->m2l = opsets[q.p]->c->m2l;
+            Tree t;
+            check(fmddm_build_tree(c.c, n, x1, y1, x2, y2, 0, &t.t), c.c, "autotune: tree");
+            double best_t = INFINITY;
+            for (int ts = 0; ts < 4; ++ts) {
+                c.c->prm.m2l_tiles = ts;
+                check(fmddm_apply(c.c, t.t, FMDDM_APPLY_FMM, dD.p, dy.p), c.c, "autotune: product");
+                FM_HIP(hipEventRecord(e0, st.s));
+                for (int k = 0; k < reps; ++k)
+                    check(fmddm_apply(c.c, t.t, FMDDM_APPLY_FMM, dD.p, dy.p), c.c, "autotune: product");
+                FM_HIP(hipEventRecord(e1, st.s));
+                FM_HIP(hipEventSynchronize(e1));
+                float t_ms = 0.f;
+                FM_HIP(hipEventElapsedTime(&t_ms, e0, e1));
+                double ms = t_ms / reps;
+                if (count < log_cap) log[count] = fmddm_tune_entry{q.leaf, q.p, ms, best_err_m, ts};
+                ++count;
+                if (ms < best_t) {
+                    best_t = ms;
+                    bestp.m2l_tiles = ts;
+                }
             }
         }
         if (nlog) *nlog = count;

@@ -177,8 +177,13 @@ def test_autotune_picks_fastest_accurate_configuration():
     base = F.fmddm_default_params(E=wl.E, nu=wl.nu, m2l=F.FMDDM_M2L_SVD, m2l_tol=1e-10)
     st, best, log = F.fmddm_autotune(base, wl.x1, wl.y1, wl.x2, wl.y2, leaves=(16, 32, 64), ps=(10, 4, 6, 8),
                                      target_err=1e-6, reps=3)
-    print("autotune", st, best.leaf, best.p, log)
+    print("autotune", st, best.leaf, best.p, best.m2l_tiles, log)
     assert st == F.FMDDM_OK
+    # the last four entries time the M2L tile sets on the chosen configuration
+    tiles, log = log[-4:], log[:-4]
+    assert [e["m2l_tiles"] for e in tiles] == [0, 1, 2, 3]
+    assert all((e["leaf"], e["p"]) == (best.leaf, best.p) and e["ms"] > 0 for e in tiles)
+    assert best.m2l_tiles == min(tiles, key=lambda e: e["ms"])["m2l_tiles"]
     timed = [e for e in log if e["ms"] > 0]
     assert timed and all(e["err"] <= 1e-6 for e in timed)
     assert all(e["err"] > 1e-6 for e in log if e["ms"] < 0)
@@ -194,7 +199,7 @@ def test_autotune_picks_fastest_accurate_configuration():
     # an unreachable target: ENOTCONV with the most accurate configuration
     st2, best2, log2 = F.fmddm_autotune(base, wl.x1, wl.y1, wl.x2, wl.y2, leaves=(32,), ps=(4, 6),
                                         target_err=1e-30, reps=1)
-    assert st2 == F.FMDDM_ENOTCONV and len(log2) == 2
+    assert st2 == F.FMDDM_ENOTCONV and len(log2) == 2   # no tile stage without a configuration
     assert best2.p == min(log2, key=lambda e: e["err"])["p"]
 
 
@@ -224,3 +229,17 @@ def test_full_size_sampled_rows(leaf, p):
         e = rel(ys[name], exact)
         print(f"  {name} vs oracle {e:.2e}, vs FP64 FMM {rel(ys[name], ys['fp64']):.2e}")
         assert e <= NEAR_BAR + (FAR_BAR[name] if name == "bf16" else 0.0) + e64, (name, e)
+
+
+@pytest.mark.parametrize("m2l", [F.FMDDM_M2L_SVD, F.FMDDM_M2L_DENSE])
+def test_m2l_tile_sets_agree(m2l):
+    """The M2L tile sets change split-K depth and tile heights, i.e. only the
+    order of the sums: every set gives the product of set 0 to rounding (set 0
+    is the one the oracle parity tests cover), in FP64 and FP32."""
+    wl = W.random_fractures(24, n_frac=40, elems=50)
+    D = W.random_vector(4, wl.n)
+    for prec, bar in [(F.FMDDM_PREC_FP64, 1e-13), (F.FMDDM_PREC_FP32, 1e-6)]:
+        ys = [product(wl, prec, D, p=12, leaf=32, m2l=m2l, m2l_tol=1e-10, m2l_tiles=ts)[0] for ts in range(4)]
+        for ts in range(1, 4):
+            e = rel(ys[ts], ys[0])
+            assert e <= bar, (prec, ts, e)
