@@ -373,7 +373,7 @@ __global__ __launch_bounds__(256) void k_ggemm(const double *__restrict__ ops, s
     __shared__ double As[BM][GK + 1];
     __shared__ double Bs[GK][BN + 1];
     __shared__ int src[BN];
-    int tile = blockIdx.x, mt = blockIdx.y;
+    int tile = xcd_remap(blockIdx.x, gridDim.x), mt = blockIdx.y;  // an XCD takes a run of tiles (few operators)
     int o = tile_op[tile], pb = tile_beg[tile], np = tile_end[tile] - pb;
     int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     int wm = wave >> 1, wn = wave & 1;
@@ -545,7 +545,7 @@ __global__ __launch_bounds__(256) void k_lgemm(const TA *__restrict__ ops, size_
     __shared__ __align__(16) CT As[BM][KP];
     __shared__ __align__(16) CT Bs[BN][KP];
     __shared__ int src[BN];
-    int tile = blockIdx.x, mt = blockIdx.y;
+    int tile = xcd_remap(blockIdx.x, gridDim.x), mt = blockIdx.y;  // an XCD takes a run of tiles (few operators)
     int o = tile_op[tile], pb = tile_beg[tile], np = tile_end[tile] - pb;
     int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     int wm = wave >> 1, wn = wave & 1;
