@@ -47,6 +47,10 @@ namespace {
 
 struct PoroK {
     double G, nu, alpha, kappa, S, c, eta, gc;
+    // derived (host): vfac = (1-2nu)/(2(1-nu)), ap = alpha kd / S with
+    // kd = (1-2nu)/(4 pi G (1-nu)), pv = alpha / (4 pi S), cphi = alpha kd eta / S,
+    // kdf = -alpha eta / (2 pi S), i4pk = 1 / (4 pi kappa), fe = eta / (2 pi S)
+    double vfac, ap, pv, cphi, kdf, i4pk, fe;
 };
 
 // E1(z), z > 0.  Below 2: -gamma - ln z + Ein(z), with the series
@@ -55,18 +59,26 @@ struct PoroK {
 // e^-z / (z + 1 - 1/(z + 3 - 4/(z + 5 - ...))) evaluated backwards from
 // depth 2 + 90/z (its truncation error falls like exp(-4 sqrt(depth z)),
 // below 1e-16 there); zero where e^-z underflows.
+// Series coefficients, computed on the host and uploaded with the
+// quadrature rules so that the series below are division-free:
+// c_e1w[k] = k / (k+1)^2, c_hc[k] = (-1)^(k+1) / (k+1)!, c_p2c[k] =
+// (-1)^k (k-1) / k!.
+__constant__ double c_e1w[31], c_hc[23], c_p2c[18];
+
 __device__ double e1(double z)
 {
     if (z <= 2.0) {
         double v = 1.0;
-        for (int k = 30; k >= 1; --k) v = 1.0 - z * k / ((k + 1.0) * (k + 1.0)) * v;
+        for (int k = 30; k >= 1; --k) v = 1.0 - z * c_e1w[k] * v;
         return -0.57721566490153286061 - log(z) + z * v;
     }
     if (z > 745.0) return 0.0;
+    // the reciprocal refined to full precision (within two ulp of the
+    // division) in the fraction's steps
     int depth = min(64, 2 + (int)(90.0 / z));
     double f = 0.0;
-    for (int k = depth; k >= 1; --k) f = (double)k * k / (z + 2.0 * k + 1.0 - f);
-    return exp(-z) / (z + 1.0 - f);
+    for (int k = depth; k >= 1; --k) f = (double)k * k * recip(z + 2.0 * k + 1.0 - f);
+    return exp(-z) * recip(z + 1.0 - f);
 }
 
 // h(z) = 1 - (1 - e^-z)/z with h', h'' (series below 0.5).
@@ -76,11 +88,8 @@ __device__ void hfun(double z, double &h, double &h1, double &h2)
         // h = sum_{k>=1} c_k z^k, c_k = (-1)^(k+1) / (k+1)!, by Horner
         // from k = 22 down (the first omitted term is below 1e-26)
         double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-        double f = 1.0;
-        for (int j = 2; j <= 23; ++j) f *= j;  // 23!
         for (int k = 22; k >= 1; --k) {
-            double ck = ((k & 1) ? 1.0 : -1.0) / f;
-            f /= (k + 1);
+            double ck = c_hc[k];
             a0 = a0 * z + ck;
             a1 = a1 * z + ck * k;
             if (k >= 2) a2 = a2 * z + ck * k * (k - 1);
@@ -91,7 +100,7 @@ __device__ void hfun(double z, double &h, double &h1, double &h2)
         return;
     }
     double em = exp(-z), om = -expm1(-z);
-    double iz = 1.0 / z;
+    double iz = recip(z);
     h = 1.0 - om * iz;
     h1 = om * iz * iz - em * iz;
     h2 = -2.0 * om * iz * iz * iz + 2.0 * em * iz * iz + em * iz;
@@ -100,16 +109,10 @@ __device__ void hfun(double z, double &h, double &h1, double &h2)
 __device__ double p2fun(double z)
 {
     if (z < 0.1) {
-        // sum_{k>=2} (-1)^k (k-1) z^k / k!
-        double s = 0.0, f = 2.0, zk = z * z;
-        for (int k = 2; k < 18; ++k) {
-            if (k > 2) {
-                f *= k;
-                zk *= z;
-            }
-            s += ((k & 1) ? -1.0 : 1.0) * (k - 1) * zk / f;
-        }
-        return s;
+        // sum_{k=2}^{17} (-1)^k (k-1) z^k / k!, by Horner
+        double s = 0.0;
+        for (int k = 17; k >= 2; --k) s = s * z + c_p2c[k];
+        return s * z * z;
     }
     return 1.0 - exp(-z) * (1.0 + z);
 }
@@ -127,25 +130,24 @@ __device__ __forceinline__ void rad2(double x, double y, double ir2, double f1, 
 __device__ void transient(const PoroK &K, double x, double y, double t, const double q[3], double qf,
                           double o[4])
 {
-    double r2 = x * x + y * y, ir2 = 1.0 / r2, r = sqrt(r2);
-    double z = r2 / (4.0 * K.c * t);
+    double r2 = x * x + y * y, ir2 = recip(r2), r = sqrt(r2), ir = recip(r);
+    double ict = recip(K.c * t);  // 1 / (c t)
+    double z = 0.25 * r2 * ict;
     double ez = exp(-z), om = -expm1(-z);
-    double kd = (1.0 - 2.0 * K.nu) / (4.0 * M_PI * K.G * (1.0 - K.nu));
     double a = 2.0 * K.G * (q[0] - q[1]), b = 2.0 * K.G * q[2];
-    double V = -(q[0] + q[1]) * (1.0 - 2.0 * K.nu) / (2.0 * (1.0 - K.nu));
+    double V = -(q[0] + q[1]) * K.vfac;
     double gxy = x * x - y * y, g2 = 2.0 * x * y;
-    double p = (K.alpha * kd / K.S) * (a * gxy + b * g2) * ir2 * ir2 * p2fun(z)
-               - (K.alpha / K.S) * V * ez / (4.0 * M_PI * K.c * t);
+    double p = K.ap * (a * gxy + b * g2) * ir2 * ir2 * p2fun(z) - K.pv * V * ez * ict;
     double h, h1, h2;
     hfun(z, h, h1, h2);
     double F = -0.25 * h * ir2;
-    double F1 = (h - z * h1) * 0.5 * ir2 / r;                 // F'(r)
+    double F1 = (h - z * h1) * 0.5 * ir2 * ir;                // F'(r)
     double F2 = (-2.0 * z * z * h2 - 3.0 * h + 3.0 * z * h1) * 0.5 * ir2 * ir2;  // F''(r)
     // second derivatives of F(r): F_xx etc. (F1/r plays phi'/r)
     double fxx = 0.0, fyy = 0.0, fxy = 0.0;
-    rad2(x, y, ir2, F1 / r, F2, fxx, fyy, fxy);
-    double Fx = F1 * x / r, Fy = F1 * y / r;
-    double Cphi = K.alpha * kd * K.eta / K.S;
+    rad2(x, y, ir2, F1 * ir, F2, fxx, fyy, fxy);
+    double Fx = F1 * x * ir, Fy = F1 * y * ir;
+    double Cphi = K.cphi;
     // phi_c = F (x^2 - y^2), phi_s = F 2xy
     double cxx = fxx * gxy + 4.0 * Fx * x + 2.0 * F;
     double cyy = fyy * gxy - 4.0 * Fy * y - 2.0 * F;
@@ -154,12 +156,12 @@ __device__ void transient(const PoroK &K, double x, double y, double t, const do
     double syy = fyy * g2 + 4.0 * Fy * x;
     double sxy = fxy * g2 + 2.0 * Fx * x + 2.0 * Fy * y + 2.0 * F;
     double pxx = Cphi * (a * cxx + b * sxx), pyy = Cphi * (a * cyy + b * syy), pxy = Cphi * (a * cxy + b * sxy);
-    double Kd = -K.alpha * K.eta * V / (2.0 * M_PI * K.S);
+    double Kd = K.kdf * V;
     rad2(x, y, ir2, Kd * om * ir2, Kd * (2.0 * z * ez - om) * ir2, pxx, pyy, pxy);
     if (qf != 0.0) {
         double E = e1(z);
-        p += qf * E / (4.0 * M_PI * K.kappa);
-        double Kf = qf * K.eta * t / (2.0 * M_PI * K.S);
+        p += qf * E * K.i4pk;
+        double Kf = qf * K.fe * t;
         double A = z * E + om;
         rad2(x, y, ir2, Kf * A * ir2, Kf * (2.0 * z * E - A) * ir2, pxx, pyy, pxy);
     }
@@ -554,6 +556,21 @@ void upload_rules(int device)
     FM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_gl_w), w.data(), QN * 8));
     FM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_gl8_t), t8.data(), 64));
     FM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_gl8_w), w8.data(), 64));
+    double e1w[31] = {0.0}, hc[23] = {0.0}, p2c[18] = {0.0};
+    for (int k = 1; k <= 30; ++k) e1w[k] = k / ((k + 1.0) * (k + 1.0));
+    double fact = 1.0;  // (k+1)!
+    for (int k = 1; k <= 22; ++k) {
+        fact *= (k + 1);
+        hc[k] = ((k & 1) ? 1.0 : -1.0) / fact;
+    }
+    fact = 1.0;  // k!
+    for (int k = 1; k <= 17; ++k) {
+        fact *= k;
+        if (k >= 2) p2c[k] = ((k & 1) ? -1.0 : 1.0) * (k - 1) / fact;
+    }
+    FM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_e1w), e1w, sizeof(e1w)));
+    FM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_hc), hc, sizeof(hc)));
+    FM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_p2c), p2c, sizeof(p2c)));
     if (device >= 0 && device < 64) g_gl_ready[device] = true;
 }
 
@@ -566,7 +583,16 @@ PoroK poro_constants(const fmddm_ctx *ctx)
     double eta = q.alpha * (1.0 - 2.0 * p.nu) / (2.0 * G * (1.0 - p.nu));
     double S = 1.0 / M + q.alpha * eta;
     double kap = q.perm / q.visc;
-    return PoroK{G, p.nu, q.alpha, kap, S, kap / S, eta, ctx->gc};
+    PoroK K{G, p.nu, q.alpha, kap, S, kap / S, eta, ctx->gc};
+    double kd = (1.0 - 2.0 * p.nu) / (4.0 * M_PI * G * (1.0 - p.nu));
+    K.vfac = (1.0 - 2.0 * p.nu) / (2.0 * (1.0 - p.nu));
+    K.ap = q.alpha * kd / S;
+    K.pv = q.alpha / (4.0 * M_PI * S);
+    K.cphi = q.alpha * kd * eta / S;
+    K.kdf = -q.alpha * eta / (2.0 * M_PI * S);
+    K.i4pk = 1.0 / (4.0 * M_PI * kap);
+    K.fe = eta / (2.0 * M_PI * S);
+    return K;
 }
 
 // sum over terms, into out (mode 0) or subtracted from out (mode 1)
