@@ -144,29 +144,49 @@ __global__ void k_cycle_start(SW s, double *__restrict__ sc)
 // Column j of the Hessenberg matrix from the two Gram-Schmidt passes and the
 // new norm; previous rotations applied, new rotation formed, residual
 // estimate |g_{j+1}| updated.
-__device__ void givens_step(SW s, int j, double *__restrict__ sc)
+// The whole block calls it: the column and the earlier rotations are staged
+// in LDS by all threads, then one thread runs the (serial) recurrence out
+// of LDS instead of through dependent global loads.
+constexpr int MAXRS = 1001;  // restart + 1, at most
+
+__device__ void givens_block(SW s, int j, double nrm, double *__restrict__ sc)
 {
+    __shared__ double Hc[MAXRS + 1], cs_s[MAXRS], sn_s[MAXRS];
     double *H = sc + s.H() + (size_t)j * (s.m + 1);
     double *cs = sc + s.cs(), *sn = sc + s.sn(), *g = sc + s.g();
-    for (int i = 0; i <= j; ++i) H[i] = sc[s.h1() + i] + sc[s.h2() + i];
-    H[j + 1] = sc[s.nrm()];
-    for (int i = 0; i < j; ++i) {
-        double h0 = H[i], hh = H[i + 1];
-        H[i] = cs[i] * h0 + sn[i] * hh;
-        H[i + 1] = -sn[i] * h0 + cs[i] * hh;
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) Hc[i] = sc[s.h1() + i] + sc[s.h2() + i];
+    for (int i = threadIdx.x; i < j; i += blockDim.x) {
+        cs_s[i] = cs[i];
+        sn_s[i] = sn[i];
     }
-    double h0 = H[j], hh = H[j + 1];
-    double den = sqrt(h0 * h0 + hh * hh);
-    cs[j] = den == 0.0 ? 1.0 : h0 / den;
-    sn[j] = den == 0.0 ? 0.0 : hh / den;
-    H[j] = den;
-    H[j + 1] = 0.0;
-    g[j + 1] = -sn[j] * g[j];
-    g[j] = cs[j] * g[j];
-    sc[s.est()] = fabs(g[j + 1]);
+    if (threadIdx.x == 0) Hc[j + 1] = nrm;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < j; ++i) {
+            double h0 = Hc[i], hh = Hc[i + 1];
+            Hc[i] = cs_s[i] * h0 + sn_s[i] * hh;
+            Hc[i + 1] = -sn_s[i] * h0 + cs_s[i] * hh;
+        }
+        double h0 = Hc[j], hh = Hc[j + 1];
+        double den = sqrt(h0 * h0 + hh * hh);
+        double c = den == 0.0 ? 1.0 : h0 / den, sv = den == 0.0 ? 0.0 : hh / den;
+        cs[j] = c;
+        sn[j] = sv;
+        Hc[j] = den;
+        Hc[j + 1] = 0.0;
+        double gj = g[j];
+        g[j + 1] = -sv * gj;
+        g[j] = c * gj;
+        sc[s.est()] = fabs(g[j + 1]);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) H[i] = Hc[i];
 }
 
-__global__ void k_givens(SW s, int j, double *__restrict__ sc) { givens_step(s, j, sc); }
+__global__ __launch_bounds__(64) void k_givens(SW s, int j, double *__restrict__ sc)
+{
+    givens_block(s, j, sc[s.nrm()], sc);
+}
 
 // Fused Arnoldi pieces for short vectors (few dot-product chunks), where
 // launches, not bytes, set the time.  k_vupdate_sum: every block forms the
@@ -216,9 +236,9 @@ __global__ __launch_bounds__(256) void k_scale_givens(int m, const double *__res
     for (int b = threadIdx.x; b < nnp; b += RT) q += npart[b];
     double nrm = sqrt(block_sum(q, red));
     for (int t = blockIdx.x * RT + threadIdx.x; t < m; t += gridDim.x * RT) v[t] = nrm != 0.0 ? w[t] / nrm : 0.0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        sc[s.nrm()] = nrm;
-        givens_step(s, j, sc);
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) sc[s.nrm()] = nrm;
+        givens_block(s, j, nrm, sc);
     }
 }
 
@@ -456,7 +476,7 @@ void GmresRun::step_body(int jj)
         hipLaunchKernelGGL(k_vupdate, dim3(gb), dim3(256), 0, st, n2, jj + 1, V, ldv, sc + s.h2(), -1.0, w);
         norm2(st, n2, w, t->gm_part.p, sc + s.nrm());
         hipLaunchKernelGGL(k_scale, dim3(gb), dim3(256), 0, st, n2, w, sc + s.nrm(), vn);
-        hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, st, s, jj, sc);
+        hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, st, s, jj, sc);
     }
     FM_CHECK_LAUNCH();
     FM_HIP(hipMemcpyAsync(t->gm_host + 2 * (jj & 1), sc + s.nrm(), 16, hipMemcpyDeviceToHost, st));
