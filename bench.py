@@ -116,7 +116,10 @@ def traffic_for(phase):
     return d.get("phases", {}).get(phase, {}).get("bytes_per_launch")
 
 
-SERVE_PARAMS = dict(p=10, leaf=32, m2l=1, m2l_tol=1e-10, restart=50, maxit=20000, use_graphs=0)
+# direct_below: the exact on-the-fly product beats the FMM's chain of
+# launches below about 3000 elements on MI355X (0.048 vs 0.074 ms at 2000,
+# 0.093 vs 0.078 ms at 4000)
+SERVE_PARAMS = dict(p=10, leaf=32, m2l=1, m2l_tol=1e-10, restart=50, maxit=20000, use_graphs=0, direct_below=3000)
 
 
 def serve_run(F, wls, reqs, slots, arrivals, precond=1, precision=0):
@@ -184,7 +187,8 @@ def serving_leg(F, W, count, slots, load):
         "gmres_products_total": iters,
         "params": {"p": SERVE_PARAMS["p"], "leaf": SERVE_PARAMS["leaf"], "m2l": "svd 1e-10", "tol": 1e-6,
                    "restart": SERVE_PARAMS["restart"], "precond": "block-Jacobi, 32-element groups",
-                   "graphs": bool(SERVE_PARAMS["use_graphs"])},
+                   "graphs": bool(SERVE_PARAMS["use_graphs"]),
+                   "exact_product_at_or_below_elements": SERVE_PARAMS["direct_below"]},
         "unpreconditioned": {"batched_saturated_solves_per_s": count / span_np,
                              "gmres_products_total": iters_np},
         "fp32_products": {"batched_saturated_solves_per_s": count / span_32, "gmres_products_total": iters_32,

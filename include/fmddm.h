@@ -120,6 +120,10 @@ typedef struct {
                                  row tile of the expansion) = (4, 64, 64),
                                  (2, 32, 64), (8, 64, 32), (4, 32, 32);
                                  fmddm_autotune picks one */
+    int64_t direct_below;     /* server: requests of at most this many elements
+                                 are solved with the exact on-the-fly product
+                                 instead of the FMM (faster below the size where
+                                 the FMM's chain of launches dominates); 0: never */
 } fmddm_params;
 
 typedef struct {
@@ -149,7 +153,7 @@ typedef struct {
 /* Fill *p with defaults: E=20e9, nu=0.25, leaf=32, p=20, max_level=24,
  * kappa=8, m2l=DENSE, m2l_tol=1e-12, no root box, restart=50,
  * maxit=10000, tol=1e-10, precision=FP64, use_graphs=0, precond=NONE,
- * m2l_tiles=0. */
+ * m2l_tiles=0, direct_below=0. */
 void fmddm_default_params(fmddm_params *p);
 
 /* Create a context on the current HIP device bound to `hip_stream`
@@ -391,6 +395,8 @@ int64_t fmddm_trim_cache(void);
  * The server's parameters apply to every request.  With a reduced
  * precision, a solve's Arnoldi steps use the reduced-precision FMM product
  * and its residuals and stopping test the FP64 product (as fmddm_solve).
+ * Requests of at most direct_below elements use the exact on-the-fly
+ * product instead of the FMM (FP64).
  *
  * Threading: a server is driven from one host thread.  All host memory
  * passed in is copied; nothing is kept after the call returns.

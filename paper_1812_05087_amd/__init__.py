@@ -57,6 +57,7 @@ class Params(C.Structure):
         ("use_root_box", C.c_int), ("root_x0", C.c_double), ("root_y0", C.c_double),
         ("root_L", C.c_double), ("restart", C.c_int), ("maxit", C.c_int), ("tol", C.c_double),
         ("precision", C.c_int), ("use_graphs", C.c_int), ("precond", C.c_int), ("m2l_tiles", C.c_int),
+        ("direct_below", C.c_int64),
     ]
 
 

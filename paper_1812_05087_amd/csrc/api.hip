@@ -53,6 +53,7 @@ const char *check_params(const fmddm_params *p)
     if (p->use_graphs != 0 && p->use_graphs != 1) return "use_graphs must be 0 or 1";
     if (p->precond != FMDDM_PRECOND_NONE && p->precond != FMDDM_PRECOND_BLOCK) return "unknown precond";
     if (p->m2l_tiles < 0 || p->m2l_tiles > 3) return "m2l_tiles must lie in [0, 3]";
+    if (p->direct_below < 0) return "direct_below must be >= 0";
     return nullptr;
 }
 

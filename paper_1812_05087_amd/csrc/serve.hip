@@ -47,6 +47,7 @@ struct Slot {
     size_t host_cap = 0;
     hipEvent_t ev = nullptr;
     int64_t charged = 0;
+    int mode = FMDDM_APPLY_FMM;  // product of the current request
 };
 
 double seconds_since(std::chrono::steady_clock::time_point t0)
@@ -155,11 +156,11 @@ void fail(fmddm_server *s, Slot &sl, fmddm_status st)
     retire(s, sl);
 }
 
-// Reduced-precision products: Arnoldi on them, residuals and the stopping
-// test with the FP64 product (as fmddm_solve)
-int residual_mode(const fmddm_server *s)
+// Reduced-precision FMM products: Arnoldi on them, residuals and the
+// stopping test with the FP64 product (as fmddm_solve)
+int residual_mode(const fmddm_server *s, const Slot &sl)
 {
-    return s->prm.precision != FMDDM_PREC_FP64 ? fmddm::APPLY_FMM_FP64 : -1;
+    return sl.mode == FMDDM_APPLY_FMM && s->prm.precision != FMDDM_PREC_FP64 ? fmddm::APPLY_FMM_FP64 : -1;
 }
 
 void admit(fmddm_server *s, Slot &sl, int64_t id)
@@ -175,14 +176,16 @@ void admit(fmddm_server *s, Slot &sl, int64_t id)
     const double *g = q.geo.data();
     sl.t = new fmddm_tree();
     fmddm::build_tree(sl.ctx, sl.t, n, g, g + n, g + 2 * n, g + 3 * n, 0);
-    fmddm::setup_fmm(sl.ctx, sl.t);
+    // small requests: the exact product, one launch, beats the FMM's chain
+    sl.mode = n <= s->prm.direct_below ? FMDDM_APPLY_DIRECT : FMDDM_APPLY_FMM;
+    if (sl.mode == FMDDM_APPLY_FMM) fmddm::setup_fmm(sl.ctx, sl.t);
     if (sl.pf.n < (size_t)n) sl.pf.alloc(n);
     if (sl.b.n < (size_t)(2 * n)) sl.b.alloc(2 * n);
     if (sl.x.n < (size_t)(2 * n)) sl.x.alloc(2 * n);
     FM_HIP(hipMemcpyAsync(sl.pf.p, g + 4 * n, n * 8, hipMemcpyHostToDevice, sl.stream));
     FM_HIP(hipMemsetAsync(sl.x.p, 0, 2 * n * 8, sl.stream));
     fmddm::rhs_build(sl.ctx, sl.t, sl.pf.p, q.r.SH, q.r.Sh, sl.b.p, 1.0 / q.r.steps);
-    sl.g.start(sl.ctx, sl.t, FMDDM_APPLY_FMM, sl.b.p, sl.x.p, q.r.tol, s->prm.maxit, residual_mode(s));
+    sl.g.start(sl.ctx, sl.t, sl.mode, sl.b.p, sl.x.p, q.r.tol, s->prm.maxit, residual_mode(s, sl));
     sl.phase = 1;
 }
 
@@ -203,7 +206,7 @@ void advance(fmddm_server *s, Slot &sl)
         if (sl.step < q.r.steps) {
             double scale = (double)(sl.step + 1) / q.r.steps;
             fmddm::rhs_build(sl.ctx, sl.t, sl.pf.p, q.r.SH, q.r.Sh, sl.b.p, scale);
-            sl.g.start(sl.ctx, sl.t, FMDDM_APPLY_FMM, sl.b.p, sl.x.p, q.r.tol, s->prm.maxit, residual_mode(s));
+            sl.g.start(sl.ctx, sl.t, sl.mode, sl.b.p, sl.x.p, q.r.tol, s->prm.maxit, residual_mode(s, sl));
             return;
         }
         size_t need = (size_t)(2 * n) * 8;

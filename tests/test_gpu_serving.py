@@ -187,3 +187,28 @@ def test_served_mixed_precision_meets_tolerance(prec):
     d = np.linalg.norm(out[prec] - out[F.FMDDM_PREC_FP64]) / np.linalg.norm(out[F.FMDDM_PREC_FP64])
     print(f"precision {prec}: exact residual {res:.2e}, vs FP64 server {d:.2e}")
     assert res <= 1e-6 and d <= 1e-6, (res, d)
+
+
+def test_small_requests_on_exact_product():
+    """Requests at or below direct_below elements are solved with the exact
+    on-the-fly product: the served DDs satisfy the oracle's exact system to
+    the requested tolerance itself (no FMM error), beside FMM requests."""
+    reqs = W.serving_stream(seed=41, count=3, nmin=600, nmax=3000, steps_max=1)
+    prm = F.fmddm_default_params(**P_SERVE, precond=F.FMDDM_PRECOND_BLOCK, direct_below=1500)
+    srv = F.fmddm_server_create(prm, 3)
+    try:
+        subs = [submit(srv, r, tol=1e-9) for r in reqs]
+        res = drain(srv, [t for t, _ in subs])
+        for (t, wl) in subs:
+            r = res[t]
+            assert r["state"] == F.FMDDM_REQ_DONE and r["relres"] <= 1e-9, r
+            D = F.fmddm_server_poll(srv, t, wl.n)[1]
+            g = O.Geometry.of(wl)
+            b = O.rhs(g, wl.pressure, wl.SH, wl.Sh)
+            e = np.linalg.norm(O.direct_matvec(g, D) - b) / np.linalg.norm(b)
+            bar = 1.01e-9 if wl.n <= 1500 else 1e-6   # exact product vs FMM
+            print(f"n={wl.n}: exact residual {e:.2e}")
+            assert e <= bar, (wl.n, e)
+        assert any(wl.n <= 1500 for _, wl in subs) and any(wl.n > 1500 for _, wl in subs)
+    finally:
+        F.fmddm_server_destroy(srv)
