@@ -241,6 +241,19 @@ fmddm_status fmddm_solve(fmddm_ctx *ctx, fmddm_tree *t, int mode, const double *
 fmddm_status fmddm_sif(fmddm_ctx *ctx, fmddm_tree *t, const double *D, int64_t elem,
                        double *KI, double *KII);
 
+/* Measured device peaks (fmddm_measure_peaks). */
+typedef struct {
+    double fp64_vector_tflops;  /* FP64 FMA loop on the vector ALUs */
+    double fp64_mfma_tflops;    /* FP64 16x16x4 MFMA loop */
+    double copy_gbps;           /* device-to-device copy of 1 GiB, bytes read + written per second */
+} fmddm_peaks;
+
+/* Microbenchmarks of the current device, the measured roofline denominators
+ * reported beside the vendor figures: register-resident FP64 FMA and MFMA
+ * loops over 16 blocks per compute unit, and a 1 GiB stream copy.  Runs on
+ * a stream of its own and synchronises it; allocates 2 GiB for the copy. */
+fmddm_status fmddm_measure_peaks(fmddm_peaks *out);
+
 /* One configuration tried by fmddm_autotune. */
 typedef struct {
     int32_t leaf, p;

@@ -36,7 +36,7 @@ EXPORTED = [
     "fmddm_server_submit", "fmddm_server_step", "fmddm_server_poll", "fmddm_server_release",
     "fmddm_memory_in_use", "fmddm_memory_cached", "fmddm_trim_cache",
     "fmddm_poro_set", "fmddm_poro_apply", "fmddm_add_history", "fmddm_poro_rhs", "fmddm_poro_solve",
-    "fmddm_autotune",
+    "fmddm_autotune", "fmddm_measure_peaks",
 ]
 FMDDM_REQ_QUEUED, FMDDM_REQ_RUNNING, FMDDM_REQ_DONE, FMDDM_REQ_FAILED = 0, 1, 2, 3
 PHASES = ["prep", "p2m", "m2m", "m2m_sum", "compress", "compress_sum", "m2l", "m2l_sum", "decompress",
@@ -88,6 +88,10 @@ class Result(C.Structure):
 class PoroParams(C.Structure):
     _fields_ = [("nu_u", C.c_double), ("alpha", C.c_double), ("perm", C.c_double), ("visc", C.c_double),
                 ("dt", C.c_double), ("p0", C.c_double), ("mode", C.c_int32)]
+
+
+class Peaks(C.Structure):
+    _fields_ = [("fp64_vector_tflops", C.c_double), ("fp64_mfma_tflops", C.c_double), ("copy_gbps", C.c_double)]
 
 
 class TuneEntry(C.Structure):
@@ -150,6 +154,7 @@ def lib():
         L.fmddm_add_history.argtypes = [_vp, _vp, C.c_int, _vp, _vp]
         L.fmddm_poro_rhs.argtypes = [_vp, _vp, _vp, C.c_double, C.c_double, _vp]
         L.fmddm_poro_solve.argtypes = [_vp, _vp, _vp, _vp, C.POINTER(SolveInfo)]
+        L.fmddm_measure_peaks.argtypes = [C.POINTER(Peaks)]
         L.fmddm_autotune.argtypes = [C.POINTER(Params), C.c_int64, _vp, _vp, _vp, _vp, _vp, C.c_int32, _vp,
                                      C.c_int32, C.c_double, C.c_int32, C.POINTER(Params), _vp, C.c_int32,
                                      C.POINTER(C.c_int32)]
@@ -296,6 +301,14 @@ def fmddm_autotune(params: Params, x1, y1, x2, y2, leaves=(16, 32, 64, 128), ps=
     if st < 0:
         raise FmddmError(st, "autotune failed")
     return st, best, [{k: getattr(log[i], k) for k, _ in TuneEntry._fields_} for i in range(nlog.value)]
+
+
+def fmddm_measure_peaks():
+    p = Peaks()
+    st = lib().fmddm_measure_peaks(C.byref(p))
+    if st < 0:
+        raise FmddmError(st, "peak measurement failed")
+    return {k: getattr(p, k) for k, _ in Peaks._fields_}
 
 
 def fmddm_sif(ctx, tree, D, elem):

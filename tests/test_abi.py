@@ -38,7 +38,7 @@ def test_struct_layouts_match_header():
     src = '#include "fmddm.h"\n#include <stdio.h>\nint main(){printf("%zu %zu %zu %zu %zu %zu %zu\\n",' \
           'sizeof(fmddm_params),sizeof(fmddm_tree_info),sizeof(fmddm_solve_info),' \
           'sizeof(fmddm_request),sizeof(fmddm_result),sizeof(fmddm_poro_params),' \
-          'sizeof(fmddm_tune_entry));return 0;}\n'
+          'sizeof(fmddm_tune_entry));printf("%zu\\n",sizeof(fmddm_peaks));return 0;}\n'
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "s.c")
         open(c, "w").write(src)
@@ -47,7 +47,7 @@ def test_struct_layouts_match_header():
         sizes = list(map(int, subprocess.check_output([exe]).split()))
     assert sizes == [C.sizeof(F.Params), C.sizeof(F.TreeInfo), C.sizeof(F.SolveInfo),
                      C.sizeof(F.Request), C.sizeof(F.Result), C.sizeof(F.PoroParams),
-                     C.sizeof(F.TuneEntry)]
+                     C.sizeof(F.TuneEntry), C.sizeof(F.Peaks)]
 
 
 def test_default_params_and_validation_without_device():
@@ -100,6 +100,7 @@ def test_default_params_and_validation_without_device():
         a2 = list(args)
         a2[i] = bad
         assert lib.fmddm_autotune(*a2) == F.FMDDM_EINVAL, i
+    assert lib.fmddm_measure_peaks(None) == F.FMDDM_EINVAL
     bad_p = (C.c_int32 * 2)(8, 33)
     a2 = list(args)
     a2[8] = bad_p
