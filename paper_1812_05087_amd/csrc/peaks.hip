@@ -28,27 +28,42 @@ __global__ __launch_bounds__(PT) void k_fma_loop(int iters, double a, double b, 
     out[blockIdx.x * PT + threadIdx.x] = s;
 }
 
-// 4 independent 16x16x4 FP64 MFMA accumulators per wave, `iters` rounds:
-// 4 x 2048 flops per wave and round
+// MACC independent 16x16x4 FP64 MFMA accumulators per wave, `iters`
+// rounds: MACC x 2048 flops per wave and round
+constexpr int MACC = 8;
+
 __global__ __launch_bounds__(PT) void k_mfma_loop(int iters, double a, double b, double *__restrict__ out)
 {
-    d4 acc[4];
+    d4 acc[MACC];
 #pragma unroll
-    for (int c = 0; c < 4; ++c) acc[c] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int c = 0; c < MACC; ++c) acc[c] = d4{0.0, 0.0, 0.0, 0.0};
     double x = a + threadIdx.x * 1e-6, y = b - threadIdx.x * 1e-6;
     for (int i = 0; i < iters; ++i) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc[c], 0, 0, 0);
+        for (int c = 0; c < MACC; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc[c], 0, 0, 0);
     }
     double s = 0.0;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
+    for (int c = 0; c < MACC; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
     out[blockIdx.x * PT + threadIdx.x] = s;
 }
 
+// grid-stride copy with CU loads in flight per thread (n a multiple of the
+// grid's stride times CU is not required: the tail is guarded)
+constexpr int CU = 4;
+
 __global__ __launch_bounds__(PT) void k_copy(int64_t n, const double2 *__restrict__ src, double2 *__restrict__ dst)
 {
-    for (int64_t i = (int64_t)blockIdx.x * PT + threadIdx.x; i < n; i += (int64_t)gridDim.x * PT) dst[i] = src[i];
+    const int64_t stride = (int64_t)gridDim.x * PT;
+    for (int64_t i = (int64_t)blockIdx.x * PT + threadIdx.x; i < n; i += CU * stride) {
+        double2 v[CU];
+#pragma unroll
+        for (int u = 0; u < CU; ++u)
+            if (i + u * stride < n) v[u] = src[i + u * stride];
+#pragma unroll
+        for (int u = 0; u < CU; ++u)
+            if (i + u * stride < n) dst[i + u * stride] = v[u];
+    }
 }
 
 }  // namespace
@@ -100,7 +115,7 @@ extern "C" fmddm_status fmddm_measure_peaks(fmddm_peaks *out)
             hipLaunchKernelGGL(k_mfma_loop, dim3(nblk), dim3(PT), 0, s, it_mfma, 0.999999, 1e-7, sink.p);
             FM_CHECK_LAUNCH();
         });
-        out->fp64_mfma_tflops = (double)nblk * (PT / 64) * it_mfma * 4 * 2048.0 / t * 1e-12;
+        out->fp64_mfma_tflops = (double)nblk * (PT / 64) * it_mfma * MACC * 2048.0 / t * 1e-12;
         const int64_t bytes = (int64_t)1 << 30;
         DBuf<double> a, b;
         a.alloc(bytes / 8);
