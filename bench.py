@@ -203,16 +203,18 @@ def serving_leg(F, W, count, slots, load):
     }
 
 
-def history_run(F, W, elems, steps, mode, p):
+def history_run(F, W, elems, steps, mode, p, near_cache=0):
     """One left-hand-side product and the history sum of step `steps` on the
     horizontal-well cluster (5 fractures of `elems` 0.2 m elements, 10 m
-    apart; Biot constants of the well example, 60 s steps), timed on the
-    device after one untimed pass that builds the operators."""
+    apart; Biot constants of the well example, 60 s steps), timed after a
+    first pass that builds the multipole operators and, with the near-field
+    cache (near_cache >= 0), integrates every time level's near blocks once;
+    that first pass is timed too."""
     import torch
     wl = W.well_cluster(n_frac=5, elems=elems, half_length=0.1 * elems, spacing=10.0)
     prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=20e9, nu=0.2, p=p, leaf=32)
     try:
-        F.fmddm_poro_set(prob.ctx, 0.35, 0.8, 1e-18, 1e-3, 60.0, 48.26e6, mode=mode)
+        F.fmddm_poro_set(prob.ctx, 0.35, 0.8, 1e-18, 1e-3, 60.0, 48.26e6, mode=mode, near_cache_bytes=near_cache)
         n3 = 3 * prob.n
         rng = np.random.default_rng(3)
         scale = np.tile([1e-4, 1e-4, 1e-10], prob.n)
@@ -221,9 +223,12 @@ def history_run(F, W, elems, steps, mode, p):
         D = hist[:n3].clone()
         out = torch.zeros(n3, dtype=torch.float64, device="cuda")
         rhs = torch.zeros(n3, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         F.fmddm_poro_apply(prob.ctx, prob.tree, 0, D, out)        # builds operators
         F.fmddm_add_history(prob.ctx, prob.tree, steps, hist, rhs)
         torch.cuda.synchronize()
+        t_first = time.perf_counter() - t0
         t0 = time.perf_counter()
         F.fmddm_poro_apply(prob.ctx, prob.tree, 0, D, out)
         torch.cuda.synchronize()
@@ -232,7 +237,7 @@ def history_run(F, W, elems, steps, mode, p):
         F.fmddm_add_history(prob.ctx, prob.tree, steps, hist, rhs)
         torch.cuda.synchronize()
         t_hist = time.perf_counter() - t0
-        return prob.n, t_lhs, t_hist, out.cpu().numpy(), rhs.cpu().numpy()
+        return prob.n, t_lhs, t_hist, out.cpu().numpy(), rhs.cpu().numpy(), t_first
     finally:
         prob.close()
 
@@ -243,17 +248,22 @@ def history_leg(F, W, elems, steps, p=10):
     and multipole against exact evaluation at a tenth of it."""
     small = max(elems // 10, 40)
     out = {"dt_s": 60.0, "history_of_step": steps, "time_levels": steps, "p": p}
-    n, tl, th, _, _ = history_run(F, W, elems, steps, F.FMDDM_APPLY_FMM, p)
+    n, tl, th, o_c, r_c, tf = history_run(F, W, elems, steps, F.FMDDM_APPLY_FMM, p)
+    _, tl0, th0, o_0, r_0, tf0 = history_run(F, W, elems, steps, F.FMDDM_APPLY_FMM, p, near_cache=-1)
     out["fmm_full"] = {"workload": f"well cluster 5 x {elems} elements (N={n})", "lhs_product_ms": tl * 1e3,
-                       "history_ms": th * 1e3, "lag_applications_per_s": (steps - 1) / th}
-    n2, tl2, th2, o_f, r_f = history_run(F, W, small, steps, F.FMDDM_APPLY_FMM, p)
-    _, tl3, th3, o_e, r_e = history_run(F, W, small, steps, F.FMDDM_APPLY_DIRECT, p)
+                       "history_ms": th * 1e3, "lag_applications_per_s": (steps - 1) / th,
+                       "first_pass_ms": tf * 1e3,
+                       "near_on_the_fly": {"lhs_product_ms": tl0 * 1e3, "history_ms": th0 * 1e3,
+                                           "first_pass_ms": tf0 * 1e3}}
+    n2, tl2, th2, o_f, r_f, _ = history_run(F, W, small, steps, F.FMDDM_APPLY_FMM, p)
+    _, tl3, th3, o_e, r_e, _ = history_run(F, W, small, steps, F.FMDDM_APPLY_DIRECT, p)
     rel = lambda a, b: float(max(np.abs(a[k::3] - b[k::3]).max() / max(np.abs(b[k::3]).max(), 1e-300)
                                  for k in range(3)))
     out["small"] = {"workload": f"well cluster 5 x {small} elements (N={n2})",
                     "fmm": {"lhs_product_ms": tl2 * 1e3, "history_ms": th2 * 1e3},
                     "exact": {"lhs_product_ms": tl3 * 1e3, "history_ms": th3 * 1e3},
                     "fmm_err_vs_exact": {"lhs": rel(o_f, o_e), "history": rel(r_f, r_e)}}
+    out["fmm_full"]["stored_vs_on_the_fly"] = {"lhs": rel(o_c, o_0), "history": rel(r_c, r_0)}
     return out
 
 

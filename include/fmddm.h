@@ -346,6 +346,15 @@ typedef struct {
                                  FMDDM_APPLY_FMM: the same for neighbouring elements and
                                  Chebyshev multipoles (the context's p, 2..16) for well-separated
                                  cells, the time levels contracted in one M2L product */
+    int64_t near_cache_bytes; /* FMDDM_APPLY_FMM only: device memory for the near-field cache.
+                                 The exact element integrals of neighbouring elements depend only
+                                 on the geometry, the medium and the time level, so each level's
+                                 4 x 3 response blocks (96 bytes per near pair) are integrated
+                                 once, on first use, and kept with the tree; later products at
+                                 that level are block-sparse products.  Levels beyond the budget
+                                 are integrated on the fly at every product.  0: a quarter of
+                                 the free device memory at first use, at most 32 GiB; > 0: that
+                                 many bytes; < 0: no cache. */
 } fmddm_poro_params;
 
 /* Attaches the poroelastic medium to the context (validated: EINVAL). */

@@ -87,7 +87,7 @@ class Result(C.Structure):
 
 class PoroParams(C.Structure):
     _fields_ = [("nu_u", C.c_double), ("alpha", C.c_double), ("perm", C.c_double), ("visc", C.c_double),
-                ("dt", C.c_double), ("p0", C.c_double), ("mode", C.c_int32)]
+                ("dt", C.c_double), ("p0", C.c_double), ("mode", C.c_int32), ("near_cache_bytes", C.c_int64)]
 
 
 class Peaks(C.Structure):
@@ -450,9 +450,11 @@ def fmddm_trim_cache() -> int:
 
 
 # ------------------------------------------------------------ poroelastic
-def fmddm_poro_set(ctx, nu_u, alpha, perm, visc, dt, p0=0.0, mode=1):
-    """mode: FMDDM_APPLY_DIRECT (1, exact) or FMDDM_APPLY_FMM (0)."""
-    pp = PoroParams(float(nu_u), float(alpha), float(perm), float(visc), float(dt), float(p0), int(mode))
+def fmddm_poro_set(ctx, nu_u, alpha, perm, visc, dt, p0=0.0, mode=1, near_cache_bytes=0):
+    """mode: FMDDM_APPLY_DIRECT (1, exact) or FMDDM_APPLY_FMM (0).
+    near_cache_bytes: FMM near-field cache budget (0 default, < 0 none)."""
+    pp = PoroParams(float(nu_u), float(alpha), float(perm), float(visc), float(dt), float(p0), int(mode),
+                    int(near_cache_bytes))
     _check(lib().fmddm_poro_set(ctx, C.byref(pp)), ctx)
 
 

@@ -180,6 +180,7 @@ struct fmddm_tree {
     int nitem = 0;
     int64_t npartial = 0;
     fmddm::DBuf<int> it_leaf, it_s0, it_s1, it_poff, lk_off, tleaf;
+    fmddm::DBuf<int64_t> it_coff;  // per item: (target, source) pairs of the items before it
     std::vector<int> leaves;          // host list of leaf cells (tree order)
     fmddm::DBuf<int> dleaves;
     int64_t near_pairs = 0, l2p_pairs = 0, m2m_pairs = 0;
@@ -232,6 +233,15 @@ struct fmddm_tree {
     fmddm::DBuf<int> pf_tile_op, pf_tile_beg, pf_tile_end, pf_psrc, pf_pdst, pf_combo_lvl, pf_combo_ox,
         pf_combo_oy;
     fmddm::DBuf<double> pf_ops, pf_W, pf_part, pf_Z, pf_G, pf_far, pf_Q, pf_D3, pf_near, pf_D2, pf_o2;
+    double pf_key[8] = {};  // medium the operators were built for
+    // poroelastic near field: per time level j (time (j+1) dt), the 4 x 3
+    // response blocks of every near (target, source) pair in item order,
+    // integrated on first use; pn_ptr holds the levels' device addresses
+    std::vector<std::unique_ptr<fmddm::DBuf<double>>> pn_lvl;
+    std::vector<double *> pn_hptr;
+    fmddm::DBuf<double *> pn_ptr;
+    int pn_cap = -1;        // levels that fit the budget (-1: not sized yet)
+    double pn_key[8] = {};  // medium and budget the levels were built for
     // Arnoldi steps captured as graphs, one per step index, valid for the
     // context and apply mode they were captured with
     std::vector<hipGraphExec_t> gm_graph;

@@ -126,18 +126,28 @@ __device__ __forceinline__ void rad2(double x, double y, double ir2, double f1, 
     dxy += (f2 - f1) * x * y * ir2;
 }
 
-// Transient response (sxx, syy, sxy, p) at offset (x, y) and time t.
-__device__ void transient(const PoroK &K, double x, double y, double t, const double q[3], double qf,
-                          double o[4])
+// Parts of the transient point response at offset (x, y) and time t that
+// do not depend on the source strengths: the charges enter only through
+// a = 2G (q0 - q1), b = 2G q2 and V, and the fluid source through q_f.
+struct TPoint {
+    double ir2, ict, z, ez, om, gxy, g2, P2;
+    // second derivatives of phi_c = F (x^2 - y^2) and phi_s = F 2xy
+    double cxx, cyy, cxy, sxx, syy, sxy;
+};
+
+__device__ __forceinline__ void tpoint(const PoroK &K, double x, double y, double t, TPoint &T)
 {
     double r2 = x * x + y * y, ir2 = recip(r2), r = sqrt(r2), ir = recip(r);
     double ict = recip(K.c * t);  // 1 / (c t)
     double z = 0.25 * r2 * ict;
-    double ez = exp(-z), om = -expm1(-z);
-    double a = 2.0 * K.G * (q[0] - q[1]), b = 2.0 * K.G * q[2];
-    double V = -(q[0] + q[1]) * K.vfac;
-    double gxy = x * x - y * y, g2 = 2.0 * x * y;
-    double p = K.ap * (a * gxy + b * g2) * ir2 * ir2 * p2fun(z) - K.pv * V * ez * ict;
+    T.ir2 = ir2;
+    T.ict = ict;
+    T.z = z;
+    T.ez = exp(-z);
+    T.om = -expm1(-z);
+    T.gxy = x * x - y * y;
+    T.g2 = 2.0 * x * y;
+    T.P2 = p2fun(z);
     double h, h1, h2;
     hfun(z, h, h1, h2);
     double F = -0.25 * h * ir2;
@@ -147,15 +157,28 @@ __device__ void transient(const PoroK &K, double x, double y, double t, const do
     double fxx = 0.0, fyy = 0.0, fxy = 0.0;
     rad2(x, y, ir2, F1 * ir, F2, fxx, fyy, fxy);
     double Fx = F1 * x * ir, Fy = F1 * y * ir;
+    double gxy = T.gxy, g2 = T.g2;
+    T.cxx = fxx * gxy + 4.0 * Fx * x + 2.0 * F;
+    T.cyy = fyy * gxy - 4.0 * Fy * y - 2.0 * F;
+    T.cxy = fxy * gxy - 2.0 * Fx * y + 2.0 * Fy * x;
+    T.sxx = fxx * g2 + 4.0 * Fx * y;
+    T.syy = fyy * g2 + 4.0 * Fy * x;
+    T.sxy = fxy * g2 + 2.0 * Fx * x + 2.0 * Fy * y + 2.0 * F;
+}
+
+// Transient response (sxx, syy, sxy, p) at offset (x, y) and time t.
+__device__ void transient(const PoroK &K, double x, double y, double t, const double q[3], double qf,
+                          double o[4])
+{
+    TPoint T;
+    tpoint(K, x, y, t, T);
+    double ir2 = T.ir2, z = T.z, ez = T.ez, om = T.om;
+    double a = 2.0 * K.G * (q[0] - q[1]), b = 2.0 * K.G * q[2];
+    double V = -(q[0] + q[1]) * K.vfac;
+    double p = K.ap * (a * T.gxy + b * T.g2) * ir2 * ir2 * T.P2 - K.pv * V * ez * T.ict;
     double Cphi = K.cphi;
-    // phi_c = F (x^2 - y^2), phi_s = F 2xy
-    double cxx = fxx * gxy + 4.0 * Fx * x + 2.0 * F;
-    double cyy = fyy * gxy - 4.0 * Fy * y - 2.0 * F;
-    double cxy = fxy * gxy - 2.0 * Fx * y + 2.0 * Fy * x;
-    double sxx = fxx * g2 + 4.0 * Fx * y;
-    double syy = fyy * g2 + 4.0 * Fy * x;
-    double sxy = fxy * g2 + 2.0 * Fx * x + 2.0 * Fy * y + 2.0 * F;
-    double pxx = Cphi * (a * cxx + b * sxx), pyy = Cphi * (a * cyy + b * syy), pxy = Cphi * (a * cxy + b * sxy);
+    double pxx = Cphi * (a * T.cxx + b * T.sxx), pyy = Cphi * (a * T.cyy + b * T.syy),
+           pxy = Cphi * (a * T.cxy + b * T.sxy);
     double Kd = K.kdf * V;
     rad2(x, y, ir2, Kd * om * ir2, Kd * (2.0 * z * ez - om) * ir2, pxx, pyy, pxy);
     if (qf != 0.0) {
@@ -171,14 +194,48 @@ __device__ void transient(const PoroK &K, double x, double y, double t, const do
     o[3] = p;
 }
 
+// The same response to each source strength alone, added times w into R:
+// R[4 s + k] is response k (sxx, syy, sxy, p) to unit s (a, b, V, q_f).
+__device__ __forceinline__ void transient_basis(const PoroK &K, double x, double y, double t, double w,
+                                                double R[16])
+{
+    TPoint T;
+    tpoint(K, x, y, t, T);
+    double ir2 = T.ir2, z = T.z, ez = T.ez, om = T.om;
+    double m2g = -2.0 * K.G * w, p2g = 2.0 * K.G * w;
+    double pc = K.ap * ir2 * ir2 * T.P2 * w, Cw = K.cphi;
+    R[0] += m2g * Cw * T.cyy;
+    R[1] += m2g * Cw * T.cxx;
+    R[2] += p2g * Cw * T.cxy;
+    R[3] += pc * T.gxy;
+    R[4] += m2g * Cw * T.syy;
+    R[5] += m2g * Cw * T.sxx;
+    R[6] += p2g * Cw * T.sxy;
+    R[7] += pc * T.g2;
+    double dxx = 0.0, dyy = 0.0, dxy = 0.0;
+    rad2(x, y, ir2, K.kdf * om * ir2, K.kdf * (2.0 * z * ez - om) * ir2, dxx, dyy, dxy);
+    R[8] += m2g * dyy;
+    R[9] += m2g * dxx;
+    R[10] += p2g * dxy;
+    R[11] -= w * K.pv * ez * T.ict;
+    double E = e1(z), A = z * E + om, ft = K.fe * t;
+    dxx = dyy = dxy = 0.0;
+    rad2(x, y, ir2, ft * A * ir2, ft * (2.0 * z * E - A) * ir2, dxx, dyy, dxy);
+    R[12] += m2g * dyy;
+    R[13] += m2g * dxx;
+    R[14] += p2g * dxy;
+    R[15] += w * E * K.i4pk;
+}
+
 constexpr int QN = 12;  // Gauss-Legendre points per panel
 __constant__ double c_gl_t[QN], c_gl_w[QN], c_gl8_t[8], c_gl8_w[8];
 
-// Element integral of the transient response at time t, added (times w0)
-// into o: element (cx, cy, cb, sb, a) with charges q per unit length and
-// fluid source qf, receiver (X, Y).
-__device__ void elem_transient(const PoroK &K, double X, double Y, double cx, double cy, double cb, double sb,
-                               double a, const double q[3], double qf, double t, double w0, double o[4])
+// Quadrature of a function along the element (cx, cy, cb, sb, a) seen from
+// the receiver (X, Y) at time t: f(x, y, w) for every point, with (x, y)
+// the receiver's offset from the point and w the weight per unit length.
+template <class Fn>
+__device__ __forceinline__ void elem_quad(const PoroK &K, double X, double Y, double cx, double cy, double cb,
+                                          double sb, double a, double t, Fn &&f)
 {
     double dx = X - cx, dy = Y - cy;
     double xl = dx * cb + dy * sb, yl = dy * cb - dx * sb;
@@ -186,13 +243,10 @@ __device__ void elem_transient(const PoroK &K, double X, double Y, double cx, do
     double far = 8.0 * fmax(2.0 * a, ell);
     double ox = fabs(xl) - a;
     double d2 = yl * yl + (ox > 0.0 ? ox * ox : 0.0);
-    double r[4];
     if (d2 >= far * far) {
         for (int g = 0; g < 8; ++g) {
             double s = a * c_gl8_t[g];
-            transient(K, X - (cx + s * cb), Y - (cy + s * sb), t, q, qf, r);
-            double w = w0 * a * c_gl8_w[g];
-            for (int k = 0; k < 4; ++k) o[k] += w * r[k];
+            f(X - (cx + s * cb), Y - (cy + s * sb), a * c_gl8_w[g]);
         }
         return;
     }
@@ -206,12 +260,51 @@ __device__ void elem_transient(const PoroK &K, double X, double Y, double cx, do
         for (int pn = 0; pn < np; ++pn) {
             for (int g = 0; g < QN; ++g) {
                 double u = (pn + 0.5 + 0.5 * c_gl_t[g]) * du;
-                double w = w0 * 0.5 * du * c_gl_w[g] * 3.0 * L * u * u;
+                double w = 0.5 * du * c_gl_w[g] * 3.0 * L * u * u;
                 double s = side ? s0 + L * u * u * u : s0 - L * u * u * u;
-                transient(K, X - (cx + s * cb), Y - (cy + s * sb), t, q, qf, r);
-                for (int k = 0; k < 4; ++k) o[k] += w * r[k];
+                f(X - (cx + s * cb), Y - (cy + s * sb), w);
             }
         }
+    }
+}
+
+// Element integral of the transient response at time t, added into o:
+// element (cx, cy, cb, sb, a) with charges q per unit length and fluid
+// source qf, receiver (X, Y).
+__device__ void elem_transient(const PoroK &K, double X, double Y, double cx, double cy, double cb, double sb,
+                               double a, const double q[3], double qf, double t, double o[4])
+{
+    elem_quad(K, X, Y, cx, cy, cb, sb, a, t, [&](double x, double y, double w) {
+        double r[4];
+        transient(K, x, y, t, q, qf, r);
+        for (int k = 0; k < 4; ++k) o[k] += w * r[k];
+    });
+}
+
+// The element's 4 x 3 response block at time t: B[3 k + c] is response k
+// (sxx, syy, sxy, p) at (X, Y) to unit D_s (c = 0), D_n (1) or D_q (2) on
+// the element.  The strengths (a, b, V) of a unit DD are constant along the
+// element, so the four unit-strength responses are integrated once and
+// combined at the end.
+__device__ void elem_block(const PoroK &K, double X, double Y, double cx, double cy, double cb, double sb,
+                           double a, double t, double B[12])
+{
+    double R[16];
+    for (int k = 0; k < 16; ++k) R[k] = 0.0;
+    elem_quad(K, X, Y, cx, cy, cb, sb, a, t,
+              [&](double x, double y, double w) { transient_basis(K, x, y, t, w, R); });
+    double sa[2], sbb[2], sv[2];
+    for (int c = 0; c < 2; ++c) {
+        double q[3];
+        charge(cb, sb, c == 0 ? 1.0 : 0.0, c == 1 ? 1.0 : 0.0, q[0], q[1], q[2]);
+        sa[c] = 2.0 * K.G * (q[0] - q[1]);
+        sbb[c] = 2.0 * K.G * q[2];
+        sv[c] = -(q[0] + q[1]) * K.vfac;
+    }
+    for (int k = 0; k < 4; ++k) {
+        B[3 * k] = sa[0] * R[k] + sbb[0] * R[4 + k] + sv[0] * R[8 + k];
+        B[3 * k + 1] = sa[1] * R[k] + sbb[1] * R[4 + k] + sv[1] * R[8 + k];
+        B[3 * k + 2] = R[12 + k];
     }
 }
 
@@ -243,7 +336,7 @@ __global__ __launch_bounds__(PT) void k_poro_pairs(int n, const double *__restri
             if (Ds == 0.0 && Dn == 0.0 && Dq == 0.0) continue;
             double q[3];
             charge(ecb, esb, Ds, Dn, q[0], q[1], q[2]);
-            elem_transient(K, X, Y, ecx, ecy, ecb, esb, ea, q, Dq, times[k], 1.0, o);
+            elem_transient(K, X, Y, ecx, ecy, ecb, esb, ea, q, Dq, times[k], o);
             if (k == drained_term) elem_stress_add(X, Y, ecx, ecy, ecb, esb, ea, Ds, Dn, K.gc, o[0], o[1], o[2]);
         }
     }
@@ -286,7 +379,7 @@ __global__ __launch_bounds__(256) void k_ppc_build(int nblk, const int *__restri
         double Ds = c == 0 ? 1.0 : 0.0, Dn = c == 1 ? 1.0 : 0.0, Dq = c == 2 ? 1.0 : 0.0;
         double q[3], o[4] = {0.0, 0.0, 0.0, 0.0};
         charge(e_cb[j], e_sb[j], Ds, Dn, q[0], q[1], q[2]);
-        elem_transient(K, e_cx[i], e_cy[i], e_cx[j], e_cy[j], e_cb[j], e_sb[j], e_a[j], q, Dq, dt, 1.0, o);
+        elem_transient(K, e_cx[i], e_cy[i], e_cx[j], e_cy[j], e_cb[j], e_sb[j], e_a[j], q, Dq, dt, o);
         elem_stress_add(e_cx[i], e_cy[i], e_cx[j], e_cy[j], e_cb[j], e_sb[j], e_a[j], Ds, Dn, K.gc, o[0], o[1],
                         o[2]);
         double ts, tn;
@@ -448,8 +541,8 @@ __global__ __launch_bounds__(PN) void k_pp2p(int nitem, const int *__restrict__ 
                                              const int *__restrict__ npre, const double *__restrict__ cx,
                                              const double *__restrict__ cy, const double *__restrict__ cb,
                                              const double *__restrict__ sb, const double *__restrict__ a, int n,
-                                             int H, double dt, const double *__restrict__ D3, PoroK K,
-                                             double *__restrict__ part)
+                                             int j0, int H, double dt, const double *__restrict__ D3, PoroK K,
+                                             int acc, double *__restrict__ part)
 {
     int k = blockIdx.x;
     int li = it_leaf[k], s0 = it_s0[k], s1 = it_s1[k];
@@ -473,12 +566,12 @@ __global__ __launch_bounds__(PN) void k_pp2p(int nitem, const int *__restrict__ 
                 while (lo + 1 < nn && npre[nb + lo + 1] <= v) ++lo;  // v ascends
                 int jsrc = nbeg[nb + lo] + (v - npre[nb + lo]);
                 double ecx = cx[jsrc], ecy = cy[jsrc], ecb = cb[jsrc], esb = sb[jsrc], ea = a[jsrc];
-                for (int j = 0; j < H; ++j) {
+                for (int j = j0; j < H; ++j) {
                     const double *d = D3 + ((size_t)j * n + jsrc) * 3;
                     if (d[0] == 0.0 && d[1] == 0.0 && d[2] == 0.0) continue;
                     double q[3];
                     charge(ecb, esb, d[0], d[1], q[0], q[1], q[2]);
-                    elem_transient(K, X, Y, ecx, ecy, ecb, esb, ea, q, d[2], (j + 1) * dt, 1.0, o);
+                    elem_transient(K, X, Y, ecx, ecy, ecb, esb, ea, q, d[2], (j + 1) * dt, o);
                 }
             }
         }
@@ -486,10 +579,96 @@ __global__ __launch_bounds__(PN) void k_pp2p(int nitem, const int *__restrict__ 
             for (int cc = 0; cc < 4; ++cc) o[cc] += __shfl_xor(o[cc], w);
         if (act && sub == 0) {
             double *pp = pk + 4 * (size_t)(i - tb);
-            pp[0] = o[0];
-            pp[1] = o[1];
-            pp[2] = o[2];
-            pp[3] = o[3];
+            for (int cc = 0; cc < 4; ++cc) pp[cc] = acc ? pp[cc] + o[cc] : o[cc];
+        }
+    }
+}
+
+// Near-field blocks of time level (t = (j+1) dt) for every near pair, one
+// thread per pair: pair g lies in item k with it_coff[k] <= g <
+// it_coff[k+1]; within the item, pair e = v nt + i (source v of the chunk,
+// target i of the leaf) stores its 12 entries at 12 it_coff[k] + (12 v + c)
+// nt + i, so that consecutive targets are adjacent for every entry c.
+__global__ __launch_bounds__(256) void k_pnear_build(int64_t npair, int nitem, const int64_t *__restrict__ it_coff,
+                                                     const int *__restrict__ it_leaf, const int *__restrict__ it_s0,
+                                                     const int *__restrict__ leaves, const int *__restrict__ pbeg,
+                                                     const int *__restrict__ pend, const int *__restrict__ noff,
+                                                     const int *__restrict__ nbeg, const int *__restrict__ npre,
+                                                     const double *__restrict__ cx, const double *__restrict__ cy,
+                                                     const double *__restrict__ cb, const double *__restrict__ sb,
+                                                     const double *__restrict__ a, double t, PoroK K,
+                                                     double *__restrict__ blk)
+{
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= npair) return;
+    int lo = 0, hi = nitem - 1;  // last item with it_coff <= g
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (it_coff[mid] <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    const int k = lo, li = it_leaf[k], c = leaves[li];
+    const int tb = pbeg[c], nt = pend[c] - tb;
+    const int64_t e = g - it_coff[k];
+    const int v = (int)(e / nt), i = (int)(e - (int64_t)v * nt);
+    const int sv = it_s0[k] + v;
+    const int nb = noff[li], nn = noff[li + 1] - nb;
+    int r = 0;
+    while (r + 1 < nn && npre[nb + r + 1] <= sv) ++r;
+    const int jsrc = nbeg[nb + r] + (sv - npre[nb + r]);
+    double B[12];
+    elem_block(K, cx[tb + i], cy[tb + i], cx[jsrc], cy[jsrc], cb[jsrc], sb[jsrc], a[jsrc], t, B);
+    double *o = blk + 12 * it_coff[k] + (int64_t)12 * v * nt + i;
+    for (int q = 0; q < 12; ++q) o[(int64_t)q * nt] = B[q];
+}
+
+// Near field from the stored blocks of time levels j0 .. j1-1 (lv[j] the
+// level's blocks): partial (sxx, syy, sxy, p) per target point of every
+// item, in the layout of k_pp2p, which adds the levels beyond the store.
+__global__ __launch_bounds__(PN) void k_pnear(int nitem, const int *__restrict__ it_leaf,
+                                              const int *__restrict__ it_s0, const int *__restrict__ it_s1,
+                                              const int *__restrict__ it_poff, const int64_t *__restrict__ it_coff,
+                                              const int *__restrict__ leaves, const int *__restrict__ pbeg,
+                                              const int *__restrict__ pend, const int *__restrict__ noff,
+                                              const int *__restrict__ nbeg, const int *__restrict__ npre, int n,
+                                              int j0, int j1, const double *const *__restrict__ lv,
+                                              const double *__restrict__ D3, double *__restrict__ part)
+{
+    int k = blockIdx.x;
+    int li = it_leaf[k], s0 = it_s0[k], ns = it_s1[k] - s0;
+    int c = leaves[li];
+    int tb = pbeg[c], nt = pend[c] - tb;
+    int nb = noff[li], nn = noff[li + 1] - nb;
+    int tpt = 1;
+    while (tpt < 16 && tpt * 2 * nt <= PN) tpt *= 2;
+    int tpg = PN / tpt, sub = threadIdx.x & (tpt - 1);
+    const int64_t base = 12 * it_coff[k];
+    double *pk = part + 4 * (size_t)it_poff[k];
+    for (int t0 = 0; t0 < nt; t0 += tpg) {
+        int i = t0 + (int)threadIdx.x / tpt;
+        bool act = i < nt;
+        double o[4] = {0.0, 0.0, 0.0, 0.0};
+        if (act) {
+            int r = 0;
+            for (int v = sub; v < ns; v += tpt) {
+                while (r + 1 < nn && npre[nb + r + 1] <= s0 + v) ++r;  // v ascends
+                int jsrc = nbeg[nb + r] + (s0 + v - npre[nb + r]);
+                const int64_t off = base + (int64_t)12 * v * nt + i;
+                for (int j = j0; j < j1; ++j) {
+                    const double *d = D3 + ((size_t)j * n + jsrc) * 3;
+                    const double d0 = d[0], d1 = d[1], d2 = d[2];
+                    const double *bq = lv[j] + off;
+#pragma unroll
+                    for (int cc = 0; cc < 4; ++cc)
+                        o[cc] += bq[(3 * cc) * nt] * d0 + bq[(3 * cc + 1) * nt] * d1 + bq[(3 * cc + 2) * nt] * d2;
+                }
+            }
+        }
+        for (int w = 1; w < tpt; w <<= 1)
+            for (int cc = 0; cc < 4; ++cc) o[cc] += __shfl_xor(o[cc], w);
+        if (act && sub == 0) {
+            double *pp = pk + 4 * (size_t)i;
+            for (int cc = 0; cc < 4; ++cc) pp[cc] = o[cc];
         }
     }
 }
@@ -615,6 +794,76 @@ void poro_sum(fmddm_ctx *ctx, fmddm_tree *t, int nterm, const std::vector<double
     FM_CHECK_LAUNCH();
 }
 
+// Everything a transient kernel value depends on besides the geometry.
+void medium_key(const fmddm_ctx *ctx, double k[8])
+{
+    const fmddm_poro_params &q = ctx->poro;
+    k[0] = q.nu_u;
+    k[1] = q.alpha;
+    k[2] = q.perm;
+    k[3] = q.visc;
+    k[4] = q.dt;
+    k[5] = ctx->prm.E;
+    k[6] = ctx->prm.nu;
+    k[7] = (double)q.near_cache_bytes;
+}
+
+bool same_key(const double a[8], const double b[8], int nk)
+{
+    for (int k = 0; k < nk; ++k)
+        if (a[k] != b[k]) return false;
+    return true;
+}
+
+constexpr int PN_MAXLEV = 4096;  // stored near-field levels at most
+
+// Makes the near-field blocks of time levels 0 .. min(H, budget) - 1
+// resident, integrating the missing ones, and returns how many are.
+int near_levels(fmddm_ctx *ctx, fmddm_tree *t, int H)
+{
+    double key[8];
+    medium_key(ctx, key);
+    const int64_t per = 96 * std::max<int64_t>(t->near_pairs, 1);
+    if (t->pn_cap < 0 || !same_key(key, t->pn_key, 8)) {
+        for (auto &l : t->pn_lvl) t->bytes -= (int64_t)l->bytes();
+        t->pn_lvl.clear();
+        t->pn_hptr.clear();
+        int64_t budget = ctx->poro.near_cache_bytes;
+        if (budget == 0) {
+            size_t fr = 0, tot = 0;
+            FM_HIP(hipMemGetInfo(&fr, &tot));
+            budget = std::min<int64_t>((int64_t)(fr / 4), (int64_t)32 << 30);
+        }
+        t->pn_cap = budget > 0 ? (int)std::min<int64_t>(budget / per, PN_MAXLEV) : 0;
+        t->pn_hptr.reserve(PN_MAXLEV);
+        if (t->pn_cap > 0 && t->pn_ptr.n < (size_t)PN_MAXLEV) t->pn_ptr.alloc(PN_MAXLEV);
+        for (int k = 0; k < 8; ++k) t->pn_key[k] = key[k];
+    }
+    const int want = std::min(H, t->pn_cap);
+    if ((int)t->pn_lvl.size() >= want) return want;
+    hipStream_t s = ctx->stream;
+    const PoroK K = poro_constants(ctx);
+    const int first = (int)t->pn_lvl.size();
+    for (int j = first; j < want; ++j) {
+        t->pn_lvl.emplace_back(new DBuf<double>());
+        DBuf<double> &b = *t->pn_lvl.back();
+        b.alloc((size_t)12 * std::max<int64_t>(t->near_pairs, 1));
+        t->bytes += (int64_t)b.bytes();
+        t->pn_hptr.push_back(b.p);
+        if (t->near_pairs > 0) {
+            hipLaunchKernelGGL(k_pnear_build, dim3(cdiv(t->near_pairs, 256)), dim3(256), 0, s, t->near_pairs,
+                               t->nitem, t->it_coff.p, t->it_leaf.p, t->it_s0.p, t->dleaves.p, t->cpbeg.p,
+                               t->cpend.p, t->noff.p, t->nbeg.p, t->npre.p, t->scx.p, t->scy.p, t->scb.p,
+                               t->ssb.p, t->sa.p, (j + 1) * ctx->poro.dt, K, b.p);
+            FM_CHECK_LAUNCH();
+        }
+    }
+    FM_HIP(hipMemcpyAsync(t->pn_ptr.p + first, t->pn_hptr.data() + first, (want - first) * sizeof(double *),
+                          hipMemcpyHostToDevice, s));
+    FM_HIP(hipStreamSynchronize(s));
+    return want;
+}
+
 // Schedule and operators of the multipole form for H time levels.
 void poro_fmm_setup(fmddm_ctx *ctx, fmddm_tree *t, int H)
 {
@@ -622,7 +871,9 @@ void poro_fmm_setup(fmddm_ctx *ctx, fmddm_tree *t, int H)
     hipStream_t s = ctx->stream;
     const int p = ctx->prm.p, p2 = p * p, Mq = (4 * p2 + 63) / 64 * 64;
     const fmddm_poro_params &pp = ctx->poro;
-    bool same = t->pf_ready && t->pf_p == p && t->pf_dt == pp.dt;
+    double key[8];
+    medium_key(ctx, key);
+    bool same = t->pf_ready && t->pf_p == p && same_key(key, t->pf_key, 7);
     if (!same) {
         const int ncell = t->ncell;
         std::vector<int> hv(t->nV), hix(ncell), hiy(ncell);
@@ -676,6 +927,7 @@ void poro_fmm_setup(fmddm_ctx *ctx, fmddm_tree *t, int H)
         t->pf_p = p;
         t->pf_Mq = Mq;
         t->pf_dt = pp.dt;
+        for (int k = 0; k < 8; ++k) t->pf_key[k] = key[k];
         t->pf_H = 0;
         t->pf_G.alloc((size_t)ncell * Mq);
         t->pf_G.zero(s);
@@ -711,8 +963,10 @@ void poro_fmm_setup(fmddm_ctx *ctx, fmddm_tree *t, int H)
 
 // out (mode 0: =, 1: -=) the sum over time levels j = 1..H of F_transient(j dt)
 // applied to E[j-1] (3n each, caller order), plus, if drained, the drained
-// elastic part of E[0]; multipole form.
-void poro_fmm_sum(fmddm_ctx *ctx, fmddm_tree *t, int H, const double *E, bool drained, int mode, double *out)
+// elastic part of E[0]; multipole form.  E[j-1] is zero for j <= jlo (the
+// near field skips those levels).
+void poro_fmm_sum(fmddm_ctx *ctx, fmddm_tree *t, int H, const double *E, bool drained, int mode, double *out,
+                  int jlo = 0)
 {
     upload_rules(ctx->device);
     poro_fmm_setup(ctx, t, H);
@@ -734,11 +988,24 @@ void poro_fmm_sum(fmddm_ctx *ctx, fmddm_tree *t, int H, const double *E, bool dr
         fmm_sum_pairs(s, t, t->pf_Z.p, Mq, Mq, t->pf_G.p, Mq);
         fmm_l2p4(ctx, t, t->pf_G.p, Mq, t->pf_far.p);
     }
-    hipLaunchKernelGGL(k_pp2p, dim3(t->nitem), dim3(PN), 0, s, t->nitem, t->it_leaf.p, t->it_s0.p, t->it_s1.p,
-                       t->it_poff.p, t->dleaves.p, t->cpbeg.p, t->cpend.p, t->noff.p, t->nbeg.p, t->npre.p,
-                       t->scx.p, t->scy.p, t->scb.p, t->ssb.p, t->sa.p, n, H, ctx->poro.dt, t->pf_D3.p, K,
-                       t->pf_near.p);
-    FM_CHECK_LAUNCH();
+    // near field: stored levels jlo .. Hc-1 as block-sparse products, the
+    // rest integrated here
+    const int Hc = near_levels(ctx, t, H);
+    const bool stored = Hc > jlo;
+    if (stored) {
+        hipLaunchKernelGGL(k_pnear, dim3(t->nitem), dim3(PN), 0, s, t->nitem, t->it_leaf.p, t->it_s0.p,
+                           t->it_s1.p, t->it_poff.p, t->it_coff.p, t->dleaves.p, t->cpbeg.p, t->cpend.p, t->noff.p,
+                           t->nbeg.p, t->npre.p, n, jlo, Hc, (const double *const *)t->pn_ptr.p, t->pf_D3.p,
+                           t->pf_near.p);
+        FM_CHECK_LAUNCH();
+    }
+    if (Hc < H || !stored) {
+        hipLaunchKernelGGL(k_pp2p, dim3(t->nitem), dim3(PN), 0, s, t->nitem, t->it_leaf.p, t->it_s0.p, t->it_s1.p,
+                           t->it_poff.p, t->dleaves.p, t->cpbeg.p, t->cpend.p, t->noff.p, t->nbeg.p, t->npre.p,
+                           t->scx.p, t->scy.p, t->scb.p, t->ssb.p, t->sa.p, n, std::max(jlo, Hc), H,
+                           ctx->poro.dt, t->pf_D3.p, K, stored ? 1 : 0, t->pf_near.p);
+        FM_CHECK_LAUNCH();
+    }
     const double *o2 = nullptr;
     if (drained) {
         hipLaunchKernelGGL(k_take2, dim3(cdiv(n, 256)), dim3(256), 0, s, n, E, t->pf_D2.p);
@@ -778,7 +1045,7 @@ void poro_apply(fmddm_ctx *ctx, fmddm_tree *t, int lag, const double *D, double 
         hipLaunchKernelGGL(k_scale_copy, dim3(cdiv(m3, 256)), dim3(256), 0, s, m3, 1.0, D,
                            t->poro_E.p + (size_t)lag * m3);
         FM_CHECK_LAUNCH();
-        poro_fmm_sum(ctx, t, H, t->poro_E.p, false, 0, out);
+        poro_fmm_sum(ctx, t, H, t->poro_E.p, false, 0, out, lag - 1);
         return;
     }
     // terms (t1, D) and (t0, -D): the drained parts cancel

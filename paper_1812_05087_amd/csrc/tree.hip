@@ -718,7 +718,8 @@ void build_tree(fmddm_ctx *ctx, fmddm_tree *t, int64_t n64, const double *x1, co
         up(t->aidx, aidx);
         // near-field work items and the leaf of every point
         std::vector<int> it_leaf, it_s0, it_s1, it_poff, lk_off(t->nleaf + 1, 0), tleaf(n, -1);
-        int64_t poff = 0;
+        std::vector<int64_t> it_coff;  // pairs (target, source) before each item
+        int64_t poff = 0, coff = 0;
         for (int i = 0; i < t->nleaf; ++i) {
             int c = t->leaves[i];
             int nt = he[c] - hb[c];
@@ -730,18 +731,24 @@ void build_tree(fmddm_ctx *ctx, fmddm_tree *t, int64_t n64, const double *x1, co
                 it_s0.push_back(s0);
                 it_s1.push_back(s1);
                 it_poff.push_back((int)poff);
+                it_coff.push_back(coff);
                 poff += nt;
+                coff += (int64_t)nt * (s1 - s0);
                 s0 = s1;
             } while (s0 < ntot[i]);
             lk_off[i + 1] = (int)it_leaf.size();
         }
         if (poff > (int64_t)1 << 30) throw Error{FMDDM_EINVAL, "near-field partials too large"};
+        if (coff != t->near_pairs) throw Error{FMDDM_EDEVICE, "near-field schedule does not cover the near pairs"};
         t->nitem = (int)it_leaf.size();
         t->npartial = poff;
         up(t->it_leaf, it_leaf);
         up(t->it_s0, it_s0);
         up(t->it_s1, it_s1);
         up(t->it_poff, it_poff);
+        t->it_coff.alloc(it_coff.size());
+        if (!it_coff.empty())
+            FM_HIP(hipMemcpyAsync(t->it_coff.p, it_coff.data(), it_coff.size() * 8, hipMemcpyHostToDevice, s));
         up(t->lk_off, lk_off);
         up(t->tleaf, tleaf);
         FM_HIP(hipStreamSynchronize(s));

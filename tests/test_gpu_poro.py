@@ -271,3 +271,67 @@ def test_poro_full_size_sampled_rows():
     e0, eh = cmp(y0, ref0), cmp(yh - b[idx], refh - b[idx])
     print(f"N=20000 poro FMM vs oracle rows: lhs {e0:.2e}, history {eh:.2e}")
     assert e0 <= 1e-6 and eh <= 1e-6, (e0, eh)
+
+
+def test_poro_near_cache():
+    """The resident near-field blocks (each time level integrated once, then
+    block-sparse products) against on-the-fly integration at every product:
+    the same element integrals summed in another order, so the products
+    agree to 1e-12 of the largest entry of each response kind.  Budgets: no
+    cache, two levels (the lag-4 product and the 6-level history mix stored
+    and integrated levels) and the default.  A second call on the stored
+    blocks repeats the first bit for bit, and a new medium (another Biot
+    coefficient) rebuilds both the blocks and the multipole operators."""
+    wl = W.well_cluster(n_frac=5, elems=200, half_length=20.0, spacing=10.0)
+    n3 = 3 * wl.n
+    rng = np.random.default_rng(11)
+    scale = np.tile([1e-4, 1e-4, 1e-10], wl.n)
+    D = dev(rng.standard_normal(n3) * scale)
+    hist = dev(np.concatenate([rng.standard_normal(n3) * scale for _ in range(5)]))
+
+    def products(prob):
+        outs = []
+        for lag in (0, 2, 4):
+            o = torch.zeros(n3, dtype=torch.float64, device="cuda")
+            F.fmddm_poro_apply(prob.ctx, prob.tree, lag, D, o)
+            outs.append(o.cpu().numpy())
+        r = torch.zeros(n3, dtype=torch.float64, device="cuda")
+        F.fmddm_add_history(prob.ctx, prob.tree, 6, hist, r)
+        outs.append(r.cpu().numpy())
+        return outs
+
+    def problem(budget, alpha=MED["alpha"]):
+        prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=MED["E"], nu=MED["nu"], p=12, leaf=32)
+        F.fmddm_poro_set(prob.ctx, MED["nuu"], alpha, MED["perm"], MED["visc"], DT, P0,
+                         mode=F.FMDDM_APPLY_FMM, near_cache_bytes=budget)
+        return prob
+
+    prob = problem(-1)
+    ref = products(prob)
+    pairs = F.fmddm_tree_get_info(prob.ctx, prob.tree)["near_pairs"]
+    prob.close()
+    assert pairs > 0
+    for budget in (2 * 96 * pairs, 0):
+        prob = problem(budget)
+        try:
+            first = products(prob)
+            again = products(prob)
+            for k, (a, b) in enumerate(zip(first, ref)):
+                e = cmp(a, b)
+                print(f"near cache budget {budget}: product {k} vs on the fly {e:.2e}")
+                assert e <= 1e-12, (budget, k, e)
+            for a, b in zip(again, first):
+                assert np.array_equal(a, b)
+            if budget == 0:
+                F.fmddm_poro_set(prob.ctx, MED["nuu"], 0.6, MED["perm"], MED["visc"], DT, P0,
+                                 mode=F.FMDDM_APPLY_FMM)
+                changed = products(prob)
+        finally:
+            prob.close()
+    prob = problem(-1, alpha=0.6)
+    ref2 = products(prob)
+    prob.close()
+    for k, (a, b) in enumerate(zip(changed, ref2)):
+        e = cmp(a, b)
+        print(f"new medium: product {k} vs on the fly {e:.2e}")
+        assert e <= 1e-12, (k, e)
