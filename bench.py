@@ -368,23 +368,23 @@ def precision_leg(F, W, steps, tune, leaf, p, solve_tol=1e-8, target_err=1e-6):
     return out
 
 
-def march_leg(F, W, elems, steps, p=10):
+def march_leg(F, W, elems, steps, p=10, restart=100):
     """A full poroelastic time march (the horizontal-well example's shape,
     Section 5.2.1): 5 fractures of `elems` 0.2 m elements 10 m apart, `steps`
     steps of 60 s, every step's history sum and GMRES solve (tol 1e-6,
-    block-Jacobi, restart 100) on the multipole operators."""
+    block-Jacobi, the given restart) on the multipole operators."""
     import torch
     wl = W.well_cluster(n_frac=5, elems=elems, half_length=0.1 * elems, spacing=10.0)
     n3 = 3 * wl.n
     prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=20e9, nu=0.2, p=p, leaf=32, m2l=1, m2l_tol=1e-10, tol=1e-6,
-                     restart=100, maxit=5000, precond=F.FMDDM_PRECOND_BLOCK)
+                     restart=restart, maxit=20000, precond=F.FMDDM_PRECOND_BLOCK)
     F.fmddm_poro_set(prob.ctx, 0.35, 0.8, 1e-18, 1e-3, 60.0, 48.26e6, mode=F.FMDDM_APPLY_FMM)
     b0 = torch.zeros(n3, dtype=torch.float64, device="cuda")
     F.fmddm_poro_rhs(prob.ctx, prob.tree, torch.as_tensor(wl.pressure).cuda(), wl.SH, wl.Sh, b0)
     hist = torch.zeros(steps * n3, dtype=torch.float64, device="cuda")
     D = torch.zeros(n3, dtype=torch.float64, device="cuda")
     th = tsv = 0.0
-    its, worst = 0, 0.0
+    its, worst, per_step = 0, 0.0, []
     torch.cuda.synchronize()
     t_all = time.perf_counter()
     for h in range(1, steps + 1):
@@ -402,12 +402,16 @@ def march_leg(F, W, elems, steps, p=10):
         th += t1 - t0
         tsv += t2 - t1
         its += info["iters"]
+        per_step.append(info["iters"])
         worst = max(worst, info["relres"])
+        if wl.n > 5000:
+            print(f"march step {h}: {info['iters']} products, {t2 - t0:.2f} s", file=sys.stderr, flush=True)
     total = time.perf_counter() - t_all
     Dm = D.cpu().numpy().reshape(-1, 3)
     mid = Dm[2 * elems: 3 * elems]
     prob.close()
     return {"workload": f"well cluster 5 x {elems} elements (N={wl.n}), {steps} steps of 60 s", "p": p,
+            "restart": restart, "gmres_products_per_step": per_step,
             "total_s": total, "history_s": th, "solve_s": tsv, "gmres_products": its,
             "max_step_relres": worst,
             "middle_fracture_max_shear_over_opening": float(np.abs(mid[:, 0]).max() / np.abs(Dm[:, 1]).max())}
@@ -454,6 +458,7 @@ def main():
     ap.add_argument("--march-elems", type=int, default=400)
     ap.add_argument("--march-steps", type=int, default=50,
                     help="poroelastic time steps of the full-march leg (0 skips it)")
+    ap.add_argument("--march-restart", type=int, default=100)
     ap.add_argument("--precision-steps", type=int, default=20,
                     help="products timed per precision at N=200000 (0 skips the mixed-precision leg)")
     ap.add_argument("--precision-no-tune", action="store_true")
@@ -602,7 +607,7 @@ def main():
     if args.history_elems > 0:
         line["history"] = history_leg(F, W, args.history_elems, args.history_steps)
     if args.march_steps > 0:
-        line["march"] = march_leg(F, W, args.march_elems, args.march_steps)
+        line["march"] = march_leg(F, W, args.march_elems, args.march_steps, restart=args.march_restart)
     if args.precision_steps > 0:
         line["mixed_precision"] = precision_leg(F, W, args.precision_steps, not args.precision_no_tune,
                                                 args.precision_leaf, args.precision_p)

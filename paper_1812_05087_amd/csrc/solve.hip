@@ -48,13 +48,14 @@ __device__ double block_sum(double v, double *red)
     return r;
 }
 
-// Dot products V_i . w (i < k) in two fixed-order stages.  Stage 1: block c
-// takes the chunk [c DCH, (c+1) DCH) of the vectors, stages w's chunk in
-// LDS, and each of its four waves forms the chunk's partial dot for
-// i = wave, wave + 4, ... (lanes stride the chunk, then a shuffle tree);
-// part[i * nchunk + c].  Stage 2: one block per i sums the partials in
-// chunk order.  The vectors are read once in total, over m / DCH blocks.
-constexpr int DCH = 1024;
+// Dot products V_i . w (i < k) in two fixed-order stages.  Stage 1: block
+// (c, g) takes the chunk [c DCH, (c+1) DCH) of vectors g DKG .. g DKG +
+// DKG - 1, stages w's chunk in LDS, and each of its four waves forms the
+// chunk's partial dot for i = g DKG + wave, + 4, ... (lanes stride the
+// chunk, then a shuffle tree); part[i * nchunk + c].  Stage 2: one block
+// per i sums the partials in chunk order.  The vectors are read once in
+// total, over (m / DCH) x (k / DKG) blocks.
+constexpr int DCH = 1024, DKG = 8;
 
 __global__ __launch_bounds__(RT) void k_dots_part(int m, int k, const double *__restrict__ V, int ldv,
                                                   const double *__restrict__ w, int nchunk,
@@ -65,7 +66,8 @@ __global__ __launch_bounds__(RT) void k_dots_part(int m, int k, const double *__
     for (int t = threadIdx.x; t < DCH; t += RT) ws[t] = t < len ? w[t0 + t] : 0.0;
     __syncthreads();
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int i = wave; i < k; i += RT / 64) {
+    const int i1 = min(k, (int)(blockIdx.y + 1) * DKG);
+    for (int i = blockIdx.y * DKG + wave; i < i1; i += RT / 64) {
         const double *v = V + (size_t)i * ldv + t0;
         double s = 0.0;
 #pragma unroll 4
@@ -87,15 +89,32 @@ __global__ __launch_bounds__(RT) void k_dots_sum(int nchunk, const double *__res
     if (threadIdx.x == 0) out[i] = root ? sqrt(s) : s;
 }
 
+// sum_{i<k} h[i] V_i[t] in index order, with VU loads in flight
+constexpr int VU = 8;
+
+__device__ __forceinline__ double vcomb(int k, const double *__restrict__ h, const double *__restrict__ V,
+                                        int ldv, int t)
+{
+    double s = 0.0;
+    int i = 0;
+    for (; i + VU <= k; i += VU) {
+        double v[VU];
+#pragma unroll
+        for (int u = 0; u < VU; ++u) v[u] = V[(size_t)(i + u) * ldv + t];
+#pragma unroll
+        for (int u = 0; u < VU; ++u) s += h[i + u] * v[u];
+    }
+    for (; i < k; ++i) s += h[i] * V[(size_t)i * ldv + t];
+    return s;
+}
+
 // w += sign * sum_{i<k} h[i] V_i
 __global__ void k_vupdate(int m, int k, const double *__restrict__ V, int ldv,
                           const double *__restrict__ h, double sign, double *__restrict__ w)
 {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= m) return;
-    double s = 0.0;
-    for (int i = 0; i < k; ++i) s += h[i] * V[(size_t)i * ldv + t];
-    w[t] += sign * s;
+    w[t] += sign * vcomb(k, h, V, ldv, t);
 }
 
 
@@ -213,9 +232,7 @@ __global__ __launch_bounds__(256) void k_vupdate_sum(int m, int k, const double 
     int t = blockIdx.x * RT + threadIdx.x;
     double wt = 0.0;
     if (t < m) {
-        double s = 0.0;
-        for (int i = 0; i < k; ++i) s += hs[i] * V[(size_t)i * ldv + t];
-        wt = w[t] + sign * s;
+        wt = w[t] + sign * vcomb(k, hs, V, ldv, t);
         w[t] = wt;
     }
     if (npart) {
@@ -266,7 +283,7 @@ __global__ void k_sif(const double *__restrict__ D, const double *__restrict__ a
 void dots(hipStream_t st, int m, int k, const double *V, int ldv, const double *w, double *part, double *out)
 {
     int nchunk = cdiv(m, DCH);
-    hipLaunchKernelGGL(k_dots_part, dim3(nchunk), dim3(RT), 0, st, m, k, V, ldv, w, nchunk, part);
+    hipLaunchKernelGGL(k_dots_part, dim3(nchunk, cdiv(k, DKG)), dim3(RT), 0, st, m, k, V, ldv, w, nchunk, part);
     hipLaunchKernelGGL(k_dots_sum, dim3(k), dim3(RT), 0, st, nchunk, part, 0, out);
     FM_CHECK_LAUNCH();
 }
@@ -462,10 +479,12 @@ void GmresRun::step_body(int jj)
         // scaling and rotation
         const size_t hsm = (size_t)(jj + 1) * 8;
         double *np = t->gm_part.p + (size_t)(m + 1) * nchunk;  // gb norm partials after the dot partials
-        hipLaunchKernelGGL(k_dots_part, dim3(nchunk), dim3(RT), 0, st, n2, jj + 1, V, ldv, w, nchunk, t->gm_part.p);
+        hipLaunchKernelGGL(k_dots_part, dim3(nchunk, cdiv(jj + 1, DKG)), dim3(RT), 0, st, n2, jj + 1, V, ldv, w,
+                           nchunk, t->gm_part.p);
         hipLaunchKernelGGL(k_vupdate_sum, dim3(gb), dim3(RT), hsm, st, n2, jj + 1, V, ldv, t->gm_part.p, nchunk,
                            -1.0, w, sc + s.h1(), (double *)nullptr);
-        hipLaunchKernelGGL(k_dots_part, dim3(nchunk), dim3(RT), 0, st, n2, jj + 1, V, ldv, w, nchunk, t->gm_part.p);
+        hipLaunchKernelGGL(k_dots_part, dim3(nchunk, cdiv(jj + 1, DKG)), dim3(RT), 0, st, n2, jj + 1, V, ldv, w,
+                           nchunk, t->gm_part.p);
         hipLaunchKernelGGL(k_vupdate_sum, dim3(gb), dim3(RT), hsm, st, n2, jj + 1, V, ldv, t->gm_part.p, nchunk,
                            -1.0, w, sc + s.h2(), np);
         hipLaunchKernelGGL(k_scale_givens, dim3(std::min(gb, 64)), dim3(RT), 0, st, n2, w, np, gb, vn, s, jj, sc);
