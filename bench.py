@@ -455,10 +455,10 @@ def main():
                     help="only copy 256 MiB device-to-device 5 times (reference for HBM byte counters)")
     ap.add_argument("--history-elems", type=int, default=4000)
     ap.add_argument("--history-steps", type=int, default=10)
-    ap.add_argument("--march-elems", type=int, default=400)
+    ap.add_argument("--march-elems", type=int, default=4000)
     ap.add_argument("--march-steps", type=int, default=50,
                     help="poroelastic time steps of the full-march leg (0 skips it)")
-    ap.add_argument("--march-restart", type=int, default=100)
+    ap.add_argument("--march-restart", type=int, default=300)
     ap.add_argument("--precision-steps", type=int, default=20,
                     help="products timed per precision at N=200000 (0 skips the mixed-precision leg)")
     ap.add_argument("--precision-no-tune", action="store_true")
