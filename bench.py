@@ -167,8 +167,9 @@ def serving_leg(F, W, count, slots, load):
     1-10 load steps, tol 1e-6): the one-at-a-time service rate, the batched
     saturation rate, and a Poisson stream at `load` x the one-at-a-time rate
     served batched and one at a time; GMRES with block-Jacobi
-    preconditioning, and the batched saturation rate without it (the
-    paper's plain GMRES) for comparison."""
+    preconditioning, and the batched saturation rates without it (the
+    paper's plain GMRES) and with the two-level preconditioner (fewer
+    products, but a coarse LU per request) for comparison."""
     reqs = W.serving_stream(5, count)
     wls = [r.workload() for r in reqs]
     zero = [0.0] * count
@@ -181,6 +182,7 @@ def serving_leg(F, W, count, slots, load):
     span_o, lat_o, _ = serve_run(F, wls, reqs, 1, arr)
     span_np, _, iters_np = serve_run(F, wls, reqs, slots, zero, precond=0)
     span_32, _, iters_32 = serve_run(F, wls, reqs, slots, zero, precision=F.FMDDM_PREC_FP32)
+    span_2l, _, iters_2l = serve_run(F, wls, reqs, slots, zero, precond=F.FMDDM_PRECOND_TWO_LEVEL)
     pct = lambda a, q: float(np.percentile(a, q))
     return {
         "requests": count, "slots": slots, "elements_total": int(sum(w.n for w in wls)),
@@ -191,6 +193,7 @@ def serving_leg(F, W, count, slots, load):
                    "exact_product_at_or_below_elements": SERVE_PARAMS["direct_below"]},
         "unpreconditioned": {"batched_saturated_solves_per_s": count / span_np,
                              "gmres_products_total": iters_np},
+        "two_level": {"batched_saturated_solves_per_s": count / span_2l, "gmres_products_total": iters_2l},
         "fp32_products": {"batched_saturated_solves_per_s": count / span_32, "gmres_products_total": iters_32,
                           "note": "Arnoldi on FP32-P2P/FP32-M2L products, residuals and stopping test FP64"},
         "one_at_a_time_solves_per_s": rate1,
@@ -270,8 +273,9 @@ def history_leg(F, W, elems, steps, p=10):
 def precision_leg(F, W, steps, tune, leaf, p, solve_tol=1e-8, target_err=1e-6):
     """Mixed precision at N=200000 (2000 random fractures x 100 elements,
     seed 4): autotuned leaf and p for the FP64 product, then products and
-    solves at FP64, FP32 and BF16-M2L on that configuration (block-Jacobi
-    preconditioned GMRES; the FP64 solve also unpreconditioned).  Errors of each
+    solves at FP64, FP32 and BF16-M2L on that configuration (two-level
+    preconditioned GMRES; the FP64 solve also unpreconditioned and with
+    block-Jacobi alone).  Errors of each
     product against the FP64 FMM product and the exact product (on-the-fly
     FP64 on the GPU); each solve reaches tol on the FP64 FMM residual, and
     its exact-operator residual and distance to the FP64 solve are stated."""
@@ -301,7 +305,7 @@ def precision_leg(F, W, steps, tune, leaf, p, solve_tol=1e-8, target_err=1e-6):
     ref = None
     for name, prec in [("fp64", F.FMDDM_PREC_FP64), ("fp32", F.FMDDM_PREC_FP32), ("bf16", F.FMDDM_PREC_BF16)]:
         prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, leaf=leaf, p=p, precision=prec, tol=solve_tol,
-                         precond=F.FMDDM_PRECOND_BLOCK, **common)
+                         precond=F.FMDDM_PRECOND_TWO_LEVEL, **common)
         if D is None:
             D = prob.vec(W.random_vector(9, n))
             b = prob.rhs(wl.pressure, wl.SH, wl.Sh)
@@ -341,6 +345,22 @@ def precision_leg(F, W, steps, tune, leaf, p, solve_tol=1e-8, target_err=1e-6):
             torch.cuda.synchronize()
             out["fp64_unpreconditioned_solve"] = {"solve_s": time.perf_counter() - t0, "solve": info0}
             prob0.close()
+            # the same with block-Jacobi alone (set-up timed apart)
+            prob2 = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, leaf=leaf, p=p, tol=solve_tol,
+                              precond=F.FMDDM_PRECOND_BLOCK, **common)
+            prob2.apply(D, F.FMDDM_APPLY_FMM, o)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x2, info2 = prob2.solve(b)
+            torch.cuda.synchronize()
+            t_first = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            x2, info2 = prob2.solve(b)
+            torch.cuda.synchronize()
+            out["fp64_block_jacobi_solve"] = {"solve_s": time.perf_counter() - t0, "first_solve_s": t_first,
+                                              "solve": info2}
+            x["fp64_block_jacobi"] = x2
+            prob2.close()
         else:
             prob.close()
         res[name] = r
@@ -363,21 +383,28 @@ def precision_leg(F, W, steps, tune, leaf, p, solve_tol=1e-8, target_err=1e-6):
                                                          torch.linalg.norm(x["fp64"]))
         res[name]["matvecs_over_fp64"] = res[name]["matvecs_per_s"] / res["fp64"]["matvecs_per_s"]
         res[name]["solve_speedup_over_fp64"] = res["fp64"]["solve_s"] / res[name]["solve_s"]
+    if "fp64_block_jacobi" in x:
+        tl = out["fp64_block_jacobi_solve"]
+        ax = ref.apply(x["fp64_block_jacobi"], F.FMDDM_APPLY_DIRECT)
+        tl["solution_exact_residual"] = float(torch.linalg.norm(b - ax)) / bn
+        tl["solution_diff_vs_fp64_solve"] = float(torch.linalg.norm(x["fp64_block_jacobi"] - x["fp64"]) /
+                                                  torch.linalg.norm(x["fp64"]))
     ref.close()
     out["precisions"] = res
     return out
 
 
-def march_leg(F, W, elems, steps, p=10, restart=100):
+def march_leg(F, W, elems, steps, p=10, restart=100, precond=2):
     """A full poroelastic time march (the horizontal-well example's shape,
     Section 5.2.1): 5 fractures of `elems` 0.2 m elements 10 m apart, `steps`
     steps of 60 s, every step's history sum and GMRES solve (tol 1e-6,
-    block-Jacobi, the given restart) on the multipole operators."""
+    the given restart and preconditioner: 2 two-level, 1 block-Jacobi) on
+    the multipole operators."""
     import torch
     wl = W.well_cluster(n_frac=5, elems=elems, half_length=0.1 * elems, spacing=10.0)
     n3 = 3 * wl.n
     prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=20e9, nu=0.2, p=p, leaf=32, m2l=1, m2l_tol=1e-10, tol=1e-6,
-                     restart=restart, maxit=20000, precond=F.FMDDM_PRECOND_BLOCK)
+                     restart=restart, maxit=20000, precond=precond)
     F.fmddm_poro_set(prob.ctx, 0.35, 0.8, 1e-18, 1e-3, 60.0, 48.26e6, mode=F.FMDDM_APPLY_FMM)
     b0 = torch.zeros(n3, dtype=torch.float64, device="cuda")
     F.fmddm_poro_rhs(prob.ctx, prob.tree, torch.as_tensor(wl.pressure).cuda(), wl.SH, wl.Sh, b0)
@@ -411,10 +438,56 @@ def march_leg(F, W, elems, steps, p=10, restart=100):
     mid = Dm[2 * elems: 3 * elems]
     prob.close()
     return {"workload": f"well cluster 5 x {elems} elements (N={wl.n}), {steps} steps of 60 s", "p": p,
-            "restart": restart, "gmres_products_per_step": per_step,
+            "restart": restart, "precond": {1: "block-Jacobi", 2: "two-level"}[precond],
+            "gmres_products_per_step": per_step,
             "total_s": total, "history_s": th, "solve_s": tsv, "gmres_products": its,
             "max_step_relres": worst,
             "middle_fracture_max_shear_over_opening": float(np.abs(mid[:, 0]).max() / np.abs(Dm[:, 1]).max())}
+
+
+def p_sweep_leg(F, W, ps, reps=50):
+    """Accuracy against time over the number of Chebyshev nodes per dimension
+    (the paper compares 3 and 6, Section 5.2): the C2 product (SVD M2L at
+    1e-12, leaf 32) against the exact on-the-fly product, and the C3
+    left-hand side (well cluster, FMM on both the product and the history)
+    at N = 2000 against its exact evaluation, timed at N = 20 000."""
+    import torch
+
+    def timed(apply, reps):
+        apply()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            apply()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps * 1e3
+
+    out = {"c2": [], "c3_lhs": []}
+    wl = W.c2()
+    ref = None
+    for p in ps:
+        prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=wl.E, nu=wl.nu, leaf=32, p=p, m2l=F.FMDDM_M2L_SVD,
+                         m2l_tol=1e-12)
+        D = prob.vec(W.random_vector(5, wl.n))
+        o = prob.vec()
+        if ref is None:
+            r = prob.vec()
+            prob.apply(D, F.FMDDM_APPLY_DIRECT, r)
+            ref = r.cpu().numpy()
+        ms = timed(lambda: prob.apply(D, F.FMDDM_APPLY_FMM, o), reps)
+        y = o.cpu().numpy()
+        out["c2"].append({"p": p, "ms_per_product": ms,
+                          "rel_err_vs_exact": float(np.linalg.norm(y - ref) / np.linalg.norm(ref))})
+        prob.close()
+    rel = lambda a, b: float(max(np.abs(a[k::3] - b[k::3]).max() / max(np.abs(b[k::3]).max(), 1e-300)
+                                 for k in range(3)))
+    for p in [q for q in ps if q <= 16]:
+        _, _, _, o_f, _, _ = history_run(F, W, 400, 2, F.FMDDM_APPLY_FMM, p)
+        if p == ps[0]:
+            _, _, _, o_e, _, _ = history_run(F, W, 400, 2, F.FMDDM_APPLY_DIRECT, p)
+        _, tl, _, _, _, _ = history_run(F, W, 4000, 2, F.FMDDM_APPLY_FMM, p)
+        out["c3_lhs"].append({"p": p, "lhs_ms_N20000": tl * 1e3, "rel_err_vs_exact_N2000": rel(o_f, o_e)})
+    return out
 
 
 def cpu_baseline(wl, D, seconds):
@@ -458,7 +531,10 @@ def main():
     ap.add_argument("--march-elems", type=int, default=4000)
     ap.add_argument("--march-steps", type=int, default=50,
                     help="poroelastic time steps of the full-march leg (0 skips it)")
-    ap.add_argument("--march-restart", type=int, default=300)
+    ap.add_argument("--march-restart", type=int, default=100)
+    ap.add_argument("--march-precond", type=int, default=2, choices=[1, 2])
+    ap.add_argument("--p-sweep", type=str, default="",
+                    help="comma-separated Chebyshev orders for the accuracy/time sweep (off by default)")
     ap.add_argument("--precision-steps", type=int, default=20,
                     help="products timed per precision at N=200000 (0 skips the mixed-precision leg)")
     ap.add_argument("--precision-no-tune", action="store_true")
@@ -606,8 +682,11 @@ def main():
         line["serving"] = serving_leg(F, W, args.serve_requests, args.serve_slots, args.serve_load)
     if args.history_elems > 0:
         line["history"] = history_leg(F, W, args.history_elems, args.history_steps)
+    if args.p_sweep:
+        line["p_sweep"] = p_sweep_leg(F, W, [int(q) for q in args.p_sweep.split(",")])
     if args.march_steps > 0:
-        line["march"] = march_leg(F, W, args.march_elems, args.march_steps, restart=args.march_restart)
+        line["march"] = march_leg(F, W, args.march_elems, args.march_steps, restart=args.march_restart,
+                                  precond=args.march_precond)
     if args.precision_steps > 0:
         line["mixed_precision"] = precision_leg(F, W, args.precision_steps, not args.precision_no_tune,
                                                 args.precision_leaf, args.precision_p)

@@ -88,11 +88,18 @@ typedef enum {
  * groups of neighbouring elements (runs in tree order within one leaf):
  * at most 32 elements for the elastic system (8 (2m)^2 bytes per group of
  * m), at most 21 for the poroelastic left-hand side F(dt) (8 (3m)^2 bytes;
- * rebuilt when the medium or dt changes).  Built once per tree.  It
- * changes the iteration count, not the solution. */
+ * rebuilt when the medium or dt changes).  TWO_LEVEL adds a coarse level
+ * for the long-wavelength modes of long fractures (8 (2 nc)^2 bytes for nc
+ * aggregates, nc <= about 1024; the poroelastic one uses the undrained
+ * modulus).  Built once per tree.  It changes the iteration count, not the
+ * solution. */
 typedef enum {
     FMDDM_PRECOND_NONE = 0,
-    FMDDM_PRECOND_BLOCK = 1
+    FMDDM_PRECOND_BLOCK = 1,
+    FMDDM_PRECOND_TWO_LEVEL = 2  /* block-Jacobi plus a coarse level: aggregates of up to
+                                    max(16, n / 1024) consecutive collinear elements (caller
+                                    order) taken as long elements, their coarse matrix R A P
+                                    inverted once per tree; M^-1 r = B^-1 r + P A_c^-1 R r */
 } fmddm_precond;
 
 typedef struct {

@@ -24,7 +24,7 @@ FMDDM_EINVAL, FMDDM_ENOMEM, FMDDM_EDEVICE, FMDDM_EGEOM, FMDDM_EUNSUPPORTED = -1,
 FMDDM_APPLY_FMM, FMDDM_APPLY_DIRECT, FMDDM_APPLY_DENSE = 0, 1, 2
 FMDDM_M2L_DENSE, FMDDM_M2L_SVD = 0, 1
 FMDDM_PREC_FP64, FMDDM_PREC_FP32, FMDDM_PREC_BF16 = 0, 1, 2
-FMDDM_PRECOND_NONE, FMDDM_PRECOND_BLOCK = 0, 1
+FMDDM_PRECOND_NONE, FMDDM_PRECOND_BLOCK, FMDDM_PRECOND_TWO_LEVEL = 0, 1, 2
 LIST_U, LIST_V, LIST_W, LIST_X = 0, 1, 2, 3
 
 EXPORTED = [

@@ -51,7 +51,9 @@ const char *check_params(const fmddm_params *p)
     if (!(p->tol >= 0.0)) return "tol must be >= 0";
     if (p->precision < FMDDM_PREC_FP64 || p->precision > FMDDM_PREC_BF16) return "unknown precision";
     if (p->use_graphs != 0 && p->use_graphs != 1) return "use_graphs must be 0 or 1";
-    if (p->precond != FMDDM_PRECOND_NONE && p->precond != FMDDM_PRECOND_BLOCK) return "unknown precond";
+    if (p->precond != FMDDM_PRECOND_NONE && p->precond != FMDDM_PRECOND_BLOCK &&
+        p->precond != FMDDM_PRECOND_TWO_LEVEL)
+        return "unknown precond";
     if (p->m2l_tiles < 0 || p->m2l_tiles > 3) return "m2l_tiles must lie in [0, 3]";
     if (p->direct_below < 0) return "direct_below must be >= 0";
     return nullptr;

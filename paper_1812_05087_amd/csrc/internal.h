@@ -88,6 +88,17 @@ struct PcBlocks {
     double key[6] = {0, 0, 0, 0, 0, 0};
 };
 
+// Coarse level of the two-level preconditioner: aggregates of consecutive
+// collinear elements (caller order), each taken as one long element; the
+// explicit inverse of their coarse matrix R A P (2 nc x 2 nc, row-major,
+// traction components from shear/normal DDs).
+struct PcCoarse {
+    int nc = 0;                // aggregates (0: not built)
+    DBuf<int> abeg;            // first element of each aggregate, nc + 1 entries
+    DBuf<double> ainv, rc, yc;
+    double key[6] = {0, 0, 0, 0, 0, 0};
+};
+
 struct M2LOps {
     int ready = 0;
     int mode = 0;           // fmddm_m2l_mode
@@ -222,6 +233,7 @@ struct fmddm_tree {
     int64_t gm_len = 0;
     // block-Jacobi preconditioners of the elastic and poroelastic systems
     fmddm::PcBlocks pc, ppc;
+    fmddm::PcCoarse pcc, ppcc;  // coarse levels (two-level preconditioning)
     fmddm::DBuf<double> gm_z;          // preconditioned basis vector M^-1 v_j
     // poroelastic workspace: chunk partials, term times, term vectors
     fmddm::DBuf<double> poro_part, poro_times, poro_E;
@@ -331,9 +343,11 @@ struct GmresRun {
     void enqueue_residual();
     void enqueue_step();
     void step_body(int jj);
+    void precond(const double *in, int acc, double *out);  // out (+)= M^-1 in
     void post(int slot, int count);
     bool eager_done = false;       // a first step ran uncaptured (lazy set-up done)
     bool pc = false;               // right preconditioning by the block-Jacobi inverse
+    bool pc2 = false;              // ... plus the coarse level
 };
 void apply_mode(fmddm_ctx *ctx, fmddm_tree *t, int mode, const double *D, double *out);
 // apply mode of the poroelastic left-hand side F(dt) (3 unknowns per element)
@@ -349,6 +363,11 @@ void pc_setup(fmddm_ctx *ctx, fmddm_tree *t);
 void pc_groups(fmddm_ctx *ctx, fmddm_tree *t, int maxm, int nc, PcBlocks &B);
 // out = M^-1 in (acc = 0) or out += M^-1 in (acc = 1), caller order
 void pc_apply(fmddm_ctx *ctx, fmddm_tree *t, const PcBlocks &B, const double *in, int acc, double *out);
+// coarse level for the elastic (poro = false) or poroelastic system
+void pc_coarse_setup(fmddm_ctx *ctx, fmddm_tree *t, bool poro);
+// out += P A_c^-1 R in: coarse correction added into out (nc unknowns per
+// element in caller order)
+void pc_coarse_add(fmddm_ctx *ctx, fmddm_tree *t, const PcCoarse &C, int ncomp, const double *in, double *out);
 // poro.hip
 void poro_apply(fmddm_ctx *ctx, fmddm_tree *t, int lag, const double *D, double *out);
 void poro_history(fmddm_ctx *ctx, fmddm_tree *t, int h, const double *Dh, double *rhs);

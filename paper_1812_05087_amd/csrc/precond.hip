@@ -17,6 +17,9 @@
 #include "gj.h"
 #include "internal.h"
 
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
 #include <cmath>
 #include <vector>
 
@@ -93,6 +96,78 @@ __global__ __launch_bounds__(64) void k_pc_apply(int nblk, int nc, const int *__
     }
 }
 
+// Coarse matrix R A P, one thread per (receiver aggregate I, source
+// aggregate J): A[2I + r][2J + c] = mean over I's elements of traction r
+// (0 shear, 1 normal) at their midpoints from a unit DD c on all of J's
+// elements.  J is a straight run, so that DD is one long element's; I's
+// elements share its direction, so the mean of their tractions is the
+// traction of the mean stress.  gc of the modulus the coarse scale sees.
+__global__ void k_coarse_build(int nc, const int *__restrict__ abeg, const double *__restrict__ ex,
+                               const double *__restrict__ ey, const double *__restrict__ ccx,
+                               const double *__restrict__ ccy, const double *__restrict__ ccb,
+                               const double *__restrict__ csb, const double *__restrict__ ca, double gc,
+                               double *__restrict__ A)
+{
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (int64_t)nc * nc) return;
+    int I = (int)(g / nc), J = (int)(g - (int64_t)I * nc);
+    const int e0 = abeg[I], e1 = abeg[I + 1];
+    const size_t ld = 2 * (size_t)nc;
+    for (int c = 0; c < 2; ++c) {
+        double sxx = 0.0, syy = 0.0, sxy = 0.0, ts, tn;
+        for (int e = e0; e < e1; ++e)
+            elem_stress_add(ex[e], ey[e], ccx[J], ccy[J], ccb[J], csb[J], ca[J], c == 0 ? 1.0 : 0.0,
+                            c == 1 ? 1.0 : 0.0, gc, sxx, syy, sxy);
+        traction(ccb[I], csb[I], sxx, syy, sxy, ts, tn);
+        A[(2 * (size_t)I) * ld + 2 * J + c] = ts / (e1 - e0);
+        A[(2 * (size_t)I + 1) * ld + 2 * J + c] = tn / (e1 - e0);
+    }
+}
+
+// rc[2I + r] = mean over aggregate I's elements of in[ncomp e + r], r < 2
+__global__ void k_coarse_restrict(int nc, int ncomp, const int *__restrict__ abeg, const double *__restrict__ in,
+                                  double *__restrict__ rc)
+{
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= 2 * nc) return;
+    int I = g >> 1, r = g & 1, e0 = abeg[I], e1 = abeg[I + 1];
+    double s = 0.0;
+    for (int e = e0; e < e1; ++e) s += in[(size_t)ncomp * e + r];
+    rc[g] = s / (e1 - e0);
+}
+
+// y = Ainv rc, Ainv row-major (m x m): one wave per row
+__global__ __launch_bounds__(256) void k_coarse_gemv(int m, const double *__restrict__ Ainv,
+                                                     const double *__restrict__ rc, double *__restrict__ y)
+{
+    int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (row >= m) return;
+    const double *a = Ainv + (size_t)row * m;
+    double s = 0.0;
+    for (int c = lane; c < m; c += 64) s += a[c] * rc[c];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) y[row] = s;
+}
+
+// out[ncomp e + r] += y[2 agg(e) + r], r < 2; one thread per aggregate and
+// component, over its elements
+__global__ void k_coarse_prolong(int nc, int ncomp, const int *__restrict__ abeg, const double *__restrict__ y,
+                                 double *__restrict__ out)
+{
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= 2 * nc) return;
+    int I = g >> 1, r = g & 1;
+    double v = y[g];
+    for (int e = abeg[I]; e < abeg[I + 1]; ++e) out[(size_t)ncomp * e + r] += v;
+}
+
+template <typename T>
+void up(hipStream_t s, DBuf<T> &d, const std::vector<T> &h)
+{
+    d.alloc(std::max<size_t>(h.size(), 1));
+    if (!h.empty()) FM_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
 }  // namespace
 
 void pc_groups(fmddm_ctx *ctx, fmddm_tree *t, int maxm, int nc, PcBlocks &B)
@@ -153,6 +228,123 @@ void pc_apply(fmddm_ctx *ctx, fmddm_tree *t, const PcBlocks &B, const double *in
 {
     hipLaunchKernelGGL(k_pc_apply, dim3(B.nblk), dim3(64), 0, ctx->stream, B.nblk, B.nc, B.beg.p, B.cnt.p,
                        B.off.p, t->perm.p, B.inv.p, in, acc, out);
+    FM_CHECK_LAUNCH();
+}
+
+// Two-level preconditioning (an addition to the paper's plain GMRES): the
+// block-Jacobi groups span a few metres, so the long-wavelength modes of
+// long fractures (and of parallel fractures that shield each other) keep
+// the Krylov iteration long.  The coarse level represents them with
+// piecewise-constant DDs over aggregates of consecutive collinear elements
+// of one fracture; an aggregate is a straight run, so the constant-element
+// formulas give the coarse operator A_c = R A P exactly (up to the
+// medium, below).  M^-1 r = B^-1 r + P A_c^-1 R r, with R the mean over an
+// aggregate of the traction residuals and P the constant extension of the
+// coarse DDs: the coarse term alone makes the aggregate means of the
+// residual vanish.  For the
+// poroelastic left-hand side the coarse scale sees the undrained medium
+// (nu_u): the diffusion length of one step is far below an aggregate.
+constexpr int AGG_MIN = 16;      // elements per aggregate, at least
+constexpr int COARSE_MAX = 1024;  // aggregates, about at most
+
+void pc_coarse_setup(fmddm_ctx *ctx, fmddm_tree *t, bool poro)
+{
+    PcCoarse &C = poro ? t->ppcc : t->pcc;
+    const double nu_eff = poro ? ctx->poro.nu_u : ctx->prm.nu;
+    const double key[6] = {ctx->prm.E, ctx->prm.nu, nu_eff, 0, 0, 0};
+    bool same = C.nc > 0;
+    for (int k = 0; k < 6; ++k) same = same && C.key[k] == key[k];
+    if (same) return;
+    hipStream_t s = ctx->stream;
+    const int n = (int)t->n;
+    std::vector<double> x(n), y(n), cb(n), sb(n), a(n);
+    FM_HIP(hipMemcpyAsync(x.data(), t->ocx.p, n * 8, hipMemcpyDeviceToHost, s));
+    FM_HIP(hipMemcpyAsync(y.data(), t->ocy.p, n * 8, hipMemcpyDeviceToHost, s));
+    FM_HIP(hipMemcpyAsync(cb.data(), t->ocb.p, n * 8, hipMemcpyDeviceToHost, s));
+    FM_HIP(hipMemcpyAsync(sb.data(), t->osb.p, n * 8, hipMemcpyDeviceToHost, s));
+    FM_HIP(hipMemcpyAsync(a.data(), t->oa.p, n * 8, hipMemcpyDeviceToHost, s));
+    FM_HIP(hipStreamSynchronize(s));
+    // aggregates: runs in caller order of at most `ag` elements where each
+    // element starts at the previous one's end, in the same direction
+    const int ag = std::max(AGG_MIN, (n + COARSE_MAX - 1) / COARSE_MAX);
+    std::vector<int> abeg;
+    std::vector<double> hx, hy, hcb, hsb, ha;
+    auto close_run = [&](int b, int e) {  // elements [b, e)
+        double x0 = x[b] - a[b] * cb[b], y0 = y[b] - a[b] * sb[b];
+        double x1 = x[e - 1] + a[e - 1] * cb[e - 1], y1 = y[e - 1] + a[e - 1] * sb[e - 1];
+        abeg.push_back(b);
+        hx.push_back(0.5 * (x0 + x1));
+        hy.push_back(0.5 * (y0 + y1));
+        hcb.push_back(cb[b]);
+        hsb.push_back(sb[b]);
+        ha.push_back(0.5 * std::hypot(x1 - x0, y1 - y0));
+    };
+    int b = 0;
+    for (int e = 1; e <= n; ++e) {
+        bool cont = e < n && e - b < ag;
+        if (cont) {
+            double ex = x[e - 1] + a[e - 1] * cb[e - 1], ey = y[e - 1] + a[e - 1] * sb[e - 1];
+            double sx = x[e] - a[e] * cb[e], sy = y[e] - a[e] * sb[e];
+            double tol = 1e-9 * (a[e - 1] + a[e]);
+            cont = std::hypot(ex - sx, ey - sy) <= tol && std::fabs(cb[e] - cb[e - 1]) <= 1e-9 &&
+                   std::fabs(sb[e] - sb[e - 1]) <= 1e-9;
+        }
+        if (!cont) {
+            close_run(b, e);
+            b = e;
+        }
+    }
+    const int nc = (int)hx.size();
+    abeg.push_back(n);
+    const int m = 2 * nc;
+    up(s, C.abeg, abeg);
+    DBuf<double> dx, dy, dcb, dsb, da;
+    up(s, dx, hx);
+    up(s, dy, hy);
+    up(s, dcb, hcb);
+    up(s, dsb, hsb);
+    up(s, da, ha);
+    C.ainv.alloc((size_t)m * m);
+    C.rc.alloc(m);
+    C.yc.alloc(m);
+    const double G = ctx->prm.E / (2.0 * (1.0 + ctx->prm.nu));
+    const double gc = G / (2.0 * M_PI * (1.0 - nu_eff));
+    hipLaunchKernelGGL(k_coarse_build, dim3(cdiv((int64_t)nc * nc, 256)), dim3(256), 0, s, nc, C.abeg.p, t->ocx.p,
+                       t->ocy.p, dx.p, dy.p, dcb.p, dsb.p, da.p, gc, C.ainv.p);
+    FM_CHECK_LAUNCH();
+    // the row-major matrix is its transpose column-major; inverting that in
+    // place leaves the inverse row-major
+    DBuf<int> ipiv, info;
+    ipiv.alloc(m);
+    info.alloc(2);
+    info.zero(s);
+    rocblas_handle h;
+    if (rocblas_create_handle(&h) != rocblas_status_success) throw Error{FMDDM_EDEVICE, "rocblas handle"};
+    rocblas_set_stream(h, s);
+    rocblas_status st = rocsolver_dgetrf(h, m, m, C.ainv.p, m, ipiv.p, info.p);
+    if (st == rocblas_status_success) st = rocsolver_dgetri(h, m, C.ainv.p, m, ipiv.p, info.p + 1);
+    FM_HIP(hipStreamSynchronize(s));
+    rocblas_destroy_handle(h);
+    if (st != rocblas_status_success) throw Error{FMDDM_EDEVICE, "coarse LU failed"};
+    int hinfo[2] = {0, 0};
+    FM_HIP(hipMemcpy(hinfo, info.p, 8, hipMemcpyDeviceToHost));
+    if (hinfo[0] != 0 || hinfo[1] != 0) {
+        C.nc = 0;
+        throw Error{FMDDM_EGEOM, "singular coarse matrix (coincident fractures?)"};
+    }
+    C.nc = nc;
+    for (int k = 0; k < 6; ++k) C.key[k] = key[k];
+    t->bytes += (int64_t)C.ainv.bytes();
+}
+
+void pc_coarse_add(fmddm_ctx *ctx, fmddm_tree *t, const PcCoarse &C, int ncomp, const double *in, double *out)
+{
+    (void)t;
+    hipStream_t s = ctx->stream;
+    const int m = 2 * C.nc;
+    hipLaunchKernelGGL(k_coarse_restrict, dim3(cdiv(m, 256)), dim3(256), 0, s, C.nc, ncomp, C.abeg.p, in, C.rc.p);
+    hipLaunchKernelGGL(k_coarse_gemv, dim3(cdiv(m, 4)), dim3(256), 0, s, m, C.ainv.p, C.rc.p, C.yc.p);
+    hipLaunchKernelGGL(k_coarse_prolong, dim3(cdiv(m, 256)), dim3(256), 0, s, C.nc, ncomp, C.abeg.p, C.yc.p, out);
     FM_CHECK_LAUNCH();
 }
 

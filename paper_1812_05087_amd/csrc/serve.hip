@@ -99,7 +99,8 @@ namespace {
 // field vectors, their compressed forms, split-K partials, the M2L pair
 // results (up to 27 interaction pairs per cell) and the upward-pass
 // partials; with block-Jacobi preconditioning the group inverses (at most
-// (2 x 32)^2 doubles per 32 elements) and one more vector.  Sizes are
+// (2 x 32)^2 doubles per 32 elements) and one more vector, with the two-level
+// one also the coarse inverse.  Sizes are
 // rounded up by the allocator, hence the final 25 %.
 int64_t footprint(const fmddm_params &p, int rank_pad, int64_t n)
 {
@@ -107,10 +108,14 @@ int64_t footprint(const fmddm_params &p, int rank_pad, int64_t n)
     const int64_t rp = p.m2l == FMDDM_M2L_SVD ? rank_pad : Mp;
     const int64_t cells = 4 * n / std::max(1, p.leaf) + 64;
     int64_t per_elem = 8LL * p.p * p.p + 8 * 2 * (p.restart + 4) + 8 * 48;
-    if (p.precond == FMDDM_PRECOND_BLOCK) per_elem += 8 * 128 + 8 * 2 + 16;
+    if (p.precond != FMDDM_PRECOND_NONE) per_elem += 8 * 128 + 8 * 2 + 16;
     int64_t per_cell = 8 * (3 * Mp + 2 * rp + 4 * rp + 27 * rp) + 4 * 64;
     if (p.precision != FMDDM_PREC_FP64) per_cell += 4 * (2 * rp + 4 * rp + 27 * rp);  // FP32 intermediates
     int64_t b = n * per_elem + cells * per_cell + (4 << 20);
+    if (p.precond == FMDDM_PRECOND_TWO_LEVEL) {  // coarse inverse: aggregates of >= 16 elements, <= ~1024 of them
+        const int64_t nc = std::min<int64_t>(n / 16 + 1, 1100);
+        b += 8 * (2 * nc) * (2 * nc) + 8 * 6 * nc;
+    }
     return b + b / 4;
 }
 

@@ -259,15 +259,22 @@ __global__ __launch_bounds__(256) void k_scale_givens(int m, const double *__res
     }
 }
 
-// y = R^{-1} g over the first k columns.
-__global__ void k_backsolve(SW s, int k, double *__restrict__ sc)
+// y = R^{-1} g over the first k columns, by one block: column sweep from
+// the last unknown, the remaining right-hand side in LDS (each column of R
+// is read once, its entries spread over the threads).
+__global__ __launch_bounds__(RT) void k_backsolve(SW s, int k, double *__restrict__ sc)
 {
+    __shared__ double v[MAXRS];
     const double *H = sc + s.H();
     double *y = sc + s.y();
+    for (int r = threadIdx.x; r < k; r += RT) v[r] = sc[s.g() + r];
+    __syncthreads();
     for (int i = k - 1; i >= 0; --i) {
-        double v = sc[s.g() + i];
-        for (int c = i + 1; c < k; ++c) v -= H[(size_t)c * (s.m + 1) + i] * y[c];
-        y[i] = v / H[(size_t)i * (s.m + 1) + i];
+        const double *col = H + (size_t)i * (s.m + 1);
+        const double yi = v[i] / col[i];
+        for (int r = threadIdx.x; r < i; r += RT) v[r] -= col[r] * yi;
+        if (threadIdx.x == 0) y[i] = yi;
+        __syncthreads();
     }
 }
 
@@ -378,13 +385,15 @@ void GmresRun::start(fmddm_ctx *c, fmddm_tree *tr, int md, const double *rhs, do
     maxit = mx;
     j = next = it = restarts = 0;
     eager_done = false;
-    pc = ctx->prm.precond == FMDDM_PRECOND_BLOCK;
+    pc = ctx->prm.precond != FMDDM_PRECOND_NONE;
+    pc2 = ctx->prm.precond == FMDDM_PRECOND_TWO_LEVEL;
     bnorm = relres = 0.0;
     converged = false;
     gmres_workspace(t, ctx->prm.restart, (int)vec_len(t, mode));
     if (pc) {
         if (mode == APPLY_PORO) pc_setup_poro(ctx, t);
         else pc_setup(ctx, t);
+        if (pc2) pc_coarse_setup(ctx, t, mode == APPLY_PORO);
         if (!t->gm_z.p || t->gm_z.n < (size_t)vec_len(t, mode)) t->gm_z.alloc(vec_len(t, mode));
     }
     SW s{ctx->prm.restart};
@@ -459,6 +468,13 @@ void GmresRun::enqueue_step()
     FM_HIP(hipEventRecord(t->gm_ev[jj & 1], st));
 }
 
+void GmresRun::precond(const double *in, int acc, double *out)
+{
+    const bool poro = mode == APPLY_PORO;
+    pc_apply(ctx, t, poro ? t->ppc : t->pc, in, acc, out);
+    if (pc2) pc_coarse_add(ctx, t, poro ? t->ppcc : t->pcc, poro ? 3 : 2, in, out);
+}
+
 void GmresRun::step_body(int jj)
 {
     const int m = ctx->prm.restart;
@@ -468,7 +484,7 @@ void GmresRun::step_body(int jj)
     double *V = t->gm_V.p, *w = t->gm_w.p, *sc = t->gm_sc.p;
     double *vj = V + (size_t)jj * ldv, *vn = V + (size_t)(jj + 1) * ldv;
     if (pc) {
-        pc_apply(ctx, t, mode == APPLY_PORO ? t->ppc : t->pc, vj, 0, t->gm_z.p);
+        precond(vj, 0, t->gm_z.p);
         apply_mode(ctx, t, mode, t->gm_z.p, w);
     } else {
         apply_mode(ctx, t, mode, vj, w);
@@ -565,13 +581,13 @@ bool GmresRun::advance(bool block)
         if (est <= tol * bnorm || nrm == 0.0 || k == m || (!ahead && it >= maxit)) {
             // a step enqueued ahead leaves H's first k columns and g[0..k)
             // as they were: the update uses the first k only
-            hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(1), 0, st, s, k, sc);
+            hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(RT), 0, st, s, k, sc);
             if (pc) {  // x += M^-1 V y
                 double *u = t->gm_w.p;
                 hipLaunchKernelGGL(k_fill, dim3(gb), dim3(256), 0, st, n2, 0.0, u);
                 hipLaunchKernelGGL(k_vupdate, dim3(gb), dim3(256), 0, st, n2, k, V, ldv, sc + s.y(), 1.0, u);
                 FM_CHECK_LAUNCH();
-                pc_apply(ctx, t, mode == APPLY_PORO ? t->ppc : t->pc, u, 1, x);
+                precond(u, 1, x);
             } else {
                 hipLaunchKernelGGL(k_vupdate, dim3(gb), dim3(256), 0, st, n2, k, V, ldv, sc + s.y(), 1.0, x);
             }

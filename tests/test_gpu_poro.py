@@ -204,12 +204,13 @@ def test_poro_fmm_time_marching():
 @pytest.mark.parametrize("mode", [F.FMDDM_APPLY_DIRECT, F.FMDDM_APPLY_FMM])
 def test_poro_block_jacobi(mode):
     """Block-Jacobi preconditioning of the poroelastic left-hand side (groups
-    of at most 21 elements, 3 unknowns each): same solution as plain GMRES
-    (both to 1e-11), in at most half the products."""
+    of at most 21 elements, 3 unknowns each), alone and with the coarse
+    level (undrained long elements over aggregates): same solution as plain
+    GMRES (all to 1e-11), in at most half the products."""
     wl = W.well_cluster(n_frac=3, elems=60, half_length=6.0, spacing=2.0)
     n3 = 3 * wl.n
     res = {}
-    for pc in (F.FMDDM_PRECOND_NONE, F.FMDDM_PRECOND_BLOCK):
+    for pc in (F.FMDDM_PRECOND_NONE, F.FMDDM_PRECOND_BLOCK, F.FMDDM_PRECOND_TWO_LEVEL):
         prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=MED["E"], nu=MED["nu"], p=8, leaf=16, tol=1e-11,
                          restart=50, maxit=20000, precond=pc)
         F.fmddm_poro_set(prob.ctx, MED["nuu"], MED["alpha"], MED["perm"], MED["visc"], DT, P0, mode=mode)
@@ -229,10 +230,11 @@ def test_poro_block_jacobi(mode):
         print(f"mode {mode} precond {pc}: iterations {its}")
         prob.close()
     for h in range(2):
-        a = res[F.FMDDM_PRECOND_BLOCK][0][h * n3:(h + 1) * n3]
         b = res[F.FMDDM_PRECOND_NONE][0][h * n3:(h + 1) * n3]
-        assert cmp(a, b) <= 1e-7, (h, cmp(a, b))
-        assert 2 * res[F.FMDDM_PRECOND_BLOCK][1][h] <= res[F.FMDDM_PRECOND_NONE][1][h], res
+        for pc in (F.FMDDM_PRECOND_BLOCK, F.FMDDM_PRECOND_TWO_LEVEL):
+            a = res[pc][0][h * n3:(h + 1) * n3]
+            assert cmp(a, b) <= 1e-7, (pc, h, cmp(a, b))
+            assert 2 * res[pc][1][h] <= res[F.FMDDM_PRECOND_NONE][1][h], res
 
 
 def test_poro_full_size_sampled_rows():
