@@ -209,6 +209,52 @@ __global__ __launch_bounds__(256) void k_p2m(int nleaf, const int *__restrict__ 
     }
 }
 
+// D (R x C) = A (R x K) . B (K x C) by one wave on FP64 MFMA 16x16x4, the
+// operands read through a(i, k) and b(k, j) (zero outside the shape) and the
+// result handed to st(i, j, v) after every operand has been read, so the
+// product may overwrite its inputs.  Lane L holds A[L%16][L/16] and
+// B[L/16][L%16]; accumulator register r holds D[4r + L/16][L%16].
+template <int R, int C, int K, class FA, class FB, class FS>
+__device__ __forceinline__ void wave_gemm(FA a, FB b, FS st)
+{
+    constexpr int MT = (R + 15) / 16, NT = (C + 15) / 16, KS = (K + 3) / 4;
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    d4 acc[MT][NT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        const int k = 4 * ks + lk;
+        double av[MT], bv[NT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const int i = 16 * mt + li;
+            av[mt] = (i < R && k < K) ? a(i, k) : 0.0;
+        }
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const int j = 16 * nt + li;
+            bv[nt] = (j < C && k < K) ? b(k, j) : 0.0;
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mt], bv[nt], acc[mt][nt], 0, 0, 0);
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = 16 * mt + 4 * r + lk, j = 16 * nt + li;
+                if (i < R && j < C) st(i, j, acc[mt][nt][r]);
+            }
+}
+
 // ------------------------------------------------------------ M2M
 // eq. 3.7 applied level after level gives an ancestor A the weights
 //   W_A = sum over leaves L below A of  Tx_{A<-L} W_L Ty_{A<-L}^T,
@@ -283,6 +329,29 @@ __global__ __launch_bounds__(XT) void k_m2m(int nitem, const int *__restrict__ i
         for (int l = 0; l < P; ++l) T[l * P + l2] = S[l];
     }
     __syncthreads();
+    if (NS == XT / 64) {
+        // wave d transfers slot d on the matrix cores: the x pass is
+        // Tx_d (P x P) . [W_c]_c (P x NC P), the y pass [W'_c]_c (NC P x P) . Ty_d^T
+        const int d = tid >> 6;
+        double *bd = buf + d * N3;
+        const double *tx = Tx[d], *ty = Ty[d];
+        if (k4[d] >= 0) {
+            wave_gemm<P, NC * P, P>([&](int l, int l2) { return tx[l * P + l2]; },
+                                    [&](int l2, int j) { return bd[(j / P) * P2 + l2 * P + j % P]; },
+                                    [&](int l, int j, double v) { bd[(j / P) * P2 + l * P + j % P] = v; });
+            wave_gemm<NC * P, P, P>([&](int row, int m2) { return bd[row * P + m2]; },
+                                    [&](int m2, int m) { return ty[m * P + m2]; },
+                                    [&](int row, int m, double v) { bd[row * P + m] = v; });
+        }
+        __syncthreads();
+        for (int e = tid; e < N3; e += XT) {
+            double acc = buf[e];
+#pragma unroll
+            for (int dd = 1; dd < NS; ++dd) acc += buf[dd * N3 + e];
+            part[(size_t)item * Mp + e] = acc;
+        }
+        return;
+    }
     // x pass: task (slot d, component, column m2): column <- Tx_d . column
     for (int q = tid; q < NC * NS * P; q += XT) {
         int d = q / (NC * P), r = q - d * NC * P, comp = r / P, m2 = r - comp * P;
