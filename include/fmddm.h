@@ -90,8 +90,9 @@ typedef enum {
  * m), at most 21 for the poroelastic left-hand side F(dt) (8 (3m)^2 bytes;
  * rebuilt when the medium or dt changes).  TWO_LEVEL adds a coarse level
  * for the long-wavelength modes of long fractures (8 (2 nc)^2 bytes for nc
- * aggregates, nc <= about 1024; the poroelastic one uses the undrained
- * modulus).  Built once per tree.  It changes the iteration count, not the
+ * aggregates, about 1024 for long fractures; the poroelastic one uses the
+ * undrained modulus).  A geometry with more than 2048 aggregates (few
+ * collinear runs, e.g. many one-element fractures) gets block-Jacobi alone.  Built once per tree.  It changes the iteration count, not the
  * solution. */
 typedef enum {
     FMDDM_PRECOND_NONE = 0,

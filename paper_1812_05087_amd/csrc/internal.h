@@ -93,7 +93,8 @@ struct PcBlocks {
 // explicit inverse of their coarse matrix R A P (2 nc x 2 nc, row-major,
 // traction components from shear/normal DDs).
 struct PcCoarse {
-    int nc = 0;                // aggregates (0: not built)
+    int nc = 0;                // aggregates (0: not built, or left out)
+    int off = 0;               // left out: more than a few thousand aggregates
     DBuf<int> abeg;            // first element of each aggregate, nc + 1 entries
     DBuf<double> ainv, rc, yc;
     double key[6] = {0, 0, 0, 0, 0, 0};

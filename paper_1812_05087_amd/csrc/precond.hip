@@ -245,14 +245,15 @@ void pc_apply(fmddm_ctx *ctx, fmddm_tree *t, const PcBlocks &B, const double *in
 // poroelastic left-hand side the coarse scale sees the undrained medium
 // (nu_u): the diffusion length of one step is far below an aggregate.
 constexpr int AGG_MIN = 16;      // elements per aggregate, at least
-constexpr int COARSE_MAX = 1024;  // aggregates, about at most
+constexpr int COARSE_MAX = 1024;  // aggregates aimed at (runs end at fracture ends)
+constexpr int COARSE_CAP = 2048;  // above this many aggregates the coarse level is left out
 
 void pc_coarse_setup(fmddm_ctx *ctx, fmddm_tree *t, bool poro)
 {
     PcCoarse &C = poro ? t->ppcc : t->pcc;
     const double nu_eff = poro ? ctx->poro.nu_u : ctx->prm.nu;
     const double key[6] = {ctx->prm.E, ctx->prm.nu, nu_eff, 0, 0, 0};
-    bool same = C.nc > 0;
+    bool same = C.nc > 0 || C.off;
     for (int k = 0; k < 6; ++k) same = same && C.key[k] == key[k];
     if (same) return;
     hipStream_t s = ctx->stream;
@@ -295,6 +296,13 @@ void pc_coarse_setup(fmddm_ctx *ctx, fmddm_tree *t, bool poro)
         }
     }
     const int nc = (int)hx.size();
+    for (int k = 0; k < 6; ++k) C.key[k] = key[k];
+    if (nc > COARSE_CAP) {  // few collinear runs: block-Jacobi alone
+        C.nc = 0;
+        C.off = 1;
+        return;
+    }
+    C.off = 0;
     abeg.push_back(n);
     const int m = 2 * nc;
     up(s, C.abeg, abeg);
@@ -333,13 +341,13 @@ void pc_coarse_setup(fmddm_ctx *ctx, fmddm_tree *t, bool poro)
         throw Error{FMDDM_EGEOM, "singular coarse matrix (coincident fractures?)"};
     }
     C.nc = nc;
-    for (int k = 0; k < 6; ++k) C.key[k] = key[k];
     t->bytes += (int64_t)C.ainv.bytes();
 }
 
 void pc_coarse_add(fmddm_ctx *ctx, fmddm_tree *t, const PcCoarse &C, int ncomp, const double *in, double *out)
 {
     (void)t;
+    if (C.nc == 0) return;  // left out (too few collinear runs)
     hipStream_t s = ctx->stream;
     const int m = 2 * C.nc;
     hipLaunchKernelGGL(k_coarse_restrict, dim3(cdiv(m, 256)), dim3(256), 0, s, C.nc, ncomp, C.abeg.p, in, C.rc.p);

@@ -112,8 +112,8 @@ int64_t footprint(const fmddm_params &p, int rank_pad, int64_t n)
     int64_t per_cell = 8 * (3 * Mp + 2 * rp + 4 * rp + 27 * rp) + 4 * 64;
     if (p.precision != FMDDM_PREC_FP64) per_cell += 4 * (2 * rp + 4 * rp + 27 * rp);  // FP32 intermediates
     int64_t b = n * per_elem + cells * per_cell + (4 << 20);
-    if (p.precond == FMDDM_PRECOND_TWO_LEVEL) {  // coarse inverse: aggregates of >= 16 elements, <= ~1024 of them
-        const int64_t nc = std::min<int64_t>(n / 16 + 1, 1100);
+    if (p.precond == FMDDM_PRECOND_TWO_LEVEL) {  // coarse inverse: at most 2048 aggregates, else left out
+        const int64_t nc = std::min<int64_t>(n, 2048);
         b += 8 * (2 * nc) * (2 * nc) + 8 * 6 * nc;
     }
     return b + b / 4;

@@ -116,6 +116,26 @@ def test_two_level_on_long_fractures():
     assert 2 * res[F.FMDDM_PRECOND_TWO_LEVEL] <= res[F.FMDDM_PRECOND_BLOCK], res
 
 
+def test_two_level_left_out_without_collinear_runs():
+    """2100 one-element fractures form 2100 aggregates, above the coarse
+    level's cap (2048): the two-level solve is then the block-Jacobi one,
+    bit for bit, instead of inverting a 4200 x 4200 coarse matrix."""
+    wl = W.random_fractures(44, n_frac=2100, elems=1, box=200.0, lmin=0.5, lmax=1.0)
+    kw = dict(p=8, leaf=32, m2l=F.FMDDM_M2L_SVD, m2l_tol=1e-10, restart=30, tol=1e-10, maxit=3000)
+    res = {}
+    for pc in (F.FMDDM_PRECOND_BLOCK, F.FMDDM_PRECOND_TWO_LEVEL):
+        prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=wl.E, nu=wl.nu, precond=pc, **kw)
+        try:
+            b = prob.rhs(wl.pressure, wl.SH, wl.Sh)
+            x, info = prob.solve(b)
+        finally:
+            prob.close()
+        assert info["status"] == F.FMDDM_OK, (pc, info)
+        res[pc] = (x.cpu().numpy(), info["iters"])
+    a, c = res[F.FMDDM_PRECOND_TWO_LEVEL], res[F.FMDDM_PRECOND_BLOCK]
+    assert a[1] == c[1] and np.array_equal(a[0], c[0])
+
+
 @pytest.mark.parametrize("pc", [F.FMDDM_PRECOND_BLOCK, F.FMDDM_PRECOND_TWO_LEVEL])
 def test_preconditioned_graph_replays_match_plain_launches(pc):
     wl = W.random_fractures(43, n_frac=25, elems=40)
