@@ -63,13 +63,23 @@ struct PoroK {
 // quadrature rules so that the series below are division-free:
 // c_e1w[k] = k / (k+1)^2, c_hc[k] = (-1)^(k+1) / (k+1)!, c_p2c[k] =
 // (-1)^k (k-1) / k!.
+// ROLL keeps the series loops rolled: a coefficient load per term, but far
+// fewer registers than the unrolled form, which holds every coefficient;
+// the kernel that builds the stored near blocks uses it to run more waves.
+// Both forms do the same operations in the same order.
 __constant__ double c_e1w[31], c_hc[23], c_p2c[18];
 
+template <bool ROLL = false>
 __device__ double e1(double z)
 {
     if (z <= 2.0) {
         double v = 1.0;
-        for (int k = 30; k >= 1; --k) v = 1.0 - z * c_e1w[k] * v;
+        if constexpr (ROLL) {
+#pragma unroll 1
+            for (int k = 30; k >= 1; --k) v = 1.0 - z * c_e1w[k] * v;
+        } else {
+            for (int k = 30; k >= 1; --k) v = 1.0 - z * c_e1w[k] * v;
+        }
         return -0.57721566490153286061 - log(z) + z * v;
     }
     if (z > 745.0) return 0.0;
@@ -82,17 +92,24 @@ __device__ double e1(double z)
 }
 
 // h(z) = 1 - (1 - e^-z)/z with h', h'' (series below 0.5).
+template <bool ROLL = false>
 __device__ void hfun(double z, double &h, double &h1, double &h2)
 {
     if (z < 0.5) {
         // h = sum_{k>=1} c_k z^k, c_k = (-1)^(k+1) / (k+1)!, by Horner
         // from k = 22 down (the first omitted term is below 1e-26)
         double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-        for (int k = 22; k >= 1; --k) {
+        auto term = [&](int k) {
             double ck = c_hc[k];
             a0 = a0 * z + ck;
             a1 = a1 * z + ck * k;
             if (k >= 2) a2 = a2 * z + ck * k * (k - 1);
+        };
+        if constexpr (ROLL) {
+#pragma unroll 1
+            for (int k = 22; k >= 1; --k) term(k);
+        } else {
+            for (int k = 22; k >= 1; --k) term(k);
         }
         h = a0 * z;
         h1 = a1;
@@ -106,12 +123,18 @@ __device__ void hfun(double z, double &h, double &h1, double &h2)
     h2 = -2.0 * om * iz * iz * iz + 2.0 * em * iz * iz + em * iz;
 }
 
+template <bool ROLL = false>
 __device__ double p2fun(double z)
 {
     if (z < 0.1) {
         // sum_{k=2}^{17} (-1)^k (k-1) z^k / k!, by Horner
         double s = 0.0;
-        for (int k = 17; k >= 2; --k) s = s * z + c_p2c[k];
+        if constexpr (ROLL) {
+#pragma unroll 1
+            for (int k = 17; k >= 2; --k) s = s * z + c_p2c[k];
+        } else {
+            for (int k = 17; k >= 2; --k) s = s * z + c_p2c[k];
+        }
         return s * z * z;
     }
     return 1.0 - exp(-z) * (1.0 + z);
@@ -135,6 +158,7 @@ struct TPoint {
     double cxx, cyy, cxy, sxx, syy, sxy;
 };
 
+template <bool ROLL = false>
 __device__ __forceinline__ void tpoint(const PoroK &K, double x, double y, double t, TPoint &T)
 {
     double r2 = x * x + y * y, ir2 = recip(r2), r = sqrt(r2), ir = recip(r);
@@ -147,9 +171,9 @@ __device__ __forceinline__ void tpoint(const PoroK &K, double x, double y, doubl
     T.om = -expm1(-z);
     T.gxy = x * x - y * y;
     T.g2 = 2.0 * x * y;
-    T.P2 = p2fun(z);
+    T.P2 = p2fun<ROLL>(z);
     double h, h1, h2;
-    hfun(z, h, h1, h2);
+    hfun<ROLL>(z, h, h1, h2);
     double F = -0.25 * h * ir2;
     double F1 = (h - z * h1) * 0.5 * ir2 * ir;                // F'(r)
     double F2 = (-2.0 * z * z * h2 - 3.0 * h + 3.0 * z * h1) * 0.5 * ir2 * ir2;  // F''(r)
@@ -200,7 +224,7 @@ __device__ __forceinline__ void transient_basis(const PoroK &K, double x, double
                                                 double R[16])
 {
     TPoint T;
-    tpoint(K, x, y, t, T);
+    tpoint<true>(K, x, y, t, T);
     double ir2 = T.ir2, z = T.z, ez = T.ez, om = T.om;
     double m2g = -2.0 * K.G * w, p2g = 2.0 * K.G * w;
     double pc = K.ap * ir2 * ir2 * T.P2 * w, Cw = K.cphi;
@@ -218,7 +242,7 @@ __device__ __forceinline__ void transient_basis(const PoroK &K, double x, double
     R[9] += m2g * dxx;
     R[10] += p2g * dxy;
     R[11] -= w * K.pv * ez * T.ict;
-    double E = e1(z), A = z * E + om, ft = K.fe * t;
+    double E = e1<true>(z), A = z * E + om, ft = K.fe * t;
     dxx = dyy = dxy = 0.0;
     rad2(x, y, ir2, ft * A * ir2, ft * (2.0 * z * E - A) * ir2, dxx, dyy, dxy);
     R[12] += m2g * dyy;
@@ -589,7 +613,7 @@ __global__ __launch_bounds__(PN) void k_pp2p(int nitem, const int *__restrict__ 
 // it_coff[k+1]; within the item, pair e = v nt + i (source v of the chunk,
 // target i of the leaf) stores its 12 entries at 12 it_coff[k] + (12 v + c)
 // nt + i, so that consecutive targets are adjacent for every entry c.
-__global__ __launch_bounds__(256) void k_pnear_build(int64_t npair, int nitem, const int64_t *__restrict__ it_coff,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_pnear_build(int64_t npair, int nitem, const int64_t *__restrict__ it_coff,
                                                      const int *__restrict__ it_leaf, const int *__restrict__ it_s0,
                                                      const int *__restrict__ leaves, const int *__restrict__ pbeg,
                                                      const int *__restrict__ pend, const int *__restrict__ noff,
