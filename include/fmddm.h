@@ -132,6 +132,10 @@ typedef struct {
                                  are solved with the exact on-the-fly product
                                  instead of the FMM (faster below the size where
                                  the FMM's chain of launches dominates); 0: never */
+    int32_t coarse_aggregates; /* TWO_LEVEL: the number of coarse aggregates aimed at
+                                 (elements per aggregate max(16, n / this), runs ending
+                                 at fracture ends); 0: 1024.  Fewer make the coarse LU
+                                 cheaper and the coarse space poorer. */
 } fmddm_params;
 
 typedef struct {
@@ -161,7 +165,7 @@ typedef struct {
 /* Fill *p with defaults: E=20e9, nu=0.25, leaf=32, p=20, max_level=24,
  * kappa=8, m2l=DENSE, m2l_tol=1e-12, no root box, restart=50,
  * maxit=10000, tol=1e-10, precision=FP64, use_graphs=0, precond=NONE,
- * m2l_tiles=0, direct_below=0. */
+ * m2l_tiles=0, direct_below=0, coarse_aggregates=0 (1024). */
 void fmddm_default_params(fmddm_params *p);
 
 /* Create a context on the current HIP device bound to `hip_stream`

@@ -57,7 +57,7 @@ class Params(C.Structure):
         ("use_root_box", C.c_int), ("root_x0", C.c_double), ("root_y0", C.c_double),
         ("root_L", C.c_double), ("restart", C.c_int), ("maxit", C.c_int), ("tol", C.c_double),
         ("precision", C.c_int), ("use_graphs", C.c_int), ("precond", C.c_int), ("m2l_tiles", C.c_int),
-        ("direct_below", C.c_int64),
+        ("direct_below", C.c_int64), ("coarse_aggregates", C.c_int32),
     ]
 
 
@@ -116,6 +116,13 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: run paper_1812_05087_amd/build.py "
                                "(or __graft_entry__.build()) first; there is no fallback")
+        # PyTorch's HIP runtime is loaded first, so that the library binds
+        # to the same one (a second runtime in the process would leave
+        # torch without devices)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         L.fmddm_default_params.argtypes = [C.POINTER(Params)]
         L.fmddm_default_params.restype = None

@@ -56,6 +56,7 @@ const char *check_params(const fmddm_params *p)
         return "unknown precond";
     if (p->m2l_tiles < 0 || p->m2l_tiles > 3) return "m2l_tiles must lie in [0, 3]";
     if (p->direct_below < 0) return "direct_below must be >= 0";
+    if (p->coarse_aggregates < 0 || p->coarse_aggregates > 2048) return "coarse_aggregates must lie in [0, 2048]";
     return nullptr;
 }
 

@@ -144,7 +144,10 @@ struct fmddm_ctx {
     // idle stream that graphs are captured on (the caller's stream may be
     // the null stream, which cannot capture); graphs launch on `stream`
     hipStream_t cap = nullptr;
-    ~fmddm_ctx()
+    // rocBLAS handle of the coarse-level factorisation, made on first use
+    void *blas = nullptr;
+    ~fmddm_ctx();
+    void release()
     {
         if (cap) (void)hipStreamDestroy(cap);
         if (ev_fork) (void)hipEventDestroy(ev_fork);

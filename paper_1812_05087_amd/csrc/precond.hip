@@ -245,14 +245,14 @@ void pc_apply(fmddm_ctx *ctx, fmddm_tree *t, const PcBlocks &B, const double *in
 // poroelastic left-hand side the coarse scale sees the undrained medium
 // (nu_u): the diffusion length of one step is far below an aggregate.
 constexpr int AGG_MIN = 16;      // elements per aggregate, at least
-constexpr int COARSE_MAX = 1024;  // aggregates aimed at (runs end at fracture ends)
+constexpr int COARSE_MAX = 1024;  // aggregates aimed at by default (runs end at fracture ends)
 constexpr int COARSE_CAP = 2048;  // above this many aggregates the coarse level is left out
 
 void pc_coarse_setup(fmddm_ctx *ctx, fmddm_tree *t, bool poro)
 {
     PcCoarse &C = poro ? t->ppcc : t->pcc;
     const double nu_eff = poro ? ctx->poro.nu_u : ctx->prm.nu;
-    const double key[6] = {ctx->prm.E, ctx->prm.nu, nu_eff, 0, 0, 0};
+    const double key[6] = {ctx->prm.E, ctx->prm.nu, nu_eff, (double)ctx->prm.coarse_aggregates, 0, 0};
     bool same = C.nc > 0 || C.off;
     for (int k = 0; k < 6; ++k) same = same && C.key[k] == key[k];
     if (same) return;
@@ -267,7 +267,8 @@ void pc_coarse_setup(fmddm_ctx *ctx, fmddm_tree *t, bool poro)
     FM_HIP(hipStreamSynchronize(s));
     // aggregates: runs in caller order of at most `ag` elements where each
     // element starts at the previous one's end, in the same direction
-    const int ag = std::max(AGG_MIN, (n + COARSE_MAX - 1) / COARSE_MAX);
+    const int target = ctx->prm.coarse_aggregates > 0 ? ctx->prm.coarse_aggregates : COARSE_MAX;
+    const int ag = std::max(AGG_MIN, (n + target - 1) / target);
     std::vector<int> abeg;
     std::vector<double> hx, hy, hcb, hsb, ha;
     auto close_run = [&](int b, int e) {  // elements [b, e)
@@ -326,13 +327,16 @@ void pc_coarse_setup(fmddm_ctx *ctx, fmddm_tree *t, bool poro)
     ipiv.alloc(m);
     info.alloc(2);
     info.zero(s);
-    rocblas_handle h;
-    if (rocblas_create_handle(&h) != rocblas_status_success) throw Error{FMDDM_EDEVICE, "rocblas handle"};
+    if (!ctx->blas) {
+        rocblas_handle h;
+        if (rocblas_create_handle(&h) != rocblas_status_success) throw Error{FMDDM_EDEVICE, "rocblas handle"};
+        ctx->blas = h;
+    }
+    rocblas_handle h = (rocblas_handle)ctx->blas;
     rocblas_set_stream(h, s);
     rocblas_status st = rocsolver_dgetrf(h, m, m, C.ainv.p, m, ipiv.p, info.p);
     if (st == rocblas_status_success) st = rocsolver_dgetri(h, m, C.ainv.p, m, ipiv.p, info.p + 1);
     FM_HIP(hipStreamSynchronize(s));
-    rocblas_destroy_handle(h);
     if (st != rocblas_status_success) throw Error{FMDDM_EDEVICE, "coarse LU failed"};
     int hinfo[2] = {0, 0};
     FM_HIP(hipMemcpy(hinfo, info.p, 8, hipMemcpyDeviceToHost));
@@ -357,3 +361,9 @@ void pc_coarse_add(fmddm_ctx *ctx, fmddm_tree *t, const PcCoarse &C, int ncomp, 
 }
 
 }  // namespace fmddm
+
+fmddm_ctx::~fmddm_ctx()
+{
+    if (blas) (void)rocblas_destroy_handle((rocblas_handle)blas);
+    release();
+}

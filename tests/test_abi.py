@@ -60,7 +60,7 @@ def test_default_params_and_validation_without_device():
     out = C.c_void_p()
     for field, bad in [("p", 0), ("p", 33), ("leaf", 0), ("nu", 0.5), ("E", -1.0),
                        ("max_level", 31), ("restart", 0), ("tol", -1.0), ("precision", 3),
-                       ("precision", -1), ("use_graphs", 2), ("precond", 3), ("precond", -1)]:
+                       ("precision", -1), ("use_graphs", 2), ("precond", 3), ("precond", -1), ("coarse_aggregates", -1), ("coarse_aggregates", 4096)]:
         q = F.fmddm_default_params(**{field: bad})
         assert lib.fmddm_create(C.byref(q), None, C.byref(out)) == F.FMDDM_EINVAL, field
         assert not out.value

@@ -49,9 +49,10 @@ def drain(srv, tickets, limit_s=120.0, watch=None):
         assert time.time() - t0 < limit_s, "serving loop did not finish"
 
 
-def test_alone_equals_mix_bitwise():
+@pytest.mark.parametrize("pc", [F.FMDDM_PRECOND_NONE, F.FMDDM_PRECOND_TWO_LEVEL])
+def test_alone_equals_mix_bitwise(pc):
     reqs = W.serving_stream(seed=7, count=10, nmin=500, nmax=6000, steps_max=3)
-    prm = F.fmddm_default_params(**P_SERVE)
+    prm = F.fmddm_default_params(**P_SERVE, precond=pc, coarse_aggregates=128)
     srv = F.fmddm_server_create(prm, 5)
     try:
         mix = {}
@@ -76,10 +77,11 @@ def test_alone_equals_mix_bitwise():
         F.fmddm_server_destroy(srv)
 
 
-def test_served_solution_satisfies_exact_system():
+@pytest.mark.parametrize("pc", [F.FMDDM_PRECOND_NONE, F.FMDDM_PRECOND_TWO_LEVEL])
+def test_served_solution_satisfies_exact_system(pc):
     req = W.serving_stream(seed=11, count=1, nmin=600, nmax=600, steps_max=1)[0]
     req.steps = 3
-    prm = F.fmddm_default_params(**P_SERVE)
+    prm = F.fmddm_default_params(**P_SERVE, precond=pc, coarse_aggregates=128)
     srv = F.fmddm_server_create(prm, 2)
     try:
         tol = 1e-9
@@ -128,8 +130,9 @@ def test_admission_respects_budget():
         F.fmddm_server_destroy(srv)
 
 
-def test_footprint_estimate_covers_allocation():
-    prm = F.fmddm_default_params(**P_SERVE)
+@pytest.mark.parametrize("pc", [F.FMDDM_PRECOND_NONE, F.FMDDM_PRECOND_TWO_LEVEL])
+def test_footprint_estimate_covers_allocation(pc):
+    prm = F.fmddm_default_params(**P_SERVE, precond=pc, coarse_aggregates=128)
     for seed, n in [(19, 1000), (23, 8000), (29, 30000)]:
         srv = F.fmddm_server_create(prm, 1)
         try:
