@@ -867,24 +867,26 @@ int near_levels(fmddm_ctx *ctx, fmddm_tree *t, int H)
     if ((int)t->pn_lvl.size() >= want) return want;
     hipStream_t s = ctx->stream;
     const PoroK K = poro_constants(ctx);
-    const int first = (int)t->pn_lvl.size();
-    for (int j = first; j < want; ++j) {
-        t->pn_lvl.emplace_back(new DBuf<double>());
-        DBuf<double> &b = *t->pn_lvl.back();
-        b.alloc((size_t)12 * std::max<int64_t>(t->near_pairs, 1));
-        t->bytes += (int64_t)b.bytes();
-        t->pn_hptr.push_back(b.p);
+    // a level counts as stored only once it is allocated, built and its
+    // address is in the device table, so an error leaves the levels before
+    // it intact and no half-built one behind
+    for (int j = (int)t->pn_lvl.size(); j < want; ++j) {
+        std::unique_ptr<DBuf<double>> b(new DBuf<double>());
+        b->alloc((size_t)12 * std::max<int64_t>(t->near_pairs, 1));
         if (t->near_pairs > 0) {
             hipLaunchKernelGGL(k_pnear_build, dim3(cdiv(t->near_pairs, 256)), dim3(256), 0, s, t->near_pairs,
                                t->nitem, t->it_coff.p, t->it_leaf.p, t->it_s0.p, t->dleaves.p, t->cpbeg.p,
                                t->cpend.p, t->noff.p, t->nbeg.p, t->npre.p, t->scx.p, t->scy.p, t->scb.p,
-                               t->ssb.p, t->sa.p, (j + 1) * ctx->poro.dt, K, b.p);
+                               t->ssb.p, t->sa.p, (j + 1) * ctx->poro.dt, K, b->p);
             FM_CHECK_LAUNCH();
         }
+        t->pn_hptr.resize(j);
+        t->pn_hptr.push_back(b->p);
+        FM_HIP(hipMemcpyAsync(t->pn_ptr.p + j, t->pn_hptr.data() + j, sizeof(double *), hipMemcpyHostToDevice, s));
+        FM_HIP(hipStreamSynchronize(s));
+        t->bytes += (int64_t)b->bytes();
+        t->pn_lvl.push_back(std::move(b));
     }
-    FM_HIP(hipMemcpyAsync(t->pn_ptr.p + first, t->pn_hptr.data() + first, (want - first) * sizeof(double *),
-                          hipMemcpyHostToDevice, s));
-    FM_HIP(hipStreamSynchronize(s));
     return want;
 }
 

@@ -256,6 +256,10 @@ void pc_coarse_setup(fmddm_ctx *ctx, fmddm_tree *t, bool poro)
     bool same = C.nc > 0 || C.off;
     for (int k = 0; k < 6; ++k) same = same && C.key[k] == key[k];
     if (same) return;
+    // unbuilt until the new level is complete (a failed rebuild leaves none)
+    if (C.nc > 0) t->bytes -= (int64_t)C.ainv.bytes();
+    C.nc = 0;
+    C.off = 0;
     hipStream_t s = ctx->stream;
     const int n = (int)t->n;
     std::vector<double> x(n), y(n), cb(n), sb(n), a(n);
@@ -297,13 +301,11 @@ void pc_coarse_setup(fmddm_ctx *ctx, fmddm_tree *t, bool poro)
         }
     }
     const int nc = (int)hx.size();
-    for (int k = 0; k < 6; ++k) C.key[k] = key[k];
     if (nc > COARSE_CAP) {  // few collinear runs: block-Jacobi alone
-        C.nc = 0;
         C.off = 1;
+        for (int k = 0; k < 6; ++k) C.key[k] = key[k];
         return;
     }
-    C.off = 0;
     abeg.push_back(n);
     const int m = 2 * nc;
     up(s, C.abeg, abeg);
@@ -340,11 +342,9 @@ void pc_coarse_setup(fmddm_ctx *ctx, fmddm_tree *t, bool poro)
     if (st != rocblas_status_success) throw Error{FMDDM_EDEVICE, "coarse LU failed"};
     int hinfo[2] = {0, 0};
     FM_HIP(hipMemcpy(hinfo, info.p, 8, hipMemcpyDeviceToHost));
-    if (hinfo[0] != 0 || hinfo[1] != 0) {
-        C.nc = 0;
-        throw Error{FMDDM_EGEOM, "singular coarse matrix (coincident fractures?)"};
-    }
+    if (hinfo[0] != 0 || hinfo[1] != 0) throw Error{FMDDM_EGEOM, "singular coarse matrix (coincident fractures?)"};
     C.nc = nc;
+    for (int k = 0; k < 6; ++k) C.key[k] = key[k];
     t->bytes += (int64_t)C.ainv.bytes();
 }
 
