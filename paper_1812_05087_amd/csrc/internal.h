@@ -257,6 +257,12 @@ struct fmddm_tree {
     std::vector<double *> pn_hptr;
     fmddm::DBuf<double *> pn_ptr;
     int pn_cap = -1;        // levels that fit the budget (-1: not sized yet)
+    // left-hand side F(dt) in one multipole pass: the first level's near
+    // blocks and M2L operators with the drained elastic part added
+    fmddm::DBuf<double> pn_lhs, pf_ops0;
+    fmddm::DBuf<double *> pn_lhs_ptr;
+    double *pn_lhs_host = nullptr;  // source of the copy into pn_lhs_ptr
+    int pn_lhs_ok = 0, pf_ops0_ok = 0;
     double pn_key[8] = {};  // medium and budget the levels were built for
     // Arnoldi steps captured as graphs, one per step index, valid for the
     // context and apply mode they were captured with

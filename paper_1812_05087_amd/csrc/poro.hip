@@ -478,7 +478,7 @@ __global__ void k_poro_rhs(int n, const double *__restrict__ cb, const double *_
 // combo c; rows (component_out, tn), columns (j, component_in, sn)
 __global__ void k_pops(int ncombo, const int *__restrict__ clvl, const int *__restrict__ cox,
                        const int *__restrict__ coy, double rootL, const double *__restrict__ xbar, int p, int H,
-                       double dt, int Mq, PoroK K, double *__restrict__ ops)
+                       double dt, int Mq, PoroK K, int drained, double *__restrict__ ops)
 {
     int p2 = p * p;
     int64_t per = (int64_t)p2 * p2 * H;
@@ -495,10 +495,14 @@ __global__ void k_pops(int ncombo, const int *__restrict__ clvl, const int *__re
     double t = (j + 1) * dt;
     const size_t ld = (size_t)H * Mq;
     double *op = ops + (size_t)c * Mq * ld;
+    double Kd[9];  // drained elastic point kernel (left-hand-side operators only)
+    if (drained) point_kernel(X - sx, Y - sy, K.gc, Kd);
     for (int ci = 0; ci < 4; ++ci) {
         double q[3] = {ci == 0 ? 1.0 : 0.0, ci == 1 ? 1.0 : 0.0, ci == 2 ? 1.0 : 0.0};
         double o[4];
         transient(K, X - sx, Y - sy, t, q, ci == 3 ? 1.0 : 0.0, o);
+        if (drained && ci < 3)
+            for (int co = 0; co < 3; ++co) o[co] += Kd[co * 3 + ci];
         for (int co = 0; co < 4; ++co) op[(size_t)(co * p2 + tn) * ld + (size_t)j * Mq + ci * p2 + sn] = o[co];
     }
 }
@@ -621,7 +625,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                                                      const double *__restrict__ cx, const double *__restrict__ cy,
                                                      const double *__restrict__ cb, const double *__restrict__ sb,
                                                      const double *__restrict__ a, double t, PoroK K,
-                                                     double *__restrict__ blk)
+                                                     int drained, double *__restrict__ blk)
 {
     int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= npair) return;
@@ -642,6 +646,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const int jsrc = nbeg[nb + r] + (sv - npre[nb + r]);
     double B[12];
     elem_block(K, cx[tb + i], cy[tb + i], cx[jsrc], cy[jsrc], cb[jsrc], sb[jsrc], a[jsrc], t, B);
+    if (drained)  // the drained elastic element response, closed form
+        for (int c = 0; c < 2; ++c) {
+            double sxx = 0.0, syy = 0.0, sxy = 0.0;
+            elem_stress_add(cx[tb + i], cy[tb + i], cx[jsrc], cy[jsrc], cb[jsrc], sb[jsrc], a[jsrc],
+                            c == 0 ? 1.0 : 0.0, c == 1 ? 1.0 : 0.0, K.gc, sxx, syy, sxy);
+            B[c] += sxx;
+            B[3 + c] += syy;
+            B[6 + c] += sxy;
+        }
     double *o = blk + 12 * it_coff[k] + (int64_t)12 * v * nt + i;
     for (int q = 0; q < 12; ++q) o[(int64_t)q * nt] = B[q];
 }
@@ -852,6 +865,8 @@ int near_levels(fmddm_ctx *ctx, fmddm_tree *t, int H)
         for (auto &l : t->pn_lvl) t->bytes -= (int64_t)l->bytes();
         t->pn_lvl.clear();
         t->pn_hptr.clear();
+        if (t->pn_lhs_ok) t->bytes -= (int64_t)t->pn_lhs.bytes();
+        t->pn_lhs_ok = 0;
         int64_t budget = ctx->poro.near_cache_bytes;
         if (budget == 0) {
             size_t fr = 0, tot = 0;
@@ -877,7 +892,7 @@ int near_levels(fmddm_ctx *ctx, fmddm_tree *t, int H)
             hipLaunchKernelGGL(k_pnear_build, dim3(cdiv(t->near_pairs, 256)), dim3(256), 0, s, t->near_pairs,
                                t->nitem, t->it_coff.p, t->it_leaf.p, t->it_s0.p, t->dleaves.p, t->cpbeg.p,
                                t->cpend.p, t->noff.p, t->nbeg.p, t->npre.p, t->scx.p, t->scy.p, t->scb.p,
-                               t->ssb.p, t->sa.p, (j + 1) * ctx->poro.dt, K, b->p);
+                               t->ssb.p, t->sa.p, (j + 1) * ctx->poro.dt, K, 0, b->p);
             FM_CHECK_LAUNCH();
         }
         t->pn_hptr.resize(j);
@@ -888,6 +903,32 @@ int near_levels(fmddm_ctx *ctx, fmddm_tree *t, int H)
         t->pn_lvl.push_back(std::move(b));
     }
     return want;
+}
+
+// The left-hand side's near blocks (first level plus the drained elastic
+// part), built on first use when the budget holds two levels; returns
+// whether they are resident.
+bool near_lhs(fmddm_ctx *ctx, fmddm_tree *t)
+{
+    near_levels(ctx, t, 0);  // refreshes the key and the budget
+    if (t->pn_lhs_ok) return true;
+    if (t->pn_cap < 2) return false;
+    hipStream_t s = ctx->stream;
+    t->pn_lhs.alloc((size_t)12 * std::max<int64_t>(t->near_pairs, 1));
+    if (t->near_pairs > 0) {
+        hipLaunchKernelGGL(k_pnear_build, dim3(cdiv(t->near_pairs, 256)), dim3(256), 0, s, t->near_pairs, t->nitem,
+                           t->it_coff.p, t->it_leaf.p, t->it_s0.p, t->dleaves.p, t->cpbeg.p, t->cpend.p, t->noff.p,
+                           t->nbeg.p, t->npre.p, t->scx.p, t->scy.p, t->scb.p, t->ssb.p, t->sa.p, ctx->poro.dt,
+                           poro_constants(ctx), 1, t->pn_lhs.p);
+        FM_CHECK_LAUNCH();
+    }
+    if (t->pn_lhs_ptr.n < 1) t->pn_lhs_ptr.alloc(1);
+    t->pn_lhs_host = t->pn_lhs.p;
+    FM_HIP(hipMemcpyAsync(t->pn_lhs_ptr.p, &t->pn_lhs_host, sizeof(double *), hipMemcpyHostToDevice, s));
+    FM_HIP(hipStreamSynchronize(s));
+    t->bytes += (int64_t)t->pn_lhs.bytes();
+    t->pn_lhs_ok = 1;
+    return true;
 }
 
 // Schedule and operators of the multipole form for H time levels.
@@ -955,6 +996,7 @@ void poro_fmm_setup(fmddm_ctx *ctx, fmddm_tree *t, int H)
         t->pf_dt = pp.dt;
         for (int k = 0; k < 8; ++k) t->pf_key[k] = key[k];
         t->pf_H = 0;
+        t->pf_ops0_ok = 0;
         t->pf_G.alloc((size_t)ncell * Mq);
         t->pf_G.zero(s);
         t->pf_Z.alloc((size_t)std::max<int64_t>(t->nV, 1) * Mq);
@@ -974,7 +1016,7 @@ void poro_fmm_setup(fmddm_ctx *ctx, fmddm_tree *t, int H)
             int64_t work = (int64_t)p2 * p2 * Hn * t->pf_ncombo;
             hipLaunchKernelGGL(k_pops, dim3(cdiv(work, 256)), dim3(256), 0, s, t->pf_ncombo, t->pf_combo_lvl.p,
                                t->pf_combo_ox.p, t->pf_combo_oy.p, t->L, ctx->cheb->xbar.p, p, Hn, pp.dt, Mq,
-                               poro_constants(ctx), t->pf_ops.p);
+                               poro_constants(ctx), 0, t->pf_ops.p);
             FM_CHECK_LAUNCH();
         }
         t->pf_W.alloc((size_t)t->ncell * Hn * Mq);
@@ -985,6 +1027,26 @@ void poro_fmm_setup(fmddm_ctx *ctx, fmddm_tree *t, int H)
         t->pf_H = Hn;
         FM_HIP(hipStreamSynchronize(s));
     }
+}
+
+// The left-hand side's M2L operators (first level plus the drained elastic
+// point kernel), built once per operator set.
+void lhs_ops(fmddm_ctx *ctx, fmddm_tree *t)
+{
+    if (t->pf_ops0_ok) return;
+    if (t->pf_ncombo > 0) {
+        hipStream_t s = ctx->stream;
+        const int p = ctx->prm.p, p2 = p * p, Mq = t->pf_Mq;
+        t->pf_ops0.alloc((size_t)t->pf_ncombo * Mq * Mq);
+        t->pf_ops0.zero(s);
+        int64_t work = (int64_t)p2 * p2 * t->pf_ncombo;
+        hipLaunchKernelGGL(k_pops, dim3(cdiv(work, 256)), dim3(256), 0, s, t->pf_ncombo, t->pf_combo_lvl.p,
+                           t->pf_combo_ox.p, t->pf_combo_oy.p, t->L, ctx->cheb->xbar.p, p, 1, ctx->poro.dt, Mq,
+                           poro_constants(ctx), 1, t->pf_ops0.p);
+        FM_CHECK_LAUNCH();
+        FM_HIP(hipStreamSynchronize(s));
+    }
+    t->pf_ops0_ok = 1;
 }
 
 // out (mode 0: =, 1: -=) the sum over time levels j = 1..H of F_transient(j dt)
@@ -999,6 +1061,10 @@ void poro_fmm_sum(fmddm_ctx *ctx, fmddm_tree *t, int H, const double *E, bool dr
     hipStream_t s = ctx->stream;
     const int n = (int)t->n, p = ctx->prm.p, p2 = p * p, Mq = t->pf_Mq;
     PoroK K = poro_constants(ctx);
+    // the left-hand side F(dt) in one pass: operators and near blocks that
+    // include the drained elastic part (when the near budget holds them)
+    const bool fused = H == 1 && drained && jlo == 0 && near_lhs(ctx, t);
+    if (fused) lhs_ops(ctx, t);
     hipLaunchKernelGGL(k_pprep, dim3(cdiv(n, 256), H), dim3(256), 0, s, n, H, t->perm.p, E, t->scb.p, t->ssb.p,
                        t->pf_Q.p, t->pf_D3.p);
     FM_CHECK_LAUNCH();
@@ -1008,11 +1074,28 @@ void poro_fmm_sum(fmddm_ctx *ctx, fmddm_tree *t, int H, const double *E, bool dr
                            t->cpend.p, t->p2m_mat.p, t->pf_Q.p, n, p2, H, Mq, t->pf_W.p);
         FM_CHECK_LAUNCH();
         fmm_m2m4(ctx, t, H, H * Mq, Mq, t->pf_W.p, t->pf_part.p);
-        fmm_pair_gemm(s, t->pf_ntile, Mq, t->pf_ops.p, (size_t)Mq * t->pf_H * Mq, t->pf_H * Mq, H * Mq, t->pf_W.p,
-                      H * Mq, t->pf_tile_op.p, t->pf_tile_beg.p, t->pf_tile_end.p, t->pf_psrc.p, t->pf_pdst.p,
-                      t->pf_Z.p, Mq);
+        if (fused)
+            fmm_pair_gemm(s, t->pf_ntile, Mq, t->pf_ops0.p, (size_t)Mq * Mq, Mq, Mq, t->pf_W.p, Mq, t->pf_tile_op.p,
+                          t->pf_tile_beg.p, t->pf_tile_end.p, t->pf_psrc.p, t->pf_pdst.p, t->pf_Z.p, Mq);
+        else
+            fmm_pair_gemm(s, t->pf_ntile, Mq, t->pf_ops.p, (size_t)Mq * t->pf_H * Mq, t->pf_H * Mq, H * Mq,
+                          t->pf_W.p, H * Mq, t->pf_tile_op.p, t->pf_tile_beg.p, t->pf_tile_end.p, t->pf_psrc.p,
+                          t->pf_pdst.p, t->pf_Z.p, Mq);
         fmm_sum_pairs(s, t, t->pf_Z.p, Mq, Mq, t->pf_G.p, Mq);
         fmm_l2p4(ctx, t, t->pf_G.p, Mq, t->pf_far.p);
+    }
+    if (fused) {
+        hipLaunchKernelGGL(k_pnear, dim3(t->nitem), dim3(PN), 0, s, t->nitem, t->it_leaf.p, t->it_s0.p,
+                           t->it_s1.p, t->it_poff.p, t->it_coff.p, t->dleaves.p, t->cpbeg.p, t->cpend.p, t->noff.p,
+                           t->nbeg.p, t->npre.p, n, 0, 1, (const double *const *)t->pn_lhs_ptr.p, t->pf_D3.p,
+                           t->pf_near.p);
+        FM_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_pfinal, dim3(cdiv(n, 256)), dim3(256), 0, s, n, t->tleaf.p, t->dleaves.p, t->cpbeg.p,
+                           t->clevel.p, t->lk_off.p, t->it_poff.p, t->pf_near.p,
+                           far ? t->pf_far.p : (const double *)nullptr, t->scb.p, t->ssb.p, t->perm.p,
+                           (const double *)nullptr, mode, out);
+        FM_CHECK_LAUNCH();
+        return;
     }
     // near field: stored levels jlo .. Hc-1 as block-sparse products, the
     // rest integrated here
