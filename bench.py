@@ -561,7 +561,7 @@ def main():
     ap.add_argument("--precision-p", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs one instance per GPU and has no "
+        print("bench.py measures one GPU: the library runs one instance per GPU and has no "
               "multi-GPU path; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
