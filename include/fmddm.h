@@ -364,9 +364,12 @@ typedef struct {
                                  4 x 3 response blocks (96 bytes per near pair) are integrated
                                  once, on first use, and kept with the tree; later products at
                                  that level are block-sparse products.  Levels beyond the budget
-                                 are integrated on the fly at every product.  0: a quarter of
-                                 the free device memory at first use, at most 32 GiB; > 0: that
-                                 many bytes; < 0: no cache. */
+                                 are integrated on the fly at every product.  When the budget
+                                 holds two levels, the left-hand side F(dt) also gets its own
+                                 blocks with the drained elastic part added (one more level's
+                                 96 bytes per near pair), and is then one multipole pass.  0: a
+                                 quarter of the free device memory at first use, at most 32 GiB;
+                                 > 0: that many bytes; < 0: no cache. */
 } fmddm_poro_params;
 
 /* Attaches the poroelastic medium to the context (validated: EINVAL). */
