@@ -362,6 +362,8 @@ void pc_coarse_add(fmddm_ctx *ctx, fmddm_tree *t, const PcCoarse &C, int ncomp, 
 
 }  // namespace fmddm
 
+// The context's destructor lives here, beside the one user of its rocBLAS
+// handle (the coarse factorisation), so that no other file needs rocBLAS.
 fmddm_ctx::~fmddm_ctx()
 {
     if (blas) (void)rocblas_destroy_handle((rocblas_handle)blas);
