@@ -14,7 +14,14 @@ physics determine independently of the derivation:
   - element integrals: quadrature convergence, the two-halves identity, the
     point-source far-field limit;
   - time marching: telescoping of the history coefficients;
-  - the symmetric well cluster: zero shear DD on the middle fracture.
+  - the symmetric well cluster: zero shear DD on the middle fracture;
+  - the transient stress potential at intermediate times, which equilibrium
+    cannot see: the trace identity sxx + syy = -2 G eta p (fixes its
+    Laplacian, hence the radial factor of the DD part), boundedness of the
+    transient at the source, and the Biot reciprocal theorem between a DD's
+    pressure and a fluid source's stress (fixes the source's potential),
+    for points and for a symmetric element pair.  A 1 % error planted in
+    either radial factor fails these and none of the others.
 """
 import numpy as np
 import pytest
@@ -202,3 +209,94 @@ def test_matrix_rows_are_rows_of_the_matrix(po):
         R = O.poro_matrix_rows(g, po, 60.0, m, rows)
         idx = np.stack([3 * rows, 3 * rows + 1, 3 * rows + 2], 1).reshape(-1)
         assert np.array_equal(R, A[idx])
+
+
+# --------------------------------------------------------------------------
+# Pins of the transient stress potential at intermediate times.  The stress
+# of the transient part is 2G (grad grad phi - I lap phi) for some potential
+# phi, which is divergence-free for any phi, so equilibrium alone cannot see
+# an error in phi; these three relations can.
+# --------------------------------------------------------------------------
+Z_MID = [0.05, 0.2, 1.5, 5.0, 14.0]
+
+
+@pytest.mark.parametrize("z", Z_MID)
+def test_transient_trace_is_minus_2G_eta_p(po, z):
+    """Biot plane strain: the irrotational transient displacement carries a
+    volumetric strain alpha p / (lambda + 2G) = eta p, so the in-plane trace
+    of the transient stress is 2 (lambda + G) eta p - 2 alpha p
+    = -2 G eta p.  Holds at every z for displacement discontinuities and
+    for fluid sources alike."""
+    x, y = 0.8, 0.35
+    t = (x * x + y * y) / (4 * po.c * z)
+    for q, qf in [(c, 0.0) for c in CHARGES] + [(np.zeros(3), 1.0), (CHARGES[3], 2e-9)]:
+        s = O.poro_point(po, x, y, t, q, qf=qf, transient=True)
+        scale = max(np.abs(s[:3]).max(), 2 * po.G * po.eta * abs(s[3]))
+        assert abs(s[0] + s[1] + 2 * po.G * po.eta * s[3]) <= 1e-12 * scale, (z, q, qf)
+
+
+def test_transient_bounded_at_the_source(po):
+    """At a fixed time the transient part of a displacement discontinuity
+    (total minus drained) stays finite as the receiver approaches the
+    source: the singular part is the drained elastic field alone.  The
+    values converge as r -> 0."""
+    t = 600.0
+    ell = np.sqrt(4 * po.c * t)
+    for q in CHARGES:
+        prev, rprev = None, None
+        for rr in [1e-3, 1e-4, 1e-5, 1e-6]:
+            s = O.poro_point(po, 0.6 * rr * ell, 0.8 * rr * ell, t, q, transient=True)
+            assert np.all(np.isfinite(s))
+            if prev is not None:
+                # z = rr^2 and the approach is O(z): the step from rprev to rr
+                # changes the values by O(rprev^2)
+                assert np.abs(s - prev).max() <= 10 * rprev * rprev * np.abs(s).max(), (q, rr)
+            prev, rprev = s, rr
+        # and the limit is of the size of the field one diffusion length away
+        far = O.poro_point(po, 0.6 * ell, 0.8 * ell, t, q, transient=True)
+        assert np.abs(prev).max() <= 100 * np.abs(far).max()
+
+
+@pytest.mark.parametrize("z", Z_MID)
+def test_reciprocity_dd_pressure_vs_source_stress(po, z):
+    """Reciprocal theorem of Biot poroelasticity in the Laplace domain:
+    sigma1 : e2 + p1 zeta2 is symmetric in the two states (e the matrix
+    strain, zeta the fluid content), and for an infinite plane it gives,
+    for a point DD (eigenstrain charges q) held at y and a unit fluid source
+    rate held at x,
+        integral_0^t p_DD(x - y, tau) d tau = -sigma_src(y - x, t) : q.
+    This ties the fluid source's stress (its potential) to the DD's
+    pressure, which the diffusion and limit pins fix."""
+    x, y = 0.8, 0.35
+    t = (x * x + y * y) / (4 * po.c * z)
+    for q in CHARGES:
+        P = lambda tau: O.poro_point(po, x, y, tau, q, transient=True)[3]
+        lhs = integrate.quad(P, 0.0, t, epsabs=0, epsrel=1e-12, limit=200)[0]
+        f = O.poro_point(po, -x, -y, t, np.zeros(3), qf=1.0, transient=True)
+        rhs = -(f[0] * q[0] + f[1] * q[1] + f[2] * q[2])
+        scale = np.abs(f[:3]).max() * np.abs(q).max()
+        assert abs(lhs - rhs) <= 1e-9 * scale, (z, q, lhs, rhs)
+
+
+def test_reciprocity_symmetric_element_pair(po):
+    """The same reciprocity for two equal parallel elements (receiver at one
+    midpoint, source integrated over the other): with D_n = 1 on element 2
+    and a unit fluid source on element 1, the time integral of the pressure
+    at midpoint 1 equals minus the normal-charge stress at midpoint 2; and
+    the DD-to-stress and source-to-pressure blocks are symmetric."""
+    a, t = 0.1, 1800.0
+    cb, sb = np.cos(0.3), np.sin(0.3)
+    for d in [(0.35, 0.12), (0.0, 0.25), (0.7, 0.0)]:
+        x1, y1 = 0.0, 0.0
+        x2, y2 = d
+        q = np.zeros(3)
+        O.lib().ora_charge(cb, sb, 0.0, 1.0, O._p(q))     # charges of D_n = 1
+        P = lambda tau: O.poro_elem_transient(po, x1, y1, x2, y2, cb, sb, a, 0.0, 1.0, 0.0, tau)[3]
+        lhs = integrate.quad(P, 0.0, t, epsabs=0, epsrel=1e-11, limit=200)[0]
+        f = O.poro_elem_transient(po, x2, y2, x1, y1, cb, sb, a, 0.0, 0.0, 1.0, t)
+        rhs = -(f[0] * q[0] + f[1] * q[1] + f[2] * q[2])
+        assert abs(lhs - rhs) <= 1e-8 * np.abs(f[:3]).max(), (d, lhs, rhs)
+        for Ds, Dn, Dq in [(1e-3, 0.0, 0.0), (0.0, 1e-3, 0.0), (0.0, 0.0, 1e-9)]:
+            s12 = O.poro_elem_transient(po, x1, y1, x2, y2, cb, sb, a, Ds, Dn, Dq, t)
+            s21 = O.poro_elem_transient(po, x2, y2, x1, y1, cb, sb, a, Ds, Dn, Dq, t)
+            assert np.abs(s12 - s21).max() <= 1e-11 * np.abs(s12).max(), (d, Ds, Dn, Dq)
