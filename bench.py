@@ -39,52 +39,59 @@ FLOP_PER_PAIR = 78
 
 def phase_work(info, p, tree, rank, svd):
     """Algorithmic work of each kernel of one FMM product:
-    (bound, amount, unit, peak).  Flops count +,-,* as 1 and a fused
+    (bound, amount, unit, peak, executed).  `amount` is the method's own
+    count (the per-unit figures of the bbFMM steps, eqs. 3.6-3.11);
+    `executed` is what the kernel computes where its restructuring differs
+    (None where it is the same).  Flops count +,-,* as 1 and a fused
     multiply-add as 2; bytes are the compulsory HBM traffic."""
     n = info["n"]
-    M = 3 * p * p
-    lev, leaf = tree["level"], tree["isleaf"]
-    internal = int(((lev >= 2) & (leaf == 0)).sum())
+    c = 3                      # charge / field components per node
+    M = c * p * p
     nleaf, nfar, nV = info["nleaf"], info["nfar"], info["nV"]
     hbm, mfma, alu = PEAK["hbm_GBps"], PEAK["fp64_mfma_TFLOPs"], PEAK["fp64_vector_TFLOPs"]
-    slots = 4 if p <= 24 else 2
+    # child-to-parent transfers of the upward pass (cells whose parent has
+    # an expansion); the downward pass has the same number of L2L transfers
+    transfers = info["m2m_pairs"]
+    lev, leaf = tree["level"], tree["isleaf"]
+    parents = int(((lev >= 2) & (leaf == 0)).sum())
     work = {
         # D in, sorted D and charges out, permutation, orientation
-        "prep": ("hbm", 76.0 * n, "GB/s", hbm),
+        "prep": ("hbm", 76.0 * n, "GB/s", hbm, None),
         # eq. 3.6: the per-element anterpolation matrices streamed once, the
         # charges, the leaf weights written
-        "p2m": ("hbm", 8.0 * p * p * n + 24.0 * n + 8.0 * M * nleaf, "GB/s", hbm),
-        # eq. 3.7 per (ancestor, leaf) pair: the two p x p composite
-        # transfers applied to 3 components (12 p^3), plus forming them
-        # (2p barycentric interpolants of about 6p flops)
-        "m2m": ("alu", (12.0 * p ** 3 + 12.0 * p * p) * info["m2m_pairs"], "TFLOP/s", alu),
-        # item partials read once, the weights of internal cells written once
-        "m2m_sum": ("hbm", 8.0 * M * (-(-info["m2m_pairs"] // slots) + internal), "GB/s", hbm),
-        # eqs. 3.9-3.11: every (midpoint, ancestor) pair evaluates that
-        # ancestor's field there: two barycentric interpolants (about 6p
-        # each) and the 3-component p x p contraction (6p^2 + 6p)
-        "l2p": ("alu", (6.0 * p * p + 18.0 * p) * info["l2p_pairs"], "TFLOP/s", alu),
-        "p2p": ("alu", float(FLOP_PER_PAIR) * info["near_pairs"], "TFLOP/s", alu),
+        "p2m": ("hbm", 8.0 * p * p * n + 24.0 * n + 8.0 * M * nleaf, "GB/s", hbm, None),
+        # eq. 3.7: two p x p passes over c components per child transfer,
+        # 4 p^3 c; the kernel shares the y pass of children with equal y side
+        # (a p^3 c x pass per child and two 2 p^3 c y passes per parent)
+        "m2m": ("alu", 4.0 * p ** 3 * c * transfers, "TFLOP/s", alu,
+                2.0 * p ** 3 * c * transfers + 4.0 * p ** 3 * c * parents),
+        # eqs. 3.9-3.11: an L2L transfer per child (4 p^3 c) and the p^2-node
+        # interpolation at every midpoint (2 p^2 c); the kernel evaluates
+        # every ancestor's field at the midpoint directly: two barycentric
+        # interpolants (about 6p each) and the c-component p x p contraction
+        "l2p": ("alu", 4.0 * p ** 3 * c * transfers + 2.0 * p * p * c * n, "TFLOP/s", alu,
+                (6.0 * p * p + 18.0 * p) * info["l2p_pairs"]),
+        "p2p": ("alu", float(FLOP_PER_PAIR) * info["near_pairs"], "TFLOP/s", alu, None),
         # far and near stress in, geometry and permutation, tractions out
-        "final": ("hbm", 80.0 * n, "GB/s", hbm),
+        "final": ("hbm", 80.0 * n, "GB/s", hbm, None),
     }
     if svd:
         # projections in and out of the rank-r space, one per far cell, and
         # the r x r operator product per interaction pair (eq. 3.8)
-        work["compress"] = ("mfma", 2.0 * rank * M * nfar, "TFLOP/s", mfma)
-        work["compress_sum"] = ("hbm", 8.0 * rank * nfar * 5, "GB/s", hbm)
-        work["m2l"] = ("mfma", 2.0 * rank * rank * nV, "TFLOP/s", mfma)
-        work["m2l_sum"] = ("hbm", 8.0 * rank * (nV + nfar), "GB/s", hbm)
-        work["decompress"] = ("mfma", 2.0 * rank * M * nfar, "TFLOP/s", mfma)
+        work["compress"] = ("mfma", 2.0 * rank * M * nfar, "TFLOP/s", mfma, None)
+        work["compress_sum"] = ("hbm", 8.0 * rank * nfar * 5, "GB/s", hbm, None)
+        work["m2l"] = ("mfma", 2.0 * rank * rank * nV, "TFLOP/s", mfma, None)
+        work["m2l_sum"] = ("hbm", 8.0 * rank * (nV + nfar), "GB/s", hbm, None)
+        work["decompress"] = ("mfma", 2.0 * rank * M * nfar, "TFLOP/s", mfma, None)
     else:
-        work["m2l"] = ("mfma", 2.0 * M * M * nV, "TFLOP/s", mfma)
-        work["m2l_sum"] = ("hbm", 8.0 * M * (nV + nfar), "GB/s", hbm)
+        work["m2l"] = ("mfma", 2.0 * M * M * nV, "TFLOP/s", mfma, None)
+        work["m2l_sum"] = ("hbm", 8.0 * M * (nV + nfar), "GB/s", hbm, None)
     return work
 
 
 def kernel_name(phase, p):
     """The library kernel behind each profiled launch."""
-    return {"prep": "k_prep", "p2m": "k_p2m", "m2m": f"k_m2m<{p}, 3>", "m2m_sum": "k_m2m_sum",
+    return {"prep": "k_prep", "p2m": "k_p2m", "m2m": f"k_m2m<{p}, 3>",
             "compress": "k_ggemm<32, 32, *> (projection)", "compress_sum": "k_reduce_split<double>",
             "m2l": "k_ggemm<64, 32, *> (pair products)", "m2l_sum": "k_sum_pairs<double, double>",
             "decompress": "k_ggemm<64, 32, *> (back-projection)", "l2p": f"k_l2p<{p}, 3>",
@@ -104,7 +111,7 @@ def kernel_source_hash():
 
 
 def traffic_for(phase):
-    """HBM bytes per launch from the committed rocprofv3 counter summary,
+    """HBM bytes per product from the committed rocprofv3 counter summary,
     or None when absent or taken on different kernel sources."""
     path = os.path.join(ROOT, "profiles", "traffic_c2.json")
     if not os.path.exists(path):
@@ -113,7 +120,10 @@ def traffic_for(phase):
         d = json.load(f)
     if d.get("source_hash") != kernel_source_hash():
         return None
-    return d.get("phases", {}).get(phase, {}).get("bytes_per_launch")
+    ph = d.get("phases", {}).get(phase, {})
+    # per product, like the roofline's work and time (the upward pass is
+    # several launches per product)
+    return ph.get("bytes_per_product", ph.get("bytes_per_launch"))
 
 
 # direct_below: the exact on-the-fly product beats the FMM's chain of
@@ -289,7 +299,7 @@ def history_leg(F, W, elems, steps, p=10):
     return out
 
 
-def precision_leg(F, W, steps, tune, leaf, p, solve_tol=1e-8, target_err=1e-6):
+def precision_leg(F, W, steps, tune, leaf, p, solve_tol=1e-8, target_err=1e-6, solves=True):
     """Mixed precision at N=200000 (2000 random fractures x 100 elements,
     seed 4): autotuned leaf and p for the FP64 product, then products and
     solves at FP64, FP32 and BF16-M2L on that configuration (two-level
@@ -346,6 +356,10 @@ def precision_leg(F, W, steps, tune, leaf, p, solve_tol=1e-8, target_err=1e-6):
         F.fmddm_profile(prob.ctx, 0)
         r["phase_ms"] = {k: v[0] / 3 for k, v in ph.items() if v[1] > 0}   # per product
         y[name] = o.cpu().numpy()
+        if not solves:              # products only (profiling runs)
+            prob.close()
+            res[name] = r
+            continue
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         xs, info = prob.solve(b)
@@ -383,6 +397,9 @@ def precision_leg(F, W, steps, tune, leaf, p, solve_tol=1e-8, target_err=1e-6):
         else:
             prob.close()
         res[name] = r
+    if not solves:
+        out["precisions"] = res
+        return out
     # exact (on-the-fly FP64) products on the GPU
     ex = ref.apply(D, F.FMDDM_APPLY_DIRECT)
     torch.cuda.synchronize()
@@ -413,24 +430,26 @@ def precision_leg(F, W, steps, tune, leaf, p, solve_tol=1e-8, target_err=1e-6):
     return out
 
 
-def march_leg(F, W, elems, steps, p=10, restart=100, precond=2, coarse=0):
-    """A full poroelastic time march (the horizontal-well example's shape,
-    Section 5.2.1): 5 fractures of `elems` 0.2 m elements 10 m apart, `steps`
-    steps of 60 s, every step's history sum and GMRES solve (tol 1e-6,
-    the given restart and preconditioner: 2 two-level, 1 block-Jacobi) on
-    the multipole operators."""
+def march_run(F, W, elems, steps, p, restart, precond, coarse, tol, keep=()):
+    """One poroelastic time march (the horizontal-well example's shape,
+    Section 5.2.1): 5 fractures of `elems` 0.2 m elements 10 m apart,
+    `steps` steps of 60 s, every step's history sum and GMRES solve (the
+    given tolerance, restart and preconditioner: 2 two-level, 1
+    block-Jacobi) on the multipole operators.  Returns the timings and the
+    DDs (caller order, [D_s, D_n, D_q] per element) after the steps in
+    `keep`."""
     import torch
     wl = W.well_cluster(n_frac=5, elems=elems, half_length=0.1 * elems, spacing=10.0)
     n3 = 3 * wl.n
-    prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=20e9, nu=0.2, p=p, leaf=32, m2l=1, m2l_tol=1e-10, tol=1e-6,
-                     restart=restart, maxit=20000, precond=precond, coarse_aggregates=coarse)
+    prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=20e9, nu=0.2, p=p, leaf=32, m2l=1, m2l_tol=1e-10, tol=tol,
+                     restart=restart, maxit=40000, precond=precond, coarse_aggregates=coarse)
     F.fmddm_poro_set(prob.ctx, 0.35, 0.8, 1e-18, 1e-3, 60.0, 48.26e6, mode=F.FMDDM_APPLY_FMM)
     b0 = torch.zeros(n3, dtype=torch.float64, device="cuda")
     F.fmddm_poro_rhs(prob.ctx, prob.tree, torch.as_tensor(wl.pressure).cuda(), wl.SH, wl.Sh, b0)
     hist = torch.zeros(steps * n3, dtype=torch.float64, device="cuda")
     D = torch.zeros(n3, dtype=torch.float64, device="cuda")
     th = tsv = 0.0
-    its, worst, per_step = 0, 0.0, []
+    its, worst, per_step, kept = 0, 0.0, [], {}
     torch.cuda.synchronize()
     t_all = time.perf_counter()
     for h in range(1, steps + 1):
@@ -450,18 +469,52 @@ def march_leg(F, W, elems, steps, p=10, restart=100, precond=2, coarse=0):
         its += info["iters"]
         per_step.append(info["iters"])
         worst = max(worst, info["relres"])
+        if h in keep:
+            kept[h] = D.cpu().numpy().reshape(-1, 3).copy()
         if wl.n > 5000:
-            print(f"march step {h}: {info['iters']} products, {t2 - t0:.2f} s", file=sys.stderr, flush=True)
+            print(f"march (tol {tol:g}) step {h}: {info['iters']} products, {t2 - t0:.2f} s", file=sys.stderr,
+                  flush=True)
     total = time.perf_counter() - t_all
     Dm = D.cpu().numpy().reshape(-1, 3)
-    mid = Dm[2 * elems: 3 * elems]
     prob.close()
-    return {"workload": f"well cluster 5 x {elems} elements (N={wl.n}), {steps} steps of 60 s", "p": p,
-            "restart": restart, "precond": {1: "block-Jacobi", 2: "two-level"}[precond],
-            "gmres_products_per_step": per_step,
-            "total_s": total, "history_s": th, "solve_s": tsv, "gmres_products": its,
-            "max_step_relres": worst,
-            "middle_fracture_max_shear_over_opening": float(np.abs(mid[:, 0]).max() / np.abs(Dm[:, 1]).max())}
+    return {"total_s": total, "history_s": th, "solve_s": tsv, "gmres_products": its, "per_step": per_step,
+            "max_step_relres": worst, "last": Dm, "kept": kept, "n": wl.n}
+
+
+def middle_ratio(Dm, elems):
+    """max |D_s| on the middle fracture over max |D_n| of the cluster (the
+    stack is symmetric about it, so its shear is zero, Section 5.2.1)."""
+    mid = Dm[2 * elems: 3 * elems]
+    return float(np.abs(mid[:, 0]).max() / np.abs(Dm[:, 1]).max())
+
+
+def march_leg(F, W, elems, steps, p=10, restart=100, precond=2, coarse=0, ref_tol=1e-10):
+    """The full C3 march at GMRES tol 1e-6 (the paper's), timed, and the
+    same march at ref_tol as the reference its accuracy is measured
+    against: per component (D_s, D_n, D_q) the largest difference over the
+    largest reference value, after steps 1, 10 and the last; and the middle
+    fracture's shear over the opening for both."""
+    keep = tuple(sorted({1, min(10, steps), steps}))
+    run = march_run(F, W, elems, steps, p, restart, precond, coarse, 1e-6, keep)
+    out = {"workload": f"well cluster 5 x {elems} elements (N={run['n']}), {steps} steps of 60 s", "p": p,
+           "restart": restart, "precond": {1: "block-Jacobi", 2: "two-level"}[precond], "tol": 1e-6,
+           "gmres_products_per_step": run["per_step"], "total_s": run["total_s"], "history_s": run["history_s"],
+           "solve_s": run["solve_s"], "gmres_products": run["gmres_products"],
+           "max_step_relres": run["max_step_relres"],
+           "middle_fracture_max_shear_over_opening": middle_ratio(run["last"], elems)}
+    if ref_tol:
+        ref = march_run(F, W, elems, steps, p, restart, precond, coarse, ref_tol, keep)
+        acc = {}
+        for h in keep:
+            a, r = run["kept"][h], ref["kept"][h]
+            acc[f"step_{h}"] = {name: float(np.abs(a[:, k] - r[:, k]).max() / np.abs(r[:, k]).max())
+                                for k, name in enumerate(("D_s", "D_n", "D_q"))}
+        out["accuracy_vs_reference"] = {
+            "reference_tol": ref_tol, "reference_total_s": ref["total_s"],
+            "reference_gmres_products": ref["gmres_products"],
+            "max_diff_over_max_ref": acc,
+            "reference_middle_fracture_max_shear_over_opening": middle_ratio(ref["last"], elems)}
+    return out
 
 
 def p_sweep_leg(F, W, ps, reps=50):
@@ -509,22 +562,132 @@ def p_sweep_leg(F, W, ps, reps=50):
     return out
 
 
-def cpu_baseline(wl, D, seconds):
-    """The oracle's exact on-the-fly product of the whole workload on all
-    host cores, repeated for about `seconds` of wall time."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, D, seconds, fmm_p=6):
+    """The oracle on the host: its exact on-the-fly product of the whole
+    workload on all host cores, repeated for about `seconds` of wall time
+    (the reported value); the same product on one thread over 1000 rows
+    (scaled to whole products); and the oracle's level-by-level FMM at
+    p = fmm_p (the paper's six Chebyshev nodes, Section 5.2) on one
+    thread."""
     import oracle as O
     g = O.Geometry.of(wl)
     O.direct_matvec_rows(g, D, [0])  # load the library
-    reps, t0 = 0, time.perf_counter()
+    cores = O.num_threads()
+    reps, times, t0 = 0, [], time.perf_counter()
     while True:
+        t1 = time.perf_counter()
         O.direct_matvec(g, D)
+        times.append(time.perf_counter() - t1)
         reps += 1
         dt = time.perf_counter() - t0
         if dt >= seconds:
             break
-    return {"value": reps / dt, "unit": "matvecs/s", "cores": O.num_threads(), "kind": "oracle",
-            "sample": f"oracle exact on-the-fly product of the full workload (N={g.n}), "
-                      f"{reps} products in {dt:.1f} s wall"}
+    prev = O.set_num_threads(1)
+    try:
+        rows = min(1000, g.n)
+        t1 = time.perf_counter()
+        O.direct_matvec(g, D, rows=(0, rows))
+        t_rows = time.perf_counter() - t1
+        T = O.Tree(g, leaf=32)
+        t1 = time.perf_counter()
+        T.fmm(D, fmm_p)
+        t_fmm = time.perf_counter() - t1
+    finally:
+        O.set_num_threads(prev)
+    ms = np.array(times) * 1e3
+    return {"value": reps / dt, "unit": "matvecs/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": f"oracle exact on-the-fly product of the full workload (N={g.n}) on {cores} threads, "
+                      f"{reps} products in {dt:.1f} s wall",
+            "product_ms_median": float(np.median(ms)), "product_ms_p90": float(np.percentile(ms, 90)),
+            "single_thread_exact_matvecs_per_s": rows / g.n / t_rows,
+            "single_thread_exact_sample": f"{rows} of {g.n} rows in {t_rows:.2f} s, scaled to whole products",
+            "oracle_fmm_single_thread": {"p": fmm_p, "leaf": 32, "seconds_per_product": t_fmm,
+                                         "note": "level-by-level bbFMM with dense M2L, plain C"}}
+
+
+def c1_leg(F, W, reps=200, solve_reps=5, cpu=True):
+    """C1, the pressurized Griffith crack (N = 256; Section 2.1, eq. 2.6):
+    microseconds per product (stored dense matrix, on-the-fly exact, FMM at
+    the library's default p = 20 and leaf 32), GMRES(50) to 1e-10 from zero
+    on each (median of `solve_reps` solves), the opening's relative L2
+    error against Sneddon's ellipse and K_I by eq. 2.6 against
+    p sqrt(pi a); with `cpu`, the oracle's dense assembly and GMRES(50)
+    solve on one thread and on all host cores."""
+    import torch
+    wl = W.c1()
+    n, pr, a = wl.n, wl.meta["p"], wl.meta.get("a", 1.0)
+    prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=wl.E, nu=wl.nu, tol=1e-10, restart=50)
+    out = {"workload": f"Griffith crack, a = {a} m, N = {n}, p = {pr / 1e6:.0f} MPa, E = {wl.E / 1e9:.0f} GPa, "
+                       f"nu = {wl.nu}", "gmres": "restart 50, tol 1e-10, x0 = 0"}
+    try:
+        D = prob.vec(W.random_vector(1, n))
+        o = prob.vec()
+        b = prob.rhs(wl.pressure, 0.0, 0.0)
+        xm = 0.5 * (wl.x1 + wl.x2)
+        w_exact = 4.0 * (1.0 - wl.nu ** 2) * pr / wl.E * np.sqrt(np.maximum(a * a - xm * xm, 0.0))
+        K_exact = pr * np.sqrt(np.pi * a)
+        for name, mode in (("dense", F.FMDDM_APPLY_DENSE), ("direct", F.FMDDM_APPLY_DIRECT),
+                           ("fmm", F.FMDDM_APPLY_FMM)):
+            prob.apply(D, mode, o)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                prob.apply(D, mode, o)
+            torch.cuda.synchronize()
+            us = (time.perf_counter() - t0) / reps * 1e6
+            prob.solve(b, mode)
+            ts = []
+            for _ in range(solve_reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                x, info = prob.solve(b, mode)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            xn = x.cpu().numpy()
+            KI, KII = F.fmddm_sif(prob.ctx, prob.tree, x, n - 1)
+            out[name] = {"us_per_product": us, "solve_ms_median": float(np.median(ts)) * 1e3,
+                         "gmres_iters": info["iters"], "relres": info["relres"],
+                         "sneddon_rel_l2": float(np.linalg.norm(xn[1::2] - w_exact) / np.linalg.norm(w_exact)),
+                         "KI_over_exact": KI / K_exact}
+    finally:
+        prob.close()
+    if cpu:
+        import oracle as O
+        g = O.Geometry.of(wl)
+        bo = O.rhs(g, wl.pressure, 0.0, 0.0)
+        res = {}
+        for label, th in (("1_thread", 1), ("all_cores", 0)):
+            prev = O.set_num_threads(th)
+            try:
+                cores = O.num_threads()
+                ta, tsv = [], []
+                for _ in range(3):
+                    t0 = time.perf_counter()
+                    A = O.dense_matrix(g)
+                    t1 = time.perf_counter()
+                    xo, info = O.gmres_dense(A, bo, restart=50, tol=1e-10)
+                    t2 = time.perf_counter()
+                    ta.append(t1 - t0)
+                    tsv.append(t2 - t1)
+            finally:
+                O.set_num_threads(prev)
+            res[label] = {"threads": cores, "assembly_ms_median": float(np.median(ta)) * 1e3,
+                          "solve_ms_median": float(np.median(tsv)) * 1e3, "gmres_iters": info["iters"]}
+        res["cpu_model"] = cpu_model()
+        out["oracle_cpu"] = res
+    return out
 
 
 def main():
@@ -538,6 +701,8 @@ def main():
     ap.add_argument("--m2l", choices=["svd", "dense"], default="svd")
     ap.add_argument("--m2l-tol", type=float, default=1e-12)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--c1-reps", type=int, default=200,
+                    help="products timed per mode on the Griffith crack, C1 (0 skips the leg)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=48)
@@ -552,11 +717,14 @@ def main():
                     help="poroelastic time steps of the full-march leg (0 skips it)")
     ap.add_argument("--march-restart", type=int, default=100)
     ap.add_argument("--march-precond", type=int, default=2, choices=[1, 2])
+    ap.add_argument("--march-ref-tol", type=float, default=1e-10,
+                    help="GMRES tol of the reference march the C3 accuracy is measured against (0: none)")
     ap.add_argument("--p-sweep", type=str, default="",
                     help="comma-separated Chebyshev orders for the accuracy/time sweep (off by default)")
     ap.add_argument("--precision-steps", type=int, default=20,
                     help="products timed per precision at N=200000 (0 skips the mixed-precision leg)")
     ap.add_argument("--precision-no-tune", action="store_true")
+    ap.add_argument("--precision-no-solve", action="store_true", help="products only (profiling runs)")
     ap.add_argument("--precision-leaf", type=int, default=64)
     ap.add_argument("--precision-p", type=int, default=10)
     args = ap.parse_args()
@@ -624,6 +792,16 @@ def main():
     dom_ms = dom_tot / args.steps          # kernel time per product
     value = args.steps / elapsed
     y_fmm = out.cpu().numpy()
+    # distribution of single products: HIP events on the stream the
+    # product runs on (the near field's side stream joins back into it)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(min(args.steps, 200))]
+    for e0, e1 in evs:
+        e0.record()
+        prob.apply(D, F.FMDDM_APPLY_FMM, out)
+        e1.record()
+    torch.cuda.synchronize()
+    one = np.array([e0.elapsed_time(e1) for e0, e1 in evs])
 
     # exact products on the same GPU
     exact = {}
@@ -647,7 +825,7 @@ def main():
     work = phase_work(info, args.p, tree, info["m2l_rank"], svd)
     scale = {"GB/s": 1e9, "TFLOP/s": 1e12}
     phases = {}
-    for ph, (bound, amount, unit, peak) in work.items():
+    for ph, (bound, amount, unit, peak, executed) in work.items():
         ms = phase_ms.get(ph, 0.0)
         if ms <= 0:
             continue
@@ -655,11 +833,19 @@ def main():
         phases[ph] = {"ms": ms, "launches": phase_launches.get(ph), "bound": bound, "work": amount,
                       "achieved": ach, "unit": unit, "frac": ach / peak if ach else None,
                       "frac_measured": ach / measured[bound] if ach else None}
-    bound, amount, unit, peak = work[dom]
+        if executed is not None:
+            phases[ph]["work_executed"] = executed
+    bound, amount, unit, peak, executed = work[dom]
+    # launches of the dominant kernel per product (the upward pass is one
+    # launch per schedule step)
+    dom_launches = info["m2m_launches"] if dom == "m2m" else 1
     achieved = amount / (dom_ms * 1e-3) / scale[unit]
     roof = {"bound": bound, "kernel": kernel_name(dom, args.p), "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": traffic_for(dom), "ms_per_product": dom_ms,
-            "avg_launch_ms": dom_tot / max(dom_cnt, 1), "peak_measured": measured[bound],
+            "frac": achieved / peak, "traffic": traffic_for(dom), "work": amount,
+            "work_basis": "per product: the bbFMM step's own per-unit count (eqs. 3.6-3.11) x units",
+            "work_executed": executed, "ms_per_product": dom_ms,
+            "launches_per_product": dom_launches,
+            "avg_launch_ms": dom_ms / dom_launches, "peak_measured": measured[bound],
             "frac_measured": achieved / measured[bound]}
 
     line = {
@@ -686,6 +872,7 @@ def main():
             "fmm_over_direct": value / exact["direct"],
             "fmm_rel_err_vs_exact": err,
         },
+        "product_ms_median": float(np.median(one)), "product_ms_p90": float(np.percentile(one, 90)),
         "phases": phases,
         "tree_build_ms": tree_ms,
         "first_product_setup_ms": setup_ms,
@@ -697,6 +884,8 @@ def main():
                            "kernels": "FP64 FMA loop, FP64 16x16x4 MFMA loop, 1 GiB device copy"},
     }
     prob.close()
+    if args.c1_reps > 0:
+        line["c1"] = c1_leg(F, W, args.c1_reps, cpu=not args.no_cpu_baseline)
     if args.serve_requests > 0:
         line["serving"] = serving_leg(F, W, args.serve_requests, args.serve_slots, args.serve_load)
     if args.history_elems > 0:
@@ -705,10 +894,11 @@ def main():
         line["p_sweep"] = p_sweep_leg(F, W, [int(q) for q in args.p_sweep.split(",")])
     if args.march_steps > 0:
         line["march"] = march_leg(F, W, args.march_elems, args.march_steps, restart=args.march_restart,
-                                  precond=args.march_precond)
+                                  precond=args.march_precond, ref_tol=args.march_ref_tol)
     if args.precision_steps > 0:
         line["mixed_precision"] = precision_leg(F, W, args.precision_steps, not args.precision_no_tune,
-                                                args.precision_leaf, args.precision_p)
+                                                args.precision_leaf, args.precision_p,
+                                                solves=not args.precision_no_solve)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(wl, Dh, args.cpu_seconds)
     print(json.dumps(line), flush=True)

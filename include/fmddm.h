@@ -145,11 +145,14 @@ typedef struct {
     int64_t nU, nV, nW, nX;   /* list lengths (sum over cells) */
     int64_t near_pairs;       /* directly evaluated point pairs per product */
     int64_t l2p_pairs;        /* (midpoint, ancestor cell) interpolations per product */
-    int64_t m2m_pairs;        /* (ancestor cell, leaf) composite transfers per product */
+    int64_t m2m_pairs;        /* child-to-parent transfers of the upward pass per product (cells
+                                 whose parent is at level >= 2); the downward pass has as many */
     int64_t nfar;             /* cells at level >= 2 (those with interaction lists) */
     int64_t m2l_rank;         /* M2L rank (3p^2 when uncompressed; 0 before the first product) */
     double root_x0, root_y0, root_L;
     int64_t device_bytes;     /* device memory held by the tree */
+    int64_t m2m_launches;     /* launches of the upward pass per product (0 before the first product) */
+    int32_t m2m_cut;          /* level below which each subtree's upward pass runs in one block */
 } fmddm_tree_info;
 
 typedef struct {

@@ -88,6 +88,7 @@ def lib():
         L.ora_fmm_apply.argtypes = ([C.c_void_p] + [_d] * 5 + [C.c_double] * 2 +
                                     [C.c_int, C.c_int, _d, _d])
         L.ora_fmm_apply.restype = C.c_int
+        L.ora_set_num_threads.argtypes = [C.c_int]
         L.ora_poro_consts.argtypes = [C.c_double] * 6 + [_d]
         L.ora_E1.argtypes = [C.c_double]
         L.ora_E1.restype = C.c_double
@@ -121,7 +122,9 @@ class Geometry:
         self.cx = _f64(0.5 * (x1 + x2))
         self.cy = _f64(0.5 * (y1 + y2))
         dx, dy = x2 - x1, y2 - y1
-        ln = np.hypot(dx, dy)
+        # separately rounded squares, sum and square root (the device path
+        # computes the half-length, which decides tree splits, the same way)
+        ln = np.sqrt(dx * dx + dy * dy)
         self.cb = _f64(dx / ln)
         self.sb = _f64(dy / ln)
         self.a = _f64(0.5 * ln)
@@ -334,6 +337,15 @@ class Tree:
 def num_threads() -> int:
     """Host threads the oracle's parallel loops use."""
     return int(lib().ora_num_threads())
+
+
+def set_num_threads(n: int) -> int:
+    """Use n threads in the parallel loops (n <= 0: one per processor);
+    returns the previous count.  Timing only: the loops parallelise over
+    independent rows, so results do not depend on it."""
+    prev = num_threads()
+    lib().ora_set_num_threads(int(n))
+    return prev
 
 
 # --------------------------------------------------------------------------

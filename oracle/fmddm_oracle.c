@@ -1314,6 +1314,9 @@ void ora_poro_matrix_rows(int64_t n, const double *cx, const double *cy,
 #ifdef _OPENMP
 #include <omp.h>
 int ora_num_threads(void) { return omp_get_max_threads(); }
+/* Threads of the parallel loops from here on (n <= 0: one per processor);
+ * timing only, no arithmetic depends on it. */
+void ora_set_num_threads(int n) { omp_set_num_threads(n > 0 ? n : omp_get_num_procs()); }
 #else
 int ora_num_threads(void) { return 1; }
 #endif

@@ -69,7 +69,7 @@ class TreeInfo(C.Structure):
         ("nfar", C.c_int64),
         ("m2l_rank", C.c_int64),
         ("root_x0", C.c_double), ("root_y0", C.c_double), ("root_L", C.c_double),
-        ("device_bytes", C.c_int64),
+        ("device_bytes", C.c_int64), ("m2m_launches", C.c_int64), ("m2m_cut", C.c_int32),
     ]
 
 

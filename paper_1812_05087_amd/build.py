@@ -21,6 +21,9 @@ FLAGS = [
     "-I", os.path.join(ROOT, "include"),
 ]
 LIBS = ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
+# per-source flags: the tree's floating-point decisions must not depend on
+# FMA contraction (hipcc contracts by default, whatever a pragma says)
+FILE_FLAGS = {"tree.hip": ["-ffp-contract=off"]}
 
 
 def build(verbose: bool = False, jobs: int = 0) -> str:
@@ -33,7 +36,7 @@ def build(verbose: bool = False, jobs: int = 0) -> str:
 
     def compile_one(src):
         obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
-        cmd = [HIPCC, *cflags, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC, *cflags, *FILE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)

@@ -12,28 +12,10 @@ void sif_eval(fmddm_ctx *ctx, fmddm_tree *t, const double *D, int64_t e, double 
 }
 
 using fmddm::Error;
+using fmddm::guarded;
 
 namespace {
 
-template <class F>
-fmddm_status guarded(fmddm_ctx *ctx, F &&f)
-{
-    try {
-        FM_HIP(hipSetDevice(ctx->device));
-        fmddm_status st = f();
-        if (ctx) ctx->err.clear();
-        return st;
-    } catch (const Error &e) {
-        if (ctx) ctx->err = e.msg;
-        return e.code;
-    } catch (const std::bad_alloc &) {
-        if (ctx) ctx->err = "host allocation failed";
-        return FMDDM_ENOMEM;
-    } catch (...) {
-        if (ctx) ctx->err = "unexpected error";
-        return FMDDM_EDEVICE;
-    }
-}
 
 const char *check_params(const fmddm_params *p)
 {
@@ -184,6 +166,8 @@ fmddm_status fmddm_tree_get_info(fmddm_ctx *ctx, const fmddm_tree *t, fmddm_tree
     add(t->Zm2l.bytes()); add(t->q.bytes()); add(t->Dsort.bytes()); add(t->Adense.bytes());
     add(t->gm_V.bytes()); add(t->gm_w.bytes()); add(t->gm_r.bytes());
     info->device_bytes = b;
+    info->m2m_launches = (int64_t)t->m2m_launch.size();
+    info->m2m_cut = t->m2m_cut;
     return FMDDM_OK;
 }
 

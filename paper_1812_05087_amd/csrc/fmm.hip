@@ -209,212 +209,152 @@ __global__ __launch_bounds__(256) void k_p2m(int nleaf, const int *__restrict__ 
     }
 }
 
-// D (R x C) = A (R x K) . B (K x C) by one wave on FP64 MFMA 16x16x4, the
-// operands read through a(i, k) and b(k, j) (zero outside the shape) and the
-// result handed to st(i, j, v) after every operand has been read, so the
-// product may overwrite its inputs.  Lane L holds A[L%16][L/16] and
-// B[L/16][L%16]; accumulator register r holds D[4r + L/16][L%16].
-template <int R, int C, int K, class FA, class FB, class FS>
-__device__ __forceinline__ void wave_gemm(FA a, FB b, FS st)
+// ------------------------------------------------------------ M2M
+// eq. 3.7: a parent's weights are its children's weights interpolated onto
+// the parent's nodes and summed.  A child is exactly one quadrant of its
+// parent, so the 1D transfer from a child on side s (0: low, 1: high) is the
+// same p x p matrix at every level,
+//   S_s[l][l'] = S_p(xbar_l, (xbar_l' + 2s - 1) / 2),
+// and child d (x side d & 1, y side d >> 1, the order of Fig. 3) adds
+// S_{d&1} W_d S_{d>>1}^T to each component.  Children of equal y side share
+// their y transfer:
+//   W_A = sum_sy (sum_sx S_sx W_{sx,sy}) S_sy^T,
+// so a parent costs four x passes and two y passes, all on FP64 MFMA
+// (16x16x4 blocks).  The transfer matrices stay in registers for the whole
+// block; the children's weights go straight from memory into the x pass's
+// B operands, its results through LDS into the y pass's A operands.
+//
+// A block works through a chain of parents in order, writing each parent's
+// weights before the next starts (a barrier orders them), so a chain may
+// climb: the subtrees below a cut level go one chain each in one launch,
+// and every level above it is one launch of one-parent chains.  Each child
+// transfer is done once.
+constexpr int XT = 256;
+
+// NC components per cell (3 stress charges; 4 with a fluid source).  Cell
+// k's weights for term blockIdx.y are at W + k ldw + blockIdx.y tstride.
+// MFMA operands: lane L holds A[L%16][L/16] and B[L/16][L%16]; accumulator
+// register r of lane L holds D[4r + L/16][L%16].
+// Chain b is the steps coff[b] .. coff[b+1] - 1 (step b alone when coff is
+// null); step i is item[5 i .. 5 i + 4] = (parent, its four children or -1).
+template <int P, int NC>
+__global__ __launch_bounds__(XT) void k_m2m(int nchain, const int *__restrict__ coff, const int *__restrict__ item,
+                                            const double *__restrict__ S, int ldw, int tstride,
+                                            double *__restrict__ W)
 {
-    constexpr int MT = (R + 15) / 16, NT = (C + 15) / 16, KS = (K + 3) / 4;
+    constexpr int P2 = P * P, R = NC * P, RS = P + 1;
+    constexpr int MT = (P + 15) / 16, KS = (P + 3) / 4, NT = (R + 15) / 16;  // x pass (P x P).(P x R)
+    constexpr int MY = (R + 15) / 16, NY = (P + 15) / 16, MYW = (MY + 3) / 4;  // y pass (R x P).(P x P)
+    __shared__ double X[4][R * RS];  // x pass of child d: X_d[(c, l)][m], rows padded
+    W += (size_t)blockIdx.y * tstride;
+    const int b = xcd_remap(blockIdx.x, nchain);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
-    d4 acc[MT][NT];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-        const int k = 4 * ks + lk;
-        double av[MT], bv[NT];
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-            const int i = 16 * mt + li;
-            av[mt] = (i < R && k < K) ? a(i, k) : 0.0;
-        }
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            const int j = 16 * nt + li;
-            bv[nt] = (j < C && k < K) ? b(k, j) : 0.0;
-        }
+    // x pass A operands: S_{wave & 1}[16 mt + li][4 ks + lk]
+    double ax[MT][KS];
+    {
+        const double *Sx = S + (wave & 1) * P2;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
-                acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[mt], bv[nt], acc[mt][nt], 0, 0, 0);
-    }
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int i = 16 * mt + 4 * r + lk, j = 16 * nt + li;
-                if (i < R && j < C) st(i, j, acc[mt][nt][r]);
+            for (int ks = 0; ks < KS; ++ks) {
+                const int r = 16 * mt + li, k = 4 * ks + lk;
+                ax[mt][ks] = (r < P && k < P) ? Sx[r * P + k] : 0.0;
             }
-}
-
-// ------------------------------------------------------------ M2M
-// eq. 3.7 applied level after level gives an ancestor A the weights
-//   W_A = sum over leaves L below A of  Tx_{A<-L} W_L Ty_{A<-L}^T,
-// where the composite transfer is the product of the 1D child-to-parent
-// interpolation matrices along the path.  Each of them maps a polynomial of
-// degree < p exactly, so the composite is A's interpolant evaluated at L's
-// nodes: Tx_{A<-L}[l][l'] = S_p(xbar_l, (x_L + h_L xbar_l' - x_A) / h_A).
-// Evaluating it directly removes the level-by-level chain of dependent
-// launches.  Work items are (ancestor, up to 4 of its leaves); each writes
-// its partial sum, and the partials of an ancestor are added in a fixed
-// order afterwards.
-constexpr int XT = 256;
-
-// leaves per work item: 4, or 2 where 4 would not fit in LDS
-__host__ __device__ constexpr int m2m_slots(int p) { return p <= 24 ? 4 : 2; }
-
-// NC components per cell (3 stress charges; 4 with a fluid source).  Cell
-// k's weights for term blockIdx.y are at W + k ldw + blockIdx.y tstride,
-// item partials at part + item ldw + blockIdx.y tstride.
-template <int P, int NC>
-__global__ __launch_bounds__(XT) void k_m2m(int nitem, const int *__restrict__ it_anc,
-                                            const int *__restrict__ it_leaf, const double *__restrict__ ccx,
-                                            const double *__restrict__ ccy, const double *__restrict__ chw,
-                                            const double *__restrict__ xbar, const double *__restrict__ bw, int Mp,
-                                            int tstride, const double *__restrict__ W, double *__restrict__ part)
-{
-    constexpr int P2 = P * P, N3 = NC * P2, NS = m2m_slots(P);
-    W += (size_t)blockIdx.y * tstride;
-    part += (size_t)blockIdx.y * tstride;
-    constexpr int UO = P <= 20 ? P : 4;  // outer unroll: bounds the live operator values
-    __shared__ double buf[NS * N3];
-    __shared__ double Tx[NS][P2], Ty[NS][P2];  // [leaf slot][l * P + l']
-    __shared__ double s_xb[P], s_bw[P];
-    int item = xcd_remap(blockIdx.x, nitem);
-    int tid = threadIdx.x;
-    int A = it_anc[item];
-    // every leaf weight is requested before any is stored; an empty slot
-    // reads the first leaf and stores zeros
-    int k4[NS];
-#pragma unroll
-    for (int d = 0; d < NS; ++d) k4[d] = it_leaf[4 * item + d];
-    constexpr int NL = (NS * N3 + XT - 1) / XT;
-    double v[NL];
-#pragma unroll
-    for (int j = 0; j < NL; ++j) {
-        int e = tid + j * XT;
-        int d = min(e / N3, NS - 1), r = min(e - d * N3, N3 - 1);
-        int k = k4[d] >= 0 ? k4[d] : k4[0];
-        v[j] = W[(size_t)k * Mp + r];
     }
-    if (tid < P) {
-        s_xb[tid] = xbar[tid];
-        s_bw[tid] = bw[tid];
-    }
+    // y pass B operands: B[k][n] = S_sy[n][k] at n = 16 nt + li, k = 4 ks + lk
+    double by[2][KS][NY];
 #pragma unroll
-    for (int j = 0; j < NL; ++j) {
-        int e = tid + j * XT;
-        int d = min(e / N3, NS - 1);
-        if (e < NS * N3) buf[e] = k4[d] >= 0 ? v[j] : 0.0;
-    }
-    __syncthreads();
-    // composite transfers: task (slot, coordinate, child node l')
-    double xa = ccx[A], ya = ccy[A], iha = 1.0 / chw[A];
-    for (int q = tid; q < 2 * NS * P; q += XT) {
-        int d = q / (2 * P), r = q - d * 2 * P, coord = r / P, l2 = r - coord * P;
-        int L = k4[d] >= 0 ? k4[d] : k4[0];
-        double u = coord ? (ccy[L] + chw[L] * s_xb[l2] - ya) * iha : (ccx[L] + chw[L] * s_xb[l2] - xa) * iha;
-        double S[P];
-        bary<P>(s_xb, s_bw, u, S);
-        double *T = coord ? Ty[d] : Tx[d];
+    for (int sy = 0; sy < 2; ++sy)
 #pragma unroll
-        for (int l = 0; l < P; ++l) T[l * P + l2] = S[l];
-    }
-    __syncthreads();
-    if (NS == XT / 64) {
-        // wave d transfers slot d on the matrix cores: the x pass is
-        // Tx_d (P x P) . [W_c]_c (P x NC P), the y pass [W'_c]_c (NC P x P) . Ty_d^T
-        const int d = tid >> 6;
-        double *bd = buf + d * N3;
-        const double *tx = Tx[d], *ty = Ty[d];
-        if (k4[d] >= 0) {
-            wave_gemm<P, NC * P, P>([&](int l, int l2) { return tx[l * P + l2]; },
-                                    [&](int l2, int j) { return bd[(j / P) * P2 + l2 * P + j % P]; },
-                                    [&](int l, int j, double v) { bd[(j / P) * P2 + l * P + j % P] = v; });
-            wave_gemm<NC * P, P, P>([&](int row, int m2) { return bd[row * P + m2]; },
-                                    [&](int m2, int m) { return ty[m * P + m2]; },
-                                    [&](int row, int m, double v) { bd[row * P + m] = v; });
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+            for (int nt = 0; nt < NY; ++nt) {
+                const int n = 16 * nt + li, k = 4 * ks + lk;
+                by[sy][ks][nt] = (n < P && k < P) ? S[sy * P2 + n * P + k] : 0.0;
+            }
+    const int i0 = coff ? coff[b] : b, i1 = coff ? coff[b + 1] : b + 1;
+    for (int it = i0; it < i1; ++it) {
+        const int A = item[5 * it];
+        // x pass, wave d on child d: X_d = S_{d&1} . W_d with W_d as the
+        // P x R matrix [l'][(c, m)]
+        {
+            const int ch = item[5 * it + 1 + wave];
+            double *Xd = X[wave];
+            if (ch >= 0) {
+                const double *Wd = W + (size_t)ch * ldw;
+                double bw[KS][NT];
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) {
+                        const int k = 4 * ks + lk, col = 16 * nt + li, c = col / P, m = col - c * P;
+                        bw[ks][nt] = (k < P && col < R) ? Wd[c * P2 + k * P + m] : 0.0;
+                    }
+                d4 acc[MT][NT];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                        for (int nt = 0; nt < NT; ++nt)
+                            acc[mt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ax[mt][ks], bw[ks][nt], acc[mt][nt],
+                                                                               0, 0, 0);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int l = 16 * mt + 4 * r + lk, col = 16 * nt + li, c = col / P, m = col - c * P;
+                            if (l < P && col < R) Xd[(c * P + l) * RS + m] = acc[mt][nt][r];
+                        }
+            } else {
+                for (int e = lane; e < R * RS; e += 64) Xd[e] = 0.0;
+            }
         }
         __syncthreads();
-        for (int e = tid; e < N3; e += XT) {
-            double acc = buf[e];
+        // y pass: W_A = sum_sy (X_{0,sy} + X_{1,sy}) . S_sy^T, wave w on row
+        // tiles w, w + 4, ... of the R x P result
+        {
+            double *WA = W + (size_t)A * ldw;
 #pragma unroll
-            for (int dd = 1; dd < NS; ++dd) acc += buf[dd * N3 + e];
-            part[(size_t)item * Mp + e] = acc;
+            for (int i = 0; i < MYW; ++i) {
+                const int mt = wave + 4 * i;
+                if (mt < MY) {
+                    d4 acc[NY];
+#pragma unroll
+                    for (int nt = 0; nt < NY; ++nt) acc[nt] = d4{0.0, 0.0, 0.0, 0.0};
+                    const int row = 16 * mt + li;
+#pragma unroll
+                    for (int sy = 0; sy < 2; ++sy)
+#pragma unroll
+                        for (int ks = 0; ks < KS; ++ks) {
+                            const int k = 4 * ks + lk;
+                            const double a = (row < R && k < P)
+                                                 ? X[2 * sy][row * RS + k] + X[2 * sy + 1][row * RS + k]
+                                                 : 0.0;
+#pragma unroll
+                            for (int nt = 0; nt < NY; ++nt)
+                                acc[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, by[sy][ks][nt], acc[nt], 0, 0, 0);
+                        }
+#pragma unroll
+                    for (int nt = 0; nt < NY; ++nt)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int rr = 16 * mt + 4 * r + lk, n = 16 * nt + li;
+                            if (rr < R && n < P) WA[rr * P + n] = acc[nt][r];
+                        }
+                }
+            }
         }
-        return;
-    }
-    // x pass: task (slot d, component, column m2): column <- Tx_d . column
-    for (int q = tid; q < NC * NS * P; q += XT) {
-        int d = q / (NC * P), r = q - d * NC * P, comp = r / P, m2 = r - comp * P;
-        double *col = buf + d * N3 + comp * P2 + m2;
-        const double *T = Tx[d];
-        double u[P];
-#pragma unroll
-        for (int l2 = 0; l2 < P; ++l2) u[l2] = col[l2 * P];
-#pragma unroll UO
-        for (int l = 0; l < P; ++l) {
-            double acc = 0.0;
-#pragma unroll
-            for (int l2 = 0; l2 < P; ++l2) acc += T[l * P + l2] * u[l2];
-            col[l * P] = acc;
-        }
-    }
-    __syncthreads();
-    // y pass: task (slot d, component, row l): row <- row . Ty_d^T
-    for (int q = tid; q < NC * NS * P; q += XT) {
-        int d = q / (NC * P), r = q - d * NC * P, comp = r / P, l = r - comp * P;
-        double *row = buf + d * N3 + comp * P2 + l * P;
-        const double *T = Ty[d];
-        double u[P];
-#pragma unroll
-        for (int m2 = 0; m2 < P; ++m2) u[m2] = row[m2];
-#pragma unroll UO
-        for (int m = 0; m < P; ++m) {
-            double acc = 0.0;
-#pragma unroll
-            for (int m2 = 0; m2 < P; ++m2) acc += T[m * P + m2] * u[m2];
-            row[m] = acc;
-        }
-    }
-    __syncthreads();
-    for (int e = tid; e < N3; e += XT) {
-        double acc = buf[e];
-#pragma unroll
-        for (int d = 1; d < NS; ++d) acc += buf[d * N3 + e];
-        part[(size_t)item * Mp + e] = acc;
-    }
-}
-
-// W_A = sum of A's item partials, in item order.
-__global__ __launch_bounds__(256) void k_m2m_sum(int nanc, const int *__restrict__ anc,
-                                                 const int *__restrict__ ioff, const double *__restrict__ part,
-                                                 int n3, int Mp, int tstride, double *__restrict__ W)
-{
-    part += (size_t)blockIdx.y * tstride;
-    W += (size_t)blockIdx.y * tstride;
-    constexpr int U = 8;  // loads in flight per thread; the sum stays in item order
-    int i = xcd_remap(blockIdx.x, nanc);
-    int A = anc[i], kb = ioff[i], ke = ioff[i + 1];
-    for (int e = threadIdx.x; e < n3; e += 256) {
-        double s = 0.0;
-        for (int k0 = kb; k0 < ke; k0 += U) {
-            double v[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) v[u] = part[(size_t)min(k0 + u, ke - 1) * Mp + e];
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (k0 + u < ke) s += v[u];
-        }
-        W[(size_t)A * Mp + e] = s;
+        // the parent's weights are written before a later parent of the
+        // chain reads them, and X is free again
+        __syncthreads();
     }
 }
 
@@ -1022,6 +962,109 @@ void upload(hipStream_t s, DBuf<double> &d, const std::vector<double> &h)
     if (!h.empty()) FM_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * 8, hipMemcpyHostToDevice, s));
 }
 
+// Upward-pass schedule (eq. 3.7 bottom-up).  Every internal cell of level
+// >= 2 is a parent.  The subtrees below a cut level Lc run as one chain
+// each in one launch; each level above Lc is a launch of one-parent
+// chains.  Lc minimises a latency model: a launch costs about T_LAUNCH, a
+// parent on its block about T_PARENT (both microseconds, measured on
+// MI355X at p = 20), so the deep launch costs its longest chain.
+void m2m_schedule(hipStream_t s, fmddm_tree *t)
+{
+    constexpr double T_LAUNCH = 4.0, T_PARENT = 2.5;
+    constexpr int WAVE_BLOCKS = 512;  // parents one launch runs side by side
+    const int ncell = t->ncell, maxlev = t->nlevel - 1;
+    t->m2m_launch.clear();
+    std::vector<int> hch(4 * (size_t)std::max(ncell, 1));
+    FM_HIP(hipMemcpyAsync(hch.data(), t->cchild.p, 4 * (size_t)ncell * sizeof(int), hipMemcpyDeviceToHost, s));
+    FM_HIP(hipStreamSynchronize(s));
+    std::vector<std::vector<int>> bylev(std::max(maxlev + 1, 3));
+    for (int c = 0; c < ncell; ++c)
+        if (!t->h_isleaf[c] && t->h_level[c] >= 2) bylev[t->h_level[c]].push_back(c);
+    // internal cells of each parent's subtree (itself included)
+    std::vector<int> sub(ncell, 0);
+    for (int l = maxlev; l >= 2; --l)
+        for (int c : bylev[l]) {
+            sub[c] = 1;
+            for (int d = 0; d < 4; ++d)
+                if (hch[4 * c + d] >= 0) sub[c] += sub[hch[4 * c + d]];
+        }
+    int best = maxlev + 1;
+    double best_cost = 1e300;
+    for (int Lc = 2; Lc <= maxlev + 1; ++Lc) {
+        double cost = 0.0;
+        int longest = 0;
+        if (Lc <= maxlev)
+            for (int c : bylev[Lc]) longest = std::max(longest, sub[c]);
+        if (longest) cost += T_LAUNCH + longest * T_PARENT;
+        for (int l = 2; l < Lc && l <= maxlev; ++l)
+            if (!bylev[l].empty())
+                cost += T_LAUNCH + T_PARENT * (double)((bylev[l].size() + WAVE_BLOCKS - 1) / WAVE_BLOCKS);
+        if (cost < best_cost) {
+            best_cost = cost;
+            best = Lc;
+        }
+    }
+    std::vector<int> coff(1, 0), par;
+    auto close_launch = [&](int first) {
+        int nch = (int)coff.size() - 1 - first;
+        if (nch <= 0) return;
+        fmddm_tree::M2MLaunch L;
+        L.first = first;
+        L.nchain = nch;
+        L.step0 = coff[first];
+        L.single = coff[first + nch] - coff[first] == nch;
+        t->m2m_launch.push_back(L);
+    };
+    // deep launch: each subtree rooted at level best, deepest parents first
+    if (best <= maxlev) {
+        int first = (int)coff.size() - 1;
+        std::vector<int> cells, stack;
+        for (int r : bylev[best]) {
+            cells.clear();
+            stack.assign(1, r);
+            while (!stack.empty()) {
+                int c = stack.back();
+                stack.pop_back();
+                cells.push_back(c);
+                for (int d = 0; d < 4; ++d) {
+                    int k = hch[4 * c + d];
+                    if (k >= 0 && !t->h_isleaf[k]) stack.push_back(k);
+                }
+            }
+            std::stable_sort(cells.begin(), cells.end(),
+                             [&](int a, int b) { return t->h_level[a] > t->h_level[b]; });
+            par.insert(par.end(), cells.begin(), cells.end());
+            coff.push_back((int)par.size());
+        }
+        close_launch(first);
+    }
+    // one launch per level above it, deepest first
+    for (int l = std::min(best, maxlev + 1) - 1; l >= 2; --l) {
+        int first = (int)coff.size() - 1;
+        for (int c : bylev[l]) {
+            par.push_back(c);
+            coff.push_back((int)par.size());
+        }
+        close_launch(first);
+    }
+    t->m2m_cut = best;
+    // per launch: chain offsets from its first step (at m2m_coff + first)
+    std::vector<int> item(5 * par.size());
+    for (size_t i = 0; i < par.size(); ++i) {
+        item[5 * i] = par[i];
+        for (int d = 0; d < 4; ++d) item[5 * i + 1 + d] = hch[4 * (size_t)par[i] + d];
+    }
+    std::vector<int> loff;
+    for (fmddm_tree::M2MLaunch &L : t->m2m_launch) {
+        int at = (int)loff.size();
+        for (int c = L.first; c <= L.first + L.nchain; ++c) loff.push_back(coff[c] - L.step0);
+        L.first = at;
+    }
+    upload(s, t->m2m_coff, loff);
+    upload(s, t->m2m_item, item);
+    FM_HIP(hipStreamSynchronize(s));
+}
+
 template <int BM, int BN>
 void launch_ggemm(hipStream_t s, int ntile, int Mrows, const double *ops, size_t op_stride, int lda, int Kd,
                   const double *X, int ldx, const int *top, const int *tbeg, const int *tend,
@@ -1176,13 +1219,14 @@ void setup_lowp(fmddm_ctx *ctx, fmddm_tree *t, int prec)
 }
 
 template <int P, int NC = 3>
-void launch_m2m(hipStream_t s, fmddm_ctx *ctx, fmddm_tree *t, int ldw, int nterm, int tstride, const double *W,
-                double *part)
+void launch_m2m(hipStream_t s, fmddm_ctx *ctx, fmddm_tree *t, int ldw, int nterm, int tstride, double *W)
 {
-    hipLaunchKernelGGL((k_m2m<P, NC>), dim3(t->nuitem, nterm), dim3(XT), 0, s, t->nuitem, t->uit_anc.p,
-                       t->uit_leaf.p, t->ccx.p, t->ccy.p, t->chw.p, ctx->cheb->xbar.p, ctx->cheb->bw.p, ldw, tstride,
-                       W, part);
-    FM_CHECK_LAUNCH();
+    for (const fmddm_tree::M2MLaunch &L : t->m2m_launch) {
+        hipLaunchKernelGGL((k_m2m<P, NC>), dim3(L.nchain, nterm), dim3(XT), 0, s, L.nchain,
+                           L.single ? (const int *)nullptr : t->m2m_coff.p + L.first, t->m2m_item.p + 5 * L.step0,
+                           ctx->cheb->m2mS.p, ldw, tstride, W);
+        FM_CHECK_LAUNCH();
+    }
 }
 
 template <int P, int NC = 3>
@@ -1337,17 +1381,14 @@ void Profiler::read(hipStream_t s, double *ms, int64_t *count)
 // The passes of the product above for fields with four components per node
 // (three eigenstrain charges and a fluid source), several terms at once:
 // weights of cell k and term j at W + k ldw + j tstride.
-void fmm_m2m4(fmddm_ctx *ctx, fmddm_tree *t, int nterm, int ldw, int tstride, double *W, double *part)
+void fmm_m2m4(fmddm_ctx *ctx, fmddm_tree *t, int nterm, int ldw, int tstride, double *W)
 {
-    if (t->nuitem == 0) return;
+    if (t->m2m_launch.empty()) return;
     hipStream_t s = ctx->stream;
     int p = ctx->prm.p;
-#define FM_M2M4(PP) launch_m2m<PP, 4>(s, ctx, t, ldw, nterm, tstride, W, part)
+#define FM_M2M4(PP) launch_m2m<PP, 4>(s, ctx, t, ldw, nterm, tstride, W)
     FM_DISPATCH_P16(p, FM_M2M4)
 #undef FM_M2M4
-    hipLaunchKernelGGL(k_m2m_sum, dim3(t->nuanc, nterm), dim3(256), 0, s, t->nuanc, t->uanc.p, t->uioff.p, part,
-                       4 * p * p, ldw, tstride, W);
-    FM_CHECK_LAUNCH();
 }
 
 void fmm_l2p4(fmddm_ctx *ctx, fmddm_tree *t, const double *G, int ldg, double *far)
@@ -1398,12 +1439,30 @@ void setup_cheb(fmddm_ctx *ctx)
         for (int k = 0; k < p; ++k) C.h_tnode[l * p + k] = std::cos(k * th);
     }
     gauss_legendre(p, C.h_glt, C.h_glw);
+    // child-to-parent transfers of eq. 3.7: S_s[l][l'] = S_p(xbar_l, u) at
+    // u = (xbar_l' + 2s - 1) / 2, by the Chebyshev sum 1/p + 2/p sum_k
+    // T_k(xbar_l) T_k(u) with T_k(u) from the three-term recurrence
+    C.h_m2mS.assign(2 * (size_t)p * p, 0.0);
+    for (int sd = 0; sd < 2; ++sd)
+        for (int l2 = 0; l2 < p; ++l2) {
+            double u = 0.5 * (C.h_xbar[l2] + 2.0 * sd - 1.0);
+            std::vector<double> T(p);
+            T[0] = 1.0;
+            if (p > 1) T[1] = u;
+            for (int k = 2; k < p; ++k) T[k] = 2.0 * u * T[k - 1] - T[k - 2];
+            for (int l = 0; l < p; ++l) {
+                double acc = 0.0;
+                for (int k = 1; k < p; ++k) acc += C.h_tnode[l * p + k] * T[k];
+                C.h_m2mS[(size_t)sd * p * p + l * p + l2] = (1.0 + 2.0 * acc) / p;
+            }
+        }
     hipStream_t s = ctx->stream;
     upload(s, C.xbar, C.h_xbar);
     upload(s, C.bw, C.h_bw);
     upload(s, C.tnode, C.h_tnode);
     upload(s, C.gl_t, C.h_glt);
     upload(s, C.gl_w, C.h_glw);
+    upload(s, C.m2mS, C.h_m2mS);
     FM_HIP(hipStreamSynchronize(s));
 }
 
@@ -1600,35 +1659,7 @@ void setup_fmm(fmddm_ctx *ctx, fmddm_tree *t)
     t->Zm2l.alloc((size_t)std::max<int64_t>(t->nV, 1) * rp);
     t->Wexp.zero(s);
     t->Gexp.zero(s);
-    // upward-pass work items: every non-leaf cell of level >= 2 with its
-    // leaf descendants, in tree order, m2m_slots(p) per item
-    {
-        std::vector<int> hpar(ncell);
-        FM_HIP(hipMemcpyAsync(hpar.data(), t->cparent.p, ncell * 4, hipMemcpyDeviceToHost, s));
-        FM_HIP(hipStreamSynchronize(s));
-        std::vector<std::vector<int>> desc(ncell);
-        for (int L : t->leaves)
-            for (int A = hpar[L]; A >= 0 && t->h_level[A] >= 2; A = hpar[A]) desc[A].push_back(L);
-        std::vector<int> anc, ioff(1, 0), ianc, ileaf;
-        for (int A = 0; A < ncell; ++A) {
-            if (desc[A].empty()) continue;
-            anc.push_back(A);
-            size_t ns = m2m_slots(p);
-            for (size_t b = 0; b < desc[A].size(); b += ns) {
-                ianc.push_back(A);
-                for (size_t d = 0; d < 4; ++d)
-                    ileaf.push_back(d < ns && b + d < desc[A].size() ? desc[A][b + d] : -1);
-            }
-            ioff.push_back((int)ianc.size());
-        }
-        t->nuanc = (int)anc.size();
-        t->nuitem = (int)ianc.size();
-        upload(s, t->uanc, anc);
-        upload(s, t->uioff, ioff);
-        upload(s, t->uit_anc, ianc);
-        upload(s, t->uit_leaf, ileaf);
-        t->upart.alloc((size_t)std::max(t->nuitem, 1) * Mp);
-    }
+    m2m_schedule(s, t);
     if (M.mode == FMDDM_M2L_SVD) {
         t->What.alloc((size_t)ncell * rp);
         t->Ghat.alloc((size_t)ncell * rp);
@@ -1663,10 +1694,26 @@ void setup_fmm(fmddm_ctx *ctx, fmddm_tree *t)
     FM_HIP(hipStreamSynchronize(s));
 }
 
+FmmBufs tree_bufs(fmddm_tree *t)
+{
+    return FmmBufs{t->Dsort.p, t->q.p, t->part_s.p, t->Wexp.p, t->ksplit.p, t->What.p,
+                   t->Zm2l.p,  t->Ghat.p, t->Gexp.p, t->far_s.p};
+}
+
+int fmm_ksplit(const fmddm_ctx *ctx) { return TILESETS[ctx->prm.m2l_tiles].ksplit; }
+
 void fmm_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out, int prec)
 {
     setup_fmm(ctx, t);
     if (prec != FMDDM_PREC_FP64) setup_lowp(ctx, t, prec);
+    fmm_apply_bufs(ctx, t, D, out, prec, tree_bufs(t));
+}
+
+void fmm_apply_bufs(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out, int prec, const FmmBufs &B)
+{
+    // the reduced-precision M2L products keep their intermediates with the tree
+    if (prec != FMDDM_PREC_FP64 && B.Wexp != t->Wexp.p)
+        throw Error{FMDDM_EUNSUPPORTED, "reduced-precision products use the tree's buffers"};
     hipStream_t s = ctx->stream;
     const M2LOps &M = *ctx->m2l;
     int p = ctx->prm.p, Mp = M.Mp, rp = M.rp, n = (int)t->n;
@@ -1676,7 +1723,7 @@ void fmm_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out, int 
     hipEvent_t e0;
     P.begin(FMDDM_PH_PREP, s, e0);
     hipLaunchKernelGGL(k_prep, dim3(cdiv(n, 256)), dim3(256), 0, s, n, t->perm.p, D, t->scb.p, t->ssb.p,
-                       t->Dsort.p, t->q.p);
+                       B.Dsort, B.q);
     FM_CHECK_LAUNCH();
     P.end(FMDDM_PH_PREP, s, e0);
     // the near field depends only on the prepared sources: it runs on the
@@ -1689,13 +1736,13 @@ void fmm_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out, int 
     if (prec == FMDDM_PREC_FP64)
         hipLaunchKernelGGL(k_p2p<double>, dim3(t->nitem), dim3(NT), 0, s2, t->nitem, t->it_leaf.p, t->it_s0.p,
                            t->it_s1.p, t->it_poff.p, t->dleaves.p, t->cpbeg.p, t->cpend.p, t->noff.p, t->nbeg.p,
-                           t->npre.p, t->scx.p, t->scy.p, t->scb.p, t->ssb.p, t->sa.p, t->Dsort.p, ctx->gc,
-                           t->part_s.p);
+                           t->npre.p, t->scx.p, t->scy.p, t->scb.p, t->ssb.p, t->sa.p, B.Dsort, ctx->gc,
+                           B.part_s);
     else
         hipLaunchKernelGGL(k_p2p<float>, dim3(t->nitem), dim3(NT), 0, s2, t->nitem, t->it_leaf.p, t->it_s0.p,
                            t->it_s1.p, t->it_poff.p, t->dleaves.p, t->cpbeg.p, t->cpend.p, t->noff.p, t->nbeg.p,
-                           t->npre.p, t->scx.p, t->scy.p, t->scb.p, t->ssb.p, t->sa.p, t->Dsort.p, ctx->gc,
-                           t->part_s.p);
+                           t->npre.p, t->scx.p, t->scy.p, t->scb.p, t->ssb.p, t->sa.p, B.Dsort, ctx->gc,
+                           B.part_s);
     FM_CHECK_LAUNCH();
     P.end(FMDDM_PH_P2P, s2, e1);
     FM_HIP(hipEventRecord(ctx->ev_join, s2));
@@ -1703,20 +1750,15 @@ void fmm_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out, int 
     if (far) {
         P.begin(FMDDM_PH_P2M, s, e0);
         hipLaunchKernelGGL(k_p2m, dim3(t->nleaf), dim3(256), 0, s, t->nleaf, t->dleaves.p, t->cpbeg.p,
-                           t->cpend.p, t->p2m_mat.p, t->q.p, p * p, Mp, t->Wexp.p);
+                           t->cpend.p, t->p2m_mat.p, B.q, p * p, Mp, B.Wexp);
         FM_CHECK_LAUNCH();
         P.end(FMDDM_PH_P2M, s, e0);
-        if (t->nuitem > 0) {
+        if (!t->m2m_launch.empty()) {
             P.begin(FMDDM_PH_M2M, s, e0);
-#define FM_M2M(PP) launch_m2m<PP>(s, ctx, t, Mp, 1, 0, t->Wexp.p, t->upart.p)
+#define FM_M2M(PP) launch_m2m<PP>(s, ctx, t, Mp, 1, 0, B.Wexp)
             FM_DISPATCH_P(p, FM_M2M)
 #undef FM_M2M
             P.end(FMDDM_PH_M2M, s, e0);
-            P.begin(FMDDM_PH_M2M_SUM, s, e0);
-            hipLaunchKernelGGL(k_m2m_sum, dim3(t->nuanc), dim3(256), 0, s, t->nuanc, t->uanc.p, t->uioff.p,
-                               t->upart.p, 3 * p * p, Mp, 0, t->Wexp.p);
-            FM_CHECK_LAUNCH();
-            P.end(FMDDM_PH_M2M_SUM, s, e0);
         }
         if (prec == FMDDM_PREC_FP32) {
             m2l_lowp<float>(s, t, M, M.Vt32.p, M.ops32.p, M.Ur32.p, P, ts);
@@ -1726,47 +1768,47 @@ void fmm_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out, int 
             // projection onto the singular vectors: K = 3p^2 is long and the
             // output small, so K is split over ts.ksplit blocks and summed after
             P.begin(FMDDM_PH_COMPRESS, s, e0);
-            launch_ggemm<32, 32>(s, t->nftile, rp, M.Vt.p, 0, Mp, Mp, t->Wexp.p, Mp, t->ftile_op.p,
+            launch_ggemm<32, 32>(s, t->nftile, rp, M.Vt.p, 0, Mp, Mp, B.Wexp, Mp, t->ftile_op.p,
                                  t->ftile_beg.p, t->ftile_end.p, t->far_cells.p, t->far_cells.p, nullptr,
-                                 t->ksplit.p, rp, ts.ksplit, (size_t)t->ncell * rp);
+                                 B.ksplit, rp, ts.ksplit, (size_t)t->ncell * rp);
             P.end(FMDDM_PH_COMPRESS, s, e0);
             P.begin(FMDDM_PH_COMPRESS_SUM, s, e0);
             {
                 int64_t c0 = t->level_start[2], cnt = (int64_t)(t->ncell - c0) * rp;
                 hipLaunchKernelGGL(k_reduce_split<double>, dim3(cdiv(cnt, 256)), dim3(256), 0, s, cnt, ts.ksplit,
-                                   (size_t)t->ncell * rp, t->ksplit.p + c0 * rp, t->What.p + c0 * rp);
+                                   (size_t)t->ncell * rp, B.ksplit + c0 * rp, B.What + c0 * rp);
                 FM_CHECK_LAUNCH();
             }
             P.end(FMDDM_PH_COMPRESS_SUM, s, e0);
             P.begin(FMDDM_PH_M2L, s, e0);
-            ggemm_bm(ts.bm_pair, s, t->ntile, rp, M.ops.p, (size_t)rp * rp, rp, rp, t->What.p, rp, t->tile_op.p,
+            ggemm_bm(ts.bm_pair, s, t->ntile, rp, M.ops.p, (size_t)rp * rp, rp, rp, B.What, rp, t->tile_op.p,
                                  t->tile_beg.p, t->tile_end.p, t->pair_src.p, t->pair_dst.p, t->pair_scale.p,
-                                 t->Zm2l.p, rp);
+                                 B.Zm2l, rp);
             P.end(FMDDM_PH_M2L, s, e0);
             P.begin(FMDDM_PH_M2L_SUM, s, e0);
             hipLaunchKernelGGL((k_sum_pairs<double, double>), dim3(t->nfar), dim3(256), 0, s, t->nfar, t->far_cells.p,
-                               t->loff[1].p, t->Zm2l.p, rp, rp, t->Ghat.p, rp);
+                               t->loff[1].p, B.Zm2l, rp, rp, B.Ghat, rp);
             FM_CHECK_LAUNCH();
             P.end(FMDDM_PH_M2L_SUM, s, e0);
             P.begin(FMDDM_PH_DECOMPRESS, s, e0);
-            ggemm_bm(ts.bm_back, s, t->nftile, Mp, M.Ur.p, 0, rp, rp, t->Ghat.p, rp, t->ftile_op.p,
+            ggemm_bm(ts.bm_back, s, t->nftile, Mp, M.Ur.p, 0, rp, rp, B.Ghat, rp, t->ftile_op.p,
                                  t->ftile_beg.p, t->ftile_end.p, t->far_cells.p, t->far_cells.p, nullptr,
-                                 t->Gexp.p, Mp);
+                                 B.Gexp, Mp);
             P.end(FMDDM_PH_DECOMPRESS, s, e0);
         } else {
             P.begin(FMDDM_PH_M2L, s, e0);
-            ggemm_bm(ts.bm_pair, s, t->ntile, Mp, M.ops.p, (size_t)Mp * Mp, Mp, Mp, t->Wexp.p, Mp, t->tile_op.p,
+            ggemm_bm(ts.bm_pair, s, t->ntile, Mp, M.ops.p, (size_t)Mp * Mp, Mp, Mp, B.Wexp, Mp, t->tile_op.p,
                                  t->tile_beg.p, t->tile_end.p, t->pair_src.p, t->pair_dst.p, t->pair_scale.p,
-                                 t->Zm2l.p, Mp);
+                                 B.Zm2l, Mp);
             P.end(FMDDM_PH_M2L, s, e0);
             P.begin(FMDDM_PH_M2L_SUM, s, e0);
             hipLaunchKernelGGL((k_sum_pairs<double, double>), dim3(t->nfar), dim3(256), 0, s, t->nfar, t->far_cells.p,
-                               t->loff[1].p, t->Zm2l.p, Mp, Mp, t->Gexp.p, Mp);
+                               t->loff[1].p, B.Zm2l, Mp, Mp, B.Gexp, Mp);
             FM_CHECK_LAUNCH();
             P.end(FMDDM_PH_M2L_SUM, s, e0);
         }
         P.begin(FMDDM_PH_L2P, s, e0);
-#define FM_L2P(PP) launch_l2p<PP>(s, ctx, t, t->Gexp.p, Mp, t->far_s.p)
+#define FM_L2P(PP) launch_l2p<PP>(s, ctx, t, B.Gexp, Mp, B.far_s)
         FM_DISPATCH_P(p, FM_L2P)
 #undef FM_L2P
         P.end(FMDDM_PH_L2P, s, e0);
@@ -1774,8 +1816,8 @@ void fmm_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out, int 
     FM_HIP(hipStreamWaitEvent(s, ctx->ev_join, 0));
     P.begin(FMDDM_PH_FINAL, s, e0);
     hipLaunchKernelGGL(k_final, dim3(cdiv(n, 256)), dim3(256), 0, s, n, t->tleaf.p, t->dleaves.p, t->cpbeg.p,
-                       t->clevel.p, t->lk_off.p, t->it_poff.p, t->part_s.p,
-                       far ? t->far_s.p : (const double *)nullptr,
+                       t->clevel.p, t->lk_off.p, t->it_poff.p, B.part_s,
+                       far ? B.far_s : (const double *)nullptr,
                        t->scb.p, t->ssb.p, t->perm.p, out);
     FM_CHECK_LAUNCH();
     P.end(FMDDM_PH_FINAL, s, e0);

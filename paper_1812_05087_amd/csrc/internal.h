@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <memory>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -73,7 +74,8 @@ struct Cheb {
     DBuf<double> xbar;      // p nodes
     DBuf<double> gl_t, gl_w;  // p-point Gauss-Legendre
     DBuf<double> bw;        // barycentric weights of the nodes
-    std::vector<double> h_xbar, h_tnode, h_glt, h_glw, h_bw;
+    DBuf<double> m2mS;      // child-to-parent transfers S_0, S_1 (eq. 3.7), p x p each, row-major
+    std::vector<double> h_xbar, h_tnode, h_glt, h_glw, h_bw, h_m2mS;
 };
 
 // Block-Jacobi preconditioner: groups of elements (first tree position,
@@ -211,10 +213,17 @@ struct fmddm_tree {
     // expansions
     fmddm::DBuf<double> p2m_mat;      // per element (tree order): p^2 weights of its anterpolation
     fmddm::DBuf<double> Wexp;         // multipole weights, ncell x Mp
-    int nuanc = 0, nuitem = 0;         // upward pass: ancestors, (ancestor, 4 leaves) items
-    fmddm::DBuf<int> uanc, uioff;      // ancestors and their item ranges
-    fmddm::DBuf<int> uit_anc, uit_leaf;  // per item: ancestor, 4 leaf slots (-1 = empty)
-    fmddm::DBuf<double> upart;         // per item partial weights, nuitem x Mp
+    // upward pass: steps (parent, four children or -1) in m2m_item, grouped
+    // into chains (children before parents) and launches; a launch's chain
+    // offsets (nchain + 1, from its first step step0) start at m2m_coff +
+    // first.  m2m_cut: the level below which each subtree is one chain
+    struct M2MLaunch {
+        int first = 0, nchain = 0, step0 = 0;
+        bool single = false;  // every chain one step: no offsets needed
+    };
+    std::vector<M2MLaunch> m2m_launch;
+    fmddm::DBuf<int> m2m_coff, m2m_item;
+    int m2m_cut = 0;
     fmddm::DBuf<double> What;         // compressed weights, ncell x rp
     fmddm::DBuf<double> Zm2l;         // one M2L product per V pair, nV x rp
     fmddm::DBuf<double> Ghat;         // summed compressed M2L fields, ncell x rp
@@ -248,7 +257,7 @@ struct fmddm_tree {
     std::vector<int> pf_h_combo_lvl, pf_h_combo_ox, pf_h_combo_oy;
     fmddm::DBuf<int> pf_tile_op, pf_tile_beg, pf_tile_end, pf_psrc, pf_pdst, pf_combo_lvl, pf_combo_ox,
         pf_combo_oy;
-    fmddm::DBuf<double> pf_ops, pf_W, pf_part, pf_Z, pf_G, pf_far, pf_Q, pf_D3, pf_near, pf_D2, pf_o2;
+    fmddm::DBuf<double> pf_ops, pf_W, pf_Z, pf_G, pf_far, pf_Q, pf_D3, pf_near, pf_D2, pf_o2;
     double pf_key[8] = {};  // medium the operators were built for
     // poroelastic near field: per time level j (time (j+1) dt), the 4 x 3
     // response blocks of every near (target, source) pair in item order,
@@ -301,7 +310,7 @@ void setup_cheb(fmddm_ctx *ctx);
 void build_m2l_ops(fmddm_ctx *ctx);
 void v_offsets(std::vector<int> &dx, std::vector<int> &dy, std::vector<int> &slot2op);
 int offset_slot(int x, int y);
-void fmm_m2m4(fmddm_ctx *ctx, fmddm_tree *t, int nterm, int ldw, int tstride, double *W, double *part);
+void fmm_m2m4(fmddm_ctx *ctx, fmddm_tree *t, int nterm, int ldw, int tstride, double *W);
 void fmm_l2p4(fmddm_ctx *ctx, fmddm_tree *t, const double *G, int ldg, double *far);
 void fmm_pair_gemm(hipStream_t s, int ntile, int Mrows, const double *ops, size_t op_stride, int lda, int Kd,
                    const double *X, int ldx, const int *tile_op, const int *tile_beg, const int *tile_end,
@@ -310,6 +319,20 @@ void fmm_sum_pairs(hipStream_t s, fmddm_tree *t, const double *Z, int ldz, int w
 void setup_fmm(fmddm_ctx *ctx, fmddm_tree *t);
 // prec: fmddm_precision of the near field and the M2L products
 void fmm_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out, int prec = FMDDM_PREC_FP64);
+// The buffers one FMM product writes and reads again (nothing else in the
+// tree changes during a product): sorted DDs, charges, near partials,
+// multipole weights, split-K partials, compressed weights, pair products,
+// compressed fields, fields at the nodes, far stress per level.
+struct FmmBufs {
+    double *Dsort, *q, *part_s, *Wexp, *ksplit, *What, *Zm2l, *Ghat, *Gexp, *far_s;
+};
+FmmBufs tree_bufs(fmddm_tree *t);
+// the same product with the given buffers (the tree's, or another set of
+// the same sizes); the tree's schedules and operators must be set up
+void fmm_apply_bufs(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out, int prec, const FmmBufs &B);
+// split-K depth of the projection onto the singular vectors (the
+// context's M2L tile set)
+int fmm_ksplit(const fmddm_ctx *ctx);
 // direct.hip
 void direct_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out);
 void dense_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out);
@@ -385,5 +408,27 @@ void poro_rhs(fmddm_ctx *ctx, fmddm_tree *t, const double *pf, double SH, double
 void pc_setup_poro(fmddm_ctx *ctx, fmddm_tree *t);
 
 inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
+
+// Runs an entry point's body on the context's device and turns internal
+// errors into a status code, with the message kept in ctx->err.
+template <class F>
+fmddm_status guarded(fmddm_ctx *ctx, F &&f)
+{
+    try {
+        FM_HIP(hipSetDevice(ctx->device));
+        fmddm_status st = f();
+        if (ctx) ctx->err.clear();
+        return st;
+    } catch (const Error &e) {
+        if (ctx) ctx->err = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        if (ctx) ctx->err = "host allocation failed";
+        return FMDDM_ENOMEM;
+    } catch (...) {
+        if (ctx) ctx->err = "unexpected error";
+        return FMDDM_EDEVICE;
+    }
+}
 
 }  // namespace fmddm

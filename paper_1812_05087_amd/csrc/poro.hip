@@ -1021,7 +1021,6 @@ void poro_fmm_setup(fmddm_ctx *ctx, fmddm_tree *t, int H)
         }
         t->pf_W.alloc((size_t)t->ncell * Hn * Mq);
         t->pf_W.zero(s);
-        t->pf_part.alloc((size_t)std::max(t->nuitem, 1) * Hn * Mq);
         t->pf_Q.alloc((size_t)Hn * t->n * 4);
         t->pf_D3.alloc((size_t)Hn * t->n * 3);
         t->pf_H = Hn;
@@ -1073,7 +1072,7 @@ void poro_fmm_sum(fmddm_ctx *ctx, fmddm_tree *t, int H, const double *E, bool dr
         hipLaunchKernelGGL(k_pp2m, dim3(t->nleaf, H), dim3(256), 0, s, t->nleaf, t->dleaves.p, t->cpbeg.p,
                            t->cpend.p, t->p2m_mat.p, t->pf_Q.p, n, p2, H, Mq, t->pf_W.p);
         FM_CHECK_LAUNCH();
-        fmm_m2m4(ctx, t, H, H * Mq, Mq, t->pf_W.p, t->pf_part.p);
+        fmm_m2m4(ctx, t, H, H * Mq, Mq, t->pf_W.p);
         if (fused)
             fmm_pair_gemm(s, t->pf_ntile, Mq, t->pf_ops0.p, (size_t)Mq * Mq, Mq, Mq, t->pf_W.p, Mq, t->pf_tile_op.p,
                           t->pf_tile_beg.p, t->pf_tile_end.p, t->pf_psrc.p, t->pf_pdst.p, t->pf_Z.p, Mq);

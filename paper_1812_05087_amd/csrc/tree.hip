@@ -18,6 +18,12 @@
 #include <algorithm>
 #include <cmath>
 
+// Every floating-point decision of the tree (grid coordinates, half-lengths
+// in the split test, cell centres) uses separately rounded operations.
+// hipcc contracts a * b + c into an FMA by default, and __dmul_rn /
+// __dadd_rn are plain operators, so this file is built with
+// -ffp-contract=off (the build script's per-file flags).
+
 namespace fmddm {
 namespace {
 
@@ -30,7 +36,10 @@ __global__ void k_elem_geom(int n, const double *__restrict__ x1, const double *
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double dx = x2[i] - x1[i], dy = y2[i] - y1[i];
-    double len = sqrt(dx * dx + dy * dy);
+    // separately rounded products, sum and (correctly rounded) square root:
+    // the half-length decides splits (child side >= kappa * largest
+    // half-length)
+    double len = __dsqrt_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)));
     cx[i] = 0.5 * (x1[i] + x2[i]);
     cy[i] = 0.5 * (y1[i] + y2[i]);
     bool ok = isfinite(x1[i]) && isfinite(y1[i]) && isfinite(x2[i]) && isfinite(y2[i]) && len > 0.0;
@@ -704,9 +713,12 @@ void build_tree(fmddm_ctx *ctx, fmddm_tree *t, int64_t n64, const double *x1, co
                 if (t->h_level[A] >= 2) aidx.push_back(A);
             aoff[i + 1] = (int)aidx.size();
             t->l2p_pairs += (int64_t)(aoff[i + 1] - aoff[i]) * (he[c] - hb[c]);
-            t->m2m_pairs += aoff[i + 1] - aoff[i] - (t->h_level[c] >= 2 ? 1 : 0);
         }
         t->near_pairs = pairs;
+        // upward pass (eq. 3.7): one transfer per cell whose parent has an
+        // expansion (level >= 2)
+        for (int c = 0; c < ncell; ++c)
+            if (hp[c] >= 0 && t->h_level[hp[c]] >= 2) ++t->m2m_pairs;
         auto up = [&](DBuf<int> &d, const std::vector<int> &h) {
             d.alloc(h.size());
             if (!h.empty()) FM_HIP(hipMemcpyAsync(d.p, h.data(), h.size() * 4, hipMemcpyHostToDevice, s));

@@ -30,7 +30,12 @@ def test_phase_work_counts():
     import numpy as np
     tree = {"level": np.array([0, 1, 2, 2, 3]), "isleaf": np.array([0, 0, 0, 1, 1])}
     w = bench.phase_work(info, 20, tree, 117, True)
-    assert w["m2m"][1] == (12.0 * 20 ** 3 + 12.0 * 20 ** 2) * 100
+    # eq. 3.7 per child transfer: two p x p passes over 3 components
+    assert w["m2m"][1] == 4.0 * 20 ** 3 * 3 * 100
+    # executed: an x pass per child, two y passes per parent (one parent here)
+    assert w["m2m"][4] == 2.0 * 20 ** 3 * 3 * 100 + 4.0 * 20 ** 3 * 3 * 1
+    # eqs. 3.9-3.11: an L2L transfer per child and the interpolation at each point
+    assert w["l2p"][1] == 4.0 * 20 ** 3 * 3 * 100 + 2.0 * 20 ** 2 * 3 * 1000
     assert w["p2p"][1] == bench.FLOP_PER_PAIR * 50000
     assert w["m2l"][1] == 2.0 * 117 * 117 * 200
     assert all(v[0] in ("hbm", "alu", "mfma") for v in w.values())

@@ -93,6 +93,25 @@ def test_tree_user_root_box_and_ties():
     prob.close()
 
 
+def test_tree_split_tie_bit_exact():
+    """The long element of W.split_tie() ties the split test of its level-2
+    cell at this kappa, and a half-length one ulp larger (a contracted or
+    hypot-style length) would stop the split a level earlier: the device's
+    separately rounded half-length must build the oracle's tree."""
+    wl = W.split_tie()
+    g = O.Geometry.of(wl)
+    amax = g.a.max()
+    kappa = 2.0 / amax
+    assert kappa * amax == 2.0
+    x0, y0, L = wl.meta["root_box"]
+    prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, leaf=4, use_root_box=1, root_x0=x0, root_y0=y0, root_L=L,
+                     p=4, kappa=kappa)
+    T = O.Tree(g, leaf=4, kappa=kappa, box=(x0, y0, L))
+    assert T.level.max() == 3
+    compare_tree(prob, T)
+    prob.close()
+
+
 def test_geometry_errors():
     x1 = np.array([0.0, 1.0])
     y1 = np.array([0.0, 0.0])
@@ -201,6 +220,9 @@ def test_c2_products_full_size(c2):
     yf = prob.apply(Dd, F.FMDDM_APPLY_FMM).cpu().numpy().reshape(-1, 2)
     assert rel(yf, yd) < 1e-6
     assert elementwise(yf[idx], yo) < 1e-6
+    # the interpolation error at p = 20 is ~1e-14 on this geometry; a bar
+    # far below the 1e-6 contract catches an order-specific indexing error
+    assert rel(yf, yd) < 1e-11
 
 
 def test_solve_griffith_c1():
@@ -298,4 +320,35 @@ def test_solve_svd_griffith():
     x, info = prob.solve(b, F.FMDDM_APPLY_FMM)
     assert info["converged"]
     assert rel(x.cpu().numpy(), xo) < 1e-8
+    prob.close()
+
+
+# ------------------------------------------------ high Chebyshev orders
+def _highp_module():
+    import importlib.util
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "make_fmm_highp.py")
+    spec = importlib.util.spec_from_file_location("make_fmm_highp", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+@pytest.mark.parametrize("name", ["random2000_p20", "random2000_p24", "random400_p28", "random400_p32"])
+def test_fmm_high_order_matches_oracle_fmm(name):
+    """FMM (dense M2L) at p = 20 (the benchmark order), 24 (the largest
+    order with four leaf slots per multipole-transfer block) and 28, 32 (the
+    two-slot path) against the oracle's level-by-level FMM (eqs. 3.6-3.11),
+    stored by tests/golden/make_fmm_highp.py: <= 1e-12 relative, on trees of
+    9-11 levels."""
+    G = _highp_module()
+    wl, D, leaf, p = G.case_inputs(name)
+    ref = np.load(G.path_of(name), allow_pickle=False)
+    assert np.array_equal(ref["checksum"], G.checksum(wl, D)), "input generators changed: rerun the script"
+    assert int(ref["p"]) == p and int(ref["leaf"]) == leaf and int(ref["levels"]) >= 5
+    prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=wl.E, nu=wl.nu, leaf=leaf, p=p, m2l=F.FMDDM_M2L_DENSE)
+    y = prob.apply(prob.vec(D), F.FMDDM_APPLY_FMM).cpu().numpy()
+    yo = ref["y"]
+    assert rel(y, yo) < 1e-12
+    assert elementwise(y, yo) < 1e-11
     prob.close()

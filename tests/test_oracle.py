@@ -412,3 +412,39 @@ def test_well_cluster_paper_observations():
     assert abs(Ds[2, 20]) < 1e-3 * Dn[2, 20]
     assert Dn[0, 20] > Dn[2, 20] and Dn[4, 20] > Dn[2, 20]
     assert np.allclose(Dn[0], Dn[4], rtol=1e-9)               # mirror symmetry
+
+
+def _split_tie_kappa(g):
+    """kappa at which the long element of W.split_tie() ties the split test
+    of its level-2 cell exactly: children of side 2 >= kappa * amax."""
+    amax = g.a.max()
+    kappa = 2.0 / amax
+    assert kappa * amax == 2.0
+    return kappa
+
+
+def test_tree_split_at_a_tie():
+    """Section 3.1 split rule with the size reading (children at least kappa
+    times the largest half-length): a tie splits (>=).  One unit in the last
+    place more on the half-length stops the split one level earlier, so the
+    tree depends on the half-length's rounding (the GPU builds the same tree
+    bit for bit, test_gpu_parity)."""
+    wl = W.split_tie()
+    g = O.Geometry.of(wl)
+    dx, dy = wl.x2[0] - wl.x1[0], wl.y2[0] - wl.y1[0]
+    assert g.a[0] == 0.5 * np.sqrt(dx * dx + dy * dy)           # separately rounded
+    assert 0.5 * np.hypot(dx, dy) == np.nextafter(g.a[0], 1.0)  # one ulp above
+    kappa = _split_tie_kappa(g)
+    box = wl.meta["root_box"]
+
+    def leaf_level_of_long_element(gg):
+        T = O.Tree(gg, leaf=4, kappa=kappa, box=box, lists=False)
+        pos = int(np.where(T.perm == 0)[0][0])
+        leafs = np.where((T.isleaf == 1) & (T.pbeg <= pos) & (T.pend > pos))[0]
+        assert len(leafs) == 1
+        return int(T.level[leafs[0]])
+
+    assert leaf_level_of_long_element(g) == 3
+    g.a = g.a.copy()
+    g.a[0] = np.nextafter(g.a[0], 1.0)
+    assert leaf_level_of_long_element(g) == 2

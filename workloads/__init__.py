@@ -170,6 +170,24 @@ def well_cluster(n_frac: int = 5, elems: int = 4000, half_length: float = 400.0,
                     meta={"half_length": half_length, "spacing": spacing})
 
 
+def split_tie() -> Workload:
+    """Nine elements in the root square [0, 16)^2 (pass it as the user root
+    box): one long element from (2, 2) to (2.7896393349678577,
+    2.8656608821898697) and eight short horizontal ones (length 0.02)
+    centred at (2.1 + 0.2 k, 3.5).  The long element's squared length is
+    not a double; rounding its two squares and their sum separately gives a
+    length one unit in the last place below the value a fused multiply-add
+    or a correctly rounded hypot gives."""
+    cxs = 2.1 + 0.2 * np.arange(8)
+    x1 = np.concatenate([[2.0], cxs - 0.01])
+    x2 = np.concatenate([[2.7896393349678577], cxs + 0.01])
+    y1 = np.concatenate([[2.0], np.full(8, 3.5)])
+    y2 = np.concatenate([[2.8656608821898697], np.full(8, 3.5)])
+    n = x1.shape[0]
+    return Workload("split_tie", x1, y1, x2, y2, np.zeros(n), np.zeros(n, np.int64),
+                    meta={"root_box": (0.0, 0.0, 16.0)})
+
+
 def random_vector(seed: int, n: int, scale: float = 1e-3) -> np.ndarray:
     """Seeded displacement-discontinuity vector, element-major [Ds, Dn]."""
     rng = np.random.Generator(np.random.PCG64(seed))
