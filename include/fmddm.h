@@ -224,6 +224,23 @@ fmddm_status fmddm_tree_export_list(fmddm_ctx *ctx, const fmddm_tree *t, int whi
 fmddm_status fmddm_apply(fmddm_ctx *ctx, fmddm_tree *t, int mode, const double *D,
                          double *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the FMM
+ * product of fmddm_apply (FMDDM_APPLY_FMM, FP64 contexts only) with every
+ * intermediate it writes and reads again in one static device workspace
+ * of 96 MiB, which each device the library runs on holds until the
+ * process ends.  The call allocates nothing: no hipMalloc, hipFree or
+ * allocating library routine.  D, out: device, 2n doubles each, out may
+ * not alias D.  The tree must already have run one fmddm_apply FMM product
+ * (that builds its schedules and operators); otherwise FMDDM_EINVAL.  A
+ * product whose intermediates exceed the workspace (the message states
+ * both sizes; C2, N = 20000 at p = 20, needs 72 MB) returns FMDDM_EINVAL.
+ * FMDDM_EUNSUPPORTED for FP32/BF16 contexts.  Same kernels, same order:
+ * the result equals fmddm_apply's bit for bit.  Every call on one device
+ * shares that device's workspace and leaves its contents behind; calls
+ * that overlap on one device (other streams, other threads) race. */
+fmddm_status fmddm_apply_static(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out);
+
 /* Right-hand side of one elastic step (Section 4): tractions the
  * discontinuities must induce so that the element faces carry the fluid
  * pressure pf[i] (device, n doubles, compression-positive) under the far

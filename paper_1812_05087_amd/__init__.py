@@ -30,7 +30,7 @@ LIST_U, LIST_V, LIST_W, LIST_X = 0, 1, 2, 3
 EXPORTED = [
     "fmddm_default_params", "fmddm_create", "fmddm_destroy", "fmddm_last_error",
     "fmddm_build_tree", "fmddm_tree_free", "fmddm_tree_get_info", "fmddm_tree_export",
-    "fmddm_tree_export_list", "fmddm_apply", "fmddm_rhs", "fmddm_solve", "fmddm_sif",
+    "fmddm_tree_export_list", "fmddm_apply", "fmddm_apply_static", "fmddm_rhs", "fmddm_solve", "fmddm_sif",
     "fmddm_profile", "fmddm_profile_read",
     "fmddm_server_create", "fmddm_server_destroy", "fmddm_server_last_error", "fmddm_server_footprint",
     "fmddm_server_submit", "fmddm_server_step", "fmddm_server_poll", "fmddm_server_release",
@@ -138,6 +138,7 @@ def lib():
         L.fmddm_tree_export.argtypes = [_vp, _vp] + [_vp] * 11
         L.fmddm_tree_export_list.argtypes = [_vp, _vp, C.c_int, _vp, _vp]
         L.fmddm_apply.argtypes = [_vp, _vp, C.c_int, _vp, _vp]
+        L.fmddm_apply_static.argtypes = [_vp, _vp, _vp, _vp]
         L.fmddm_rhs.argtypes = [_vp, _vp, _vp, C.c_double, C.c_double, _vp]
         L.fmddm_solve.argtypes = [_vp, _vp, C.c_int, _vp, _vp, C.POINTER(SolveInfo)]
         L.fmddm_sif.argtypes = [_vp, _vp, _vp, C.c_int64, _d, _d]
@@ -278,6 +279,12 @@ def fmddm_tree_export_list(ctx, tree, which):
 
 def fmddm_apply(ctx, tree, mode, D, out):
     return _check(lib().fmddm_apply(ctx, tree, mode, _ptr(D), _ptr(out)), ctx)
+
+
+def fmddm_apply_static(ctx, tree, D, out):
+    """The FMM product in the library's static device workspace (allocates
+    nothing); the tree must have run one fmddm_apply FMM product."""
+    _check(lib().fmddm_apply_static(ctx, tree, _ptr(D), _ptr(out)), ctx)
 
 
 def fmddm_rhs(ctx, tree, pf, SH, Sh, rhs):

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfmddm.so")
 SOURCES = ["api.hip", "alloc.hip", "tree.hip", "fmm.hip", "direct.hip", "solve.hip", "serve.hip", "poro.hip",
-           "tune.hip", "precond.hip", "peaks.hip"]
+           "tune.hip", "precond.hip", "peaks.hip", "noalloc.hip"]
 OBJDIR = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
