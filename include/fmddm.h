@@ -367,6 +367,11 @@ fmddm_status fmddm_profile_read(fmddm_ctx *ctx, double *ms, int64_t *count);
  * level); with FMDDM_APPLY_FMM the far field goes through the black-box
  * FMM of Section 3 with the time-dependent kernel (operators per tree
  * level and time level, built on first use and kept with the tree).
+ * FMDDM_APPLY_DENSE is the history-only variant (the earlier method the
+ * paper builds on, Section 2): the left-hand side K_0 as a stored dense
+ * 3n x 3n matrix of exact element integrals (72 n^2 bytes, assembled on
+ * first use; ENOMEM if it does not fit), the history coefficients K_m,
+ * m >= 1, and the history sum through the FMM.
  * ------------------------------------------------------------------------ */
 typedef struct {
     double nu_u;              /* undrained Poisson ratio, nu < nu_u < 0.5 */
@@ -377,7 +382,8 @@ typedef struct {
     int32_t mode;             /* FMDDM_APPLY_DIRECT: exact element integrals for every pair;
                                  FMDDM_APPLY_FMM: the same for neighbouring elements and
                                  Chebyshev multipoles (the context's p, 2..16) for well-separated
-                                 cells, the time levels contracted in one M2L product */
+                                 cells, the time levels contracted in one M2L product;
+                                 FMDDM_APPLY_DENSE: K_0 stored dense and exact, history by FMM */
     int64_t near_cache_bytes; /* FMDDM_APPLY_FMM only: device memory for the near-field cache.
                                  The exact element integrals of neighbouring elements depend only
                                  on the geometry, the medium and the time level, so each level's
@@ -434,11 +440,15 @@ int64_t fmddm_trim_cache(void);
  *
  * Each request is the problem of Section 4 for its own geometry: build the
  * tree, form the right-hand side, solve with GMRES whose products are FMM
- * products.  `steps` load steps ramp the fluid pressure linearly from
- * pf/steps to pf (far-field stress constant), each solved to `tol` starting
- * from the previous step's DDs (an elastic, quasi-static sequence of single
- * time steps; the time-dependent poroelastic history term is not part of a
- * request).
+ * products.  On an elastic server `steps` load steps ramp the fluid
+ * pressure linearly from pf/steps to pf (far-field stress constant), each
+ * solved to `tol` starting from the previous step's DDs.  On a server given
+ * a poroelastic medium (fmddm_server_set_poro) a request is a time march of
+ * `steps` steps of dt (Section 2, eqs. 2.3-2.5): constant loads pf, SH, Sh
+ * from t = 0, step h solving F(dt) D^h = b - sum_{k<h} K_{h-k} D^k as
+ * fmddm_poro_rhs, fmddm_add_history and fmddm_poro_solve do, with the
+ * multipole form on the product and the history sum; the result is D^steps
+ * (3 unknowns per element).
  *
  * Continuous batching: fmddm_server_step advances every admitted request by
  * one unit of work (one GMRES residual or Arnoldi step, enqueued on that
@@ -489,7 +499,8 @@ typedef struct {
 /* Creates a server for problems with parameters `p` (material, tree and FMM
  * settings, GMRES restart and maxit; p->tol is ignored, each request has
  * its own).  At most `max_slots` requests are admitted at once (1..64);
- * `hbm_budget` bytes (0: 90 % of the device memory free at creation) bound
+ * `hbm_budget` bytes (0: 90 % of the device memory free at creation, counting
+ * the blocks the library caches for reuse) bound
  * the sum of the admitted requests' estimated footprints.  The M2L operators
  * are built once here and shared by all requests. */
 fmddm_status fmddm_server_create(const fmddm_params *p, int max_slots, int64_t hbm_budget,
@@ -497,8 +508,17 @@ fmddm_status fmddm_server_create(const fmddm_params *p, int max_slots, int64_t h
 void fmddm_server_destroy(fmddm_server *s);
 const char *fmddm_server_last_error(const fmddm_server *s);
 
+/* Makes the server poroelastic (eqs. 2.1-2.5): the medium, dt and p0 of
+ * fmddm_poro_set apply to every later request (mode must be
+ * FMDDM_APPLY_FMM; near_cache_bytes 0 gives each request a quarter of the
+ * budget divided by max_slots for its stored near blocks).  Only while no
+ * request is queued or running (EINVAL otherwise); EINVAL / EUNSUPPORTED
+ * as fmddm_poro_set. */
+fmddm_status fmddm_server_set_poro(fmddm_server *s, const fmddm_poro_params *pp);
+
 /* Device-memory estimate (bytes) the server charges a request of n
- * elements against the budget. */
+ * elements against the budget (poroelastic servers: a march of 10 steps;
+ * a submitted request is charged for its own step count). */
 int64_t fmddm_server_footprint(const fmddm_server *s, int64_t n);
 
 /* Queues a request; *ticket identifies it.  Validates the request (EINVAL)
@@ -511,9 +531,10 @@ fmddm_status fmddm_server_submit(fmddm_server *s, const fmddm_request *r, int64_
  * and its one-time set-up). */
 fmddm_status fmddm_server_step(fmddm_server *s, int *active, int *queued);
 
-/* State of a request.  Once it is DONE, D (host, 2n doubles, may be NULL)
- * receives its DDs in the convention of fmddm_apply; the server keeps them
- * until fmddm_server_release. */
+/* State of a request.  Once it is DONE, D (host, may be NULL) receives its
+ * DDs in the convention of fmddm_apply (2n doubles) or, on a poroelastic
+ * server, of fmddm_poro_apply (3n doubles); the server keeps them until
+ * fmddm_server_release. */
 fmddm_status fmddm_server_poll(fmddm_server *s, int64_t ticket, fmddm_result *res, double *D);
 
 /* Forgets a finished request. */

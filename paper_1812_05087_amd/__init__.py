@@ -32,7 +32,7 @@ EXPORTED = [
     "fmddm_build_tree", "fmddm_tree_free", "fmddm_tree_get_info", "fmddm_tree_export",
     "fmddm_tree_export_list", "fmddm_apply", "fmddm_apply_static", "fmddm_rhs", "fmddm_solve", "fmddm_sif",
     "fmddm_profile", "fmddm_profile_read",
-    "fmddm_server_create", "fmddm_server_destroy", "fmddm_server_last_error", "fmddm_server_footprint",
+    "fmddm_server_create", "fmddm_server_set_poro", "fmddm_server_destroy", "fmddm_server_last_error", "fmddm_server_footprint",
     "fmddm_server_submit", "fmddm_server_step", "fmddm_server_poll", "fmddm_server_release",
     "fmddm_memory_in_use", "fmddm_memory_cached", "fmddm_trim_cache",
     "fmddm_poro_set", "fmddm_poro_apply", "fmddm_add_history", "fmddm_poro_rhs", "fmddm_poro_solve",
@@ -158,6 +158,7 @@ def lib():
         for name in ("fmddm_memory_in_use", "fmddm_memory_cached", "fmddm_trim_cache"):
             getattr(L, name).argtypes = []
         L.fmddm_poro_set.argtypes = [_vp, C.POINTER(PoroParams)]
+        L.fmddm_server_set_poro.argtypes = [_vp, C.POINTER(PoroParams)]
         L.fmddm_poro_apply.argtypes = [_vp, _vp, C.c_int, _vp, _vp]
         L.fmddm_add_history.argtypes = [_vp, _vp, C.c_int, _vp, _vp]
         L.fmddm_poro_rhs.argtypes = [_vp, _vp, _vp, C.c_double, C.c_double, _vp]
@@ -437,14 +438,23 @@ def fmddm_server_step(srv):
     return a.value, q.value
 
 
-def fmddm_server_poll(srv, ticket: int, n: int = 0):
-    """(result dict, D or None); D (host, 2n) once the request is done."""
+def fmddm_server_poll(srv, ticket: int, n: int = 0, comps: int = 2):
+    """(result dict, D or None); D (host, comps x n: 2 on elastic servers,
+    3 on poroelastic ones) once the request is done."""
     r = Result()
-    D = np.empty(2 * n) if n else None
+    D = np.empty(comps * n) if n else None
     _scheck(lib().fmddm_server_poll(srv, int(ticket), C.byref(r),
                                     C.c_void_p(D.ctypes.data) if D is not None else None), srv)
     res = {k: getattr(r, k) for k, _ in Result._fields_}
     return res, (D if res["state"] == FMDDM_REQ_DONE else None)
+
+
+def fmddm_server_set_poro(srv, nu_u, alpha, perm, visc, dt, p0=0.0, near_cache_bytes=0):
+    """Poroelastic medium for every later request (time marches with the
+    multipole form, FMDDM_APPLY_FMM)."""
+    pp = PoroParams(float(nu_u), float(alpha), float(perm), float(visc), float(dt), float(p0), FMDDM_APPLY_FMM,
+                    int(near_cache_bytes))
+    _scheck(lib().fmddm_server_set_poro(srv, C.byref(pp)), srv)
 
 
 def fmddm_server_release(srv, ticket: int):

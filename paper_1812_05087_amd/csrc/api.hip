@@ -99,6 +99,10 @@ void fmddm_destroy(fmddm_ctx *ctx)
 {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
+    // the caller may destroy the stream next: its work ends here, and the
+    // blocks released on it become idle
+    (void)hipStreamSynchronize(ctx->stream);
+    fmddm::dev_stream_idle(ctx->stream);
     delete ctx;
 }
 
@@ -120,6 +124,7 @@ fmddm_status fmddm_build_tree(fmddm_ctx *ctx, int64_t n, const double *x1, const
         return FMDDM_OK;
     });
     if (st != FMDDM_OK) {
+        fmddm::StreamScope scope(ctx->stream);  // its blocks may be in use by enqueued work
         delete t;
         return st;
     }
@@ -255,16 +260,16 @@ fmddm_status fmddm_poro_set(fmddm_ctx *ctx, const fmddm_poro_params *pp)
     const double nu = ctx->prm.nu;
     if (!(pp->nu_u > nu && pp->nu_u < 0.5) || !(pp->alpha > 0.0 && pp->alpha <= 1.0) || !(pp->perm > 0.0) ||
         !(pp->visc > 0.0) || !(pp->dt > 0.0) || !std::isfinite(pp->p0) ||
-        (pp->mode != FMDDM_APPLY_DIRECT && pp->mode != FMDDM_APPLY_FMM)) {
+        (pp->mode != FMDDM_APPLY_DIRECT && pp->mode != FMDDM_APPLY_FMM && pp->mode != FMDDM_APPLY_DENSE)) {
         ctx->err = "poroelastic parameters: need nu < nu_u < 0.5, 0 < alpha <= 1, perm, visc, dt > 0, "
-                   "mode DIRECT or FMM";
+                   "mode DIRECT, FMM or DENSE";
         return FMDDM_EINVAL;
     }
     if (ctx->prm.precision != FMDDM_PREC_FP64) {
         ctx->err = "the poroelastic operators are FP64 only";
         return FMDDM_EUNSUPPORTED;
     }
-    if (pp->mode == FMDDM_APPLY_FMM && (ctx->prm.p < 2 || ctx->prm.p > 16)) {
+    if (pp->mode != FMDDM_APPLY_DIRECT && (ctx->prm.p < 2 || ctx->prm.p > 16)) {
         ctx->err = "poroelastic FMM needs 2 <= p <= 16";
         return FMDDM_EUNSUPPORTED;
     }

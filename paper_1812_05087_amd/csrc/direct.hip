@@ -21,8 +21,8 @@ __global__ __launch_bounds__(DT) void k_direct(int n, const double *__restrict__
                                                const double *__restrict__ D, double gc,
                                                double *__restrict__ out)
 {
-    __shared__ double s_cx[DTILE], s_cy[DTILE], s_cb[DTILE], s_sb[DTILE], s_a[DTILE], s_ds[DTILE],
-        s_dn[DTILE];
+    __shared__ double s_cx[DTILE], s_cy[DTILE], s_cb[DTILE], s_sb[DTILE], s_c2[DTILE], s_s2[DTILE], s_a[DTILE],
+        s_ds[DTILE], s_dn[DTILE];
     int tid = threadIdx.x, sub = tid & (DTPT - 1);
     int i = blockIdx.x * DTGT + tid / DTPT;
     bool act = i < n;
@@ -32,15 +32,17 @@ __global__ __launch_bounds__(DT) void k_direct(int n, const double *__restrict__
         __syncthreads();
         int j = base + tid;
         if (j < n) {
-            s_cx[tid] = cx[j]; s_cy[tid] = cy[j]; s_cb[tid] = cb[j]; s_sb[tid] = sb[j];
+            const double c = cb[j], sn = sb[j];
+            s_cx[tid] = cx[j]; s_cy[tid] = cy[j]; s_cb[tid] = c; s_sb[tid] = sn;
+            s_c2[tid] = c * c - sn * sn; s_s2[tid] = 2.0 * c * sn;
             s_a[tid] = a[j]; s_ds[tid] = D[2 * j]; s_dn[tid] = D[2 * j + 1];
         }
         __syncthreads();
         int cnt = min(DTILE, n - base);
         if (act)
             for (int k = sub; k < cnt; k += DTPT)
-                elem_stress_unit(X, Y, s_cx[k], s_cy[k], s_cb[k], s_sb[k], s_a[k], s_ds[k], s_dn[k], sxx, syy,
-                                 sxy);
+                elem_stress_unit(X, Y, s_cx[k], s_cy[k], s_cb[k], s_sb[k], s_c2[k], s_s2[k], s_a[k], s_ds[k], s_dn[k],
+                                 sxx, syy, sxy);
     }
     sxx *= -gc;
     syy *= -gc;
@@ -81,7 +83,7 @@ __global__ void k_dense_assemble(int n, const double *__restrict__ cx, const dou
     }
 }
 
-// y = A x, one 256-thread block per row, 16-byte loads, fixed-order
+// y = A x, one 256-thread block per row, 16-byte loads (m even), fixed-order
 // reduction.  Streams the matrix once: HBM bound.
 __global__ __launch_bounds__(256) void k_gemv(int m, const double *__restrict__ A,
                                               const double *__restrict__ x, double *__restrict__ y)
@@ -92,11 +94,16 @@ __global__ __launch_bounds__(256) void k_gemv(int m, const double *__restrict__ 
     const dv2 *Ar = reinterpret_cast<const dv2 *>(A + (size_t)row * m);
     const dv2 *x2 = reinterpret_cast<const dv2 *>(x);
     double s = 0.0;
-    int m2 = m / 2;  // m = 2n is even
-    for (int k = threadIdx.x; k < m2; k += 256) {
-        dv2 av = __builtin_nontemporal_load(&Ar[k]);
-        dv2 xv = x2[k];
-        s += av.x * xv.x + av.y * xv.y;
+    if ((m & 1) == 0) {  // rows 16-byte aligned: pairs
+        int m2 = m / 2;
+        for (int k = threadIdx.x; k < m2; k += 256) {
+            dv2 av = __builtin_nontemporal_load(&Ar[k]);
+            dv2 xv = x2[k];
+            s += av.x * xv.x + av.y * xv.y;
+        }
+    } else {
+        const double *a1 = A + (size_t)row * m;
+        for (int k = threadIdx.x; k < m; k += 256) s += __builtin_nontemporal_load(&a1[k]) * x[k];
     }
     red[threadIdx.x] = s;
     __syncthreads();
@@ -114,6 +121,12 @@ void direct_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out)
     int n = (int)t->n;
     hipLaunchKernelGGL(k_direct, dim3(cdiv(n, DTGT)), dim3(DT), 0, ctx->stream, n, t->ocx.p, t->ocy.p,
                        t->ocb.p, t->osb.p, t->oa.p, D, ctx->gc, out);
+    FM_CHECK_LAUNCH();
+}
+
+void dense_gemv(hipStream_t s, int m, const double *A, const double *x, double *y)
+{
+    hipLaunchKernelGGL(k_gemv, dim3((unsigned)m), dim3(256), 0, s, m, A, x, y);
     FM_CHECK_LAUNCH();
 }
 

@@ -63,12 +63,18 @@ __device__ __forceinline__ void elem_stress_add(double X, double Y, double cx, d
 }
 
 // elem_stress_add without the factor -gc (the caller scales the sum once),
-// and with one reciprocal for both end-point distances: r = 1/(d1 d2) to
-// full precision (two Newton steps), 1/d1 = d2 r, 1/d2 = d1 r (within two
-// ulp).  For the inner loops of the near field and the exact product.
+// with one reciprocal for both end-point distances (r = 1/(d1 d2) to full
+// precision, 1/d1 = d2 r, 1/d2 = d1 r, within two ulp), and the rotation to
+// the global frame in double-angle form.  With c2 = cos 2 beta and s2 =
+// sin 2 beta of the source (computed once per source by the caller):
+//   sxx = m + d c2 - lxy s2,  syy = m - d c2 + lxy s2,  sxy = d s2 + lxy c2,
+// m = (lxx + lyy) / 2 = Ds f_xy + Dn f_yy,
+// d = (lxx - lyy) / 2 = Ds (f_xy + y f_xyy) + Dn y f_yyy,
+// the local-frame stresses l of elem_stress_add.  For the inner loops of
+// the near field and the exact product.
 __device__ __forceinline__ void elem_stress_unit(double X, double Y, double cx, double cy, double cb, double sb,
-                                                 double a, double Ds, double Dn, double &sxx, double &syy,
-                                                 double &sxy)
+                                                 double c2, double s2, double a, double Ds, double Dn, double &sxx,
+                                                 double &syy, double &sxy)
 {
     double dx = X - cx, dy = Y - cy;
     double x = dx * cb + dy * sb;
@@ -81,15 +87,15 @@ __device__ __forceinline__ void elem_stress_unit(double X, double Y, double cx, 
     double fyy = xp * i2 - xm * i1;
     double j1 = i1 * i1, j2 = i2 * i2;
     double fxyy = (xm * xm - y2) * j1 - (xp * xp - y2) * j2;
-    double fyyy = 2.0 * y * (xm * j1 - xp * j2);
-    double yfxyy = y * fxyy, yfyyy = y * fyyy;
-    double lxx = Ds * (2.0 * fxy + yfxyy) + Dn * (fyy + yfyyy);
-    double lyy = Dn * (fyy - yfyyy) - Ds * yfxyy;
+    double yfyyy = 2.0 * y2 * (xm * j1 - xp * j2);
+    double yfxyy = y * fxyy;
+    double m = Ds * fxy + Dn * fyy;
+    double d = Ds * (fxy + yfxyy) + Dn * yfyyy;
     double lxy = Ds * (fyy + yfyyy) - Dn * yfxyy;
-    double c2 = cb * cb, s2 = sb * sb, cs = cb * sb;
-    sxx += c2 * lxx - 2.0 * cs * lxy + s2 * lyy;
-    syy += s2 * lxx + 2.0 * cs * lxy + c2 * lyy;
-    sxy += cs * (lxx - lyy) + (c2 - s2) * lxy;
+    double w = d * c2 - lxy * s2;
+    sxx += m + w;
+    syy += m - w;
+    sxy += d * s2 + lxy * c2;
 }
 
 // The same element stress in FP32 arithmetic, for the reduced-precision

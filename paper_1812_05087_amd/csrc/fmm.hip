@@ -820,44 +820,33 @@ __global__ __launch_bounds__(LT) void k_l2p(int nitem, const int *__restrict__ i
 // the item's partial stresses go to part_s.  RT = float is the
 // reduced-precision variant: offsets formed in FP64, the element formulas
 // and the per-point sums in FP32.
-constexpr int NT = 128, MAXE = 256;
+constexpr int NT = 128;
 
 template <typename RT>
 __global__ __launch_bounds__(NT) void k_p2p(
     int nitem, const int *__restrict__ it_leaf, const int *__restrict__ it_s0, const int *__restrict__ it_s1,
     const int *__restrict__ it_poff, const int *__restrict__ leaves, const int *__restrict__ pbeg,
-    const int *__restrict__ pend, const int *__restrict__ noff, const int *__restrict__ nbeg,
-    const int *__restrict__ npre, const double *__restrict__ cx, const double *__restrict__ cy,
-    const double *__restrict__ cb, const double *__restrict__ sb, const double *__restrict__ a,
-    const double *__restrict__ Ds, double gc, double *__restrict__ part)
+    const int *__restrict__ pend, const int *__restrict__ nfoff, const int *__restrict__ nflat,
+    const double *__restrict__ cx, const double *__restrict__ cy, const double *__restrict__ cb,
+    const double *__restrict__ sb, const double *__restrict__ a, const double *__restrict__ Ds, double gc,
+    double *__restrict__ part)
 {
     __shared__ double s_cx[NEAR_CHUNK], s_cy[NEAR_CHUNK];
-    __shared__ RT s_cb[NEAR_CHUNK], s_sb[NEAR_CHUNK], s_a[NEAR_CHUNK], s_ds[NEAR_CHUNK], s_dn[NEAR_CHUNK];
-    __shared__ int s_pre[MAXE], s_beg[MAXE];
+    __shared__ RT s_cb[NEAR_CHUNK], s_sb[NEAR_CHUNK], s_c2[NEAR_CHUNK], s_s2[NEAR_CHUNK], s_a[NEAR_CHUNK],
+        s_ds[NEAR_CHUNK], s_dn[NEAR_CHUNK];
     int k = xcd_remap(blockIdx.x, nitem);
     int li = it_leaf[k], s0 = it_s0[k], s1 = it_s1[k];
     int c = leaves[li];
     int tid = threadIdx.x;
     int tb = pbeg[c], te = pend[c], nt = te - tb;
-    int nb = noff[li], nn = noff[li + 1] - nb;
-    bool lds = nn <= MAXE;
-    if (lds)
-        for (int e = tid; e < nn; e += NT) {
-            s_pre[e] = npre[nb + e];
-            s_beg[e] = nbeg[nb + e];
-        }
-    __syncthreads();
+    // the leaf's near sources, flattened: position v is point nflat[nfoff[li] + v]
+    const int *src = nflat + nfoff[li];
     for (int v = s0 + tid; v < s1; v += NT) {
-        int lo = 0, hi = nn - 1;  // last entry with prefix <= v
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            int pm = lds ? s_pre[mid] : npre[nb + mid];
-            if (pm <= v) lo = mid;
-            else hi = mid - 1;
-        }
-        int j = (lds ? s_beg[lo] : nbeg[nb + lo]) + (v - (lds ? s_pre[lo] : npre[nb + lo]));
+        int j = src[v];
         int q = v - s0;
-        s_cx[q] = cx[j]; s_cy[q] = cy[j]; s_cb[q] = (RT)cb[j]; s_sb[q] = (RT)sb[j];
+        double cc = cb[j], ss = sb[j];
+        s_cx[q] = cx[j]; s_cy[q] = cy[j]; s_cb[q] = (RT)cc; s_sb[q] = (RT)ss;
+        s_c2[q] = (RT)(cc * cc - ss * ss); s_s2[q] = (RT)(2.0 * cc * ss);
         s_a[q] = (RT)a[j]; s_ds[q] = (RT)Ds[2 * j]; s_dn[q] = (RT)Ds[2 * j + 1];
     }
     __syncthreads();
@@ -874,8 +863,8 @@ __global__ __launch_bounds__(NT) void k_p2p(
         if (act) {
             if constexpr (sizeof(RT) == 8) {
                 for (int q = sub; q < cnt; q += tpt)
-                    elem_stress_unit(X, Y, s_cx[q], s_cy[q], s_cb[q], s_sb[q], s_a[q], s_ds[q], s_dn[q], sxx, syy,
-                                     sxy);
+                    elem_stress_unit(X, Y, s_cx[q], s_cy[q], s_cb[q], s_sb[q], s_c2[q], s_s2[q], s_a[q], s_ds[q],
+                                     s_dn[q], sxx, syy, sxy);
                 sxx *= -gc;
                 syy *= -gc;
                 sxy *= -gc;
@@ -1169,9 +1158,11 @@ void m2l_lowp(hipStream_t s, fmddm_tree *t, const M2LOps &M, const TO *Vt, const
     }
 }
 
-// Reduced-precision operator copies (once per operator set) and the tree's
-// FP32 intermediates (once per tree).
-void setup_lowp(fmddm_ctx *ctx, fmddm_tree *t, int prec)
+}  // namespace
+
+// Reduced-precision copies of the operator set, made once (on first use,
+// or up front where several threads share the set)
+void lowp_ops(fmddm_ctx *ctx, int prec)
 {
     M2LOps &M = *ctx->m2l;
     hipStream_t s = ctx->stream;
@@ -1204,6 +1195,17 @@ void setup_lowp(fmddm_ctx *ctx, fmddm_tree *t, int prec)
         FM_HIP(hipStreamSynchronize(s));
         M.have16 = true;
     }
+}
+
+namespace {
+
+// the operator copies and the tree's FP32 intermediates (once per tree)
+void setup_lowp(fmddm_ctx *ctx, fmddm_tree *t, int prec)
+{
+    lowp_ops(ctx, prec);
+    M2LOps &M = *ctx->m2l;
+    hipStream_t s = ctx->stream;
+    bool svd = M.mode == FMDDM_M2L_SVD;
     if (!t->Zm2l32.p) {
         int w = svd ? M.rp : M.Mp;
         t->Zm2l32.alloc((size_t)std::max<int64_t>(t->nV, 1) * w);
@@ -1735,14 +1737,12 @@ void fmm_apply_bufs(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out,
     P.begin(FMDDM_PH_P2P, s2, e1);
     if (prec == FMDDM_PREC_FP64)
         hipLaunchKernelGGL(k_p2p<double>, dim3(t->nitem), dim3(NT), 0, s2, t->nitem, t->it_leaf.p, t->it_s0.p,
-                           t->it_s1.p, t->it_poff.p, t->dleaves.p, t->cpbeg.p, t->cpend.p, t->noff.p, t->nbeg.p,
-                           t->npre.p, t->scx.p, t->scy.p, t->scb.p, t->ssb.p, t->sa.p, B.Dsort, ctx->gc,
-                           B.part_s);
+                           t->it_s1.p, t->it_poff.p, t->dleaves.p, t->cpbeg.p, t->cpend.p, t->nfoff.p, t->nflat.p,
+                           t->scx.p, t->scy.p, t->scb.p, t->ssb.p, t->sa.p, B.Dsort, ctx->gc, B.part_s);
     else
         hipLaunchKernelGGL(k_p2p<float>, dim3(t->nitem), dim3(NT), 0, s2, t->nitem, t->it_leaf.p, t->it_s0.p,
-                           t->it_s1.p, t->it_poff.p, t->dleaves.p, t->cpbeg.p, t->cpend.p, t->noff.p, t->nbeg.p,
-                           t->npre.p, t->scx.p, t->scy.p, t->scb.p, t->ssb.p, t->sa.p, B.Dsort, ctx->gc,
-                           B.part_s);
+                           t->it_s1.p, t->it_poff.p, t->dleaves.p, t->cpbeg.p, t->cpend.p, t->nfoff.p, t->nflat.p,
+                           t->scx.p, t->scy.p, t->scb.p, t->ssb.p, t->sa.p, B.Dsort, ctx->gc, B.part_s);
     FM_CHECK_LAUNCH();
     P.end(FMDDM_PH_P2P, s2, e1);
     FM_HIP(hipEventRecord(ctx->ev_join, s2));

@@ -37,6 +37,29 @@ void *dev_alloc(size_t bytes, size_t *rounded);
 void dev_release(void *p, size_t rounded);
 size_t dev_cache_trim();
 size_t dev_bytes(bool cached);
+// The work enqueued on s so far has completed (the caller synchronized it):
+// the blocks released under a scope on s become idle.  Called before a
+// stream is destroyed, and when a context lets go of its stream.
+void dev_stream_idle(hipStream_t s);
+
+// The stream whose work uses the buffers that this host thread allocates
+// and releases, for the duration of a scope (an entry point on a context,
+// a serving slot's set-up or step).  A block released inside the scope is
+// handed to allocations on the same stream at once (stream order keeps
+// the old work first) and to other streams only once the work enqueued on
+// it before the release has completed.  Outside every scope a released
+// block is taken to be idle.
+class StreamScope {
+  public:
+    explicit StreamScope(hipStream_t s);
+    ~StreamScope();
+    StreamScope(const StreamScope &) = delete;
+    StreamScope &operator=(const StreamScope &) = delete;
+
+  private:
+    hipStream_t prev_;
+    bool prev_set_;
+};
 
 // Owning device allocation from the cache, returned to it in the destructor.
 template <class T>
@@ -191,6 +214,7 @@ struct fmddm_tree {
     // near field: per leaf, source cells whose points act directly
     fmddm::DBuf<int> noff, nsrc;
     fmddm::DBuf<int> nbeg, npre, ntot;  // per near entry: first source, prefix in its leaf; per leaf: total
+    fmddm::DBuf<int> nfoff, nflat;      // per leaf: its near source points as one list (offsets, points)
     fmddm::DBuf<int> aoff, aidx;        // per leaf: its ancestors (itself first) at level >= 2
     // near-field work items: a leaf's sources split into chunks of at most
     // NEAR_CHUNK, each item producing partial stresses for the leaf's points
@@ -269,6 +293,10 @@ struct fmddm_tree {
     // left-hand side F(dt) in one multipole pass: the first level's near
     // blocks and M2L operators with the drained elastic part added
     fmddm::DBuf<double> pn_lhs, pf_ops0;
+    // history-only variant: the left-hand side as a dense 3n x 3n matrix
+    fmddm::DBuf<double> pdense;
+    int pdense_ok = 0;
+    double pdense_key[8] = {};
     fmddm::DBuf<double *> pn_lhs_ptr;
     double *pn_lhs_host = nullptr;  // source of the copy into pn_lhs_ptr
     int pn_lhs_ok = 0, pf_ops0_ok = 0;
@@ -336,6 +364,8 @@ int fmm_ksplit(const fmddm_ctx *ctx);
 // direct.hip
 void direct_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out);
 void dense_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out);
+// y = A x, A row-major m x m (one block per row, fixed-order sums)
+void dense_gemv(hipStream_t s, int m, const double *A, const double *x, double *y);
 // solve.hip
 void rhs_build(fmddm_ctx *ctx, fmddm_tree *t, const double *pf, double SH, double Sh, double *rhs,
                double pscale = 1.0);
@@ -406,6 +436,10 @@ void poro_apply(fmddm_ctx *ctx, fmddm_tree *t, int lag, const double *D, double 
 void poro_history(fmddm_ctx *ctx, fmddm_tree *t, int h, const double *Dh, double *rhs);
 void poro_rhs(fmddm_ctx *ctx, fmddm_tree *t, const double *pf, double SH, double Sh, double *rhs);
 void pc_setup_poro(fmddm_ctx *ctx, fmddm_tree *t);
+// fmm.hip: the reduced-precision copies of ctx's operator set for prec
+void lowp_ops(fmddm_ctx *ctx, int prec);
+// builds now what a march of H steps would build on first use
+void poro_prepare(fmddm_ctx *ctx, fmddm_tree *t, int H);
 
 inline int cdiv(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
@@ -416,6 +450,7 @@ fmddm_status guarded(fmddm_ctx *ctx, F &&f)
 {
     try {
         FM_HIP(hipSetDevice(ctx->device));
+        StreamScope scope(ctx->stream);
         fmddm_status st = f();
         if (ctx) ctx->err.clear();
         return st;

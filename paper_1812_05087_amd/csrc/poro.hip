@@ -40,6 +40,9 @@
 #include "gj.h"
 #include "internal.h"
 
+#include <atomic>
+#include <mutex>
+
 #include <cmath>
 
 namespace fmddm {
@@ -371,6 +374,40 @@ __global__ __launch_bounds__(PT) void k_poro_pairs(int n, const double *__restri
     pp[0] = ts;
     pp[1] = tn;
     pp[2] = o[3];
+}
+
+// The left-hand side F(dt) as a dense matrix (history-only variant): row
+// 3i + r (shear traction, normal traction, pressure at element i), column
+// 3j + c (unit D_s, D_n, D_q on element j), caller order, row-major.  One
+// thread per (i, j): the element's transient block by the near-field
+// quadrature plus the drained elastic part in closed form.
+__global__ __launch_bounds__(256) void k_pdense(int n, const double *__restrict__ cx, const double *__restrict__ cy,
+                                                const double *__restrict__ cb, const double *__restrict__ sb,
+                                                const double *__restrict__ ha, double dt, PoroK K,
+                                                double *__restrict__ A)
+{
+    const int i = blockIdx.x, j = blockIdx.y * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const double X = cx[i], Y = cy[i];
+    double B[12];
+    elem_block(K, X, Y, cx[j], cy[j], cb[j], sb[j], ha[j], dt, B);
+    for (int c = 0; c < 2; ++c) {
+        double sxx = 0.0, syy = 0.0, sxy = 0.0;
+        elem_stress_add(X, Y, cx[j], cy[j], cb[j], sb[j], ha[j], c == 0 ? 1.0 : 0.0, c == 1 ? 1.0 : 0.0, K.gc, sxx,
+                        syy, sxy);
+        B[c] += sxx;
+        B[3 + c] += syy;
+        B[6 + c] += sxy;
+    }
+    const size_t ld = 3 * (size_t)n;
+    double *row = A + 3 * (size_t)i * ld + 3 * (size_t)j;
+    for (int c = 0; c < 3; ++c) {
+        double ts, tn;
+        traction(cb[i], sb[i], B[c], B[3 + c], B[6 + c], ts, tn);
+        row[c] = ts;
+        row[ld + c] = tn;
+        row[2 * ld + c] = B[9 + c];
+    }
 }
 
 // Block-Jacobi blocks of the left-hand side F(dt): one workgroup per group
@@ -760,11 +797,16 @@ __global__ void k_take2(int n, const double *__restrict__ E, double *__restrict_
     D2[2 * i + 1] = E[3 * i + 1];
 }
 
-bool g_gl_ready[64] = {false};
+// quadrature rules and series coefficients in constant memory, uploaded
+// once per device (serving set-ups may ask from several host threads)
+std::atomic<bool> g_gl_ready[64];
+std::mutex g_gl_mu;
 
 void upload_rules(int device)
 {
-    if (device >= 0 && device < 64 && g_gl_ready[device]) return;
+    if (device >= 0 && device < 64 && g_gl_ready[device].load(std::memory_order_acquire)) return;
+    std::lock_guard<std::mutex> lock(g_gl_mu);
+    if (device >= 0 && device < 64 && g_gl_ready[device].load(std::memory_order_acquire)) return;
     std::vector<double> t, w, t8, w8;
     gauss_legendre(QN, t, w);
     gauss_legendre(8, t8, w8);
@@ -787,7 +829,7 @@ void upload_rules(int device)
     FM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_e1w), e1w, sizeof(e1w)));
     FM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_hc), hc, sizeof(hc)));
     FM_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_p2c), p2c, sizeof(p2c)));
-    if (device >= 0 && device < 64) g_gl_ready[device] = true;
+    if (device >= 0 && device < 64) g_gl_ready[device].store(true, std::memory_order_release);
 }
 
 PoroK poro_constants(const fmddm_ctx *ctx)
@@ -1130,15 +1172,44 @@ void poro_fmm_sum(fmddm_ctx *ctx, fmddm_tree *t, int H, const double *E, bool dr
 
 }  // namespace
 
+// out = F(dt) D with the stored dense left-hand side (assembled on first
+// use, and again when the medium or dt changes).
+void poro_dense_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *out)
+{
+    const int n = (int)t->n;
+    const size_t m = 3 * (size_t)n;
+    double key[8];
+    medium_key(ctx, key);
+    hipStream_t s = ctx->stream;
+    if (!t->pdense_ok || !same_key(key, t->pdense_key, 8)) {
+        if (!t->pdense.p || t->pdense.n < m * m) {
+            size_t freeb = 0, totalb = 0;
+            FM_HIP(hipMemGetInfo(&freeb, &totalb));
+            if (m * m * 8 + ((size_t)1 << 30) > freeb + dev_bytes(true))
+                throw Error{FMDDM_ENOMEM, "dense poroelastic left-hand side does not fit"};
+            t->pdense.alloc(m * m);
+            t->bytes += (int64_t)(m * m * 8);
+        }
+        upload_rules(ctx->device);
+        hipLaunchKernelGGL(k_pdense, dim3(n, cdiv(n, 256)), dim3(256), 0, s, n, t->ocx.p, t->ocy.p, t->ocb.p,
+                           t->osb.p, t->oa.p, ctx->poro.dt, poro_constants(ctx), t->pdense.p);
+        FM_CHECK_LAUNCH();
+        for (int k = 0; k < 8; ++k) t->pdense_key[k] = key[k];
+        t->pdense_ok = 1;
+    }
+    dense_gemv(s, (int)m, t->pdense.p, D, out);
+}
+
 void poro_apply(fmddm_ctx *ctx, fmddm_tree *t, int lag, const double *D, double *out)
 {
     if (!ctx->poro_set) throw Error{FMDDM_EINVAL, "poroelastic parameters not set (fmddm_poro_set)"};
     const double dt = ctx->poro.dt;
     const int n = (int)t->n, m3 = 3 * n;
-    const bool fmm = ctx->poro.mode == FMDDM_APPLY_FMM;
+    const bool fmm = ctx->poro.mode != FMDDM_APPLY_DIRECT;  // DENSE: multipole history coefficients
     hipStream_t s = ctx->stream;
     if (lag == 0) {
-        if (fmm) poro_fmm_sum(ctx, t, 1, D, true, 0, out);
+        if (ctx->poro.mode == FMDDM_APPLY_DENSE) poro_dense_apply(ctx, t, D, out);
+        else if (fmm) poro_fmm_sum(ctx, t, 1, D, true, 0, out);
         else poro_sum(ctx, t, 1, {dt}, D, 0, 0, out);
         return;
     }
@@ -1174,13 +1245,28 @@ void poro_history(fmddm_ctx *ctx, fmddm_tree *t, int h, const double *Dh, double
     hipStream_t s = ctx->stream;
     hipLaunchKernelGGL(k_hist_terms, dim3(cdiv(m3, 256), h), dim3(256), 0, s, m3, h, Dh, t->poro_E.p);
     FM_CHECK_LAUNCH();
-    if (ctx->poro.mode == FMDDM_APPLY_FMM) {
+    if (ctx->poro.mode != FMDDM_APPLY_DIRECT) {  // FMM, or the history-only variant
         poro_fmm_sum(ctx, t, h, t->poro_E.p, false, 1, rhs);
         return;
     }
     std::vector<double> times(h);
     for (int j = 1; j <= h; ++j) times[j - 1] = j * dt;
     poro_sum(ctx, t, h, times, t->poro_E.p, -1, 1, rhs);
+}
+
+// Everything a march of H steps builds on first use, built now: the
+// multipole schedule and operators for H time levels, the left-hand side's
+// operators and near blocks, and the history's near blocks for the levels
+// the budget holds.  A serving loop calls this at admission so that the
+// steps themselves enqueue work without waiting on the device.
+void poro_prepare(fmddm_ctx *ctx, fmddm_tree *t, int H)
+{
+    if (!ctx->poro_set) throw Error{FMDDM_EINVAL, "poroelastic parameters not set (fmddm_poro_set)"};
+    upload_rules(ctx->device);
+    if (ctx->poro.mode != FMDDM_APPLY_FMM) return;
+    poro_fmm_setup(ctx, t, std::max(H, 1));
+    if (near_lhs(ctx, t)) lhs_ops(ctx, t);
+    if (H > 1) near_levels(ctx, t, H);
 }
 
 // Block-Jacobi preconditioner of the poroelastic left-hand side, rebuilt

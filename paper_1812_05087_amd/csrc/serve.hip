@@ -2,24 +2,34 @@
 // batched continuously.
 //
 // A request is the problem of Section 4 for its own geometry (tree, right-
-// hand side, GMRES with FMM products), repeated over `steps` load steps of
-// a linearly ramped fluid pressure, each warm-started from the previous
-// DDs.  The engine keeps up to max_slots requests admitted.  Each slot owns
-// a context with its own pair of streams (default priority) and shares the
+// hand side, GMRES with FMM products), repeated over `steps` steps, each
+// warm-started from the previous DDs.  Elastic servers ramp the fluid
+// pressure linearly over the steps (quasi-static load steps).  A server
+// given a poroelastic medium (fmddm_server_set_poro) marches in time
+// instead (Section 2, eqs. 2.3-2.5): step h solves F(dt) D^h = b - sum over
+// k < h of K_{h-k} D^k with the multipole form on both the product and the
+// history sum.
+//
+// The engine keeps up to max_slots requests admitted.  Each slot owns a
+// context with its own pair of streams (default priority) and shares the
 // M2L operators and Chebyshev tables built once for the server.  One engine
 // step polls every slot's last enqueued work without blocking and enqueues
 // its next unit (a GMRES residual or Arnoldi step), so the kernels of
 // different requests run side by side on the device; then it admits at
 // most one queued request if a slot is free and its footprint estimate
-// fits the memory budget (first come, first served).  A request's buffers
-// are its own and every kernel is deterministic, so its result does not
-// depend on what runs beside it.
+// fits the memory budget (first come, first served).  An admitted
+// request's set-up (tree, schedules, operators, near blocks,
+// preconditioner), which waits on its stream several times, runs on a host
+// thread of its own, so the other slots keep receiving work meanwhile.  A
+// request's buffers are its own and every kernel is deterministic, so its
+// result does not depend on what runs beside it.
 #include "internal.h"
 
 #include <chrono>
 #include <cmath>
 #include <cstring>
 #include <deque>
+#include <future>
 #include <unordered_map>
 
 using fmddm::DBuf;
@@ -38,10 +48,12 @@ struct Slot {
     fmddm_ctx *ctx = nullptr;
     hipStream_t stream = nullptr;
     int64_t req = 0;          // 0: free
-    int phase = 0;            // 1 solving, 2 copying the result out
+    int phase = 0;            // 1 solving, 2 copying the result out, 3 setting up (host thread)
+    std::future<void> setup;  // the set-up of phase 3
     int step = 0;
     fmddm_tree *t = nullptr;
     DBuf<double> pf, b, x;
+    DBuf<double> b0, hist;    // poroelastic: right-hand side, DDs of the steps so far
     fmddm::GmresRun g;
     double *hostD = nullptr;  // pinned
     size_t host_cap = 0;
@@ -59,6 +71,8 @@ double seconds_since(std::chrono::steady_clock::time_point t0)
 
 struct fmddm_server {
     fmddm_params prm{};
+    fmddm_poro_params poro{};  // poroelastic medium (poro_set)
+    int poro_set = 0;
     int max_slots = 0;
     int64_t budget = 0, used = 0;
     int device = 0;
@@ -75,6 +89,8 @@ struct fmddm_server {
 
 fmddm_server::~fmddm_server()
 {
+    for (Slot &s : slots)
+        if (s.setup.valid()) s.setup.wait();  // set-ups still running
     (void)hipSetDevice(device);
     (void)hipDeviceSynchronize();
     for (Slot &s : slots) {
@@ -82,13 +98,21 @@ fmddm_server::~fmddm_server()
         s.pf.reset();
         s.b.reset();
         s.x.reset();
+        s.b0.reset();
+        s.hist.reset();
         if (s.hostD) (void)hipHostFree(s.hostD);
         if (s.ev) (void)hipEventDestroy(s.ev);
         delete s.ctx;
-        if (s.stream) (void)hipStreamDestroy(s.stream);
+        if (s.stream) {
+            fmddm::dev_stream_idle(s.stream);
+            (void)hipStreamDestroy(s.stream);
+        }
     }
     delete base;
-    if (base_stream) (void)hipStreamDestroy(base_stream);
+    if (base_stream) {
+        fmddm::dev_stream_idle(base_stream);
+        (void)hipStreamDestroy(base_stream);
+    }
 }
 
 namespace {
@@ -102,7 +126,7 @@ namespace {
 // (2 x 32)^2 doubles per 32 elements) and one more vector, with the two-level
 // one also the coarse inverse.  Sizes are
 // rounded up by the allocator, hence the final 25 %.
-int64_t footprint(const fmddm_params &p, int rank_pad, int64_t n)
+int64_t footprint(const fmddm_params &p, int rank_pad, int64_t n, int steps = 0, int64_t near_cap = 0)
 {
     const int64_t M = 3LL * p.p * p.p, Mp = (M + 63) / 64 * 64;
     const int64_t rp = p.m2l == FMDDM_M2L_SVD ? rank_pad : Mp;
@@ -115,6 +139,21 @@ int64_t footprint(const fmddm_params &p, int rank_pad, int64_t n)
     if (p.precond == FMDDM_PRECOND_TWO_LEVEL) {  // coarse inverse: at most 2048 aggregates, else left out
         const int64_t nc = std::min<int64_t>(n, 2048);
         b += 8 * (2 * nc) * (2 * nc) + 8 * 6 * nc;
+    }
+    if (steps > 0) {
+        // poroelastic march of `steps` steps (3 unknowns, 4 charges): the
+        // Krylov basis and vectors at 3n, the step history and its terms,
+        // per time level the four-charge weights and sources; per cell the
+        // fields, pair products and far stress; the M2L operators per
+        // (level, offset) combination and time level (at most 40 offsets on
+        // each of ~log4(n) + 4 levels); the near blocks (96 B per near pair
+        // and level, capped by the near-field budget)
+        const int64_t Mq = (4LL * p.p * p.p + 63) / 64 * 64;
+        const int64_t H = steps, levels = 4 + (int64_t)std::ceil(std::log((double)cells) / std::log(4.0));
+        b += n * 8 * (3 * (p.restart + 6) + 6 * H + 7 * H + 4 * levels) + cells * 8 * (2 * Mq + 27 * Mq + H * Mq);
+        b += 40 * levels * Mq * Mq * 8 * (H + 1);
+        if (p.precond != FMDDM_PRECOND_NONE) b += n * 8 * 3 * 3 * 21;  // 3 x 3 blocks of 21-element groups
+        b += std::min<int64_t>(near_cap, 96LL * n * 64 * 4 * (H + 1));
     }
     return b + b / 4;
 }
@@ -168,19 +207,44 @@ int residual_mode(const fmddm_server *s, const Slot &sl)
     return sl.mode == FMDDM_APPLY_FMM && s->prm.precision != FMDDM_PREC_FP64 ? fmddm::APPLY_FMM_FP64 : -1;
 }
 
-void admit(fmddm_server *s, Slot &sl, int64_t id)
+int64_t request_footprint(const fmddm_server *s, const fmddm_request &r)
 {
-    Req &q = s->reqs[id];
-    const int64_t n = q.r.n;
-    sl.req = id;
-    sl.step = 0;
-    sl.charged = q.res.device_bytes = footprint(s->prm, s->base->m2l->rp, n);
-    s->used += sl.charged;
-    q.res.state = FMDDM_REQ_RUNNING;
-    q.res.t_admit = seconds_since(s->t0);
-    const double *g = q.geo.data();
+    return s->poro_set ? footprint(s->prm, s->base->m2l->rp, r.n, r.steps, s->poro.near_cache_bytes)
+                       : footprint(s->prm, s->base->m2l->rp, r.n);
+}
+
+// The set-up of an admitted request: tree, schedules and operators,
+// right-hand side, preconditioner and the start of its first solve.  It
+// runs on a host thread of its own (admit), on the slot's context and
+// stream only, while the engine keeps stepping the other slots; it waits
+// on nothing but its own stream.  r and g are copies / stable storage of
+// the request.
+void admit_work(fmddm_server *s, Slot &sl, const fmddm_request r, const double *g)
+{
+    FM_HIP(hipSetDevice(s->device));
+    fmddm::StreamScope scope(sl.stream);
+    const int64_t n = r.n;
     sl.t = new fmddm_tree();
     fmddm::build_tree(sl.ctx, sl.t, n, g, g + n, g + 2 * n, g + 3 * n, 0);
+    if (s->poro_set) {
+        // time march: the multipole form throughout (exact transient
+        // integration is far slower at every size); operators and near
+        // blocks of all its time levels built now
+        const int64_t n3 = 3 * n;
+        sl.mode = fmddm::APPLY_PORO;
+        fmddm::poro_prepare(sl.ctx, sl.t, r.steps);
+        if (sl.pf.n < (size_t)n) sl.pf.alloc(n);
+        if (sl.b.n < (size_t)n3) sl.b.alloc(n3);
+        if (sl.x.n < (size_t)n3) sl.x.alloc(n3);
+        if (sl.b0.n < (size_t)n3) sl.b0.alloc(n3);
+        if (sl.hist.n < (size_t)(n3 * r.steps)) sl.hist.alloc(n3 * r.steps);
+        FM_HIP(hipMemcpyAsync(sl.pf.p, g + 4 * n, n * 8, hipMemcpyHostToDevice, sl.stream));
+        FM_HIP(hipMemsetAsync(sl.x.p, 0, n3 * 8, sl.stream));
+        fmddm::poro_rhs(sl.ctx, sl.t, sl.pf.p, r.SH, r.Sh, sl.b0.p);
+        FM_HIP(hipMemcpyAsync(sl.b.p, sl.b0.p, n3 * 8, hipMemcpyDeviceToDevice, sl.stream));
+        sl.g.start(sl.ctx, sl.t, sl.mode, sl.b.p, sl.x.p, r.tol, s->prm.maxit);
+        return;
+    }
     // small requests: the exact product, one launch, beats the FMM's chain
     sl.mode = n <= s->prm.direct_below ? FMDDM_APPLY_DIRECT : FMDDM_APPLY_FMM;
     if (sl.mode == FMDDM_APPLY_FMM) fmddm::setup_fmm(sl.ctx, sl.t);
@@ -189,9 +253,37 @@ void admit(fmddm_server *s, Slot &sl, int64_t id)
     if (sl.x.n < (size_t)(2 * n)) sl.x.alloc(2 * n);
     FM_HIP(hipMemcpyAsync(sl.pf.p, g + 4 * n, n * 8, hipMemcpyHostToDevice, sl.stream));
     FM_HIP(hipMemsetAsync(sl.x.p, 0, 2 * n * 8, sl.stream));
-    fmddm::rhs_build(sl.ctx, sl.t, sl.pf.p, q.r.SH, q.r.Sh, sl.b.p, 1.0 / q.r.steps);
-    sl.g.start(sl.ctx, sl.t, sl.mode, sl.b.p, sl.x.p, q.r.tol, s->prm.maxit, residual_mode(s, sl));
-    sl.phase = 1;
+    fmddm::rhs_build(sl.ctx, sl.t, sl.pf.p, r.SH, r.Sh, sl.b.p, 1.0 / r.steps);
+    sl.g.start(sl.ctx, sl.t, sl.mode, sl.b.p, sl.x.p, r.tol, s->prm.maxit, residual_mode(s, sl));
+}
+
+// Admits request `id` into the free slot: charges its footprint and starts
+// its set-up on a host thread (phase 3); the engine moves the slot to
+// solving once the set-up has finished.
+void admit(fmddm_server *s, Slot &sl, int64_t id)
+{
+    Req &q = s->reqs[id];
+    sl.req = id;
+    sl.step = 0;
+    sl.charged = q.res.device_bytes = request_footprint(s, q.r);
+    s->used += sl.charged;
+    q.res.state = FMDDM_REQ_RUNNING;
+    q.res.t_admit = seconds_since(s->t0);
+    const fmddm_request r = q.r;
+    const double *g = q.geo.data();  // not modified while the request exists
+    Slot *ps = &sl;
+    sl.setup = std::async(std::launch::async, [s, ps, r, g] {
+        try {
+            admit_work(s, *ps, r, g);
+        } catch (const Error &) {
+            throw;
+        } catch (const std::bad_alloc &) {
+            throw Error{FMDDM_ENOMEM, "request set-up: host allocation failed"};
+        } catch (...) {
+            throw Error{FMDDM_EDEVICE, "request set-up failed"};
+        }
+    });
+    sl.phase = 3;
 }
 
 // Moves one slot forward if its last enqueued work has finished.
@@ -199,6 +291,12 @@ void advance(fmddm_server *s, Slot &sl)
 {
     Req &q = s->reqs[sl.req];
     const int64_t n = q.r.n;
+    if (sl.phase == 3) {
+        if (sl.setup.wait_for(std::chrono::seconds(0)) != std::future_status::ready) return;
+        sl.phase = 1;
+        sl.setup.get();  // the set-up's error, if any, fails the request
+        return;
+    }
     if (sl.phase == 1) {
         if (!sl.g.advance(false)) return;
         q.res.iters += sl.g.it;
@@ -208,13 +306,25 @@ void advance(fmddm_server *s, Slot &sl)
             return;
         }
         q.res.steps_done = ++sl.step;
-        if (sl.step < q.r.steps) {
+        const int64_t nv = (s->poro_set ? 3 : 2) * n;
+        if (s->poro_set) {
+            // D^h joins the history; the next step's right-hand side is b
+            // minus the history sum over D^1 .. D^h
+            FM_HIP(hipMemcpyAsync(sl.hist.p + (size_t)(sl.step - 1) * nv, sl.x.p, nv * 8, hipMemcpyDeviceToDevice,
+                                  sl.stream));
+            if (sl.step < q.r.steps) {
+                FM_HIP(hipMemcpyAsync(sl.b.p, sl.b0.p, nv * 8, hipMemcpyDeviceToDevice, sl.stream));
+                fmddm::poro_history(sl.ctx, sl.t, sl.step + 1, sl.hist.p, sl.b.p);
+                sl.g.start(sl.ctx, sl.t, sl.mode, sl.b.p, sl.x.p, q.r.tol, s->prm.maxit);
+                return;
+            }
+        } else if (sl.step < q.r.steps) {
             double scale = (double)(sl.step + 1) / q.r.steps;
             fmddm::rhs_build(sl.ctx, sl.t, sl.pf.p, q.r.SH, q.r.Sh, sl.b.p, scale);
             sl.g.start(sl.ctx, sl.t, sl.mode, sl.b.p, sl.x.p, q.r.tol, s->prm.maxit, residual_mode(s, sl));
             return;
         }
-        size_t need = (size_t)(2 * n) * 8;
+        size_t need = (size_t)nv * 8;
         if (sl.host_cap < need) {
             if (sl.hostD) FM_HIP(hipHostFree(sl.hostD));
             sl.hostD = nullptr;
@@ -230,7 +340,7 @@ void advance(fmddm_server *s, Slot &sl)
         hipError_t e = hipEventQuery(sl.ev);
         if (e == hipErrorNotReady) return;
         FM_HIP(e);
-        q.D.assign(sl.hostD, sl.hostD + 2 * n);
+        q.D.assign(sl.hostD, sl.hostD + (s->poro_set ? 3 : 2) * n);
         q.res.state = FMDDM_REQ_DONE;
         q.res.status = FMDDM_OK;
         q.res.t_done = seconds_since(s->t0);
@@ -276,11 +386,17 @@ fmddm_status fmddm_server_create(const fmddm_params *p, int max_slots, int64_t h
         fmddm_status cs = fmddm_create(p, s->base_stream, &b);
         if (cs != FMDDM_OK) throw Error{cs, "server: invalid parameters"};
         s->base = b;
+        fmddm::StreamScope scope(s->base_stream);
         fmddm::build_m2l_ops(b);
+        // the slots share the operator set and set up on host threads of
+        // their own: its reduced-precision copy is made here, not on use
+        if (p->precision != FMDDM_PREC_FP64) fmddm::lowp_ops(b, p->precision);
         if (hbm_budget == 0) {
+            // free device memory, counting the blocks the library's cache
+            // holds for reuse (earlier servers' requests leave them there)
             size_t fr = 0, tot = 0;
             FM_HIP(hipMemGetInfo(&fr, &tot));
-            hbm_budget = (int64_t)(0.9 * (double)fr);
+            hbm_budget = (int64_t)(0.9 * (double)(fr + fmddm::dev_bytes(true)));
         }
         s->budget = hbm_budget;
         s->slots.resize(max_slots);
@@ -299,6 +415,31 @@ fmddm_status fmddm_server_create(const fmddm_params *p, int max_slots, int64_t h
     return FMDDM_OK;
 }
 
+fmddm_status fmddm_server_set_poro(fmddm_server *s, const fmddm_poro_params *pp)
+{
+    if (!s || !pp) return FMDDM_EINVAL;
+    return sguard(s, [&] {
+        if (!s->queue.empty()) throw Error{FMDDM_EINVAL, "server_set_poro: requests are queued"};
+        for (Slot &sl : s->slots)
+            if (sl.req) throw Error{FMDDM_EINVAL, "server_set_poro: requests are running"};
+        if (pp->mode != FMDDM_APPLY_FMM) throw Error{FMDDM_EUNSUPPORTED, "server_set_poro: mode must be FMM"};
+        fmddm_poro_params q = *pp;
+        if (q.near_cache_bytes == 0) {
+            // stored near blocks: a share of the budget per slot
+            q.near_cache_bytes = std::max<int64_t>(1, s->budget / (4 * (int64_t)s->slots.size()));
+        }
+        fmddm_status st = fmddm_poro_set(s->base, &q);
+        if (st != FMDDM_OK) throw Error{st, std::string("server_set_poro: ") + fmddm_last_error(s->base)};
+        for (Slot &sl : s->slots) {
+            st = fmddm_poro_set(sl.ctx, &q);
+            if (st != FMDDM_OK) throw Error{st, std::string("server_set_poro: ") + fmddm_last_error(sl.ctx)};
+        }
+        s->poro = q;
+        s->poro_set = 1;
+        return FMDDM_OK;
+    });
+}
+
 void fmddm_server_destroy(fmddm_server *s) { delete s; }
 
 const char *fmddm_server_last_error(const fmddm_server *s) { return s ? s->err.c_str() : "null server"; }
@@ -306,7 +447,9 @@ const char *fmddm_server_last_error(const fmddm_server *s) { return s ? s->err.c
 int64_t fmddm_server_footprint(const fmddm_server *s, int64_t n)
 {
     if (!s || n <= 0) return 0;
-    return footprint(s->prm, s->base->m2l->rp, n);
+    // poroelastic servers: a march of the longest length requests use here
+    return s->poro_set ? footprint(s->prm, s->base->m2l->rp, n, 10, s->poro.near_cache_bytes)
+                       : footprint(s->prm, s->base->m2l->rp, n);
 }
 
 fmddm_status fmddm_server_submit(fmddm_server *s, const fmddm_request *r, int64_t *ticket)
@@ -339,6 +482,7 @@ fmddm_status fmddm_server_step(fmddm_server *s, int *active, int *queued)
     return sguard(s, [&] {
         for (Slot &sl : s->slots) {
             if (!sl.req) continue;
+            fmddm::StreamScope scope(sl.stream);
             try {
                 advance(s, sl);
             } catch (const Error &e) {
@@ -357,7 +501,7 @@ fmddm_status fmddm_server_step(fmddm_server *s, int *active, int *queued)
             if (!free_slot) break;
             int64_t id = s->queue.front();
             Req &q = s->reqs[id];
-            int64_t est = footprint(s->prm, s->base->m2l->rp, q.r.n);
+            int64_t est = request_footprint(s, q.r);
             if (est > s->budget) {
                 s->queue.pop_front();
                 q.res.state = FMDDM_REQ_FAILED;
@@ -367,6 +511,7 @@ fmddm_status fmddm_server_step(fmddm_server *s, int *active, int *queued)
             }
             if (s->used + est > s->budget && busy > 0) break;
             s->queue.pop_front();
+            fmddm::StreamScope scope(free_slot->stream);
             try {
                 admit(s, *free_slot, id);
             } catch (const Error &e) {

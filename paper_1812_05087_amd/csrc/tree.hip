@@ -726,6 +726,18 @@ void build_tree(fmddm_ctx *ctx, fmddm_tree *t, int64_t n64, const double *x1, co
         up(t->nbeg, nbeg);
         up(t->npre, npre);
         up(t->ntot, ntot);
+        // the same near sources as one flat list of points per leaf (the
+        // elastic near-field kernel indexes it directly)
+        {
+            std::vector<int> nfoff(t->nleaf + 1, 0), nflat;
+            for (int i = 0; i < t->nleaf; ++i) nfoff[i + 1] = nfoff[i] + ntot[i];
+            nflat.reserve(nfoff[t->nleaf]);
+            for (int i = 0; i < t->nleaf; ++i)
+                for (int k = hnoff[i]; k < hnoff[i + 1]; ++k)
+                    for (int j = hb[hn[k]]; j < he[hn[k]]; ++j) nflat.push_back(j);
+            up(t->nfoff, nfoff);
+            up(t->nflat, nflat);
+        }
         up(t->aoff, aoff);
         up(t->aidx, aidx);
         // near-field work items and the leaf of every point
