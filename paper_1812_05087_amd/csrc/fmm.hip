@@ -834,6 +834,7 @@ __global__ __launch_bounds__(NT) void k_p2p(
     __shared__ double s_cx[NEAR_CHUNK], s_cy[NEAR_CHUNK];
     __shared__ RT s_cb[NEAR_CHUNK], s_sb[NEAR_CHUNK], s_c2[NEAR_CHUNK], s_s2[NEAR_CHUNK], s_a[NEAR_CHUNK],
         s_ds[NEAR_CHUNK], s_dn[NEAR_CHUNK];
+    __shared__ double s_red[3 * NT];
     int k = xcd_remap(blockIdx.x, nitem);
     int li = it_leaf[k], s0 = it_s0[k], s1 = it_s1[k];
     int c = leaves[li];
@@ -850,14 +851,17 @@ __global__ __launch_bounds__(NT) void k_p2p(
         s_a[q] = (RT)a[j]; s_ds[q] = (RT)Ds[2 * j]; s_dn[q] = (RT)Ds[2 * j + 1];
     }
     __syncthreads();
-    int cnt = s1 - s0;
-    int tpt = 1;
-    while (tpt < 16 && tpt * 2 * nt <= NT) tpt *= 2;
-    int tpg = NT / tpt, sub = tid & (tpt - 1);
+    const int cnt = s1 - s0;
+    // tpt lanes per target point, tpt = NT / nt (at most 16): with leaves of
+    // 33-63 points a power of two would idle up to half the lanes.  Lane
+    // (g, sub) takes sources sub, sub + tpt, ...; the tpt partials of a
+    // point are summed in LDS in lane order.
+    const int tpt = nt >= NT ? 1 : min(16, NT / nt);
+    const int tpg = NT / tpt, g = tid / tpt, sub = tid - g * tpt;
     double *pk = part + 3 * (size_t)it_poff[k];
     for (int t0 = tb; t0 < te; t0 += tpg) {
-        int i = t0 + tid / tpt;
-        bool act = i < te;
+        const int i = t0 + g;
+        const bool act = g < tpg && i < te;
         double X = act ? cx[i] : 0.0, Y = act ? cy[i] : 0.0;
         RT sxx = 0, syy = 0, sxy = 0;
         if (act) {
@@ -869,23 +873,38 @@ __global__ __launch_bounds__(NT) void k_p2p(
                 syy *= -gc;
                 sxy *= -gc;
             } else {
-                float g = (float)gc;
+                float gf = (float)gc;
                 for (int q = sub; q < cnt; q += tpt)
                     elem_stress_add32((float)(X - s_cx[q]), (float)(Y - s_cy[q]), s_cb[q], s_sb[q], s_a[q],
-                                      s_ds[q], s_dn[q], g, sxx, syy, sxy);
+                                      s_ds[q], s_dn[q], gf, sxx, syy, sxy);
             }
         }
-        for (int w = 1; w < tpt; w <<= 1) {
-            sxx += __shfl_xor(sxx, w);
-            syy += __shfl_xor(syy, w);
-            sxy += __shfl_xor(sxy, w);
+        if (tpt == 1) {
+            if (act) {
+                double *o = pk + 3 * (size_t)(i - tb);
+                o[0] = sxx;
+                o[1] = syy;
+                o[2] = sxy;
+            }
+            continue;
         }
+        s_red[tid] = sxx;
+        s_red[NT + tid] = syy;
+        s_red[2 * NT + tid] = sxy;
+        __syncthreads();
         if (act && sub == 0) {
+            double r0 = 0.0, r1 = 0.0, r2 = 0.0;
+            for (int u = tid; u < tid + tpt; ++u) {
+                r0 += s_red[u];
+                r1 += s_red[NT + u];
+                r2 += s_red[2 * NT + u];
+            }
             double *o = pk + 3 * (size_t)(i - tb);
-            o[0] = sxx;
-            o[1] = syy;
-            o[2] = sxy;
+            o[0] = r0;
+            o[1] = r1;
+            o[2] = r2;
         }
+        __syncthreads();
     }
 }
 

@@ -16,9 +16,12 @@ Bars (max norm, relative to the largest entry of the compared outputs):
     i.e. 2 u rho relative to y with rho = sum |a_k x_k| / |y| the sum's
     cancellation; three such products are chained (projection, translation,
     expansion).  FP32 (u = 2^-24): 1e-5 leaves rho ~ 30 per product.  BF16
-    (u = 2^-9): 2^-8 per product; 3e-2 allows rho ~ 2.5 on each of the
-    three (measured 6e-3 SVD, 4e-3 uncompressed).  A wrong lane layout or a
-    dropped pass gives O(1).
+    (8 significand bits, u = 2^-8, both operands rounded: 2u = 7.8e-3 per
+    product at rho = 1, 2.3e-2 for the three in the worst case).  Rounding
+    errors of many terms add like a random walk, far below that bound:
+    measured 6.4e-3 (SVD) and 3.9e-3 (uncompressed), and the kernels are
+    deterministic, so the bar 1.2e-2 (2x the larger) holds them with room
+    for other inputs.  A wrong lane layout or a dropped pass gives O(1).
   - Iterative refinement stops on the FP64 FMM residual <= tol; the
     solutions then agree with the FP64 solve to about cond(A) * tol
     (bar 1e-7 at tol 1e-8; measured 3e-9) and with the oracle's LU solve to
@@ -42,7 +45,7 @@ import paper_1812_05087_amd as F  # noqa: E402
 
 PRECS = {"fp32": F.FMDDM_PREC_FP32, "bf16": F.FMDDM_PREC_BF16}
 NEAR_BAR = 2e-6                          # FP32 near field, whole product
-FAR_BAR = {"fp32": 1e-5, "bf16": 3e-2}   # far field alone
+FAR_BAR = {"fp32": 1e-5, "bf16": 1.2e-2}  # far field alone
 
 
 def rel(a, b):
