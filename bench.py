@@ -136,11 +136,24 @@ SERVE_PARAMS = dict(p=10, leaf=32, m2l=1, m2l_tol=1e-10, restart=50, maxit=20000
                     coarse_aggregates=128)
 
 
-def serve_run(F, wls, reqs, slots, arrivals, precond=2, precision=0):
+# the poroelastic medium of the horizontal-well example (Section 5.2.1,
+# Table 2; drained E, nu of the well example), 60 s steps
+SERVE_PORO = dict(E=20e9, nu=0.2, nu_u=0.35, alpha=0.8, perm=1e-18, visc=1e-3, dt=60.0, p0=48.26e6)
+
+
+FAILED = {}  # request index -> status of the last serve_run's failed requests
+
+
+def serve_run(F, wls, reqs, slots, arrivals, precond=2, precision=0, poro=False, failed=FAILED):
     """Serve the requests with `slots` admission slots; request i is
-    submitted at arrivals[i] seconds.  Returns (makespan s, latencies s)."""
-    prm = F.fmddm_default_params(**SERVE_PARAMS, precond=precond, precision=precision)
+    submitted at arrivals[i] seconds.  Returns (makespan s, latencies s).
+    poro: requests are poroelastic time marches (steps of 60 s)."""
+    extra = dict(E=SERVE_PORO["E"], nu=SERVE_PORO["nu"]) if poro else {}
+    prm = F.fmddm_default_params(**SERVE_PARAMS, **extra, precond=precond, precision=precision)
     srv = F.fmddm_server_create(prm, slots)
+    if poro:
+        m = SERVE_PORO
+        F.fmddm_server_set_poro(srv, m["nu_u"], m["alpha"], m["perm"], m["visc"], m["dt"], m["p0"])
     try:
         warm = F.fmddm_server_submit(srv, wls[0].x1, wls[0].y1, wls[0].x2, wls[0].y2, wls[0].pressure,
                                      wls[0].SH, wls[0].Sh, 1, 1e-6)
@@ -148,6 +161,7 @@ def serve_run(F, wls, reqs, slots, arrivals, precond=2, precision=0):
             F.fmddm_server_step(srv)
         order = sorted(range(len(reqs)), key=lambda i: arrivals[i])
         tickets, pend, done = {}, 0, {}
+        failed.clear()
         t0 = time.perf_counter()
         while len(done) < len(reqs):
             now = time.perf_counter() - t0
@@ -165,7 +179,9 @@ def serve_run(F, wls, reqs, slots, arrivals, precond=2, precision=0):
                     r = F.fmddm_server_poll(srv, t)[0]
                     if r["state"] >= F.FMDDM_REQ_DONE:
                         if r["state"] != F.FMDDM_REQ_DONE:
-                            raise RuntimeError(f"request {i} failed: status {r['status']}")
+                            failed[i] = r["status"]
+                            print(f"serving: request {i} (N={wls[i].n}, {reqs[i].steps} steps) failed, "
+                                  f"status {r['status']}", file=sys.stderr, flush=True)
                         done[i] = r
         t_first = min(r["t_submit"] for r in done.values())
         span = max(r["t_done"] for r in done.values()) - t_first
@@ -176,34 +192,44 @@ def serve_run(F, wls, reqs, slots, arrivals, precond=2, precision=0):
         F.fmddm_server_destroy(srv)
 
 
-def serving_leg(F, W, count, slots, load):
-    """Serving of the seed-5 request stream (N log-uniform in [1e3, 5e4],
-    1-10 load steps, tol 1e-6): the one-at-a-time service rate, the batched
-    saturation rate, and a Poisson stream at `load` x the one-at-a-time rate
-    served batched and one at a time; GMRES with the two-level
-    preconditioner (block-Jacobi plus a 128-aggregate coarse level), and
-    the batched saturation rates with block-Jacobi alone and without
-    preconditioning (the paper's plain GMRES) for comparison."""
+def serving_leg(F, W, count, slots, load, poro=True, alone_sample=128):
+    """Serving of the seed-5 request stream (random fractures at C2's
+    density, N log-uniform in [1e3, 5e4], 1-10 steps, tol 1e-6), GMRES with
+    the two-level preconditioner (block-Jacobi plus a 128-aggregate coarse
+    level).  poro: every request is a poroelastic time march of its steps
+    (60 s each, the well example's medium) with the history sum; else
+    elastic load steps (a pressure ramp).  Measured: the one-at-a-time
+    service rate (on the first `alone_sample` requests), the batched
+    saturation rate (all `count` arriving at once), and a Poisson stream at
+    `load` x the batched saturation rate served batched and one at a time
+    (solves/s, p50/p99 latency).  At most 100 elastic requests, also the
+    batched saturation rates with block-Jacobi alone, without
+    preconditioning (the paper's plain GMRES) and with FP32 products."""
     reqs = W.serving_stream(5, count)
     wls = [r.workload() for r in reqs]
     zero = [0.0] * count
-    def note(what, span):
-        print(f"serving: {what} done, {count / span:.1f} solves/s", file=sys.stderr, flush=True)
+    def note(what, k, span):
+        print(f"serving: {what} done, {k / span:.1f} solves/s", file=sys.stderr, flush=True)
 
-    span1, _, iters = serve_run(F, wls, reqs, 1, zero)
-    note("one at a time", span1)
-    rate1 = count / span1
-    spanb, _, _ = serve_run(F, wls, reqs, slots, zero)
-    note("batched", spanb)
-    lam = load * rate1
+    k1 = min(alone_sample, count)
+    span1, _, _ = serve_run(F, wls[:k1], reqs[:k1], 1, zero[:k1], poro=poro)
+    note("one at a time", k1, span1)
+    rate1 = k1 / span1
+    spanb, _, iters = serve_run(F, wls, reqs, slots, zero, poro=poro)
+    failures = {"batched": dict(FAILED)}
+    note("batched", count, spanb)
+    rateb = count / spanb
+    lam = load * rateb
     arr = [r.arrival_units / lam for r in reqs]
-    spans, lat, _ = serve_run(F, wls, reqs, slots, arr)
-    note("Poisson batched", spans)
-    span_o, lat_o, _ = serve_run(F, wls, reqs, 1, arr)
-    note("Poisson one at a time", span_o)
+    spans, lat, _ = serve_run(F, wls, reqs, slots, arr, poro=poro)
+    failures["poisson_batched"] = dict(FAILED)
+    note("Poisson batched", count, spans)
+    span_o, lat_o, _ = serve_run(F, wls, reqs, 1, arr, poro=poro)
+    failures["poisson_one_at_a_time"] = dict(FAILED)
+    note("Poisson one at a time", count, span_o)
     pct = lambda a, q: float(np.percentile(a, q))
     comp = {}
-    if count <= 100:  # the comparison runs (plain GMRES is ~7x slower)
+    if count <= 100 and not poro:  # the comparison runs (plain GMRES is ~7x slower)
         span_np, _, iters_np = serve_run(F, wls, reqs, slots, zero, precond=0)
         span_32, _, iters_32 = serve_run(F, wls, reqs, slots, zero, precision=F.FMDDM_PREC_FP32)
         span_bj, _, iters_bj = serve_run(F, wls, reqs, slots, zero, precond=F.FMDDM_PRECOND_BLOCK)
@@ -220,18 +246,22 @@ def serving_leg(F, W, count, slots, load):
         "gmres_products_total": iters,
         "params": {"p": SERVE_PARAMS["p"], "leaf": SERVE_PARAMS["leaf"], "m2l": "svd 1e-10", "tol": 1e-6,
                    "restart": SERVE_PARAMS["restart"],
-                   "precond": "two-level: block-Jacobi (32-element groups) + coarse level of "
+                   "precond": f"two-level: block-Jacobi ({21 if poro else 32}-element groups) + coarse level of "
                               f"{SERVE_PARAMS['coarse_aggregates']} aggregates",
                    "graphs": bool(SERVE_PARAMS["use_graphs"]),
-                   "exact_product_at_or_below_elements": SERVE_PARAMS["direct_below"]},
+                   "exact_product_at_or_below_elements": None if poro else SERVE_PARAMS["direct_below"]},
         **comp,
-        "one_at_a_time_solves_per_s": rate1,
-        "batched_saturated_solves_per_s": count / spanb,
-        "poisson_rate_per_s": lam,
+        "one_at_a_time_solves_per_s": rate1, "one_at_a_time_sample": k1,
+        "batched_saturated_solves_per_s": rateb,
+        "poisson_rate_per_s": lam, "poisson_load": f"{load} x the batched saturation rate",
         "served": {"solves_per_s": count / spans, "p50_s": pct(lat, 50), "p99_s": pct(lat, 99)},
         "one_at_a_time_same_stream": {"solves_per_s": count / span_o, "p50_s": pct(lat_o, 50),
                                       "p99_s": pct(lat_o, 99)},
-        "note": "elastic quasi-static load steps (pressure ramp); the first requests of the seed-5 stream",
+        "failed_requests": {k: {str(i): st for i, st in v.items()} for k, v in failures.items()},
+        "kind": ("poroelastic time marches (60 s steps, history sum, FMM on product and history; "
+                 "medium of the well example: E 20 GPa, nu 0.2, nu_u 0.35, alpha 0.8, k 1e-18 m^2, "
+                 "mu 1e-3 Pa s, p0 48.26 MPa)" if poro else "elastic quasi-static load steps (pressure ramp)"),
+        "note": f"the first {count} requests of the seed-5 stream",
     }
 
 
@@ -274,7 +304,7 @@ def history_run(F, W, elems, steps, mode, p, near_cache=0):
         prob.close()
 
 
-def history_leg(F, W, elems, steps, p=10):
+def history_leg(F, W, elems, steps, p=16):
     """Poroelastic time marching (the left-hand-side product and the history
     sum over earlier steps): multipole form at the full well-cluster size,
     and multipole against exact evaluation at a tenth of it."""
@@ -430,7 +460,7 @@ def precision_leg(F, W, steps, tune, leaf, p, solve_tol=1e-8, target_err=1e-6, s
     return out
 
 
-def march_run(F, W, elems, steps, p, restart, precond, coarse, tol, keep=()):
+def march_run(F, W, elems, steps, p, restart, precond, coarse, tol, keep=(), mode=None):
     """One poroelastic time march (the horizontal-well example's shape,
     Section 5.2.1): 5 fractures of `elems` 0.2 m elements 10 m apart,
     `steps` steps of 60 s, every step's history sum and GMRES solve (the
@@ -443,13 +473,22 @@ def march_run(F, W, elems, steps, p, restart, precond, coarse, tol, keep=()):
     n3 = 3 * wl.n
     prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=20e9, nu=0.2, p=p, leaf=32, m2l=1, m2l_tol=1e-10, tol=tol,
                      restart=restart, maxit=40000, precond=precond, coarse_aggregates=coarse)
-    F.fmddm_poro_set(prob.ctx, 0.35, 0.8, 1e-18, 1e-3, 60.0, 48.26e6, mode=F.FMDDM_APPLY_FMM)
+    F.fmddm_poro_set(prob.ctx, 0.35, 0.8, 1e-18, 1e-3, 60.0, 48.26e6,
+                     mode=F.FMDDM_APPLY_FMM if mode is None else mode)
     b0 = torch.zeros(n3, dtype=torch.float64, device="cuda")
     F.fmddm_poro_rhs(prob.ctx, prob.tree, torch.as_tensor(wl.pressure).cuda(), wl.SH, wl.Sh, b0)
     hist = torch.zeros(steps * n3, dtype=torch.float64, device="cuda")
     D = torch.zeros(n3, dtype=torch.float64, device="cuda")
+    t_setup = 0.0
+    if mode == F.FMDDM_APPLY_DENSE:  # assemble the dense left-hand side outside the timed march
+        tmp = torch.zeros(n3, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F.fmddm_poro_apply(prob.ctx, prob.tree, 0, D, tmp)
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t0
     th = tsv = 0.0
-    its, worst, per_step, kept = 0, 0.0, [], {}
+    its, worst, per_step, kept, step_s = 0, 0.0, [], {}, []
     torch.cuda.synchronize()
     t_all = time.perf_counter()
     for h in range(1, steps + 1):
@@ -468,6 +507,7 @@ def march_run(F, W, elems, steps, p, restart, precond, coarse, tol, keep=()):
         tsv += t2 - t1
         its += info["iters"]
         per_step.append(info["iters"])
+        step_s.append(t2 - t0)
         worst = max(worst, info["relres"])
         if h in keep:
             kept[h] = D.cpu().numpy().reshape(-1, 3).copy()
@@ -478,7 +518,7 @@ def march_run(F, W, elems, steps, p, restart, precond, coarse, tol, keep=()):
     Dm = D.cpu().numpy().reshape(-1, 3)
     prob.close()
     return {"total_s": total, "history_s": th, "solve_s": tsv, "gmres_products": its, "per_step": per_step,
-            "max_step_relres": worst, "last": Dm, "kept": kept, "n": wl.n}
+            "max_step_relres": worst, "last": Dm, "kept": kept, "n": wl.n, "setup_s": t_setup, "step_s": step_s}
 
 
 def middle_ratio(Dm, elems):
@@ -488,13 +528,17 @@ def middle_ratio(Dm, elems):
     return float(np.abs(mid[:, 0]).max() / np.abs(Dm[:, 1]).max())
 
 
-def march_leg(F, W, elems, steps, p=10, restart=100, precond=2, coarse=0, ref_tol=1e-10):
-    """The full C3 march at GMRES tol 1e-6 (the paper's), timed, and the
-    same march at ref_tol as the reference its accuracy is measured
-    against: per component (D_s, D_n, D_q) the largest difference over the
-    largest reference value, after steps 1, 10 and the last; and the middle
-    fracture's shear over the opening for both."""
-    keep = tuple(sorted({1, min(10, steps), steps}))
+def march_leg(F, W, elems, steps, p=16, restart=100, precond=2, coarse=0, ref_tol=1e-10, ref_steps=10, low_p=10):
+    """The full C3 march at GMRES tol 1e-6 (the paper's), timed, and its
+    accuracy: the first ref_steps steps again at ref_tol (the solver's
+    error at this tolerance), and the same steps with p = low_p against
+    that reference (the interpolation error of a lower order: on the long
+    parallel fractures the solution amplifies the operator's error on
+    smooth DDs, 1.1e-5 at p = 10 against 7e-9 at p = 16).  Per unknown
+    kind (D_s, D_n, D_q): the largest difference over the largest
+    reference value; and the middle fracture's shear over the opening,
+    zero by symmetry (Section 5.2.1)."""
+    keep = tuple(sorted({1, min(ref_steps, steps), steps}))
     run = march_run(F, W, elems, steps, p, restart, precond, coarse, 1e-6, keep)
     out = {"workload": f"well cluster 5 x {elems} elements (N={run['n']}), {steps} steps of 60 s", "p": p,
            "restart": restart, "precond": {1: "block-Jacobi", 2: "two-level"}[precond], "tol": 1e-6,
@@ -502,18 +546,40 @@ def march_leg(F, W, elems, steps, p=10, restart=100, precond=2, coarse=0, ref_to
            "solve_s": run["solve_s"], "gmres_products": run["gmres_products"],
            "max_step_relres": run["max_step_relres"],
            "middle_fracture_max_shear_over_opening": middle_ratio(run["last"], elems)}
-    if ref_tol:
-        ref = march_run(F, W, elems, steps, p, restart, precond, coarse, ref_tol, keep)
-        acc = {}
-        for h in keep:
-            a, r = run["kept"][h], ref["kept"][h]
-            acc[f"step_{h}"] = {name: float(np.abs(a[:, k] - r[:, k]).max() / np.abs(r[:, k]).max())
-                                for k, name in enumerate(("D_s", "D_n", "D_q"))}
+
+    def diff(a, r):
+        return {name: float(np.abs(a[:, k] - r[:, k]).max() / np.abs(r[:, k]).max())
+                for k, name in enumerate(("D_s", "D_n", "D_q"))}
+
+    if ref_tol and ref_steps:
+        rs = min(ref_steps, steps)
+        k2 = tuple(sorted({1, rs}))
+        ref = march_run(F, W, elems, rs, p, restart, precond, coarse, ref_tol, k2)
+        acc = {f"step_{h}": diff(run["kept"][h], ref["kept"][h]) for h in k2}
         out["accuracy_vs_reference"] = {
-            "reference_tol": ref_tol, "reference_total_s": ref["total_s"],
-            "reference_gmres_products": ref["gmres_products"],
+            "reference": f"the same march (p = {p}) at GMRES tol {ref_tol:g}, {rs} steps",
+            "reference_total_s": ref["total_s"], "reference_gmres_products": ref["gmres_products"],
             "max_diff_over_max_ref": acc,
-            "reference_middle_fracture_max_shear_over_opening": middle_ratio(ref["last"], elems)}
+            f"middle_fracture_max_shear_over_opening_step_{rs}": middle_ratio(run["kept"][rs], elems),
+            f"reference_middle_fracture_max_shear_over_opening_step_{rs}": middle_ratio(ref["kept"][rs], elems)}
+        # the history-only variant (Section 2: the earlier method applied
+        # the FMM to the history sum only): dense exact left-hand side,
+        # multipole history, same steps and tolerance
+        ho = march_run(F, W, elems, rs, p, restart, precond, coarse, 1e-6, k2, mode=F.FMDDM_APPLY_DENSE)
+        fmm_first = sum(run["per_step"][:rs])
+        out["history_only"] = {
+            "steps": rs, "dense_lhs_assembly_s": ho["setup_s"], "total_s": ho["total_s"],
+            "history_s": ho["history_s"], "solve_s": ho["solve_s"], "gmres_products": ho["gmres_products"],
+            "fmm_on_both_first_steps": {"gmres_products": fmm_first, "seconds": float(sum(run["step_s"][:rs]))},
+            "max_diff_over_max_ref": {f"step_{h}": diff(ho["kept"][h], ref["kept"][h]) for h in k2},
+            "note": "left-hand side F(dt) a stored dense 3N x 3N matrix of exact element integrals "
+                    "(FMDDM_APPLY_DENSE), history sum by FMM; the reference is the FMM-on-both march"}
+        if low_p:
+            low = march_run(F, W, elems, rs, low_p, restart, precond, coarse, 1e-6, k2)
+            out["lower_order"] = {
+                "p": low_p, "total_s": low["total_s"], "gmres_products": low["gmres_products"],
+                "max_diff_over_max_ref": {f"step_{h}": diff(low["kept"][h], ref["kept"][h]) for h in k2},
+                f"middle_fracture_max_shear_over_opening_step_{rs}": middle_ratio(low["kept"][rs], elems)}
     return out
 
 
@@ -560,6 +626,47 @@ def p_sweep_leg(F, W, ps, reps=50):
         _, tl, _, _, _, _ = history_run(F, W, 4000, 2, F.FMDDM_APPLY_FMM, p)
         out["c3_lhs"].append({"p": p, "lhs_ms_N20000": tl * 1e3, "rel_err_vs_exact_N2000": rel(o_f, o_e)})
     return out
+
+
+def n_sweep_leg(F, W, ns, reps=5):
+    """Time per product against N (the shape of the paper's one-step timing
+    figures, Section 5.1: the conventional method grows as N^2, the
+    multipole one as N): random fractures at C2's density (100 elements
+    each, box scaled with sqrt(N)), the exact on-the-fly product and the
+    FMM product (leaf 32, p = 20, SVD M2L at 1e-12) on the GPU, with the
+    log-log slopes fitted over the sizes."""
+    import torch
+
+    def timed(apply, k):
+        apply()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            apply()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / k * 1e3
+
+    rows = []
+    for n in ns:
+        nf = max(1, n // 100)
+        wl = W.random_fractures(100 + nf, nf, 100, box=100.0 * np.sqrt(nf / 200.0))
+        prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=wl.E, nu=wl.nu, leaf=32, p=20, m2l=F.FMDDM_M2L_SVD,
+                         m2l_tol=1e-12)
+        try:
+            D = prob.vec(W.random_vector(5, wl.n))
+            o = prob.vec()
+            fmm = timed(lambda: prob.apply(D, F.FMDDM_APPLY_FMM, o), max(reps, 20))
+            direct = timed(lambda: prob.apply(D, F.FMDDM_APPLY_DIRECT, o), reps if wl.n <= 50000 else 2)
+            rows.append({"N": wl.n, "fmm_ms": fmm, "direct_ms": direct})
+            print(f"n-sweep: N={wl.n} fmm {fmm:.3f} ms direct {direct:.3f} ms", file=sys.stderr, flush=True)
+        finally:
+            prob.close()
+    x = np.log([r["N"] for r in rows])
+    big = x >= np.log(5000)  # the asymptotic range: below it both are launch-latency bound
+    slope = lambda key: float(np.polyfit(x[big], np.log([r[key] for r in rows])[big], 1)[0])
+    return {"workload": "random fractures at C2's density, 100 elements each", "rows": rows,
+            "slope_fmm": slope("fmm_ms"), "slope_direct": slope("direct_ms"),
+            "fit_range": "N >= 5000"}
 
 
 def cpu_model():
@@ -705,7 +812,8 @@ def main():
                     help="products timed per mode on the Griffith crack, C1 (0 skips the leg)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=48)
+    ap.add_argument("--serve-requests", type=int, default=1024)
+    ap.add_argument("--serve-kind", choices=["poro", "elastic"], default="poro")
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-load", type=float, default=0.75)
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -717,10 +825,13 @@ def main():
                     help="poroelastic time steps of the full-march leg (0 skips it)")
     ap.add_argument("--march-restart", type=int, default=100)
     ap.add_argument("--march-precond", type=int, default=2, choices=[1, 2])
+    ap.add_argument("--march-p", type=int, default=16)
     ap.add_argument("--march-ref-tol", type=float, default=1e-10,
                     help="GMRES tol of the reference march the C3 accuracy is measured against (0: none)")
-    ap.add_argument("--p-sweep", type=str, default="",
-                    help="comma-separated Chebyshev orders for the accuracy/time sweep (off by default)")
+    ap.add_argument("--p-sweep", type=str, default="3,6,10,16,20",
+                    help="comma-separated Chebyshev orders for the accuracy/time sweep ('' skips it)")
+    ap.add_argument("--n-sweep", type=str, default="1000,2000,5000,10000,20000,50000,100000,200000",
+                    help="comma-separated element counts for the time-per-product sweep ('' skips it)")
     ap.add_argument("--precision-steps", type=int, default=20,
                     help="products timed per precision at N=200000 (0 skips the mixed-precision leg)")
     ap.add_argument("--precision-no-tune", action="store_true")
@@ -887,14 +998,17 @@ def main():
     if args.c1_reps > 0:
         line["c1"] = c1_leg(F, W, args.c1_reps, cpu=not args.no_cpu_baseline)
     if args.serve_requests > 0:
-        line["serving"] = serving_leg(F, W, args.serve_requests, args.serve_slots, args.serve_load)
+        line["serving"] = serving_leg(F, W, args.serve_requests, args.serve_slots, args.serve_load,
+                                      poro=args.serve_kind == "poro")
     if args.history_elems > 0:
         line["history"] = history_leg(F, W, args.history_elems, args.history_steps)
     if args.p_sweep:
         line["p_sweep"] = p_sweep_leg(F, W, [int(q) for q in args.p_sweep.split(",")])
+    if args.n_sweep:
+        line["n_sweep"] = n_sweep_leg(F, W, [int(q) for q in args.n_sweep.split(",")])
     if args.march_steps > 0:
-        line["march"] = march_leg(F, W, args.march_elems, args.march_steps, restart=args.march_restart,
-                                  precond=args.march_precond, ref_tol=args.march_ref_tol)
+        line["march"] = march_leg(F, W, args.march_elems, args.march_steps, p=args.march_p,
+                                  restart=args.march_restart, precond=args.march_precond, ref_tol=args.march_ref_tol)
     if args.precision_steps > 0:
         line["mixed_precision"] = precision_leg(F, W, args.precision_steps, not args.precision_no_tune,
                                                 args.precision_leaf, args.precision_p,
