@@ -153,6 +153,8 @@ typedef struct {
     int64_t device_bytes;     /* device memory held by the tree */
     int64_t m2m_launches;     /* launches of the upward pass per product (0 before the first product) */
     int32_t m2m_cut;          /* level below which each subtree's upward pass runs in one block */
+    int32_t poro_m2l_rank;    /* poroelastic left-hand side with m2l = SVD: the largest rank kept
+                                 over the tree levels (0: uncompressed or not built yet) */
 } fmddm_tree_info;
 
 typedef struct {
@@ -396,6 +398,14 @@ typedef struct {
                                  96 bytes per near pair), and is then one multipole pass.  0: a
                                  quarter of the free device memory at first use, at most 32 GiB;
                                  > 0: that many bytes; < 0: no cache. */
+    int32_t m2l;              /* FMDDM_APPLY_FMM left-hand side (the product GMRES applies):
+                                 FMDDM_M2L_DENSE (0): the (4p^2)^2 operator per (tree level,
+                                 offset) of eq. 3.8; FMDDM_M2L_SVD (1): those operators
+                                 compressed per tree level (shared bases from a truncated SVD
+                                 at the context's m2l_tol; rebuilt with the operators), used
+                                 when the stored near field holds the left-hand side.  A
+                                 one-time cost per tree (an SVD of every level's operators)
+                                 that pays over many products. */
 } fmddm_poro_params;
 
 /* Attaches the poroelastic medium to the context (validated: EINVAL). */

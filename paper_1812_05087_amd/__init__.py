@@ -70,6 +70,7 @@ class TreeInfo(C.Structure):
         ("m2l_rank", C.c_int64),
         ("root_x0", C.c_double), ("root_y0", C.c_double), ("root_L", C.c_double),
         ("device_bytes", C.c_int64), ("m2m_launches", C.c_int64), ("m2m_cut", C.c_int32),
+        ("poro_m2l_rank", C.c_int32),
     ]
 
 
@@ -87,7 +88,8 @@ class Result(C.Structure):
 
 class PoroParams(C.Structure):
     _fields_ = [("nu_u", C.c_double), ("alpha", C.c_double), ("perm", C.c_double), ("visc", C.c_double),
-                ("dt", C.c_double), ("p0", C.c_double), ("mode", C.c_int32), ("near_cache_bytes", C.c_int64)]
+                ("dt", C.c_double), ("p0", C.c_double), ("mode", C.c_int32), ("near_cache_bytes", C.c_int64),
+                ("m2l", C.c_int32)]
 
 
 class Peaks(C.Structure):
@@ -449,11 +451,11 @@ def fmddm_server_poll(srv, ticket: int, n: int = 0, comps: int = 2):
     return res, (D if res["state"] == FMDDM_REQ_DONE else None)
 
 
-def fmddm_server_set_poro(srv, nu_u, alpha, perm, visc, dt, p0=0.0, near_cache_bytes=0):
+def fmddm_server_set_poro(srv, nu_u, alpha, perm, visc, dt, p0=0.0, near_cache_bytes=0, m2l=0):
     """Poroelastic medium for every later request (time marches with the
     multipole form, FMDDM_APPLY_FMM)."""
     pp = PoroParams(float(nu_u), float(alpha), float(perm), float(visc), float(dt), float(p0), FMDDM_APPLY_FMM,
-                    int(near_cache_bytes))
+                    int(near_cache_bytes), int(m2l))
     _scheck(lib().fmddm_server_set_poro(srv, C.byref(pp)), srv)
 
 
@@ -474,11 +476,13 @@ def fmddm_trim_cache() -> int:
 
 
 # ------------------------------------------------------------ poroelastic
-def fmddm_poro_set(ctx, nu_u, alpha, perm, visc, dt, p0=0.0, mode=1, near_cache_bytes=0):
-    """mode: FMDDM_APPLY_DIRECT (1, exact) or FMDDM_APPLY_FMM (0).
-    near_cache_bytes: FMM near-field cache budget (0 default, < 0 none)."""
+def fmddm_poro_set(ctx, nu_u, alpha, perm, visc, dt, p0=0.0, mode=1, near_cache_bytes=0, m2l=0):
+    """mode: FMDDM_APPLY_DIRECT (1, exact), FMDDM_APPLY_FMM (0) or
+    FMDDM_APPLY_DENSE (2, history-only).  near_cache_bytes: FMM near-field
+    cache budget (0 default, < 0 none).  m2l: FMDDM_M2L_DENSE (0) or
+    FMDDM_M2L_SVD (1, the left-hand side's M2L compressed per tree level)."""
     pp = PoroParams(float(nu_u), float(alpha), float(perm), float(visc), float(dt), float(p0), int(mode),
-                    int(near_cache_bytes))
+                    int(near_cache_bytes), int(m2l))
     _check(lib().fmddm_poro_set(ctx, C.byref(pp)), ctx)
 
 

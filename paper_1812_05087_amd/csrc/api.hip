@@ -3,6 +3,7 @@
 // any internal error into a status code plus a message.
 #include "internal.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -173,6 +174,8 @@ fmddm_status fmddm_tree_get_info(fmddm_ctx *ctx, const fmddm_tree *t, fmddm_tree
     info->device_bytes = b;
     info->m2m_launches = (int64_t)t->m2m_launch.size();
     info->m2m_cut = t->m2m_cut;
+    if (t->pc_ok == 1)
+        for (int r : t->pc_rank) info->poro_m2l_rank = std::max(info->poro_m2l_rank, (int32_t)r);
     return FMDDM_OK;
 }
 
@@ -260,9 +263,10 @@ fmddm_status fmddm_poro_set(fmddm_ctx *ctx, const fmddm_poro_params *pp)
     const double nu = ctx->prm.nu;
     if (!(pp->nu_u > nu && pp->nu_u < 0.5) || !(pp->alpha > 0.0 && pp->alpha <= 1.0) || !(pp->perm > 0.0) ||
         !(pp->visc > 0.0) || !(pp->dt > 0.0) || !std::isfinite(pp->p0) ||
-        (pp->mode != FMDDM_APPLY_DIRECT && pp->mode != FMDDM_APPLY_FMM && pp->mode != FMDDM_APPLY_DENSE)) {
+        (pp->mode != FMDDM_APPLY_DIRECT && pp->mode != FMDDM_APPLY_FMM && pp->mode != FMDDM_APPLY_DENSE) ||
+        (pp->m2l != FMDDM_M2L_DENSE && pp->m2l != FMDDM_M2L_SVD)) {
         ctx->err = "poroelastic parameters: need nu < nu_u < 0.5, 0 < alpha <= 1, perm, visc, dt > 0, "
-                   "mode DIRECT, FMM or DENSE";
+                   "mode DIRECT, FMM or DENSE, m2l DENSE or SVD";
         return FMDDM_EINVAL;
     }
     if (ctx->prm.precision != FMDDM_PREC_FP64) {

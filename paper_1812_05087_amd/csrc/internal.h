@@ -293,6 +293,16 @@ struct fmddm_tree {
     // left-hand side F(dt) in one multipole pass: the first level's near
     // blocks and M2L operators with the drained elastic part added
     fmddm::DBuf<double> pn_lhs, pf_ops0;
+    // the left-hand side's M2L compressed per tree level (poro m2l = SVD):
+    // level slot k has row-space basis Vt (rq x Mq), column-space basis U
+    // (Mq x rq); each combination's operator becomes C (rq x rq)
+    int pc_ok = 0;             // 1 built, -1 not worth it (rank near full)
+    double pc_tol = 0.0;
+    int pc_rq = 0, pc_nlev = 0, pc_nptile = 0, pc_netile = 0;
+    std::vector<int> pc_rank;  // retained rank per level slot
+    fmddm::DBuf<double> pc_Vt, pc_U, pc_C, pc_What, pc_Z, pc_Ghat;
+    fmddm::DBuf<int> pc_ptile_op, pc_ptile_beg, pc_ptile_end, pc_pcell, pc_etile_op, pc_etile_beg, pc_etile_end,
+        pc_ecell;
     // history-only variant: the left-hand side as a dense 3n x 3n matrix
     fmddm::DBuf<double> pdense;
     int pdense_ok = 0;

@@ -40,6 +40,10 @@
 #include "gj.h"
 #include "internal.h"
 
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
 #include <atomic>
 #include <mutex>
 
@@ -544,6 +548,77 @@ __global__ void k_pops(int ncombo, const int *__restrict__ clvl, const int *__re
     }
 }
 
+// Compressed left-hand-side M2L.  For the combinations o of one tree level
+// (operators K_o, m x m with m = 4 p^2, stored row-major with leading
+// dimension Mq), side 0 packs [K_o1 | K_o2 | ...] and side 1 [K_o1^T |
+// K_o2^T | ...], m x (n m) column-major: the left singular vectors of the
+// first span the operators' column space, of the second their row space.
+__global__ void k_pc_pack(int nc, const int *__restrict__ combos, int m, int Mq, int side,
+                          const double *__restrict__ ops, double *__restrict__ fat)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)m * nc * m) return;
+    int col = (int)(e / m), i = (int)(e - (int64_t)col * m);
+    int o = col / m, j = col - o * m;
+    const double *K = ops + (size_t)combos[o] * Mq * Mq;
+    fat[e] = side == 0 ? K[(size_t)i * Mq + j] : K[(size_t)j * Mq + i];
+}
+
+// uniform random numbers in [-1, 1) from the splitmix64 finaliser of the
+// index (deterministic test matrices for the range finder)
+__global__ void k_pc_rand(int64_t count, uint64_t seed, double *__restrict__ out)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(e + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    out[e] = (double)(z >> 11) * 0x1.0p-52 - 1.0;
+}
+
+// the lower triangle of the leading m x m block of an LQ factorisation
+__global__ void k_pc_lower(int m, const double *__restrict__ lq, double *__restrict__ L)
+{
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= m * m) return;
+    int j = e / m, i = e - j * m;
+    L[e] = i >= j ? lq[e] : 0.0;
+}
+
+// Bases of level slot k from the left singular vectors (column-major m x m)
+// of its column space (Uc) and row space (Ur), rank[k] columns kept:
+// Vt (rq x Mq) and UT (rq x Mq) hold the vectors as rows, U (Mq x rq) the
+// column-space vectors as columns; the padding is zero.
+__global__ void k_pc_bases(int nlev, int m, int Mq, int rq, const int *__restrict__ rank,
+                           const double *__restrict__ Uc, const double *__restrict__ Ur, double *__restrict__ Vt,
+                           double *__restrict__ UT, double *__restrict__ U)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)nlev * rq * Mq) return;
+    int k = (int)(e / ((int64_t)rq * Mq));
+    int r = (int)(e - (int64_t)k * rq * Mq);
+    int a = r / Mq, i = r - a * Mq;
+    bool in = a < rank[k] && i < m;
+    const size_t mm = (size_t)m * m;
+    double vr = in ? Ur[k * mm + (size_t)a * m + i] : 0.0;
+    double vc = in ? Uc[k * mm + (size_t)a * m + i] : 0.0;
+    Vt[e] = vr;
+    UT[e] = vc;
+    U[((size_t)k * Mq + i) * rq + a] = vc;
+}
+
+// C_o[b][a] = Ct[o rq + a][b] (row-major rq x rq per combination)
+__global__ void k_pc_transpose(int nc, int rq, const double *__restrict__ Ct, double *__restrict__ C)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)nc * rq * rq) return;
+    int o = (int)(e / ((int64_t)rq * rq));
+    int r = (int)(e - (int64_t)o * rq * rq);
+    int b = r / rq, a = r - b * rq;
+    C[e] = Ct[((size_t)o * rq + a) * rq + b];
+}
+
 // charges per element (tree order) and term: Q[(j n + i) 4 + c], and the
 // DDs in tree order D3[(j n + i) 3 + c]
 __global__ void k_pprep(int n, int H, const int *__restrict__ perm, const double *__restrict__ E,
@@ -1033,12 +1108,14 @@ void poro_fmm_setup(fmddm_ctx *ctx, fmddm_tree *t, int H)
         up(t->pf_combo_oy, coy);
         t->pf_ncombo = (int)clvl.size();
         t->pf_ntile = (int)top.size();
+        t->pf_h_combo_lvl = clvl;
         t->pf_p = p;
         t->pf_Mq = Mq;
         t->pf_dt = pp.dt;
         for (int k = 0; k < 8; ++k) t->pf_key[k] = key[k];
         t->pf_H = 0;
         t->pf_ops0_ok = 0;
+        t->pc_ok = 0;
         t->pf_G.alloc((size_t)ncell * Mq);
         t->pf_G.zero(s);
         t->pf_Z.alloc((size_t)std::max<int64_t>(t->nV, 1) * Mq);
@@ -1090,6 +1167,218 @@ void lhs_ops(fmddm_ctx *ctx, fmddm_tree *t)
     t->pf_ops0_ok = 1;
 }
 
+// Compresses the left-hand side's M2L operators per tree level (the kernel
+// is not homogeneous, so unlike the elastic operators each level has its
+// own bases): for the combinations K_o of a level, the leading left
+// singular vectors of [K_o ...] (column space, U) and of [K_o^T ...] (row
+// space, V), cut where the singular values fall below m2l_tol of the
+// largest; then K_o ~ U C_o V^T with C_o = U^T K_o V.  The singular vectors
+// come from a randomized range finder on the m x (n m) packing (the ranks
+// are far below m: ~90 of 400 at p = 10, of 1024 at p = 16).  A product
+// is then a projection per source cell, the rq x rq translations per
+// interaction pair, and an expansion per target cell.  Left uncompressed
+// (pc_ok = -1) when a level's rank would exceed 3/4 of m.
+void lhs_compress(fmddm_ctx *ctx, fmddm_tree *t)
+{
+    const double tol = ctx->prm.m2l_tol;
+    if (t->pc_ok != 0 && t->pc_tol == tol) return;
+    lhs_ops(ctx, t);
+    t->pc_ok = -1;
+    t->pc_tol = tol;
+    const int nc = t->pf_ncombo;
+    if (nc == 0) return;
+    hipStream_t s = ctx->stream;
+    const int p = ctx->prm.p, m = 4 * p * p, Mq = t->pf_Mq;
+    std::vector<int> levs(t->pf_h_combo_lvl);
+    std::sort(levs.begin(), levs.end());
+    levs.erase(std::unique(levs.begin(), levs.end()), levs.end());
+    const int nlev = (int)levs.size();
+    std::vector<int> slot_of(64, -1);
+    for (int k = 0; k < nlev; ++k) slot_of[levs[k]] = k;
+    std::vector<std::vector<int>> bylev(nlev);
+    for (int o = 0; o < nc; ++o) bylev[slot_of[t->pf_h_combo_lvl[o]]].push_back(o);
+    size_t maxn = 0;
+    for (auto &v : bylev) maxn = std::max(maxn, v.size());
+    if (!ctx->blas) {
+        rocblas_handle h;
+        if (rocblas_create_handle(&h) != rocblas_status_success) throw Error{FMDDM_EDEVICE, "rocblas handle"};
+        ctx->blas = h;
+    }
+    rocblas_handle h = (rocblas_handle)ctx->blas;
+    rocblas_set_stream(h, s);
+    const size_t mm = (size_t)m * m;
+    const int64_t Nmax = (int64_t)maxn * m;
+    DBuf<double> fat, Om, Y, B, L, S, E, tau, UL, Uc, Ur;
+    DBuf<int> info, dcomb;
+    fat.alloc(mm * maxn);
+    B.alloc(mm * maxn);
+    Om.alloc((size_t)Nmax * m);
+    Y.alloc(mm);
+    L.alloc(mm);
+    UL.alloc(mm);
+    S.alloc(m);
+    E.alloc(m);
+    tau.alloc(m);
+    Uc.alloc(mm * nlev);
+    Ur.alloc(mm * nlev);
+    info.alloc(1);
+    dcomb.alloc(maxn);
+    std::vector<int> rank(nlev, 1);
+    std::vector<double> hs(m);
+    const double one = 1.0, zero = 0.0;
+    // Left singular vectors of fat (m x N) down to tol of the largest
+    // singular value, by a randomized range finder: Y = fat Om for k random
+    // columns, Q = orth(Y), B = Q^T fat, and the SVD of B through its LQ
+    // factor (B = L P, L = U_L S W^T) gives fat ~ (Q U_L) S (P^T W)^T.  k
+    // doubles until the k-th singular value of B falls below tol (all m:
+    // exact).  Written to Uo (m x k, leading dimension m); returns the rank.
+    auto left_basis = [&](int N, double *Uo, uint64_t seed) {
+        int k = std::min(m, 192);
+        for (;;) {
+            hipLaunchKernelGGL(k_pc_rand, dim3(cdiv((int64_t)N * k, 256)), dim3(256), 0, s, (int64_t)N * k, seed,
+                               Om.p);
+            FM_CHECK_LAUNCH();
+            bool ok = rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, m, k, N, &one, fat.p, m,
+                                    Om.p, N, &zero, Y.p, m) == rocblas_status_success;
+            ok = ok && rocsolver_dgeqrf(h, m, k, Y.p, m, tau.p) == rocblas_status_success;
+            ok = ok && rocsolver_dorgqr(h, m, k, k, Y.p, m, tau.p) == rocblas_status_success;
+            ok = ok && rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, k, N, m, &one, Y.p, m,
+                                     fat.p, m, &zero, B.p, k) == rocblas_status_success;
+            ok = ok && rocsolver_dgelqf(h, k, N, B.p, k, tau.p) == rocblas_status_success;
+            if (!ok) throw Error{FMDDM_EDEVICE, "range finder of the poroelastic M2L operators failed"};
+            hipLaunchKernelGGL(k_pc_lower, dim3(cdiv((int64_t)k * k, 256)), dim3(256), 0, s, k, B.p, L.p);
+            FM_CHECK_LAUNCH();
+            if (rocsolver_dgesvd(h, rocblas_svect_all, rocblas_svect_none, k, k, L.p, k, S.p, UL.p, k, nullptr, 1,
+                                 E.p, rocblas_outofplace, info.p) != rocblas_status_success)
+                throw Error{FMDDM_EDEVICE, "rocsolver_dgesvd failed"};
+            int hinfo = 0;
+            FM_HIP(hipMemcpyAsync(&hinfo, info.p, 4, hipMemcpyDeviceToHost, s));
+            FM_HIP(hipMemcpyAsync(hs.data(), S.p, (size_t)k * 8, hipMemcpyDeviceToHost, s));
+            FM_HIP(hipStreamSynchronize(s));
+            if (hinfo != 0) throw Error{FMDDM_EDEVICE, "SVD of the poroelastic M2L operators did not converge"};
+            if (k < m && hs[k - 1] > tol * hs[0]) {
+                k = std::min(m, 2 * k);
+                continue;
+            }
+            if (rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, m, k, k, &one, Y.p, m, UL.p, k,
+                              &zero, Uo, m) != rocblas_status_success)
+                throw Error{FMDDM_EDEVICE, "rocblas_dgemm failed"};
+            int r = 1;
+            for (int i = 0; i < k; ++i)
+                if (hs[0] > 0.0 && hs[i] > tol * hs[0]) r = i + 1;
+            return r;
+        }
+    };
+    for (int k = 0; k < nlev; ++k) {
+        const int n = (int)bylev[k].size();
+        FM_HIP(hipMemcpyAsync(dcomb.p, bylev[k].data(), n * 4, hipMemcpyHostToDevice, s));
+        for (int side = 0; side < 2; ++side) {
+            int64_t tot = (int64_t)m * n * m;
+            hipLaunchKernelGGL(k_pc_pack, dim3(cdiv(tot, 256)), dim3(256), 0, s, n, dcomb.p, m, Mq, side,
+                               t->pf_ops0.p, fat.p);
+            FM_CHECK_LAUNCH();
+            double *Uo = (side == 0 ? Uc.p : Ur.p) + (size_t)k * mm;
+            rank[k] = std::max(rank[k], left_basis(n * m, Uo, 2 * (uint64_t)k + side));
+        }
+    }
+    int rmax = *std::max_element(rank.begin(), rank.end());
+    const int rq = (rmax + 63) / 64 * 64;
+    if (4 * rmax > 3 * m || rq >= Mq) return;  // not worth it: the dense operators stay
+    t->pc_rank = rank;
+    t->pc_rq = rq;
+    t->pc_nlev = nlev;
+    DBuf<int> drank;
+    drank.alloc(nlev);
+    FM_HIP(hipMemcpyAsync(drank.p, rank.data(), nlev * 4, hipMemcpyHostToDevice, s));
+    DBuf<double> UT;
+    t->pc_Vt.alloc((size_t)nlev * rq * Mq);
+    t->pc_U.alloc((size_t)nlev * Mq * rq);
+    UT.alloc((size_t)nlev * rq * Mq);
+    hipLaunchKernelGGL(k_pc_bases, dim3(cdiv((int64_t)nlev * rq * Mq, 256)), dim3(256), 0, s, nlev, m, Mq, rq,
+                       drank.p, Uc.p, Ur.p, t->pc_Vt.p, UT.p, t->pc_U.p);
+    FM_CHECK_LAUNCH();
+    // C_o = U^T K_o V: T1[o rq + a] = K_o v_a, then Ct[o rq + a] = U^T T1[o rq + a]
+    std::vector<int> top, tb, te, src, dst, lop;
+    for (int o = 0; o < nc; ++o) {
+        const int k = slot_of[t->pf_h_combo_lvl[o]];
+        for (int a0 = 0; a0 < rq; a0 += 32) {
+            top.push_back(o);
+            lop.push_back(k);
+            tb.push_back((int)src.size());
+            for (int a = a0; a < std::min(rq, a0 + 32); ++a) {
+                src.push_back(k * rq + a);
+                dst.push_back(o * rq + a);
+            }
+            te.push_back((int)src.size());
+        }
+    }
+    auto up = [&](DBuf<int> &d, const std::vector<int> &v) {
+        d.alloc(std::max<size_t>(v.size(), 1));
+        if (!v.empty()) FM_HIP(hipMemcpyAsync(d.p, v.data(), v.size() * 4, hipMemcpyHostToDevice, s));
+    };
+    DBuf<int> dtop, dtb, dte, dsrc, ddst, dlop;
+    up(dtop, top);
+    up(dtb, tb);
+    up(dte, te);
+    up(dsrc, src);
+    up(ddst, dst);
+    up(dlop, lop);
+    DBuf<double> T1, Ct;
+    T1.alloc((size_t)nc * rq * Mq);
+    Ct.alloc((size_t)nc * rq * rq);
+    fmm_pair_gemm(s, (int)top.size(), Mq, t->pf_ops0.p, (size_t)Mq * Mq, Mq, Mq, t->pc_Vt.p, Mq, dtop.p, dtb.p,
+                  dte.p, dsrc.p, ddst.p, T1.p, Mq);
+    fmm_pair_gemm(s, (int)top.size(), rq, UT.p, (size_t)rq * Mq, Mq, Mq, T1.p, Mq, dlop.p, dtb.p, dte.p, ddst.p,
+                  ddst.p, Ct.p, rq);
+    t->pc_C.alloc((size_t)nc * rq * rq);
+    hipLaunchKernelGGL(k_pc_transpose, dim3(cdiv((int64_t)nc * rq * rq, 256)), dim3(256), 0, s, nc, rq, Ct.p,
+                       t->pc_C.p);
+    FM_CHECK_LAUNCH();
+    // schedules: projection of every V-list source cell, expansion of every
+    // cell with a V list, in tiles of at most 32 cells of one level
+    const int ncell = t->ncell;
+    const std::vector<int> &vo = t->h_loff[1];
+    std::vector<int> hv(t->nV);
+    if (t->nV) FM_HIP(hipMemcpyAsync(hv.data(), t->lidx[1].p, t->nV * 4, hipMemcpyDeviceToHost, s));
+    FM_HIP(hipStreamSynchronize(s));
+    std::vector<char> is_src(ncell, 0);
+    for (int v : hv) is_src[v] = 1;
+    auto tiles = [&](bool proj, std::vector<int> &op, std::vector<int> &b, std::vector<int> &e,
+                     std::vector<int> &cell) {
+        for (int k = 0; k < nlev; ++k) {
+            std::vector<int> cs;
+            for (int c = 0; c < ncell; ++c)
+                if (t->h_level[c] == levs[k] && (proj ? is_src[c] != 0 : vo[c + 1] > vo[c])) cs.push_back(c);
+            for (size_t i0 = 0; i0 < cs.size(); i0 += 32) {
+                op.push_back(k);
+                b.push_back((int)cell.size());
+                for (size_t i = i0; i < std::min(cs.size(), i0 + 32); ++i) cell.push_back(cs[i]);
+                e.push_back((int)cell.size());
+            }
+        }
+    };
+    std::vector<int> pop, pb, pe, pcell, eop, eb, ee, ecell;
+    tiles(true, pop, pb, pe, pcell);
+    tiles(false, eop, eb, ee, ecell);
+    up(t->pc_ptile_op, pop);
+    up(t->pc_ptile_beg, pb);
+    up(t->pc_ptile_end, pe);
+    up(t->pc_pcell, pcell);
+    up(t->pc_etile_op, eop);
+    up(t->pc_etile_beg, eb);
+    up(t->pc_etile_end, ee);
+    up(t->pc_ecell, ecell);
+    t->pc_nptile = (int)pop.size();
+    t->pc_netile = (int)eop.size();
+    t->pc_What.alloc((size_t)ncell * rq);
+    t->pc_Z.alloc((size_t)std::max<int64_t>(t->nV, 1) * rq);
+    t->pc_Ghat.alloc((size_t)ncell * rq);
+    FM_HIP(hipStreamSynchronize(s));
+    t->bytes += (int64_t)(t->pc_Vt.bytes() + t->pc_U.bytes() + t->pc_C.bytes() + t->pc_What.bytes() +
+                          t->pc_Z.bytes() + t->pc_Ghat.bytes());
+    t->pc_ok = 1;
+}
+
 // out (mode 0: =, 1: -=) the sum over time levels j = 1..H of F_transient(j dt)
 // applied to E[j-1] (3n each, caller order), plus, if drained, the drained
 // elastic part of E[0]; multipole form.  E[j-1] is zero for j <= jlo (the
@@ -1106,6 +1395,8 @@ void poro_fmm_sum(fmddm_ctx *ctx, fmddm_tree *t, int H, const double *E, bool dr
     // include the drained elastic part (when the near budget holds them)
     const bool fused = H == 1 && drained && jlo == 0 && near_lhs(ctx, t);
     if (fused) lhs_ops(ctx, t);
+    if (fused && ctx->poro.m2l == FMDDM_M2L_SVD) lhs_compress(ctx, t);
+    const bool comp = fused && ctx->poro.m2l == FMDDM_M2L_SVD && t->pc_ok == 1;
     hipLaunchKernelGGL(k_pprep, dim3(cdiv(n, 256), H), dim3(256), 0, s, n, H, t->perm.p, E, t->scb.p, t->ssb.p,
                        t->pf_Q.p, t->pf_D3.p);
     FM_CHECK_LAUNCH();
@@ -1115,14 +1406,28 @@ void poro_fmm_sum(fmddm_ctx *ctx, fmddm_tree *t, int H, const double *E, bool dr
                            t->cpend.p, t->p2m_mat.p, t->pf_Q.p, n, p2, H, Mq, t->pf_W.p);
         FM_CHECK_LAUNCH();
         fmm_m2m4(ctx, t, H, H * Mq, Mq, t->pf_W.p);
-        if (fused)
-            fmm_pair_gemm(s, t->pf_ntile, Mq, t->pf_ops0.p, (size_t)Mq * Mq, Mq, Mq, t->pf_W.p, Mq, t->pf_tile_op.p,
-                          t->pf_tile_beg.p, t->pf_tile_end.p, t->pf_psrc.p, t->pf_pdst.p, t->pf_Z.p, Mq);
-        else
-            fmm_pair_gemm(s, t->pf_ntile, Mq, t->pf_ops.p, (size_t)Mq * t->pf_H * Mq, t->pf_H * Mq, H * Mq,
-                          t->pf_W.p, H * Mq, t->pf_tile_op.p, t->pf_tile_beg.p, t->pf_tile_end.p, t->pf_psrc.p,
-                          t->pf_pdst.p, t->pf_Z.p, Mq);
-        fmm_sum_pairs(s, t, t->pf_Z.p, Mq, Mq, t->pf_G.p, Mq);
+        if (comp) {
+            const int rq = t->pc_rq;
+            fmm_pair_gemm(s, t->pc_nptile, rq, t->pc_Vt.p, (size_t)rq * Mq, Mq, Mq, t->pf_W.p, Mq,
+                          t->pc_ptile_op.p, t->pc_ptile_beg.p, t->pc_ptile_end.p, t->pc_pcell.p, t->pc_pcell.p,
+                          t->pc_What.p, rq);
+            fmm_pair_gemm(s, t->pf_ntile, rq, t->pc_C.p, (size_t)rq * rq, rq, rq, t->pc_What.p, rq, t->pf_tile_op.p,
+                          t->pf_tile_beg.p, t->pf_tile_end.p, t->pf_psrc.p, t->pf_pdst.p, t->pc_Z.p, rq);
+            fmm_sum_pairs(s, t, t->pc_Z.p, rq, rq, t->pc_Ghat.p, rq);
+            fmm_pair_gemm(s, t->pc_netile, Mq, t->pc_U.p, (size_t)Mq * rq, rq, rq, t->pc_Ghat.p, rq,
+                          t->pc_etile_op.p, t->pc_etile_beg.p, t->pc_etile_end.p, t->pc_ecell.p, t->pc_ecell.p,
+                          t->pf_G.p, Mq);
+        } else {
+            if (fused)
+                fmm_pair_gemm(s, t->pf_ntile, Mq, t->pf_ops0.p, (size_t)Mq * Mq, Mq, Mq, t->pf_W.p, Mq,
+                              t->pf_tile_op.p, t->pf_tile_beg.p, t->pf_tile_end.p, t->pf_psrc.p, t->pf_pdst.p,
+                              t->pf_Z.p, Mq);
+            else
+                fmm_pair_gemm(s, t->pf_ntile, Mq, t->pf_ops.p, (size_t)Mq * t->pf_H * Mq, t->pf_H * Mq, H * Mq,
+                              t->pf_W.p, H * Mq, t->pf_tile_op.p, t->pf_tile_beg.p, t->pf_tile_end.p, t->pf_psrc.p,
+                              t->pf_pdst.p, t->pf_Z.p, Mq);
+            fmm_sum_pairs(s, t, t->pf_Z.p, Mq, Mq, t->pf_G.p, Mq);
+        }
         fmm_l2p4(ctx, t, t->pf_G.p, Mq, t->pf_far.p);
     }
     if (fused) {

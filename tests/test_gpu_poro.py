@@ -423,3 +423,47 @@ def test_poro_history_only_variant():
         e = float(np.linalg.norm(marched[h] - ref[h]) / np.linalg.norm(ref[h]))
         print(f"history-only march step {h + 1}: {e:.2e}")
         assert e <= 1e-6, (h, e)
+
+
+@pytest.mark.parametrize("p", [10, 16])
+def test_poro_lhs_compressed_m2l(p):
+    """The left-hand side's M2L compressed per tree level (poro m2l = SVD,
+    m2l_tol 1e-12) against the uncompressed operators and the exact
+    products, on a 5 x 200-element well cluster (four V-list levels).  The
+    truncation drops singular values below 1e-12 of the largest, and the
+    compressed product sums 27 translations of projected weights, so it
+    stays within ~1e-10 of the uncompressed one (bar 1e-9); against the
+    exact product the uncompressed bar holds (1e-6).  Not bitwise equal to
+    the uncompressed product, so the compressed path ran."""
+    wl = W.well_cluster(n_frac=5, elems=200, half_length=20.0, spacing=10.0)
+    n3 = 3 * wl.n
+    rng = np.random.default_rng(6)
+    scale = np.tile([1e-4, 1e-4, 1e-10], wl.n)
+    D = dev(rng.standard_normal(n3) * scale)
+    res = {}
+    for mode, m2l in ((F.FMDDM_APPLY_DIRECT, 0), (F.FMDDM_APPLY_FMM, 0), (F.FMDDM_APPLY_FMM, 1)):
+        prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=MED["E"], nu=MED["nu"], p=p, leaf=32, m2l_tol=1e-12)
+        try:
+            F.fmddm_poro_set(prob.ctx, MED["nuu"], MED["alpha"], MED["perm"], MED["visc"], DT, P0, mode=mode,
+                             m2l=m2l)
+            o = torch.zeros(n3, dtype=torch.float64, device="cuda")
+            F.fmddm_poro_apply(prob.ctx, prob.tree, 0, D, o)
+            o2 = torch.zeros(n3, dtype=torch.float64, device="cuda")
+            F.fmddm_poro_apply(prob.ctx, prob.tree, 0, D, o2)  # the stored compressed operators
+            assert torch.equal(o, o2)
+            res[(mode, m2l)] = o.cpu().numpy()
+            info = F.fmddm_tree_get_info(prob.ctx, prob.tree)
+            if mode == F.FMDDM_APPLY_FMM:
+                rank = info["poro_m2l_rank"]
+                assert (rank > 0) == (m2l == 1), rank
+                assert rank < 3 * 4 * p * p // 4
+        finally:
+            prob.close()
+    assert info["nV"] > 0
+    exact, dense, comp = res[(F.FMDDM_APPLY_DIRECT, 0)], res[(F.FMDDM_APPLY_FMM, 0)], res[(F.FMDDM_APPLY_FMM, 1)]
+    e_cd, e_ce, e_de = cmp(comp, dense), cmp(comp, exact), cmp(dense, exact)
+    print(f"p = {p}: rank {rank} of {4 * p * p}; compressed vs uncompressed {e_cd:.2e}, vs exact {e_ce:.2e} "
+          f"(uncompressed vs exact {e_de:.2e})")
+    assert not np.array_equal(comp, dense)
+    assert e_cd <= 1e-9, e_cd
+    assert e_ce <= 1e-6, e_ce
