@@ -406,6 +406,14 @@ typedef struct {
                                  when the stored near field holds the left-hand side.  A
                                  one-time cost per tree (an SVD of every level's operators)
                                  that pays over many products. */
+    int32_t exact_far_levels; /* FMDDM_APPLY_FMM history sums and lag products: 0 (default):
+                                 where every V-list pair lies far outside the diffusion length
+                                 at the last time level (z = r^2 / (4 c t) >= 50, checked per
+                                 tree level from the cell size), the transient kernel is affine
+                                 in t to double precision, and the far field takes two
+                                 multipole terms (the first two time levels' operators) for any
+                                 number of levels; 1: one term per time level always.  The near
+                                 field is exact per level either way. */
 } fmddm_poro_params;
 
 /* Attaches the poroelastic medium to the context (validated: EINVAL). */

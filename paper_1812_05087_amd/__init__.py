@@ -89,7 +89,7 @@ class Result(C.Structure):
 class PoroParams(C.Structure):
     _fields_ = [("nu_u", C.c_double), ("alpha", C.c_double), ("perm", C.c_double), ("visc", C.c_double),
                 ("dt", C.c_double), ("p0", C.c_double), ("mode", C.c_int32), ("near_cache_bytes", C.c_int64),
-                ("m2l", C.c_int32)]
+                ("m2l", C.c_int32), ("exact_far_levels", C.c_int32)]
 
 
 class Peaks(C.Structure):
@@ -455,7 +455,7 @@ def fmddm_server_set_poro(srv, nu_u, alpha, perm, visc, dt, p0=0.0, near_cache_b
     """Poroelastic medium for every later request (time marches with the
     multipole form, FMDDM_APPLY_FMM)."""
     pp = PoroParams(float(nu_u), float(alpha), float(perm), float(visc), float(dt), float(p0), FMDDM_APPLY_FMM,
-                    int(near_cache_bytes), int(m2l))
+                    int(near_cache_bytes), int(m2l), 0)
     _scheck(lib().fmddm_server_set_poro(srv, C.byref(pp)), srv)
 
 
@@ -476,13 +476,16 @@ def fmddm_trim_cache() -> int:
 
 
 # ------------------------------------------------------------ poroelastic
-def fmddm_poro_set(ctx, nu_u, alpha, perm, visc, dt, p0=0.0, mode=1, near_cache_bytes=0, m2l=0):
+def fmddm_poro_set(ctx, nu_u, alpha, perm, visc, dt, p0=0.0, mode=1, near_cache_bytes=0, m2l=0,
+                   exact_far_levels=0):
     """mode: FMDDM_APPLY_DIRECT (1, exact), FMDDM_APPLY_FMM (0) or
     FMDDM_APPLY_DENSE (2, history-only).  near_cache_bytes: FMM near-field
     cache budget (0 default, < 0 none).  m2l: FMDDM_M2L_DENSE (0) or
-    FMDDM_M2L_SVD (1, the left-hand side's M2L compressed per tree level)."""
+    FMDDM_M2L_SVD (1, the left-hand side's M2L compressed per tree level).
+    exact_far_levels: 1 keeps one far-field term per time level in history
+    sums (0: two terms where the far field is affine in time)."""
     pp = PoroParams(float(nu_u), float(alpha), float(perm), float(visc), float(dt), float(p0), int(mode),
-                    int(near_cache_bytes), int(m2l))
+                    int(near_cache_bytes), int(m2l), int(exact_far_levels))
     _check(lib().fmddm_poro_set(ctx, C.byref(pp)), ctx)
 
 

@@ -264,9 +264,10 @@ fmddm_status fmddm_poro_set(fmddm_ctx *ctx, const fmddm_poro_params *pp)
     if (!(pp->nu_u > nu && pp->nu_u < 0.5) || !(pp->alpha > 0.0 && pp->alpha <= 1.0) || !(pp->perm > 0.0) ||
         !(pp->visc > 0.0) || !(pp->dt > 0.0) || !std::isfinite(pp->p0) ||
         (pp->mode != FMDDM_APPLY_DIRECT && pp->mode != FMDDM_APPLY_FMM && pp->mode != FMDDM_APPLY_DENSE) ||
-        (pp->m2l != FMDDM_M2L_DENSE && pp->m2l != FMDDM_M2L_SVD)) {
+        (pp->m2l != FMDDM_M2L_DENSE && pp->m2l != FMDDM_M2L_SVD) ||
+        (pp->exact_far_levels != 0 && pp->exact_far_levels != 1)) {
         ctx->err = "poroelastic parameters: need nu < nu_u < 0.5, 0 < alpha <= 1, perm, visc, dt > 0, "
-                   "mode DIRECT, FMM or DENSE, m2l DENSE or SVD";
+                   "mode DIRECT, FMM or DENSE, m2l DENSE or SVD, exact_far_levels 0 or 1";
         return FMDDM_EINVAL;
     }
     if (ctx->prm.precision != FMDDM_PREC_FP64) {

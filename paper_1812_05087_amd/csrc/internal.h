@@ -282,6 +282,7 @@ struct fmddm_tree {
     fmddm::DBuf<int> pf_tile_op, pf_tile_beg, pf_tile_end, pf_psrc, pf_pdst, pf_combo_lvl, pf_combo_ox,
         pf_combo_oy;
     fmddm::DBuf<double> pf_ops, pf_W, pf_Z, pf_G, pf_far, pf_Q, pf_D3, pf_near, pf_D2, pf_o2;
+    fmddm::DBuf<double> pf_D3a;  // per-level DDs of a history sum whose far field takes two terms
     double pf_key[8] = {};  // medium the operators were built for
     // poroelastic near field: per time level j (time (j+1) dt), the 4 x 3
     // response blocks of every near (target, source) pair in item order,

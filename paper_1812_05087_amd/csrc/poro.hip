@@ -642,6 +642,46 @@ __global__ void k_pprep(int n, int H, const int *__restrict__ perm, const double
     d[2] = e[2];
 }
 
+// The far field of a history sum in two terms.  Where every V-list pair is
+// far outside the diffusion length (z = r^2 / (4 c t) >= 50 at the last
+// time level), the transient kernel is affine in t to double precision:
+// h(z) = 1 - 1/z, P(2, z) = 1 and z E1(z) + 1 - e^-z = 1 up to e^-z terms,
+// so F(t) = A + t B.  Then sum_j F(j dt) E_j = F(dt) sum_j (2 - j) E_j
+// + F(2 dt) sum_j (j - 1) E_j: two multipole terms with the operators of
+// the first two time levels, whatever the number of levels.  Q2 gets the
+// two combined charges [(m n + i) 4 + c], D3 the DDs of every level (the
+// near field stays exact per level).
+__global__ void k_pprep_affine(int n, int H, const int *__restrict__ perm, const double *__restrict__ E,
+                               const double *__restrict__ cb, const double *__restrict__ sb,
+                               double *__restrict__ Q2, double *__restrict__ D3)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double a[4] = {0.0, 0.0, 0.0, 0.0}, b[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < H; ++j) {  // time level j + 1
+        const double *e = E + (size_t)j * 3 * n + 3 * (size_t)perm[i];
+        double q0, q1, q2;
+        charge(cb[i], sb[i], e[0], e[1], q0, q1, q2);
+        const double wa = (double)(1 - j), wb = (double)j;
+        a[0] += wa * q0;
+        a[1] += wa * q1;
+        a[2] += wa * q2;
+        a[3] += wa * e[2];
+        b[0] += wb * q0;
+        b[1] += wb * q1;
+        b[2] += wb * q2;
+        b[3] += wb * e[2];
+        double *d = D3 + ((size_t)j * n + i) * 3;
+        d[0] = e[0];
+        d[1] = e[1];
+        d[2] = e[2];
+    }
+    for (int c = 0; c < 4; ++c) {
+        Q2[(size_t)i * 4 + c] = a[c];
+        Q2[((size_t)n + i) * 4 + c] = b[c];
+    }
+}
+
 // leaf weights per term (eq. 3.6): W[(leaf H + j) Mq + c p^2 + t]
 __global__ __launch_bounds__(256) void k_pp2m(int nleaf, const int *__restrict__ leaves,
                                               const int *__restrict__ pbeg, const int *__restrict__ pend,
@@ -1379,6 +1419,22 @@ void lhs_compress(fmddm_ctx *ctx, fmddm_tree *t)
     t->pc_ok = 1;
 }
 
+// Whether the far field of an H-level history sum may take the two-term
+// form (k_pprep_affine): the nodes of V-list cells at level l (half-width
+// hw) are at least 2 hw apart, so z >= hw^2 / (c H dt) for every pair.
+constexpr double FAR_AFFINE_Z = 50.0;  // e^-50 z^2 < 1e-18
+
+bool far_affine(const fmddm_ctx *ctx, const fmddm_tree *t, int H)
+{
+    const PoroK K = poro_constants(ctx);
+    const double ct = K.c * H * ctx->poro.dt;
+    for (int l : t->pf_h_combo_lvl) {
+        const double hw = t->L / (double)(2LL << l);
+        if (hw * hw < FAR_AFFINE_Z * ct) return false;
+    }
+    return true;
+}
+
 // out (mode 0: =, 1: -=) the sum over time levels j = 1..H of F_transient(j dt)
 // applied to E[j-1] (3n each, caller order), plus, if drained, the drained
 // elastic part of E[0]; multipole form.  E[j-1] is zero for j <= jlo (the
@@ -1387,7 +1443,13 @@ void poro_fmm_sum(fmddm_ctx *ctx, fmddm_tree *t, int H, const double *E, bool dr
                   int jlo = 0)
 {
     upload_rules(ctx->device);
-    poro_fmm_setup(ctx, t, H);
+    bool affine = false;  // the far field in two terms (history sums only)
+    if (!drained && H > 2 && ctx->poro.exact_far_levels == 0) {
+        poro_fmm_setup(ctx, t, 2);
+        affine = far_affine(ctx, t, H);
+    }
+    if (!affine) poro_fmm_setup(ctx, t, H);
+    const int Hf = affine ? 2 : H;  // multipole terms
     hipStream_t s = ctx->stream;
     const int n = (int)t->n, p = ctx->prm.p, p2 = p * p, Mq = t->pf_Mq;
     PoroK K = poro_constants(ctx);
@@ -1397,15 +1459,23 @@ void poro_fmm_sum(fmddm_ctx *ctx, fmddm_tree *t, int H, const double *E, bool dr
     if (fused) lhs_ops(ctx, t);
     if (fused && ctx->poro.m2l == FMDDM_M2L_SVD) lhs_compress(ctx, t);
     const bool comp = fused && ctx->poro.m2l == FMDDM_M2L_SVD && t->pc_ok == 1;
-    hipLaunchKernelGGL(k_pprep, dim3(cdiv(n, 256), H), dim3(256), 0, s, n, H, t->perm.p, E, t->scb.p, t->ssb.p,
-                       t->pf_Q.p, t->pf_D3.p);
+    double *D3 = t->pf_D3.p;  // DDs per time level, tree order (near field)
+    if (affine) {
+        if (t->pf_D3a.n < (size_t)H * n * 3) t->pf_D3a.alloc((size_t)H * n * 3);
+        D3 = t->pf_D3a.p;
+        hipLaunchKernelGGL(k_pprep_affine, dim3(cdiv(n, 256)), dim3(256), 0, s, n, H, t->perm.p, E, t->scb.p,
+                           t->ssb.p, t->pf_Q.p, D3);
+    } else {
+        hipLaunchKernelGGL(k_pprep, dim3(cdiv(n, 256), H), dim3(256), 0, s, n, H, t->perm.p, E, t->scb.p,
+                           t->ssb.p, t->pf_Q.p, D3);
+    }
     FM_CHECK_LAUNCH();
     bool far = t->nV > 0 && t->pf_ntile > 0;
     if (far) {
-        hipLaunchKernelGGL(k_pp2m, dim3(t->nleaf, H), dim3(256), 0, s, t->nleaf, t->dleaves.p, t->cpbeg.p,
-                           t->cpend.p, t->p2m_mat.p, t->pf_Q.p, n, p2, H, Mq, t->pf_W.p);
+        hipLaunchKernelGGL(k_pp2m, dim3(t->nleaf, Hf), dim3(256), 0, s, t->nleaf, t->dleaves.p, t->cpbeg.p,
+                           t->cpend.p, t->p2m_mat.p, t->pf_Q.p, n, p2, Hf, Mq, t->pf_W.p);
         FM_CHECK_LAUNCH();
-        fmm_m2m4(ctx, t, H, H * Mq, Mq, t->pf_W.p);
+        fmm_m2m4(ctx, t, Hf, Hf * Mq, Mq, t->pf_W.p);
         if (comp) {
             const int rq = t->pc_rq;
             fmm_pair_gemm(s, t->pc_nptile, rq, t->pc_Vt.p, (size_t)rq * Mq, Mq, Mq, t->pf_W.p, Mq,
@@ -1423,8 +1493,8 @@ void poro_fmm_sum(fmddm_ctx *ctx, fmddm_tree *t, int H, const double *E, bool dr
                               t->pf_tile_op.p, t->pf_tile_beg.p, t->pf_tile_end.p, t->pf_psrc.p, t->pf_pdst.p,
                               t->pf_Z.p, Mq);
             else
-                fmm_pair_gemm(s, t->pf_ntile, Mq, t->pf_ops.p, (size_t)Mq * t->pf_H * Mq, t->pf_H * Mq, H * Mq,
-                              t->pf_W.p, H * Mq, t->pf_tile_op.p, t->pf_tile_beg.p, t->pf_tile_end.p, t->pf_psrc.p,
+                fmm_pair_gemm(s, t->pf_ntile, Mq, t->pf_ops.p, (size_t)Mq * t->pf_H * Mq, t->pf_H * Mq, Hf * Mq,
+                              t->pf_W.p, Hf * Mq, t->pf_tile_op.p, t->pf_tile_beg.p, t->pf_tile_end.p, t->pf_psrc.p,
                               t->pf_pdst.p, t->pf_Z.p, Mq);
             fmm_sum_pairs(s, t, t->pf_Z.p, Mq, Mq, t->pf_G.p, Mq);
         }
@@ -1433,7 +1503,7 @@ void poro_fmm_sum(fmddm_ctx *ctx, fmddm_tree *t, int H, const double *E, bool dr
     if (fused) {
         hipLaunchKernelGGL(k_pnear, dim3(t->nitem), dim3(PN), 0, s, t->nitem, t->it_leaf.p, t->it_s0.p,
                            t->it_s1.p, t->it_poff.p, t->it_coff.p, t->dleaves.p, t->cpbeg.p, t->cpend.p, t->noff.p,
-                           t->nbeg.p, t->npre.p, n, 0, 1, (const double *const *)t->pn_lhs_ptr.p, t->pf_D3.p,
+                           t->nbeg.p, t->npre.p, n, 0, 1, (const double *const *)t->pn_lhs_ptr.p, D3,
                            t->pf_near.p);
         FM_CHECK_LAUNCH();
         hipLaunchKernelGGL(k_pfinal, dim3(cdiv(n, 256)), dim3(256), 0, s, n, t->tleaf.p, t->dleaves.p, t->cpbeg.p,
@@ -1450,7 +1520,7 @@ void poro_fmm_sum(fmddm_ctx *ctx, fmddm_tree *t, int H, const double *E, bool dr
     if (stored) {
         hipLaunchKernelGGL(k_pnear, dim3(t->nitem), dim3(PN), 0, s, t->nitem, t->it_leaf.p, t->it_s0.p,
                            t->it_s1.p, t->it_poff.p, t->it_coff.p, t->dleaves.p, t->cpbeg.p, t->cpend.p, t->noff.p,
-                           t->nbeg.p, t->npre.p, n, jlo, Hc, (const double *const *)t->pn_ptr.p, t->pf_D3.p,
+                           t->nbeg.p, t->npre.p, n, jlo, Hc, (const double *const *)t->pn_ptr.p, D3,
                            t->pf_near.p);
         FM_CHECK_LAUNCH();
     }
@@ -1458,7 +1528,7 @@ void poro_fmm_sum(fmddm_ctx *ctx, fmddm_tree *t, int H, const double *E, bool dr
         hipLaunchKernelGGL(k_pp2p, dim3(t->nitem), dim3(PN), 0, s, t->nitem, t->it_leaf.p, t->it_s0.p, t->it_s1.p,
                            t->it_poff.p, t->dleaves.p, t->cpbeg.p, t->cpend.p, t->noff.p, t->nbeg.p, t->npre.p,
                            t->scx.p, t->scy.p, t->scb.p, t->ssb.p, t->sa.p, n, std::max(jlo, Hc), H,
-                           ctx->poro.dt, t->pf_D3.p, K, stored ? 1 : 0, t->pf_near.p);
+                           ctx->poro.dt, D3, K, stored ? 1 : 0, t->pf_near.p);
         FM_CHECK_LAUNCH();
     }
     const double *o2 = nullptr;
@@ -1569,7 +1639,10 @@ void poro_prepare(fmddm_ctx *ctx, fmddm_tree *t, int H)
     if (!ctx->poro_set) throw Error{FMDDM_EINVAL, "poroelastic parameters not set (fmddm_poro_set)"};
     upload_rules(ctx->device);
     if (ctx->poro.mode != FMDDM_APPLY_FMM) return;
-    poro_fmm_setup(ctx, t, std::max(H, 1));
+    // operators of the first two time levels, all H where the far field
+    // of the history sums cannot take the two-term form
+    poro_fmm_setup(ctx, t, std::min(std::max(H, 1), 2));
+    if (H > 2 && !(ctx->poro.exact_far_levels == 0 && far_affine(ctx, t, H))) poro_fmm_setup(ctx, t, H);
     if (near_lhs(ctx, t)) lhs_ops(ctx, t);
     if (H > 1) near_levels(ctx, t, H);
 }

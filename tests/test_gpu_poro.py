@@ -467,3 +467,47 @@ def test_poro_lhs_compressed_m2l(p):
     assert not np.array_equal(comp, dense)
     assert e_cd <= 1e-9, e_cd
     assert e_ce <= 1e-6, e_ce
+
+
+def test_poro_history_far_field_two_terms():
+    """History sums and lag products with the far field in two multipole
+    terms (the transient kernel affine in t outside the diffusion length)
+    against one term per time level (exact_far_levels = 1) and the exact
+    products, on the 5 x 200-element well cluster (cells of metres, a
+    diffusion length below 0.2 m after 9 steps).  The two forms differ by
+    e^-z terms with z >= 50 and by the rounding of the extrapolation
+    F(dt) + (j - 1)(F(2 dt) - F(dt)), a few ulp times the number of levels:
+    bar 1e-12 of each kind's largest entry.  With a permeability 1e5 times
+    larger the check refuses the two-term form, and the results are bitwise
+    the per-level ones."""
+    wl = W.well_cluster(n_frac=5, elems=200, half_length=20.0, spacing=10.0)
+    n3 = 3 * wl.n
+    rng = np.random.default_rng(8)
+    scale = np.tile([1e-4, 1e-4, 1e-10], wl.n)
+    D = dev(rng.standard_normal(n3) * scale)
+    hist = dev(np.concatenate([rng.standard_normal(n3) * scale for _ in range(8)]))
+    for perm, affine in ((MED["perm"], True), (1e5 * MED["perm"], False)):
+        res = {}
+        for mode, exact in ((F.FMDDM_APPLY_DIRECT, 0), (F.FMDDM_APPLY_FMM, 0), (F.FMDDM_APPLY_FMM, 1)):
+            prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=MED["E"], nu=MED["nu"], p=12, leaf=32)
+            try:
+                F.fmddm_poro_set(prob.ctx, MED["nuu"], MED["alpha"], perm, MED["visc"], DT, P0, mode=mode,
+                                 exact_far_levels=exact)
+                o = torch.zeros(n3, dtype=torch.float64, device="cuda")
+                F.fmddm_poro_apply(prob.ctx, prob.tree, 6, D, o)
+                r = torch.zeros(n3, dtype=torch.float64, device="cuda")
+                F.fmddm_add_history(prob.ctx, prob.tree, 9, hist, r)
+                res[(mode, exact)] = (o.cpu().numpy(), r.cpu().numpy())
+            finally:
+                prob.close()
+        two, per, ex = res[(F.FMDDM_APPLY_FMM, 0)], res[(F.FMDDM_APPLY_FMM, 1)], res[(F.FMDDM_APPLY_DIRECT, 0)]
+        for k, name in enumerate(("lag 6", "history of step 9")):
+            e_tp, e_te, e_pe = cmp(two[k], per[k]), cmp(two[k], ex[k]), cmp(per[k], ex[k])
+            print(f"perm {perm:g}, {name}: two-term vs per-level {e_tp:.2e}, vs exact {e_te:.2e} "
+                  f"(per-level vs exact {e_pe:.2e})")
+            assert e_te <= 1e-6, (name, e_te)
+            if affine:
+                assert e_tp <= 1e-12, (name, e_tp)
+                assert not np.array_equal(two[k], per[k])
+            else:
+                assert np.array_equal(two[k], per[k])
