@@ -680,6 +680,29 @@ __global__ void k_m2l_ops(int nop, const int *__restrict__ odx, const int *__res
 
 // All operators side by side, column-major M x (nop M):
 // fat[(o M + k) M + i] = K_o[i][k].
+// uniform random numbers in [-1, 1) from the splitmix64 finaliser of the
+// index (the range finder's test matrices; deterministic)
+__global__ void k_rf_rand(int64_t count, uint64_t seed, double *__restrict__ out)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(e + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    out[e] = (double)(z >> 11) * 0x1.0p-52 - 1.0;
+}
+
+// the lower triangle of the leading k x k block of an LQ factorisation
+// (leading dimension k)
+__global__ void k_rf_lower(int k, const double *__restrict__ lq, double *__restrict__ L)
+{
+    int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= k * k) return;
+    int j = e / k, i = e - j * k;
+    L[e] = i >= j ? lq[e] : 0.0;
+}
+
 __global__ void k_pack_fat(int nop, int M, int Mp, const double *__restrict__ ops, double *__restrict__ fat)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1179,6 +1202,74 @@ void m2l_lowp(hipStream_t s, fmddm_tree *t, const M2LOps &M, const TO *Vt, const
 
 }  // namespace
 
+// Leading left singular vectors of A (m x N, column-major, N >= m) down to
+// tol of the largest singular value, by a randomized range finder (Halko,
+// Martinsson and Tropp, 2011): Y = A Om for k uniform random columns,
+// Q = orth(Y) (Householder QR), B = Q^T A, B = L P (LQ), L = U_L S W^T
+// (one-sided Jacobi SVD); then A ~ (Q U_L) S (P^T W)^T.  k starts at 192
+// and doubles until the k-th singular value is a decade below tol (k = m:
+// exact).
+// U (m x m, leading dimension m) receives the vectors in its first k
+// columns, sv the k singular values (descending); returns the number above
+// tol (at least 1).  Runs on the handle's stream and waits for it.
+int range_basis(void *hv, hipStream_t s, int m, int N, const double *A, double tol, double *U,
+                std::vector<double> &sv)
+{
+    rocblas_handle h = (rocblas_handle)hv;
+    const size_t mm = (size_t)m * m;
+    DBuf<double> Om, Y, B, L, S, tau, UL, res;
+    DBuf<int> info, sweeps;
+    Om.alloc((size_t)N * std::min(m, 384));
+    Y.alloc(mm);
+    L.alloc(mm);
+    UL.alloc(mm);
+    S.alloc(m);
+    tau.alloc(m);
+    res.alloc(1);
+    info.alloc(1);
+    sweeps.alloc(1);
+    const double one = 1.0, zero = 0.0;
+    int k = std::min(m, 192);
+    for (;;) {
+        if ((size_t)N * k > Om.n) Om.alloc((size_t)N * k);
+        if ((size_t)k * N > B.n) B.alloc((size_t)k * N);
+        hipLaunchKernelGGL(k_rf_rand, dim3(cdiv((int64_t)N * k, 256)), dim3(256), 0, s, (int64_t)N * k,
+                           (uint64_t)k, Om.p);
+        FM_CHECK_LAUNCH();
+        bool ok = rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, m, k, N, &one, A, m, Om.p, N,
+                                &zero, Y.p, m) == rocblas_status_success;
+        ok = ok && rocsolver_dgeqrf(h, m, k, Y.p, m, tau.p) == rocblas_status_success;
+        ok = ok && rocsolver_dorgqr(h, m, k, k, Y.p, m, tau.p) == rocblas_status_success;
+        ok = ok && rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, k, N, m, &one, Y.p, m, A,
+                                 m, &zero, B.p, k) == rocblas_status_success;
+        ok = ok && rocsolver_dgelqf(h, k, N, B.p, k, tau.p) == rocblas_status_success;
+        if (!ok) throw Error{FMDDM_EDEVICE, "range finder: rocBLAS / rocSOLVER call failed"};
+        hipLaunchKernelGGL(k_rf_lower, dim3(cdiv((int64_t)k * k, 256)), dim3(256), 0, s, k, B.p, L.p);
+        FM_CHECK_LAUNCH();
+        if (rocsolver_dgesvdj(h, rocblas_svect_singular, rocblas_svect_none, k, k, L.p, k, 0.0, res.p, 100,
+                              sweeps.p, S.p, UL.p, k, nullptr, 1, info.p) != rocblas_status_success)
+            throw Error{FMDDM_EDEVICE, "range finder: rocsolver_dgesvdj failed"};
+        int hinfo = 0;
+        sv.assign(k, 0.0);
+        FM_HIP(hipMemcpyAsync(&hinfo, info.p, 4, hipMemcpyDeviceToHost, s));
+        FM_HIP(hipMemcpyAsync(sv.data(), S.p, (size_t)k * 8, hipMemcpyDeviceToHost, s));
+        FM_HIP(hipStreamSynchronize(s));
+        if (hinfo != 0) throw Error{FMDDM_EDEVICE, "range finder: the Jacobi SVD did not converge"};
+        if (k < m && sv[k - 1] > 0.1 * tol * sv[0]) {  // a decade of margin below the cut
+            k = std::min(m, 2 * k);
+            continue;
+        }
+        if (rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, m, k, k, &one, Y.p, m, UL.p, k, &zero,
+                          U, m) != rocblas_status_success)
+            throw Error{FMDDM_EDEVICE, "range finder: rocblas_dgemm failed"};
+        int r = 1;
+        for (int i = 0; i < k; ++i)
+            if (sv[0] > 0.0 && sv[i] > tol * sv[0]) r = i + 1;
+        FM_HIP(hipStreamSynchronize(s));
+        return r;
+    }
+}
+
 // Reduced-precision copies of the operator set, made once (on first use,
 // or up front where several threads share the set)
 void lowp_ops(fmddm_ctx *ctx, int prec)
@@ -1526,35 +1617,26 @@ void build_m2l_ops(fmddm_ctx *ctx)
                        ctx->cheb->xbar.p, p, M.Mp, 1.0, raw.p);
     FM_CHECK_LAUNCH();
     int m = M.M, ncol = nop * M.M;
-    DBuf<double> fat, S, U, E;
-    DBuf<int> info;
+    DBuf<double> fat, U;
     fat.alloc((size_t)m * ncol);
-    S.alloc(m);
     U.alloc((size_t)m * m);
-    E.alloc(m);
-    info.alloc(1);
     int64_t ftot = (int64_t)m * ncol;
     hipLaunchKernelGGL(k_pack_fat, dim3(cdiv(ftot, 256)), dim3(256), 0, s, nop, m, M.Mp, raw.p, fat.p);
     FM_CHECK_LAUNCH();
     rocblas_handle h;
     if (rocblas_create_handle(&h) != rocblas_status_success) throw Error{FMDDM_EDEVICE, "rocblas handle"};
     rocblas_set_stream(h, s);
-    rocblas_status st = rocsolver_dgesvd(h, rocblas_svect_singular, rocblas_svect_none, m, ncol, fat.p, m, S.p,
-                                         U.p, m, nullptr, 1, E.p, rocblas_outofplace, info.p);
-    FM_HIP(hipStreamSynchronize(s));
-    rocblas_destroy_handle(h);
-    if (st != rocblas_status_success) throw Error{FMDDM_EDEVICE, "rocsolver_dgesvd failed"};
-    int hinfo = 0;
-    std::vector<double> hs(m);
-    FM_HIP(hipMemcpy(&hinfo, info.p, 4, hipMemcpyDeviceToHost));
-    FM_HIP(hipMemcpy(hs.data(), S.p, m * 8, hipMemcpyDeviceToHost));
-    if (hinfo != 0) throw Error{FMDDM_EDEVICE, "SVD did not converge"};
+    std::vector<double> hs;
     int r = 0;
-    M.sv.resize(m);
-    for (int i = 0; i < m; ++i) {
-        M.sv[i] = hs[0] > 0 ? hs[i] / hs[0] : 0.0;
-        if (M.sv[i] > ctx->prm.m2l_tol) r = i + 1;
+    try {
+        r = range_basis(h, s, m, ncol, fat.p, ctx->prm.m2l_tol, U.p, hs);
+    } catch (...) {
+        rocblas_destroy_handle(h);
+        throw;
     }
+    rocblas_destroy_handle(h);
+    M.sv.assign(m, 0.0);
+    for (size_t i = 0; i < hs.size(); ++i) M.sv[i] = hs[0] > 0 ? hs[i] / hs[0] : 0.0;
     r = std::max(r, 1);
     M.r = r;
     M.rp = (r + 63) / 64 * 64;

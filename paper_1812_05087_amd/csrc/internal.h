@@ -449,6 +449,12 @@ void poro_rhs(fmddm_ctx *ctx, fmddm_tree *t, const double *pf, double SH, double
 void pc_setup_poro(fmddm_ctx *ctx, fmddm_tree *t);
 // fmm.hip: the reduced-precision copies of ctx's operator set for prec
 void lowp_ops(fmddm_ctx *ctx, int prec);
+// fmm.hip: leading left singular vectors of A (m x N, column-major) down to
+// tol of the largest singular value (randomized range finder); U (m x m)
+// gets them in its first columns, sv the sampled singular values; returns
+// the rank.  h is a rocblas_handle on stream s.
+int range_basis(void *h, hipStream_t s, int m, int N, const double *A, double tol, double *U,
+                std::vector<double> &sv);
 // builds now what a march of H steps would build on first use
 void poro_prepare(fmddm_ctx *ctx, fmddm_tree *t, int H);
 

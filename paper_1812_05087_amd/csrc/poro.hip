@@ -41,7 +41,6 @@
 #include "internal.h"
 
 #include <rocblas/rocblas.h>
-#include <rocsolver/rocsolver.h>
 
 #include <algorithm>
 #include <atomic>
@@ -562,28 +561,6 @@ __global__ void k_pc_pack(int nc, const int *__restrict__ combos, int m, int Mq,
     int o = col / m, j = col - o * m;
     const double *K = ops + (size_t)combos[o] * Mq * Mq;
     fat[e] = side == 0 ? K[(size_t)i * Mq + j] : K[(size_t)j * Mq + i];
-}
-
-// uniform random numbers in [-1, 1) from the splitmix64 finaliser of the
-// index (deterministic test matrices for the range finder)
-__global__ void k_pc_rand(int64_t count, uint64_t seed, double *__restrict__ out)
-{
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= count) return;
-    uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(e + 1);
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    z ^= z >> 31;
-    out[e] = (double)(z >> 11) * 0x1.0p-52 - 1.0;
-}
-
-// the lower triangle of the leading m x m block of an LQ factorisation
-__global__ void k_pc_lower(int m, const double *__restrict__ lq, double *__restrict__ L)
-{
-    int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= m * m) return;
-    int j = e / m, i = e - j * m;
-    L[e] = i >= j ? lq[e] : 0.0;
 }
 
 // Bases of level slot k from the left singular vectors (column-major m x m)
@@ -1213,8 +1190,9 @@ void lhs_ops(fmddm_ctx *ctx, fmddm_tree *t)
 // singular vectors of [K_o ...] (column space, U) and of [K_o^T ...] (row
 // space, V), cut where the singular values fall below m2l_tol of the
 // largest; then K_o ~ U C_o V^T with C_o = U^T K_o V.  The singular vectors
-// come from a randomized range finder on the m x (n m) packing (the ranks
-// are far below m: ~90 of 400 at p = 10, of 1024 at p = 16).  A product
+// come from the randomized range finder of the elastic operators
+// (range_basis) on the m x (n m) packing; the ranks are far below m (~90
+// of 400 at p = 10, of 1024 at p = 16).  A product
 // is then a projection per source cell, the rq x rq translations per
 // interaction pair, and an expansion per target cell.  Left uncompressed
 // (pc_ok = -1) when a level's rank would exceed 3/4 of m.
@@ -1247,68 +1225,14 @@ void lhs_compress(fmddm_ctx *ctx, fmddm_tree *t)
     rocblas_handle h = (rocblas_handle)ctx->blas;
     rocblas_set_stream(h, s);
     const size_t mm = (size_t)m * m;
-    const int64_t Nmax = (int64_t)maxn * m;
-    DBuf<double> fat, Om, Y, B, L, S, E, tau, UL, Uc, Ur;
-    DBuf<int> info, dcomb;
+    DBuf<double> fat, Uc, Ur;
+    DBuf<int> dcomb;
     fat.alloc(mm * maxn);
-    B.alloc(mm * maxn);
-    Om.alloc((size_t)Nmax * m);
-    Y.alloc(mm);
-    L.alloc(mm);
-    UL.alloc(mm);
-    S.alloc(m);
-    E.alloc(m);
-    tau.alloc(m);
     Uc.alloc(mm * nlev);
     Ur.alloc(mm * nlev);
-    info.alloc(1);
     dcomb.alloc(maxn);
     std::vector<int> rank(nlev, 1);
-    std::vector<double> hs(m);
-    const double one = 1.0, zero = 0.0;
-    // Left singular vectors of fat (m x N) down to tol of the largest
-    // singular value, by a randomized range finder: Y = fat Om for k random
-    // columns, Q = orth(Y), B = Q^T fat, and the SVD of B through its LQ
-    // factor (B = L P, L = U_L S W^T) gives fat ~ (Q U_L) S (P^T W)^T.  k
-    // doubles until the k-th singular value of B falls below tol (all m:
-    // exact).  Written to Uo (m x k, leading dimension m); returns the rank.
-    auto left_basis = [&](int N, double *Uo, uint64_t seed) {
-        int k = std::min(m, 192);
-        for (;;) {
-            hipLaunchKernelGGL(k_pc_rand, dim3(cdiv((int64_t)N * k, 256)), dim3(256), 0, s, (int64_t)N * k, seed,
-                               Om.p);
-            FM_CHECK_LAUNCH();
-            bool ok = rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, m, k, N, &one, fat.p, m,
-                                    Om.p, N, &zero, Y.p, m) == rocblas_status_success;
-            ok = ok && rocsolver_dgeqrf(h, m, k, Y.p, m, tau.p) == rocblas_status_success;
-            ok = ok && rocsolver_dorgqr(h, m, k, k, Y.p, m, tau.p) == rocblas_status_success;
-            ok = ok && rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, k, N, m, &one, Y.p, m,
-                                     fat.p, m, &zero, B.p, k) == rocblas_status_success;
-            ok = ok && rocsolver_dgelqf(h, k, N, B.p, k, tau.p) == rocblas_status_success;
-            if (!ok) throw Error{FMDDM_EDEVICE, "range finder of the poroelastic M2L operators failed"};
-            hipLaunchKernelGGL(k_pc_lower, dim3(cdiv((int64_t)k * k, 256)), dim3(256), 0, s, k, B.p, L.p);
-            FM_CHECK_LAUNCH();
-            if (rocsolver_dgesvd(h, rocblas_svect_all, rocblas_svect_none, k, k, L.p, k, S.p, UL.p, k, nullptr, 1,
-                                 E.p, rocblas_outofplace, info.p) != rocblas_status_success)
-                throw Error{FMDDM_EDEVICE, "rocsolver_dgesvd failed"};
-            int hinfo = 0;
-            FM_HIP(hipMemcpyAsync(&hinfo, info.p, 4, hipMemcpyDeviceToHost, s));
-            FM_HIP(hipMemcpyAsync(hs.data(), S.p, (size_t)k * 8, hipMemcpyDeviceToHost, s));
-            FM_HIP(hipStreamSynchronize(s));
-            if (hinfo != 0) throw Error{FMDDM_EDEVICE, "SVD of the poroelastic M2L operators did not converge"};
-            if (k < m && hs[k - 1] > tol * hs[0]) {
-                k = std::min(m, 2 * k);
-                continue;
-            }
-            if (rocblas_dgemm(h, rocblas_operation_none, rocblas_operation_none, m, k, k, &one, Y.p, m, UL.p, k,
-                              &zero, Uo, m) != rocblas_status_success)
-                throw Error{FMDDM_EDEVICE, "rocblas_dgemm failed"};
-            int r = 1;
-            for (int i = 0; i < k; ++i)
-                if (hs[0] > 0.0 && hs[i] > tol * hs[0]) r = i + 1;
-            return r;
-        }
-    };
+    std::vector<double> sv;
     for (int k = 0; k < nlev; ++k) {
         const int n = (int)bylev[k].size();
         FM_HIP(hipMemcpyAsync(dcomb.p, bylev[k].data(), n * 4, hipMemcpyHostToDevice, s));
@@ -1318,7 +1242,7 @@ void lhs_compress(fmddm_ctx *ctx, fmddm_tree *t)
                                t->pf_ops0.p, fat.p);
             FM_CHECK_LAUNCH();
             double *Uo = (side == 0 ? Uc.p : Ur.p) + (size_t)k * mm;
-            rank[k] = std::max(rank[k], left_basis(n * m, Uo, 2 * (uint64_t)k + side));
+            rank[k] = std::max(rank[k], range_basis(h, s, m, n * m, fat.p, tol, Uo, sv));
         }
     }
     int rmax = *std::max_element(rank.begin(), rank.end());
