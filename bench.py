@@ -265,7 +265,7 @@ def serving_leg(F, W, count, slots, load, poro=True, alone_sample=128):
     }
 
 
-def history_run(F, W, elems, steps, mode, p, near_cache=0):
+def history_run(F, W, elems, steps, mode, p, near_cache=0, m2l=0):
     """One left-hand-side product and the history sum of step `steps` on the
     horizontal-well cluster (5 fractures of `elems` 0.2 m elements, 10 m
     apart; Biot constants of the well example, 60 s steps), timed after a
@@ -276,7 +276,8 @@ def history_run(F, W, elems, steps, mode, p, near_cache=0):
     wl = W.well_cluster(n_frac=5, elems=elems, half_length=0.1 * elems, spacing=10.0)
     prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=20e9, nu=0.2, p=p, leaf=32)
     try:
-        F.fmddm_poro_set(prob.ctx, 0.35, 0.8, 1e-18, 1e-3, 60.0, 48.26e6, mode=mode, near_cache_bytes=near_cache)
+        F.fmddm_poro_set(prob.ctx, 0.35, 0.8, 1e-18, 1e-3, 60.0, 48.26e6, mode=mode, near_cache_bytes=near_cache,
+                         m2l=m2l)
         n3 = 3 * prob.n
         rng = np.random.default_rng(3)
         scale = np.tile([1e-4, 1e-4, 1e-10], prob.n)
@@ -326,6 +327,11 @@ def history_leg(F, W, elems, steps, p=16):
                     "exact": {"lhs_product_ms": tl3 * 1e3, "history_ms": th3 * 1e3},
                     "fmm_err_vs_exact": {"lhs": rel(o_f, o_e), "history": rel(r_f, r_e)}}
     out["fmm_full"]["stored_vs_on_the_fly"] = {"lhs": rel(o_c, o_0), "history": rel(r_c, r_0)}
+    _, tlc, _, o_s, _, tfc = history_run(F, W, elems, steps, F.FMDDM_APPLY_FMM, p, m2l=F.FMDDM_M2L_SVD)
+    out["fmm_full"]["lhs_m2l_compressed"] = {
+        "lhs_product_ms": tlc * 1e3, "first_pass_ms": tfc * 1e3, "diff_vs_uncompressed": rel(o_s, o_c),
+        "note": "left-hand side M2L compressed per tree level (m2l_tol 1e-10); the first pass includes the "
+                "range finder and the compressed operators"}
     return out
 
 
@@ -460,7 +466,7 @@ def precision_leg(F, W, steps, tune, leaf, p, solve_tol=1e-8, target_err=1e-6, s
     return out
 
 
-def march_run(F, W, elems, steps, p, restart, precond, coarse, tol, keep=(), mode=None):
+def march_run(F, W, elems, steps, p, restart, precond, coarse, tol, keep=(), mode=None, m2l=1):
     """One poroelastic time march (the horizontal-well example's shape,
     Section 5.2.1): 5 fractures of `elems` 0.2 m elements 10 m apart,
     `steps` steps of 60 s, every step's history sum and GMRES solve (the
@@ -474,7 +480,7 @@ def march_run(F, W, elems, steps, p, restart, precond, coarse, tol, keep=(), mod
     prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=20e9, nu=0.2, p=p, leaf=32, m2l=1, m2l_tol=1e-10, tol=tol,
                      restart=restart, maxit=40000, precond=precond, coarse_aggregates=coarse)
     F.fmddm_poro_set(prob.ctx, 0.35, 0.8, 1e-18, 1e-3, 60.0, 48.26e6,
-                     mode=F.FMDDM_APPLY_FMM if mode is None else mode)
+                     mode=F.FMDDM_APPLY_FMM if mode is None else mode, m2l=m2l)
     b0 = torch.zeros(n3, dtype=torch.float64, device="cuda")
     F.fmddm_poro_rhs(prob.ctx, prob.tree, torch.as_tensor(wl.pressure).cuda(), wl.SH, wl.Sh, b0)
     hist = torch.zeros(steps * n3, dtype=torch.float64, device="cuda")
@@ -516,9 +522,13 @@ def march_run(F, W, elems, steps, p, restart, precond, coarse, tol, keep=(), mod
                   flush=True)
     total = time.perf_counter() - t_all
     Dm = D.cpu().numpy().reshape(-1, 3)
+    tinfo = F.fmddm_tree_get_info(prob.ctx, prob.tree)
+    rank = tinfo["poro_m2l_rank"]
     prob.close()
     return {"total_s": total, "history_s": th, "solve_s": tsv, "gmres_products": its, "per_step": per_step,
-            "max_step_relres": worst, "last": Dm, "kept": kept, "n": wl.n, "setup_s": t_setup, "step_s": step_s}
+            "max_step_relres": worst, "last": Dm, "kept": kept, "n": wl.n, "setup_s": t_setup, "step_s": step_s,
+            "lhs_m2l_rank": rank,
+            "tree": {k: tinfo[k] for k in ("ncell", "nleaf", "nlevel", "nV", "near_pairs")}}
 
 
 def middle_ratio(Dm, elems):
@@ -541,6 +551,8 @@ def march_leg(F, W, elems, steps, p=16, restart=100, precond=2, coarse=0, ref_to
     keep = tuple(sorted({1, min(ref_steps, steps), steps}))
     run = march_run(F, W, elems, steps, p, restart, precond, coarse, 1e-6, keep)
     out = {"workload": f"well cluster 5 x {elems} elements (N={run['n']}), {steps} steps of 60 s", "p": p,
+           "lhs_m2l": f"compressed per tree level (m2l_tol 1e-10), largest rank {run['lhs_m2l_rank']} of {4 * p * p}",
+           "tree": run["tree"],
            "restart": restart, "precond": {1: "block-Jacobi", 2: "two-level"}[precond], "tol": 1e-6,
            "gmres_products_per_step": run["per_step"], "total_s": run["total_s"], "history_s": run["history_s"],
            "solve_s": run["solve_s"], "gmres_products": run["gmres_products"],
@@ -554,14 +566,18 @@ def march_leg(F, W, elems, steps, p=16, restart=100, precond=2, coarse=0, ref_to
     if ref_tol and ref_steps:
         rs = min(ref_steps, steps)
         k2 = tuple(sorted({1, rs}))
-        ref = march_run(F, W, elems, rs, p, restart, precond, coarse, ref_tol, k2)
+        ref = march_run(F, W, elems, rs, p, restart, precond, coarse, ref_tol, k2, m2l=0)
         acc = {f"step_{h}": diff(run["kept"][h], ref["kept"][h]) for h in k2}
         out["accuracy_vs_reference"] = {
-            "reference": f"the same march (p = {p}) at GMRES tol {ref_tol:g}, {rs} steps",
+            "reference": f"the same march (p = {p}, uncompressed M2L) at GMRES tol {ref_tol:g}, {rs} steps",
             "reference_total_s": ref["total_s"], "reference_gmres_products": ref["gmres_products"],
             "max_diff_over_max_ref": acc,
             f"middle_fracture_max_shear_over_opening_step_{rs}": middle_ratio(run["kept"][rs], elems),
             f"reference_middle_fracture_max_shear_over_opening_step_{rs}": middle_ratio(ref["kept"][rs], elems)}
+        unc = march_run(F, W, elems, rs, p, restart, precond, coarse, 1e-6, k2, m2l=0)
+        out["uncompressed_lhs_m2l_first_steps"] = {
+            "steps": rs, "total_s": unc["total_s"], "solve_s": unc["solve_s"], "gmres_products": unc["gmres_products"],
+            "compressed": {"total_s": float(sum(run["step_s"][:rs])), "gmres_products": sum(run["per_step"][:rs])}}
         # the history-only variant (Section 2: the earlier method applied
         # the FMM to the history sum only): dense exact left-hand side,
         # multipole history, same steps and tolerance

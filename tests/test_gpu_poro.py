@@ -237,16 +237,19 @@ def test_poro_block_jacobi(mode):
             assert 2 * res[pc][1][h] <= res[F.FMDDM_PRECOND_NONE][1][h], res
 
 
-def test_poro_full_size_sampled_rows():
-    """N = 20000 (five fractures of 4000 0.2 m elements, 10 m apart), the
-    multipole configuration the bench times (p = 10, leaf 32): the
-    left-hand-side product and a 4-level history sum against the oracle's
-    exact rows for 20 sampled receivers; bar 1e-6 of the largest entry of
-    each response kind, as for the smaller multipole test."""
+@pytest.mark.parametrize("p,m2l,nrow", [(10, 0, 20), (16, 1, 40)])
+def test_poro_full_size_sampled_rows(p, m2l, nrow):
+    """N = 20000 (five fractures of 4000 0.2 m elements, 10 m apart) in the
+    serving configuration (p = 10, leaf 32) and the march's (p = 16, the
+    left-hand side's M2L compressed per tree level; the 4-level history's
+    far field in two terms): the left-hand-side product and the history
+    sum against the oracle's exact rows for 20 / 40 sampled receivers; bar
+    1e-6 of the largest entry of each response kind, as for the smaller
+    multipole test."""
     wl = W.well_cluster(n_frac=5, elems=4000, half_length=400.0, spacing=10.0)
     g = O.Geometry.of(wl)
     po = O.Poro(**MED)
-    rows = np.random.default_rng(2).choice(g.n, 20, replace=False)
+    rows = np.random.default_rng(2).choice(g.n, nrow, replace=False)
     idx = np.stack([3 * rows, 3 * rows + 1, 3 * rows + 2], 1).reshape(-1)
     rng = np.random.default_rng(5)
     scale = np.tile([1e-4, 1e-4, 1e-10], g.n)
@@ -254,16 +257,17 @@ def test_poro_full_size_sampled_rows():
     h = 4
     Dh = [rng.standard_normal(3 * g.n) * scale for _ in range(h - 1)]
     b = rng.standard_normal(3 * g.n) * 1e6
-    prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=MED["E"], nu=MED["nu"], p=10, leaf=32)
+    prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=MED["E"], nu=MED["nu"], p=p, leaf=32, m2l_tol=1e-10)
     try:
         F.fmddm_poro_set(prob.ctx, MED["nuu"], MED["alpha"], MED["perm"], MED["visc"], DT, P0,
-                         mode=F.FMDDM_APPLY_FMM)
+                         mode=F.FMDDM_APPLY_FMM, m2l=m2l)
         out = torch.zeros(3 * g.n, dtype=torch.float64, device="cuda")
         F.fmddm_poro_apply(prob.ctx, prob.tree, 0, dev(D), out)
         rhs = dev(b)
         F.fmddm_add_history(prob.ctx, prob.tree, h, dev(np.concatenate(Dh)), rhs)
         y0 = out.cpu().numpy()[idx]
         yh = rhs.cpu().numpy()[idx]
+        assert (F.fmddm_tree_get_info(prob.ctx, prob.tree)["poro_m2l_rank"] > 0) == (m2l == 1)
     finally:
         prob.close()
     ref0 = O.poro_matrix_rows(g, po, DT, 0, rows) @ D
@@ -271,7 +275,7 @@ def test_poro_full_size_sampled_rows():
     for k in range(1, h):
         refh -= O.poro_matrix_rows(g, po, DT, h - k, rows) @ Dh[k - 1]
     e0, eh = cmp(y0, ref0), cmp(yh - b[idx], refh - b[idx])
-    print(f"N=20000 poro FMM vs oracle rows: lhs {e0:.2e}, history {eh:.2e}")
+    print(f"N=20000 poro FMM (p = {p}, m2l {m2l}) vs oracle rows: lhs {e0:.2e}, history {eh:.2e}")
     assert e0 <= 1e-6 and eh <= 1e-6, (e0, eh)
 
 
