@@ -791,34 +791,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 // Near field from the stored blocks of time levels j0 .. j1-1 (lv[j] the
 // level's blocks): partial (sxx, syy, sxy, p) per target point of every
 // item, in the layout of k_pp2p, which adds the levels beyond the store.
-__global__ __launch_bounds__(PN) void k_pnear(int nitem, const int *__restrict__ it_leaf,
-                                              const int *__restrict__ it_s0, const int *__restrict__ it_s1,
-                                              const int *__restrict__ it_poff, const int64_t *__restrict__ it_coff,
-                                              const int *__restrict__ leaves, const int *__restrict__ pbeg,
-                                              const int *__restrict__ pend, const int *__restrict__ noff,
-                                              const int *__restrict__ nbeg, const int *__restrict__ npre, int n,
-                                              int j0, int j1, const double *const *__restrict__ lv,
-                                              const double *__restrict__ D3, double *__restrict__ part)
+// A stream of 96 bytes per pair and level: 256 lanes per item, tpt =
+// 256 / (leaf points) lanes per point (all lanes busy for any leaf size,
+// two sources' coefficients in flight per lane), sources from the
+// flattened per-leaf list; a point's tpt partials are summed in LDS in
+// lane order.
+constexpr int PNB = 256;
+__global__ __launch_bounds__(PNB) void k_pnear(int nitem, const int *__restrict__ it_leaf,
+                                               const int *__restrict__ it_s0, const int *__restrict__ it_s1,
+                                               const int *__restrict__ it_poff, const int64_t *__restrict__ it_coff,
+                                               const int *__restrict__ leaves, const int *__restrict__ pbeg,
+                                               const int *__restrict__ pend, const int *__restrict__ nfoff,
+                                               const int *__restrict__ nflat, int n, int j0, int j1,
+                                               const double *const *__restrict__ lv, const double *__restrict__ D3,
+                                               double *__restrict__ part)
 {
-    int k = blockIdx.x;
-    int li = it_leaf[k], s0 = it_s0[k], ns = it_s1[k] - s0;
-    int c = leaves[li];
-    int tb = pbeg[c], nt = pend[c] - tb;
-    int nb = noff[li], nn = noff[li + 1] - nb;
-    int tpt = 1;
-    while (tpt < 16 && tpt * 2 * nt <= PN) tpt *= 2;
-    int tpg = PN / tpt, sub = threadIdx.x & (tpt - 1);
+    __shared__ double s_red[4 * PNB];
+    const int k = blockIdx.x, tid = threadIdx.x;
+    const int li = it_leaf[k], s0 = it_s0[k], ns = it_s1[k] - s0;
+    const int c = leaves[li];
+    const int nt = pend[c] - pbeg[c];
+    const int *src = nflat + nfoff[li] + s0;
+    const int tpt = nt >= PNB ? 1 : min(16, PNB / nt);
+    const int tpg = PNB / tpt, g = tid / tpt, sub = tid - g * tpt;
     const int64_t base = 12 * it_coff[k];
     double *pk = part + 4 * (size_t)it_poff[k];
     for (int t0 = 0; t0 < nt; t0 += tpg) {
-        int i = t0 + (int)threadIdx.x / tpt;
-        bool act = i < nt;
+        const int i = t0 + g;
+        const bool act = g < tpg && i < nt;
         double o[4] = {0.0, 0.0, 0.0, 0.0};
         if (act) {
-            int r = 0;
+#pragma unroll 2
             for (int v = sub; v < ns; v += tpt) {
-                while (r + 1 < nn && npre[nb + r + 1] <= s0 + v) ++r;  // v ascends
-                int jsrc = nbeg[nb + r] + (s0 + v - npre[nb + r]);
+                const int jsrc = src[v];
                 const int64_t off = base + (int64_t)12 * v * nt + i;
                 for (int j = j0; j < j1; ++j) {
                     const double *d = D3 + ((size_t)j * n + jsrc) * 3;
@@ -830,12 +835,20 @@ __global__ __launch_bounds__(PN) void k_pnear(int nitem, const int *__restrict__
                 }
             }
         }
-        for (int w = 1; w < tpt; w <<= 1)
-            for (int cc = 0; cc < 4; ++cc) o[cc] += __shfl_xor(o[cc], w);
-        if (act && sub == 0) {
-            double *pp = pk + 4 * (size_t)i;
-            for (int cc = 0; cc < 4; ++cc) pp[cc] = o[cc];
+        if (tpt == 1) {
+            if (act)
+                for (int cc = 0; cc < 4; ++cc) pk[4 * (size_t)i + cc] = o[cc];
+            continue;
         }
+        for (int cc = 0; cc < 4; ++cc) s_red[cc * PNB + tid] = o[cc];
+        __syncthreads();
+        if (act && sub == 0)
+            for (int cc = 0; cc < 4; ++cc) {
+                double r = 0.0;
+                for (int u = tid; u < tid + tpt; ++u) r += s_red[cc * PNB + u];
+                pk[4 * (size_t)i + cc] = r;
+            }
+        __syncthreads();
     }
 }
 
@@ -1425,10 +1438,9 @@ void poro_fmm_sum(fmddm_ctx *ctx, fmddm_tree *t, int H, const double *E, bool dr
         fmm_l2p4(ctx, t, t->pf_G.p, Mq, t->pf_far.p);
     }
     if (fused) {
-        hipLaunchKernelGGL(k_pnear, dim3(t->nitem), dim3(PN), 0, s, t->nitem, t->it_leaf.p, t->it_s0.p,
-                           t->it_s1.p, t->it_poff.p, t->it_coff.p, t->dleaves.p, t->cpbeg.p, t->cpend.p, t->noff.p,
-                           t->nbeg.p, t->npre.p, n, 0, 1, (const double *const *)t->pn_lhs_ptr.p, D3,
-                           t->pf_near.p);
+        hipLaunchKernelGGL(k_pnear, dim3(t->nitem), dim3(PNB), 0, s, t->nitem, t->it_leaf.p, t->it_s0.p,
+                           t->it_s1.p, t->it_poff.p, t->it_coff.p, t->dleaves.p, t->cpbeg.p, t->cpend.p, t->nfoff.p,
+                           t->nflat.p, n, 0, 1, (const double *const *)t->pn_lhs_ptr.p, D3, t->pf_near.p);
         FM_CHECK_LAUNCH();
         hipLaunchKernelGGL(k_pfinal, dim3(cdiv(n, 256)), dim3(256), 0, s, n, t->tleaf.p, t->dleaves.p, t->cpbeg.p,
                            t->clevel.p, t->lk_off.p, t->it_poff.p, t->pf_near.p,
@@ -1442,10 +1454,9 @@ void poro_fmm_sum(fmddm_ctx *ctx, fmddm_tree *t, int H, const double *E, bool dr
     const int Hc = near_levels(ctx, t, H);
     const bool stored = Hc > jlo;
     if (stored) {
-        hipLaunchKernelGGL(k_pnear, dim3(t->nitem), dim3(PN), 0, s, t->nitem, t->it_leaf.p, t->it_s0.p,
-                           t->it_s1.p, t->it_poff.p, t->it_coff.p, t->dleaves.p, t->cpbeg.p, t->cpend.p, t->noff.p,
-                           t->nbeg.p, t->npre.p, n, jlo, Hc, (const double *const *)t->pn_ptr.p, D3,
-                           t->pf_near.p);
+        hipLaunchKernelGGL(k_pnear, dim3(t->nitem), dim3(PNB), 0, s, t->nitem, t->it_leaf.p, t->it_s0.p,
+                           t->it_s1.p, t->it_poff.p, t->it_coff.p, t->dleaves.p, t->cpbeg.p, t->cpend.p, t->nfoff.p,
+                           t->nflat.p, n, jlo, Hc, (const double *const *)t->pn_ptr.p, D3, t->pf_near.p);
         FM_CHECK_LAUNCH();
     }
     if (Hc < H || !stored) {
