@@ -30,6 +30,9 @@ PEAK = {  # MI355X published peaks
     "hbm_GBps": 8000.0,
     "fp64_mfma_TFLOPs": 78.6,
     "fp64_vector_TFLOPs": 78.6,
+    "fp32_vector_TFLOPs": 157.3,   # packed; the kernels here issue non-packed FP32 (half of it)
+    "fp32_mfma_TFLOPs": 157.3,
+    "bf16_mfma_TFLOPs": 2500.0,    # dense
 }
 # Algorithmic flop count of one near-field element pair (constant-element
 # stress, rotation to the global frame, accumulation): +,-,* count 1, a
@@ -391,6 +394,24 @@ def precision_leg(F, W, steps, tune, leaf, p, solve_tol=1e-8, target_err=1e-6, s
         ph = F.fmddm_profile_read(prob.ctx)
         F.fmddm_profile(prob.ctx, 0)
         r["phase_ms"] = {k: v[0] / 3 for k, v in ph.items() if v[1] > 0}   # per product
+        # the near field and the M2L pair products against the peak of the
+        # arithmetic they run in (work by the method's own count)
+        ti = F.fmddm_tree_get_info(prob.ctx, prob.tree)
+        rk = ti["m2l_rank"]
+        alu_peak = PEAK["fp64_vector_TFLOPs"] if name == "fp64" else PEAK["fp32_vector_TFLOPs"]
+        mf_peak = {"fp64": PEAK["fp64_mfma_TFLOPs"], "fp32": PEAK["fp32_mfma_TFLOPs"],
+                   "bf16": PEAK["bf16_mfma_TFLOPs"]}[name]
+        rl = {}
+        for ph_name, flop, peak, what in (
+                ("p2p", float(FLOP_PER_PAIR) * ti["near_pairs"], alu_peak,
+                 "FP64 vector" if name == "fp64" else "FP32 vector (published, packed)"),
+                ("m2l", 2.0 * rk * rk * ti["nV"], mf_peak, f"{name.upper()} MFMA")):
+            ms = r["phase_ms"].get(ph_name, 0.0)
+            if ms > 0:
+                tf = flop / (ms * 1e-3) / 1e12
+                rl[ph_name] = {"achieved_TFLOPs": tf, "peak_TFLOPs": peak, "frac": tf / peak, "peak_kind": what,
+                               "work_flop": flop, "ms": ms}
+        r["roofline"] = rl
         y[name] = o.cpu().numpy()
         if not solves:              # products only (profiling runs)
             prob.close()
@@ -549,6 +570,7 @@ def march_leg(F, W, elems, steps, p=16, restart=100, precond=2, coarse=0, ref_to
     reference value; and the middle fracture's shear over the opening,
     zero by symmetry (Section 5.2.1)."""
     keep = tuple(sorted({1, min(ref_steps, steps), steps}))
+    red = march_run(F, W, 40, 10, p, restart, precond, coarse, 1e-6, m2l=0)
     run = march_run(F, W, elems, steps, p, restart, precond, coarse, 1e-6, keep)
     out = {"workload": f"well cluster 5 x {elems} elements (N={run['n']}), {steps} steps of 60 s", "p": p,
            "lhs_m2l": f"compressed per tree level (m2l_tol 1e-10), largest rank {run['lhs_m2l_rank']} of {4 * p * p}",
@@ -557,7 +579,9 @@ def march_leg(F, W, elems, steps, p=16, restart=100, precond=2, coarse=0, ref_to
            "gmres_products_per_step": run["per_step"], "total_s": run["total_s"], "history_s": run["history_s"],
            "solve_s": run["solve_s"], "gmres_products": run["gmres_products"],
            "max_step_relres": run["max_step_relres"],
-           "middle_fracture_max_shear_over_opening": middle_ratio(run["last"], elems)}
+           "middle_fracture_max_shear_over_opening": middle_ratio(run["last"], elems),
+           "reduced": {"workload": "5 x 40 elements (N=200), 10 steps (the oracle's C3 run; cpu_baseline "
+                                   "c3_reduced_march)", "total_s": red["total_s"], "gmres_products": red["gmres_products"]}}
 
     def diff(a, r):
         return {name: float(np.abs(a[:, k] - r[:, k]).max() / np.abs(r[:, k]).max())
@@ -696,13 +720,15 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_baseline(wl, D, seconds, fmm_p=6):
+def cpu_baseline(wl, D, seconds, fmm_p=6, others=True):
     """The oracle on the host: its exact on-the-fly product of the whole
     workload on all host cores, repeated for about `seconds` of wall time
     (the reported value); the same product on one thread over 1000 rows
     (scaled to whole products); and the oracle's level-by-level FMM at
     p = fmm_p (the paper's six Chebyshev nodes, Section 5.2) on one
-    thread."""
+    thread; with `others`, 1000 exact rows of the N = 200 000 workload and
+    the whole poroelastic march at 5 x 40 elements, 10 steps (C3 reduced),
+    on all host cores."""
     import oracle as O
     g = O.Geometry.of(wl)
     O.direct_matvec_rows(g, D, [0])  # load the library
@@ -729,7 +755,32 @@ def cpu_baseline(wl, D, seconds, fmm_p=6):
     finally:
         O.set_num_threads(prev)
     ms = np.array(times) * 1e3
-    return {"value": reps / dt, "unit": "matvecs/s", "cores": cores, "kind": "oracle",
+    extra = {}
+    if others:
+        import workloads as W
+        # N = 200 000 (C4): exact rows on all host cores, scaled to products
+        w4 = W.c4()
+        g4 = O.Geometry.of(w4)
+        D4 = W.random_vector(9, g4.n)
+        rows4 = np.random.default_rng(1).choice(g4.n, 1000, replace=False)
+        O.direct_matvec_rows(g4, D4, rows4[:2])
+        t1 = time.perf_counter()
+        O.direct_matvec_rows(g4, D4, rows4)
+        t4 = time.perf_counter() - t1
+        extra["c4_exact_rows"] = {"rows": len(rows4), "seconds": t4, "threads": cores,
+                                  "exact_matvecs_per_s_scaled": len(rows4) / g4.n / t4,
+                                  "sample": f"1000 random rows of the N = {g4.n} exact product"}
+        # C3 at reduced size: the whole poroelastic march, 5 x 40 elements,
+        # 10 steps of 60 s (dense exact operators and LU per step)
+        wl3 = W.well_cluster(n_frac=5, elems=40, half_length=4.0, spacing=10.0)
+        g3 = O.Geometry.of(wl3)
+        po = O.Poro(E=20e9, nu=0.2, nuu=0.35, alpha=0.8, perm=1e-18, visc=1e-3)
+        t1 = time.perf_counter()
+        O.poro_march(g3, po, 60.0, 10, wl3.pressure, 48.26e6, wl3.SH, wl3.Sh)
+        t3 = time.perf_counter() - t1
+        extra["c3_reduced_march"] = {"n": g3.n, "steps": 10, "seconds": t3, "threads": cores,
+                                     "sample": "oracle poroelastic march, well cluster 5 x 40 elements, 10 steps"}
+    return {"value": reps / dt, "unit": "matvecs/s", "cores": cores, "kind": "oracle", **extra,
             "cpu_model": cpu_model(),
             "sample": f"oracle exact on-the-fly product of the full workload (N={g.n}) on {cores} threads, "
                       f"{reps} products in {dt:.1f} s wall",
