@@ -274,23 +274,28 @@ __global__ __launch_bounds__(XT) void k_m2m(int nchain, const int *__restrict__ 
                 by[sy][ks][nt] = (n < P && k < P) ? S[sy * P2 + n * P + k] : 0.0;
             }
     const int i0 = coff ? coff[b] : b, i1 = coff ? coff[b + 1] : b + 1;
+    // child ch's weights as the x pass's B operands: bw[ks][nt] =
+    // W_ch[l' = 4 ks + lk][(c, m) = 16 nt + li]
+    double bw[KS][NT];
+    auto load_child = [&](int ch) {
+        const double *Wd = W + (size_t)ch * ldw;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const int k = 4 * ks + lk, col = 16 * nt + li, c = col / P, m = col - c * P;
+                bw[ks][nt] = (k < P && col < R) ? Wd[c * P2 + k * P + m] : 0.0;
+            }
+    };
+    int ch = i0 < i1 ? item[5 * i0 + 1 + wave] : -1;
+    if (ch >= 0) load_child(ch);
     for (int it = i0; it < i1; ++it) {
         const int A = item[5 * it];
         // x pass, wave d on child d: X_d = S_{d&1} . W_d with W_d as the
         // P x R matrix [l'][(c, m)]
         {
-            const int ch = item[5 * it + 1 + wave];
             double *Xd = X[wave];
             if (ch >= 0) {
-                const double *Wd = W + (size_t)ch * ldw;
-                double bw[KS][NT];
-#pragma unroll
-                for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-                    for (int nt = 0; nt < NT; ++nt) {
-                        const int k = 4 * ks + lk, col = 16 * nt + li, c = col / P, m = col - c * P;
-                        bw[ks][nt] = (k < P && col < R) ? Wd[c * P2 + k * P + m] : 0.0;
-                    }
                 d4 acc[MT][NT];
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt)
@@ -317,6 +322,11 @@ __global__ __launch_bounds__(XT) void k_m2m(int nchain, const int *__restrict__ 
                 for (int e = lane; e < R * RS; e += 64) Xd[e] = 0.0;
             }
         }
+        // the next step's child is fetched while this step's y pass runs,
+        // unless it is this step's parent (written below)
+        const int chn = it + 1 < i1 ? item[5 * (it + 1) + 1 + wave] : -1;
+        const bool early = chn >= 0 && chn != A;
+        if (early) load_child(chn);
         __syncthreads();
         // y pass: W_A = sum_sy (X_{0,sy} + X_{1,sy}) . S_sy^T, wave w on row
         // tiles w, w + 4, ... of the R x P result
@@ -355,6 +365,8 @@ __global__ __launch_bounds__(XT) void k_m2m(int nchain, const int *__restrict__ 
         // the parent's weights are written before a later parent of the
         // chain reads them, and X is free again
         __syncthreads();
+        if (chn >= 0 && !early) load_child(chn);
+        ch = chn;
     }
 }
 
