@@ -294,6 +294,8 @@ struct fmddm_tree {
     // left-hand side F(dt) in one multipole pass: the first level's near
     // blocks and M2L operators with the drained elastic part added
     fmddm::DBuf<double> pn_lhs, pf_ops0;
+    fmddm::DBuf<int64_t> pn_close;                 // near pairs within the composite rule's reach
+    fmddm::DBuf<unsigned long long> pn_ccount;     // their count
     // the left-hand side's M2L compressed per tree level (poro m2l = SVD):
     // level slot k has row-space basis Vt (rq x Mq), column-space basis U
     // (Mq x rq); each combination's operator becomes C (rq x rq)

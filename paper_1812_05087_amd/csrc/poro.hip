@@ -263,9 +263,17 @@ __constant__ double c_gl_t[QN], c_gl_w[QN], c_gl8_t[8], c_gl8_w[8];
 // Quadrature of a function along the element (cx, cy, cb, sb, a) seen from
 // the receiver (X, Y) at time t: f(x, y, w) for every point, with (x, y)
 // the receiver's offset from the point and w the weight per unit length.
-template <class Fn>
-__device__ __forceinline__ void elem_quad(const PoroK &K, double X, double Y, double cx, double cy, double cb,
-                                          double sb, double a, double t, Fn &&f)
+// Where the receiver lies for the element's quadrature: xl its coordinate
+// along the element, ell the diffusion length; far: beyond 8 x the larger
+// of the element's length and ell (one 8-point rule), else the composite
+// graded rule on both sides of the foot xl.
+struct QuadGeom {
+    double xl, ell;
+    bool far;
+};
+
+__device__ __forceinline__ QuadGeom quad_geom(const PoroK &K, double X, double Y, double cx, double cy, double cb,
+                                              double sb, double a, double t)
 {
     double dx = X - cx, dy = Y - cy;
     double xl = dx * cb + dy * sb, yl = dy * cb - dx * sb;
@@ -273,7 +281,23 @@ __device__ __forceinline__ void elem_quad(const PoroK &K, double X, double Y, do
     double far = 8.0 * fmax(2.0 * a, ell);
     double ox = fabs(xl) - a;
     double d2 = yl * yl + (ox > 0.0 ? ox * ox : 0.0);
-    if (d2 >= far * far) {
+    return QuadGeom{xl, ell, d2 >= far * far};
+}
+
+// panels of the composite rule on side `side` (0: from the foot towards
+// -a, 1: towards +a) of the length L it covers
+__device__ __forceinline__ int quad_panels(double L, double ell)
+{
+    return L <= 0.0 ? 0 : min(4 + (int)ceil(2.0 * L / ell), 400);
+}
+
+template <class Fn>
+__device__ __forceinline__ void elem_quad(const PoroK &K, double X, double Y, double cx, double cy, double cb,
+                                          double sb, double a, double t, Fn &&f)
+{
+    const QuadGeom Q = quad_geom(K, X, Y, cx, cy, cb, sb, a, t);
+    const double xl = Q.xl, ell = Q.ell;
+    if (Q.far) {
         for (int g = 0; g < 8; ++g) {
             double s = a * c_gl8_t[g];
             f(X - (cx + s * cb), Y - (cy + s * sb), a * c_gl8_w[g]);
@@ -283,9 +307,8 @@ __device__ __forceinline__ void elem_quad(const PoroK &K, double X, double Y, do
     double s0 = fmin(a, fmax(-a, xl));
     for (int side = 0; side < 2; ++side) {
         double L = side ? a - s0 : s0 + a;
-        if (L <= 0.0) continue;
-        int np = 4 + (int)ceil(2.0 * L / ell);
-        np = min(np, 400);
+        const int np = quad_panels(L, ell);
+        if (np == 0) continue;
         double du = 1.0 / np;
         for (int pn = 0; pn < np; ++pn) {
             for (int g = 0; g < QN; ++g) {
@@ -311,6 +334,8 @@ __device__ void elem_transient(const PoroK &K, double X, double Y, double cx, do
     });
 }
 
+__device__ void block_of_unit_responses(const PoroK &K, double cb, double sb, const double R[16], double B[12]);
+
 // The element's 4 x 3 response block at time t: B[3 k + c] is response k
 // (sxx, syy, sxy, p) at (X, Y) to unit D_s (c = 0), D_n (1) or D_q (2) on
 // the element.  The strengths (a, b, V) of a unit DD are constant along the
@@ -323,6 +348,13 @@ __device__ void elem_block(const PoroK &K, double X, double Y, double cx, double
     for (int k = 0; k < 16; ++k) R[k] = 0.0;
     elem_quad(K, X, Y, cx, cy, cb, sb, a, t,
               [&](double x, double y, double w) { transient_basis(K, x, y, t, w, R); });
+    block_of_unit_responses(K, cb, sb, R, B);
+}
+
+// B (4 x 3, per unit D_s, D_n, D_q) from the integrated unit-strength
+// responses R (per unit a, b, V, q_f) of an element with direction (cb, sb)
+__device__ void block_of_unit_responses(const PoroK &K, double cb, double sb, const double R[16], double B[12])
+{
     double sa[2], sbb[2], sv[2];
     for (int c = 0; c < 2; ++c) {
         double q[3];
@@ -741,51 +773,131 @@ __global__ __launch_bounds__(PN) void k_pp2p(int nitem, const int *__restrict__ 
     }
 }
 
-// Near-field blocks of time level (t = (j+1) dt) for every near pair, one
-// thread per pair: pair g lies in item k with it_coff[k] <= g <
-// it_coff[k+1]; within the item, pair e = v nt + i (source v of the chunk,
-// target i of the leaf) stores its 12 entries at 12 it_coff[k] + (12 v + c)
-// nt + i, so that consecutive targets are adjacent for every entry c.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_pnear_build(int64_t npair, int nitem, const int64_t *__restrict__ it_coff,
-                                                     const int *__restrict__ it_leaf, const int *__restrict__ it_s0,
-                                                     const int *__restrict__ leaves, const int *__restrict__ pbeg,
-                                                     const int *__restrict__ pend, const int *__restrict__ noff,
-                                                     const int *__restrict__ nbeg, const int *__restrict__ npre,
-                                                     const double *__restrict__ cx, const double *__restrict__ cy,
-                                                     const double *__restrict__ cb, const double *__restrict__ sb,
-                                                     const double *__restrict__ a, double t, PoroK K,
-                                                     int drained, double *__restrict__ blk)
+// Near pair g: item k (it_coff[k] <= g < it_coff[k+1]), target i of the
+// item's leaf (points tb .. tb + nt - 1), source v of the item's chunk,
+// the source's point jsrc.
+struct NearPair {
+    int k, tb, nt, i, v, jsrc;
+};
+
+__device__ __forceinline__ NearPair near_pair(int64_t g, int nitem, const int64_t *__restrict__ it_coff,
+                                              const int *__restrict__ it_leaf, const int *__restrict__ it_s0,
+                                              const int *__restrict__ leaves, const int *__restrict__ pbeg,
+                                              const int *__restrict__ pend, const int *__restrict__ nfoff,
+                                              const int *__restrict__ nflat)
 {
-    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= npair) return;
     int lo = 0, hi = nitem - 1;  // last item with it_coff <= g
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
         if (it_coff[mid] <= g) lo = mid;
         else hi = mid - 1;
     }
-    const int k = lo, li = it_leaf[k], c = leaves[li];
-    const int tb = pbeg[c], nt = pend[c] - tb;
-    const int64_t e = g - it_coff[k];
-    const int v = (int)(e / nt), i = (int)(e - (int64_t)v * nt);
-    const int sv = it_s0[k] + v;
-    const int nb = noff[li], nn = noff[li + 1] - nb;
-    int r = 0;
-    while (r + 1 < nn && npre[nb + r + 1] <= sv) ++r;
-    const int jsrc = nbeg[nb + r] + (sv - npre[nb + r]);
-    double B[12];
-    elem_block(K, cx[tb + i], cy[tb + i], cx[jsrc], cy[jsrc], cb[jsrc], sb[jsrc], a[jsrc], t, B);
-    if (drained)  // the drained elastic element response, closed form
+    NearPair P;
+    P.k = lo;
+    const int li = it_leaf[lo], c = leaves[li];
+    P.tb = pbeg[c];
+    P.nt = pend[c] - P.tb;
+    const int64_t e = g - it_coff[lo];
+    P.v = (int)(e / P.nt);
+    P.i = (int)(e - (int64_t)P.v * P.nt);
+    P.jsrc = nflat[nfoff[li] + it_s0[lo] + P.v];
+    return P;
+}
+
+// the block B of pair P (plus the drained elastic response in closed form)
+// into its place: 12 it_coff[k] + (12 v + q) nt + i for entry q
+__device__ __forceinline__ void store_block(const PoroK &K, const NearPair &P, const int64_t *__restrict__ it_coff,
+                                            const double *__restrict__ cx, const double *__restrict__ cy,
+                                            const double *__restrict__ cb, const double *__restrict__ sb,
+                                            const double *__restrict__ a, int drained, double B[12],
+                                            double *__restrict__ blk)
+{
+    const int tgt = P.tb + P.i, j = P.jsrc;
+    if (drained)
         for (int c = 0; c < 2; ++c) {
             double sxx = 0.0, syy = 0.0, sxy = 0.0;
-            elem_stress_add(cx[tb + i], cy[tb + i], cx[jsrc], cy[jsrc], cb[jsrc], sb[jsrc], a[jsrc],
-                            c == 0 ? 1.0 : 0.0, c == 1 ? 1.0 : 0.0, K.gc, sxx, syy, sxy);
+            elem_stress_add(cx[tgt], cy[tgt], cx[j], cy[j], cb[j], sb[j], a[j], c == 0 ? 1.0 : 0.0,
+                            c == 1 ? 1.0 : 0.0, K.gc, sxx, syy, sxy);
             B[c] += sxx;
             B[3 + c] += syy;
             B[6 + c] += sxy;
         }
-    double *o = blk + 12 * it_coff[k] + (int64_t)12 * v * nt + i;
-    for (int q = 0; q < 12; ++q) o[(int64_t)q * nt] = B[q];
+    double *o = blk + 12 * it_coff[P.k] + (int64_t)12 * P.v * P.nt + P.i;
+    for (int q = 0; q < 12; ++q) o[(int64_t)q * P.nt] = B[q];
+}
+
+// Near-field blocks of time level (t = (j+1) dt) for every near pair, one
+// thread per pair: pair g lies in item k with it_coff[k] <= g <
+// it_coff[k+1]; within the item, pair e = v nt + i (source v of the chunk,
+// target i of the leaf) stores its 12 entries at 12 it_coff[k] + (12 v + c)
+// nt + i, so that consecutive targets are adjacent for every entry c.
+// With near_list, pairs whose receiver is within the composite rule's
+// reach (up to 800 points against 8) are listed there instead, for
+// k_pnear_build_close: one of them in a lane would hold its whole wave.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_pnear_build(
+    int64_t npair, int nitem, const int64_t *__restrict__ it_coff, const int *__restrict__ it_leaf,
+    const int *__restrict__ it_s0, const int *__restrict__ leaves, const int *__restrict__ pbeg,
+    const int *__restrict__ pend, const int *__restrict__ nfoff, const int *__restrict__ nflat,
+    const double *__restrict__ cx, const double *__restrict__ cy, const double *__restrict__ cb,
+    const double *__restrict__ sb, const double *__restrict__ a, double t, PoroK K, int drained,
+    double *__restrict__ blk, int64_t *__restrict__ near_list, unsigned long long *__restrict__ near_count)
+{
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= npair) return;
+    const NearPair P = near_pair(g, nitem, it_coff, it_leaf, it_s0, leaves, pbeg, pend, nfoff, nflat);
+    const int tgt = P.tb + P.i, j = P.jsrc;
+    if (near_list && !quad_geom(K, cx[tgt], cy[tgt], cx[j], cy[j], cb[j], sb[j], a[j], t).far) {
+        near_list[atomicAdd(near_count, 1ull)] = g;
+        return;
+    }
+    double B[12];
+    elem_block(K, cx[tgt], cy[tgt], cx[j], cy[j], cb[j], sb[j], a[j], t, B);
+    store_block(K, P, it_coff, cx, cy, cb, sb, a, drained, B, blk);
+}
+
+// The listed close pairs, one wave each (a fixed grid of waves takes the
+// list in turn): the 64 lanes split the composite rule's points, and the
+// 16 unit-strength responses are summed across the wave by a fixed
+// butterfly, so a pair's block does not depend on the list's order.
+__global__ __launch_bounds__(256) void k_pnear_build_close(
+    const int64_t *__restrict__ near_list, const unsigned long long *__restrict__ near_count, int nitem,
+    const int64_t *__restrict__ it_coff, const int *__restrict__ it_leaf, const int *__restrict__ it_s0,
+    const int *__restrict__ leaves, const int *__restrict__ pbeg, const int *__restrict__ pend,
+    const int *__restrict__ nfoff, const int *__restrict__ nflat, const double *__restrict__ cx,
+    const double *__restrict__ cy, const double *__restrict__ cb, const double *__restrict__ sb,
+    const double *__restrict__ ha, double t, PoroK K, int drained, double *__restrict__ blk)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const int64_t cnt = (int64_t)*near_count;
+    for (int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < cnt; w += nw) {
+        const NearPair P = near_pair(near_list[w], nitem, it_coff, it_leaf, it_s0, leaves, pbeg, pend, nfoff, nflat);
+        const int tgt = P.tb + P.i, j = P.jsrc;
+        const double X = cx[tgt], Y = cy[tgt], ecx = cx[j], ecy = cy[j], ecb = cb[j], esb = sb[j], a = ha[j];
+        const QuadGeom Q = quad_geom(K, X, Y, ecx, ecy, ecb, esb, a, t);
+        const double s0 = fmin(a, fmax(-a, Q.xl));
+        const double L0 = s0 + a, L1 = a - s0;
+        const int np0 = quad_panels(L0, Q.ell), np1 = quad_panels(L1, Q.ell);
+        const int n0 = QN * np0, total = n0 + QN * np1;
+        double R[16];
+        for (int q = 0; q < 16; ++q) R[q] = 0.0;
+        for (int idx = lane; idx < total; idx += 64) {
+            const int side = idx >= n0;
+            const int loc = side ? idx - n0 : idx, pn = loc / QN, gq = loc - pn * QN;
+            const double L = side ? L1 : L0, du = 1.0 / (side ? np1 : np0);
+            const double u = (pn + 0.5 + 0.5 * c_gl_t[gq]) * du;
+            const double wq = 0.5 * du * c_gl_w[gq] * 3.0 * L * u * u;
+            const double sq = side ? s0 + L * u * u * u : s0 - L * u * u * u;
+            transient_basis(K, X - (ecx + sq * ecb), Y - (ecy + sq * esb), t, wq, R);
+        }
+        for (int m = 32; m >= 1; m >>= 1)
+            for (int q = 0; q < 16; ++q) R[q] += __shfl_xor(R[q], m);
+        if (lane == 0) {
+            double B[12];
+            block_of_unit_responses(K, ecb, esb, R, B);
+            store_block(K, P, it_coff, cx, cy, cb, sb, ha, drained, B, blk);
+        }
+    }
 }
 
 // Near field from the stored blocks of time levels j0 .. j1-1 (lv[j] the
@@ -999,6 +1111,27 @@ bool same_key(const double a[8], const double b[8], int nk)
     return true;
 }
 
+// One time level's near blocks (at time t, with the drained part when
+// drained): far pairs one per thread, close pairs one per wave.
+void build_near_blocks(fmddm_ctx *ctx, fmddm_tree *t, double time, const PoroK &K, int drained, double *out)
+{
+    if (t->near_pairs == 0) return;
+    hipStream_t s = ctx->stream;
+    if (t->pn_close.n < (size_t)t->near_pairs) t->pn_close.alloc((size_t)t->near_pairs);
+    if (t->pn_ccount.n < 1) t->pn_ccount.alloc(1);
+    t->pn_ccount.zero(s);
+    hipLaunchKernelGGL(k_pnear_build, dim3(cdiv(t->near_pairs, 256)), dim3(256), 0, s, t->near_pairs, t->nitem,
+                       t->it_coff.p, t->it_leaf.p, t->it_s0.p, t->dleaves.p, t->cpbeg.p, t->cpend.p, t->nfoff.p,
+                       t->nflat.p, t->scx.p, t->scy.p, t->scb.p, t->ssb.p, t->sa.p, time, K, drained, out,
+                       t->pn_close.p, t->pn_ccount.p);
+    FM_CHECK_LAUNCH();
+    const int nblk = (int)std::min<int64_t>(cdiv(t->near_pairs, 4), 2048);
+    hipLaunchKernelGGL(k_pnear_build_close, dim3(nblk), dim3(256), 0, s, t->pn_close.p, t->pn_ccount.p, t->nitem,
+                       t->it_coff.p, t->it_leaf.p, t->it_s0.p, t->dleaves.p, t->cpbeg.p, t->cpend.p, t->nfoff.p,
+                       t->nflat.p, t->scx.p, t->scy.p, t->scb.p, t->ssb.p, t->sa.p, time, K, drained, out);
+    FM_CHECK_LAUNCH();
+}
+
 constexpr int PN_MAXLEV = 4096;  // stored near-field levels at most
 
 // Makes the near-field blocks of time levels 0 .. min(H, budget) - 1
@@ -1036,11 +1169,7 @@ int near_levels(fmddm_ctx *ctx, fmddm_tree *t, int H)
         std::unique_ptr<DBuf<double>> b(new DBuf<double>());
         b->alloc((size_t)12 * std::max<int64_t>(t->near_pairs, 1));
         if (t->near_pairs > 0) {
-            hipLaunchKernelGGL(k_pnear_build, dim3(cdiv(t->near_pairs, 256)), dim3(256), 0, s, t->near_pairs,
-                               t->nitem, t->it_coff.p, t->it_leaf.p, t->it_s0.p, t->dleaves.p, t->cpbeg.p,
-                               t->cpend.p, t->noff.p, t->nbeg.p, t->npre.p, t->scx.p, t->scy.p, t->scb.p,
-                               t->ssb.p, t->sa.p, (j + 1) * ctx->poro.dt, K, 0, b->p);
-            FM_CHECK_LAUNCH();
+            build_near_blocks(ctx, t, (j + 1) * ctx->poro.dt, K, 0, b->p);
         }
         t->pn_hptr.resize(j);
         t->pn_hptr.push_back(b->p);
@@ -1063,11 +1192,7 @@ bool near_lhs(fmddm_ctx *ctx, fmddm_tree *t)
     hipStream_t s = ctx->stream;
     t->pn_lhs.alloc((size_t)12 * std::max<int64_t>(t->near_pairs, 1));
     if (t->near_pairs > 0) {
-        hipLaunchKernelGGL(k_pnear_build, dim3(cdiv(t->near_pairs, 256)), dim3(256), 0, s, t->near_pairs, t->nitem,
-                           t->it_coff.p, t->it_leaf.p, t->it_s0.p, t->dleaves.p, t->cpbeg.p, t->cpend.p, t->noff.p,
-                           t->nbeg.p, t->npre.p, t->scx.p, t->scy.p, t->scb.p, t->ssb.p, t->sa.p, ctx->poro.dt,
-                           poro_constants(ctx), 1, t->pn_lhs.p);
-        FM_CHECK_LAUNCH();
+        build_near_blocks(ctx, t, ctx->poro.dt, poro_constants(ctx), 1, t->pn_lhs.p);
     }
     if (t->pn_lhs_ptr.n < 1) t->pn_lhs_ptr.alloc(1);
     t->pn_lhs_host = t->pn_lhs.p;
