@@ -142,6 +142,9 @@ SERVE_PARAMS = dict(p=10, leaf=32, m2l=1, m2l_tol=1e-10, restart=50, maxit=20000
 # the poroelastic medium of the horizontal-well example (Section 5.2.1,
 # Table 2; drained E, nu of the well example), 60 s steps
 SERVE_PORO = dict(E=20e9, nu=0.2, nu_u=0.35, alpha=0.8, perm=1e-18, visc=1e-3, dt=60.0, p0=48.26e6)
+# the left-hand side's M2L of a poroelastic request: 1 compressed (bases
+# shared per cell size over the requests), 0 dense
+SERVE_PORO_M2L = 1
 
 
 FAILED = {}  # request index -> status of the last serve_run's failed requests
@@ -156,7 +159,8 @@ def serve_run(F, wls, reqs, slots, arrivals, precond=2, precision=0, poro=False,
     srv = F.fmddm_server_create(prm, slots)
     if poro:
         m = SERVE_PORO
-        F.fmddm_server_set_poro(srv, m["nu_u"], m["alpha"], m["perm"], m["visc"], m["dt"], m["p0"])
+        F.fmddm_server_set_poro(srv, m["nu_u"], m["alpha"], m["perm"], m["visc"], m["dt"], m["p0"],
+                                m2l=SERVE_PORO_M2L)
     try:
         warm = F.fmddm_server_submit(srv, wls[0].x1, wls[0].y1, wls[0].x2, wls[0].y2, wls[0].pressure,
                                      wls[0].SH, wls[0].Sh, 1, 1e-6)

@@ -85,6 +85,7 @@ fmddm_status fmddm_create(const fmddm_params *p, void *hip_stream, fmddm_ctx **o
         fmddm::init_streams(ctx);
         ctx->cheb = std::make_shared<fmddm::Cheb>();
         ctx->m2l = std::make_shared<fmddm::M2LOps>();
+        ctx->pcache = std::make_shared<fmddm::PoroLhsCache>();
         fmddm::setup_cheb(ctx);
         return FMDDM_OK;
     });

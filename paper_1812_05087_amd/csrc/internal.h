@@ -7,6 +7,8 @@
 #include <memory>
 #include <new>
 #include <string>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "../../include/fmddm.h"
@@ -142,6 +144,20 @@ struct M2LOps {
     DBuf<uint16_t> ops16, Vt16, Ur16;   // bf16 bit patterns
 };
 
+// One tree level's poroelastic left-hand-side M2L operators in compressed
+// form, for all 40 V-list offsets: a cell half-width hw, medium, dt, p and
+// cut determine them, so trees whose levels share hw share them.
+struct PoroLhsBasis {
+    bool ok = false;             // false: the rank is too close to 4p^2 to pay
+    int r = 0, rq = 0;           // rank, padded to a multiple of 64
+    DBuf<double> Vt, U;          // rq x Mq (row-space vectors as rows), Mq x rq (column-space ones)
+    DBuf<double> C;              // 40 x rq x rq, row-major, in v_offsets order
+};
+struct PoroLhsCache {
+    std::mutex mu;
+    std::map<std::vector<double>, std::shared_ptr<PoroLhsBasis>> lev;
+};
+
 }  // namespace fmddm
 
 namespace fmddm {
@@ -185,6 +201,9 @@ struct fmddm_ctx {
     // the M2L mode: contexts created by a server share one set
     std::shared_ptr<fmddm::Cheb> cheb;
     std::shared_ptr<fmddm::M2LOps> m2l;
+    // compressed poroelastic left-hand-side operators per cell size (shared
+    // like the operator set)
+    std::shared_ptr<fmddm::PoroLhsCache> pcache;
     fmddm_poro_params poro{};  // poroelastic medium and time step (fmddm_poro_set)
     int poro_set = 0;
     double gc = 0.0;        // G / (2 pi (1 - nu))

@@ -499,6 +499,14 @@ __global__ void k_scale_copy(int m, double a, const double *__restrict__ x, doub
     if (e < m) y[e] = a * x[e];
 }
 
+// y = 0 (a buffer from the cache may hold any bit pattern, NaN included,
+// which a product with zero would keep)
+__global__ void k_zero(int64_t m, double *__restrict__ y)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < m) y[e] = 0.0;
+}
+
 // out[e] (mode 0: =, mode 1: -=) sum of the chunk partials, in chunk order.
 __global__ void k_poro_reduce(int m3, int nchunk, const double *__restrict__ part, int mode,
                               double *__restrict__ out)
@@ -1264,6 +1272,8 @@ void poro_fmm_setup(fmddm_ctx *ctx, fmddm_tree *t, int H)
         t->pf_ncombo = (int)clvl.size();
         t->pf_ntile = (int)top.size();
         t->pf_h_combo_lvl = clvl;
+        t->pf_h_combo_ox = cox;
+        t->pf_h_combo_oy = coy;
         t->pf_p = p;
         t->pf_Mq = Mq;
         t->pf_dt = pp.dt;
@@ -1322,39 +1332,51 @@ void lhs_ops(fmddm_ctx *ctx, fmddm_tree *t)
     t->pf_ops0_ok = 1;
 }
 
-// Compresses the left-hand side's M2L operators per tree level (the kernel
-// is not homogeneous, so unlike the elastic operators each level has its
-// own bases): for the combinations K_o of a level, the leading left
-// singular vectors of [K_o ...] (column space, U) and of [K_o^T ...] (row
-// space, V), cut where the singular values fall below m2l_tol of the
-// largest; then K_o ~ U C_o V^T with C_o = U^T K_o V.  The singular vectors
-// come from the randomized range finder of the elastic operators
-// (range_basis) on the m x (n m) packing; the ranks are far below m (~90
-// of 400 at p = 10, of 1024 at p = 16).  A product
-// is then a projection per source cell, the rq x rq translations per
-// interaction pair, and an expansion per target cell.  Left uncompressed
-// (pc_ok = -1) when a level's rank would exceed 3/4 of m.
-void lhs_compress(fmddm_ctx *ctx, fmddm_tree *t)
+// The left-hand side's M2L operators compressed for one cell half-width hw
+// (the kernel is not homogeneous, so unlike the elastic operators each
+// cell size has its own bases): the operators K_o of all 40 V-list offsets
+// at that size (k_pops), the leading left singular vectors of [K_o ...]
+// (column space, U) and of [K_o^T ...] (row space, V) from the randomized
+// range finder (range_basis), cut where the singular values fall below
+// m2l_tol of the largest; then K_o ~ U C_o V^T with C_o = U^T K_o V.  The
+// ranks are far below m = 4p^2 (~90 of 400 at p = 10, of 1024 at p = 16).
+// Kept in the context's cache, which a server's slots share: every tree
+// with cells of that size takes them from there.
+std::shared_ptr<PoroLhsBasis> level_basis(fmddm_ctx *ctx, double hw)
 {
+    const fmddm_poro_params &q = ctx->poro;
     const double tol = ctx->prm.m2l_tol;
-    if (t->pc_ok != 0 && t->pc_tol == tol) return;
-    lhs_ops(ctx, t);
-    t->pc_ok = -1;
-    t->pc_tol = tol;
-    const int nc = t->pf_ncombo;
-    if (nc == 0) return;
+    const int p = ctx->prm.p, p2 = p * p, m = 4 * p2, Mq = (m + 63) / 64 * 64;
+    const std::vector<double> key = {hw, q.nu_u, q.alpha, q.perm, q.visc, q.dt, ctx->prm.E, ctx->prm.nu,
+                                     (double)p, tol};
+    if (ctx->pcache) {
+        std::lock_guard<std::mutex> g(ctx->pcache->mu);
+        auto it = ctx->pcache->lev.find(key);
+        if (it != ctx->pcache->lev.end()) return it->second;
+    }
+    auto E = std::make_shared<PoroLhsBasis>();
     hipStream_t s = ctx->stream;
-    const int p = ctx->prm.p, m = 4 * p * p, Mq = t->pf_Mq;
-    std::vector<int> levs(t->pf_h_combo_lvl);
-    std::sort(levs.begin(), levs.end());
-    levs.erase(std::unique(levs.begin(), levs.end()), levs.end());
-    const int nlev = (int)levs.size();
-    std::vector<int> slot_of(64, -1);
-    for (int k = 0; k < nlev; ++k) slot_of[levs[k]] = k;
-    std::vector<std::vector<int>> bylev(nlev);
-    for (int o = 0; o < nc; ++o) bylev[slot_of[t->pf_h_combo_lvl[o]]].push_back(o);
-    size_t maxn = 0;
-    for (auto &v : bylev) maxn = std::max(maxn, v.size());
+    std::vector<int> dx, dy, slot;
+    v_offsets(dx, dy, slot);
+    const int nop = (int)dx.size();
+    std::vector<int> zero(nop, 0), all(nop);
+    for (int o = 0; o < nop; ++o) all[o] = o;
+    auto up = [&](DBuf<int> &d, const std::vector<int> &v) {
+        d.alloc(std::max<size_t>(v.size(), 1));
+        if (!v.empty()) FM_HIP(hipMemcpyAsync(d.p, v.data(), v.size() * 4, hipMemcpyHostToDevice, s));
+    };
+    DBuf<int> dlvl, dox, doy, dall;
+    up(dlvl, zero);
+    up(dox, dx);
+    up(doy, dy);
+    up(dall, all);
+    // the operators at this size: level 0 of a root of side 2 hw
+    DBuf<double> ops;
+    ops.alloc((size_t)nop * Mq * Mq);
+    ops.zero(s);
+    hipLaunchKernelGGL(k_pops, dim3(cdiv((int64_t)p2 * p2 * nop, 256)), dim3(256), 0, s, nop, dlvl.p, dox.p, doy.p,
+                       2.0 * hw, ctx->cheb->xbar.p, p, 1, q.dt, Mq, poro_constants(ctx), 1, ops.p);
+    FM_CHECK_LAUNCH();
     if (!ctx->blas) {
         rocblas_handle h;
         if (rocblas_create_handle(&h) != rocblas_status_success) throw Error{FMDDM_EDEVICE, "rocblas handle"};
@@ -1364,78 +1386,135 @@ void lhs_compress(fmddm_ctx *ctx, fmddm_tree *t)
     rocblas_set_stream(h, s);
     const size_t mm = (size_t)m * m;
     DBuf<double> fat, Uc, Ur;
-    DBuf<int> dcomb;
-    fat.alloc(mm * maxn);
-    Uc.alloc(mm * nlev);
-    Ur.alloc(mm * nlev);
-    dcomb.alloc(maxn);
-    std::vector<int> rank(nlev, 1);
+    fat.alloc(mm * nop);
+    Uc.alloc(mm);
+    Ur.alloc(mm);
     std::vector<double> sv;
-    for (int k = 0; k < nlev; ++k) {
-        const int n = (int)bylev[k].size();
-        FM_HIP(hipMemcpyAsync(dcomb.p, bylev[k].data(), n * 4, hipMemcpyHostToDevice, s));
-        for (int side = 0; side < 2; ++side) {
-            int64_t tot = (int64_t)m * n * m;
-            hipLaunchKernelGGL(k_pc_pack, dim3(cdiv(tot, 256)), dim3(256), 0, s, n, dcomb.p, m, Mq, side,
-                               t->pf_ops0.p, fat.p);
-            FM_CHECK_LAUNCH();
-            double *Uo = (side == 0 ? Uc.p : Ur.p) + (size_t)k * mm;
-            rank[k] = std::max(rank[k], range_basis(h, s, m, n * m, fat.p, tol, Uo, sv));
-        }
+    int r = 1;
+    for (int side = 0; side < 2; ++side) {
+        hipLaunchKernelGGL(k_pc_pack, dim3(cdiv((int64_t)m * nop * m, 256)), dim3(256), 0, s, nop, dall.p, m, Mq, side,
+                           ops.p, fat.p);
+        FM_CHECK_LAUNCH();
+        r = std::max(r, range_basis(h, s, m, nop * m, fat.p, tol, side == 0 ? Uc.p : Ur.p, sv));
     }
-    int rmax = *std::max_element(rank.begin(), rank.end());
-    const int rq = (rmax + 63) / 64 * 64;
-    if (4 * rmax > 3 * m || rq >= Mq) return;  // not worth it: the dense operators stay
+    E->r = r;
+    E->rq = (r + 63) / 64 * 64;
+    E->ok = 4 * r <= 3 * m && E->rq < Mq;
+    if (E->ok) {
+        const int rq = E->rq;
+        DBuf<int> drank;
+        std::vector<int> hr(1, r);
+        up(drank, hr);
+        DBuf<double> UT;
+        E->Vt.alloc((size_t)rq * Mq);
+        E->U.alloc((size_t)Mq * rq);
+        UT.alloc((size_t)rq * Mq);
+        hipLaunchKernelGGL(k_pc_bases, dim3(cdiv((int64_t)rq * Mq, 256)), dim3(256), 0, s, 1, m, Mq, rq, drank.p,
+                           Uc.p, Ur.p, E->Vt.p, UT.p, E->U.p);
+        FM_CHECK_LAUNCH();
+        // C_o = U^T K_o V: T1[o rq + a] = K_o v_a, then Ct[o rq + a] = U^T T1[o rq + a]
+        std::vector<int> top, tb, te, src, z0;
+        for (int o = 0; o < nop; ++o)
+            for (int a0 = 0; a0 < rq; a0 += 32) {
+                top.push_back(o);
+                z0.push_back(0);
+                tb.push_back((int)src.size());
+                for (int a = a0; a < std::min(rq, a0 + 32); ++a) src.push_back(o * rq + a);
+                te.push_back((int)src.size());
+            }
+        std::vector<int> vrow(src.size());
+        for (size_t i = 0; i < src.size(); ++i) vrow[i] = src[i] % rq;
+        DBuf<int> dtop, dtb, dte, dsrc, dvrow, dz0;
+        up(dtop, top);
+        up(dtb, tb);
+        up(dte, te);
+        up(dsrc, src);
+        up(dvrow, vrow);
+        up(dz0, z0);
+        DBuf<double> T1, Ct;
+        T1.alloc((size_t)nop * rq * Mq);
+        Ct.alloc((size_t)nop * rq * rq);
+        fmm_pair_gemm(s, (int)top.size(), Mq, ops.p, (size_t)Mq * Mq, Mq, Mq, E->Vt.p, Mq, dtop.p, dtb.p, dte.p,
+                      dvrow.p, dsrc.p, T1.p, Mq);
+        fmm_pair_gemm(s, (int)top.size(), rq, UT.p, 0, Mq, Mq, T1.p, Mq, dz0.p, dtb.p, dte.p, dsrc.p, dsrc.p, Ct.p,
+                      rq);
+        E->C.alloc((size_t)nop * rq * rq);
+        hipLaunchKernelGGL(k_pc_transpose, dim3(cdiv((int64_t)nop * rq * rq, 256)), dim3(256), 0, s, nop, rq, Ct.p,
+                           E->C.p);
+        FM_CHECK_LAUNCH();
+    }
+    FM_HIP(hipStreamSynchronize(s));  // complete before other streams may read it
+    if (ctx->pcache) {
+        std::lock_guard<std::mutex> g(ctx->pcache->mu);
+        auto it = ctx->pcache->lev.find(key);
+        if (it != ctx->pcache->lev.end()) return it->second;  // another thread was first
+        if (ctx->pcache->lev.size() >= 64) ctx->pcache->lev.clear();  // trees keep what they hold
+        ctx->pcache->lev[key] = E;
+    }
+    return E;
+}
+
+// The tree's compressed left-hand side: per level slot the bases of its
+// cell size (level_basis), padded to the tree's largest rank rq, and per
+// (level, offset) combination its C_o; then the schedules of a product:
+// projection of every V-list source cell, the rq x rq translations per
+// pair, and expansion of every cell with a V list, in tiles of at most 32
+// cells of one level.  Left uncompressed (pc_ok = -1) when a level's rank
+// would exceed 3/4 of 4p^2.
+void lhs_compress(fmddm_ctx *ctx, fmddm_tree *t)
+{
+    const double tol = ctx->prm.m2l_tol;
+    if (t->pc_ok != 0 && t->pc_tol == tol) return;
+    t->pc_ok = -1;
+    t->pc_tol = tol;
+    const int nc = t->pf_ncombo;
+    if (nc == 0) return;
+    hipStream_t s = ctx->stream;
+    const int Mq = t->pf_Mq;
+    std::vector<int> levs(t->pf_h_combo_lvl);
+    std::sort(levs.begin(), levs.end());
+    levs.erase(std::unique(levs.begin(), levs.end()), levs.end());
+    const int nlev = (int)levs.size();
+    std::vector<int> slot_of(64, -1);
+    std::vector<std::shared_ptr<PoroLhsBasis>> lb(nlev);
+    int rq = 64;
+    std::vector<int> rank(nlev);
+    for (int k = 0; k < nlev; ++k) {
+        slot_of[levs[k]] = k;
+        lb[k] = level_basis(ctx, t->L / (double)(2LL << levs[k]));
+        if (!lb[k]->ok) return;  // not worth it: the dense operators stay
+        rq = std::max(rq, lb[k]->rq);
+        rank[k] = lb[k]->r;
+    }
     t->pc_rank = rank;
     t->pc_rq = rq;
     t->pc_nlev = nlev;
-    DBuf<int> drank;
-    drank.alloc(nlev);
-    FM_HIP(hipMemcpyAsync(drank.p, rank.data(), nlev * 4, hipMemcpyHostToDevice, s));
-    DBuf<double> UT;
     t->pc_Vt.alloc((size_t)nlev * rq * Mq);
     t->pc_U.alloc((size_t)nlev * Mq * rq);
-    UT.alloc((size_t)nlev * rq * Mq);
-    hipLaunchKernelGGL(k_pc_bases, dim3(cdiv((int64_t)nlev * rq * Mq, 256)), dim3(256), 0, s, nlev, m, Mq, rq,
-                       drank.p, Uc.p, Ur.p, t->pc_Vt.p, UT.p, t->pc_U.p);
-    FM_CHECK_LAUNCH();
-    // C_o = U^T K_o V: T1[o rq + a] = K_o v_a, then Ct[o rq + a] = U^T T1[o rq + a]
-    std::vector<int> top, tb, te, src, dst, lop;
+    t->pc_C.alloc((size_t)nc * rq * rq);
+    t->pc_Vt.zero(s);
+    t->pc_U.zero(s);
+    t->pc_C.zero(s);
+    for (int k = 0; k < nlev; ++k) {
+        const int rk = lb[k]->rq;
+        FM_HIP(hipMemcpyAsync(t->pc_Vt.p + (size_t)k * rq * Mq, lb[k]->Vt.p, (size_t)rk * Mq * 8,
+                              hipMemcpyDeviceToDevice, s));
+        FM_HIP(hipMemcpy2DAsync(t->pc_U.p + (size_t)k * Mq * rq, (size_t)rq * 8, lb[k]->U.p, (size_t)rk * 8,
+                                (size_t)rk * 8, Mq, hipMemcpyDeviceToDevice, s));
+    }
+    std::vector<int> dx, dy, vslot;
+    v_offsets(dx, dy, vslot);
     for (int o = 0; o < nc; ++o) {
-        const int k = slot_of[t->pf_h_combo_lvl[o]];
-        for (int a0 = 0; a0 < rq; a0 += 32) {
-            top.push_back(o);
-            lop.push_back(k);
-            tb.push_back((int)src.size());
-            for (int a = a0; a < std::min(rq, a0 + 32); ++a) {
-                src.push_back(k * rq + a);
-                dst.push_back(o * rq + a);
-            }
-            te.push_back((int)src.size());
-        }
+        const PoroLhsBasis &B = *lb[slot_of[t->pf_h_combo_lvl[o]]];
+        const int rk = B.rq, vo = vslot[offset_slot(t->pf_h_combo_ox[o], t->pf_h_combo_oy[o])];
+        if (vo < 0) throw Error{FMDDM_EDEVICE, "V-list offset outside the 40 of the operator set"};
+        FM_HIP(hipMemcpy2DAsync(t->pc_C.p + (size_t)o * rq * rq, (size_t)rq * 8, B.C.p + (size_t)vo * rk * rk,
+                                (size_t)rk * 8, (size_t)rk * 8, rk, hipMemcpyDeviceToDevice, s));
     }
     auto up = [&](DBuf<int> &d, const std::vector<int> &v) {
         d.alloc(std::max<size_t>(v.size(), 1));
         if (!v.empty()) FM_HIP(hipMemcpyAsync(d.p, v.data(), v.size() * 4, hipMemcpyHostToDevice, s));
     };
-    DBuf<int> dtop, dtb, dte, dsrc, ddst, dlop;
-    up(dtop, top);
-    up(dtb, tb);
-    up(dte, te);
-    up(dsrc, src);
-    up(ddst, dst);
-    up(dlop, lop);
-    DBuf<double> T1, Ct;
-    T1.alloc((size_t)nc * rq * Mq);
-    Ct.alloc((size_t)nc * rq * rq);
-    fmm_pair_gemm(s, (int)top.size(), Mq, t->pf_ops0.p, (size_t)Mq * Mq, Mq, Mq, t->pc_Vt.p, Mq, dtop.p, dtb.p,
-                  dte.p, dsrc.p, ddst.p, T1.p, Mq);
-    fmm_pair_gemm(s, (int)top.size(), rq, UT.p, (size_t)rq * Mq, Mq, Mq, T1.p, Mq, dlop.p, dtb.p, dte.p, ddst.p,
-                  ddst.p, Ct.p, rq);
-    t->pc_C.alloc((size_t)nc * rq * rq);
-    hipLaunchKernelGGL(k_pc_transpose, dim3(cdiv((int64_t)nc * rq * rq, 256)), dim3(256), 0, s, nc, rq, Ct.p,
-                       t->pc_C.p);
-    FM_CHECK_LAUNCH();
     // schedules: projection of every V-list source cell, expansion of every
     // cell with a V list, in tiles of at most 32 cells of one level
     const int ncell = t->ncell;
@@ -1518,9 +1597,9 @@ void poro_fmm_sum(fmddm_ctx *ctx, fmddm_tree *t, int H, const double *E, bool dr
     // the left-hand side F(dt) in one pass: operators and near blocks that
     // include the drained elastic part (when the near budget holds them)
     const bool fused = H == 1 && drained && jlo == 0 && near_lhs(ctx, t);
-    if (fused) lhs_ops(ctx, t);
     if (fused && ctx->poro.m2l == FMDDM_M2L_SVD) lhs_compress(ctx, t);
     const bool comp = fused && ctx->poro.m2l == FMDDM_M2L_SVD && t->pc_ok == 1;
+    if (fused && !comp) lhs_ops(ctx, t);
     double *D3 = t->pf_D3.p;  // DDs per time level, tree order (near field)
     if (affine) {
         if (t->pf_D3a.n < (size_t)H * n * 3) t->pf_D3a.alloc((size_t)H * n * 3);
@@ -1652,8 +1731,8 @@ void poro_apply(fmddm_ctx *ctx, fmddm_tree *t, int lag, const double *D, double 
         // time levels 1..lag+1 with E[lag-1] = -D, E[lag] = D, the rest zero
         const int H = lag + 1;
         if (t->poro_E.n < (size_t)H * m3) t->poro_E.alloc((size_t)H * m3);
-        hipLaunchKernelGGL(k_scale_copy, dim3(cdiv((int64_t)H * m3, 256)), dim3(256), 0, s, H * m3, 0.0,
-                           t->poro_E.p, t->poro_E.p);
+        hipLaunchKernelGGL(k_zero, dim3(cdiv((int64_t)H * m3, 256)), dim3(256), 0, s, (int64_t)H * m3,
+                           t->poro_E.p);
         hipLaunchKernelGGL(k_scale_copy, dim3(cdiv(m3, 256)), dim3(256), 0, s, m3, -1.0, D,
                            t->poro_E.p + (size_t)(lag - 1) * m3);
         hipLaunchKernelGGL(k_scale_copy, dim3(cdiv(m3, 256)), dim3(256), 0, s, m3, 1.0, D,
@@ -1703,7 +1782,10 @@ void poro_prepare(fmddm_ctx *ctx, fmddm_tree *t, int H)
     // of the history sums cannot take the two-term form
     poro_fmm_setup(ctx, t, std::min(std::max(H, 1), 2));
     if (H > 2 && !(ctx->poro.exact_far_levels == 0 && far_affine(ctx, t, H))) poro_fmm_setup(ctx, t, H);
-    if (near_lhs(ctx, t)) lhs_ops(ctx, t);
+    if (near_lhs(ctx, t)) {
+        if (ctx->poro.m2l == FMDDM_M2L_SVD) lhs_compress(ctx, t);
+        if (t->pc_ok != 1) lhs_ops(ctx, t);
+    }
     if (H > 1) near_levels(ctx, t, H);
 }
 

@@ -176,6 +176,7 @@ fmddm_ctx *slot_context(fmddm_server *s, hipStream_t st)
     c->gc = s->base->gc;
     c->cheb = s->base->cheb;
     c->m2l = s->base->m2l;
+    c->pcache = s->base->pcache;
     fmddm::init_streams(c);
     return c;
 }
@@ -225,6 +226,31 @@ void admit_work(fmddm_server *s, Slot &sl, const fmddm_request r, const double *
     fmddm::StreamScope scope(sl.stream);
     const int64_t n = r.n;
     sl.t = new fmddm_tree();
+    if (s->poro_set && s->poro.m2l == FMDDM_M2L_SVD && n > 0) {
+        // a root square of power-of-two side, centred on the midpoints'
+        // bounding box: the cell sizes of all requests of one scale then
+        // coincide, and so do their compressed left-hand-side operators,
+        // built once per cell size and shared by the slots
+        double x0 = HUGE_VAL, x1 = -HUGE_VAL, y0 = HUGE_VAL, y1 = -HUGE_VAL;
+        for (int64_t i = 0; i < n; ++i) {
+            const double cx = 0.5 * (g[i] + g[2 * n + i]), cy = 0.5 * (g[n + i] + g[3 * n + i]);
+            x0 = std::min(x0, cx);
+            x1 = std::max(x1, cx);
+            y0 = std::min(y0, cy);
+            y1 = std::max(y1, cy);
+        }
+        const double ext = std::max(std::max(x1 - x0, y1 - y0), 1e-300);
+        const double L = std::exp2(std::ceil(std::log2(ext * 1.0001)));
+        sl.ctx->prm.use_root_box = 1;
+        sl.ctx->prm.root_L = L;
+        sl.ctx->prm.root_x0 = x0 - 0.5 * (L - (x1 - x0));
+        sl.ctx->prm.root_y0 = y0 - 0.5 * (L - (y1 - y0));
+    } else {
+        sl.ctx->prm.use_root_box = s->base->prm.use_root_box;
+        sl.ctx->prm.root_L = s->base->prm.root_L;
+        sl.ctx->prm.root_x0 = s->base->prm.root_x0;
+        sl.ctx->prm.root_y0 = s->base->prm.root_y0;
+    }
     fmddm::build_tree(sl.ctx, sl.t, n, g, g + n, g + 2 * n, g + 3 * n, 0);
     if (s->poro_set) {
         // time march: the multipole form throughout (exact transient

@@ -224,18 +224,22 @@ def test_small_requests_on_exact_product():
 MED = dict(nu_u=0.35, alpha=0.8, perm=1e-18, visc=1e-3, dt=60.0, p0=48.26e6)
 
 
-def poro_server(slots, pc=F.FMDDM_PRECOND_TWO_LEVEL, **kw):
+def poro_server(slots, pc=F.FMDDM_PRECOND_TWO_LEVEL, m2l=F.FMDDM_M2L_DENSE, **kw):
     prm = F.fmddm_default_params(**dict(P_SERVE, E=20e9, nu=0.2, precond=pc, coarse_aggregates=128, **kw))
     srv = F.fmddm_server_create(prm, slots)
-    F.fmddm_server_set_poro(srv, MED["nu_u"], MED["alpha"], MED["perm"], MED["visc"], MED["dt"], MED["p0"])
+    F.fmddm_server_set_poro(srv, MED["nu_u"], MED["alpha"], MED["perm"], MED["visc"], MED["dt"], MED["p0"],
+                            m2l=m2l)
     return srv
 
 
-def test_poro_alone_equals_mix_bitwise():
+@pytest.mark.parametrize("m2l", [F.FMDDM_M2L_DENSE, F.FMDDM_M2L_SVD])
+def test_poro_alone_equals_mix_bitwise(m2l):
     """Poroelastic time marches (1-3 steps of 60 s with the history sum):
-    each request's DDs are the same alone and in the mix."""
+    each request's DDs are the same alone and in the mix; with the
+    compressed left-hand side too, whose operators the slots share per cell
+    size (built by whichever request needs a size first)."""
     reqs = W.serving_stream(seed=43, count=6, nmin=500, nmax=3000, steps_max=3)
-    srv = poro_server(4)
+    srv = poro_server(4, m2l=m2l)
     try:
         tickets, sizes = [], {}
         for r in reqs:
@@ -256,17 +260,19 @@ def test_poro_alone_equals_mix_bitwise():
         F.fmddm_server_destroy(srv)
 
 
-def test_poro_served_march_matches_oracle():
+@pytest.mark.parametrize("m2l", [F.FMDDM_M2L_DENSE, F.FMDDM_M2L_SVD])
+def test_poro_served_march_matches_oracle(m2l):
     """A served poroelastic request (3 steps) against the oracle's march on
     the exact operator (Gaussian elimination per step): GMRES at 1e-10 on
-    the multipole operators (p = 10, ~1e-8 from the exact ones) agrees to
+    the multipole operators (p = 10, ~1e-8 from the exact ones; compressed
+    left-hand side at m2l_tol 1e-10 on a power-of-two root square) agrees to
     1e-5 of the largest entry of each unknown kind."""
     wl = W.random_fractures(47, n_frac=6, elems=20, box=20.0)
     po = O.Poro(E=20e9, nu=0.2, nuu=MED["nu_u"], alpha=MED["alpha"], perm=MED["perm"], visc=MED["visc"])
     g = O.Geometry(wl.x1, wl.y1, wl.x2, wl.y2, 20e9, 0.2)
     steps = 3
     ref, _, _ = O.poro_march(g, po, MED["dt"], steps, wl.pressure, MED["p0"], wl.SH, wl.Sh)
-    srv = poro_server(2)
+    srv = poro_server(2, m2l=m2l)
     try:
         t = F.fmddm_server_submit(srv, wl.x1, wl.y1, wl.x2, wl.y2, wl.pressure, wl.SH, wl.Sh, steps, 1e-10)
         r = drain(srv, [t], limit_s=120)[t]
@@ -281,9 +287,10 @@ def test_poro_served_march_matches_oracle():
         assert e <= 1e-5, (k, e)
 
 
-def test_poro_footprint_covers_allocation():
+@pytest.mark.parametrize("m2l", [F.FMDDM_M2L_DENSE, F.FMDDM_M2L_SVD])
+def test_poro_footprint_covers_allocation(m2l):
     for seed, n, steps in [(53, 1000, 3), (59, 8000, 10)]:
-        srv = poro_server(1)
+        srv = poro_server(1, m2l=m2l)
         try:
             req = W.serving_stream(seed=seed, count=1, nmin=n, nmax=n, steps_max=1)[0]
             req.steps = steps
