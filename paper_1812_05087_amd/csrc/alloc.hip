@@ -18,6 +18,7 @@
 // then never share a block while the old user's work is pending.
 #include "internal.h"
 
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -88,9 +89,40 @@ int usable(const Block &b)
     return -1;
 }
 
+// FMDDM_POISON_ALLOC=1 (read once): every floating-point block handed out
+// is first filled with 0xFF bytes, a NaN in every double and float lane,
+// on the allocating scope's stream, so a kernel that reads memory its
+// owner has not written yields NaN instead of whatever the block held.
+// Integer blocks (indices, counters) are left as they are.  A debugging
+// aid; skipped for a stream under graph capture.
+bool poison_on()
+{
+    static const bool on = [] {
+        const char *v = std::getenv("FMDDM_POISON_ALLOC");
+        return v && v[0] == '1';
+    }();
+    return on;
+}
+
+void poison(void *p, size_t r)
+{
+    if (!poison_on()) return;
+    if (tl_set) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(tl_stream, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+            (void)hipGetLastError();
+            return;
+        }
+        FM_HIP(hipMemsetAsync(p, 0xFF, r, tl_stream));
+    } else {
+        FM_HIP(hipMemset(p, 0xFF, r));
+        FM_HIP(hipDeviceSynchronize());
+    }
+}
+
 }  // namespace
 
-void *dev_alloc(size_t bytes, size_t *rounded)
+void *dev_alloc(size_t bytes, size_t *rounded, bool fp)
 {
     int dev = 0;
     FM_HIP(hipGetDevice(&dev));
@@ -126,6 +158,7 @@ void *dev_alloc(size_t bytes, size_t *rounded)
             c.held[dev] -= got;
             c.live[dev] += got;
             *rounded = got;
+            if (fp) poison(p, got);
             return p;
         }
     }
@@ -144,8 +177,11 @@ void *dev_alloc(size_t bytes, size_t *rounded)
         }
     }
     FM_HIP(e);
-    std::lock_guard<std::mutex> g(c.mu);
-    c.live[dev] += r;
+    {
+        std::lock_guard<std::mutex> g(c.mu);
+        c.live[dev] += r;
+    }
+    if (fp) poison(p, r);
     return p;
 }
 

@@ -9,6 +9,7 @@
 #include <string>
 #include <map>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/fmddm.h"
@@ -35,7 +36,7 @@ struct Error {
 // ------------------------------------------------------- device buffers
 // alloc.hip: caching device allocator; sizes are rounded up and *rounded
 // receives the block size that dev_release takes back
-void *dev_alloc(size_t bytes, size_t *rounded);
+void *dev_alloc(size_t bytes, size_t *rounded, bool fp = false);
 void dev_release(void *p, size_t rounded);
 size_t dev_cache_trim();
 size_t dev_bytes(bool cached);
@@ -82,7 +83,7 @@ struct DBuf {
     void alloc(size_t count) {
         reset();
         if (count == 0) count = 1;
-        p = (T *)dev_alloc(count * sizeof(T), &cap);
+        p = (T *)dev_alloc(count * sizeof(T), &cap, std::is_floating_point<T>::value);
         n = count;
     }
     void zero(hipStream_t s) { FM_HIP(hipMemsetAsync(p, 0, n * sizeof(T), s)); }
