@@ -705,14 +705,14 @@ __global__ void k_rf_rand(int64_t count, uint64_t seed, double *__restrict__ out
     out[e] = (double)(z >> 11) * 0x1.0p-52 - 1.0;
 }
 
-// the lower triangle of the leading k x k block of an LQ factorisation
-// (leading dimension k)
-__global__ void k_rf_lower(int k, const double *__restrict__ lq, double *__restrict__ L)
+// L = R^T from the QR factorisation of B^T (N x k, leading dimension N,
+// R in its upper triangle): the LQ factor of B, k x k column-major
+__global__ void k_rf_lower(int k, int64_t N, const double *__restrict__ qr, double *__restrict__ L)
 {
     int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= k * k) return;
     int j = e / k, i = e - j * k;
-    L[e] = i >= j ? lq[e] : 0.0;
+    L[e] = i >= j ? qr[(size_t)i * N + j] : 0.0;
 }
 
 __global__ void k_pack_fat(int nop, int M, int Mp, const double *__restrict__ ops, double *__restrict__ fat)
@@ -1217,7 +1217,8 @@ void m2l_lowp(hipStream_t s, fmddm_tree *t, const M2LOps &M, const TO *Vt, const
 // Leading left singular vectors of A (m x N, column-major, N >= m) down to
 // tol of the largest singular value, by a randomized range finder (Halko,
 // Martinsson and Tropp, 2011): Y = A Om for k uniform random columns,
-// Q = orth(Y) (Householder QR), B = Q^T A, B = L P (LQ), L = U_L S W^T
+// Q = orth(Y) (Householder QR), B = Q^T A, B = L P (LQ, taken as the QR
+// factorisation B^T = P^T L^T of the tall transpose), L = U_L S W^T
 // (one-sided Jacobi SVD); then A ~ (Q U_L) S (P^T W)^T.  k starts at 192
 // and doubles until the k-th singular value is a decade below tol (k = m:
 // exact).
@@ -1252,11 +1253,13 @@ int range_basis(void *hv, hipStream_t s, int m, int N, const double *A, double t
                                 &zero, Y.p, m) == rocblas_status_success;
         ok = ok && rocsolver_dgeqrf(h, m, k, Y.p, m, tau.p) == rocblas_status_success;
         ok = ok && rocsolver_dorgqr(h, m, k, k, Y.p, m, tau.p) == rocblas_status_success;
-        ok = ok && rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, k, N, m, &one, Y.p, m, A,
-                                 m, &zero, B.p, k) == rocblas_status_success;
-        ok = ok && rocsolver_dgelqf(h, k, N, B.p, k, tau.p) == rocblas_status_success;
+        // B = Q^T A (k x N) is wide; its LQ factor is R^T of the QR
+        // factorisation of the tall B^T = A^T Q, which takes the blocked path
+        ok = ok && rocblas_dgemm(h, rocblas_operation_transpose, rocblas_operation_none, N, k, m, &one, A, m, Y.p,
+                                 m, &zero, B.p, N) == rocblas_status_success;
+        ok = ok && rocsolver_dgeqrf(h, N, k, B.p, N, tau.p) == rocblas_status_success;
         if (!ok) throw Error{FMDDM_EDEVICE, "range finder: rocBLAS / rocSOLVER call failed"};
-        hipLaunchKernelGGL(k_rf_lower, dim3(cdiv((int64_t)k * k, 256)), dim3(256), 0, s, k, B.p, L.p);
+        hipLaunchKernelGGL(k_rf_lower, dim3(cdiv((int64_t)k * k, 256)), dim3(256), 0, s, k, (int64_t)N, B.p, L.p);
         FM_CHECK_LAUNCH();
         if (rocsolver_dgesvdj(h, rocblas_svect_singular, rocblas_svect_none, k, k, L.p, k, 0.0, res.p, 100,
                               sweeps.p, S.p, UL.p, k, nullptr, 1, info.p) != rocblas_status_success)
