@@ -914,8 +914,8 @@ __global__ __launch_bounds__(256) void k_pnear_build_close(
 // A stream of 96 bytes per pair and level: 256 lanes per item, tpt =
 // 256 / (leaf points) lanes per point (all lanes busy for any leaf size,
 // two sources' coefficients in flight per lane), sources from the
-// flattened per-leaf list; a point's tpt partials are summed in LDS in
-// lane order.
+// flattened per-leaf list; a point's tpt partials (one per source slice)
+// are summed in LDS in slice order.
 constexpr int PNB = 256;
 __global__ __launch_bounds__(PNB) void k_pnear(int nitem, const int *__restrict__ it_leaf,
                                                const int *__restrict__ it_s0, const int *__restrict__ it_s1,
@@ -932,13 +932,15 @@ __global__ __launch_bounds__(PNB) void k_pnear(int nitem, const int *__restrict_
     const int c = leaves[li];
     const int nt = pend[c] - pbeg[c];
     const int *src = nflat + nfoff[li] + s0;
+    // lane tid takes target g = tid % tpg and source slice sub = tid / tpg,
+    // so the lanes of one slice read consecutive targets' entries
     const int tpt = nt >= PNB ? 1 : min(16, PNB / nt);
-    const int tpg = PNB / tpt, g = tid / tpt, sub = tid - g * tpt;
+    const int tpg = PNB / tpt, g = tid % tpg, sub = tid / tpg;
     const int64_t base = 12 * it_coff[k];
     double *pk = part + 4 * (size_t)it_poff[k];
     for (int t0 = 0; t0 < nt; t0 += tpg) {
         const int i = t0 + g;
-        const bool act = g < tpg && i < nt;
+        const bool act = sub < tpt && i < nt;
         double o[4] = {0.0, 0.0, 0.0, 0.0};
         if (act) {
 #pragma unroll 2
@@ -965,7 +967,7 @@ __global__ __launch_bounds__(PNB) void k_pnear(int nitem, const int *__restrict_
         if (act && sub == 0)
             for (int cc = 0; cc < 4; ++cc) {
                 double r = 0.0;
-                for (int u = tid; u < tid + tpt; ++u) r += s_red[cc * PNB + u];
+                for (int u = 0; u < tpt; ++u) r += s_red[cc * PNB + u * tpg + g];
                 pk[4 * (size_t)i + cc] = r;
             }
         __syncthreads();
