@@ -762,8 +762,9 @@ __global__ void k_transpose_ops(int nop, int rp, double scale, const double *__r
 // cell's field once, forms the barycentric interpolants Sx, Sy of its
 // points, computes R[(c,l)][t] = sum_m G[c][l][m] Sy[t][m] on FP64 MFMA
 // (rows (c,l) in 16-row tiles, one per wave; points in two 16-column
-// tiles; m in k-steps of 4) and sigma_c(t) = sum_l Sx[t][l] R[(c,l)][t],
-// and writes it to the slot of the cell's level:
+// tiles; m in k-steps of 4) and sigma_c(t) = sum_l Sx[t][l] R[(c,l)][t]
+// (summed within each row tile in registers and by a fixed butterfly, then
+// over the tiles in order), and writes it to the slot of the cell's level:
 // far[((level - 2) n + point) NC + c].  The final pass sums a point's levels
 // in order.
 constexpr int LT = 256, LTM = 32;
@@ -783,7 +784,7 @@ __global__ __launch_bounds__(LT) void k_l2p(int nitem, const int *__restrict__ i
     constexpr int KS = (P + 3) / 4;         // k-steps over m
     __shared__ double Gb[N3];
     __shared__ double Sx[LTM][P + 1], Sy[LTM][P + 1];
-    __shared__ double Rb[16 * RT][LTM + 1];
+    __shared__ double part[RT][NC][LTM];  // per row tile: sum over its rows of each component
     __shared__ double s_xb[P], s_bw[P];
     int item = xcd_remap(blockIdx.x, nitem);
     int A = it_cell[item], t0 = it_p0[item];
@@ -824,15 +825,40 @@ __global__ __launch_bounds__(LT) void k_l2p(int nitem, const int *__restrict__ i
             r0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, r0, 0, 0, 0);
             r1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, r1, 0, 0, 0);
         }
+        // sigma_c(t) over this tile's rows: each lane sums its four rows
+        // (r ascending) per component, then the four row groups of a column
+        // are combined by a fixed butterfly
+        const int t = lane & 15;
+        double a0[NC], a1[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) a0[c] = a1[c] = 0.0;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            int rw = 16 * mt + 4 * r + (lane >> 4);
+            const int rw = 16 * mt + 4 * r + (lane >> 4);
             if (rw < NC * P) {
-                int l = rw % P, t = lane & 15;
-                Rb[rw][t] = r0[r] * Sx[t][l];
-                Rb[rw][t + 16] = r1[r] * Sx[t + 16][l];
+                const int c = rw / P, l = rw - c * P;
+                const double x0 = r0[r] * Sx[t][l], x1 = r1[r] * Sx[t + 16][l];
+#pragma unroll
+                for (int cc = 0; cc < NC; ++cc)
+                    if (cc == c) {
+                        a0[cc] += x0;
+                        a1[cc] += x1;
+                    }
             }
         }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            a0[c] += __shfl_xor(a0[c], 16);
+            a1[c] += __shfl_xor(a1[c], 16);
+            a0[c] += __shfl_xor(a0[c], 32);
+            a1[c] += __shfl_xor(a1[c], 32);
+        }
+        if (lane < 16)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                part[mt][c][t] = a0[c];
+                part[mt][c][t + 16] = a1[c];
+            }
     }
     __syncthreads();
     if (tid < NC * LTM) {
@@ -840,7 +866,7 @@ __global__ __launch_bounds__(LT) void k_l2p(int nitem, const int *__restrict__ i
         if (t < ntp) {
             double sum = 0.0;
 #pragma unroll
-            for (int l = 0; l < P; ++l) sum += Rb[comp * P + l][t];
+            for (int mt = 0; mt < RT; ++mt) sum += part[mt][comp][t];
             far[(((size_t)(level[A] - 2)) * n + t0 + t) * NC + comp] = sum;
         }
     }
