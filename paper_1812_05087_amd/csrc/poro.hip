@@ -493,6 +493,82 @@ __global__ __launch_bounds__(256) void k_ppc_build(int nblk, const int *__restri
     }
 }
 
+// The same blocks taken from the left-hand side's stored near blocks (blk:
+// 12 entries per near pair, the drained part included, in the layout of
+// k_pnear_build) instead of integrating them again: a group lies in one
+// leaf, whose near sources include the leaf itself, so the pair (i, j) is
+// source pos_j of leaf li, in the item whose chunk holds pos_j.  A pair not
+// found there is integrated as in k_ppc_build.
+__global__ __launch_bounds__(256) void k_ppc_gather(
+    int nblk, const int *__restrict__ beg, const int *__restrict__ cnt, const int64_t *__restrict__ off,
+    const int *__restrict__ tleaf, const int *__restrict__ leaves, const int *__restrict__ pbeg,
+    const int *__restrict__ pend, const int *__restrict__ lk_off, const int *__restrict__ it_s0,
+    const int *__restrict__ it_s1, const int64_t *__restrict__ it_coff, const int *__restrict__ nfoff,
+    const int *__restrict__ nflat, const double *__restrict__ blk, const double *__restrict__ cx,
+    const double *__restrict__ cy, const double *__restrict__ cb, const double *__restrict__ sb,
+    const double *__restrict__ ha, double dt, PoroK K, double *__restrict__ inv, int *__restrict__ bad)
+{
+    __shared__ double A[GJN][GJN + 1];
+    __shared__ double colk[GJN];
+    __shared__ int piv[GJN];
+    __shared__ int s_item[PPB], s_v[PPB];
+    const int b = blockIdx.x, tid = threadIdx.x;
+    const int s0 = beg[b], m = cnt[b], nb = 3 * m;
+    const int li = tleaf[s0], c = leaves[li], tb = pbeg[c], nt = pend[c] - tb;
+    if (tid < m) {
+        // source s0 + tid in the leaf's near list, and its item and slot
+        const int j = s0 + tid, f0 = nfoff[li], len = nfoff[li + 1] - f0;
+        int pos = -1;
+        for (int u = 0; u < len && pos < 0; ++u)
+            if (nflat[f0 + u] == j) pos = u;
+        int item = -1, v = 0;
+        if (pos >= 0)
+            for (int k = lk_off[li]; k < lk_off[li + 1]; ++k)
+                if (it_s0[k] <= pos && pos < it_s1[k]) {
+                    item = k;
+                    v = pos - it_s0[k];
+                    break;
+                }
+        s_item[tid] = item;
+        s_v[tid] = v;
+    }
+    __syncthreads();
+    for (int e = tid; e < m * m; e += 256) {
+        const int i = e / m, j = e - i * m, ti = s0 + i, tj = s0 + j;
+        double B[12];
+        const int item = s_item[j];
+        if (item >= 0 && tleaf[ti] == li) {
+            const double *q = blk + 12 * it_coff[item] + (int64_t)12 * s_v[j] * nt + (ti - tb);
+#pragma unroll
+            for (int r = 0; r < 12; ++r) B[r] = q[(int64_t)r * nt];
+        } else {
+            elem_block(K, cx[ti], cy[ti], cx[tj], cy[tj], cb[tj], sb[tj], ha[tj], dt, B);
+            for (int cc = 0; cc < 2; ++cc) {
+                double sxx = 0.0, syy = 0.0, sxy = 0.0;
+                elem_stress_add(cx[ti], cy[ti], cx[tj], cy[tj], cb[tj], sb[tj], ha[tj], cc == 0 ? 1.0 : 0.0,
+                                cc == 1 ? 1.0 : 0.0, K.gc, sxx, syy, sxy);
+                B[cc] += sxx;
+                B[3 + cc] += syy;
+                B[6 + cc] += sxy;
+            }
+        }
+        for (int cc = 0; cc < 3; ++cc) {
+            double ts, tn;
+            traction(cb[ti], sb[ti], B[cc], B[3 + cc], B[6 + cc], ts, tn);
+            A[3 * i][3 * j + cc] = ts;
+            A[3 * i + 1][3 * j + cc] = tn;
+            A[3 * i + 2][3 * j + cc] = B[9 + cc];
+        }
+    }
+    __syncthreads();
+    gj_invert(A, nb, colk, piv, bad);
+    double *o = inv + off[b];
+    for (int e = tid; e < nb * nb; e += 256) {
+        int cc = e / nb, r = e % nb;
+        o[e] = A[r][cc];
+    }
+}
+
 __global__ void k_scale_copy(int m, double a, const double *__restrict__ x, double *__restrict__ y)
 {
     int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1808,8 +1884,14 @@ void pc_setup_poro(fmddm_ctx *ctx, fmddm_tree *t)
     DBuf<int> bad;
     bad.alloc(1);
     bad.zero(s);
-    hipLaunchKernelGGL(k_ppc_build, dim3(B.nblk), dim3(256), 0, s, B.nblk, B.beg.p, B.cnt.p, B.off.p, t->scx.p,
-                       t->scy.p, t->scb.p, t->ssb.p, t->sa.p, q.dt, poro_constants(ctx), B.inv.p, bad.p);
+    if (t->near_pairs > 0 && near_lhs(ctx, t))
+        hipLaunchKernelGGL(k_ppc_gather, dim3(B.nblk), dim3(256), 0, s, B.nblk, B.beg.p, B.cnt.p, B.off.p,
+                           t->tleaf.p, t->dleaves.p, t->cpbeg.p, t->cpend.p, t->lk_off.p, t->it_s0.p, t->it_s1.p,
+                           t->it_coff.p, t->nfoff.p, t->nflat.p, t->pn_lhs.p, t->scx.p, t->scy.p, t->scb.p,
+                           t->ssb.p, t->sa.p, q.dt, poro_constants(ctx), B.inv.p, bad.p);
+    else
+        hipLaunchKernelGGL(k_ppc_build, dim3(B.nblk), dim3(256), 0, s, B.nblk, B.beg.p, B.cnt.p, B.off.p, t->scx.p,
+                           t->scy.p, t->scb.p, t->ssb.p, t->sa.p, q.dt, poro_constants(ctx), B.inv.p, bad.p);
     FM_CHECK_LAUNCH();
     int hbad = 0;
     FM_HIP(hipMemcpyAsync(&hbad, bad.p, 4, hipMemcpyDeviceToHost, s));
