@@ -1560,6 +1560,22 @@ void fmm_pair_gemm(hipStream_t s, int ntile, int Mrows, const double *ops, size_
                          nullptr, Z, ldz);
 }
 
+// The same product with K split over nsplit slices (partials at part + z
+// zsplit, leading dimension ldz) and the slices summed in order into
+// Z[0 .. count): for few tiles over a long K.
+void fmm_pair_gemm_split(hipStream_t s, int ntile, int Mrows, const double *ops, size_t op_stride, int lda, int Kd,
+                         const double *X, int ldx, const int *tile_op, const int *tile_beg, const int *tile_end,
+                         const int *psrc, const int *pdst, double *part, int ldz, int nsplit, size_t zsplit,
+                         double *Z, int64_t count)
+{
+    if (ntile == 0) return;
+    launch_ggemm<64, 32>(s, ntile, Mrows, ops, op_stride, lda, Kd, X, ldx, tile_op, tile_beg, tile_end, psrc, pdst,
+                         nullptr, part, ldz, nsplit, zsplit);
+    hipLaunchKernelGGL(k_reduce_split<double>, dim3(cdiv(count, 256)), dim3(256), 0, s, count, nsplit, zsplit, part,
+                       Z);
+    FM_CHECK_LAUNCH();
+}
+
 void fmm_sum_pairs(hipStream_t s, fmddm_tree *t, const double *Z, int ldz, int width, double *out, int ldo)
 {
     if (t->nfar == 0) return;

@@ -324,6 +324,8 @@ struct fmddm_tree {
     int pc_rq = 0, pc_nlev = 0, pc_nptile = 0, pc_netile = 0;
     std::vector<int> pc_rank;  // retained rank per level slot
     fmddm::DBuf<double> pc_Vt, pc_U, pc_C, pc_What, pc_Z, pc_Ghat;
+    fmddm::DBuf<double> pc_Wsplit;  // split-K partials of the projection (zero where never written)
+    int pc_ksplit = 1;
     fmddm::DBuf<int> pc_ptile_op, pc_ptile_beg, pc_ptile_end, pc_pcell, pc_etile_op, pc_etile_beg, pc_etile_end,
         pc_ecell;
     // history-only variant: the left-hand side as a dense 3n x 3n matrix
@@ -376,6 +378,10 @@ void fmm_l2p4(fmddm_ctx *ctx, fmddm_tree *t, const double *G, int ldg, double *f
 void fmm_pair_gemm(hipStream_t s, int ntile, int Mrows, const double *ops, size_t op_stride, int lda, int Kd,
                    const double *X, int ldx, const int *tile_op, const int *tile_beg, const int *tile_end,
                    const int *psrc, const int *pdst, double *Z, int ldz);
+void fmm_pair_gemm_split(hipStream_t s, int ntile, int Mrows, const double *ops, size_t op_stride, int lda, int Kd,
+                         const double *X, int ldx, const int *tile_op, const int *tile_beg, const int *tile_end,
+                         const int *psrc, const int *pdst, double *part, int ldz, int nsplit, size_t zsplit,
+                         double *Z, int64_t count);
 void fmm_sum_pairs(hipStream_t s, fmddm_tree *t, const double *Z, int ldz, int width, double *out, int ldo);
 void setup_fmm(fmddm_ctx *ctx, fmddm_tree *t);
 // prec: fmddm_precision of the near field and the M2L products

@@ -1632,9 +1632,21 @@ void lhs_compress(fmddm_ctx *ctx, fmddm_tree *t)
     t->pc_What.alloc((size_t)ncell * rq);
     t->pc_Z.alloc((size_t)std::max<int64_t>(t->nV, 1) * rq);
     t->pc_Ghat.alloc((size_t)ncell * rq);
+    // the projection has one tile per 32 source cells and rq / 64 row
+    // tiles, too few blocks for a long K (4p^2): K is split so that about
+    // 512 blocks run, and the slices are summed in order; slices of cells
+    // that are never projected stay zero
+    {
+        const int base = std::max(1, t->pc_nptile * (rq / 64));
+        t->pc_ksplit = std::min(8, std::max(1, (512 + base - 1) / base));
+        if (t->pc_ksplit > 1) {
+            t->pc_Wsplit.alloc((size_t)t->pc_ksplit * ncell * rq);
+            t->pc_Wsplit.zero(s);
+        }
+    }
     FM_HIP(hipStreamSynchronize(s));
     t->bytes += (int64_t)(t->pc_Vt.bytes() + t->pc_U.bytes() + t->pc_C.bytes() + t->pc_What.bytes() +
-                          t->pc_Z.bytes() + t->pc_Ghat.bytes());
+                          t->pc_Z.bytes() + t->pc_Ghat.bytes() + (t->pc_ksplit > 1 ? t->pc_Wsplit.bytes() : 0));
     t->pc_ok = 1;
 }
 
@@ -1697,9 +1709,15 @@ void poro_fmm_sum(fmddm_ctx *ctx, fmddm_tree *t, int H, const double *E, bool dr
         fmm_m2m4(ctx, t, Hf, Hf * Mq, Mq, t->pf_W.p);
         if (comp) {
             const int rq = t->pc_rq;
-            fmm_pair_gemm(s, t->pc_nptile, rq, t->pc_Vt.p, (size_t)rq * Mq, Mq, Mq, t->pf_W.p, Mq,
-                          t->pc_ptile_op.p, t->pc_ptile_beg.p, t->pc_ptile_end.p, t->pc_pcell.p, t->pc_pcell.p,
-                          t->pc_What.p, rq);
+            if (t->pc_ksplit > 1)
+                fmm_pair_gemm_split(s, t->pc_nptile, rq, t->pc_Vt.p, (size_t)rq * Mq, Mq, Mq, t->pf_W.p, Mq,
+                                    t->pc_ptile_op.p, t->pc_ptile_beg.p, t->pc_ptile_end.p, t->pc_pcell.p,
+                                    t->pc_pcell.p, t->pc_Wsplit.p, rq, t->pc_ksplit, (size_t)t->ncell * rq,
+                                    t->pc_What.p, (int64_t)t->ncell * rq);
+            else
+                fmm_pair_gemm(s, t->pc_nptile, rq, t->pc_Vt.p, (size_t)rq * Mq, Mq, Mq, t->pf_W.p, Mq,
+                              t->pc_ptile_op.p, t->pc_ptile_beg.p, t->pc_ptile_end.p, t->pc_pcell.p, t->pc_pcell.p,
+                              t->pc_What.p, rq);
             fmm_pair_gemm(s, t->pf_ntile, rq, t->pc_C.p, (size_t)rq * rq, rq, rq, t->pc_What.p, rq, t->pf_tile_op.p,
                           t->pf_tile_beg.p, t->pf_tile_end.p, t->pf_psrc.p, t->pf_pdst.p, t->pc_Z.p, rq);
             fmm_sum_pairs(s, t, t->pc_Z.p, rq, rq, t->pc_Ghat.p, rq);
