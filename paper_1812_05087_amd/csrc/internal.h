@@ -341,6 +341,10 @@ struct fmddm_tree {
     std::vector<hipGraphExec_t> gm_graph;
     const fmddm_ctx *gm_graph_ctx = nullptr;
     int gm_graph_mode = -1;
+    // bumped whenever a buffer or constant that a poroelastic product or
+    // its preconditioner reads is (re)built; captured steps of an older
+    // generation are dropped
+    int64_t poro_gen = 0, gm_graph_gen = 0;
     void drop_graphs()
     {
         for (hipGraphExec_t &g : gm_graph)

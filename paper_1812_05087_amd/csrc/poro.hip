@@ -1233,6 +1233,7 @@ int near_levels(fmddm_ctx *ctx, fmddm_tree *t, int H)
         t->pn_hptr.clear();
         if (t->pn_lhs_ok) t->bytes -= (int64_t)t->pn_lhs.bytes();
         t->pn_lhs_ok = 0;
+        ++t->poro_gen;
         int64_t budget = ctx->poro.near_cache_bytes;
         if (budget == 0) {
             size_t fr = 0, tot = 0;
@@ -1286,6 +1287,7 @@ bool near_lhs(fmddm_ctx *ctx, fmddm_tree *t)
     FM_HIP(hipStreamSynchronize(s));
     t->bytes += (int64_t)t->pn_lhs.bytes();
     t->pn_lhs_ok = 1;
+    ++t->poro_gen;
     return true;
 }
 
@@ -1367,6 +1369,7 @@ void poro_fmm_setup(fmddm_ctx *ctx, fmddm_tree *t, int H)
         t->pf_D2.alloc(2 * (size_t)t->n);
         t->pf_o2.alloc(2 * (size_t)t->n);
         t->pf_ready = 1;
+        ++t->poro_gen;
         FM_HIP(hipStreamSynchronize(s));
     }
     if (t->pf_H < H) {
@@ -1383,6 +1386,7 @@ void poro_fmm_setup(fmddm_ctx *ctx, fmddm_tree *t, int H)
         }
         t->pf_W.alloc((size_t)t->ncell * Hn * Mq);
         t->pf_W.zero(s);
+        ++t->poro_gen;
         t->pf_Q.alloc((size_t)Hn * t->n * 4);
         t->pf_D3.alloc((size_t)Hn * t->n * 3);
         t->pf_H = Hn;
@@ -1408,6 +1412,7 @@ void lhs_ops(fmddm_ctx *ctx, fmddm_tree *t)
         FM_HIP(hipStreamSynchronize(s));
     }
     t->pf_ops0_ok = 1;
+    ++t->poro_gen;
 }
 
 // The left-hand side's M2L operators compressed for one cell half-width hw
@@ -1648,6 +1653,7 @@ void lhs_compress(fmddm_ctx *ctx, fmddm_tree *t)
     t->bytes += (int64_t)(t->pc_Vt.bytes() + t->pc_U.bytes() + t->pc_C.bytes() + t->pc_What.bytes() +
                           t->pc_Z.bytes() + t->pc_Ghat.bytes() + (t->pc_ksplit > 1 ? t->pc_Wsplit.bytes() : 0));
     t->pc_ok = 1;
+    ++t->poro_gen;
 }
 
 // Whether the far field of an H-level history sum may take the two-term
@@ -1806,6 +1812,7 @@ void poro_dense_apply(fmddm_ctx *ctx, fmddm_tree *t, const double *D, double *ou
         FM_CHECK_LAUNCH();
         for (int k = 0; k < 8; ++k) t->pdense_key[k] = key[k];
         t->pdense_ok = 1;
+        ++t->poro_gen;
     }
     dense_gemv(s, (int)m, t->pdense.p, D, out);
 }
@@ -1919,6 +1926,7 @@ void pc_setup_poro(fmddm_ctx *ctx, fmddm_tree *t)
         throw Error{FMDDM_EGEOM, "singular poroelastic preconditioner block"};
     }
     for (int k = 0; k < 6; ++k) B.key[k] = key[k];
+    ++t->poro_gen;
 }
 
 void poro_rhs(fmddm_ctx *ctx, fmddm_tree *t, const double *pf, double SH, double Sh, double *rhs)

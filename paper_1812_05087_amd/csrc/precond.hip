@@ -256,6 +256,7 @@ void pc_coarse_setup(fmddm_ctx *ctx, fmddm_tree *t, bool poro)
     bool same = C.nc > 0 || C.off;
     for (int k = 0; k < 6; ++k) same = same && C.key[k] == key[k];
     if (same) return;
+    ++t->poro_gen;  // captured steps read the coarse level
     // unbuilt until the new level is complete (a failed rebuild leaves none)
     if (C.nc > 0) t->bytes -= (int64_t)C.ainv.bytes();
     C.nc = 0;

@@ -422,15 +422,27 @@ void GmresRun::enqueue_residual()
 // over fixed buffers (the basis, the work vector, the scalars; b and x are
 // not touched), so after one uncaptured step has done the product's lazy
 // set-up, step jj is captured once as a graph and replayed in later cycles
-// and later solves on the tree.  Modes whose products may allocate on use
-// (the poroelastic operators) and profiled products stay uncaptured.
+// and later solves on the tree.  The poroelastic products are captured too:
+// whatever they build on first use (operators, near blocks, preconditioner
+// blocks) bumps the tree's generation, which drops the captured steps and
+// runs the next step uncaptured.  Profiled products stay uncaptured.
 void GmresRun::enqueue_step()
 {
     const int m = ctx->prm.restart, jj = next++;
     hipStream_t st = ctx->stream;
     ++it;
+    if (ctx->prm.use_graphs && t->gm_graph_gen != t->poro_gen) {
+        // something the captured steps read was rebuilt: drop them (after
+        // any replay still in flight), and let one step run uncaptured
+        // first (it may finish lazy set-up)
+        FM_HIP(hipStreamSynchronize(st));
+        t->drop_graphs();
+        t->gm_graph_gen = t->poro_gen;
+        eager_done = false;
+    }
     bool graph = ctx->prm.use_graphs && eager_done && ctx->prof.mask == 0 &&
-                 (mode == FMDDM_APPLY_FMM || mode == FMDDM_APPLY_DIRECT || mode == FMDDM_APPLY_DENSE);
+                 (mode == FMDDM_APPLY_FMM || mode == FMDDM_APPLY_DIRECT || mode == FMDDM_APPLY_DENSE ||
+                  mode == APPLY_PORO);
     if (graph) {
         if (t->gm_graph_ctx != ctx || t->gm_graph_mode != mode || (int)t->gm_graph.size() != m) {
             t->drop_graphs();

@@ -515,3 +515,47 @@ def test_poro_history_far_field_two_terms():
                 assert not np.array_equal(two[k], per[k])
             else:
                 assert np.array_equal(two[k], per[k])
+
+
+@pytest.mark.parametrize("far_levels", [0, 1])
+def test_poro_graph_replays_match_plain_launches(far_levels):
+    """Poroelastic steps with captured GMRES steps (use_graphs = 1) equal the
+    same steps launched plainly, bit for bit, in the same numbers of
+    products: four steps with the history sum (with one far-field term per
+    time level the history's operators grow with the step, reallocating
+    buffers the left-hand side reads), then a new Biot coefficient (every
+    operator and preconditioner block rebuilt) and two more steps.
+    Two-level preconditioning, restart 10 (several cycles per solve), the
+    left-hand side's M2L compressed."""
+    wl = W.well_cluster(n_frac=3, elems=60, half_length=6.0, spacing=2.0)
+    n3 = 3 * wl.n
+    out = {}
+    for graphs in (0, 1):
+        prob = F.Problem(wl.x1, wl.y1, wl.x2, wl.y2, E=MED["E"], nu=MED["nu"], p=10, leaf=16, tol=1e-10,
+                         restart=10, maxit=20000, precond=F.FMDDM_PRECOND_TWO_LEVEL, use_graphs=graphs)
+
+        def medium(alpha):
+            F.fmddm_poro_set(prob.ctx, MED["nuu"], alpha, MED["perm"], MED["visc"], DT, P0, mode=F.FMDDM_APPLY_FMM,
+                             m2l=F.FMDDM_M2L_SVD, exact_far_levels=far_levels)
+            b = torch.zeros(n3, dtype=torch.float64, device="cuda")
+            F.fmddm_poro_rhs(prob.ctx, prob.tree, dev(wl.pressure), wl.SH, wl.Sh, b)
+            return b
+
+        b0 = medium(MED["alpha"])
+        hist = torch.zeros(6 * n3, dtype=torch.float64, device="cuda")
+        D = torch.zeros(n3, dtype=torch.float64, device="cuda")
+        iters = []
+        for h in range(1, 7):
+            if h == 5:
+                b0 = medium(0.6)
+            rhs = b0.clone()
+            F.fmddm_add_history(prob.ctx, prob.tree, h, hist[: (h - 1) * n3] if h > 1 else None, rhs)
+            st, info = F.fmddm_poro_solve(prob.ctx, prob.tree, rhs, D)
+            assert st == F.FMDDM_OK and info["converged"], info
+            hist[(h - 1) * n3: h * n3] = D
+            iters.append(info["iters"])
+        out[graphs] = (hist.cpu().numpy(), iters)
+        prob.close()
+    print("products per step, plain / captured:", out[0][1], out[1][1])
+    assert out[0][1] == out[1][1] and min(out[0][1]) > 10
+    assert np.array_equal(out[0][0], out[1][0]), float(np.max(np.abs(out[0][0] - out[1][0])))
