@@ -337,7 +337,7 @@ def history_leg(F, W, elems, steps, p=16):
     _, tlc, _, o_s, _, tfc = history_run(F, W, elems, steps, F.FMDDM_APPLY_FMM, p, m2l=F.FMDDM_M2L_SVD)
     out["fmm_full"]["lhs_m2l_compressed"] = {
         "lhs_product_ms": tlc * 1e3, "first_pass_ms": tfc * 1e3, "diff_vs_uncompressed": rel(o_s, o_c),
-        "note": "left-hand side M2L compressed per tree level (m2l_tol 1e-10); the first pass includes the "
+        "note": "left-hand side M2L compressed per cell size (m2l_tol 1e-10); the first pass includes the "
                 "range finder and the compressed operators"}
     return out
 
@@ -577,7 +577,7 @@ def march_leg(F, W, elems, steps, p=16, restart=100, precond=2, coarse=0, ref_to
     red = march_run(F, W, 40, 10, p, restart, precond, coarse, 1e-6, m2l=0)
     run = march_run(F, W, elems, steps, p, restart, precond, coarse, 1e-6, keep)
     out = {"workload": f"well cluster 5 x {elems} elements (N={run['n']}), {steps} steps of 60 s", "p": p,
-           "lhs_m2l": f"compressed per tree level (m2l_tol 1e-10), largest rank {run['lhs_m2l_rank']} of {4 * p * p}",
+           "lhs_m2l": f"compressed per cell size (m2l_tol 1e-10), largest rank {run['lhs_m2l_rank']} of {4 * p * p}",
            "tree": run["tree"],
            "restart": restart, "precond": {1: "block-Jacobi", 2: "two-level"}[precond], "tol": 1e-6,
            "gmres_products_per_step": run["per_step"], "total_s": run["total_s"], "history_s": run["history_s"],

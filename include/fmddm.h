@@ -401,11 +401,12 @@ typedef struct {
     int32_t m2l;              /* FMDDM_APPLY_FMM left-hand side (the product GMRES applies):
                                  FMDDM_M2L_DENSE (0): the (4p^2)^2 operator per (tree level,
                                  offset) of eq. 3.8; FMDDM_M2L_SVD (1): those operators
-                                 compressed per tree level (shared bases from a truncated SVD
-                                 at the context's m2l_tol; rebuilt with the operators), used
-                                 when the stored near field holds the left-hand side.  A
-                                 one-time cost per tree (an SVD of every level's operators)
-                                 that pays over many products. */
+                                 compressed per cell size (bases of all 40 V-list offsets at
+                                 that size from a truncated SVD at the context's m2l_tol),
+                                 used when the stored near field holds the left-hand side.
+                                 The compressed operators of a cell size are built once and
+                                 kept in a cache that the contexts of one server share; a
+                                 one-time cost that pays over many products. */
     int32_t exact_far_levels; /* FMDDM_APPLY_FMM history sums and lag products: 0 (default):
                                  where every V-list pair lies far outside the diffusion length
                                  at the last time level (z = r^2 / (4 c t) >= 50, checked per

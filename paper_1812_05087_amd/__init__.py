@@ -481,7 +481,7 @@ def fmddm_poro_set(ctx, nu_u, alpha, perm, visc, dt, p0=0.0, mode=1, near_cache_
     """mode: FMDDM_APPLY_DIRECT (1, exact), FMDDM_APPLY_FMM (0) or
     FMDDM_APPLY_DENSE (2, history-only).  near_cache_bytes: FMM near-field
     cache budget (0 default, < 0 none).  m2l: FMDDM_M2L_DENSE (0) or
-    FMDDM_M2L_SVD (1, the left-hand side's M2L compressed per tree level).
+    FMDDM_M2L_SVD (1, the left-hand side's M2L compressed per cell size).
     exact_far_levels: 1 keeps one far-field term per time level in history
     sums (0: two terms where the far field is affine in time)."""
     pp = PoroParams(float(nu_u), float(alpha), float(perm), float(visc), float(dt), float(p0), int(mode),

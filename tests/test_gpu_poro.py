@@ -241,7 +241,7 @@ def test_poro_block_jacobi(mode):
 def test_poro_full_size_sampled_rows(p, m2l, nrow):
     """N = 20000 (five fractures of 4000 0.2 m elements, 10 m apart) in the
     serving configuration (p = 10, leaf 32) and the march's (p = 16, the
-    left-hand side's M2L compressed per tree level; the 4-level history's
+    left-hand side's M2L compressed per cell size; the 4-level history's
     far field in two terms): the left-hand-side product and the history
     sum against the oracle's exact rows for 20 / 40 sampled receivers; bar
     1e-6 of the largest entry of each response kind, as for the smaller
@@ -431,7 +431,7 @@ def test_poro_history_only_variant():
 
 @pytest.mark.parametrize("p", [10, 16])
 def test_poro_lhs_compressed_m2l(p):
-    """The left-hand side's M2L compressed per tree level (poro m2l = SVD,
+    """The left-hand side's M2L compressed per cell size (poro m2l = SVD,
     m2l_tol 1e-12) against the uncompressed operators and the exact
     products, on a 5 x 200-element well cluster (four V-list levels).  The
     truncation drops singular values below 1e-12 of the largest, and the
