@@ -530,7 +530,11 @@ const char *fmddm_server_last_error(const fmddm_server *s);
 /* Makes the server poroelastic (eqs. 2.1-2.5): the medium, dt and p0 of
  * fmddm_poro_set apply to every later request (mode must be
  * FMDDM_APPLY_FMM; near_cache_bytes 0 gives each request a quarter of the
- * budget divided by max_slots for its stored near blocks).  Only while no
+ * budget divided by max_slots for its stored near blocks).  With m2l =
+ * FMDDM_M2L_SVD each request's tree gets a root square of power-of-two
+ * side centred on its midpoints' bounding box, so that requests of one
+ * scale share cell sizes, and the compressed left-hand-side operators of a
+ * cell size are built once and shared by all slots.  Only while no
  * request is queued or running (EINVAL otherwise); EINVAL / EUNSUPPORTED
  * as fmddm_poro_set. */
 fmddm_status fmddm_server_set_poro(fmddm_server *s, const fmddm_poro_params *pp);
