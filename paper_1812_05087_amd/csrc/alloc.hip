@@ -5,8 +5,9 @@
 // therefore kept in per-device free lists keyed by their rounded size and
 // handed out again by later allocations (the smallest that fits, a large
 // one up to a quarter bigger than asked); memory goes back to the runtime
-// only when an allocation fails (the cache is emptied and the allocation
-// retried) or on fmddm_trim_cache.
+// when a new block would leave less than a reserve (2 GiB or 1 % of the
+// device) free for the runtime's own allocations, when an allocation fails
+// (the cache is emptied and the allocation retried) or on fmddm_trim_cache.
 //
 // Blocks are released when their owner lets go of them, which may be
 // before the work enqueued on them has run (a buffer regrown or a
@@ -18,6 +19,7 @@
 // then never share a block while the old user's work is pending.
 #include "internal.h"
 
+#include <algorithm>
 #include <cstdlib>
 #include <map>
 #include <mutex>
@@ -160,6 +162,22 @@ void *dev_alloc(size_t bytes, size_t *rounded, bool fp)
             *rounded = got;
             if (fp) poison(p, got);
             return p;
+        }
+    }
+    // the runtime allocates memory of its own on the way (kernel scratch,
+    // library workspaces) and fails a launch when it cannot: keep a reserve
+    // free by returning the cached blocks first when a new block would eat
+    // into it
+    {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess) {
+            const size_t reserve = std::max<size_t>(size_t(2) << 30, tot / 100);
+            if (fr < r + reserve) {
+                std::lock_guard<std::mutex> g(c.mu);
+                drop_all(dev);
+            }
+        } else {
+            (void)hipGetLastError();
         }
     }
     void *p = nullptr;
