@@ -252,6 +252,8 @@ def serving_leg(F, W, count, slots, load, poro=True, alone_sample=128):
         "requests": count, "slots": slots, "elements_total": int(sum(w.n for w in wls)),
         "gmres_products_total": iters,
         "params": {"p": SERVE_PARAMS["p"], "leaf": SERVE_PARAMS["leaf"], "m2l": "svd 1e-10", "tol": 1e-6,
+                   "poro_lhs_m2l": ("compressed per cell size, shared by the slots (power-of-two root squares)"
+                                    if poro and SERVE_PORO_M2L else "dense"),
                    "restart": SERVE_PARAMS["restart"],
                    "precond": f"two-level: block-Jacobi ({21 if poro else 32}-element groups) + coarse level of "
                               f"{SERVE_PARAMS['coarse_aggregates']} aggregates",
